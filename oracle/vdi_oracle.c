@@ -1,0 +1,748 @@
+/*
+ * vdi_oracle.c -- plain, slow, fp64 CPU reference for VDI generation,
+ * compositing, original-view rendering and direct volume rendering.
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code
+ * with the HIP path: it is written directly from the paper's definitions,
+ * one step at a time, without blocking, fusion or early exits.
+ *
+ * Paper: Gupta et al., "Parallel Compositing of Volumetric Depth Images for
+ * Interactive Visualization of Distributed Volumes at High Frame Rates"
+ * (arXiv 2206.14503).
+ *
+ * Precision.  Everything is fp64 except the steps whose result is an integer
+ * decision that the GPU must take identically (which sample a brick owns,
+ * how many samples a ray has, the voxel and transfer-function cells a sample
+ * falls in, whether a sample is transparent).  Those are evaluated in fp32
+ * with a fixed operation order and no fused multiply-add, exactly as the
+ * kernels do: the ray (origin, direction, entry/exit), the sample position,
+ * the trilinear blend and the transfer-function coordinate.  From the
+ * transfer-function lookup on, the arithmetic is fp64.
+ *
+ * Readings of the paper where it is silent or garbled (all shared with the
+ * kernels):
+ *  - world box [0,1]^3, voxel centres at (i+1/2)/n, clamp-to-edge;
+ *  - sample k covers [t0 + k*step, t0 + (k+1)*step) and is taken at its
+ *    midpoint; t0 is the ray's entry into the whole volume, so every brick
+ *    sees the same sample grid;
+ *  - a brick owns a sample iff floor(p*n) (clamped) lies in its box;
+ *  - transfer function: linear interpolation between entries at s=i/(E-1);
+ *  - Eq. 1 compares per-unit-length premultiplied RGB colours, strictly
+ *    (gamma < distance);
+ *  - the open supersegment's per-unit opacity is 1 - T^(1/L) (the exponent in
+ *    the supplementary algorithm is read as 1/l_s), each element is
+ *    accumulated with its length-corrected opacity (Eq. 2);
+ *  - a close and an open can happen on the same element; gaps between
+ *    elements are transparent elements (compositing only);
+ *  - a supersegment stores front f, back of its last non-transparent element,
+ *    un-premultiplied RGB and per-ref-step opacity 1 - T^(ref/(b-f));
+ *  - bisection over gamma in [0, 2] for B halvings, feasible iff
+ *    count <= N, result = upper bracket;
+ *  - composite passes the merged list through unchanged when it already has
+ *    at most N entries;
+ *  - fixed-threshold mode saturates: after N-1 closes no further close.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Inputs                                                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t ortho;
+    float eye[3], fwd[3], right[3], up[3];
+    int32_t width, height;
+} orc_camera;
+
+typedef struct {
+    const void *data;   /* whole volume, [nz][ny][nx], x fastest */
+    int32_t dtype;      /* 0 = fp32, 1 = fp16 (IEEE binary16 bits) */
+    int32_t n[3];       /* nx, ny, nz */
+} orc_volume;
+
+enum { ORC_FIXED = 0, ORC_BISECT = 1 };
+
+/* IEEE binary16 -> float, written out from the format definition. */
+static float half_to_float(uint16_t h)
+{
+    int sign = (h >> 15) & 1, expo = (h >> 10) & 31, mant = h & 1023;
+    double v;
+    if (expo == 0)
+        v = ldexp((double)mant, -24);
+    else if (expo == 31)
+        v = mant ? NAN : INFINITY;
+    else
+        v = ldexp((double)(mant | 1024), expo - 25);
+    return (float)(sign ? -v : v);
+}
+
+static float voxel(const orc_volume *vol, int x, int y, int z)
+{
+    size_t i = ((size_t)z * vol->n[1] + y) * vol->n[0] + x;
+    if (vol->dtype == 1)
+        return half_to_float(((const uint16_t *)vol->data)[i]);
+    return ((const float *)vol->data)[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rays (fp32, fixed order): one ray per pixel through the shared camera      */
+/* (Sec. 2.4: one list per viewport pixel; Sec. 5.1: all PEs share the camera) */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { float o[3], d[3], tn, tf; int hit; } orc_ray;
+
+static orc_ray make_ray(const orc_camera *c, int i, int j)
+{
+    orc_ray r;
+    float sx = (float)(2 * i + 1) / (float)c->width - 1.0f;
+    float sy = 1.0f - (float)(2 * j + 1) / (float)c->height;
+    if (c->ortho) {
+        for (int a = 0; a < 3; ++a) {
+            float t1 = sx * c->right[a];
+            float t2 = sy * c->up[a];
+            float s = c->eye[a] + t1;
+            r.o[a] = s + t2;
+            r.d[a] = c->fwd[a];
+        }
+    } else {
+        float v[3];
+        for (int a = 0; a < 3; ++a) {
+            float t1 = sx * c->right[a];
+            float t2 = sy * c->up[a];
+            float s = c->fwd[a] + t1;
+            v[a] = s + t2;
+            r.o[a] = c->eye[a];
+        }
+        float xx = v[0] * v[0], yy = v[1] * v[1], zz = v[2] * v[2];
+        float n2 = xx + yy;
+        n2 = n2 + zz;
+        float nrm = sqrtf(n2);
+        for (int a = 0; a < 3; ++a) r.d[a] = v[a] / nrm;
+    }
+    /* slab test against the world box [0,1]^3 */
+    float tn = 0.0f, tf = INFINITY;
+    r.hit = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (r.d[a] == 0.0f) {
+            if (r.o[a] < 0.0f || r.o[a] > 1.0f) r.hit = 0;
+            continue;
+        }
+        float ta = (0.0f - r.o[a]) / r.d[a];
+        float tb = (1.0f - r.o[a]) / r.d[a];
+        float lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
+        if (lo > tn) tn = lo;
+        if (hi < tf) tf = hi;
+    }
+    if (!(tn < tf)) r.hit = 0;
+    r.tn = tn;
+    r.tf = tf;
+    return r;
+}
+
+/* Midpoint of sample k (fp32, fixed order); returns 0 once past the exit. */
+static int sample_point(const orc_ray *r, int k, float step, float p[3])
+{
+    float kk = (float)k + 0.5f;
+    float m = kk * step;
+    float t = r->tn + m;
+    if (!(t < r->tf)) return 0;
+    for (int a = 0; a < 3; ++a) {
+        float q = t * r->d[a];
+        p[a] = r->o[a] + q;
+    }
+    return 1;
+}
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* Voxel that contains p: decides brick ownership. */
+static void voxel_of(const orc_volume *vol, const float p[3], int v[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        float g = p[a] * (float)vol->n[a];
+        v[a] = clampi((int)floorf(g), 0, vol->n[a] - 1);
+    }
+}
+
+static float lerpf32(float a, float b, float w)
+{
+    float d = b - a;
+    float e = w * d;
+    return a + e;
+}
+
+/* Trilinear reconstruction at p on the global voxel grid (fp32, fixed order). */
+static float trilinear(const orc_volume *vol, const float p[3])
+{
+    int i0[3], i1[3];
+    float w[3];
+    for (int a = 0; a < 3; ++a) {
+        float g = p[a] * (float)vol->n[a];
+        float u = g - 0.5f;
+        float f = floorf(u);
+        w[a] = u - f;
+        int ii = (int)f;
+        i0[a] = clampi(ii, 0, vol->n[a] - 1);
+        i1[a] = clampi(ii + 1, 0, vol->n[a] - 1);
+    }
+    float c00 = lerpf32(voxel(vol, i0[0], i0[1], i0[2]), voxel(vol, i1[0], i0[1], i0[2]), w[0]);
+    float c10 = lerpf32(voxel(vol, i0[0], i1[1], i0[2]), voxel(vol, i1[0], i1[1], i0[2]), w[0]);
+    float c01 = lerpf32(voxel(vol, i0[0], i0[1], i1[2]), voxel(vol, i1[0], i0[1], i1[2]), w[0]);
+    float c11 = lerpf32(voxel(vol, i0[0], i1[1], i1[2]), voxel(vol, i1[0], i1[1], i1[2]), w[0]);
+    float c0 = lerpf32(c00, c10, w[1]);
+    float c1 = lerpf32(c01, c11, w[1]);
+    return lerpf32(c0, c1, w[2]);
+}
+
+/* Transfer-function cell and weight (fp32, fixed order). */
+static void tf_coord(float s, int entries, int *cell, float *w)
+{
+    float sc = s < 0.0f ? 0.0f : (s > 1.0f ? 1.0f : s);
+    float q = sc * (float)(entries - 1);
+    int i = (int)floorf(q);
+    if (i > entries - 2) i = entries - 2;
+    *cell = i;
+    *w = q - (float)i;
+}
+
+/* Classified sample: colour and per-ref-step opacity in fp64. */
+typedef struct { double rgb[3]; double a; float a32; } orc_class;
+
+static orc_class classify(const float *tf, int entries, float s)
+{
+    orc_class c;
+    int i;
+    float w;
+    tf_coord(s, entries, &i, &w);
+    const float *lo = tf + 4 * i, *hi = tf + 4 * (i + 1);
+    for (int ch = 0; ch < 3; ++ch)
+        c.rgb[ch] = (double)lo[ch] + (double)w * ((double)hi[ch] - (double)lo[ch]);
+    c.a = (double)lo[3] + (double)w * ((double)hi[3] - (double)lo[3]);
+    c.a32 = lerpf32(lo[3], hi[3], w);
+    return c;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Elements and the segmenter                                               */
+/* ------------------------------------------------------------------------ */
+
+/* An element is a sample (generation) or a sub-supersegment (compositing):
+ * front/back depth along the ray, un-premultiplied colour and opacity per
+ * reference step.  Its own length in reference steps is l = (b-f)/ref. */
+typedef struct { double f, b, rgb[3], a; } orc_elem;
+
+typedef struct { double f, b, rgb[3], a; } orc_sseg;
+
+typedef struct {
+    double gamma;
+    int cap;            /* >0: saturate after cap-1 closes (fixed mode) */
+    int gaps;           /* insert transparent gap elements (compositing) */
+    double ref;
+    int count_limit;    /* margins are only recorded while count <= limit */
+    /* outputs */
+    orc_sseg *out;       /* may be NULL */
+    int max_out;
+    int count;
+    double margin;      /* min |distance - gamma| over recorded decisions */
+} orc_segrun;
+
+typedef struct {
+    int open;
+    double f, b, bt;
+    double C[3];        /* premultiplied colour accumulated front to back */
+    double T;           /* transmittance of the open supersegment */
+} orc_state;
+
+static void seg_close(orc_state *S, orc_segrun *R)
+{
+    if (R->out && R->count < R->max_out) {
+        orc_sseg *o = &R->out[R->count];
+        double A = 1.0 - S->T;
+        o->f = S->f;
+        o->b = S->bt;
+        for (int ch = 0; ch < 3; ++ch) o->rgb[ch] = A > 0.0 ? S->C[ch] / A : 0.0;
+        /* opacity per reference step over the stored extent [f, bt] */
+        o->a = 1.0 - pow(S->T, R->ref / (S->bt - S->f));
+    }
+    R->count += 1;
+    S->open = 0;
+}
+
+/* One element through the segmenter (Eq. 1 criterion, Eq. 2 length correction,
+ * supplementary algorithm S1 as read above). */
+static void seg_step(orc_state *S, orc_segrun *R, const orc_elem *e)
+{
+    int transparent = (e->a == 0.0);
+    double l = (e->b - e->f) / R->ref;
+    double at = transparent ? 0.0 : 1.0 - pow(1.0 - e->a, l);   /* Eq. 2 */
+    if (S->open) {
+        double L = (S->b - S->f) / R->ref;
+        double A = 1.0 - S->T;
+        double aS = 1.0 - pow(S->T, 1.0 / L);
+        double d2 = 0.0;
+        for (int ch = 0; ch < 3; ++ch) {
+            double repS = A > 0.0 ? S->C[ch] / A * aS : 0.0;
+            double repE = e->rgb[ch] * e->a;
+            d2 += (repS - repE) * (repS - repE);
+        }
+        double d = sqrt(d2);
+        int may_close = R->cap <= 0 || R->count < R->cap - 1;
+        if (may_close && R->count <= R->count_limit) {
+            double m = fabs(d - R->gamma);
+            if (m < R->margin) R->margin = m;
+        }
+        if (may_close && R->gamma < d) {
+            seg_close(S, R);
+        } else {
+            for (int ch = 0; ch < 3; ++ch) S->C[ch] += S->T * e->rgb[ch] * at;
+            S->T *= 1.0 - at;
+            S->b = e->b;
+            if (!transparent) S->bt = e->b;
+        }
+    }
+    if (!S->open && !transparent) {
+        S->open = 1;
+        S->f = e->f;
+        S->b = S->bt = e->b;
+        for (int ch = 0; ch < 3; ++ch) S->C[ch] = e->rgb[ch] * at;
+        S->T = 1.0 - at;
+    }
+}
+
+static void seg_run(const orc_elem *e, int n, orc_segrun *R)
+{
+    orc_state S;
+    memset(&S, 0, sizeof S);
+    R->count = 0;
+    R->margin = INFINITY;
+    for (int i = 0; i < n; ++i) {
+        if (S.open && e[i].f > S.b) {
+            if (R->gaps) {
+                /* compositing: the empty space before the element is a
+                 * transparent sample */
+                orc_elem g = { S.b, e[i].f, { 0.0, 0.0, 0.0 }, 0.0 };
+                seg_step(&S, R, &g);
+            } else {
+                /* generation: the ray left the brick; the supersegment ends */
+                seg_close(&S, R);
+            }
+        }
+        seg_step(&S, R, &e[i]);
+    }
+    if (S.open) seg_close(&S, R);
+}
+
+/* Per-ray threshold search by bisection (Sec. 2.4): B halvings of [0, gmax];
+ * a midpoint is feasible iff it yields at most N supersegments. */
+static double bisect(const orc_elem *e, int n, int max_n, int iters, double gmax, int gaps,
+                     double ref, double *margin)
+{
+    double lo = 0.0, hi = gmax, mg = INFINITY;
+    for (int it = 0; it < iters; ++it) {
+        double m = 0.5 * (lo + hi);
+        orc_segrun R = { m, 0, gaps, ref, max_n, NULL, 0, 0, 0.0 };
+        seg_run(e, n, &R);
+        if (R.margin < mg) mg = R.margin;
+        if (R.count <= max_n) hi = m; else lo = m;
+    }
+    *margin = mg;
+    return hi;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sample streams                                                           */
+/* ------------------------------------------------------------------------ */
+
+static int brick_owns(const int32_t *lo, const int32_t *hi, const int v[3])
+{
+    for (int a = 0; a < 3; ++a)
+        if (v[a] < lo[a] || v[a] >= hi[a]) return 0;
+    return 1;
+}
+
+/* Number of samples of a ray inside the volume. */
+static int ray_samples(const orc_ray *r, float step)
+{
+    if (!r->hit) return 0;
+    float p[3];
+    int k = 0;
+    while (sample_point(r, k, step, p)) ++k;
+    return k;
+}
+
+/* Owned sample stream of one brick along one ray.  Returns the element count;
+ * *contiguous is cleared if the owned samples are not one run (the stream is
+ * then cut at the first discontinuity: a supersegment must end where the ray
+ * leaves the domain, Sec. 5.3). */
+static int brick_stream(const orc_volume *vol, const int32_t *lo, const int32_t *hi,
+                        const orc_ray *r, const float *tf, int entries, float step,
+                        orc_elem *e, int cap, int *contiguous, float *a32_out)
+{
+    int ns = ray_samples(r, step), n = 0, last = -2;
+    *contiguous = 1;
+    for (int k = 0; k < ns; ++k) {
+        float p[3];
+        int v[3];
+        sample_point(r, k, step, p);
+        voxel_of(vol, p, v);
+        if (!brick_owns(lo, hi, v)) continue;
+        if (last >= 0 && k != last + 1) *contiguous = 0;
+        last = k;
+        if (n >= cap) break;
+        orc_class c = classify(tf, entries, trilinear(vol, p));
+        e[n].f = (double)r->tn + (double)k * (double)step;
+        e[n].b = (double)r->tn + (double)(k + 1) * (double)step;
+        for (int ch = 0; ch < 3; ++ch) e[n].rgb[ch] = c.rgb[ch];
+        e[n].a = c.a;
+        if (a32_out) a32_out[n] = c.a32;
+        ++n;
+    }
+    return n;
+}
+
+static int max_samples(float step)
+{
+    /* a ray crosses the unit box over at most sqrt(3) world units */
+    return (int)(1.7320509 / step) + 4;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported entry points                                                    */
+/* ------------------------------------------------------------------------ */
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+/* Generation (Sec. 5.1): for every brick and every requested pixel, the
+ * owned sample stream is cut into supersegments, with a fixed threshold
+ * (saturating at N) or with the per-ray bisection threshold.
+ * Outputs, regular layout over the requested pixels (npix of them):
+ *   color [nb][max_n][npix][4], depth [nb][max_n][npix][2] (zero beyond count),
+ *   count [nb][npix], gamma [nb][npix], margin [nb][npix] (may be NULL),
+ *   contiguous [nb][npix] (may be NULL).
+ * Returns 0, or -1 on bad arguments. */
+int orc_generate(const void *vol_data, int vol_dtype, const int32_t *n,
+                 const int32_t *brick_lo, const int32_t *brick_hi, int nb,
+                 const orc_camera *cam, const float *tf, int entries,
+                 float step, float ref, int mode, float tau, int max_n, int iters,
+                 const int32_t *pixels, int npix,
+                 float *color, float *depth, int32_t *count, float *gamma,
+                 double *margin, int32_t *contiguous, int nthreads)
+{
+    if (!vol_data || !n || nb <= 0 || !cam || !tf || entries < 2 || max_n <= 0 || npix < 0)
+        return -1;
+    orc_volume vol = { vol_data, vol_dtype, { n[0], n[1], n[2] } };
+    int cap = max_samples(step);
+    set_threads(nthreads);
+    size_t P = (size_t)npix;
+#pragma omp parallel
+    {
+        orc_elem *e = (orc_elem *)malloc(sizeof(orc_elem) * (size_t)cap);
+        orc_sseg *s = (orc_sseg *)malloc(sizeof(orc_sseg) * (size_t)max_n);
+#pragma omp for schedule(dynamic, 64)
+        for (long long job = 0; job < (long long)nb * npix; ++job) {
+            int r = (int)(job / npix);
+            size_t q = (size_t)(job % npix);
+            int pix = pixels ? pixels[q] : (int)q;
+            orc_ray ray = make_ray(cam, pix % cam->width, pix / cam->width);
+            int contig;
+            int ne = ray.hit ? brick_stream(&vol, brick_lo + 3 * r, brick_hi + 3 * r, &ray, tf, entries,
+                                            step, e, cap, &contig, NULL) : 0;
+            if (!ray.hit) contig = 1;
+            double g, mg = INFINITY;
+            orc_segrun R;
+            if (mode == ORC_FIXED) {
+                g = tau;
+                R = (orc_segrun){ g, max_n, 0, ref, max_n, s, max_n, 0, 0.0 };
+            } else {
+                g = bisect(e, ne, max_n, iters, 2.0, 0, ref, &mg);
+                R = (orc_segrun){ g, 0, 0, ref, max_n, s, max_n, 0, 0.0 };
+            }
+            seg_run(e, ne, &R);
+            if (R.margin < mg) mg = R.margin;
+            int c = R.count < max_n ? R.count : max_n;
+            for (int j = 0; j < max_n; ++j) {
+                size_t o = ((size_t)r * max_n + j) * P + q;
+                if (j < c) {
+                    for (int ch = 0; ch < 3; ++ch) color[4 * o + ch] = (float)s[j].rgb[ch];
+                    color[4 * o + 3] = (float)s[j].a;
+                    depth[2 * o] = (float)s[j].f;
+                    depth[2 * o + 1] = (float)s[j].b;
+                } else {
+                    memset(color + 4 * o, 0, 4 * sizeof(float));
+                    memset(depth + 2 * o, 0, 2 * sizeof(float));
+                }
+            }
+            count[(size_t)r * P + q] = R.count;
+            if (gamma) gamma[(size_t)r * P + q] = (float)g;
+            if (margin) margin[(size_t)r * P + q] = mg;
+            if (contiguous) contiguous[(size_t)r * P + q] = contig;
+        }
+        free(e);
+        free(s);
+    }
+    return 0;
+}
+
+/* Compositing (Sec. 5.2): merge the k depth-sorted lists of a pixel by front
+ * depth (equal fronts: lower input index first), then either pass the merged
+ * list through (at most N entries) or re-segment it, treating each
+ * sub-supersegment as a sample of its own length and the gaps between them
+ * as transparent samples, with the threshold found by the per-ray bisection
+ * (or fixed, saturating at N).
+ * Inputs: k regular lists over the same npix pixels, color_k [in_n][npix][4],
+ * depth_k [in_n][npix][2], count_k [npix].
+ * Outputs: color [out_n][npix][4], depth [out_n][npix][2], count, gamma,
+ * margin (may be NULL), order [npix][k*in_n] (may be NULL): merged order as
+ * rank*65536 + slot, -1 padded.
+ * Returns 0; -1 on bad arguments; -2 if an input list is not sorted by front
+ * depth, has f >= b, or a count outside [0, in_n]. */
+int orc_composite(int k, const float *const *colors, const float *const *depths,
+                  const int32_t *const *counts, int in_n, int npix, float ref,
+                  int mode, float tau, int out_n, int iters,
+                  float *color, float *depth, int32_t *count, float *gamma,
+                  double *margin, int32_t *order, int nthreads)
+{
+    if (k <= 0 || in_n <= 0 || out_n <= 0 || npix < 0) return -1;
+    set_threads(nthreads);
+    size_t P = (size_t)npix;
+    int bad = 0;
+#pragma omp parallel
+    {
+        int cap = k * in_n;
+        orc_elem *e = (orc_elem *)malloc(sizeof(orc_elem) * (size_t)cap);
+        int32_t *rk = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+        orc_sseg *s = (orc_sseg *)malloc(sizeof(orc_sseg) * (size_t)out_n);
+#pragma omp for schedule(dynamic, 64)
+        for (long long qq = 0; qq < npix; ++qq) {
+            size_t q = (size_t)qq;
+            int n = 0, ok = 1;
+            for (int r = 0; r < k; ++r) {
+                int c = counts[r][q];
+                if (c < 0 || c > in_n) { ok = 0; break; }
+                for (int j = 0; j < c; ++j) {
+                    size_t o = (size_t)j * P + q;
+                    double f = depths[r][2 * o], b = depths[r][2 * o + 1];
+                    if (!(f < b)) ok = 0;
+                    if (j > 0 && f < depths[r][2 * (o - P)]) ok = 0;
+                    /* insertion into the merged list: after every entry whose
+                     * (front, rank) key is not larger */
+                    int pos = n;
+                    while (pos > 0 && (e[pos - 1].f > f || (e[pos - 1].f == f && (rk[pos - 1] >> 16) > r)))
+                        --pos;
+                    memmove(e + pos + 1, e + pos, sizeof(orc_elem) * (size_t)(n - pos));
+                    memmove(rk + pos + 1, rk + pos, sizeof(int32_t) * (size_t)(n - pos));
+                    e[pos].f = f;
+                    e[pos].b = b;
+                    for (int ch = 0; ch < 3; ++ch) e[pos].rgb[ch] = colors[r][4 * o + ch];
+                    e[pos].a = colors[r][4 * o + 3];
+                    rk[pos] = r * 65536 + j;
+                    ++n;
+                }
+            }
+            if (!ok) {
+#pragma omp atomic write
+                bad = 1;
+                n = 0;
+            }
+            if (order)
+                for (int j = 0; j < cap; ++j) order[q * (size_t)cap + j] = j < n ? rk[j] : -1;
+            double g = 0.0, mg = INFINITY;
+            int c;
+            if (n <= out_n) {
+                /* pass-through */
+                for (int j = 0; j < n; ++j) {
+                    s[j].f = e[j].f;
+                    s[j].b = e[j].b;
+                    for (int ch = 0; ch < 3; ++ch) s[j].rgb[ch] = e[j].rgb[ch];
+                    s[j].a = e[j].a;
+                }
+                c = n;
+            } else {
+                orc_segrun R;
+                if (mode == ORC_FIXED) {
+                    g = tau;
+                    R = (orc_segrun){ g, out_n, 1, ref, out_n, s, out_n, 0, 0.0 };
+                } else {
+                    g = bisect(e, n, out_n, iters, 2.0, 1, ref, &mg);
+                    R = (orc_segrun){ g, 0, 1, ref, out_n, s, out_n, 0, 0.0 };
+                }
+                seg_run(e, n, &R);
+                if (R.margin < mg) mg = R.margin;
+                c = R.count < out_n ? R.count : out_n;
+            }
+            for (int j = 0; j < out_n; ++j) {
+                size_t o = (size_t)j * P + q;
+                if (j < c) {
+                    for (int ch = 0; ch < 3; ++ch) color[4 * o + ch] = (float)s[j].rgb[ch];
+                    color[4 * o + 3] = (float)s[j].a;
+                    depth[2 * o] = (float)s[j].f;
+                    depth[2 * o + 1] = (float)s[j].b;
+                } else {
+                    memset(color + 4 * o, 0, 4 * sizeof(float));
+                    memset(depth + 2 * o, 0, 2 * sizeof(float));
+                }
+            }
+            count[q] = c;
+            if (gamma) gamma[q] = (float)g;
+            if (margin) margin[q] = mg;
+        }
+        free(e);
+        free(rk);
+        free(s);
+    }
+    return bad ? -2 : 0;
+}
+
+/* Rendering from the viewpoint of generation (Sec. 2.3): each stored
+ * supersegment contributes its total opacity 1-(1-a)^((b-f)/ref), composited
+ * front to back with the over operator.  Output premultiplied RGBA [npix][4]. */
+int orc_render_ov(const float *color, const float *depth, const int32_t *count, int max_n,
+                  int npix, float ref, double *rgba, int nthreads)
+{
+    if (max_n <= 0 || npix < 0) return -1;
+    set_threads(nthreads);
+    size_t P = (size_t)npix;
+#pragma omp parallel for schedule(static)
+    for (long long qq = 0; qq < npix; ++qq) {
+        size_t q = (size_t)qq;
+        double C[3] = { 0, 0, 0 }, A = 0.0;
+        int c = count[q] < max_n ? count[q] : max_n;
+        for (int j = 0; j < c; ++j) {
+            size_t o = (size_t)j * P + q;
+            double a = color[4 * o + 3];
+            double len = ((double)depth[2 * o + 1] - (double)depth[2 * o]) / ref;
+            double Aj = 1.0 - pow(1.0 - a, len);
+            for (int ch = 0; ch < 3; ++ch) C[ch] += (1.0 - A) * color[4 * o + ch] * Aj;
+            A += (1.0 - A) * Aj;
+        }
+        for (int ch = 0; ch < 3; ++ch) rgba[4 * q + ch] = C[ch];
+        rgba[4 * q + 3] = A;
+    }
+    return 0;
+}
+
+/* Direct volume rendering of the whole volume (Sec. 2.1, emission-absorption,
+ * front to back, no early termination) on the same sample grid.
+ * Output premultiplied RGBA [npix][4]. */
+int orc_dvr(const void *vol_data, int vol_dtype, const int32_t *n, const orc_camera *cam,
+            const float *tf, int entries, float step, float ref, const int32_t *pixels, int npix,
+            double *rgba, int nthreads)
+{
+    if (!vol_data || !n || !cam || !tf || npix < 0) return -1;
+    orc_volume vol = { vol_data, vol_dtype, { n[0], n[1], n[2] } };
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long long qq = 0; qq < npix; ++qq) {
+        size_t q = (size_t)qq;
+        int pix = pixels ? pixels[q] : (int)q;
+        orc_ray ray = make_ray(cam, pix % cam->width, pix / cam->width);
+        int ns = ray_samples(&ray, step);
+        double C[3] = { 0, 0, 0 }, T = 1.0;
+        for (int k = 0; k < ns; ++k) {
+            float p[3];
+            sample_point(&ray, k, step, p);
+            orc_class c = classify(tf, entries, trilinear(&vol, p));
+            double alpha = 1.0 - pow(1.0 - c.a, (double)step / (double)ref);
+            for (int ch = 0; ch < 3; ++ch) C[ch] += T * c.rgb[ch] * alpha;
+            T *= 1.0 - alpha;
+        }
+        for (int ch = 0; ch < 3; ++ch) rgba[4 * q + ch] = C[ch];
+        rgba[4 * q + 3] = 1.0 - T;
+    }
+    return 0;
+}
+
+/* Segmenter on explicit elements, for unit tests.  elems [n][6] = f, b, r, g, b, a.
+ * mode FIXED: threshold gamma, saturating at cap (cap<=0: none);
+ * mode BISECT: threshold from bisection with max_n/iters.
+ * out [max_out][6]; returns the count; *gamma_used, *margin written. */
+int orc_seg(const double *elems, int n, int mode, double gamma, int cap, int max_n, int iters,
+            int gaps, double ref, double *out, int max_out, double *gamma_used, double *margin)
+{
+    orc_elem *e = (orc_elem *)malloc(sizeof(orc_elem) * (size_t)(n > 0 ? n : 1));
+    orc_sseg *s = (orc_sseg *)malloc(sizeof(orc_sseg) * (size_t)(max_out > 0 ? max_out : 1));
+    for (int i = 0; i < n; ++i) {
+        e[i].f = elems[6 * i];
+        e[i].b = elems[6 * i + 1];
+        for (int ch = 0; ch < 3; ++ch) e[i].rgb[ch] = elems[6 * i + 2 + ch];
+        e[i].a = elems[6 * i + 5];
+    }
+    double g = gamma, mg = INFINITY;
+    if (mode == ORC_BISECT) g = bisect(e, n, max_n, iters, 2.0, gaps, ref, &mg);
+    orc_segrun R = { g, mode == ORC_FIXED ? cap : 0, gaps, ref, mode == ORC_FIXED ? (cap > 0 ? cap : n) : max_n,
+                     s, max_out, 0, 0.0 };
+    seg_run(e, n, &R);
+    if (R.margin < mg) mg = R.margin;
+    int c = R.count < max_out ? R.count : max_out;
+    for (int j = 0; j < c; ++j) {
+        out[6 * j] = s[j].f;
+        out[6 * j + 1] = s[j].b;
+        for (int ch = 0; ch < 3; ++ch) out[6 * j + 2 + ch] = s[j].rgb[ch];
+        out[6 * j + 5] = s[j].a;
+    }
+    if (gamma_used) *gamma_used = g;
+    if (margin) *margin = mg;
+    free(e);
+    free(s);
+    return R.count;
+}
+
+/* Per-pixel sample streams for tests: number of samples of each ray and the
+ * brick-owned element list of one pixel. */
+int orc_ray_info(const orc_camera *cam, int pix, float step, float *o, float *d, float *tn, float *tf)
+{
+    orc_ray r = make_ray(cam, pix % cam->width, pix / cam->width);
+    for (int a = 0; a < 3; ++a) { o[a] = r.o[a]; d[a] = r.d[a]; }
+    *tn = r.tn;
+    *tf = r.tf;
+    return r.hit ? ray_samples(&r, step) : -1;
+}
+
+int orc_stream(const void *vol_data, int vol_dtype, const int32_t *n, const int32_t *lo, const int32_t *hi,
+               const orc_camera *cam, const float *tf, int entries, float step, int pix,
+               double *elems, int cap, float *a32)
+{
+    orc_volume vol = { vol_data, vol_dtype, { n[0], n[1], n[2] } };
+    orc_ray r = make_ray(cam, pix % cam->width, pix / cam->width);
+    if (!r.hit) return 0;
+    orc_elem *e = (orc_elem *)malloc(sizeof(orc_elem) * (size_t)cap);
+    int contig;
+    int ne = brick_stream(&vol, lo, hi, &r, tf, entries, step, e, cap, &contig, a32);
+    for (int i = 0; i < ne; ++i) {
+        elems[6 * i] = e[i].f;
+        elems[6 * i + 1] = e[i].b;
+        for (int ch = 0; ch < 3; ++ch) elems[6 * i + 2 + ch] = e[i].rgb[ch];
+        elems[6 * i + 5] = e[i].a;
+    }
+    free(e);
+    return contig ? ne : -ne - 1;
+}
+
+/* Trilinear value at an explicit fp32 point (tests pin the reconstruction). */
+double orc_trilinear(const void *vol_data, int vol_dtype, const int32_t *n, const float *p)
+{
+    orc_volume vol = { vol_data, vol_dtype, { n[0], n[1], n[2] } };
+    return (double)trilinear(&vol, p);
+}
+
+/* Classified colour/opacity at a scalar value (tests pin the lookup). */
+void orc_classify(const float *tf, int entries, float s, double *rgba)
+{
+    orc_class c = classify(tf, entries, s);
+    for (int ch = 0; ch < 3; ++ch) rgba[ch] = c.rgb[ch];
+    rgba[3] = c.a;
+}
