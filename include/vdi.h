@@ -1,0 +1,192 @@
+/*
+ * vdi.h -- C ABI of libvdi: Volumetric Depth Image (VDI) generation and
+ * compositing on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gupta et al., "Parallel Compositing of Volumetric Depth Images for
+ * Interactive Visualization of Distributed Volumes at High Frame Rates",
+ * arXiv 2206.14503.  A VDI holds, for each of the w*h viewport pixels, a list
+ * of at most N supersegments (front depth f, back depth b, colour, opacity)
+ * cut from the volume-rendering integral along the pixel's ray (Sec. 2.4).
+ * Each of k volume bricks yields a sub-VDI on its own (Sec. 5.1); compositing
+ * depth-merges the k lists of every pixel and re-segments them into at most
+ * N supersegments (Sec. 5.2 and supplementary Algorithm S1).
+ *
+ * Conventions for every entry point:
+ *  - All data pointers are DEVICE pointers unless stated otherwise; the caller
+ *    allocates and owns them.  The library owns only its context (scratch
+ *    memory, kept between calls and grown when a larger problem arrives).
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *    Work is enqueued on it and the call returns without synchronising.
+ *  - Shape and argument errors are detected on the host before any launch and
+ *    returned as a negative vdi_status; vdi_last_error() then describes them
+ *    (thread-local, valid until the next call on the same thread).  Nothing
+ *    is launched when an error is returned.
+ *  - Depths are world-space distances along the unit ray direction, from the
+ *    eye (perspective) or from the image plane (orthographic).  The world box
+ *    of the volume is [0,1]^3.
+ */
+#ifndef VDI_H
+#define VDI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VDI_OK = 0,
+    VDI_E_INVALID = -1,     /* bad argument or shape */
+    VDI_E_UNSUPPORTED = -2, /* valid but not supported by this build (limits below) */
+    VDI_E_HIP = -3,         /* a HIP runtime call failed */
+    VDI_E_INPUT = -4,       /* input data violates a precondition (checked on the device; see vdi_ctx_device_status) */
+    VDI_E_CAPACITY = -5     /* a compact output does not fit its capacity */
+} vdi_status;
+
+typedef enum { VDI_LAYOUT_REGULAR = 0, VDI_LAYOUT_COMPACT = 1 } vdi_layout;
+typedef enum { VDI_TAU_FIXED = 0, VDI_TAU_BISECT = 1, VDI_TAU_LEARNED = 2 } vdi_tau_mode;
+typedef enum { VDI_F32 = 0, VDI_F16 = 1 } vdi_dtype;
+
+/* Limits of this build. */
+#define VDI_MAX_INPUTS 32   /* k in vdi_composite */
+#define VDI_MAX_N 64        /* N, supersegments per list */
+#define VDI_MAX_TF 1024     /* transfer-function entries */
+
+typedef struct vdi_ctx vdi_ctx;
+
+/* A VDI (Sec. 2.4, Sec. 4).  One list per pixel p = y*width + x (row 0 at the
+ * top of the image).
+ *
+ * Regular layout (Sec. 4, Fig. 2a): slot-major planes.  Supersegment j of
+ * pixel p is color[(j*H*W + p)*4 .. +4) and depth[(j*H*W + p)*2 .. +2);
+ * slots j >= count[p] hold zeros.  color/depth hold max_n*H*W entries.
+ *
+ * Compact layout (Sec. 4, Fig. 2b/c): supersegment j of pixel p is entry
+ * offset[p] + j of color/depth; offset[p] is the exclusive prefix sum of
+ * count and offset[H*W] the total.  color/depth hold `capacity` entries.
+ *
+ * color: RGB un-premultiplied in [0,1], A = opacity per ref_step of depth
+ *        (the total opacity of the supersegment is 1-(1-A)^((b-f)/ref_step)).
+ * depth: {f, b}, f < b, lists sorted by f with non-overlapping extents.
+ * gamma: per-list threshold the generator or compositor used (optional). */
+typedef struct {
+    int32_t width, height;
+    int32_t max_n;
+    int32_t layout;          /* vdi_layout */
+    float ref_step;          /* reference step length (world units) of the opacities */
+    float *color;            /* float4 per supersegment */
+    float *depth;            /* float2 per supersegment */
+    int32_t *count;          /* [H*W] */
+    uint32_t *offset;        /* [H*W + 1], compact only (else NULL) */
+    float *gamma;            /* [H*W] or NULL */
+    uint64_t capacity;       /* compact: entries color/depth can hold */
+} vdi_t;
+
+/* A brick of the domain decomposition (Sec. 5, Sec. 3): the voxels it owns,
+ * [lo, hi) in global voxel indices (x, y, z), and its data with a ghost layer:
+ * data covers the global box [data_lo, data_lo + data_dim), x fastest.  The
+ * data box must contain [lo-1, hi+1) clipped to the volume, so that samples
+ * the brick owns reconstruct exactly as on the whole volume. */
+typedef struct {
+    const void *data;
+    int32_t dtype;           /* vdi_dtype */
+    int32_t full_dim[3];     /* global nx, ny, nz */
+    int32_t lo[3], hi[3];
+    int32_t data_lo[3], data_dim[3];
+} vdi_brick_t;
+
+/* Shared camera (Sec. 5.1: every brick casts the same rays).  For pixel
+ * (x, y): sx = (2x+1)/W - 1, sy = 1 - (2y+1)/H.  Perspective (ortho = 0):
+ * origin eye, direction normalize(fwd + sx*right + sy*up).  Orthographic:
+ * origin eye + sx*right + sy*up, direction fwd (unit length).  right/up are
+ * pre-scaled (tan(fovy/2)*aspect, tan(fovy/2); or the half extents). */
+typedef struct {
+    int32_t ortho;
+    float eye[3], fwd[3], right[3], up[3];
+    int32_t width, height;
+} vdi_camera_t;
+
+/* 1D transfer function (Sec. 7: VDIs store classified colour): `entries`
+ * RGBA rows at scalar s = i/(entries-1), linearly interpolated, A = opacity
+ * per ref_step.  rgba is a DEVICE pointer, values in [0,1]. */
+typedef struct {
+    const float *rgba;
+    int32_t entries;
+} vdi_tf_t;
+
+/* Threshold selection (Eq. 1 and Sec. 2.4).
+ *  FIXED:   gamma = tau; a list saturates at max_n (after max_n-1 closes the
+ *           last supersegment absorbs the rest of the ray).
+ *  BISECT:  per list, `iters` halvings of [0, gamma_max]; a midpoint is
+ *           feasible iff it yields at most max_n supersegments; the result is
+ *           the upper bracket.
+ *  LEARNED: per list, gamma predicted by the MLP in `mlp` (a vdi_mlp_t*) from a
+ *           64-bin opacity histogram, accepted if the resulting count c
+ *           satisfies ceil((1-fallback_tol)*min(N, cmax)) <= c <= N (cmax:
+ *           count at the smallest bisection threshold), else BISECT. */
+typedef struct {
+    int32_t mode;            /* vdi_tau_mode */
+    float tau;
+    int32_t iters;           /* B, 1..30 */
+    float gamma_max;         /* > sqrt(3), normally 2 */
+    const void *mlp;
+    float fallback_tol;
+} vdi_tau_t;
+
+/* Context: one per device and thread of use.  vdi_ctx_create makes `device`
+ * current and keeps it; VDI_E_HIP if the device cannot be used. */
+vdi_status vdi_ctx_create(vdi_ctx **out, int device);
+vdi_status vdi_ctx_destroy(vdi_ctx *ctx);
+const char *vdi_last_error(void);
+
+/* Sub-VDI generation (Sec. 5.1, Sec. 4, Eq. 1).  For each brick r < k, every
+ * pixel's ray is sampled front to back on the global sample grid (sample i
+ * covers [t_in + i*step, t_in + (i+1)*step), taken at its midpoint; t_in is
+ * the ray's entry into the volume box), samples the brick owns are
+ * classified by the transfer function (opacity corrected to the step length)
+ * and cut into at most out[r].max_n supersegments by the criterion
+ * gamma < |C(S)a(S) - C'a'| on per-step premultiplied RGB, with gamma chosen
+ * per `tau`.  A supersegment also ends where the ray leaves the brick.
+ * out[r] must match the camera's width/height and share ref_step; regular or
+ * compact layout per out[r].layout (compact: capacity must hold the total,
+ * else VDI_E_CAPACITY is reported through vdi_ctx_device_status after the
+ * stream completes and the entries beyond capacity are not written).
+ * step > 0 is the sampling distance in world units. */
+vdi_status vdi_generate(vdi_ctx *ctx, const vdi_brick_t *bricks, int k, const vdi_camera_t *cam,
+                        const vdi_tf_t *tf, float step, const vdi_tau_t *tau, vdi_t *out, void *stream);
+
+/* Compositing (Sec. 5.2, Algorithm S1).  For every pixel, the k input lists
+ * are merged by front depth (equal fronts: lower input index first; each
+ * input must already be sorted).  If the merged list has at most out->max_n
+ * entries it is written unchanged; otherwise each entry is treated as a
+ * sample of its own length with opacity corrected by Eq. 2, empty space
+ * between entries as transparent samples, and the list is re-segmented with
+ * the Eq. 1 criterion and a threshold chosen per `tau` (FIXED or BISECT).
+ * All inputs share width, height and ref_step with out; out must be regular.
+ * Inputs may mix layouts.  k in [1, VDI_MAX_INPUTS]. */
+vdi_status vdi_composite(vdi_ctx *ctx, const vdi_t *in, int k, const vdi_tau_t *tau, vdi_t *out,
+                         void *stream);
+
+/* Rendering from the viewpoint of generation (Sec. 2.3): per pixel, the
+ * supersegments are composited front to back with the over operator using
+ * their total opacities.  rgba: [H*W][4] premultiplied, fp32. */
+vdi_status vdi_render_original_view(vdi_ctx *ctx, const vdi_t *vdi, float *rgba, void *stream);
+
+/* Device-side status of the context since the last call to this function
+ * (synchronises `stream` first): bit 0 = a compact output overflowed its
+ * capacity, bit 1 = a composite input list was invalid (count outside
+ * [0, max_n], f >= b, or fronts not sorted; such pixels are written empty).
+ * Clears the flags. */
+vdi_status vdi_ctx_device_status(vdi_ctx *ctx, int32_t *flags, void *stream);
+
+/* Diagnostic: the fp32 ray of each pixel as the kernels compute it.
+ * o, d: [H*W][3]; tn, tf: [H*W]; nsamples: [H*W] (-1 for a miss). */
+vdi_status vdi_debug_rays(vdi_ctx *ctx, const vdi_camera_t *cam, float step, float *o, float *d,
+                          float *tn, float *tf, int32_t *nsamples, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VDI_H */

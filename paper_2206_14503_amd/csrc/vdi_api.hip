@@ -1,0 +1,343 @@
+// vdi_api.hip -- the C ABI of libvdi: argument checking, scratch memory and
+// kernel launches for generation, compositing and rendering.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "vdi_internal.h"
+#include "vdi_kernels.h"
+
+struct vdi_ctx {
+    int device;
+    int* status;          // device flags word
+    void* scratch;        // grown on demand, kept until destroy
+    size_t scratch_bytes;
+};
+
+namespace vdi {
+
+static thread_local char g_err[1024];
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+static vdi_status fail(vdi_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+static vdi_status launched()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VDI_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return VDI_OK;
+}
+
+static vdi_status ensure_scratch(vdi_ctx* ctx, size_t bytes)
+{
+    if (bytes <= ctx->scratch_bytes) return VDI_OK;
+    if (ctx->scratch) {
+        VDI_HIP_CHECK(hipDeviceSynchronize());
+        VDI_HIP_CHECK(hipFree(ctx->scratch));
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+    }
+    size_t sz = std::max(bytes, (size_t)1 << 20);
+    VDI_HIP_CHECK(hipMalloc(&ctx->scratch, sz));
+    ctx->scratch_bytes = sz;
+    return VDI_OK;
+}
+
+static Cam to_cam(const vdi_camera_t* c)
+{
+    Cam k;
+    k.ortho = c->ortho;
+    for (int a = 0; a < 3; ++a) {
+        k.eye[a] = c->eye[a];
+        k.fwd[a] = c->fwd[a];
+        k.right[a] = c->right[a];
+        k.up[a] = c->up[a];
+    }
+    k.width = c->width;
+    k.height = c->height;
+    return k;
+}
+
+static vdi_status check_vdi(const vdi_t* v, const char* what, bool allow_compact)
+{
+    if (!v) return fail(VDI_E_INVALID, "%s is NULL", what);
+    if (v->width <= 0 || v->height <= 0) return fail(VDI_E_INVALID, "%s: bad size %dx%d", what, v->width, v->height);
+    if ((int64_t)v->width * v->height >= ((int64_t)1 << 31))
+        return fail(VDI_E_UNSUPPORTED, "%s: more than 2^31 pixels", what);
+    if (v->max_n < 1 || v->max_n > VDI_MAX_N)
+        return fail(VDI_E_INVALID, "%s: max_n %d outside [1, %d]", what, v->max_n, VDI_MAX_N);
+    if (!(v->ref_step > 0.0f)) return fail(VDI_E_INVALID, "%s: ref_step must be > 0", what);
+    if (!v->color || !v->depth || !v->count) return fail(VDI_E_INVALID, "%s: color/depth/count must be set", what);
+    if (v->layout == VDI_LAYOUT_COMPACT) {
+        if (!allow_compact) return fail(VDI_E_INVALID, "%s must use the regular layout", what);
+        if (!v->offset) return fail(VDI_E_INVALID, "%s: compact layout needs offset", what);
+    } else if (v->layout != VDI_LAYOUT_REGULAR) {
+        return fail(VDI_E_INVALID, "%s: unknown layout %d", what, v->layout);
+    }
+    return VDI_OK;
+}
+
+static vdi_status check_tau(const vdi_tau_t* tau, bool allow_learned)
+{
+    if (!tau) return fail(VDI_E_INVALID, "tau is NULL");
+    if (tau->mode == VDI_TAU_FIXED) {
+        if (!(tau->tau >= 0.0f)) return fail(VDI_E_INVALID, "fixed tau must be >= 0");
+        return VDI_OK;
+    }
+    if (tau->mode == VDI_TAU_LEARNED && !allow_learned)
+        return fail(VDI_E_UNSUPPORTED, "learned thresholds are not available for this operation");
+    if (tau->mode != VDI_TAU_BISECT && tau->mode != VDI_TAU_LEARNED)
+        return fail(VDI_E_INVALID, "unknown tau mode %d", tau->mode);
+    if (tau->iters < 1 || tau->iters > 24) return fail(VDI_E_INVALID, "iters %d outside [1, 24]", tau->iters);
+    if (!(tau->gamma_max > 1.7320509f)) return fail(VDI_E_INVALID, "gamma_max must exceed sqrt(3)");
+    return VDI_OK;
+}
+
+}  // namespace vdi
+
+using namespace vdi;
+
+extern "C" {
+
+const char* vdi_last_error(void) { return g_err; }
+
+vdi_status vdi_ctx_create(vdi_ctx** out, int device)
+{
+    if (!out) return fail(VDI_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    VDI_HIP_CHECK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(VDI_E_INVALID, "device %d of %d", device, n);
+    VDI_HIP_CHECK(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    VDI_HIP_CHECK(hipGetDeviceProperties(&prop, device));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(VDI_E_UNSUPPORTED, "libvdi is built for gfx950, device is %s", prop.gcnArchName);
+    vdi_ctx* c = new vdi_ctx();
+    c->device = device;
+    c->scratch = nullptr;
+    c->scratch_bytes = 0;
+    hipError_t e = hipMalloc(&c->status, 64);
+    if (e == hipSuccess) e = hipMemset(c->status, 0, 64);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(VDI_E_HIP, "status allocation failed: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return VDI_OK;
+}
+
+vdi_status vdi_ctx_destroy(vdi_ctx* ctx)
+{
+    if (!ctx) return VDI_OK;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    if (ctx->scratch) hipFree(ctx->scratch);
+    if (ctx->status) hipFree(ctx->status);
+    delete ctx;
+    return VDI_OK;
+}
+
+vdi_status vdi_ctx_device_status(vdi_ctx* ctx, int32_t* flags, void* stream)
+{
+    if (!ctx || !flags) return fail(VDI_E_INVALID, "ctx/flags is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    VDI_HIP_CHECK(hipStreamSynchronize(s));
+    int32_t v = 0;
+    VDI_HIP_CHECK(hipMemcpy(&v, ctx->status, sizeof v, hipMemcpyDeviceToHost));
+    VDI_HIP_CHECK(hipMemset(ctx->status, 0, sizeof v));
+    *flags = v;
+    return VDI_OK;
+}
+
+vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vdi_camera_t* cam,
+                        const vdi_tf_t* tf, float step, const vdi_tau_t* tau, vdi_t* out, void* stream)
+{
+    if (!ctx || !bricks || !cam || !tf || !out) return fail(VDI_E_INVALID, "NULL argument");
+    if (k < 1) return fail(VDI_E_INVALID, "k must be >= 1");
+    if (cam->width <= 0 || cam->height <= 0) return fail(VDI_E_INVALID, "camera size");
+    if (!tf->rgba || tf->entries < 2 || tf->entries > VDI_MAX_TF)
+        return fail(VDI_E_INVALID, "transfer function needs 2..%d entries", VDI_MAX_TF);
+    if (!(step > 0.0f)) return fail(VDI_E_INVALID, "step must be > 0");
+    vdi_status st = check_tau(tau, false);
+    if (st != VDI_OK) return st;
+    const int dtype = bricks[0].dtype;
+    if (dtype != VDI_F32 && dtype != VDI_F16) return fail(VDI_E_INVALID, "brick dtype %d", dtype);
+    for (int r = 0; r < k; ++r) {
+        const vdi_brick_t& b = bricks[r];
+        if (!b.data) return fail(VDI_E_INVALID, "brick %d: data is NULL", r);
+        if (b.dtype != dtype) return fail(VDI_E_INVALID, "bricks must share one dtype");
+        for (int a = 0; a < 3; ++a) {
+            if (b.full_dim[a] != bricks[0].full_dim[a] || b.full_dim[a] < 1)
+                return fail(VDI_E_INVALID, "brick %d: full_dim mismatch", r);
+            int n = b.full_dim[a];
+            if (b.lo[a] < 0 || b.hi[a] > n || b.lo[a] >= b.hi[a])
+                return fail(VDI_E_INVALID, "brick %d: owned box axis %d is [%d,%d) of %d", r, a, b.lo[a], b.hi[a], n);
+            int need_lo = std::max(b.lo[a] - 1, 0), need_hi = std::min(b.hi[a] + 1, n);
+            if (b.data_lo[a] > need_lo || b.data_lo[a] + b.data_dim[a] < need_hi || b.data_dim[a] < 1)
+                return fail(VDI_E_INVALID, "brick %d: data box axis %d does not cover the owned box plus one voxel", r, a);
+        }
+        st = check_vdi(&out[r], "out", true);
+        if (st != VDI_OK) return st;
+        if (out[r].width != cam->width || out[r].height != cam->height)
+            return fail(VDI_E_INVALID, "out[%d] is %dx%d, camera %dx%d", r, out[r].width, out[r].height, cam->width,
+                        cam->height);
+        if (out[r].ref_step != out[0].ref_step) return fail(VDI_E_INVALID, "outputs must share ref_step");
+        if (out[r].layout != out[0].layout) return fail(VDI_E_INVALID, "outputs must share one layout");
+        if (out[r].max_n != out[0].max_n) return fail(VDI_E_INVALID, "outputs must share max_n");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t npix = (size_t)cam->width * cam->height;
+    const bool compact = out[0].layout == VDI_LAYOUT_COMPACT;
+
+    GenParams P;
+    memset(&P, 0, sizeof P);
+    P.cam = to_cam(cam);
+    for (int a = 0; a < 3; ++a) P.n[a] = bricks[0].full_dim[a];
+    P.step = step;
+    P.l_step = step / out[0].ref_step;
+    P.mode = tau->mode;
+    P.tau = tau->tau;
+    P.iters = tau->iters;
+    P.gmax = tau->gamma_max;
+    P.max_n = out[0].max_n;
+    P.tf_entries = tf->entries;
+    P.tf = (const float4*)tf->rgba;
+    P.status = ctx->status;
+
+    // compact outputs without a gamma plane borrow scratch for it
+    size_t gamma_bytes = 0, scan_bytes = 0;
+    if (compact) {
+        gamma_bytes = npix * sizeof(float) * kGenBricksPerLaunch;
+        scan_bytes = scan_scratch_bytes(npix);
+        st = ensure_scratch(ctx, gamma_bytes + scan_bytes + 256);
+        if (st != VDI_OK) return st;
+    }
+    for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
+        int nb = std::min(k - r0, kGenBricksPerLaunch);
+        GenBricks B;
+        memset(&B, 0, sizeof B);
+        for (int i = 0; i < nb; ++i) {
+            const vdi_brick_t& b = bricks[r0 + i];
+            vdi_t& o = out[r0 + i];
+            GenBrick& g = B.b[i];
+            g.data = b.data;
+            g.color = (float4*)o.color;
+            g.depth = (float2*)o.depth;
+            g.count = o.count;
+            g.gamma = o.gamma;
+            if (compact && !g.gamma) g.gamma = (float*)ctx->scratch + (size_t)i * npix;
+            g.offset = o.offset;
+            g.capacity = o.capacity;
+            for (int a = 0; a < 3; ++a) {
+                g.lo[a] = b.lo[a];
+                g.hi[a] = b.hi[a];
+                g.dlo[a] = b.data_lo[a];
+                g.ddim[a] = b.data_dim[a];
+            }
+        }
+        if (!compact) {
+            launch_generate(0, dtype, P, B, nb, s);
+            if ((st = launched()) != VDI_OK) return st;
+            continue;
+        }
+        // compact (Sec. 4): search -> prefix sum of counts -> write at offsets
+        launch_generate(1, dtype, P, B, nb, s);
+        if ((st = launched()) != VDI_OK) return st;
+        void* scan_scratch = (char*)ctx->scratch + gamma_bytes;
+        for (int i = 0; i < nb; ++i) {
+            launch_scan(out[r0 + i].count, out[r0 + i].offset, npix, scan_scratch, s);
+            if ((st = launched()) != VDI_OK) return st;
+        }
+        launch_generate(2, dtype, P, B, nb, s);
+        if ((st = launched()) != VDI_OK) return st;
+    }
+    return VDI_OK;
+}
+
+vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* tau, vdi_t* out, void* stream)
+{
+    if (!ctx || !in || !out) return fail(VDI_E_INVALID, "NULL argument");
+    if (k < 1 || k > VDI_MAX_INPUTS) return fail(VDI_E_INVALID, "k=%d outside [1, %d]", k, VDI_MAX_INPUTS);
+    vdi_status st = check_tau(tau, false);
+    if (st != VDI_OK) return st;
+    if ((st = check_vdi(out, "out", false)) != VDI_OK) return st;
+    CompParams P;
+    memset(&P, 0, sizeof P);
+    int seq_cap = 0;
+    for (int r = 0; r < k; ++r) {
+        if ((st = check_vdi(&in[r], "in", true)) != VDI_OK) return st;
+        if (in[r].width != out->width || in[r].height != out->height)
+            return fail(VDI_E_INVALID, "in[%d] is %dx%d, out %dx%d", r, in[r].width, in[r].height, out->width,
+                        out->height);
+        if (in[r].ref_step != out->ref_step) return fail(VDI_E_INVALID, "in[%d].ref_step differs from out", r);
+        P.in[r].color = (const float4*)in[r].color;
+        P.in[r].depth = (const float2*)in[r].depth;
+        P.in[r].count = in[r].count;
+        P.in[r].offset = in[r].offset;
+        P.in[r].max_n = in[r].max_n;
+        P.in[r].compact = in[r].layout == VDI_LAYOUT_COMPACT;
+        P.in[r].capacity = P.in[r].compact ? in[r].capacity
+                                           : (uint64_t)in[r].max_n * (uint64_t)in[r].width * in[r].height;
+        seq_cap += in[r].max_n;
+    }
+    size_t lds = (size_t)64 * (2 * (size_t)seq_cap + 12 * (size_t)k);
+    if (lds > 160 * 1024) return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", seq_cap);
+    P.k = k;
+    P.npix = (uint32_t)((size_t)out->width * out->height);
+    P.inv_ref = 1.0f / out->ref_step;
+    P.mode = tau->mode;
+    P.tau = tau->tau;
+    P.iters = tau->iters;
+    P.gmax = tau->gamma_max;
+    P.out_n = out->max_n;
+    P.out_color = (float4*)out->color;
+    P.out_depth = (float2*)out->depth;
+    P.out_count = out->count;
+    P.out_gamma = out->gamma;
+    P.status = ctx->status;
+    P.seq_cap = seq_cap;
+    launch_composite(P, (hipStream_t)stream);
+    return launched();
+}
+
+vdi_status vdi_render_original_view(vdi_ctx* ctx, const vdi_t* v, float* rgba, void* stream)
+{
+    if (!ctx || !rgba) return fail(VDI_E_INVALID, "NULL argument");
+    vdi_status st = check_vdi(v, "vdi", true);
+    if (st != VDI_OK) return st;
+    uint32_t npix = (uint32_t)((size_t)v->width * v->height);
+    const bool compact = v->layout == VDI_LAYOUT_COMPACT;
+    uint64_t cap = compact ? v->capacity : (uint64_t)v->max_n * npix;
+    launch_render((const float4*)v->color, (const float2*)v->depth, v->count, compact ? v->offset : nullptr, cap,
+                  v->max_n, npix, 1.0f / v->ref_step, (float4*)rgba, ctx->status, (hipStream_t)stream);
+    return launched();
+}
+
+vdi_status vdi_debug_rays(vdi_ctx* ctx, const vdi_camera_t* cam, float step, float* o, float* d, float* tn,
+                          float* tf, int32_t* nsamples, void* stream)
+{
+    if (!ctx || !cam || !o || !d || !tn || !tf || !nsamples) return fail(VDI_E_INVALID, "NULL argument");
+    if (cam->width <= 0 || cam->height <= 0 || !(step > 0.0f)) return fail(VDI_E_INVALID, "bad camera or step");
+    launch_rays(to_cam(cam), step, o, d, tn, tf, nsamples, (hipStream_t)stream);
+    return launched();
+}
+
+}  // extern "C"

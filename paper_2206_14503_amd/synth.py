@@ -257,18 +257,21 @@ def dense_interleaved_lists(k: int, n_per: int, npix: int, seed: int, depth_rang
                             device: str = "cpu", alpha_range=(0.02, 0.6)):
     """k rank lists of exactly n_per supersegments for each of npix pixels.
 
-    Per pixel, 2*k*n_per sorted uniform cut points in [0, depth_range] give
-    k*n_per disjoint intervals; a seeded shuffle assigns them to ranks, so the
-    ranks interleave along every ray.  Colour is U(0,1)^3, per-unit opacity
-    U(alpha_range).  Returns torch tensors (color [k, n_per, npix, 4], depth
-    [k, n_per, npix, 2], count [k, npix]) in slot-major regular layout.
+    Per pixel, 2*k*n_per increasing cut points in (0, depth_range) give
+    k*n_per disjoint intervals (gaps between consecutive cuts are U(0.05,1.05)
+    before normalisation, so no two cuts coincide in fp32); a seeded shuffle
+    assigns the intervals to ranks, so the ranks interleave along every ray.
+    Colour is U(0,1)^3, per-unit opacity U(alpha_range).  Returns torch tensors
+    (color [k, n_per, npix, 4], depth [k, n_per, npix, 2], count [k, npix]) in
+    slot-major regular layout.
     """
     import torch
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
     total = k * n_per
-    cuts = torch.rand((npix, 2 * total), generator=gen, device=device, dtype=torch.float32)
-    cuts = torch.sort(cuts * depth_range, dim=1).values
+    gaps = torch.rand((npix, 2 * total + 1), generator=gen, device=device, dtype=torch.float64) + 0.05
+    cuts = torch.cumsum(gaps, dim=1)
+    cuts = (cuts[:, :-1] / cuts[:, -1:] * depth_range).to(torch.float32)
     front, back = cuts[:, 0::2], cuts[:, 1::2]                  # [npix, total]
     keys = torch.rand((npix, total), generator=gen, device=device)
     perm = torch.argsort(keys, dim=1)                            # cell ids in rank-major order

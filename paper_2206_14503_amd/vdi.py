@@ -1,0 +1,268 @@
+"""ctypes binding of libvdi (include/vdi.h).
+
+Argument marshalling only: every step of generation, compositing and
+rendering runs in the HIP kernels of libvdi.so.  torch tensors supply device
+memory and the current HIP stream.  If libvdi.so is missing the calls raise;
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvdi.so")
+
+REGULAR, COMPACT = 0, 1
+FIXED, BISECT, LEARNED = 0, 1, 2
+F32, F16 = 0, 1
+
+_STATUS = {0: "VDI_OK", -1: "VDI_E_INVALID", -2: "VDI_E_UNSUPPORTED", -3: "VDI_E_HIP", -4: "VDI_E_INPUT",
+           -5: "VDI_E_CAPACITY"}
+
+
+class VdiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+# ---------------------------------------------------------------- C structs (mirror include/vdi.h)
+
+class vdi_t(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("max_n", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("ref_step", ctypes.c_float), ("color", ctypes.c_void_p),
+                ("depth", ctypes.c_void_p), ("count", ctypes.c_void_p), ("offset", ctypes.c_void_p),
+                ("gamma", ctypes.c_void_p), ("capacity", ctypes.c_uint64)]
+
+
+class vdi_brick_t(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("full_dim", ctypes.c_int32 * 3),
+                ("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3), ("data_lo", ctypes.c_int32 * 3),
+                ("data_dim", ctypes.c_int32 * 3)]
+
+
+class vdi_camera_t(ctypes.Structure):
+    _fields_ = [("ortho", ctypes.c_int32), ("eye", ctypes.c_float * 3), ("fwd", ctypes.c_float * 3),
+                ("right", ctypes.c_float * 3), ("up", ctypes.c_float * 3), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32)]
+
+
+class vdi_tf_t(ctypes.Structure):
+    _fields_ = [("rgba", ctypes.c_void_p), ("entries", ctypes.c_int32)]
+
+
+class vdi_tau_t(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("tau", ctypes.c_float), ("iters", ctypes.c_int32),
+                ("gamma_max", ctypes.c_float), ("mlp", ctypes.c_void_p), ("fallback_tol", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvdi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2206_14503_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I = ctypes.c_void_p, ctypes.c_int
+        L.vdi_last_error.restype = ctypes.c_char_p
+        L.vdi_ctx_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), I]
+        L.vdi_ctx_destroy.argtypes = [P]
+        L.vdi_ctx_device_status.argtypes = [P, ctypes.POINTER(ctypes.c_int32), P]
+        L.vdi_generate.argtypes = [P, ctypes.POINTER(vdi_brick_t), I, ctypes.POINTER(vdi_camera_t),
+                                   ctypes.POINTER(vdi_tf_t), ctypes.c_float, ctypes.POINTER(vdi_tau_t),
+                                   ctypes.POINTER(vdi_t), P]
+        L.vdi_composite.argtypes = [P, ctypes.POINTER(vdi_t), I, ctypes.POINTER(vdi_tau_t), ctypes.POINTER(vdi_t), P]
+        L.vdi_render_original_view.argtypes = [P, ctypes.POINTER(vdi_t), P, P]
+        L.vdi_debug_rays.argtypes = [P, ctypes.POINTER(vdi_camera_t), ctypes.c_float, P, P, P, P, P, P]
+        for name in ("vdi_ctx_create", "vdi_ctx_destroy", "vdi_ctx_device_status", "vdi_generate", "vdi_composite",
+                     "vdi_render_original_view", "vdi_debug_rays"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise VdiError(rc, lib().vdi_last_error().decode())
+
+
+_ctx = {}
+
+
+def context(device: Optional[int] = None) -> ctypes.c_void_p:
+    dev = torch.cuda.current_device() if device is None else device
+    if dev not in _ctx:
+        h = ctypes.c_void_p()
+        _check(lib().vdi_ctx_create(ctypes.byref(h), dev))
+        _ctx[dev] = h
+    return _ctx[dev]
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------- Python-side VDI
+
+@dataclasses.dataclass
+class VDI:
+    """A VDI held in torch tensors.
+
+    regular: color [max_n, H*W, 4], depth [max_n, H*W, 2]
+    compact: color [capacity, 4], depth [capacity, 2], offset [H*W+1] (int32 storage of uint32)
+    count [H*W] int32, gamma [H*W] float32 or None."""
+    width: int
+    height: int
+    max_n: int
+    ref_step: float
+    layout: int
+    color: torch.Tensor
+    depth: torch.Tensor
+    count: torch.Tensor
+    offset: Optional[torch.Tensor] = None
+    gamma: Optional[torch.Tensor] = None
+
+    @property
+    def npix(self) -> int:
+        return self.width * self.height
+
+    def c(self) -> vdi_t:
+        cap = self.color.shape[0] if self.layout == COMPACT else 0
+        return vdi_t(self.width, self.height, self.max_n, self.layout, self.ref_step, _ptr(self.color),
+                     _ptr(self.depth), _ptr(self.count), _ptr(self.offset), _ptr(self.gamma), cap)
+
+    @staticmethod
+    def empty(width: int, height: int, max_n: int, ref_step: float, layout: int = REGULAR,
+              capacity: Optional[int] = None, device=None, with_gamma: bool = True) -> "VDI":
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        P = width * height
+        if layout == REGULAR:
+            color = torch.empty((max_n, P, 4), dtype=torch.float32, device=dev)
+            depth = torch.empty((max_n, P, 2), dtype=torch.float32, device=dev)
+            offset = None
+        else:
+            cap = capacity if capacity is not None else max_n * P
+            color = torch.empty((max(cap, 1), 4), dtype=torch.float32, device=dev)
+            depth = torch.empty((max(cap, 1), 2), dtype=torch.float32, device=dev)
+            offset = torch.empty((P + 1,), dtype=torch.int32, device=dev)
+        count = torch.empty((P,), dtype=torch.int32, device=dev)
+        gamma = torch.empty((P,), dtype=torch.float32, device=dev) if with_gamma else None
+        return VDI(width, height, max_n, ref_step, layout, color, depth, count, offset, gamma)
+
+
+def camera_c(cam) -> vdi_camera_t:
+    f3 = lambda v: (ctypes.c_float * 3)(*v)
+    return vdi_camera_t(int(cam.ortho), f3(cam.eye), f3(cam.fwd), f3(cam.right), f3(cam.up), int(cam.width),
+                        int(cam.height))
+
+
+def tau_c(mode: int, tau: float = 0.0, iters: int = 10, gamma_max: float = 2.0, mlp=None,
+          fallback_tol: float = 0.1) -> vdi_tau_t:
+    return vdi_tau_t(mode, tau, iters, gamma_max, mlp, fallback_tol)
+
+
+@dataclasses.dataclass
+class DeviceBrick:
+    """A brick's halo'd data on the device plus its placement (synth.Brick)."""
+    data: torch.Tensor        # [dz, dy, dx] float32 or float16
+    lo: Sequence[int]
+    hi: Sequence[int]
+    data_lo: Sequence[int]
+    full_dim: Sequence[int]
+
+    def c(self) -> vdi_brick_t:
+        dz, dy, dx = self.data.shape
+        dt = F16 if self.data.dtype == torch.float16 else F32
+        i3 = lambda v: (ctypes.c_int32 * 3)(*[int(x) for x in v])
+        return vdi_brick_t(_ptr(self.data), dt, i3(self.full_dim), i3(self.lo), i3(self.hi), i3(self.data_lo),
+                           i3((dx, dy, dz)))
+
+
+def device_bricks(vol, bricks, device=None) -> List[DeviceBrick]:
+    """Copy each brick's halo'd block of a [nz, ny, nx] volume (numpy or torch) to the device."""
+    import numpy as np
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    nz, ny, nx = vol.shape
+    out = []
+    for b in bricks:
+        blk = vol[b.data_lo[2]:b.data_hi[2], b.data_lo[1]:b.data_hi[1], b.data_lo[0]:b.data_hi[0]]
+        t = torch.from_numpy(np.ascontiguousarray(blk)) if isinstance(blk, np.ndarray) else blk
+        out.append(DeviceBrick(t.to(dev).contiguous(), b.lo, b.hi, b.data_lo, (nx, ny, nz)))
+    return out
+
+
+# ---------------------------------------------------------------- entry points
+
+def generate(bricks: Sequence[DeviceBrick], cam, tf: torch.Tensor, step: float, ref_step: float, mode: int,
+             tau: float = 0.0, max_n: int = 8, iters: int = 10, layout: int = REGULAR,
+             capacity: Optional[int] = None, outs: Optional[List[VDI]] = None, gamma_max: float = 2.0) -> List[VDI]:
+    """vdi_generate: one sub-VDI per brick."""
+    k = len(bricks)
+    if outs is None:
+        outs = [VDI.empty(cam.width, cam.height, max_n, ref_step, layout, capacity) for _ in range(k)]
+    bc = (vdi_brick_t * k)(*[b.c() for b in bricks])
+    oc = (vdi_t * k)(*[o.c() for o in outs])
+    cc = camera_c(cam)
+    tfc = vdi_tf_t(_ptr(tf), tf.shape[0])
+    tc = tau_c(mode, tau, iters, gamma_max)
+    _check(lib().vdi_generate(context(), bc, k, ctypes.byref(cc), ctypes.byref(tfc), step, ctypes.byref(tc), oc,
+                              _stream()))
+    return outs
+
+
+def composite(vdis: Sequence[VDI], mode: int, tau: float = 0.0, max_n: int = 8, iters: int = 10,
+              out: Optional[VDI] = None, gamma_max: float = 2.0) -> VDI:
+    """vdi_composite: k-way merge + re-segmentation into one regular VDI."""
+    k = len(vdis)
+    v0 = vdis[0]
+    if out is None:
+        out = VDI.empty(v0.width, v0.height, max_n, v0.ref_step, REGULAR)
+    ic = (vdi_t * k)(*[v.c() for v in vdis])
+    oc = out.c()
+    tc = tau_c(mode, tau, iters, gamma_max)
+    _check(lib().vdi_composite(context(), ic, k, ctypes.byref(tc), ctypes.byref(oc), _stream()))
+    return out
+
+
+def render_original_view(v: VDI, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """vdi_render_original_view: premultiplied RGBA [H*W, 4]."""
+    if out is None:
+        out = torch.empty((v.npix, 4), dtype=torch.float32, device=v.color.device)
+    vc = v.c()
+    _check(lib().vdi_render_original_view(context(), ctypes.byref(vc), _ptr(out), _stream()))
+    return out
+
+
+def device_status() -> int:
+    flags = ctypes.c_int32(0)
+    _check(lib().vdi_ctx_device_status(context(), ctypes.byref(flags), _stream()))
+    return int(flags.value)
+
+
+def debug_rays(cam, step: float):
+    P = cam.width * cam.height
+    dev = torch.device("cuda", torch.cuda.current_device())
+    o = torch.empty((P, 3), dtype=torch.float32, device=dev)
+    d = torch.empty((P, 3), dtype=torch.float32, device=dev)
+    tn = torch.empty((P,), dtype=torch.float32, device=dev)
+    tf = torch.empty((P,), dtype=torch.float32, device=dev)
+    ns = torch.empty((P,), dtype=torch.int32, device=dev)
+    cc = camera_c(cam)
+    _check(lib().vdi_debug_rays(context(), ctypes.byref(cc), step, _ptr(o), _ptr(d), _ptr(tn), _ptr(tf), _ptr(ns),
+                                _stream()))
+    return dict(o=o, d=d, tn=tn, tf=tf, samples=ns)
