@@ -121,17 +121,23 @@ typedef struct {
  *  BISECT:  per list, `iters` halvings of [0, gamma_max]; a midpoint is
  *           feasible iff it yields at most max_n supersegments; the result is
  *           the upper bracket.
- *  LEARNED: per list, gamma predicted by the MLP in `mlp` (a vdi_mlp_t*) from a
- *           64-bin opacity histogram, accepted if the resulting count c
- *           satisfies ceil((1-fallback_tol)*min(N, cmax)) <= c <= N (cmax:
- *           count at the smallest bisection threshold), else BISECT. */
+ *  LEARNED: (an extension beyond the paper) per list, gamma = 2^y with y the
+ *           output of the MLP `mlp` (a vdi_mlp_t*) on the list's 64-bin opacity
+ *           histogram (see vdi_tau_features), clamped to [gamma_max*2^-iters,
+ *           gamma_max].  The result is kept if its count c satisfies
+ *           m - floor(fallback_tol*m) <= c <= N with m = min(N, cmax) (cmax:
+ *           the count at the smallest bisection threshold); otherwise the list
+ *           is regenerated by BISECT.  Lists with at most N non-transparent
+ *           samples take the bisection's result directly (every threshold is
+ *           feasible there).  Regular layout only. */
 typedef struct {
     int32_t mode;            /* vdi_tau_mode */
     float tau;
-    int32_t iters;           /* B, 1..30 */
+    int32_t iters;           /* B, 1..24 */
     float gamma_max;         /* > sqrt(3), normally 2 */
-    const void *mlp;
-    float fallback_tol;
+    const void *mlp;         /* LEARNED: const vdi_mlp_t* */
+    float fallback_tol;      /* LEARNED: 0.1 */
+    float feature_scale;     /* LEARNED: histogram counts are divided by this (s_ref) */
 } vdi_tau_t;
 
 /* Context: one per device and thread of use.  vdi_ctx_create makes `device`
@@ -172,6 +178,60 @@ vdi_status vdi_composite(vdi_ctx *ctx, const vdi_t *in, int k, const vdi_tau_t *
  * supersegments are composited front to back with the over operator using
  * their total opacities.  rgba: [H*W][4] premultiplied, fp32. */
 vdi_status vdi_render_original_view(vdi_ctx *ctx, const vdi_t *vdi, float *rgba, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned threshold (an extension beyond the paper: a regressor replaces the
+ * per-ray bisection of Sec. 2.4).
+ *
+ * MLP 64 -> 128 -> 128 -> 1, GELU (erf form) after both hidden layers, linear
+ * output = log2(gamma).  Parameters are one flat array in this order:
+ * W1 [128][64] (out, in), b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1]
+ * (VDI_MLP_PARAMS values).  The kernels multiply bf16 matrices and bf16
+ * activations on the matrix cores with fp32 accumulation; biases are read from
+ * the fp32 copy.  Hidden activations are rounded to bf16 between layers.
+ * ------------------------------------------------------------------------ */
+#define VDI_MLP_PARAMS 24961
+#define VDI_MLP_ACT_FLOATS 384   /* per row: z1[128], z2[128] fp32, h1[128], h2[128] bf16 */
+
+typedef struct {
+    uint16_t *w_bf16;        /* [VDI_MLP_PARAMS] bf16 bits */
+    float *w_f32;            /* [VDI_MLP_PARAMS] fp32 master copy */
+} vdi_mlp_t;
+
+/* Per brick-ray features for the regressor.  Over the samples brick r owns
+ * along pixel p's ray (same grid and classification as vdi_generate):
+ * hist[(r*P + p)*64 + j] = bf16(#{non-transparent samples with opacity a in
+ * (j/64, (j+1)/64]} / feature_scale), nnt[r*P + p] = number of non-transparent
+ * samples, cmax[r*P + p] = min(count at threshold gamma_max*2^-iters, N+1).
+ * tau supplies iters, gamma_max and feature_scale; N = max_n. */
+vdi_status vdi_tau_features(vdi_ctx *ctx, const vdi_brick_t *bricks, int k, const vdi_camera_t *cam,
+                            const vdi_tf_t *tf, float step, float ref_step, int max_n, const vdi_tau_t *tau,
+                            uint16_t *hist, int32_t *nnt, int32_t *cmax, void *stream);
+
+/* y[i] = MLP(x[i]) for rows i < rows; x is [rows][64] bf16.  If acts is not
+ * NULL it receives [rows][VDI_MLP_ACT_FLOATS] activations for the backward. */
+vdi_status vdi_mlp_forward(vdi_ctx *ctx, const vdi_mlp_t *mlp, const uint16_t *x, int rows, float *y,
+                           float *acts, void *stream);
+
+/* grad[VDI_MLP_PARAMS] = sum over rows of d(y_i)/d(params) * dy[i], from the
+ * activations of vdi_mlp_forward on the same x.  Deterministic (fixed
+ * reduction order); uses context scratch. */
+vdi_status vdi_mlp_backward(vdi_ctx *ctx, const vdi_mlp_t *mlp, const uint16_t *x, const float *acts,
+                            const float *dy, int rows, float *grad, void *stream);
+
+/* One Adam step (step >= 1) on w_f32 with moments m, v ([VDI_MLP_PARAMS]);
+ * refreshes w_bf16. */
+vdi_status vdi_mlp_adam(vdi_ctx *ctx, vdi_mlp_t *mlp, const float *grad, float *m, float *v, int step, float lr,
+                        float beta1, float beta2, float eps, void *stream);
+
+/* Counts of the learned path since the last call (synchronises `stream`):
+ * stats[0] kept regressed thresholds, [1] lists taking the all-feasible
+ * shortcut, [2] fallbacks to bisection, [3] empty lists.  Clears them. */
+vdi_status vdi_learned_stats(vdi_ctx *ctx, int64_t *stats, void *stream);
+
+/* Diagnostic: D = A B for 16x16 bf16 A, B (row-major) through one matrix-core
+ * instruction with the fragment layout the MLP kernels use; D fp32 16x16. */
+vdi_status vdi_debug_mfma(vdi_ctx *ctx, const uint16_t *A, const uint16_t *B, float *D, void *stream);
 
 /* Device-side status of the context since the last call to this function
  * (synchronises `stream` first): bit 0 = a compact output overflowed its

@@ -746,3 +746,108 @@ void orc_classify(const float *tf, int entries, float s, double *rgba)
     for (int ch = 0; ch < 3; ++ch) rgba[ch] = c.rgb[ch];
     rgba[3] = c.a;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Learned-threshold features (not in the paper: the extension that replaces */
+/* the per-ray search by a regression from an opacity histogram)            */
+/* ------------------------------------------------------------------------ */
+
+/* bf16 round-to-nearest-even of an fp32 value (returned as float). */
+static float bf16_round(float x)
+{
+    union { float f; uint32_t u; } v = { x };
+    if ((v.u & 0x7f800000u) == 0x7f800000u) return x;
+    uint32_t lsb = (v.u >> 16) & 1u;
+    v.u = (v.u + 0x7fffu + lsb) & 0xffff0000u;
+    return v.f;
+}
+
+/* Per brick-ray features over the owned samples:
+ *   hist [nb][npix][64]: bin j counts non-transparent samples whose fp32
+ *       opacity a lies in ((j)/64, (j+1)/64], i.e. j = min(63, ceil(64a)-1),
+ *       divided by s_ref and rounded to bf16;
+ *   nnt  [nb][npix]: number of non-transparent samples;
+ *   cmax [nb][npix]: supersegment count at the smallest threshold the
+ *       bisection can return, gmax * 2^-iters. */
+int orc_features(const void *vol_data, int vol_dtype, const int32_t *n,
+                 const int32_t *brick_lo, const int32_t *brick_hi, int nb,
+                 const orc_camera *cam, const float *tf, int entries, float step, float ref,
+                 int iters, float gmax, float s_ref, const int32_t *pixels, int npix,
+                 float *hist, int32_t *nnt, int32_t *cmax, int nthreads)
+{
+    if (!vol_data || !n || nb <= 0 || !cam || !tf || npix < 0 || !(s_ref > 0.0f)) return -1;
+    orc_volume vol = { vol_data, vol_dtype, { n[0], n[1], n[2] } };
+    int cap = max_samples(step);
+    set_threads(nthreads);
+    double gmin = ldexp((double)gmax, -iters);
+#pragma omp parallel
+    {
+        orc_elem *e = (orc_elem *)malloc(sizeof(orc_elem) * (size_t)cap);
+        float *a32 = (float *)malloc(sizeof(float) * (size_t)cap);
+#pragma omp for schedule(dynamic, 64)
+        for (long long job = 0; job < (long long)nb * npix; ++job) {
+            int r = (int)(job / npix);
+            size_t q = (size_t)(job % npix);
+            int pix = pixels ? pixels[q] : (int)q;
+            orc_ray ray = make_ray(cam, pix % cam->width, pix / cam->width);
+            int contig = 1;
+            int ne = ray.hit ? brick_stream(&vol, brick_lo + 3 * r, brick_hi + 3 * r, &ray, tf, entries,
+                                            step, e, cap, &contig, a32) : 0;
+            int bins[64];
+            memset(bins, 0, sizeof bins);
+            int m = 0;
+            for (int i = 0; i < ne; ++i) {
+                if (a32[i] == 0.0f) continue;
+                int j = (int)ceilf(64.0f * a32[i]) - 1;
+                if (j > 63) j = 63;
+                if (j < 0) j = 0;
+                bins[j] += 1;
+                m += 1;
+            }
+            size_t o = (size_t)r * npix + q;
+            for (int j = 0; j < 64; ++j) hist[o * 64 + j] = bf16_round((float)bins[j] / s_ref);
+            nnt[o] = m;
+            orc_segrun R = { gmin, 0, 0, ref, 1 << 30, NULL, 0, 0, 0.0 };
+            seg_run(e, ne, &R);
+            cmax[o] = R.count;
+        }
+        free(e);
+        free(a32);
+    }
+    return 0;
+}
+
+/* Supersegment count of each brick-ray at a given per-ray threshold
+ * (gamma [nb][npix]) and the smallest |distance - gamma| on its path. */
+int orc_count_at(const void *vol_data, int vol_dtype, const int32_t *n,
+                 const int32_t *brick_lo, const int32_t *brick_hi, int nb,
+                 const orc_camera *cam, const float *tf, int entries, float step, float ref,
+                 const float *gamma, int limit, const int32_t *pixels, int npix,
+                 int32_t *count, double *margin, int nthreads)
+{
+    if (!vol_data || !n || nb <= 0 || !cam || !tf || npix < 0) return -1;
+    orc_volume vol = { vol_data, vol_dtype, { n[0], n[1], n[2] } };
+    int cap = max_samples(step);
+    set_threads(nthreads);
+#pragma omp parallel
+    {
+        orc_elem *e = (orc_elem *)malloc(sizeof(orc_elem) * (size_t)cap);
+#pragma omp for schedule(dynamic, 64)
+        for (long long job = 0; job < (long long)nb * npix; ++job) {
+            int r = (int)(job / npix);
+            size_t q = (size_t)(job % npix);
+            int pix = pixels ? pixels[q] : (int)q;
+            orc_ray ray = make_ray(cam, pix % cam->width, pix / cam->width);
+            int contig = 1;
+            int ne = ray.hit ? brick_stream(&vol, brick_lo + 3 * r, brick_hi + 3 * r, &ray, tf, entries,
+                                            step, e, cap, &contig, NULL) : 0;
+            size_t o = (size_t)r * npix + q;
+            orc_segrun R = { gamma[o], 0, 0, ref, limit, NULL, 0, 0, 0.0 };
+            seg_run(e, ne, &R);
+            count[o] = R.count;
+            if (margin) margin[o] = R.margin;
+        }
+        free(e);
+    }
+    return 0;
+}

@@ -110,6 +110,105 @@ static vdi_status check_tau(const vdi_tau_t* tau, bool allow_learned)
     return VDI_OK;
 }
 
+static GenBricks make_bricks(const vdi_brick_t* bricks, vdi_t* out, int r0, int nb)
+{
+    GenBricks B;
+    memset(&B, 0, sizeof B);
+    B.first = r0;
+    for (int i = 0; i < nb; ++i) {
+        const vdi_brick_t& b = bricks[r0 + i];
+        GenBrick& g = B.b[i];
+        g.data = b.data;
+        if (out) {
+            vdi_t& o = out[r0 + i];
+            g.color = (float4*)o.color;
+            g.depth = (float2*)o.depth;
+            g.count = o.count;
+            g.gamma = o.gamma;
+            g.offset = o.offset;
+            g.capacity = o.capacity;
+        }
+        for (int a = 0; a < 3; ++a) {
+            g.lo[a] = b.lo[a];
+            g.hi[a] = b.hi[a];
+            g.dlo[a] = b.data_lo[a];
+            g.ddim[a] = b.data_dim[a];
+        }
+    }
+    return B;
+}
+
+__global__ void fill_i32_kernel(int* p, int v, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+static void fill_i32(int* p, int v, size_t n, hipStream_t s)
+{
+    if (n) hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+}
+
+// Scratch layout of the learned path for nb bricks of npix pixels.
+struct LearnScratch {
+    size_t hist, nnt, cmax, y, list, cnt, total;
+};
+static LearnScratch learn_layout(size_t rays, int nb)
+{
+    LearnScratch L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t a = o; o += (bytes + 255) & ~(size_t)255; return a; };
+    L.hist = take(rays * 64 * sizeof(uint16_t));
+    L.nnt = take(rays * sizeof(int));
+    L.cmax = take(rays * sizeof(int));
+    L.y = take(rays * sizeof(float));
+    L.list = take(rays * sizeof(int));
+    L.cnt = take((size_t)nb * sizeof(int));
+    L.total = o;
+    return L;
+}
+
+static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const GenParams& P,
+                                   const vdi_tau_t* tau, vdi_t* out, int dtype, hipStream_t s)
+{
+    const size_t npix = (size_t)P.cam.width * P.cam.height;
+    const size_t rays = npix * (size_t)k;
+    if (rays >= ((size_t)1 << 31)) return fail(VDI_E_UNSUPPORTED, "too many brick-rays for the learned path");
+    LearnScratch Ls = learn_layout(rays, k);
+    vdi_status st = ensure_scratch(ctx, Ls.total);
+    if (st != VDI_OK) return st;
+    char* base = (char*)ctx->scratch;
+    LearnBufs Lb;
+    Lb.hist = (uint16_t*)(base + Ls.hist);
+    Lb.nnt = (int*)(base + Ls.nnt);
+    Lb.cmax = (int*)(base + Ls.cmax);
+    Lb.y = (const float*)(base + Ls.y);
+    Lb.fb_list = (int*)(base + Ls.list);
+    Lb.fb_count = (int*)(base + Ls.cnt);
+    Lb.stats = ctx->status + 4;
+    Lb.s_ref = tau->feature_scale;
+    Lb.tol = tau->fallback_tol;
+    const vdi_mlp_t* mlp = (const vdi_mlp_t*)tau->mlp;
+    fill_i32(Lb.fb_count, 0, (size_t)k, s);
+    for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
+        int nb = std::min(k - r0, kGenBricksPerLaunch);
+        GenBricks B = make_bricks(bricks, out, r0, nb);
+        launch_learned(0, dtype, P, B, nb, Lb, s);
+        if ((st = launched()) != VDI_OK) return st;
+    }
+    launch_mlp_fwd(mlp->w_bf16, mlp->w_f32, Lb.hist, (int)rays, (float*)(base + Ls.y), nullptr, s);
+    if ((st = launched()) != VDI_OK) return st;
+    for (int phase = 1; phase <= 2; ++phase) {
+        for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
+            int nb = std::min(k - r0, kGenBricksPerLaunch);
+            GenBricks B = make_bricks(bricks, out, r0, nb);
+            launch_learned(phase, dtype, P, B, nb, Lb, s);
+            if ((st = launched()) != VDI_OK) return st;
+        }
+    }
+    return VDI_OK;
+}
+
 }  // namespace vdi
 
 using namespace vdi;
@@ -176,8 +275,15 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
     if (!tf->rgba || tf->entries < 2 || tf->entries > VDI_MAX_TF)
         return fail(VDI_E_INVALID, "transfer function needs 2..%d entries", VDI_MAX_TF);
     if (!(step > 0.0f)) return fail(VDI_E_INVALID, "step must be > 0");
-    vdi_status st = check_tau(tau, false);
+    vdi_status st = check_tau(tau, true);
     if (st != VDI_OK) return st;
+    if (tau->mode == VDI_TAU_LEARNED) {
+        const vdi_mlp_t* mlp = (const vdi_mlp_t*)tau->mlp;
+        if (!mlp || !mlp->w_bf16 || !mlp->w_f32) return fail(VDI_E_INVALID, "learned mode needs tau->mlp");
+        if (!(tau->feature_scale > 0.0f)) return fail(VDI_E_INVALID, "learned mode needs feature_scale > 0");
+        if (!(tau->fallback_tol >= 0.0f && tau->fallback_tol < 1.0f))
+            return fail(VDI_E_INVALID, "fallback_tol must be in [0, 1)");
+    }
     const int dtype = bricks[0].dtype;
     if (dtype != VDI_F32 && dtype != VDI_F16) return fail(VDI_E_INVALID, "brick dtype %d", dtype);
     for (int r = 0; r < k; ++r) {
@@ -206,6 +312,8 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
     hipStream_t s = (hipStream_t)stream;
     const size_t npix = (size_t)cam->width * cam->height;
     const bool compact = out[0].layout == VDI_LAYOUT_COMPACT;
+    const bool learned = tau->mode == VDI_TAU_LEARNED;
+    if (learned && compact) return fail(VDI_E_UNSUPPORTED, "learned thresholds need the regular layout");
 
     GenParams P;
     memset(&P, 0, sizeof P);
@@ -230,10 +338,12 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
         st = ensure_scratch(ctx, gamma_bytes + scan_bytes + 256);
         if (st != VDI_OK) return st;
     }
+    if (learned) return generate_learned(ctx, bricks, k, P, tau, out, dtype, s);
     for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
         int nb = std::min(k - r0, kGenBricksPerLaunch);
         GenBricks B;
         memset(&B, 0, sizeof B);
+        B.first = r0;
         for (int i = 0; i < nb; ++i) {
             const vdi_brick_t& b = bricks[r0 + i];
             vdi_t& o = out[r0 + i];
@@ -298,8 +408,8 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
                                            : (uint64_t)in[r].max_n * (uint64_t)in[r].width * in[r].height;
         seq_cap += in[r].max_n;
     }
-    size_t lds = (size_t)64 * (2 * (size_t)seq_cap + 12 * (size_t)k);
-    if (lds > 160 * 1024) return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", seq_cap);
+    if (composite_lds_bytes(k, seq_cap) > 160 * 1024)
+        return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", seq_cap);
     P.k = k;
     P.npix = (uint32_t)((size_t)out->width * out->height);
     P.inv_ref = 1.0f / out->ref_step;
@@ -337,6 +447,123 @@ vdi_status vdi_debug_rays(vdi_ctx* ctx, const vdi_camera_t* cam, float step, flo
     if (!ctx || !cam || !o || !d || !tn || !tf || !nsamples) return fail(VDI_E_INVALID, "NULL argument");
     if (cam->width <= 0 || cam->height <= 0 || !(step > 0.0f)) return fail(VDI_E_INVALID, "bad camera or step");
     launch_rays(to_cam(cam), step, o, d, tn, tf, nsamples, (hipStream_t)stream);
+    return launched();
+}
+
+vdi_status vdi_tau_features(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vdi_camera_t* cam,
+                            const vdi_tf_t* tf, float step, float ref_step, int max_n, const vdi_tau_t* tau,
+                            uint16_t* hist, int32_t* nnt, int32_t* cmax, void* stream)
+{
+    if (!ctx || !bricks || !cam || !tf || !tau || !hist || !nnt || !cmax) return fail(VDI_E_INVALID, "NULL argument");
+    if (k < 1 || cam->width <= 0 || cam->height <= 0) return fail(VDI_E_INVALID, "bad k or camera");
+    if (!tf->rgba || tf->entries < 2 || tf->entries > VDI_MAX_TF) return fail(VDI_E_INVALID, "transfer function");
+    if (!(step > 0.0f) || !(ref_step > 0.0f)) return fail(VDI_E_INVALID, "step and ref_step must be > 0");
+    if (max_n < 1 || max_n > VDI_MAX_N) return fail(VDI_E_INVALID, "max_n");
+    if (tau->iters < 1 || tau->iters > 24 || !(tau->gamma_max > 1.7320509f) || !(tau->feature_scale > 0.0f))
+        return fail(VDI_E_INVALID, "tau: iters, gamma_max or feature_scale");
+    const int dtype = bricks[0].dtype;
+    for (int r = 0; r < k; ++r) {
+        const vdi_brick_t& b = bricks[r];
+        if (!b.data || b.dtype != dtype) return fail(VDI_E_INVALID, "brick %d: data/dtype", r);
+        for (int a = 0; a < 3; ++a) {
+            int n = b.full_dim[a];
+            if (n != bricks[0].full_dim[a] || b.lo[a] < 0 || b.hi[a] > n || b.lo[a] >= b.hi[a])
+                return fail(VDI_E_INVALID, "brick %d: owned box", r);
+            int need_lo = std::max(b.lo[a] - 1, 0), need_hi = std::min(b.hi[a] + 1, n);
+            if (b.data_lo[a] > need_lo || b.data_lo[a] + b.data_dim[a] < need_hi)
+                return fail(VDI_E_INVALID, "brick %d: data box", r);
+        }
+    }
+    GenParams P;
+    memset(&P, 0, sizeof P);
+    P.cam = to_cam(cam);
+    for (int a = 0; a < 3; ++a) P.n[a] = bricks[0].full_dim[a];
+    P.step = step;
+    P.l_step = step / ref_step;
+    P.mode = VDI_TAU_BISECT;
+    P.iters = tau->iters;
+    P.gmax = tau->gamma_max;
+    P.max_n = max_n;
+    P.tf_entries = tf->entries;
+    P.tf = (const float4*)tf->rgba;
+    P.status = ctx->status;
+    LearnBufs Lb;
+    memset(&Lb, 0, sizeof Lb);
+    Lb.hist = hist;
+    Lb.nnt = nnt;
+    Lb.cmax = cmax;
+    Lb.s_ref = tau->feature_scale;
+    hipStream_t s = (hipStream_t)stream;
+    for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
+        int nb = std::min(k - r0, kGenBricksPerLaunch);
+        GenBricks B = make_bricks(bricks, nullptr, r0, nb);
+        launch_learned(0, dtype, P, B, nb, Lb, s);
+        vdi_status st = launched();
+        if (st != VDI_OK) return st;
+    }
+    return VDI_OK;
+}
+
+static vdi_status check_mlp(const vdi_mlp_t* mlp)
+{
+    if (!mlp || !mlp->w_bf16 || !mlp->w_f32) return fail(VDI_E_INVALID, "mlp weights are NULL");
+    if (((uintptr_t)mlp->w_bf16 & 15) != 0) return fail(VDI_E_INVALID, "mlp->w_bf16 must be 16-byte aligned");
+    return VDI_OK;
+}
+
+vdi_status vdi_mlp_forward(vdi_ctx* ctx, const vdi_mlp_t* mlp, const uint16_t* x, int rows, float* y, float* acts,
+                           void* stream)
+{
+    if (!ctx || !x || !y) return fail(VDI_E_INVALID, "NULL argument");
+    vdi_status st = check_mlp(mlp);
+    if (st != VDI_OK) return st;
+    if (rows < 0) return fail(VDI_E_INVALID, "rows < 0");
+    if (((uintptr_t)x & 7) != 0) return fail(VDI_E_INVALID, "x must be 8-byte aligned");
+    if (rows == 0) return VDI_OK;
+    launch_mlp_fwd(mlp->w_bf16, mlp->w_f32, x, rows, y, acts, (hipStream_t)stream);
+    return launched();
+}
+
+vdi_status vdi_mlp_backward(vdi_ctx* ctx, const vdi_mlp_t* mlp, const uint16_t* x, const float* acts,
+                            const float* dy, int rows, float* grad, void* stream)
+{
+    if (!ctx || !x || !acts || !dy || !grad) return fail(VDI_E_INVALID, "NULL argument");
+    vdi_status st = check_mlp(mlp);
+    if (st != VDI_OK) return st;
+    if (rows <= 0) return fail(VDI_E_INVALID, "rows must be > 0");
+    int nb = (rows + mlp_rows_per_block() - 1) / mlp_rows_per_block();
+    st = ensure_scratch(ctx, (size_t)nb * mlp_params() * sizeof(float));
+    if (st != VDI_OK) return st;
+    launch_mlp_bwd(mlp->w_bf16, x, acts, dy, rows, (float*)ctx->scratch, grad, (hipStream_t)stream);
+    return launched();
+}
+
+vdi_status vdi_mlp_adam(vdi_ctx* ctx, vdi_mlp_t* mlp, const float* grad, float* m, float* v, int step, float lr,
+                        float beta1, float beta2, float eps, void* stream)
+{
+    if (!ctx || !grad || !m || !v) return fail(VDI_E_INVALID, "NULL argument");
+    vdi_status st = check_mlp(mlp);
+    if (st != VDI_OK) return st;
+    if (step < 1) return fail(VDI_E_INVALID, "step must be >= 1");
+    launch_mlp_adam(mlp->w_f32, mlp->w_bf16, grad, m, v, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+    return launched();
+}
+
+vdi_status vdi_learned_stats(vdi_ctx* ctx, int64_t* stats, void* stream)
+{
+    if (!ctx || !stats) return fail(VDI_E_INVALID, "NULL argument");
+    VDI_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+    int32_t v[4];
+    VDI_HIP_CHECK(hipMemcpy(v, ctx->status + 4, sizeof v, hipMemcpyDeviceToHost));
+    VDI_HIP_CHECK(hipMemset(ctx->status + 4, 0, sizeof v));
+    for (int i = 0; i < 4; ++i) stats[i] = v[i];
+    return VDI_OK;
+}
+
+vdi_status vdi_debug_mfma(vdi_ctx* ctx, const uint16_t* A, const uint16_t* B, float* D, void* stream)
+{
+    if (!ctx || !A || !B || !D) return fail(VDI_E_INVALID, "NULL argument");
+    launch_mfma_probe(A, B, D, (hipStream_t)stream);
     return launched();
 }
 

@@ -3,10 +3,16 @@
 //
 // One lane per pixel, one wavefront per block.  The lane first merges the k
 // front-to-back sorted input lists by front depth (ties: lower input index)
-// into a merge sequence of (input, slot) pairs kept in LDS; every later pass
-// (the threshold bisection and the final write) replays that sequence and
-// reads the supersegments straight from the inputs, so the inputs are read
-// from HBM once and re-read from cache.
+// into a merge sequence of (input, slot) pairs kept in LDS.  Every later scan
+// replays that sequence and reads the supersegments from the inputs (HBM the
+// first time, cache afterwards), with the next element's load issued before
+// the current one is processed.
+//
+// The per-pixel threshold bisection (Sec. 2.4, run again in compositing) is
+// evaluated two levels per scan: one scan carries three segmenter states, for
+// the midpoint m and for both midpoints of the next level, and the sequential
+// decisions are then replayed from their counts.  The result is identical to
+// B one-threshold scans, with about half as many scans over the data.
 #include "vdi_internal.h"
 #include "vdi_kernels.h"
 
@@ -22,7 +28,36 @@ struct CSeg {
     float T;           // transmittance
     float f, b, bt;    // front, back (incl. trailing gap/transparent), back of last non-transparent
     int open;
+    int count;
 };
+
+// An element prepared once per scan and shared by all segmenter states.
+struct CElem {
+    float f, b;
+    float r, g, bl;    // un-premultiplied colour
+    float e0, e1, e2;  // per-step premultiplied colour (Eq. 1 operand)
+    float at;          // total opacity over its length (Eq. 2)
+    float Te;          // 1 - at
+    bool transparent;
+};
+
+__device__ inline CElem prep(float4 c, float2 fb, float inv_ref)
+{
+    CElem e;
+    e.f = fb.x;
+    e.b = fb.y;
+    e.r = c.x;
+    e.g = c.y;
+    e.bl = c.z;
+    e.e0 = c.x * c.w;
+    e.e1 = c.y * c.w;
+    e.e2 = c.z * c.w;
+    e.transparent = (c.w == 0.0f);
+    float lg = (fb.y - fb.x) * inv_ref * log2_1m(c.w);   // log2 of (1 - a)^l
+    e.Te = hw_exp2(lg);
+    e.at = e.transparent ? 0.0f : one_minus_exp2(lg);
+    return e;
+}
 
 struct COut {
     float4* color;
@@ -31,75 +66,86 @@ struct COut {
     int limit;
 };
 
-template <bool WRITE>
-__device__ inline void c_close(CSeg& S, int& count, const COut& o, float inv_ref)
+__device__ inline void seg_reset(CSeg& S)
 {
-    if (WRITE && count < o.limit) {
+    S.open = 0;
+    S.count = 0;
+    S.c0 = S.c1 = S.c2 = S.A = 0.0f;
+    S.T = 1.0f;
+    S.f = S.b = S.bt = 0.0f;
+}
+
+template <bool WRITE>
+__device__ inline void c_close(CSeg& S, const COut& o, float inv_ref)
+{
+    if (WRITE && S.count < o.limit) {
         float invA = 1.0f / S.A;
         float len = (S.bt - S.f) * inv_ref;
-        float a = -expm1f(logf(S.T) / len);
-        size_t slot = (size_t)count * o.npix + o.pix;
+        float a = one_minus_exp2(hw_log2(S.T) / len);
+        size_t slot = (size_t)S.count * o.npix + o.pix;
         o.color[slot] = make_float4(S.c0 * invA, S.c1 * invA, S.c2 * invA, a);
         o.depth[slot] = make_float2(S.f, S.bt);
     }
-    ++count;
+    ++S.count;
     S.open = 0;
 }
 
-// Eq. 1 test of the open supersegment against an element with per-unit
-// premultiplied colour (e0, e1, e2).
+// Squared Eq. 1 distance between the open supersegment's per-step
+// premultiplied colour and (e0, e1, e2).
 __device__ inline float c_dist2(const CSeg& S, float inv_ref, float e0, float e1, float e2)
 {
     float L = (S.b - S.f) * inv_ref;
-    float aS = -expm1f(logf(S.T) / L);
-    float sc = aS / S.A;
+    float aS = 1.0f - hw_exp2(hw_log2(S.T) * hw_rcp(L));
+    float sc = aS * hw_rcp(S.A);
     float d0 = S.c0 * sc - e0, d1 = S.c1 * sc - e1, d2 = S.c2 * sc - e2;
     return d0 * d0 + d1 * d1 + d2 * d2;
 }
 
 template <bool WRITE>
-__device__ inline void c_step(CSeg& S, int& count, const COut& o, float inv_ref, float g2, int cap, float fe,
-                              float be, float4 c)
+__device__ inline void c_step(CSeg& S, const COut& o, float inv_ref, float g2, int cap, const CElem& e)
 {
     // empty space before the element is a transparent sample (Alg. S1)
-    if (S.open && fe > S.b) {
-        bool may_close = cap <= 0 || count < cap - 1;
-        if (may_close && g2 < c_dist2(S, inv_ref, 0.0f, 0.0f, 0.0f)) c_close<WRITE>(S, count, o, inv_ref);
-        else S.b = fe;
+    if (S.open && e.f > S.b) {
+        bool may_close = cap <= 0 || S.count < cap - 1;
+        if (may_close && g2 < c_dist2(S, inv_ref, 0.0f, 0.0f, 0.0f)) c_close<WRITE>(S, o, inv_ref);
+        else S.b = e.f;
     }
-    const bool transparent = (c.w == 0.0f);
-    float l = (be - fe) * inv_ref;
-    float lg = l * log1pf(-c.w);
-    float Te = expf(lg);          // Eq. 2: 1 - alpha~ = (1 - a)^l
-    float at = -expm1f(lg);
     if (S.open) {
-        bool may_close = cap <= 0 || count < cap - 1;
-        if (may_close && g2 < c_dist2(S, inv_ref, c.x * c.w, c.y * c.w, c.z * c.w)) {
-            c_close<WRITE>(S, count, o, inv_ref);
+        bool may_close = cap <= 0 || S.count < cap - 1;
+        if (may_close && g2 < c_dist2(S, inv_ref, e.e0, e.e1, e.e2)) {
+            c_close<WRITE>(S, o, inv_ref);
         } else {
-            float w = S.T * at;
-            S.c0 = fmaf(w, c.x, S.c0);
-            S.c1 = fmaf(w, c.y, S.c1);
-            S.c2 = fmaf(w, c.z, S.c2);
+            float w = S.T * e.at;
+            S.c0 = fmaf(w, e.r, S.c0);
+            S.c1 = fmaf(w, e.g, S.c1);
+            S.c2 = fmaf(w, e.bl, S.c2);
             S.A += w;
-            S.T *= Te;
-            S.b = be;
-            if (!transparent) S.bt = be;
+            S.T *= e.Te;
+            S.b = e.b;
+            if (!e.transparent) S.bt = e.b;
         }
     }
-    if (!S.open && !transparent) {
+    if (!S.open && !e.transparent) {
         S.open = 1;
-        S.f = fe;
-        S.b = S.bt = be;
-        S.c0 = c.x * at;
-        S.c1 = c.y * at;
-        S.c2 = c.z * at;
-        S.A = at;
-        S.T = Te;
+        S.f = e.f;
+        S.b = S.bt = e.b;
+        S.c0 = e.r * e.at;
+        S.c1 = e.g * e.at;
+        S.c2 = e.bl * e.at;
+        S.A = e.at;
+        S.T = e.Te;
     }
 }
 
+struct InLds {
+    const float4* color;
+    const float2* depth;
+    uint32_t stride;   // slot stride: npix (regular) or 1 (compact)
+    uint32_t pad;
+};
+
 struct Lds {
+    const InLds* in;   // [k], shared by the block
     uint16_t* seq;     // [seq_cap][64]: input << 8 | slot
     float* front;      // [k][64]
     uint32_t* ebase;   // [k][64]: element index of slot 0
@@ -107,34 +153,62 @@ struct Lds {
     uint16_t* cnt;     // [k][64]
 };
 
-__device__ inline uint32_t elem_index(const CompParams& P, const Lds& L, int r, int s, int t)
+struct Src {
+    const float4* c;
+    const float2* d;
+    uint32_t e;
+};
+
+__device__ inline Src locate(const Lds& L, int t, uint32_t rs)
 {
-    uint32_t stride = P.in[r].compact ? 1u : P.npix;
-    return L.ebase[r * kWave + t] + (uint32_t)s * stride;
+    int r = (int)(rs >> 8), s = (int)(rs & 255u);
+    const InLds in = L.in[r];
+    return Src{in.color, in.depth, L.ebase[r * kWave + t] + (uint32_t)s * in.stride};
 }
 
-template <bool WRITE>
-__device__ int c_pass(const CompParams& P, const Lds& L, int t, int total, float gamma, int cap, int limit,
-                      const COut& o)
+// One scan of the merged list carrying NC segmenter states (thresholds g[]).
+// Counting scans (WRITE false) freeze a state once its count exceeds
+// `limit` and stop when every state is frozen.
+template <int NC, bool WRITE>
+__device__ void c_scan(const Lds& L, int t, int total, float inv_ref, const float* gam, int cap, int limit,
+                       const COut& o, int* counts)
 {
-    const float g2 = gamma * gamma;
-    CSeg S;
-    S.open = 0;
-    S.c0 = S.c1 = S.c2 = S.A = 0.0f;
-    S.T = 1.0f;
-    S.f = S.b = S.bt = 0.0f;
-    int count = 0;
-    for (int i = 0; i < total; ++i) {
-        uint32_t rs = L.seq[i * kWave + t];
-        int r = (int)(rs >> 8), s = (int)(rs & 255u);
-        uint32_t e = elem_index(P, L, r, s, t);
-        float4 c = P.in[r].color[e];
-        float2 fb = P.in[r].depth[e];
-        c_step<WRITE>(S, count, o, P.inv_ref, g2, cap, fb.x, fb.y, c);
-        if (!WRITE && count > limit) return count;
+    CSeg S[NC];
+    float g2[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        seg_reset(S[c]);
+        g2[c] = gam[c] * gam[c];
     }
-    if (S.open) c_close<WRITE>(S, count, o, P.inv_ref);
-    return count;
+    if (total > 0) {
+        Src src = locate(L, t, L.seq[t]);
+        float4 cn = src.c[src.e];
+        float2 fn = src.d[src.e];
+        for (int i = 0; i < total; ++i) {
+            float4 cc = cn;
+            float2 fc = fn;
+            if (i + 1 < total) {
+                Src nx = locate(L, t, L.seq[(i + 1) * kWave + t]);
+                cn = nx.c[nx.e];
+                fn = nx.d[nx.e];
+            }
+            CElem e = prep(cc, fc, inv_ref);
+            bool live = false;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (WRITE || S[c].count <= limit) {
+                    c_step<WRITE>(S[c], o, inv_ref, g2[c], cap, e);
+                    live |= WRITE || S[c].count <= limit;
+                }
+            }
+            if (!live) break;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (S[c].open && (WRITE || S[c].count <= limit)) c_close<WRITE>(S[c], o, inv_ref);
+        counts[c] = S[c].count;
+    }
 }
 
 }  // namespace
@@ -144,11 +218,20 @@ __global__ __launch_bounds__(64) void composite_kernel(CompParams P)
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int t = threadIdx.x;
     Lds L;
-    L.seq = (uint16_t*)lds_raw;
-    L.front = (float*)(lds_raw + (size_t)2 * kWave * P.seq_cap);
+    InLds* in_tab = (InLds*)lds_raw;
+    L.in = in_tab;
+    L.seq = (uint16_t*)(lds_raw + sizeof(InLds) * kMaxInputs);
+    L.front = (float*)(lds_raw + sizeof(InLds) * kMaxInputs + (size_t)2 * kWave * P.seq_cap);
     L.ebase = (uint32_t*)(L.front + kWave * P.k);
     L.cur = (uint16_t*)(L.ebase + kWave * P.k);
     L.cnt = L.cur + kWave * P.k;
+    if (t < P.k) {
+        in_tab[t].color = P.in[t].color;
+        in_tab[t].depth = P.in[t].depth;
+        in_tab[t].stride = P.in[t].compact ? 1u : P.npix;
+        in_tab[t].pad = 0;
+    }
+    __syncthreads();
 
     const uint32_t p = blockIdx.x * kWave + t;
     if (p >= P.npix) return;
@@ -191,7 +274,8 @@ __global__ __launch_bounds__(64) void composite_kernel(CompParams P)
         L.cur[rb * kWave + t] = (uint16_t)s;
         float nf = __builtin_inff();
         if (s < L.cnt[rb * kWave + t]) {
-            float2 fb = P.in[rb].depth[elem_index(P, L, rb, s, t)];
+            const InLds inr = L.in[rb];
+            float2 fb = inr.depth[L.ebase[rb * kWave + t] + (uint32_t)s * inr.stride];
             if (!(fb.x < fb.y) || !(fb.x >= best) || !isfinite(fb.y)) bad = true;
             nf = fb.x;
         }
@@ -208,27 +292,48 @@ __global__ __launch_bounds__(64) void composite_kernel(CompParams P)
     if (total <= P.out_n) {
         // pass-through: the merged list already fits
         for (int i = 0; i < total; ++i) {
-            uint32_t rs = L.seq[i * kWave + t];
-            int r = (int)(rs >> 8), s = (int)(rs & 255u);
-            uint32_t e = elem_index(P, L, r, s, t);
+            Src src = locate(L, t, L.seq[i * kWave + t]);
             size_t slot = (size_t)i * P.npix + p;
-            P.out_color[slot] = P.in[r].color[e];
-            P.out_depth[slot] = P.in[r].depth[e];
+            P.out_color[slot] = src.c[src.e];
+            P.out_depth[slot] = src.d[src.e];
         }
         count = total;
     } else if (P.mode == VDI_TAU_FIXED) {
         gm = P.tau;
-        count = c_pass<true>(P, L, t, total, gm, P.out_n, 1 << 30, o);
+        int c1[1];
+        c_scan<1, true>(L, t, total, P.inv_ref, &gm, P.out_n, 1 << 30, o, c1);
+        count = c1[0];
     } else {
+        // bisection, two levels per scan
         float lo = 0.0f, hi = P.gmax;
-        for (int it = 0; it < P.iters; ++it) {
+        int level = 0;
+        while (level + 2 <= P.iters) {
             float m = 0.5f * (lo + hi);
-            int c = c_pass<false>(P, L, t, total, m, 0, P.out_n, o);
-            if (c <= P.out_n) hi = m;
+            float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
+            int c3[3];
+            c_scan<3, false>(L, t, total, P.inv_ref, g3, 0, P.out_n, o, c3);
+            if (c3[0] <= P.out_n) {
+                hi = m;
+                if (c3[1] <= P.out_n) hi = g3[1];
+                else lo = g3[1];
+            } else {
+                lo = m;
+                if (c3[2] <= P.out_n) hi = g3[2];
+                else lo = g3[2];
+            }
+            level += 2;
+        }
+        if (level < P.iters) {
+            float m = 0.5f * (lo + hi);
+            int c1[1];
+            c_scan<1, false>(L, t, total, P.inv_ref, &m, 0, P.out_n, o, c1);
+            if (c1[0] <= P.out_n) hi = m;
             else lo = m;
         }
         gm = hi;
-        count = c_pass<true>(P, L, t, total, gm, 0, 1 << 30, o);
+        int c1[1];
+        c_scan<1, true>(L, t, total, P.inv_ref, &gm, 0, 1 << 30, o, c1);
+        count = c1[0];
     }
     if (count > P.out_n) count = P.out_n;
     for (int j = count; j < P.out_n; ++j) {
@@ -240,9 +345,14 @@ __global__ __launch_bounds__(64) void composite_kernel(CompParams P)
     if (P.out_gamma) P.out_gamma[p] = gm;
 }
 
+size_t composite_lds_bytes(int k, int seq_cap)
+{
+    return sizeof(InLds) * kMaxInputs + (size_t)kWave * (2 * (size_t)seq_cap + 12 * (size_t)k);
+}
+
 void launch_composite(const CompParams& P, hipStream_t s)
 {
-    size_t lds = (size_t)kWave * (2 * (size_t)P.seq_cap + 4 * P.k + 4 * P.k + 2 * P.k + 2 * P.k);
+    size_t lds = composite_lds_bytes(P.k, P.seq_cap);
     dim3 grid((P.npix + kWave - 1) / kWave);
     hipLaunchKernelGGL(composite_kernel, grid, dim3(kWave), lds, s, P);
 }
@@ -273,7 +383,7 @@ __global__ __launch_bounds__(256) void render_kernel(const float4* __restrict__ 
         size_t e = (size_t)base + (size_t)j * stride;
         float4 s = color[e];
         float2 fb = depth[e];
-        float Aj = -expm1f((fb.y - fb.x) * inv_ref * log1pf(-s.w));
+        float Aj = one_minus_exp2((fb.y - fb.x) * inv_ref * log2_1m(s.w));
         float w = (1.0f - A) * Aj;
         C0 = fmaf(w, s.x, C0);
         C1 = fmaf(w, s.y, C1);

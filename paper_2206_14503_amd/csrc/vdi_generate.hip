@@ -35,7 +35,7 @@ __device__ inline void gen_close(GenSeg& S, int& count, const GenOut& o, const R
     if (WRITE && (uint32_t)count < o.limit) {
         float invA = 1.0f / S.A;
         float len = (float)(S.kbt - S.kf) * l_step;
-        float a = -expm1f(logf(S.T) / len);
+        float a = one_minus_exp2(hw_log2(S.T) / len);
         size_t slot = (size_t)o.base + (size_t)count * o.stride;
         o.color[slot] = make_float4(S.c0 * invA, S.c1 * invA, S.c2 * invA, a);
         float f = r.tn + (float)S.kf * step;
@@ -46,66 +46,88 @@ __device__ inline void gen_close(GenSeg& S, int& count, const GenOut& o, const R
     S.open = 0;
 }
 
+template <typename VT>
+__device__ inline float4 gen_sample(const VT* data, const BrickGeo& g, const Ray& r, float step, int k,
+                                    const float4* tf, int entries)
+{
+    float t = sample_t(r, k, step);
+    float p[3] = { sample_coord(r, t, 0), sample_coord(r, t, 1), sample_coord(r, t, 2) };
+    float s = trilinear<VT>(data, g, p);
+    return tf_lookup(tf, entries, s);
+}
+
+__device__ inline void gen_seg_init(GenSeg& S)
+{
+    S.open = 0;
+    S.c0 = S.c1 = S.c2 = 0.0f;
+    S.A = 0.0f;
+    S.T = 1.0f;
+    S.kf = S.kb = S.kbt = 0;
+}
+
+// One sample through the segmenter (Eq. 1 test, then merge or close/open).
+template <bool WRITE>
+__device__ inline void gen_step(GenSeg& S, int& count, const GenOut& o, const Ray& r, float step, float l_step,
+                                bool unit, float g2, int cap, int k, float4 c)
+{
+    const bool transparent = (c.w == 0.0f);
+    // Eq. 2 / length-adjusted opacity of the sample
+    const float lg = unit ? 0.0f : l_step * log2_1m(c.w);
+    float at = unit ? c.w : one_minus_exp2(lg);
+    if (S.open) {
+        // per-step opacity of the open supersegment: 1 - T^(1/L)
+        float L = (float)(S.kb - S.kf) * l_step;
+        float aS = 1.0f - hw_exp2(hw_log2(S.T) * hw_rcp(L));
+        float sc = aS * hw_rcp(S.A);
+        float d0 = S.c0 * sc - c.x * c.w;
+        float d1 = S.c1 * sc - c.y * c.w;
+        float d2 = S.c2 * sc - c.z * c.w;
+        float dd = d0 * d0 + d1 * d1 + d2 * d2;
+        bool may_close = cap <= 0 || count < cap - 1;
+        if (may_close && g2 < dd) {
+            gen_close<WRITE>(S, count, o, r, step, l_step);
+        } else {
+            float w = S.T * at;
+            S.c0 = fmaf(w, c.x, S.c0);
+            S.c1 = fmaf(w, c.y, S.c1);
+            S.c2 = fmaf(w, c.z, S.c2);
+            S.A += w;
+            S.T *= unit ? (1.0f - c.w) : hw_exp2(lg);
+            S.kb = k + 1;
+            if (!transparent) S.kbt = k + 1;
+        }
+    }
+    if (!S.open && !transparent) {
+        S.open = 1;
+        S.kf = k;
+        S.kb = S.kbt = k + 1;
+        S.c0 = c.x * at;
+        S.c1 = c.y * at;
+        S.c2 = c.z * at;
+        S.A = at;
+        S.T = unit ? (1.0f - c.w) : hw_exp2(lg);
+    }
+}
+
 // One pass of the segmenter over samples [k0, k1) at threshold gamma.
-// Returns the supersegment count; a pass that is only counting stops as soon
-// as the count exceeds `limit` (its outcome "infeasible" is then decided).
+// Returns the supersegment count.  With EARLY the pass stops as soon as the
+// count exceeds `limit` (its outcome "more than limit" is then decided).
 // cap > 0 saturates after cap-1 closes (fixed-threshold mode).
-template <typename VT, bool WRITE>
+template <typename VT, bool WRITE, bool EARLY = !WRITE>
 __device__ int gen_pass(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0,
                         int k1, const float4* tf, int entries, float gamma, int cap, int limit, const GenOut& o,
                         int* n_opaque_out)
 {
     const float g2 = gamma * gamma;
     GenSeg S;
-    S.open = 0;
-    S.c0 = S.c1 = S.c2 = 0.0f;
-    S.A = 0.0f;
-    S.T = 1.0f;
-    S.kf = S.kb = S.kbt = 0;
+    gen_seg_init(S);
     int count = 0, n_opaque = 0;
     const bool unit = (l_step == 1.0f);
     for (int k = k0; k < k1; ++k) {
-        float t = sample_t(r, k, step);
-        float p[3] = { sample_coord(r, t, 0), sample_coord(r, t, 1), sample_coord(r, t, 2) };
-        float s = trilinear<VT>(data, g, p);
-        float4 c = tf_lookup(tf, entries, s);
-        const bool transparent = (c.w == 0.0f);
-        n_opaque += transparent ? 0 : 1;
-        // Eq. 2 / length-adjusted opacity of the sample
-        float at = unit ? c.w : -expm1f(l_step * log1pf(-c.w));
-        if (S.open) {
-            float L = (float)(k - S.kf) * l_step;
-            float aS = -expm1f(logf(S.T) / L);
-            float sc = aS / S.A;
-            float d0 = S.c0 * sc - c.x * c.w;
-            float d1 = S.c1 * sc - c.y * c.w;
-            float d2 = S.c2 * sc - c.z * c.w;
-            float dd = d0 * d0 + d1 * d1 + d2 * d2;
-            bool may_close = cap <= 0 || count < cap - 1;
-            if (may_close && g2 < dd) {
-                gen_close<WRITE>(S, count, o, r, step, l_step);
-                if (!WRITE && count > limit) break;
-            } else {
-                float w = S.T * at;
-                S.c0 = fmaf(w, c.x, S.c0);
-                S.c1 = fmaf(w, c.y, S.c1);
-                S.c2 = fmaf(w, c.z, S.c2);
-                S.A += w;
-                S.T *= unit ? (1.0f - c.w) : expf(l_step * log1pf(-c.w));
-                S.kb = k + 1;
-                if (!transparent) S.kbt = k + 1;
-            }
-        }
-        if (!S.open && !transparent) {
-            S.open = 1;
-            S.kf = k;
-            S.kb = S.kbt = k + 1;
-            S.c0 = c.x * at;
-            S.c1 = c.y * at;
-            S.c2 = c.z * at;
-            S.A = at;
-            S.T = unit ? (1.0f - c.w) : expf(l_step * log1pf(-c.w));
-        }
+        float4 c = gen_sample<VT>(data, g, r, step, k, tf, entries);
+        n_opaque += (c.w == 0.0f) ? 0 : 1;
+        gen_step<WRITE>(S, count, o, r, step, l_step, unit, g2, cap, k, c);
+        if (EARLY && count > limit) break;
     }
     if (S.open) gen_close<WRITE>(S, count, o, r, step, l_step);
     if (n_opaque_out) *n_opaque_out = n_opaque;
@@ -240,6 +262,220 @@ void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B
 {
     if (dtype == VDI_F16) launch_gen<__half>(kind, P, B, nb, s);
     else launch_gen<float>(kind, P, B, nb, s);
+}
+
+// ---------------------------------------------------------------- learned threshold
+//
+// The regressor of the learned path needs per brick-ray features: a 64-bin
+// histogram of the sample opacities (bin j: a in (j/64, (j+1)/64], the opacity
+// from the transfer function in the same fixed-order fp32 as the oracle, so
+// bins agree exactly), the number of non-transparent samples and the count at
+// the smallest threshold the bisection can return (saturating at N+1).
+
+__device__ inline float tf_alpha_exact(const float4* tf, int entries, float s)
+{
+    int i;
+    float w;
+    tf_coord(s, entries, i, w);
+    return lerp_exact(tf[i].w, tf[i + 1].w, w);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B, LearnBufs Lb)
+{
+    __shared__ float4 tf_s[VDI_MAX_TF];
+    __shared__ uint16_t hs[64][256];
+    for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
+    for (int j = 0; j < 64; ++j) hs[j][threadIdx.x] = 0;
+    __syncthreads();
+
+    const GenBrick& br = B.b[blockIdx.z];
+    const int brick = B.first + blockIdx.z;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
+    const int y = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+    if (x >= P.cam.width || y >= P.cam.height) return;
+    const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
+    const size_t ray = (size_t)brick * npix + (uint32_t)y * (uint32_t)P.cam.width + (uint32_t)x;
+
+    BrickGeo g;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = P.n[a];
+        g.dlo[a] = br.dlo[a];
+        g.ddim[a] = br.ddim[a];
+    }
+    const VT* data = (const VT*)br.data;
+    Ray r = make_ray(P.cam, x, y);
+    int ns = ray_samples(r, P.step);
+    int k0 = 0, k1 = 0;
+    if (ns > 0) owned_run(r, P.step, ns, P.n, br.lo, br.hi, k0, k1);
+
+    const float gmin = ldexpf(P.gmax, -P.iters);
+    const float g2 = gmin * gmin;
+    const bool unit = (P.l_step == 1.0f);
+    GenOut none{nullptr, nullptr, 0, 0, 0};
+    GenSeg S;
+    gen_seg_init(S);
+    int count = 0, m = 0;
+    for (int k = k0; k < k1; ++k) {
+        float t = sample_t(r, k, P.step);
+        float p[3] = { sample_coord(r, t, 0), sample_coord(r, t, 1), sample_coord(r, t, 2) };
+        float sv = trilinear<VT>(data, g, p);
+        float a32 = tf_alpha_exact(tf_s, P.tf_entries, sv);
+        if (a32 > 0.0f) {
+            int j = (int)ceilf(64.0f * a32) - 1;
+            j = j > 63 ? 63 : (j < 0 ? 0 : j);
+            hs[j][threadIdx.x] += 1;
+            ++m;
+        }
+        if (count <= P.max_n) {
+            float4 c = tf_lookup(tf_s, P.tf_entries, sv);
+            gen_step<false>(S, count, none, r, P.step, P.l_step, unit, g2, 0, k, c);
+        }
+    }
+    if (S.open && count <= P.max_n) gen_close<false>(S, count, none, r, P.step, P.l_step);
+    Lb.nnt[ray] = m;
+    Lb.cmax[ray] = count;
+    uint32_t* hrow = (uint32_t*)(Lb.hist + ray * 64);
+    for (int j = 0; j < 64; j += 2) {
+        float f0 = (float)hs[j][threadIdx.x] / Lb.s_ref;
+        float f1 = (float)hs[j + 1][threadIdx.x] / Lb.s_ref;
+        hrow[j / 2] = (uint32_t)bf16_bits(f0) | ((uint32_t)bf16_bits(f1) << 16);
+    }
+}
+
+// Generation at the regressed threshold, with the acceptance test; rays
+// that fail it are queued (per brick) for the plain bisection.
+template <typename VT>
+__global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, LearnBufs Lb)
+{
+    __shared__ float4 tf_s[VDI_MAX_TF];
+    for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
+    __syncthreads();
+
+    const GenBrick& br = B.b[blockIdx.z];
+    const int brick = B.first + blockIdx.z;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
+    const int y = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+    if (x >= P.cam.width || y >= P.cam.height) return;
+    const uint32_t pix = (uint32_t)y * (uint32_t)P.cam.width + (uint32_t)x;
+    const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
+    const size_t ray = (size_t)brick * npix + pix;
+
+    BrickGeo g;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = P.n[a];
+        g.dlo[a] = br.dlo[a];
+        g.ddim[a] = br.ddim[a];
+    }
+    const VT* data = (const VT*)br.data;
+    Ray r = make_ray(P.cam, x, y);
+    int ns = ray_samples(r, P.step);
+    int k0 = 0, k1 = 0;
+    if (ns > 0) owned_run(r, P.step, ns, P.n, br.lo, br.hi, k0, k1);
+
+    const float gmin = ldexpf(P.gmax, -P.iters);
+    const int m = Lb.nnt[ray];
+    GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
+    float gm = gmin;
+    int c = 0;
+    if (k1 <= k0 || m == 0) {
+        atomicAdd(&Lb.stats[3], 1);
+    } else if (m <= P.max_n) {
+        // every threshold is feasible: the bisection would return its lower end
+        c = gen_pass<VT, true, false>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gmin, 0, 1 << 30,
+                                      o, nullptr);
+        atomicAdd(&Lb.stats[1], 1);
+    } else {
+        const float lg_hi = log2f(P.gmax), lg_lo = lg_hi - (float)P.iters;
+        const float yv = fminf(fmaxf(Lb.y[ray], lg_lo), lg_hi);
+        gm = exp2f(yv);
+        c = gen_pass<VT, true, true>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, 0, P.max_n, o,
+                                     nullptr);
+        const int target = min(P.max_n, Lb.cmax[ray]);
+        const int lo = target - (int)floorf(Lb.tol * (float)target + 1e-6f);
+        if (c > P.max_n || c < lo) {
+            int pos = atomicAdd(&Lb.fb_count[brick], 1);
+            Lb.fb_list[(size_t)brick * npix + pos] = (int)pix;
+            atomicAdd(&Lb.stats[2], 1);
+            return;
+        }
+        atomicAdd(&Lb.stats[0], 1);
+    }
+    for (int j = c; j < P.max_n; ++j) {
+        size_t slot = (size_t)j * npix + pix;
+        br.color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        br.depth[slot] = make_float2(0.0f, 0.0f);
+    }
+    br.count[pix] = c;
+    if (br.gamma) br.gamma[pix] = gm;
+}
+
+// Plain bisection for the queued rays of each brick.
+template <typename VT>
+__global__ __launch_bounds__(256) void fallback_kernel(GenParams P, GenBricks B, LearnBufs Lb)
+{
+    __shared__ float4 tf_s[VDI_MAX_TF];
+    for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
+    __syncthreads();
+    const GenBrick& br = B.b[blockIdx.z];
+    const int brick = B.first + blockIdx.z;
+    const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (uint32_t)Lb.fb_count[brick]) return;
+    const uint32_t pix = (uint32_t)Lb.fb_list[(size_t)brick * npix + idx];
+    const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
+
+    BrickGeo g;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = P.n[a];
+        g.dlo[a] = br.dlo[a];
+        g.ddim[a] = br.ddim[a];
+    }
+    const VT* data = (const VT*)br.data;
+    Ray r = make_ray(P.cam, x, y);
+    int ns = ray_samples(r, P.step);
+    int k0 = 0, k1 = 0;
+    if (ns > 0) owned_run(r, P.step, ns, P.n, br.lo, br.hi, k0, k1);
+    float gm = ldexpf(P.gmax, -P.iters);
+    int c = 0;
+    GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
+    if (k1 > k0) {
+        gen_search<VT>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, P, gm, c, false);
+        c = gen_pass<VT, true>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, 0, 1 << 30, o, nullptr);
+    }
+    for (int j = c; j < P.max_n; ++j) {
+        size_t slot = (size_t)j * npix + pix;
+        br.color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        br.depth[slot] = make_float2(0.0f, 0.0f);
+    }
+    br.count[pix] = c < P.max_n ? c : P.max_n;
+    if (br.gamma) br.gamma[pix] = gm;
+}
+
+template <typename VT>
+static void launch_learned_t(int phase, const GenParams& P, const GenBricks& B, int nb, const LearnBufs& L,
+                             hipStream_t s)
+{
+    dim3 grid((P.cam.width + 15) / 16, (P.cam.height + 15) / 16, nb);
+    if (phase == 0) hipLaunchKernelGGL(features_kernel<VT>, grid, dim3(256), 0, s, P, B, L);
+    if (phase == 1) hipLaunchKernelGGL(learned_kernel<VT>, grid, dim3(256), 0, s, P, B, L);
+    if (phase == 2) {
+        size_t npix = (size_t)P.cam.width * P.cam.height;
+        dim3 g2((unsigned)((npix + 255) / 256), 1, nb);
+        hipLaunchKernelGGL(fallback_kernel<VT>, g2, dim3(256), 0, s, P, B, L);
+    }
+}
+
+void launch_learned(int phase, int dtype, const GenParams& P, const GenBricks& B, int nb, const LearnBufs& L,
+                    hipStream_t s)
+{
+    if (dtype == VDI_F16) launch_learned_t<__half>(phase, P, B, nb, L, s);
+    else launch_learned_t<float>(phase, P, B, nb, L, s);
 }
 
 // ---------------------------------------------------------------- rays (diagnostic)

@@ -295,7 +295,44 @@ __device__ inline float4 tf_lookup(const float4* tf, int entries, float s)
                        fmaf(w, hi.z - lo.z, lo.z), fmaf(w, hi.w - lo.w, lo.w));
 }
 
+// ---------------------------------------------------------------- fast math
+//
+// Hardware log2/exp2/reciprocal (about 1 ulp).  Quantities that are small
+// differences from 1 use forms that keep their relative accuracy.
+
+__device__ inline float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ inline float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ inline float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// log2(1 - a) for a in [0, 1], accurate also for tiny a.
+__device__ inline float log2_1m(float a)
+{
+    float u = 1.0f - a;
+    if (a >= 0.5f) return hw_log2(u);                 // 1 - a exact here
+    if (u == 1.0f) return -a * 1.4426950408889634f;   // a below half an ulp of 1
+    float d = 1.0f - u;                               // exact
+    return hw_log2(u) * (a * hw_rcp(d));
+}
+
+// 1 - 2^y for y <= 0, accurate also for y near 0.
+__device__ inline float one_minus_exp2(float y)
+{
+    float u = hw_exp2(y);
+    if (u == 1.0f) return -y * 0.6931471805599453f;
+    if (u == 0.0f) return 1.0f;
+    return (1.0f - u) * (y * hw_rcp(hw_log2(u)));
+}
+
 // ---------------------------------------------------------------- misc
+
+// fp32 -> bf16 bits, round to nearest even.
+__device__ inline uint16_t bf16_bits(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+    u = u + 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
 
 __device__ inline float gamma_sq(float g) { return g * g; }
 

@@ -40,10 +40,27 @@ struct GenBrick {
 constexpr int kGenBricksPerLaunch = 16;
 struct GenBricks {
     GenBrick b[kGenBricksPerLaunch];
+    int first;           // index of b[0] among all bricks of the call
+};
+
+// Buffers of the learned-threshold path (indices: brick * npix + pixel).
+struct LearnBufs {
+    uint16_t* hist;      // [nb][npix][64] bf16 features
+    int* nnt;            // [nb][npix] non-transparent samples
+    int* cmax;           // [nb][npix] count at the smallest threshold (saturates at N+1)
+    const float* y;      // [nb][npix] regressor output, log2(gamma)
+    int* fb_list;        // [nb][npix] queued pixels per brick
+    int* fb_count;       // [nb]
+    int* stats;          // [4]: accepted, all-feasible shortcut, fallback, empty
+    float s_ref;
+    float tol;
 };
 
 // kind: 0 = search + regular write, 1 = search only, 2 = compact write
 void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B, int nb, hipStream_t s);
+// phase 0: features, 1: learned generation + acceptance, 2: fallback bisection
+void launch_learned(int phase, int dtype, const GenParams& P, const GenBricks& B, int nb, const LearnBufs& L,
+                    hipStream_t s);
 void launch_rays(const Cam& cam, float step, float* o, float* d, float* tn, float* tf, int* ns, hipStream_t s);
 
 // ---------------------------------------------------------------- scan
@@ -84,7 +101,21 @@ struct CompParams {
     int seq_cap;              // merged-list capacity per pixel (sum of input max_n)
 };
 
+size_t composite_lds_bytes(int k, int seq_cap);
 void launch_composite(const CompParams& P, hipStream_t s);
+
+// ---------------------------------------------------------------- MLP (learned threshold)
+
+int mlp_params();
+int mlp_act_floats();
+int mlp_rows_per_block();
+void launch_mlp_fwd(const uint16_t* wb, const float* wf, const uint16_t* x, int rows, float* y, float* acts,
+                    hipStream_t s);
+void launch_mlp_bwd(const uint16_t* wb, const uint16_t* x, const float* acts, const float* dy, int rows,
+                    float* partial, float* grad, hipStream_t s);
+void launch_mlp_adam(float* wf, uint16_t* wb, const float* grad, float* m, float* v, float lr, float b1, float b2,
+                     float eps, int step, hipStream_t s);
+void launch_mfma_probe(const uint16_t* A, const uint16_t* B, float* D, hipStream_t s);
 
 // ---------------------------------------------------------------- rendering
 

@@ -53,9 +53,9 @@ def transfer_function(entries: int = 256, ramp: Tuple[float, float] = (0.2, 0.9)
 # --------------------------------------------------------------------------
 
 
-def _gaussian_params(rng: np.random.Generator, n: int, count: int):
+def _gaussian_params(rng: np.random.Generator, n: int, count: int, sigma=(4.0, 10.0)):
     centres = rng.uniform(0.0, n, size=(count, 3))          # voxel units, (x, y, z)
-    sigmas = rng.uniform(4.0, 10.0, size=count)
+    sigmas = rng.uniform(sigma[0], sigma[1], size=count)
     amps = rng.uniform(0.2, 1.0, size=count)
     return centres, sigmas, amps
 
@@ -94,12 +94,12 @@ def _interp_matrix(n: int, cells: int) -> np.ndarray:
 
 
 def gaussian_volume(n: int, n_gauss: int, seed: int, noise_amp: float = 0.0,
-                    dtype: str = "f32", device: str = "cpu"):
+                    dtype: str = "f32", device: str = "cpu", sigma=(4.0, 10.0)):
     """Seeded scalar volume [n, n, n] (z, y, x; x fastest) with values in [0, 1].
 
     value = clamp(sum_i amp_i * exp(-|x - c_i|^2 / (2 sigma_i^2)) + noise, 0, 1)
-    with centres U[0,n)^3 (voxel units), sigma U(4,10) voxels, amplitude
-    U(0.2,1).  Noise (if noise_amp > 0) is 4 octaves of trilinearly
+    with centres U[0,n)^3 (voxel units), sigma U(sigma) voxels (default 4..10),
+    amplitude U(0.2,1).  Noise (if noise_amp > 0) is 4 octaves of trilinearly
     interpolated lattice values U(-1,1) on 8, 16, 32, 64 cells per axis with
     octave weights 1, 1/2, 1/4, 1/8 scaled to a total of noise_amp.
 
@@ -109,7 +109,7 @@ def gaussian_volume(n: int, n_gauss: int, seed: int, noise_amp: float = 0.0,
     device="cpu", else a torch tensor on that device.  dtype "f32" or "f16".
     """
     rng = np.random.default_rng(seed)
-    centres, sigmas, amps = _gaussian_params(rng, n, n_gauss)
+    centres, sigmas, amps = _gaussian_params(rng, n, n_gauss, sigma)
     lattices = []
     if noise_amp > 0.0:
         weights = np.array([1.0, 0.5, 0.25, 0.125])
@@ -299,6 +299,7 @@ class Workload:
     noise: float
     vol_dtype: str
     grid: Tuple[int, int, int]
+    sigma: Tuple[float, float]
     width: int
     height: int
     mode: str          # "fixed" | "bisect"
@@ -310,20 +311,32 @@ class Workload:
 
 def tiny(seed: int = 0) -> Workload:
     """64^3 fp32, 12 Gaussians, 2 z-slabs, 256^2 ortho along +z, fixed tau 0.05, N=8."""
-    return Workload("tiny-64c-2slab-256sq-fixed", 64, 12, 0.0, "f32", (1, 1, 2), 256, 256,
+    return Workload("tiny-64c-2slab-256sq-fixed", 64, 12, 0.0, "f32", (1, 1, 2), (4.0, 10.0), 256, 256,
                     "fixed", 0.05, 8, 10, seed)
+
+
+def scaled_sigma(n: int) -> Tuple[float, float]:
+    """Gaussian widths that keep the feature size a fixed fraction of the box:
+    U(4,10) voxels at 128^3, i.e. 16..40 voxels at 512^3 and 32..80 at 1024^3.
+    With widths fixed in voxels the large volumes would be nearly empty
+    (mean value 0.013 at 512^3), unlike any of the paper's datasets."""
+    return (4.0 * n / 128, 10.0 * n / 128)
 
 
 def fhd(seed: int = 0) -> Workload:
     """512^3 fp32, 200 Gaussians + noise 0.1, 8 z-slabs, 1920x1080 orbit view, bisection N=20."""
-    return Workload("fhd-512c-8slab-1920x1080-bisect-N20", 512, 200, 0.1, "f32", (1, 1, 8), 1920, 1080,
-                    "bisect", 0.0, 20, 10, seed)
+    return Workload("fhd-512c-8slab-1920x1080-bisect-N20", 512, 200, 0.1, "f32", (1, 1, 8), scaled_sigma(512),
+                    1920, 1080, "bisect", 0.0, 20, 10, seed)
 
 
 def large(seed: int = 0) -> Workload:
     """1024^3 fp16, same generator, 16 bricks 4x2x2, 1920x1080 orbit view, bisection N=20."""
     return Workload("large-1024c-f16-16brick-1920x1080-bisect-N20", 1024, 200, 0.1, "f16", (4, 2, 2),
-                    1920, 1080, "bisect", 0.0, 20, 10, seed)
+                    scaled_sigma(1024), 1920, 1080, "bisect", 0.0, 20, 10, seed)
+
+
+def workload_volume(w: Workload, device: str = "cpu"):
+    return gaussian_volume(w.n, w.n_gauss, w.seed, w.noise, w.vol_dtype, device=device, sigma=w.sigma)
 
 
 def camera_for(w: Workload) -> Camera:

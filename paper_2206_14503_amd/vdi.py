@@ -58,7 +58,16 @@ class vdi_tf_t(ctypes.Structure):
 
 class vdi_tau_t(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tau", ctypes.c_float), ("iters", ctypes.c_int32),
-                ("gamma_max", ctypes.c_float), ("mlp", ctypes.c_void_p), ("fallback_tol", ctypes.c_float)]
+                ("gamma_max", ctypes.c_float), ("mlp", ctypes.c_void_p), ("fallback_tol", ctypes.c_float),
+                ("feature_scale", ctypes.c_float)]
+
+
+class vdi_mlp_t(ctypes.Structure):
+    _fields_ = [("w_bf16", ctypes.c_void_p), ("w_f32", ctypes.c_void_p)]
+
+
+MLP_PARAMS = 24961
+MLP_ACT_FLOATS = 384
 
 
 _lib = None
@@ -82,8 +91,18 @@ def lib():
         L.vdi_composite.argtypes = [P, ctypes.POINTER(vdi_t), I, ctypes.POINTER(vdi_tau_t), ctypes.POINTER(vdi_t), P]
         L.vdi_render_original_view.argtypes = [P, ctypes.POINTER(vdi_t), P, P]
         L.vdi_debug_rays.argtypes = [P, ctypes.POINTER(vdi_camera_t), ctypes.c_float, P, P, P, P, P, P]
+        L.vdi_tau_features.argtypes = [P, ctypes.POINTER(vdi_brick_t), I, ctypes.POINTER(vdi_camera_t),
+                                       ctypes.POINTER(vdi_tf_t), ctypes.c_float, ctypes.c_float, I,
+                                       ctypes.POINTER(vdi_tau_t), P, P, P, P]
+        L.vdi_mlp_forward.argtypes = [P, ctypes.POINTER(vdi_mlp_t), P, I, P, P, P]
+        L.vdi_mlp_backward.argtypes = [P, ctypes.POINTER(vdi_mlp_t), P, P, P, I, P, P]
+        L.vdi_mlp_adam.argtypes = [P, ctypes.POINTER(vdi_mlp_t), P, P, P, I, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, P]
+        L.vdi_learned_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), P]
+        L.vdi_debug_mfma.argtypes = [P, P, P, P, P]
         for name in ("vdi_ctx_create", "vdi_ctx_destroy", "vdi_ctx_device_status", "vdi_generate", "vdi_composite",
-                     "vdi_render_original_view", "vdi_debug_rays"):
+                     "vdi_render_original_view", "vdi_debug_rays", "vdi_tau_features", "vdi_mlp_forward",
+                     "vdi_mlp_backward", "vdi_mlp_adam", "vdi_learned_stats", "vdi_debug_mfma"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -172,8 +191,8 @@ def camera_c(cam) -> vdi_camera_t:
 
 
 def tau_c(mode: int, tau: float = 0.0, iters: int = 10, gamma_max: float = 2.0, mlp=None,
-          fallback_tol: float = 0.1) -> vdi_tau_t:
-    return vdi_tau_t(mode, tau, iters, gamma_max, mlp, fallback_tol)
+          fallback_tol: float = 0.1, feature_scale: float = 32.0) -> vdi_tau_t:
+    return vdi_tau_t(mode, tau, iters, gamma_max, mlp, fallback_tol, feature_scale)
 
 
 @dataclasses.dataclass
@@ -210,8 +229,9 @@ def device_bricks(vol, bricks, device=None) -> List[DeviceBrick]:
 
 def generate(bricks: Sequence[DeviceBrick], cam, tf: torch.Tensor, step: float, ref_step: float, mode: int,
              tau: float = 0.0, max_n: int = 8, iters: int = 10, layout: int = REGULAR,
-             capacity: Optional[int] = None, outs: Optional[List[VDI]] = None, gamma_max: float = 2.0) -> List[VDI]:
-    """vdi_generate: one sub-VDI per brick."""
+             capacity: Optional[int] = None, outs: Optional[List[VDI]] = None, gamma_max: float = 2.0,
+             mlp: Optional["MLP"] = None, fallback_tol: float = 0.1, feature_scale: float = 32.0) -> List[VDI]:
+    """vdi_generate: one sub-VDI per brick (mode LEARNED needs `mlp`)."""
     k = len(bricks)
     if outs is None:
         outs = [VDI.empty(cam.width, cam.height, max_n, ref_step, layout, capacity) for _ in range(k)]
@@ -219,7 +239,9 @@ def generate(bricks: Sequence[DeviceBrick], cam, tf: torch.Tensor, step: float, 
     oc = (vdi_t * k)(*[o.c() for o in outs])
     cc = camera_c(cam)
     tfc = vdi_tf_t(_ptr(tf), tf.shape[0])
-    tc = tau_c(mode, tau, iters, gamma_max)
+    mc = mlp.c() if mlp is not None else None
+    tc = tau_c(mode, tau, iters, gamma_max, ctypes.cast(ctypes.pointer(mc), ctypes.c_void_p) if mc else None,
+               fallback_tol, feature_scale)
     _check(lib().vdi_generate(context(), bc, k, ctypes.byref(cc), ctypes.byref(tfc), step, ctypes.byref(tc), oc,
                               _stream()))
     return outs
@@ -266,3 +288,98 @@ def debug_rays(cam, step: float):
     _check(lib().vdi_debug_rays(context(), ctypes.byref(cc), step, _ptr(o), _ptr(d), _ptr(tn), _ptr(tf), _ptr(ns),
                                 _stream()))
     return dict(o=o, d=d, tn=tn, tf=tf, samples=ns)
+
+
+# ---------------------------------------------------------------- learned threshold
+
+class MLP:
+    """The threshold regressor's parameters on the device: a flat fp32 master
+    copy and its bf16 bits (VDI_MLP_PARAMS values each), plus Adam moments."""
+
+    def __init__(self, w_f32: torch.Tensor):
+        assert w_f32.shape == (MLP_PARAMS,) and w_f32.dtype == torch.float32 and w_f32.is_cuda
+        self.w_f32 = w_f32.contiguous()
+        self.w_bf16 = self.w_f32.to(torch.bfloat16).view(torch.int16).contiguous()
+        self.m = torch.zeros_like(self.w_f32)
+        self.v = torch.zeros_like(self.w_f32)
+        self.step = 0
+
+    def c(self) -> vdi_mlp_t:
+        return vdi_mlp_t(_ptr(self.w_bf16), _ptr(self.w_f32))
+
+    @staticmethod
+    def from_numpy_params(params: dict, device=None) -> "MLP":
+        import numpy as np
+        flat = np.concatenate([params[k].astype(np.float32).ravel() for k in ("W1", "b1", "W2", "b2", "w3", "b3")])
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        return MLP(torch.from_numpy(flat).to(dev))
+
+    def to_numpy_params(self) -> dict:
+        w = self.w_f32.detach().cpu().numpy()
+        sizes = (("W1", (128, 64)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)), ("w3", (128,)), ("b3", (1,)))
+        out, o = {}, 0
+        for k, shp in sizes:
+            n = 1
+            for d in shp:
+                n *= d
+            out[k] = w[o:o + n].reshape(shp).copy()
+            o += n
+        return out
+
+
+def tau_features(bricks: Sequence[DeviceBrick], cam, tf: torch.Tensor, step: float, ref_step: float, max_n: int,
+                 iters: int = 10, gamma_max: float = 2.0, feature_scale: float = 32.0):
+    """vdi_tau_features: (hist bf16 bits [k, P, 64] int16, nnt [k, P], cmax [k, P])."""
+    k = len(bricks)
+    P = cam.width * cam.height
+    dev = bricks[0].data.device
+    hist = torch.empty((k, P, 64), dtype=torch.int16, device=dev)
+    nnt = torch.empty((k, P), dtype=torch.int32, device=dev)
+    cmax = torch.empty((k, P), dtype=torch.int32, device=dev)
+    bc = (vdi_brick_t * k)(*[b.c() for b in bricks])
+    cc = camera_c(cam)
+    tfc = vdi_tf_t(_ptr(tf), tf.shape[0])
+    tc = tau_c(LEARNED, 0.0, iters, gamma_max, None, 0.1, feature_scale)
+    _check(lib().vdi_tau_features(context(), bc, k, ctypes.byref(cc), ctypes.byref(tfc), step, ref_step, max_n,
+                                  ctypes.byref(tc), _ptr(hist), _ptr(nnt), _ptr(cmax), _stream()))
+    return hist, nnt, cmax
+
+
+def mlp_forward(mlp: MLP, x: torch.Tensor, want_acts: bool = False):
+    """vdi_mlp_forward on x ([R, 64] bf16 bits as int16 or bfloat16): y [R] (and activations)."""
+    x = x.view(torch.int16) if x.dtype == torch.bfloat16 else x
+    rows = x.shape[0]
+    y = torch.empty((rows,), dtype=torch.float32, device=x.device)
+    acts = torch.empty((rows, MLP_ACT_FLOATS), dtype=torch.float32, device=x.device) if want_acts else None
+    mc = mlp.c()
+    _check(lib().vdi_mlp_forward(context(), ctypes.byref(mc), _ptr(x), rows, _ptr(y), _ptr(acts), _stream()))
+    return (y, acts) if want_acts else y
+
+
+def mlp_backward(mlp: MLP, x: torch.Tensor, acts: torch.Tensor, dy: torch.Tensor) -> torch.Tensor:
+    x = x.view(torch.int16) if x.dtype == torch.bfloat16 else x
+    grad = torch.empty((MLP_PARAMS,), dtype=torch.float32, device=x.device)
+    mc = mlp.c()
+    _check(lib().vdi_mlp_backward(context(), ctypes.byref(mc), _ptr(x), _ptr(acts), _ptr(dy.contiguous()),
+                                  x.shape[0], _ptr(grad), _stream()))
+    return grad
+
+
+def mlp_adam(mlp: MLP, grad: torch.Tensor, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8):
+    mlp.step += 1
+    mc = mlp.c()
+    _check(lib().vdi_mlp_adam(context(), ctypes.byref(mc), _ptr(grad), _ptr(mlp.m), _ptr(mlp.v), mlp.step, lr,
+                              beta1, beta2, eps, _stream()))
+
+
+def learned_stats():
+    st = (ctypes.c_int64 * 4)()
+    _check(lib().vdi_learned_stats(context(), st, _stream()))
+    return {"accepted": st[0], "shortcut": st[1], "fallback": st[2], "empty": st[3]}
+
+
+def debug_mfma(A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+    D = torch.empty((16, 16), dtype=torch.float32, device=A.device)
+    _check(lib().vdi_debug_mfma(context(), _ptr(A.contiguous()), _ptr(B.contiguous()), _ptr(D), _stream()))
+    return D

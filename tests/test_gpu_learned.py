@@ -1,0 +1,194 @@
+"""GPU tests of the learned threshold: matrix-core fragment layout, MLP
+forward/backward against the oracle (same bf16 operands), features against the
+oracle, the learned generation's decisions, and a short training run that shows
+what the regressor gains over plain bisection."""
+import numpy as np
+import pytest
+
+from paper_2206_14503_amd import synth
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="no GPU")]
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    from paper_2206_14503_amd import vdi
+    vdi.lib()
+    torch.cuda.init()
+    return vdi
+
+
+@pytest.fixture(scope="module")
+def OL(orc):
+    import oracle.learned as learned
+    return learned
+
+
+def _bf16_bits(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(torch.bfloat16).view(torch.int16)
+
+
+def test_mfma_fragment_layout(V):
+    """D = A B through one matrix-core instruction equals the exact product
+    (small integers: every product and sum is exact in bf16/fp32)."""
+    import torch
+    rng = np.random.default_rng(0)
+    A = rng.integers(-4, 5, size=(16, 16)).astype(np.float32)
+    B = rng.integers(-4, 5, size=(16, 16)).astype(np.float32)
+    D = V.debug_mfma(_bf16_bits(A).cuda(), _bf16_bits(B).cuda()).cpu().numpy()
+    assert np.array_equal(D, A @ B)
+
+
+def _random_params(OL, seed):
+    p = OL.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    p["b1"] = (rng.standard_normal(128) * 0.1).astype(np.float32)
+    p["b2"] = (rng.standard_normal(128) * 0.1).astype(np.float32)
+    return p
+
+
+@pytest.mark.parametrize("rows", [1, 64, 1000, 4099])
+def test_mlp_forward_matches_oracle(V, OL, rows):
+    import torch
+    p = _random_params(OL, rows)
+    mlp = V.MLP.from_numpy_params(p)
+    rng = np.random.default_rng(rows)
+    x = OL.bf16(rng.uniform(0, 1, size=(rows, 64)) * (rng.uniform(size=(rows, 64)) < 0.3))
+    y_gpu = V.mlp_forward(mlp, _bf16_bits(x).cuda()).cpu().numpy()
+    y_ref, _ = OL.forward(x, p, round_hidden=True)
+    # fp32 vs fp64 accumulation can move a hidden activation across a bf16
+    # rounding boundary; each such flip changes y by about 2^-8 * |h * w3|
+    err = np.abs(y_gpu - y_ref)
+    assert np.median(err) < 1e-4 and err.max() < 2e-2, (np.median(err), err.max())
+
+
+def test_mlp_backward_matches_oracle(V, OL):
+    import torch
+    rows = 1024
+    p = _random_params(OL, 7)
+    mlp = V.MLP.from_numpy_params(p)
+    rng = np.random.default_rng(7)
+    x = OL.bf16(rng.uniform(0, 1, size=(rows, 64)) * (rng.uniform(size=(rows, 64)) < 0.3))
+    t = rng.uniform(-9, 0, size=rows)
+    xg = _bf16_bits(x).cuda()
+    y, acts = V.mlp_forward(mlp, xg, want_acts=True)
+    dy = (y - torch.from_numpy(t).float().cuda()) / rows
+    g = V.mlp_backward(mlp, xg, acts, dy).cpu().numpy()
+    yr, ar = OL.forward(x, p, round_hidden=True)
+    gr = OL.backward(ar, dy.cpu().numpy().astype(np.float64))
+    o = 0
+    for k, shp in (("W1", (128, 64)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)), ("w3", (128,)), ("b3", (1,))):
+        n = int(np.prod(shp))
+        gk = g[o:o + n].reshape(shp)
+        o += n
+        bound = 1e-2 * np.abs(gr[k]).max() + 1e-4
+        assert np.abs(gk - gr[k]).max() <= bound, (k, np.abs(gk - gr[k]).max(), bound)
+
+
+def test_mlp_backward_is_deterministic(V, OL):
+    import torch
+    p = _random_params(OL, 8)
+    mlp = V.MLP.from_numpy_params(p)
+    x = _bf16_bits(np.random.default_rng(8).uniform(0, 1, size=(777, 64))).cuda()
+    y, acts = V.mlp_forward(mlp, x, want_acts=True)
+    g1 = V.mlp_backward(mlp, x, acts, y / 777)
+    g2 = V.mlp_backward(mlp, x, acts, y / 777)
+    assert torch.equal(g1, g2)
+
+
+def test_adam_matches_oracle(V, OL):
+    import torch
+    p = _random_params(OL, 9)
+    mlp = V.MLP.from_numpy_params(p)
+    rng = np.random.default_rng(9)
+    m = {k: np.zeros(v.shape) for k, v in p.items()}
+    v = {k: np.zeros(v.shape) for k, v in p.items()}
+    cur = p
+    for step in range(1, 4):
+        grads = {k: rng.standard_normal(val.shape) * 1e-2 for k, val in p.items()}
+        flat = np.concatenate([grads[k].astype(np.float32).ravel() for k in ("W1", "b1", "W2", "b2", "w3", "b3")])
+        V.mlp_adam(mlp, torch.from_numpy(flat).cuda(), lr=1e-3)
+        cur = OL.adam(cur, {k: g.astype(np.float32).astype(np.float64) for k, g in grads.items()}, m, v, step)
+    got = mlp.to_numpy_params()
+    for k in cur:
+        np.testing.assert_allclose(got[k], cur[k], rtol=1e-5, atol=1e-6)
+    assert torch.equal(mlp.w_bf16, mlp.w_f32.to(torch.bfloat16).view(torch.int16))
+
+
+def test_features_match_oracle(V, OL):
+    """Histogram bins and non-transparent counts are integer decisions: exact.
+    cmax agrees exactly up to the saturation at N+1 (tie-free rays)."""
+    import torch
+    vol = synth.gaussian_volume(64, 12, 3)
+    tf = synth.transfer_function()
+    cam = synth.orbit_camera(10_040, 96, 72)
+    bricks = synth.brick_grid((64, 64, 64), (1, 1, 2))
+    dbr = V.device_bricks(vol, bricks)
+    tf_d = torch.from_numpy(tf).cuda()
+    hist, nnt, cmax = V.tau_features(dbr, cam, tf_d, 1 / 64, 1 / 64, 8, 10, 2.0, 32.0)
+    h_ref, n_ref, c_ref = OL.features(vol, bricks, cam, tf, 1 / 64, 1 / 64, 10, 2.0, 32.0)
+    h = hist.view(torch.bfloat16).float().cpu().numpy()
+    assert np.array_equal(h, h_ref)
+    assert np.array_equal(nnt.cpu().numpy(), n_ref)
+    g = np.full(n_ref.shape, 2.0 ** -9, np.float32)
+    _, margin = OL.count_at(vol, bricks, cam, tf, 1 / 64, 1 / 64, g, 8)
+    free = margin >= 2e-5
+    assert np.array_equal(cmax.cpu().numpy()[free], np.minimum(c_ref, 9)[free])
+
+
+def test_learned_generation_decisions(V, OL):
+    """With an arbitrary regressor, every list is either kept at the regressed
+    threshold (count inside the band) or equal to the plain bisection's list;
+    the all-feasible shortcut gives the bisection's result exactly."""
+    import torch
+    vol = synth.gaussian_volume(64, 12, 5)
+    tf = synth.transfer_function()
+    cam = synth.ortho_camera(128, 128, "+z")
+    bricks = synth.brick_grid((64, 64, 64), (1, 1, 2))
+    dbr = V.device_bricks(vol, bricks)
+    tf_d = torch.from_numpy(tf).cuda()
+    p = OL.init_params(11)
+    p["b3"][:] = -5.0
+    mlp = V.MLP.from_numpy_params(p)
+    plain = V.generate(dbr, cam, tf_d, 1 / 64, 1 / 64, V.BISECT, 0.0, 8, 10)
+    V.learned_stats()
+    lrn = V.generate(dbr, cam, tf_d, 1 / 64, 1 / 64, V.LEARNED, 0.0, 8, 10, mlp=mlp)
+    st = V.learned_stats()
+    hist, nnt, cmax = V.tau_features(dbr, cam, tf_d, 1 / 64, 1 / 64, 8, 10, 2.0, 32.0)
+    assert st["accepted"] + st["shortcut"] + st["fallback"] + st["empty"] == 2 * 128 * 128
+    for r in range(2):
+        cp, cl = plain[r].count.cpu().numpy(), lrn[r].count.cpu().numpy()
+        gp, gl = plain[r].gamma.cpu().numpy(), lrn[r].gamma.cpu().numpy()
+        n, cm = nnt[r].cpu().numpy(), cmax[r].cpu().numpy()
+        same = gl == gp
+        # lists not served by the regressor, or sent back to bisection, equal the plain ones bit for bit
+        eq = same & (cl == cp)
+        assert np.all(eq[n <= 8])
+        col_p, col_l = plain[r].color.cpu().numpy(), lrn[r].color.cpu().numpy()
+        assert np.array_equal(col_p[:, eq], col_l[:, eq])
+        kept = ~same
+        m = np.minimum(8, cm)
+        lo = m - np.floor(0.1 * m + 1e-6)
+        assert np.all((cl[kept] <= 8) & (cl[kept] >= lo[kept]))
+
+
+def test_learned_gain_short_training(V):
+    """Train on a few volumes with the project's kernels, evaluate on a held-out
+    volume: the learned path keeps most regressed thresholds and renders the
+    same image from the original view; report its speed against bisection."""
+    import torch
+    from paper_2206_14503_amd import learned
+    cfg = learned.LearnedConfig(res=128)
+    tf_d = torch.from_numpy(synth.transfer_function()).cuda()
+    X, Y, st = learned.training_pairs(cfg, seeds=range(6), tf_d=tf_d)
+    assert st["kept"] > 1000
+    mlp = learned.init_mlp(0)
+    losses = learned.train(mlp, X, Y, epochs=6, batch=1024, lr=3e-3)
+    assert losses[-1] < 0.5 * losses[0]
+    ev = learned.evaluate(mlp, cfg, seeds=[100], tf_d=tf_d, reps=3)
+    print("learned vs plain:", ev)
+    assert ev["rgba_mae_vs_plain_render"] <= 1e-3
+    assert ev["accepted"] > 0
