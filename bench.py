@@ -3,11 +3,18 @@
 A step is one frame of the whole path on the FHD workload: generate the 8
 sub-VDIs of a 512^3 fp32 volume split into z-slabs (per-ray bisection of the
 threshold to N=20, compact layout), composite them into one N=20 VDI and render
-it from the original view.  The metric is composited VDI pixels per second.
+it from the original view.  The headline metric is composited VDI pixels per
+second of that step.  Further legs (same JSON line):
+  large    -- 1024^3 fp16 volume in 16 bricks (4x2x2): generate + composite,
+              and the composite alone on maximally interleaved dense lists
+              (16 x 20 supersegments per pixel), the HBM-bound case;
+  learned  -- learned vs plain threshold search on held-out tiny volumes
+              (regressor trained here with the project's kernels);
+  batched  -- 64 composites of mixed size, k and N in one persistent launch
+              replayed from a hipGraph: jobs/s and per-job latency.
+Printed: ONE JSON line on stdout (progress goes to stderr).
 
-Printed: ONE JSON line on stdout (everything else goes to stderr).
-
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--legs fhd,large,learned,batched]
 """
 from __future__ import annotations
 
@@ -27,40 +34,45 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def composite_bytes(subs, out_n, npix, counts_total):
+def composite_bytes(inputs, out_n, npix, counts_total):
     """Algorithmic bytes of one composite launch: every stored input
     supersegment read once (24 B), each input's count (4 B) and, for compact
     inputs, offset (4 B) per pixel, and the zero-filled regular output written
     once (24 B per slot) plus its count and gamma planes (4 B + 4 B per pixel)."""
-    k = len(subs)
+    k = len(inputs)
     b = 24 * counts_total + 4 * k * npix
-    b += sum(4 * npix for s in subs if s.offset is not None)
+    b += sum(4 * npix for s in inputs if s.offset is not None)
     b += 24 * out_n * npix + 8 * npix
     return b
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--layout", choices=["compact", "regular"], default="compact")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
-    args = ap.parse_args()
+def ev():
+    import torch
+    return torch.cuda.Event(enable_timing=True)
 
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the k bricks of a frame are resident on one device). Run with --gpus 1.", file=sys.stderr)
-        sys.exit(2)
 
+def timed_ms(fn, reps):
+    """Per-call milliseconds of fn() over reps calls (HIP events on the current stream)."""
     import numpy as np
     import torch
+    out = []
+    for _ in range(reps):
+        a, b = ev(), ev()
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b))
+    return np.array(out)
 
+
+# ---------------------------------------------------------------- FHD (headline)
+
+def leg_fhd(args, result):
+    import numpy as np
+    import torch
     from paper_2206_14503_amd import synth, vdi
 
-    torch.cuda.set_device(0)
     w = synth.fhd(args.seed)
     log(f"[bench] workload {w.name}: building inputs on the GPU")
     t0 = time.time()
@@ -73,15 +85,12 @@ def main():
     step_len = 1.0 / w.n
     P = cam.width * cam.height
     layout = vdi.COMPACT if args.layout == "compact" else vdi.REGULAR
-    subs = [vdi.VDI.empty(cam.width, cam.height, w.max_n, step_len, layout, capacity=w.max_n * P)
-            for _ in bricks]
+    subs = [vdi.VDI.empty(cam.width, cam.height, w.max_n, step_len, layout, capacity=w.max_n * P) for _ in bricks]
     out = vdi.VDI.empty(cam.width, cam.height, w.max_n, step_len, vdi.REGULAR)
     img = torch.empty((P, 4), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     log(f"[bench] inputs ready in {time.time() - t0:.1f}s; {len(bricks)} bricks, {cam.width}x{cam.height}, N={w.max_n}")
-
     mode = vdi.BISECT if w.mode == "bisect" else vdi.FIXED
-    ev = lambda: torch.cuda.Event(enable_timing=True)
 
     def step(marks=None):
         if marks is not None:
@@ -103,23 +112,20 @@ def main():
     flags = vdi.device_status()
     if flags:
         raise RuntimeError(f"device status flags {flags} after warmup")
-
     marks = [[ev() for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     start, stop = ev(), ev()
-    t_wall = time.time()
     start.record()
     for i in range(args.steps):
         step(marks[i])
     stop.record()
     torch.cuda.synchronize()
-    t_wall = time.time() - t_wall
     total_ms = start.elapsed_time(stop)
     ms_step = total_ms / args.steps
     gen_ms = np.array([m[0].elapsed_time(m[1]) for m in marks])
     comp_ms = np.array([m[1].elapsed_time(m[2]) for m in marks])
     rend_ms = np.array([m[2].elapsed_time(m[3]) for m in marks])
-    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step (wall {t_wall:.2f}s); generate {gen_ms.mean():.3f} ms, "
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step; generate {gen_ms.mean():.3f} ms, "
         f"composite {comp_ms.mean():.3f} ms, render {rend_ms.mean():.3f} ms")
 
     counts_total = int(sum(int(s.count.to(torch.int64).sum()) for s in subs))
@@ -130,7 +136,7 @@ def main():
         f"{cbytes / 1e9:.3f} GB -> {comp_gbs:.1f} GB/s ({100 * comp_gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
 
     value = P * args.steps / (total_ms * 1e-3)
-    result = {
+    result.update({
         "metric": "composited VDI pixels/s (k ranks, N supersegs) + % HBM peak; learned vs plain τ speedup",
         "value": value,
         "unit": "pixels/s",
@@ -148,25 +154,187 @@ def main():
                    "iters": w.iters, "tau_mode": w.mode, "layout": args.layout, "seed": w.seed},
         "stages_ms": {"generate": float(gen_ms.mean()), "composite": float(comp_ms.mean()),
                       "render": float(rend_ms.mean())},
-        "composite": {"input_supersegments": counts_total, "output_supersegments": out_total,
-                      "algorithmic_bytes": cbytes, "achieved_GBps": comp_gbs,
-                      "frac_hbm_peak": comp_gbs / HBM_PEAK_GBS},
-    }
-    dominant = max(result["stages_ms"], key=result["stages_ms"].get)
+        "composite_fhd": {"input_supersegments": counts_total, "output_supersegments": out_total,
+                          "algorithmic_bytes": cbytes, "ms": float(comp_ms.mean()), "achieved_GBps": comp_gbs,
+                          "frac_hbm_peak": comp_gbs / HBM_PEAK_GBS},
+    })
     result["roofline"] = {"kernel": "composite_kernel", "bound": "hbm", "achieved": comp_gbs, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": comp_gbs / HBM_PEAK_GBS, "traffic": None,
-                          "note": f"dominant stage this run: {dominant}"}
+                          "workload": w.name}
+    return dict(w=w, vol=vol, bricks=bricks, tf=tf, cam=cam, step_len=step_len)
 
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, vol, bricks, tf, cam, step_len, args.cpu_seconds)
-        result["cpu_baseline"]["gpu_over_cpu"] = value / result["cpu_baseline"]["value"]
-    print(json.dumps(result), flush=True)
 
+# ---------------------------------------------------------------- large one-GPU share
+
+def leg_large(args, result):
+    import numpy as np
+    import torch
+    from paper_2206_14503_amd import synth, vdi
+
+    w = synth.large(args.seed)
+    log(f"[bench] large: {w.name}")
+    t0 = time.time()
+    vol = synth.workload_volume(w, device="cuda")
+    bricks = synth.brick_grid((w.n, w.n, w.n), w.grid)
+    dbr = vdi.device_bricks(vol, bricks)
+    del vol
+    tf_d = torch.from_numpy(synth.transfer_function()).cuda()
+    cam = synth.camera_for(w)
+    step_len = 1.0 / w.n
+    P = cam.width * cam.height
+    subs = [vdi.VDI.empty(cam.width, cam.height, w.max_n, step_len, vdi.REGULAR) for _ in bricks]
+    out = vdi.VDI.empty(cam.width, cam.height, w.max_n, step_len, vdi.REGULAR)
+    torch.cuda.synchronize()
+    log(f"[bench] large inputs ready in {time.time() - t0:.1f}s")
+    gen = lambda: vdi.generate(dbr, cam, tf_d, step_len, step_len, vdi.BISECT, 0.0, w.max_n, w.iters, outs=subs)
+    comp = lambda: vdi.composite(subs, vdi.BISECT, 0.0, w.max_n, w.iters, out=out)
+    gen()
+    comp()
+    torch.cuda.synchronize()
+    g_ms = timed_ms(gen, 3)
+    c_ms = timed_ms(comp, 5)
+    counts_total = int(sum(int(s.count.to(torch.int64).sum()) for s in subs))
+    cbytes = composite_bytes(subs, w.max_n, P, counts_total)
+    gbs = cbytes / (np.median(c_ms) * 1e-3) / 1e9
+    log(f"[bench] large generated: generate {np.median(g_ms):.2f} ms, composite {np.median(c_ms):.3f} ms, "
+        f"{counts_total} input supersegments, {gbs:.0f} GB/s")
+    res = {"workload": w.name, "generate_ms": float(np.median(g_ms)), "composite_ms": float(np.median(c_ms)),
+           "input_supersegments": counts_total, "algorithmic_bytes": cbytes, "achieved_GBps": gbs,
+           "frac_hbm_peak": gbs / HBM_PEAK_GBS, "composited_pixels_per_s": P / (np.median(c_ms) * 1e-3)}
+    del subs, dbr
+    torch.cuda.empty_cache()
+
+    # dense maximally interleaved lists: 16 inputs x 20 supersegments per pixel
+    k, n = 16, 20
+    color = torch.empty((k, n, P, 4), dtype=torch.float32, device="cuda")
+    depth = torch.empty((k, n, P, 2), dtype=torch.float32, device="cuda")
+    chunk = 1 << 17
+    for p0 in range(0, P, chunk):
+        p1 = min(P, p0 + chunk)
+        c, d, _ = synth.dense_interleaved_lists(k, n, p1 - p0, seed=args.seed * 1000 + p0 // chunk, device="cuda")
+        color[:, :, p0:p1] = c
+        depth[:, :, p0:p1] = d
+    cnt = torch.full((k, P), n, dtype=torch.int32, device="cuda")
+    ins = [vdi.VDI(cam.width, cam.height, n, 0.01, vdi.REGULAR, color[r], depth[r], cnt[r]) for r in range(k)]
+    out2 = vdi.VDI.empty(cam.width, cam.height, n, 0.01, vdi.REGULAR)
+    comp2 = lambda: vdi.composite(ins, vdi.BISECT, 0.0, n, 10, out=out2)
+    comp2()
+    torch.cuda.synchronize()
+    c2 = timed_ms(comp2, 3)
+    b2 = composite_bytes(ins, n, P, k * n * P)
+    gbs2 = b2 / (np.median(c2) * 1e-3) / 1e9
+    log(f"[bench] large dense interleaved: composite {np.median(c2):.3f} ms, {b2 / 1e9:.2f} GB, {gbs2:.0f} GB/s")
+    res["dense_interleaved"] = {"k": k, "n_per_input": n, "composite_ms": float(np.median(c2)),
+                                "algorithmic_bytes": b2, "achieved_GBps": gbs2, "frac_hbm_peak": gbs2 / HBM_PEAK_GBS,
+                                "composited_pixels_per_s": P / (np.median(c2) * 1e-3)}
+    result["large"] = res
+    del color, depth, ins, out2
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- learned threshold
+
+def leg_learned(args, result):
+    import torch
+    from paper_2206_14503_amd import learned, synth
+
+    cfg = learned.LearnedConfig()
+    tf_d = torch.from_numpy(synth.transfer_function()).cuda()
+    t0 = time.time()
+    X, Y, st = learned.training_pairs(cfg, seeds=range(args.learn_seeds), tf_d=tf_d)
+    log(f"[bench] learned: {X.shape[0]} training pairs ({st['rays']} brick-rays) in {time.time() - t0:.1f}s")
+    mlp = learned.init_mlp(0)
+    t1 = time.time()
+    losses = learned.train(mlp, X, Y, epochs=args.learn_epochs, batch=4096, lr=2e-3, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    ev_ = learned.evaluate(mlp, cfg, seeds=range(100, 108), tf_d=tf_d, reps=3)
+    log(f"[bench] learned vs plain: {ev_}")
+    result["learned"] = {"train_pairs": int(X.shape[0]), "train_seconds": t_train, "final_loss": losses[-1],
+                         "eval_rays": ev_["frames"] * cfg.res * cfg.res * 2, **ev_}
+
+
+# ---------------------------------------------------------------- batched composites
+
+def leg_batched(args, result):
+    import numpy as np
+    import torch
+    from paper_2206_14503_amd import synth, vdi
+
+    specs = synth.batch_jobs(5000, 64)
+    pw = synth.batch_pool_workload(5000)
+    vol = synth.workload_volume(pw, device="cuda")
+    bricks = synth.brick_grid((pw.n,) * 3, pw.grid)
+    dbr = vdi.device_bricks(vol, bricks)
+    tf_d = torch.from_numpy(synth.transfer_function()).cuda()
+    step_len = 1.0 / pw.n
+    pool = {}
+    t0 = time.time()
+    for (wd, ht, k, n) in specs:
+        if (wd, ht, n) in pool:
+            continue
+        cam = synth.orbit_camera(10_000 + 5000, wd, ht)
+        subs = vdi.generate(dbr, cam, tf_d, step_len, step_len, vdi.BISECT, 0.0, n, 10, layout=vdi.COMPACT,
+                            capacity=n * wd * ht)
+        pool[(wd, ht, n)] = subs
+    torch.cuda.synchronize()
+    log(f"[bench] batched: pooled {len(pool)} sets of 16 compact sub-VDIs in {time.time() - t0:.1f}s")
+    jobs = []
+    for (wd, ht, k, n) in specs:
+        out = vdi.VDI.empty(wd, ht, n, step_len, vdi.REGULAR)
+        jobs.append(vdi.Job(pool[(wd, ht, n)][:k], out, mode=vdi.BISECT, iters=10))
+    outdir = os.path.join(ROOT, "gpurun_out")
+    cache = os.path.join(outdir, "autotune_tiles.txt") if os.path.isdir(outdir) else None
+    t_tune = None
+    if cache:
+        t1 = time.time()
+        vdi.autotune(jobs, cache)
+        t_tune = time.time() - t1
+        log(f"[bench] batched: autotuned tile sizes in {t_tune:.1f}s -> {open(cache).read().strip()}")
+    b = vdi.Batch(jobs, autotune_cache=cache)
+    info = b.info()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.run()
+    s.synchronize()
+    with torch.cuda.stream(s):
+        b.capture(s)
+    torch.cuda.synchronize()
+    reps = 5
+    times, lats = [], []
+    for _ in range(reps):
+        a, e = ev(), ev()
+        a.record(s)
+        b.replay(s)
+        e.record(s)
+        s.synchronize()
+        times.append(a.elapsed_time(e))
+        lat, span = b.latencies_s()
+        lats.append(lat)
+    lats = np.concatenate(lats) * 1e3
+    ms = float(np.median(times))
+    bytes_total = 0
+    for j in jobs:
+        ct = int(sum(int(v.count.to(torch.int64).sum()) for v in j.inputs))
+        bytes_total += composite_bytes(j.inputs, j.out.max_n, j.out.npix, ct)
+    gbs = bytes_total / (ms * 1e-3) / 1e9
+    log(f"[bench] batched: {len(jobs)} jobs in {ms:.2f} ms -> {len(jobs) / (ms * 1e-3):.0f} jobs/s; "
+        f"p50 {np.percentile(lats, 50):.3f} ms p99 {np.percentile(lats, 99):.3f} ms; {gbs:.0f} GB/s")
+    result["batched"] = {"jobs": len(jobs), "ms_per_batch": ms, "jobs_per_s": len(jobs) / (ms * 1e-3),
+                         "latency_ms_p50": float(np.percentile(lats, 50)),
+                         "latency_ms_p99": float(np.percentile(lats, 99)),
+                         "algorithmic_bytes": bytes_total, "achieved_GBps": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+                         "tiles": info["tiles"], "grid": info["grid"], "autotune_seconds": t_tune,
+                         "launch": "one persistent kernel replayed from a hipGraph"}
+    b.close()
+
+
+# ---------------------------------------------------------------- CPU baseline
 
 def cpu_baseline(w, vol, bricks, tf, cam, step_len, target_s):
     """The oracle on a bounded, seeded sample of the same frame's pixels:
     generate all bricks' lists for those pixels, then composite them.  Pixels
-    per second of the oracle on all host cores."""
+    per second of the oracle on the host threads it was given."""
     import numpy as np
     import oracle
     host_vol = vol.float().cpu().numpy() if w.vol_dtype == "f32" else vol.cpu().numpy()
@@ -185,15 +353,61 @@ def cpu_baseline(w, vol, bricks, tf, cam, step_len, target_s):
                          [g["count"][r] for r in range(k)], step_len, mode, w.tau, w.max_n, w.iters, nthreads=cores)
         return time.time() - t
 
-    npx = 2048
+    npx = 4096
     t = run(npx)
     npx2 = int(min(P, max(npx, npx * target_s / max(t, 1e-3))))
     if npx2 > npx:
         npx, t = npx2, run(npx2)
     log(f"[bench] cpu baseline: oracle on {npx} sampled pixels took {t:.2f}s with {cores} threads")
     return {"value": npx / t, "unit": "pixels/s", "cores": cores, "kind": "oracle",
-            "sample": f"{npx} seeded random pixels of the same frame (generate all {len(bricks)} bricks + composite)",
-            "seconds": t}
+            "sample": f"{npx} seeded random pixels of the same FHD frame (generate all {len(bricks)} bricks + "
+                      f"composite)", "seconds": t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--layout", choices=["compact", "regular"], default="compact")
+    ap.add_argument("--legs", default="fhd,large,learned,batched")
+    ap.add_argument("--learn-seeds", type=int, default=32)
+    ap.add_argument("--learn-epochs", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device-to-device three times (a kernel of known traffic for counter scaling)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the k bricks of a frame are resident on one device). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    legs = set(args.legs.split(","))
+    result = {}
+    if args.copy_calibration:
+        src = torch.ones((1 << 28,), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 3 x 1 GiB device-to-device copies")
+        del src, dst
+    fhd = leg_fhd(args, result)
+    if "large" in legs:
+        leg_large(args, result)
+    if "learned" in legs:
+        leg_learned(args, result)
+    if "batched" in legs:
+        leg_batched(args, result)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(fhd["w"], fhd["vol"], fhd["bricks"], fhd["tf"], fhd["cam"],
+                                              fhd["step_len"], args.cpu_seconds)
+        result["cpu_baseline"]["gpu_over_cpu"] = result["value"] / result["cpu_baseline"]["value"]
+    print(json.dumps(result), flush=True)
 
 
 if __name__ == "__main__":

@@ -121,15 +121,17 @@ typedef struct {
  *  BISECT:  per list, `iters` halvings of [0, gamma_max]; a midpoint is
  *           feasible iff it yields at most max_n supersegments; the result is
  *           the upper bracket.
- *  LEARNED: (an extension beyond the paper) per list, gamma = 2^y with y the
- *           output of the MLP `mlp` (a vdi_mlp_t*) on the list's 64-bin opacity
- *           histogram (see vdi_tau_features), clamped to [gamma_max*2^-iters,
- *           gamma_max].  The result is kept if its count c satisfies
- *           m - floor(fallback_tol*m) <= c <= N with m = min(N, cmax) (cmax:
- *           the count at the smallest bisection threshold); otherwise the list
- *           is regenerated by BISECT.  Lists with at most N non-transparent
- *           samples take the bisection's result directly (every threshold is
- *           feasible there).  Regular layout only. */
+ *  LEARNED: (an extension beyond the paper) per list, y = output of the MLP
+ *           `mlp` (a vdi_mlp_t*) on the list's 64-bin opacity histogram (see
+ *           vdi_tau_features); the candidates gamma = 2^(y + d), d in
+ *           {0, -1/4, 1/4, -1/2, 1/2}, each clamped to [gamma_max*2^-iters,
+ *           gamma_max], are counted in one scan.  A candidate is in band if its
+ *           count c satisfies m - floor(fallback_tol*m) <= c <= N with
+ *           m = min(N, cmax) (cmax: the count at the smallest bisection
+ *           threshold); the in-band candidate with the largest count is used,
+ *           and a list with none is regenerated by BISECT.  Lists with at most
+ *           N non-transparent samples take the bisection's result directly
+ *           (every threshold is feasible there).  Regular layout only. */
 typedef struct {
     int32_t mode;            /* vdi_tau_mode */
     float tau;
@@ -232,6 +234,58 @@ vdi_status vdi_learned_stats(vdi_ctx *ctx, int64_t *stats, void *stream);
 /* Diagnostic: D = A B for 16x16 bf16 A, B (row-major) through one matrix-core
  * instruction with the fragment layout the MLP kernels use; D fp32 16x16. */
 vdi_status vdi_debug_mfma(vdi_ctx *ctx, const uint16_t *A, const uint16_t *B, float *D, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched compositing (an extension beyond the paper): many independent
+ * composites of different viewport size, k and N in one persistent launch.
+ * Each job is exactly what vdi_composite computes for it (same kernels, bit
+ * for bit).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    const vdi_t *in;         /* HOST array of k input VDIs (their data on the device) */
+    int32_t k;               /* 1..VDI_MAX_INPUTS */
+    vdi_t out;               /* regular output, same width/height/ref_step as the inputs */
+    vdi_tau_t tau;           /* FIXED or BISECT */
+} vdi_job_t;
+
+typedef struct vdi_batch vdi_batch;
+
+/* Checks the jobs (as vdi_composite would), then uploads a device job table
+ * and a tile queue: jobs ordered by decreasing estimated work (k*N*pixels),
+ * each job's pixels cut into tiles whose size is read from `autotune_cache`
+ * (a file written by vdi_autotune; NULL or no entry: 256 pixels) for the job's
+ * (k bucket, N) with k buckets 1-4, 5-8, 9-32.  This is the only batch call
+ * that allocates device memory; the job descriptors are copied, the VDIs they
+ * point to must stay valid while the batch is used. */
+vdi_status vdi_batch_create(vdi_ctx *ctx, const vdi_job_t *jobs, int n_jobs, const char *autotune_cache,
+                            vdi_batch **out);
+
+/* One persistent launch (grid sized to fill the device) whose blocks pull
+ * tiles from a device counter until none is left; preceded by two small fill
+ * kernels that reset the counter and t_start_end.  t_start_end: DEVICE
+ * [2*n_jobs] or NULL; per job the earliest tile start and the latest tile end
+ * in ticks of the device's constant-rate clock (see vdi_batch_info).  Neither
+ * allocates nor synchronises, so it can be captured in a graph. */
+vdi_status vdi_batch_run(vdi_batch *batch, uint64_t *t_start_end, void *stream);
+
+/* Captures vdi_batch_run(batch, t_start_end, stream) into a hipGraph (once;
+ * a second call replaces it).  vdi_batch_replay launches the graph on stream. */
+vdi_status vdi_batch_capture(vdi_batch *batch, uint64_t *t_start_end, void *stream);
+vdi_status vdi_batch_replay(vdi_batch *batch, void *stream);
+
+/* n_tiles, persistent grid (blocks of 64 threads), dynamic LDS bytes per block,
+ * and the frequency of the timestamp clock in Hz.  Any pointer may be NULL. */
+vdi_status vdi_batch_info(const vdi_batch *batch, int32_t *n_tiles, int32_t *grid, int32_t *lds_bytes,
+                          double *clock_hz);
+vdi_status vdi_batch_destroy(vdi_batch *batch);
+
+/* Tile-size autotuner: for each (k bucket, N) present in `jobs`, runs those
+ * jobs as a batch with each candidate tile size (64, 128, 256, 512, 1024
+ * pixels), keeps the fastest (median of 3 timed runs after one warm-up) and
+ * writes one line per bucket, "arch kbucket N tile_pixels milliseconds", to
+ * cache_path (replacing the file).  The jobs' outputs are overwritten.
+ * Synchronises stream. */
+vdi_status vdi_autotune(vdi_ctx *ctx, const vdi_job_t *jobs, int n_jobs, const char *cache_path, void *stream);
 
 /* Device-side status of the context since the last call to this function
  * (synchronises `stream` first): bit 0 = a compact output overflowed its

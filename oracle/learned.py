@@ -5,6 +5,7 @@ TEST INFRASTRUCTURE (see oracle/__init__.py).
 
 Network: 64 -> 128 -> 128 -> 1, GELU (exact erf form) after both hidden
 layers, linear output y, regressed onto log2(gamma*) with mean squared error.
+Weight matrices are stored (out, in): z1 = x W1^T + b1, z2 = h1 W2^T + b2.
 Weights and inputs are bf16; products accumulate in fp64 here.  With
 `round_hidden=True` the hidden activations are rounded to bf16 before the next
 layer, where the kernels round them; with False the network is a plain fp64
@@ -53,7 +54,7 @@ def init_params(seed: int = 0) -> Dict[str, np.ndarray]:
     """fp32 master weights (He-style scale); the forward uses their bf16 copies."""
     rng = np.random.default_rng(seed)
     return {
-        "W1": (rng.standard_normal((64, 128)) * math.sqrt(2.0 / 64)).astype(np.float32),
+        "W1": (rng.standard_normal((128, 64)) * math.sqrt(2.0 / 64)).astype(np.float32),
         "b1": np.zeros(128, np.float32),
         "W2": (rng.standard_normal((128, 128)) * math.sqrt(2.0 / 128)).astype(np.float32),
         "b2": np.zeros(128, np.float32),
@@ -68,11 +69,11 @@ def forward(x, params, round_hidden: bool = True, round_weights: bool = True):
     W1, W2, w3 = q(params["W1"]), q(params["W2"]), q(params["w3"])
     b1, b2, b3 = (np.asarray(params[k], np.float64) for k in ("b1", "b2", "b3"))
     x = np.asarray(x, np.float64)
-    z1 = x @ W1 + b1
+    z1 = x @ W1.T + b1
     h1 = gelu(z1)
     if round_hidden:
         h1 = bf16(h1)
-    z2 = h1 @ W2 + b2
+    z2 = h1 @ W2.T + b2
     h2 = gelu(z2)
     if round_hidden:
         h2 = bf16(h2)
@@ -94,11 +95,11 @@ def backward(acts, dy) -> Dict[str, np.ndarray]:
     g["b3"] = np.array([dy.sum()])
     dh2 = np.outer(dy, acts["w3"])
     dz2 = dh2 * gelu_grad(acts["z2"])
-    g["W2"] = acts["h1"].T @ dz2
+    g["W2"] = dz2.T @ acts["h1"]
     g["b2"] = dz2.sum(axis=0)
-    dh1 = dz2 @ acts["W2"].T
+    dh1 = dz2 @ acts["W2"]
     dz1 = dh1 * gelu_grad(acts["z1"])
-    g["W1"] = acts["x"].T @ dz1
+    g["W1"] = dz1.T @ acts["x"]
     g["b1"] = dz1.sum(axis=0)
     return g
 

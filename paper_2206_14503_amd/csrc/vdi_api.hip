@@ -10,13 +10,6 @@
 #include "vdi_internal.h"
 #include "vdi_kernels.h"
 
-struct vdi_ctx {
-    int device;
-    int* status;          // device flags word
-    void* scratch;        // grown on demand, kept until destroy
-    size_t scratch_bytes;
-};
-
 namespace vdi {
 
 static thread_local char g_err[1024];
@@ -29,7 +22,7 @@ void set_error(const char* fmt, ...)
     va_end(ap);
 }
 
-static vdi_status fail(vdi_status st, const char* fmt, ...)
+vdi_status fail(vdi_status st, const char* fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
@@ -38,14 +31,14 @@ static vdi_status fail(vdi_status st, const char* fmt, ...)
     return st;
 }
 
-static vdi_status launched()
+vdi_status launched()
 {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VDI_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     return VDI_OK;
 }
 
-static vdi_status ensure_scratch(vdi_ctx* ctx, size_t bytes)
+vdi_status ensure_scratch(vdi_ctx* ctx, size_t bytes)
 {
     if (bytes <= ctx->scratch_bytes) return VDI_OK;
     if (ctx->scratch) {
@@ -233,6 +226,8 @@ vdi_status vdi_ctx_create(vdi_ctx** out, int device)
     c->device = device;
     c->scratch = nullptr;
     c->scratch_bytes = 0;
+    c->num_cus = prop.multiProcessorCount;
+    snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
     hipError_t e = hipMalloc(&c->status, 64);
     if (e == hipSuccess) e = hipMemset(c->status, 0, 64);
     if (e != hipSuccess) {

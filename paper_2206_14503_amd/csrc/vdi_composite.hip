@@ -213,28 +213,28 @@ __device__ void c_scan(const Lds& L, int t, int total, float inv_ref, const floa
 
 }  // namespace
 
-__global__ __launch_bounds__(64) void composite_kernel(CompParams P)
+// The input table of a job in LDS (thread t < k writes entry t).
+__device__ inline void setup_inputs(const CompParams& P, unsigned char* lds_raw, int t)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int t = threadIdx.x;
-    Lds L;
     InLds* in_tab = (InLds*)lds_raw;
-    L.in = in_tab;
-    L.seq = (uint16_t*)(lds_raw + sizeof(InLds) * kMaxInputs);
-    L.front = (float*)(lds_raw + sizeof(InLds) * kMaxInputs + (size_t)2 * kWave * P.seq_cap);
-    L.ebase = (uint32_t*)(L.front + kWave * P.k);
-    L.cur = (uint16_t*)(L.ebase + kWave * P.k);
-    L.cnt = L.cur + kWave * P.k;
     if (t < P.k) {
         in_tab[t].color = P.in[t].color;
         in_tab[t].depth = P.in[t].depth;
         in_tab[t].stride = P.in[t].compact ? 1u : P.npix;
         in_tab[t].pad = 0;
     }
-    __syncthreads();
+}
 
-    const uint32_t p = blockIdx.x * kWave + t;
-    if (p >= P.npix) return;
+// Merge and re-segment the lists of pixel p (lane t of the wave).
+__device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int t, uint32_t p)
+{
+    Lds L;
+    L.in = (const InLds*)lds_raw;
+    L.seq = (uint16_t*)(lds_raw + sizeof(InLds) * kMaxInputs);
+    L.front = (float*)(lds_raw + sizeof(InLds) * kMaxInputs + (size_t)2 * kWave * P.seq_cap);
+    L.ebase = (uint32_t*)(L.front + kWave * P.k);
+    L.cur = (uint16_t*)(L.ebase + kWave * P.k);
+    L.cnt = L.cur + kWave * P.k;
 
     // ---- load counts, validate, set up the merge cursors
     int total = 0;
@@ -343,6 +343,75 @@ __global__ __launch_bounds__(64) void composite_kernel(CompParams P)
     }
     P.out_count[p] = count;
     if (P.out_gamma) P.out_gamma[p] = gm;
+}
+
+__global__ __launch_bounds__(64) void composite_kernel(CompParams P)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int t = threadIdx.x;
+    setup_inputs(P, lds_raw, t);
+    __syncthreads();
+    const uint32_t p = blockIdx.x * kWave + t;
+    if (p < P.npix) composite_pixel(P, lds_raw, t, p);
+}
+
+// ---------------------------------------------------------------- batched (persistent)
+//
+// One launch composites many jobs of different size, k and N.  The jobs'
+// pixels are cut into tiles (tile size chosen per (k, N) bucket); blocks pull
+// tile indices from a device counter until the queue is empty, so every block
+// exits once all tiles are taken.  Per job, the earliest tile start and the
+// latest tile end are recorded with the device's constant-rate clock.
+
+__global__ __launch_bounds__(64) void batch_kernel(const CompParams* __restrict__ jobs,
+                                                   const uint2* __restrict__ tiles, uint32_t n_tiles,
+                                                   uint32_t* head, unsigned long long* t_start_end)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ uint32_t s_tile;
+    const int t = threadIdx.x;
+    int cur_job = -1;
+    for (;;) {
+        if (t == 0) s_tile = atomicAdd(head, 1u);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        __syncthreads();
+        if (tile >= n_tiles) break;
+        const uint2 td = tiles[tile];          // x: job, y: first pixel
+        const int job = (int)(td.x & 0xffffu);
+        const uint32_t npx = td.x >> 16;       // pixels in the tile
+        const CompParams& P = jobs[job];
+        if (job != cur_job) {
+            setup_inputs(P, lds_raw, t);
+            cur_job = job;
+        }
+        __syncthreads();
+        if (t == 0 && t_start_end) atomicMin(&t_start_end[2 * job], (unsigned long long)wall_clock64());
+        for (uint32_t base = td.y; base < td.y + npx; base += kWave) {
+            const uint32_t p = base + t;
+            if (p < td.y + npx && p < P.npix) composite_pixel(P, lds_raw, t, p);
+        }
+        if (t == 0 && t_start_end) atomicMax(&t_start_end[2 * job + 1], (unsigned long long)wall_clock64());
+        __syncthreads();
+    }
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, unsigned long long lo_val, unsigned long long hi_val, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (i & 1) ? hi_val : lo_val;
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v) { p[threadIdx.x] = v; }
+
+void launch_batch(const CompParams* jobs, const uint2* tiles, uint32_t n_tiles, uint32_t* head,
+                  unsigned long long* t_se, int n_jobs, size_t lds, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(1), 0, s, head, 0u);
+    if (t_se)
+        hipLaunchKernelGGL(fill_u64_kernel, dim3((2 * n_jobs + 255) / 256), dim3(256), 0, s, t_se, ~0ull, 0ull,
+                           2 * n_jobs);
+    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kWave), lds, s, jobs, tiles, n_tiles, head, t_se);
 }
 
 size_t composite_lds_bytes(int k, int seq_cap)

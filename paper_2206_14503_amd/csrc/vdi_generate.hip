@@ -134,7 +134,51 @@ __device__ int gen_pass(const VT* data, const BrickGeo& g, const Ray& r, float s
     return count;
 }
 
-// Threshold for one brick-ray and the count it yields.
+// One counting scan over samples [k0, k1) carrying NC segmenter states
+// (thresholds g[]): the sample (position, trilinear taps, classification) is
+// computed once and fed to every state.  A state freezes once its count
+// exceeds `limit`; the scan ends when all are frozen.  n_opaque counts the
+// non-transparent samples seen (complete only if the scan ran to the end).
+template <typename VT, int NC>
+__device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0, int k1,
+                         const float4* tf, int entries, const float* gam, int limit, int* counts, int* n_opaque_out)
+{
+    GenSeg S[NC];
+    int cnt[NC];
+    float g2[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        gen_seg_init(S[c]);
+        cnt[c] = 0;
+        g2[c] = gam[c] * gam[c];
+    }
+    GenOut none{nullptr, nullptr, 0, 0, 0};
+    const bool unit = (l_step == 1.0f);
+    int n_opaque = 0;
+    for (int k = k0; k < k1; ++k) {
+        float4 c = gen_sample<VT>(data, g, r, step, k, tf, entries);
+        n_opaque += (c.w == 0.0f) ? 0 : 1;
+        bool live = false;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            if (cnt[j] <= limit) {
+                gen_step<false>(S[j], cnt[j], none, r, step, l_step, unit, g2[j], 0, k, c);
+                live |= cnt[j] <= limit;
+            }
+        }
+        if (!live) break;
+    }
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        if (S[j].open && cnt[j] <= limit) gen_close<false>(S[j], cnt[j], none, r, step, l_step);
+        counts[j] = cnt[j];
+    }
+    if (n_opaque_out) *n_opaque_out = n_opaque;
+}
+
+// Threshold for one brick-ray and the count it yields.  The bisection runs
+// two levels per scan (midpoint m and both next-level midpoints) and replays
+// the sequential decisions, which it reproduces exactly.
 template <typename VT>
 __device__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0,
                            int k1, const float4* tf, int entries, const GenParams& P, float& gamma_out,
@@ -150,24 +194,51 @@ __device__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, floa
     }
     float lo = 0.0f, hi = P.gmax;
     int hi_count = -1;
-    for (int it = 0; it < P.iters; ++it) {
+    int level = 0;
+    while (level < P.iters) {
         float m = 0.5f * (lo + hi);
-        int n_opaque = 0;
-        int c = gen_pass<VT, false>(data, g, r, step, l_step, k0, k1, tf, entries, m, 0, P.max_n, none,
-                                    it == 0 ? &n_opaque : nullptr);
-        if (c <= P.max_n) {
-            hi = m;
-            hi_count = c;
+        if (level + 2 <= P.iters) {
+            float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
+            int c3[3];
+            int n_opaque = 0;
+            gen_scan<VT, 3>(data, g, r, step, l_step, k0, k1, tf, entries, g3, P.max_n, c3, &n_opaque);
             // every supersegment starts at a non-transparent sample, so a run
-            // with at most N of them is feasible at every threshold: the
-            // remaining halvings all move the upper bracket
-            if (it == 0 && n_opaque <= P.max_n) {
-                for (int j = 1; j < P.iters; ++j) hi *= 0.5f;
-                hi_count = (P.iters > 1) ? -1 : c;
+            // with at most N of them is feasible at every threshold: all
+            // halvings move the upper bracket
+            if (level == 0 && c3[0] <= P.max_n && c3[1] <= P.max_n && n_opaque <= P.max_n) {
+                hi = ldexpf(P.gmax, -P.iters);
+                hi_count = -1;
                 break;
             }
+            if (c3[0] <= P.max_n) {
+                hi = m;
+                hi_count = c3[0];
+                if (c3[1] <= P.max_n) {
+                    hi = g3[1];
+                    hi_count = c3[1];
+                } else {
+                    lo = g3[1];
+                }
+            } else {
+                lo = m;
+                if (c3[2] <= P.max_n) {
+                    hi = g3[2];
+                    hi_count = c3[2];
+                } else {
+                    lo = g3[2];
+                }
+            }
+            level += 2;
         } else {
-            lo = m;
+            int c1[1];
+            gen_scan<VT, 1>(data, g, r, step, l_step, k0, k1, tf, entries, &m, P.max_n, c1, nullptr);
+            if (c1[0] <= P.max_n) {
+                hi = m;
+                hi_count = c1[0];
+            } else {
+                lo = m;
+            }
+            level += 1;
         }
     }
     gamma_out = hi;
@@ -390,19 +461,32 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
                                       o, nullptr);
         atomicAdd(&Lb.stats[1], 1);
     } else {
+        // the regressed threshold and four neighbours (x 2^{-1/2, -1/4, 1/4, 1/2})
+        // share one sampling scan; the in-band candidate with the largest
+        // count is kept (ties: the one listed first)
         const float lg_hi = log2f(P.gmax), lg_lo = lg_hi - (float)P.iters;
-        const float yv = fminf(fmaxf(Lb.y[ray], lg_lo), lg_hi);
-        gm = exp2f(yv);
-        c = gen_pass<VT, true, true>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, 0, P.max_n, o,
-                                     nullptr);
+        const float yv = Lb.y[ray];
+        const float dl[5] = { 0.0f, -0.25f, 0.25f, -0.5f, 0.5f };
+        float g5[5];
+        int c5[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) g5[j] = exp2f(fminf(fmaxf(yv + dl[j], lg_lo), lg_hi));
+        gen_scan<VT, 5>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, g5, P.max_n, c5, nullptr);
         const int target = min(P.max_n, Lb.cmax[ray]);
         const int lo = target - (int)floorf(Lb.tol * (float)target + 1e-6f);
-        if (c > P.max_n || c < lo) {
+        int best = -1;
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            if (c5[j] <= P.max_n && c5[j] >= lo && (best < 0 || c5[j] > c5[best])) best = j;
+        if (best < 0) {
             int pos = atomicAdd(&Lb.fb_count[brick], 1);
             Lb.fb_list[(size_t)brick * npix + pos] = (int)pix;
             atomicAdd(&Lb.stats[2], 1);
             return;
         }
+        gm = g5[best];
+        c = gen_pass<VT, true, false>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, 0, 1 << 30, o,
+                                      nullptr);
         atomicAdd(&Lb.stats[0], 1);
     }
     for (int j = c; j < P.max_n; ++j) {

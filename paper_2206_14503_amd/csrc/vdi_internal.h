@@ -15,11 +15,24 @@
 
 #include "../../include/vdi.h"
 
+// Library context: one per device.
+struct vdi_ctx {
+    int device;
+    int* status;          // device words: [0] flags, [4..7] learned-path counters
+    void* scratch;        // grown on demand, kept until destroy
+    size_t scratch_bytes;
+    int num_cus;
+    char arch[64];
+};
+
 namespace vdi {
 
 // ---------------------------------------------------------------- host plumbing
 
 void set_error(const char* fmt, ...);
+vdi_status fail(vdi_status st, const char* fmt, ...);
+vdi_status launched();                       // VDI_E_HIP if the last launch failed
+vdi_status ensure_scratch(struct ::vdi_ctx* ctx, size_t bytes);
 
 #define VDI_HIP_CHECK(expr)                                                          \
     do {                                                                             \
@@ -239,7 +252,28 @@ struct BrickGeo {
     int ddim[3];    // data box dims
 };
 
+// Two x-adjacent voxels (p[0], p[1]) with one load (4-byte or 2-byte
+// alignment; gfx950 allows unaligned dword loads from global memory).
+typedef float vdi_f2u __attribute__((ext_vector_type(2), aligned(4)));
+typedef unsigned short vdi_h2u __attribute__((ext_vector_type(2), aligned(2)));
+
+template <typename VT> __device__ inline void load_pair(const VT* p, float& a, float& b);
+template <> __device__ inline void load_pair<float>(const float* p, float& a, float& b)
+{
+    vdi_f2u v = *(const vdi_f2u*)p;
+    a = v.x;
+    b = v.y;
+}
+template <> __device__ inline void load_pair<__half>(const __half* p, float& a, float& b)
+{
+    vdi_h2u v = *(const vdi_h2u*)p;
+    a = __half2float(__ushort_as_half(v.x));
+    b = __half2float(__ushort_as_half(v.y));
+}
+
 // Trilinear reconstruction on the global voxel grid from a halo'd brick.
+// Each of the four x-rows of the 2x2x2 stencil is read with one paired load
+// at xb = min(x0, dx-2), which stays inside the row also at clamped edges.
 template <typename VT>
 __device__ inline float trilinear(const VT* data, const BrickGeo& g, const float p[3])
 {
@@ -256,14 +290,32 @@ __device__ inline float trilinear(const VT* data, const BrickGeo& g, const float
         i0[a] = clampi(clampi(ii, 0, g.n[a] - 1) - g.dlo[a], 0, g.ddim[a] - 1);
         i1[a] = clampi(clampi(ii + 1, 0, g.n[a] - 1) - g.dlo[a], 0, g.ddim[a] - 1);
     }
-    const size_t sx = 1, sy = (size_t)g.ddim[0], sz = (size_t)g.ddim[0] * g.ddim[1];
-    size_t b00 = i0[1] * sy + i0[2] * sz, b10 = i1[1] * sy + i0[2] * sz;
-    size_t b01 = i0[1] * sy + i1[2] * sz, b11 = i1[1] * sy + i1[2] * sz;
-    (void)sx;
-    float v000 = load_voxel(data, b00 + i0[0]), v100 = load_voxel(data, b00 + i1[0]);
-    float v010 = load_voxel(data, b10 + i0[0]), v110 = load_voxel(data, b10 + i1[0]);
-    float v001 = load_voxel(data, b01 + i0[0]), v101 = load_voxel(data, b01 + i1[0]);
-    float v011 = load_voxel(data, b11 + i0[0]), v111 = load_voxel(data, b11 + i1[0]);
+    const size_t sy = (size_t)g.ddim[0], sz = (size_t)g.ddim[0] * g.ddim[1];
+    const size_t r00 = i0[1] * sy + i0[2] * sz, r10 = i1[1] * sy + i0[2] * sz;
+    const size_t r01 = i0[1] * sy + i1[2] * sz, r11 = i1[1] * sy + i1[2] * sz;
+    float v000, v100, v010, v110, v001, v101, v011, v111;
+    if (g.ddim[0] >= 2) {
+        const int xb = i0[0] < g.ddim[0] - 2 ? i0[0] : g.ddim[0] - 2;
+        const bool s0 = i0[0] == xb, s1 = i1[0] == xb;
+        float a, b;
+        load_pair<VT>(data + r00 + xb, a, b);
+        v000 = s0 ? a : b;
+        v100 = s1 ? a : b;
+        load_pair<VT>(data + r10 + xb, a, b);
+        v010 = s0 ? a : b;
+        v110 = s1 ? a : b;
+        load_pair<VT>(data + r01 + xb, a, b);
+        v001 = s0 ? a : b;
+        v101 = s1 ? a : b;
+        load_pair<VT>(data + r11 + xb, a, b);
+        v011 = s0 ? a : b;
+        v111 = s1 ? a : b;
+    } else {
+        v000 = v100 = load_voxel(data, r00);
+        v010 = v110 = load_voxel(data, r10);
+        v001 = v101 = load_voxel(data, r01);
+        v011 = v111 = load_voxel(data, r11);
+    }
     float c00 = lerp_exact(v000, v100, w[0]);
     float c10 = lerp_exact(v010, v110, w[0]);
     float c01 = lerp_exact(v001, v101, w[0]);

@@ -104,6 +104,10 @@ struct CompParams {
 size_t composite_lds_bytes(int k, int seq_cap);
 void launch_composite(const CompParams& P, hipStream_t s);
 
+// Persistent batched compositing: tiles[i] = {job | pixels << 16, first pixel}.
+void launch_batch(const CompParams* jobs, const uint2* tiles, uint32_t n_tiles, uint32_t* head,
+                  unsigned long long* t_se, int n_jobs, size_t lds, int grid, hipStream_t s);
+
 // ---------------------------------------------------------------- MLP (learned threshold)
 
 int mlp_params();

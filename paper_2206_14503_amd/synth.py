@@ -78,8 +78,15 @@ def _add_gaussians(vol, n: int, centres, sigmas, amps, xp, window: float = 5.0):
             idx = xp.arange(lo[ax], hi[ax], dtype=xp.float64) if xp is np else \
                 xp.arange(lo[ax], hi[ax], dtype=xp.float64, device=vol.device)
             g.append(xp.exp(-((idx - c) ** 2) / (2.0 * sg * sg)))
-        block = amp * g[2][:, None, None] * g[1][None, :, None] * g[0][None, None, :]
-        vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] += block.to(vol.dtype) if xp is not np else block
+        plane = amp * g[1][:, None] * g[0][None, :]
+        if xp is not np:
+            plane = plane.to(vol.dtype)
+            gz = g[2].to(vol.dtype)
+        else:
+            gz = g[2]
+        for z0 in range(lo[2], hi[2], 32):          # bounded temporaries
+            z1 = min(z0 + 32, hi[2])
+            vol[z0:z1, lo[1]:hi[1], lo[0]:hi[0]] += gz[z0 - lo[2]:z1 - lo[2], None, None] * plane[None]
 
 
 def _interp_matrix(n: int, cells: int) -> np.ndarray:
@@ -343,3 +350,31 @@ def camera_for(w: Workload) -> Camera:
     if w.mode == "fixed" and w.width == w.height and w.n <= 64:
         return ortho_camera(w.width, w.height, "+z")
     return orbit_camera(10_000 + w.seed, w.width, w.height)
+
+
+# --------------------------------------------------------------------------
+# Batched compositing workload
+# --------------------------------------------------------------------------
+
+BATCH_RESOLUTIONS = ((256, 256), (512, 512), (1280, 720), (1920, 1080))
+BATCH_N = (8, 16, 20, 32)
+
+
+def batch_jobs(seed: int = 5000, n_jobs: int = 64):
+    """Seeded job list of the batched workload: (width, height, k, N) per job,
+    resolution from BATCH_RESOLUTIONS, k uniform in 2..16, N from BATCH_N."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_jobs):
+        w, h = BATCH_RESOLUTIONS[int(rng.integers(0, len(BATCH_RESOLUTIONS)))]
+        k = int(rng.integers(2, 17))
+        n = int(BATCH_N[int(rng.integers(0, len(BATCH_N)))])
+        out.append((w, h, k, n))
+    return out
+
+
+def batch_pool_workload(seed: int = 5000) -> Workload:
+    """Source of the pooled sub-VDIs of the batched workload: a 256^3 fp32
+    volume of 200 Gaussians (+ noise) in 16 bricks (4x2x2)."""
+    return Workload("batch-pool-256c-16brick", 256, 200, 0.1, "f32", (4, 2, 2), scaled_sigma(256), 0, 0,
+                    "bisect", 0.0, 0, 10, seed)

@@ -383,3 +383,104 @@ def debug_mfma(A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
     D = torch.empty((16, 16), dtype=torch.float32, device=A.device)
     _check(lib().vdi_debug_mfma(context(), _ptr(A.contiguous()), _ptr(B.contiguous()), _ptr(D), _stream()))
     return D
+
+
+# ---------------------------------------------------------------- batched compositing
+
+class vdi_job_t(ctypes.Structure):
+    _fields_ = [("in_", ctypes.POINTER(vdi_t)), ("k", ctypes.c_int32), ("out", vdi_t), ("tau", vdi_tau_t)]
+
+
+def _batch_lib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        P, I = ctypes.c_void_p, ctypes.c_int
+        L.vdi_batch_create.argtypes = [P, ctypes.POINTER(vdi_job_t), I, ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]
+        L.vdi_batch_run.argtypes = [P, P, P]
+        L.vdi_batch_capture.argtypes = [P, P, P]
+        L.vdi_batch_replay.argtypes = [P, P]
+        L.vdi_batch_info.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+        L.vdi_batch_destroy.argtypes = [P]
+        L.vdi_autotune.argtypes = [P, ctypes.POINTER(vdi_job_t), I, ctypes.c_char_p, P]
+        for name in ("vdi_batch_create", "vdi_batch_run", "vdi_batch_capture", "vdi_batch_replay", "vdi_batch_info",
+                     "vdi_batch_destroy", "vdi_autotune"):
+            getattr(L, name).restype = ctypes.c_int
+        L._batch_ready = True
+    return L
+
+
+class Job:
+    """One composite of a batch: k input VDIs -> one regular output VDI."""
+
+    def __init__(self, inputs: Sequence[VDI], out: VDI, mode: int = BISECT, tau: float = 0.0, iters: int = 10,
+                 gamma_max: float = 2.0):
+        self.inputs = list(inputs)
+        self.out = out
+        self.tau = tau_c(mode, tau, iters, gamma_max)
+        self._arr = (vdi_t * len(self.inputs))(*[v.c() for v in self.inputs])
+
+    def c(self) -> vdi_job_t:
+        return vdi_job_t(ctypes.cast(self._arr, ctypes.POINTER(vdi_t)), len(self.inputs), self.out.c(), self.tau)
+
+
+def _jobs_c(jobs: Sequence[Job]):
+    return (vdi_job_t * len(jobs))(*[j.c() for j in jobs])
+
+
+class Batch:
+    """vdi_batch_*: a persistent launch over many composites."""
+
+    def __init__(self, jobs: Sequence[Job], autotune_cache: Optional[str] = None):
+        self.jobs = list(jobs)
+        self._jc = _jobs_c(self.jobs)
+        h = ctypes.c_void_p()
+        path = autotune_cache.encode() if autotune_cache else None
+        _check(_batch_lib().vdi_batch_create(context(), self._jc, len(self.jobs), path, ctypes.byref(h)))
+        self.h = h
+        self.t_se = torch.zeros((2 * len(self.jobs),), dtype=torch.int64, device="cuda")
+        self._graph_stream = None
+
+    def info(self):
+        nt, gr, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        hz = ctypes.c_double()
+        _check(_batch_lib().vdi_batch_info(self.h, ctypes.byref(nt), ctypes.byref(gr), ctypes.byref(lds),
+                                           ctypes.byref(hz)))
+        return {"tiles": nt.value, "grid": gr.value, "lds_bytes": lds.value, "clock_hz": hz.value}
+
+    def run(self, timestamps: bool = True):
+        _check(_batch_lib().vdi_batch_run(self.h, _ptr(self.t_se) if timestamps else None, _stream()))
+
+    def capture(self, stream: torch.cuda.Stream, timestamps: bool = True):
+        """Capture run() into a hipGraph on `stream` (a non-default stream)."""
+        self._graph_stream = stream
+        _check(_batch_lib().vdi_batch_capture(self.h, _ptr(self.t_se) if timestamps else None,
+                                              ctypes.c_void_p(stream.cuda_stream)))
+
+    def replay(self, stream: Optional[torch.cuda.Stream] = None):
+        s = stream or self._graph_stream
+        _check(_batch_lib().vdi_batch_replay(self.h, ctypes.c_void_p(s.cuda_stream)))
+
+    def latencies_s(self):
+        """Per-job (last tile end - first tile start) in seconds, and the batch span."""
+        hz = self.info()["clock_hz"]
+        t = self.t_se.view(-1, 2).cpu().numpy().astype("uint64")
+        lat = (t[:, 1] - t[:, 0]).astype("float64") / hz
+        span = float(t[:, 1].max() - t[:, 0].min()) / hz
+        return lat, span
+
+    def close(self):
+        if self.h:
+            _batch_lib().vdi_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(jobs: Sequence[Job], cache_path: str):
+    jc = _jobs_c(jobs)
+    _check(_batch_lib().vdi_autotune(context(), jc, len(jobs), cache_path.encode(), _stream()))

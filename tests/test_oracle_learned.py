@@ -49,7 +49,7 @@ def test_backward_matches_central_differences(L):
     y, acts = L.forward(x, p, round_hidden=False, round_weights=False)
     g = L.backward(acts, L.mse_grad(y, t))
     h = 1e-6
-    for k, idxs in (("W1", [(0, 0), (13, 77), (63, 127)]), ("b1", [(5,), (100,)]), ("W2", [(0, 1), (127, 64)]),
+    for k, idxs in (("W1", [(0, 0), (77, 13), (127, 63)]), ("b1", [(5,), (100,)]), ("W2", [(0, 1), (127, 64)]),
                     ("b2", [(9,)]), ("w3", [(0,), (127,)]), ("b3", [(0,)])):
         for idx in idxs:
             pp, pm = {a: b.copy() for a, b in p.items()}, {a: b.copy() for a, b in p.items()}
