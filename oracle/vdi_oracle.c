@@ -15,9 +15,10 @@
  * decision that the GPU must take identically (which sample a brick owns,
  * how many samples a ray has, the voxel and transfer-function cells a sample
  * falls in, whether a sample is transparent).  Those are evaluated in fp32
- * with a fixed operation order and no fused multiply-add, exactly as the
- * kernels do: the ray (origin, direction, entry/exit), the sample position,
- * the trilinear blend and the transfer-function coordinate.  From the
+ * with a fixed operation order, exactly as the kernels do: the ray (origin,
+ * direction, entry/exit; separate multiplies and adds), the sample position,
+ * the trilinear blend (fused multiply-adds, C fmaf) and the transfer-function
+ * coordinate.  From the
  * transfer-function lookup on, the arithmetic is fp64.
  *
  * Readings of the paper where it is silent or garbled (all shared with the
@@ -146,17 +147,14 @@ static orc_ray make_ray(const orc_camera *c, int i, int j)
     return r;
 }
 
-/* Midpoint of sample k (fp32, fixed order); returns 0 once past the exit. */
+/* Midpoint of sample k (fp32, fixed order, fused multiply-adds); returns 0
+ * once past the exit. */
 static int sample_point(const orc_ray *r, int k, float step, float p[3])
 {
     float kk = (float)k + 0.5f;
-    float m = kk * step;
-    float t = r->tn + m;
+    float t = fmaf(kk, step, r->tn);
     if (!(t < r->tf)) return 0;
-    for (int a = 0; a < 3; ++a) {
-        float q = t * r->d[a];
-        p[a] = r->o[a] + q;
-    }
+    for (int a = 0; a < 3; ++a) p[a] = fmaf(t, r->d[a], r->o[a]);
     return 1;
 }
 
@@ -171,11 +169,11 @@ static void voxel_of(const orc_volume *vol, const float p[3], int v[3])
     }
 }
 
+/* a + w (b - a) with one fused multiply-add */
 static float lerpf32(float a, float b, float w)
 {
     float d = b - a;
-    float e = w * d;
-    return a + e;
+    return fmaf(w, d, a);
 }
 
 /* Trilinear reconstruction at p on the global voxel grid (fp32, fixed order). */
@@ -184,8 +182,7 @@ static float trilinear(const orc_volume *vol, const float p[3])
     int i0[3], i1[3];
     float w[3];
     for (int a = 0; a < 3; ++a) {
-        float g = p[a] * (float)vol->n[a];
-        float u = g - 0.5f;
+        float u = fmaf(p[a], (float)vol->n[a], -0.5f);
         float f = floorf(u);
         w[a] = u - f;
         int ii = (int)f;

@@ -295,6 +295,8 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
             if (b.data_lo[a] > need_lo || b.data_lo[a] + b.data_dim[a] < need_hi || b.data_dim[a] < 1)
                 return fail(VDI_E_INVALID, "brick %d: data box axis %d does not cover the owned box plus one voxel", r, a);
         }
+        if ((int64_t)b.data_dim[0] * b.data_dim[1] * b.data_dim[2] >= ((int64_t)1 << 31))
+            return fail(VDI_E_UNSUPPORTED, "brick %d: more than 2^31 data voxels", r);
         st = check_vdi(&out[r], "out", true);
         if (st != VDI_OK) return st;
         if (out[r].width != cam->width || out[r].height != cam->height)
@@ -468,6 +470,8 @@ vdi_status vdi_tau_features(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, cons
             if (b.data_lo[a] > need_lo || b.data_lo[a] + b.data_dim[a] < need_hi)
                 return fail(VDI_E_INVALID, "brick %d: data box", r);
         }
+        if ((int64_t)b.data_dim[0] * b.data_dim[1] * b.data_dim[2] >= ((int64_t)1 << 31))
+            return fail(VDI_E_UNSUPPORTED, "brick %d: more than 2^31 data voxels", r);
     }
     GenParams P;
     memset(&P, 0, sizeof P);

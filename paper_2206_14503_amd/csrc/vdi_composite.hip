@@ -26,6 +26,7 @@ struct CSeg {
     float c0, c1, c2;  // premultiplied colour
     float A;           // accumulated opacity
     float T;           // transmittance
+    float lT;          // log2 of the transmittance
     float f, b, bt;    // front, back (incl. trailing gap/transparent), back of last non-transparent
     int open;
     int count;
@@ -38,6 +39,7 @@ struct CElem {
     float e0, e1, e2;  // per-step premultiplied colour (Eq. 1 operand)
     float at;          // total opacity over its length (Eq. 2)
     float Te;          // 1 - at
+    float lg;          // log2(1 - at)
     bool transparent;
 };
 
@@ -54,6 +56,7 @@ __device__ inline CElem prep(float4 c, float2 fb, float inv_ref)
     e.e2 = c.z * c.w;
     e.transparent = (c.w == 0.0f);
     float lg = (fb.y - fb.x) * inv_ref * log2_1m(c.w);   // log2 of (1 - a)^l
+    e.lg = lg;
     e.Te = hw_exp2(lg);
     e.at = e.transparent ? 0.0f : one_minus_exp2(lg);
     return e;
@@ -72,6 +75,7 @@ __device__ inline void seg_reset(CSeg& S)
     S.count = 0;
     S.c0 = S.c1 = S.c2 = S.A = 0.0f;
     S.T = 1.0f;
+    S.lT = 0.0f;
     S.f = S.b = S.bt = 0.0f;
 }
 
@@ -81,7 +85,7 @@ __device__ inline void c_close(CSeg& S, const COut& o, float inv_ref)
     if (WRITE && S.count < o.limit) {
         float invA = 1.0f / S.A;
         float len = (S.bt - S.f) * inv_ref;
-        float a = one_minus_exp2(hw_log2(S.T) / len);
+        float a = one_minus_exp2(S.lT / len);
         size_t slot = (size_t)S.count * o.npix + o.pix;
         o.color[slot] = make_float4(S.c0 * invA, S.c1 * invA, S.c2 * invA, a);
         o.depth[slot] = make_float2(S.f, S.bt);
@@ -90,15 +94,15 @@ __device__ inline void c_close(CSeg& S, const COut& o, float inv_ref)
     S.open = 0;
 }
 
-// Squared Eq. 1 distance between the open supersegment's per-step
-// premultiplied colour and (e0, e1, e2).
-__device__ inline float c_dist2(const CSeg& S, float inv_ref, float e0, float e1, float e2)
+// Eq. 1 test: gamma < |C a_S / A - e| with a_S = 1 - 2^(log2(T) / L) the
+// open supersegment's per-step opacity, evaluated as
+// gamma^2 A^2 < |C a_S - e A|^2 (A > 0).
+__device__ inline bool c_exceeds(const CSeg& S, float inv_ref, float g2, float e0, float e1, float e2)
 {
     float L = (S.b - S.f) * inv_ref;
-    float aS = 1.0f - hw_exp2(hw_log2(S.T) * hw_rcp(L));
-    float sc = aS * hw_rcp(S.A);
-    float d0 = S.c0 * sc - e0, d1 = S.c1 * sc - e1, d2 = S.c2 * sc - e2;
-    return d0 * d0 + d1 * d1 + d2 * d2;
+    float aS = 1.0f - hw_exp2(S.lT * hw_rcp(L));
+    float d0 = S.c0 * aS - e0 * S.A, d1 = S.c1 * aS - e1 * S.A, d2 = S.c2 * aS - e2 * S.A;
+    return g2 * (S.A * S.A) < d0 * d0 + d1 * d1 + d2 * d2;
 }
 
 template <bool WRITE>
@@ -107,12 +111,12 @@ __device__ inline void c_step(CSeg& S, const COut& o, float inv_ref, float g2, i
     // empty space before the element is a transparent sample (Alg. S1)
     if (S.open && e.f > S.b) {
         bool may_close = cap <= 0 || S.count < cap - 1;
-        if (may_close && g2 < c_dist2(S, inv_ref, 0.0f, 0.0f, 0.0f)) c_close<WRITE>(S, o, inv_ref);
+        if (may_close && c_exceeds(S, inv_ref, g2, 0.0f, 0.0f, 0.0f)) c_close<WRITE>(S, o, inv_ref);
         else S.b = e.f;
     }
     if (S.open) {
         bool may_close = cap <= 0 || S.count < cap - 1;
-        if (may_close && g2 < c_dist2(S, inv_ref, e.e0, e.e1, e.e2)) {
+        if (may_close && c_exceeds(S, inv_ref, g2, e.e0, e.e1, e.e2)) {
             c_close<WRITE>(S, o, inv_ref);
         } else {
             float w = S.T * e.at;
@@ -121,6 +125,7 @@ __device__ inline void c_step(CSeg& S, const COut& o, float inv_ref, float g2, i
             S.c2 = fmaf(w, e.bl, S.c2);
             S.A += w;
             S.T *= e.Te;
+            S.lT += e.lg;
             S.b = e.b;
             if (!e.transparent) S.bt = e.b;
         }
@@ -134,6 +139,7 @@ __device__ inline void c_step(CSeg& S, const COut& o, float inv_ref, float g2, i
         S.c2 = e.bl * e.at;
         S.A = e.at;
         S.T = e.Te;
+        S.lT = e.lg;
     }
 }
 
@@ -144,14 +150,43 @@ struct InLds {
     uint32_t pad;
 };
 
+// Per-lane LDS arrays, lane-minor ([row][64]) so consecutive lanes hit
+// consecutive banks.  The merge sequence stores one input id per element
+// (4 bits when k <= 16, else 8 bits); the slot of each element is recovered
+// during a scan from per-input cursors.
 struct Lds {
     const InLds* in;   // [k], shared by the block
-    uint16_t* seq;     // [seq_cap][64]: input << 8 | slot
-    float* front;      // [k][64]
-    uint32_t* ebase;   // [k][64]: element index of slot 0
-    uint16_t* cur;     // [k][64]
-    uint16_t* cnt;     // [k][64]
+    uint8_t* seq;      // [seq bytes][64]
+    float* front;      // [k][64]  front depth of each input's current element
+    float* next;       // [k][64]  front depth of the element after it
+    uint32_t* ebase;   // [k][64]  element index of slot 0
+    uint8_t* cur;      // [k][64]  cursor (slot of the next element) per input
+    uint8_t* cnt;      // [k][64]  list length per input
+    bool nib;          // 4-bit ids
 };
+
+__device__ inline int seq_bytes(int k, int seq_cap) { return k <= 16 ? (seq_cap + 1) / 2 : seq_cap; }
+
+__device__ inline Lds lds_layout(unsigned char* lds_raw, int k, int seq_cap)
+{
+    Lds L;
+    L.in = (const InLds*)lds_raw;
+    unsigned char* q = lds_raw + sizeof(InLds) * kMaxInputs;
+    const int sb = (seq_bytes(k, seq_cap) + 3) & ~3;
+    L.seq = q;
+    q += (size_t)sb * kWave;
+    L.front = (float*)q;
+    q += (size_t)4 * k * kWave;
+    L.next = (float*)q;
+    q += (size_t)4 * k * kWave;
+    L.ebase = (uint32_t*)q;
+    q += (size_t)4 * k * kWave;
+    L.cur = q;
+    q += (size_t)k * kWave;
+    L.cnt = q;
+    L.nib = k <= 16;
+    return L;
+}
 
 struct Src {
     const float4* c;
@@ -159,18 +194,31 @@ struct Src {
     uint32_t e;
 };
 
-__device__ inline Src locate(const Lds& L, int t, uint32_t rs)
-{
-    int r = (int)(rs >> 8), s = (int)(rs & 255u);
-    const InLds in = L.in[r];
-    return Src{in.color, in.depth, L.ebase[r * kWave + t] + (uint32_t)s * in.stride};
-}
+// Sequential reader of a lane's merge sequence (one pass).
+struct SeqReader {
+    const Lds* L;
+    int t;
+    int k;
+    __device__ void reset() const
+    {
+        for (int r = 0; r < k; ++r) L->cur[r * kWave + t] = 0;
+    }
+    __device__ Src at(int i) const
+    {
+        uint32_t b = L->seq[(L->nib ? (i >> 1) : i) * kWave + t];
+        int r = L->nib ? (int)((i & 1) ? (b >> 4) : (b & 15u)) : (int)b;
+        uint32_t s = L->cur[r * kWave + t];
+        L->cur[r * kWave + t] = (uint8_t)(s + 1);
+        const InLds in = L->in[r];
+        return Src{in.color, in.depth, L->ebase[r * kWave + t] + s * in.stride};
+    }
+};
 
 // One scan of the merged list carrying NC segmenter states (thresholds g[]).
 // Counting scans (WRITE false) freeze a state once its count exceeds
 // `limit` and stop when every state is frozen.
 template <int NC, bool WRITE>
-__device__ void c_scan(const Lds& L, int t, int total, float inv_ref, const float* gam, int cap, int limit,
+__device__ void c_scan(const SeqReader& rd, int total, float inv_ref, const float* gam, int cap, int limit,
                        const COut& o, int* counts)
 {
     CSeg S[NC];
@@ -181,14 +229,15 @@ __device__ void c_scan(const Lds& L, int t, int total, float inv_ref, const floa
         g2[c] = gam[c] * gam[c];
     }
     if (total > 0) {
-        Src src = locate(L, t, L.seq[t]);
+        rd.reset();
+        Src src = rd.at(0);
         float4 cn = src.c[src.e];
         float2 fn = src.d[src.e];
         for (int i = 0; i < total; ++i) {
             float4 cc = cn;
             float2 fc = fn;
             if (i + 1 < total) {
-                Src nx = locate(L, t, L.seq[(i + 1) * kWave + t]);
+                Src nx = rd.at(i + 1);
                 cn = nx.c[nx.e];
                 fn = nx.d[nx.e];
             }
@@ -228,13 +277,8 @@ __device__ inline void setup_inputs(const CompParams& P, unsigned char* lds_raw,
 // Merge and re-segment the lists of pixel p (lane t of the wave).
 __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int t, uint32_t p)
 {
-    Lds L;
-    L.in = (const InLds*)lds_raw;
-    L.seq = (uint16_t*)(lds_raw + sizeof(InLds) * kMaxInputs);
-    L.front = (float*)(lds_raw + sizeof(InLds) * kMaxInputs + (size_t)2 * kWave * P.seq_cap);
-    L.ebase = (uint32_t*)(L.front + kWave * P.k);
-    L.cur = (uint16_t*)(L.ebase + kWave * P.k);
-    L.cnt = L.cur + kWave * P.k;
+    const Lds L = lds_layout(lds_raw, P.k, P.seq_cap);
+    const SeqReader rd{&L, t, P.k};
 
     // ---- load counts, validate, set up the merge cursors
     int total = 0;
@@ -246,20 +290,26 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
         uint32_t eb = in.compact ? in.offset[p] : p;
         uint64_t last = in.compact ? (uint64_t)eb + (uint64_t)c : (uint64_t)c * P.npix;
         if (last > in.capacity) { bad = true; c = 0; }
+        const uint32_t stride = in.compact ? 1u : P.npix;
         L.ebase[r * kWave + t] = eb;
         L.cur[r * kWave + t] = 0;
-        L.cnt[r * kWave + t] = (uint16_t)c;
-        float f = __builtin_inff();
+        L.cnt[r * kWave + t] = (uint8_t)c;
+        float f0 = __builtin_inff(), f1 = __builtin_inff();
         if (c > 0) {
             float2 fb = in.depth[eb];
             if (!(fb.x < fb.y) || !isfinite(fb.x) || !isfinite(fb.y)) bad = true;
-            f = fb.x;
+            f0 = fb.x;
         }
-        L.front[r * kWave + t] = f;
+        if (c > 1) f1 = in.depth[eb + stride].x;
+        L.front[r * kWave + t] = f0;
+        L.next[r * kWave + t] = f1;
         total += c;
     }
 
-    // ---- k-way merge by (front depth, input index)
+    // ---- k-way merge by (front depth, input index).  Each input keeps its
+    // current and next front depth in LDS; the load for the one after is
+    // issued when an input advances and only needed when it advances again.
+    uint32_t pending = 0;
     for (int i = 0; i < total && !bad; ++i) {
         float best = __builtin_inff();
         int rb = -1;
@@ -268,19 +318,29 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
             if (f < best) { best = f; rb = r; }
         }
         if (rb < 0) { bad = true; break; }
-        int s = L.cur[rb * kWave + t];
-        L.seq[i * kWave + t] = (uint16_t)((rb << 8) | s);
-        ++s;
-        L.cur[rb * kWave + t] = (uint16_t)s;
-        float nf = __builtin_inff();
-        if (s < L.cnt[rb * kWave + t]) {
-            const InLds inr = L.in[rb];
-            float2 fb = inr.depth[L.ebase[rb * kWave + t] + (uint32_t)s * inr.stride];
-            if (!(fb.x < fb.y) || !(fb.x >= best) || !isfinite(fb.y)) bad = true;
-            nf = fb.x;
+        if (L.nib) {
+            if (i & 1) L.seq[(i >> 1) * kWave + t] = (uint8_t)(pending | ((uint32_t)rb << 4));
+            else pending = (uint32_t)rb;
+        } else {
+            L.seq[i * kWave + t] = (uint8_t)rb;
         }
+        const int s = L.cur[rb * kWave + t] + 1;       // slot now at the front of input rb
+        L.cur[rb * kWave + t] = (uint8_t)s;
+        const int c = L.cnt[rb * kWave + t];
+        const InLds inr = L.in[rb];
+        const uint32_t eb = L.ebase[rb * kWave + t];
+        float nf = L.next[rb * kWave + t];
+        if (s < c) {
+            // validate the element now at the front: sorted, f < b
+            float2 fb = inr.depth[eb + (uint32_t)s * inr.stride];
+            if (!(fb.x < fb.y) || !(fb.x >= best) || !isfinite(fb.y)) bad = true;
+        }
+        float nn = __builtin_inff();
+        if (s + 1 < c) nn = inr.depth[eb + (uint32_t)(s + 1) * inr.stride].x;
         L.front[rb * kWave + t] = nf;
+        L.next[rb * kWave + t] = nn;
     }
+    if (L.nib && (total & 1) && !bad) L.seq[(total >> 1) * kWave + t] = (uint8_t)pending;
     if (bad) {
         atomicOr(P.status, 2);
         total = 0;
@@ -291,8 +351,9 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
     float gm = 0.0f;
     if (total <= P.out_n) {
         // pass-through: the merged list already fits
+        rd.reset();
         for (int i = 0; i < total; ++i) {
-            Src src = locate(L, t, L.seq[i * kWave + t]);
+            Src src = rd.at(i);
             size_t slot = (size_t)i * P.npix + p;
             P.out_color[slot] = src.c[src.e];
             P.out_depth[slot] = src.d[src.e];
@@ -301,7 +362,7 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
     } else if (P.mode == VDI_TAU_FIXED) {
         gm = P.tau;
         int c1[1];
-        c_scan<1, true>(L, t, total, P.inv_ref, &gm, P.out_n, 1 << 30, o, c1);
+        c_scan<1, true>(rd, total, P.inv_ref, &gm, P.out_n, 1 << 30, o, c1);
         count = c1[0];
     } else {
         // bisection, two levels per scan
@@ -311,7 +372,7 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
             float m = 0.5f * (lo + hi);
             float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
             int c3[3];
-            c_scan<3, false>(L, t, total, P.inv_ref, g3, 0, P.out_n, o, c3);
+            c_scan<3, false>(rd, total, P.inv_ref, g3, 0, P.out_n, o, c3);
             if (c3[0] <= P.out_n) {
                 hi = m;
                 if (c3[1] <= P.out_n) hi = g3[1];
@@ -326,13 +387,13 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
         if (level < P.iters) {
             float m = 0.5f * (lo + hi);
             int c1[1];
-            c_scan<1, false>(L, t, total, P.inv_ref, &m, 0, P.out_n, o, c1);
+            c_scan<1, false>(rd, total, P.inv_ref, &m, 0, P.out_n, o, c1);
             if (c1[0] <= P.out_n) hi = m;
             else lo = m;
         }
         gm = hi;
         int c1[1];
-        c_scan<1, true>(L, t, total, P.inv_ref, &gm, 0, 1 << 30, o, c1);
+        c_scan<1, true>(rd, total, P.inv_ref, &gm, 0, 1 << 30, o, c1);
         count = c1[0];
     }
     if (count > P.out_n) count = P.out_n;
@@ -416,7 +477,8 @@ void launch_batch(const CompParams* jobs, const uint2* tiles, uint32_t n_tiles, 
 
 size_t composite_lds_bytes(int k, int seq_cap)
 {
-    return sizeof(InLds) * kMaxInputs + (size_t)kWave * (2 * (size_t)seq_cap + 12 * (size_t)k);
+    const size_t sb = ((size_t)(k <= 16 ? (seq_cap + 1) / 2 : seq_cap) + 3) & ~(size_t)3;
+    return sizeof(InLds) * kMaxInputs + (size_t)kWave * (sb + 14 * (size_t)k);
 }
 
 void launch_composite(const CompParams& P, hipStream_t s)

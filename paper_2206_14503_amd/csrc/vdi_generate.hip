@@ -15,7 +15,8 @@ namespace vdi {
 struct GenSeg {
     float c0, c1, c2;   // premultiplied colour
     float A;            // accumulated opacity (added up, exact for thin segments)
-    float T;            // transmittance (multiplied, exact for thick segments)
+    float T;            // transmittance (multiplied)
+    float lT;           // log2 of the transmittance (added up)
     int kf, kb, kbt;    // first sample, one past the last, one past the last non-transparent
     int open;
 };
@@ -35,7 +36,7 @@ __device__ inline void gen_close(GenSeg& S, int& count, const GenOut& o, const R
     if (WRITE && (uint32_t)count < o.limit) {
         float invA = 1.0f / S.A;
         float len = (float)(S.kbt - S.kf) * l_step;
-        float a = one_minus_exp2(hw_log2(S.T) / len);
+        float a = one_minus_exp2(S.lT / len);
         size_t slot = (size_t)o.base + (size_t)count * o.stride;
         o.color[slot] = make_float4(S.c0 * invA, S.c1 * invA, S.c2 * invA, a);
         float f = r.tn + (float)S.kf * step;
@@ -62,50 +63,75 @@ __device__ inline void gen_seg_init(GenSeg& S)
     S.c0 = S.c1 = S.c2 = 0.0f;
     S.A = 0.0f;
     S.T = 1.0f;
+    S.lT = 0.0f;
     S.kf = S.kb = S.kbt = 0;
 }
 
+// A classified sample prepared once and shared by every segmenter state.
+struct GenSample {
+    float4 c;        // colour and per-step opacity a
+    float at;        // opacity over the sample's length (Eq. 2 / length-adjusted)
+    float Te;        // 1 - at
+    float lg;        // log2(1 - at)
+    float e0, e1, e2;  // per-step premultiplied colour (Eq. 1 operand)
+    bool transparent;
+};
+
+__device__ inline GenSample gen_prep(float4 c, float l_step, bool unit)
+{
+    GenSample q;
+    q.c = c;
+    q.transparent = (c.w == 0.0f);
+    float lg1 = log2_1m(c.w);
+    q.lg = unit ? lg1 : l_step * lg1;
+    q.at = unit ? c.w : one_minus_exp2(q.lg);
+    q.Te = unit ? 1.0f - c.w : hw_exp2(q.lg);
+    q.e0 = c.x * c.w;
+    q.e1 = c.y * c.w;
+    q.e2 = c.z * c.w;
+    return q;
+}
+
 // One sample through the segmenter (Eq. 1 test, then merge or close/open).
+// The test gamma < |C a_S / A - e| is evaluated as gamma^2 A^2 < |C a_S - e A|^2
+// (A > 0), with a_S = 1 - 2^(log2(T) / L) the open supersegment's per-step
+// opacity.
 template <bool WRITE>
 __device__ inline void gen_step(GenSeg& S, int& count, const GenOut& o, const Ray& r, float step, float l_step,
-                                bool unit, float g2, int cap, int k, float4 c)
+                                float g2, int cap, int k, const GenSample& q)
 {
-    const bool transparent = (c.w == 0.0f);
-    // Eq. 2 / length-adjusted opacity of the sample
-    const float lg = unit ? 0.0f : l_step * log2_1m(c.w);
-    float at = unit ? c.w : one_minus_exp2(lg);
     if (S.open) {
-        // per-step opacity of the open supersegment: 1 - T^(1/L)
         float L = (float)(S.kb - S.kf) * l_step;
-        float aS = 1.0f - hw_exp2(hw_log2(S.T) * hw_rcp(L));
-        float sc = aS * hw_rcp(S.A);
-        float d0 = S.c0 * sc - c.x * c.w;
-        float d1 = S.c1 * sc - c.y * c.w;
-        float d2 = S.c2 * sc - c.z * c.w;
+        float aS = 1.0f - hw_exp2(S.lT * hw_rcp(L));
+        float d0 = S.c0 * aS - q.e0 * S.A;
+        float d1 = S.c1 * aS - q.e1 * S.A;
+        float d2 = S.c2 * aS - q.e2 * S.A;
         float dd = d0 * d0 + d1 * d1 + d2 * d2;
         bool may_close = cap <= 0 || count < cap - 1;
-        if (may_close && g2 < dd) {
+        if (may_close && g2 * (S.A * S.A) < dd) {
             gen_close<WRITE>(S, count, o, r, step, l_step);
         } else {
-            float w = S.T * at;
-            S.c0 = fmaf(w, c.x, S.c0);
-            S.c1 = fmaf(w, c.y, S.c1);
-            S.c2 = fmaf(w, c.z, S.c2);
+            float w = S.T * q.at;
+            S.c0 = fmaf(w, q.c.x, S.c0);
+            S.c1 = fmaf(w, q.c.y, S.c1);
+            S.c2 = fmaf(w, q.c.z, S.c2);
             S.A += w;
-            S.T *= unit ? (1.0f - c.w) : hw_exp2(lg);
+            S.T *= q.Te;
+            S.lT += q.lg;
             S.kb = k + 1;
-            if (!transparent) S.kbt = k + 1;
+            if (!q.transparent) S.kbt = k + 1;
         }
     }
-    if (!S.open && !transparent) {
+    if (!S.open && !q.transparent) {
         S.open = 1;
         S.kf = k;
         S.kb = S.kbt = k + 1;
-        S.c0 = c.x * at;
-        S.c1 = c.y * at;
-        S.c2 = c.z * at;
-        S.A = at;
-        S.T = unit ? (1.0f - c.w) : hw_exp2(lg);
+        S.c0 = q.c.x * q.at;
+        S.c1 = q.c.y * q.at;
+        S.c2 = q.c.z * q.at;
+        S.A = q.at;
+        S.T = q.Te;
+        S.lT = q.lg;
     }
 }
 
@@ -124,9 +150,9 @@ __device__ int gen_pass(const VT* data, const BrickGeo& g, const Ray& r, float s
     int count = 0, n_opaque = 0;
     const bool unit = (l_step == 1.0f);
     for (int k = k0; k < k1; ++k) {
-        float4 c = gen_sample<VT>(data, g, r, step, k, tf, entries);
-        n_opaque += (c.w == 0.0f) ? 0 : 1;
-        gen_step<WRITE>(S, count, o, r, step, l_step, unit, g2, cap, k, c);
+        const GenSample q = gen_prep(gen_sample<VT>(data, g, r, step, k, tf, entries), l_step, unit);
+        n_opaque += q.transparent ? 0 : 1;
+        gen_step<WRITE>(S, count, o, r, step, l_step, g2, cap, k, q);
         if (EARLY && count > limit) break;
     }
     if (S.open) gen_close<WRITE>(S, count, o, r, step, l_step);
@@ -156,13 +182,13 @@ __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float 
     const bool unit = (l_step == 1.0f);
     int n_opaque = 0;
     for (int k = k0; k < k1; ++k) {
-        float4 c = gen_sample<VT>(data, g, r, step, k, tf, entries);
-        n_opaque += (c.w == 0.0f) ? 0 : 1;
+        const GenSample q = gen_prep(gen_sample<VT>(data, g, r, step, k, tf, entries), l_step, unit);
+        n_opaque += q.transparent ? 0 : 1;
         bool live = false;
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
             if (cnt[j] <= limit) {
-                gen_step<false>(S[j], cnt[j], none, r, step, l_step, unit, g2[j], 0, k, c);
+                gen_step<false>(S[j], cnt[j], none, r, step, l_step, g2[j], 0, k, q);
                 live |= cnt[j] <= limit;
             }
         }
@@ -401,8 +427,8 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
             ++m;
         }
         if (count <= P.max_n) {
-            float4 c = tf_lookup(tf_s, P.tf_entries, sv);
-            gen_step<false>(S, count, none, r, P.step, P.l_step, unit, g2, 0, k, c);
+            const GenSample q = gen_prep(tf_lookup(tf_s, P.tf_entries, sv), P.l_step, unit);
+            gen_step<false>(S, count, none, r, P.step, P.l_step, g2, 0, k, q);
         }
     }
     if (S.open && count <= P.max_n) gen_close<false>(S, count, none, r, P.step, P.l_step);
@@ -414,6 +440,22 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
         float f1 = (float)hs[j + 1][threadIdx.x] / Lb.s_ref;
         hrow[j / 2] = (uint32_t)bf16_bits(f0) | ((uint32_t)bf16_bits(f1) << 16);
     }
+}
+
+// Add `inc` (0 or 1 per lane) to *ctr with one atomic per wavefront; returns
+// this lane's position among the wave's incrementing lanes plus the old value
+// (meaningful for lanes with inc == 1).
+__device__ inline int wave_append(int* ctr, bool inc)
+{
+    const unsigned long long m = __ballot(inc);
+    const int n = __popcll(m);
+    const int lane = threadIdx.x & 63;
+    const int leader = m ? (__ffsll((long long)m) - 1) : 0;
+    int base = 0;
+    if (n && lane == leader) base = atomicAdd(ctr, n);
+    base = __shfl(base, leader, 64);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    return base + rank;
 }
 
 // Generation at the regressed threshold, with the acceptance test; rays
@@ -453,13 +495,14 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
     GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
     float gm = gmin;
     int c = 0;
+    int kind = 0;   // 0 kept, 1 all-feasible shortcut, 2 fallback, 3 empty
     if (k1 <= k0 || m == 0) {
-        atomicAdd(&Lb.stats[3], 1);
+        kind = 3;
     } else if (m <= P.max_n) {
         // every threshold is feasible: the bisection would return its lower end
         c = gen_pass<VT, true, false>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gmin, 0, 1 << 30,
                                       o, nullptr);
-        atomicAdd(&Lb.stats[1], 1);
+        kind = 1;
     } else {
         // the regressed threshold and four neighbours (x 2^{-1/2, -1/4, 1/4, 1/2})
         // share one sampling scan; the in-band candidate with the largest
@@ -479,16 +522,20 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
         for (int j = 0; j < 5; ++j)
             if (c5[j] <= P.max_n && c5[j] >= lo && (best < 0 || c5[j] > c5[best])) best = j;
         if (best < 0) {
-            int pos = atomicAdd(&Lb.fb_count[brick], 1);
-            Lb.fb_list[(size_t)brick * npix + pos] = (int)pix;
-            atomicAdd(&Lb.stats[2], 1);
-            return;
+            kind = 2;
+        } else {
+            gm = g5[best];
+            c = gen_pass<VT, true, false>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, 0, 1 << 30,
+                                          o, nullptr);
         }
-        gm = g5[best];
-        c = gen_pass<VT, true, false>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, 0, 1 << 30, o,
-                                      nullptr);
-        atomicAdd(&Lb.stats[0], 1);
     }
+    // every active lane of the wave reaches this point (lanes of pixels
+    // outside the image returned at the top and take no part in the ballots)
+    const int pos = wave_append(&Lb.fb_count[brick], kind == 2);
+    if (kind == 2) Lb.fb_list[(size_t)brick * npix + pos] = (int)pix;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wave_append(&Lb.stats[q], kind == q);
+    if (kind == 2) return;
     for (int j = c; j < P.max_n; ++j) {
         size_t slot = (size_t)j * npix + pix;
         br.color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);

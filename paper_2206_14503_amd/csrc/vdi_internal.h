@@ -2,11 +2,12 @@
 //
 // Geometry, sample positions, trilinear reconstruction and the
 // transfer-function coordinate are evaluated in fp32 with a fixed operation
-// order and no contraction into fused multiply-adds: their results decide
-// integers (sample counts, brick ownership, voxel and table cells,
-// transparency), which must come out the same on every run and on any other
-// implementation that follows the same order.  Everything after the
-// transfer-function lookup is free fp32 arithmetic.
+// order (the ray setup with separate multiplies and adds, no contraction; the
+// sample position and the trilinear blend with explicit fused multiply-adds):
+// their results decide integers (sample counts, brick ownership, voxel and
+// table cells, transparency), which must come out the same on every run and
+// on any other implementation that follows the same order.  Everything after
+// the transfer-function lookup is free fp32 arithmetic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -115,20 +116,17 @@ __device__ inline Ray make_ray(const Cam& c, int x, int y)
     return r;
 }
 
-// Distance of the midpoint of sample k from the ray origin.
+// Distance of the midpoint of sample k from the ray origin (one fused
+// multiply-add, the same single rounding on every implementation).
 __device__ inline float sample_t(const Ray& r, int k, float step)
 {
-#pragma clang fp contract(off)
     float kk = (float)k + 0.5f;
-    float m = kk * step;
-    return r.tn + m;
+    return __builtin_fmaf(kk, step, r.tn);
 }
 
 __device__ inline float sample_coord(const Ray& r, float t, int a)
 {
-#pragma clang fp contract(off)
-    float q = t * r.d[a];
-    return r.o[a] + q;
+    return __builtin_fmaf(t, r.d[a], r.o[a]);
 }
 
 // Number of samples of the ray: midpoints strictly before the exit.
@@ -238,12 +236,11 @@ template <typename VT> __device__ inline float load_voxel(const VT* p, size_t i)
 template <> __device__ inline float load_voxel<float>(const float* p, size_t i) { return p[i]; }
 template <> __device__ inline float load_voxel<__half>(const __half* p, size_t i) { return __half2float(p[i]); }
 
+// a + w (b - a) with one fused multiply-add.
 __device__ inline float lerp_exact(float a, float b, float w)
 {
-#pragma clang fp contract(off)
     float d = b - a;
-    float e = w * d;
-    return a + e;
+    return __builtin_fmaf(w, d, a);
 }
 
 struct BrickGeo {
@@ -282,17 +279,17 @@ __device__ inline float trilinear(const VT* data, const BrickGeo& g, const float
     float w[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float gg = p[a] * (float)g.n[a];
-        float u = gg - 0.5f;
+        float u = __builtin_fmaf(p[a], (float)g.n[a], -0.5f);
         float f = floorf(u);
         w[a] = u - f;
         int ii = (int)f;
         i0[a] = clampi(clampi(ii, 0, g.n[a] - 1) - g.dlo[a], 0, g.ddim[a] - 1);
         i1[a] = clampi(clampi(ii + 1, 0, g.n[a] - 1) - g.dlo[a], 0, g.ddim[a] - 1);
     }
-    const size_t sy = (size_t)g.ddim[0], sz = (size_t)g.ddim[0] * g.ddim[1];
-    const size_t r00 = i0[1] * sy + i0[2] * sz, r10 = i1[1] * sy + i0[2] * sz;
-    const size_t r01 = i0[1] * sy + i1[2] * sz, r11 = i1[1] * sy + i1[2] * sz;
+    // 32-bit offsets: a brick's data holds fewer than 2^31 voxels (checked on the host)
+    const uint32_t sy = (uint32_t)g.ddim[0], sz = (uint32_t)g.ddim[0] * (uint32_t)g.ddim[1];
+    const uint32_t r00 = i0[1] * sy + i0[2] * sz, r10 = i1[1] * sy + i0[2] * sz;
+    const uint32_t r01 = i0[1] * sy + i1[2] * sz, r11 = i1[1] * sy + i1[2] * sz;
     float v000, v100, v010, v110, v001, v101, v011, v111;
     if (g.ddim[0] >= 2) {
         const int xb = i0[0] < g.ddim[0] - 2 ? i0[0] : g.ddim[0] - 2;
