@@ -242,16 +242,20 @@ def leg_learned(args, result):
     tf_d = torch.from_numpy(synth.transfer_function()).cuda()
     t0 = time.time()
     X, Y, st = learned.training_pairs(cfg, seeds=range(args.learn_seeds), tf_d=tf_d)
-    log(f"[bench] learned: {X.shape[0]} training pairs ({st['rays']} brick-rays) in {time.time() - t0:.1f}s")
+    log(f"[bench] learned: {X.shape[0]} training pairs (of {st['kept']} served among {st['rays']} brick-rays) "
+        f"in {time.time() - t0:.1f}s")
     mlp = learned.init_mlp(0)
     t1 = time.time()
     losses = learned.train(mlp, X, Y, epochs=args.learn_epochs, batch=4096, lr=2e-3, log=log)
     torch.cuda.synchronize()
     t_train = time.time() - t1
-    ev_ = learned.evaluate(mlp, cfg, seeds=range(100, 108), tf_d=tf_d, reps=3)
+    del X, Y
+    torch.cuda.empty_cache()
+    ev_ = learned.evaluate(mlp, cfg, seeds=range(100, 104), tf_d=tf_d, reps=3)
     log(f"[bench] learned vs plain: {ev_}")
-    result["learned"] = {"train_pairs": int(X.shape[0]), "train_seconds": t_train, "final_loss": losses[-1],
-                         "eval_rays": ev_["frames"] * cfg.res * cfg.res * 2, **ev_}
+    result["learned"] = {"train_pairs": st["pairs"], "train_seconds": t_train, "final_loss": losses[-1],
+                         "eval_rays": ev_["brick_rays"], "workload": f"{cfg.n}^3 x {cfg.grid} bricks, "
+                         f"{cfg.res}^2 ortho views, N={cfg.max_n}", **ev_}
 
 
 # ---------------------------------------------------------------- batched composites
@@ -373,7 +377,7 @@ def main():
     ap.add_argument("--layout", choices=["compact", "regular"], default="compact")
     ap.add_argument("--legs", default="fhd,large,learned,batched")
     ap.add_argument("--learn-seeds", type=int, default=32)
-    ap.add_argument("--learn-epochs", type=int, default=4)
+    ap.add_argument("--learn-epochs", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a kernel of known traffic for counter scaling)")

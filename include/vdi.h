@@ -14,7 +14,10 @@
  * Conventions for every entry point:
  *  - All data pointers are DEVICE pointers unless stated otherwise; the caller
  *    allocates and owns them.  The library owns only its context (scratch
- *    memory, kept between calls and grown when a larger problem arrives).
+ *    memory, kept between calls and grown when a larger problem arrives;
+ *    growing it synchronises the device).  The scratch is shared by all calls
+ *    on a context: calls on different streams of one context must not run
+ *    concurrently.
  *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
  *    Work is enqueued on it and the call returns without synchronising.
  *  - Shape and argument errors are detected on the host before any launch and
@@ -87,7 +90,8 @@ typedef struct {
  * [lo, hi) in global voxel indices (x, y, z), and its data with a ghost layer:
  * data covers the global box [data_lo, data_lo + data_dim), x fastest.  The
  * data box must contain [lo-1, hi+1) clipped to the volume, so that samples
- * the brick owns reconstruct exactly as on the whole volume. */
+ * the brick owns reconstruct exactly as on the whole volume.  A data box must
+ * hold less than 4 GiB (else VDI_E_UNSUPPORTED: split into more bricks). */
 typedef struct {
     const void *data;
     int32_t dtype;           /* vdi_dtype */
@@ -123,14 +127,20 @@ typedef struct {
  *           the upper bracket.
  *  LEARNED: (an extension beyond the paper) per list, y = output of the MLP
  *           `mlp` (a vdi_mlp_t*) on the list's 64-bin opacity histogram (see
- *           vdi_tau_features); the candidates gamma = 2^(y + d), d in
- *           {0, -1/4, 1/4, -1/2, 1/2}, each clamped to [gamma_max*2^-iters,
- *           gamma_max], are counted in one scan.  A candidate is in band if its
- *           count c satisfies m - floor(fallback_tol*m) <= c <= N with
- *           m = min(N, cmax) (cmax: the count at the smallest bisection
- *           threshold); the in-band candidate with the largest count is used,
- *           and a list with none is regenerated by BISECT.  Lists with at most
- *           N non-transparent samples take the bisection's result directly
+ *           vdi_tau_features), or y from the caller's array `y`.  A count c is
+ *           in band if m - floor(fallback_tol*m) <= c <= N with m = min(N,
+ *           cmax) (cmax: the count at the smallest bisection threshold).
+ *           Round one counts gamma = 2^y_d, y_d = clamp(y + d) to
+ *           [log2(gamma_max) - iters, log2(gamma_max)], d in {0, -1/4, 1/4,
+ *           -1/2, 1/2}, in one scan and keeps the in-band candidate with the
+ *           largest count (ties: first listed).  Without one, if candidates
+ *           adjacent in threshold order straddle the band (count > N at the
+ *           smaller y_a, < the band at the larger y_b; the pair with the
+ *           smallest |d_a + d_b|, ties: smaller), round two counts
+ *           2^(y_a + (y_b - y_a) t/6), t = 1..5, and keeps its in-band
+ *           candidate with the largest count (ties: smaller t).  A list kept
+ *           by neither round is regenerated by BISECT.  Lists with at most N
+ *           non-transparent samples take the bisection's result directly
  *           (every threshold is feasible there).  Regular layout only. */
 typedef struct {
     int32_t mode;            /* vdi_tau_mode */
@@ -140,6 +150,8 @@ typedef struct {
     const void *mlp;         /* LEARNED: const vdi_mlp_t* */
     float fallback_tol;      /* LEARNED: 0.1 */
     float feature_scale;     /* LEARNED: histogram counts are divided by this (s_ref) */
+    const float *y;          /* LEARNED: optional device array [k][H*W] of log2 thresholds
+                                used instead of the MLP's output (NULL: run the MLP) */
 } vdi_tau_t;
 
 /* Context: one per device and thread of use.  vdi_ctx_create makes `device`
@@ -227,8 +239,9 @@ vdi_status vdi_mlp_adam(vdi_ctx *ctx, vdi_mlp_t *mlp, const float *grad, float *
                         float beta1, float beta2, float eps, void *stream);
 
 /* Counts of the learned path since the last call (synchronises `stream`):
- * stats[0] kept regressed thresholds, [1] lists taking the all-feasible
- * shortcut, [2] fallbacks to bisection, [3] empty lists.  Clears them. */
+ * stats[0] lists kept in round one, [1] lists taking the all-feasible
+ * shortcut, [2] fallbacks to bisection, [3] empty lists, [4] lists kept in
+ * round two.  stats holds 5 entries.  Clears them. */
 vdi_status vdi_learned_stats(vdi_ctx *ctx, int64_t *stats, void *stream);
 
 /* Diagnostic: D = A B for 16x16 bf16 A, B (row-major) through one matrix-core

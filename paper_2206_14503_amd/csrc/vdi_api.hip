@@ -144,7 +144,7 @@ static void fill_i32(int* p, int v, size_t n, hipStream_t s)
 
 // Scratch layout of the learned path for nb bricks of npix pixels.
 struct LearnScratch {
-    size_t hist, nnt, cmax, y, list, cnt, total;
+    size_t hist, nnt, cmax, y, list, cnt, rlist, ry, rcnt, svlist, svcnt, total;
 };
 static LearnScratch learn_layout(size_t rays, int nb)
 {
@@ -157,6 +157,11 @@ static LearnScratch learn_layout(size_t rays, int nb)
     L.y = take(rays * sizeof(float));
     L.list = take(rays * sizeof(int));
     L.cnt = take((size_t)nb * sizeof(int));
+    L.rlist = take(rays * sizeof(int));
+    L.ry = take(rays * sizeof(float2));
+    L.rcnt = take((size_t)nb * sizeof(int));
+    L.svlist = take(rays * sizeof(int));
+    L.svcnt = take(sizeof(int));
     L.total = o;
     return L;
 }
@@ -178,20 +183,33 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
     Lb.y = (const float*)(base + Ls.y);
     Lb.fb_list = (int*)(base + Ls.list);
     Lb.fb_count = (int*)(base + Ls.cnt);
+    Lb.rf_list = (int*)(base + Ls.rlist);
+    Lb.rf_y = (float2*)(base + Ls.ry);
+    Lb.rf_count = (int*)(base + Ls.rcnt);
+    Lb.sv_list = (int*)(base + Ls.svlist);
+    Lb.sv_count = (int*)(base + Ls.svcnt);
     Lb.stats = ctx->status + 4;
     Lb.s_ref = tau->feature_scale;
     Lb.tol = tau->fallback_tol;
+    Lb.blocks_per_brick = std::max(1, ctx->num_cus * 8 / std::min(k, kGenBricksPerLaunch));
     const vdi_mlp_t* mlp = (const vdi_mlp_t*)tau->mlp;
+    if (tau->y) Lb.y = tau->y;
     fill_i32(Lb.fb_count, 0, (size_t)k, s);
+    fill_i32(Lb.rf_count, 0, (size_t)k, s);
+    fill_i32(Lb.sv_count, 0, 1, s);
     for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
         int nb = std::min(k - r0, kGenBricksPerLaunch);
         GenBricks B = make_bricks(bricks, out, r0, nb);
         launch_learned(0, dtype, P, B, nb, Lb, s);
         if ((st = launched()) != VDI_OK) return st;
     }
-    launch_mlp_fwd(mlp->w_bf16, mlp->w_f32, Lb.hist, (int)rays, (float*)(base + Ls.y), nullptr, s);
-    if ((st = launched()) != VDI_OK) return st;
-    for (int phase = 1; phase <= 2; ++phase) {
+    if (!tau->y) {
+        // the served rays' compacted histograms; y scattered back to brick-ray order
+        launch_mlp_fwd(mlp->w_bf16, mlp->w_f32, Lb.hist, (int)rays, Lb.sv_count, Lb.sv_list, ctx->num_cus * 3,
+                       (float*)(base + Ls.y), nullptr, s);
+        if ((st = launched()) != VDI_OK) return st;
+    }
+    for (int phase = 1; phase <= 3; ++phase) {
         for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
             int nb = std::min(k - r0, kGenBricksPerLaunch);
             GenBricks B = make_bricks(bricks, out, r0, nb);
@@ -274,7 +292,8 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
     if (st != VDI_OK) return st;
     if (tau->mode == VDI_TAU_LEARNED) {
         const vdi_mlp_t* mlp = (const vdi_mlp_t*)tau->mlp;
-        if (!mlp || !mlp->w_bf16 || !mlp->w_f32) return fail(VDI_E_INVALID, "learned mode needs tau->mlp");
+        if (!tau->y && (!mlp || !mlp->w_bf16 || !mlp->w_f32))
+            return fail(VDI_E_INVALID, "learned mode needs tau->mlp or tau->y");
         if (!(tau->feature_scale > 0.0f)) return fail(VDI_E_INVALID, "learned mode needs feature_scale > 0");
         if (!(tau->fallback_tol >= 0.0f && tau->fallback_tol < 1.0f))
             return fail(VDI_E_INVALID, "fallback_tol must be in [0, 1)");
@@ -295,8 +314,9 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
             if (b.data_lo[a] > need_lo || b.data_lo[a] + b.data_dim[a] < need_hi || b.data_dim[a] < 1)
                 return fail(VDI_E_INVALID, "brick %d: data box axis %d does not cover the owned box plus one voxel", r, a);
         }
-        if ((int64_t)b.data_dim[0] * b.data_dim[1] * b.data_dim[2] >= ((int64_t)1 << 31))
-            return fail(VDI_E_UNSUPPORTED, "brick %d: more than 2^31 data voxels", r);
+        if ((int64_t)b.data_dim[0] * b.data_dim[1] * b.data_dim[2] * (b.dtype == VDI_F16 ? 2 : 4) >=
+            ((int64_t)1 << 32))
+            return fail(VDI_E_UNSUPPORTED, "brick %d: data box of 4 GiB or more; split the volume into more bricks", r);
         st = check_vdi(&out[r], "out", true);
         if (st != VDI_OK) return st;
         if (out[r].width != cam->width || out[r].height != cam->height)
@@ -405,8 +425,8 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
                                            : (uint64_t)in[r].max_n * (uint64_t)in[r].width * in[r].height;
         seq_cap += in[r].max_n;
     }
-    if (composite_lds_bytes(k, seq_cap) > 160 * 1024)
-        return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", seq_cap);
+    const size_t lds = composite_lds_bytes(k, seq_cap);
+    if (lds > 160 * 1024) return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", seq_cap);
     P.k = k;
     P.npix = (uint32_t)((size_t)out->width * out->height);
     P.inv_ref = 1.0f / out->ref_step;
@@ -421,7 +441,12 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     P.out_gamma = out->gamma;
     P.status = ctx->status;
     P.seq_cap = seq_cap;
-    launch_composite(P, (hipStream_t)stream);
+    // queue of pixels left to the general merge: [npix] + counter
+    if ((st = ensure_scratch(ctx, ((size_t)P.npix + 64) * sizeof(int))) != VDI_OK) return st;
+    P.q_count = (int*)ctx->scratch;
+    P.q_list = (int*)ctx->scratch + 64;
+    const int per_cu = std::max(1, std::min<int>((int)((160 * 1024) / (lds + 64)), 28));
+    launch_composite(P, ctx->num_cus * per_cu, (hipStream_t)stream);
     return launched();
 }
 
@@ -470,8 +495,9 @@ vdi_status vdi_tau_features(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, cons
             if (b.data_lo[a] > need_lo || b.data_lo[a] + b.data_dim[a] < need_hi)
                 return fail(VDI_E_INVALID, "brick %d: data box", r);
         }
-        if ((int64_t)b.data_dim[0] * b.data_dim[1] * b.data_dim[2] >= ((int64_t)1 << 31))
-            return fail(VDI_E_UNSUPPORTED, "brick %d: more than 2^31 data voxels", r);
+        if ((int64_t)b.data_dim[0] * b.data_dim[1] * b.data_dim[2] * (b.dtype == VDI_F16 ? 2 : 4) >=
+            ((int64_t)1 << 32))
+            return fail(VDI_E_UNSUPPORTED, "brick %d: data box of 4 GiB or more; split the volume into more bricks", r);
     }
     GenParams P;
     memset(&P, 0, sizeof P);
@@ -519,7 +545,7 @@ vdi_status vdi_mlp_forward(vdi_ctx* ctx, const vdi_mlp_t* mlp, const uint16_t* x
     if (rows < 0) return fail(VDI_E_INVALID, "rows < 0");
     if (((uintptr_t)x & 7) != 0) return fail(VDI_E_INVALID, "x must be 8-byte aligned");
     if (rows == 0) return VDI_OK;
-    launch_mlp_fwd(mlp->w_bf16, mlp->w_f32, x, rows, y, acts, (hipStream_t)stream);
+    launch_mlp_fwd(mlp->w_bf16, mlp->w_f32, x, rows, nullptr, nullptr, ctx->num_cus * 3, y, acts, (hipStream_t)stream);
     return launched();
 }
 
@@ -552,10 +578,10 @@ vdi_status vdi_learned_stats(vdi_ctx* ctx, int64_t* stats, void* stream)
 {
     if (!ctx || !stats) return fail(VDI_E_INVALID, "NULL argument");
     VDI_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
-    int32_t v[4];
+    int32_t v[kLearnStats];
     VDI_HIP_CHECK(hipMemcpy(v, ctx->status + 4, sizeof v, hipMemcpyDeviceToHost));
     VDI_HIP_CHECK(hipMemset(ctx->status + 4, 0, sizeof v));
-    for (int i = 0; i < 4; ++i) stats[i] = v[i];
+    for (int i = 0; i < kLearnStats; ++i) stats[i] = v[i];
     return VDI_OK;
 }
 

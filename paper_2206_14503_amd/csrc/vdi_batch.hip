@@ -28,13 +28,19 @@ struct BatchImpl {
     CompParams* d_jobs = nullptr;
     uint2* d_tiles = nullptr;
     uint32_t* d_head = nullptr;
+    int* d_queue = nullptr;     // per job: [npix] queued pixels, then the counters [n_jobs]
+    size_t q_total = 0;         // queue entries before the counters
     uint32_t n_tiles = 0;
-    size_t lds = 0;
+    size_t lds = 0;             // depth-disjoint phase
     int grid = 0;
+    size_t lds_gen = 0;         // general-merge phase
+    int grid_gen = 0;
     double clock_hz = 0.0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
+
+size_t queue_counters(const BatchImpl* b) { return b->q_total; }
 
 using TileMap = std::map<std::pair<int, int>, int>;
 
@@ -120,6 +126,7 @@ void destroy_impl(BatchImpl* b)
     if (b->d_jobs) hipFree(b->d_jobs);
     if (b->d_tiles) hipFree(b->d_tiles);
     if (b->d_head) hipFree(b->d_head);
+    if (b->d_queue) hipFree(b->d_queue);
     delete b;
 }
 
@@ -134,17 +141,22 @@ vdi_status create_impl(vdi_ctx* ctx, const vdi_job_t* jobs, int n_jobs, const Ti
     }
     std::vector<CompParams> hp(n_jobs);
     std::vector<double> work(n_jobs);
-    size_t lds = 0;
+    std::vector<size_t> q_off(n_jobs);
+    size_t lds = 0, lds_gen = 0, q_total = 0;
     for (int i = 0; i < n_jobs; ++i) {
         hp[i] = job_params(ctx, jobs[i]);
-        lds = std::max(lds, composite_lds_bytes(hp[i].k, hp[i].seq_cap));
+        lds_gen = std::max(lds_gen, composite_lds_bytes(hp[i].k, hp[i].seq_cap));
+        if (hp[i].k <= kCatMaxInputs) lds = std::max(lds, cat_lds_bytes(hp[i].k));
         work[i] = (double)hp[i].k * hp[i].out_n * hp[i].npix;
+        q_off[i] = q_total;
+        q_total += hp[i].k <= kCatMaxInputs ? hp[i].npix : 0;
     }
     std::vector<int> order(n_jobs);
     for (int i = 0; i < n_jobs; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
     std::vector<uint2> tiles;
     for (int j : order) {
+        if (hp[j].k > kCatMaxInputs) continue;   // general merge only
         int tile = forced_tile;
         if (tile <= 0) {
             auto it = tiles_by_bucket.find({ k_bucket(hp[j].k), hp[j].out_n });
@@ -160,18 +172,30 @@ vdi_status create_impl(vdi_ctx* ctx, const vdi_job_t* jobs, int n_jobs, const Ti
     b->n_jobs = n_jobs;
     b->n_tiles = (uint32_t)tiles.size();
     b->lds = lds;
+    b->lds_gen = lds_gen;
+    b->q_total = q_total;
     // blocks per CU: limited by LDS (160 KiB per CU) and by 7 waves per SIMD
     int per_cu = std::max(1, std::min<int>((int)((160 * 1024) / (lds + 64)), 28));
     b->grid = std::max(1, std::min<int>(ctx->num_cus * per_cu, (int)b->n_tiles));
+    int per_cu_gen = std::max(1, std::min<int>((int)((160 * 1024) / (lds_gen + 64)), 28));
+    b->grid_gen = ctx->num_cus * per_cu_gen;
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0)
         khz = 100000;
     b->clock_hz = (double)khz * 1e3;
     hipError_t e = hipMalloc(&b->d_jobs, sizeof(CompParams) * n_jobs);
-    if (e == hipSuccess) e = hipMalloc(&b->d_tiles, sizeof(uint2) * tiles.size());
+    if (e == hipSuccess) e = hipMalloc(&b->d_tiles, sizeof(uint2) * std::max<size_t>(tiles.size(), 1));
     if (e == hipSuccess) e = hipMalloc(&b->d_head, 256);
-    if (e == hipSuccess) e = hipMemcpy(b->d_jobs, hp.data(), sizeof(CompParams) * n_jobs, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(uint2) * tiles.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&b->d_queue, sizeof(int) * (q_total + (size_t)n_jobs));
+    if (e == hipSuccess) {
+        for (int i = 0; i < n_jobs; ++i) {
+            hp[i].q_list = b->d_queue + q_off[i];
+            hp[i].q_count = b->d_queue + q_total + i;
+        }
+        e = hipMemcpy(b->d_jobs, hp.data(), sizeof(CompParams) * n_jobs, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && !tiles.empty())
+        e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(uint2) * tiles.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         destroy_impl(b);
         return fail(VDI_E_HIP, "batch setup: %s", hipGetErrorString(e));
@@ -182,8 +206,8 @@ vdi_status create_impl(vdi_ctx* ctx, const vdi_job_t* jobs, int n_jobs, const Ti
 
 vdi_status run_impl(BatchImpl* b, uint64_t* t_se, hipStream_t s)
 {
-    launch_batch(b->d_jobs, b->d_tiles, b->n_tiles, b->d_head, (unsigned long long*)t_se, b->n_jobs, b->lds, b->grid,
-                 s);
+    launch_batch(b->d_jobs, b->d_tiles, b->n_tiles, b->d_head, b->d_queue + queue_counters(b), (unsigned long long*)t_se,
+                 b->n_jobs, b->lds, b->grid, b->lds_gen, b->grid_gen, s);
     return launched();
 }
 
@@ -228,8 +252,8 @@ vdi_status vdi_batch_capture(vdi_batch* batch, uint64_t* t_start_end, void* stre
         b->graph = nullptr;
     }
     VDI_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    launch_batch(b->d_jobs, b->d_tiles, b->n_tiles, b->d_head, (unsigned long long*)t_start_end, b->n_jobs, b->lds,
-                 b->grid, s);
+    launch_batch(b->d_jobs, b->d_tiles, b->n_tiles, b->d_head, b->d_queue + queue_counters(b),
+                 (unsigned long long*)t_start_end, b->n_jobs, b->lds, b->grid, b->lds_gen, b->grid_gen, s);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (e != hipSuccess) return fail(VDI_E_HIP, "graph capture failed: %s", hipGetErrorString(e));

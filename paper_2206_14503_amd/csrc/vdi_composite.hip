@@ -28,7 +28,7 @@ struct CSeg {
     float T;           // transmittance
     float lT;          // log2 of the transmittance
     float f, b, bt;    // front, back (incl. trailing gap/transparent), back of last non-transparent
-    int open;
+    bool open;
     int count;
 };
 
@@ -71,7 +71,7 @@ struct COut {
 
 __device__ inline void seg_reset(CSeg& S)
 {
-    S.open = 0;
+    S.open = false;
     S.count = 0;
     S.c0 = S.c1 = S.c2 = S.A = 0.0f;
     S.T = 1.0f;
@@ -91,56 +91,54 @@ __device__ inline void c_close(CSeg& S, const COut& o, float inv_ref)
         o.depth[slot] = make_float2(S.f, S.bt);
     }
     ++S.count;
-    S.open = 0;
+    S.open = false;
 }
 
 // Eq. 1 test: gamma < |C a_S / A - e| with a_S = 1 - 2^(log2(T) / L) the
-// open supersegment's per-step opacity, evaluated as
+// open supersegment's per-step opacity over L = (b - f) / ref, evaluated as
 // gamma^2 A^2 < |C a_S - e A|^2 (A > 0).
-__device__ inline bool c_exceeds(const CSeg& S, float inv_ref, float g2, float e0, float e1, float e2)
+__device__ inline bool c_exceeds(const CSeg& S, float b, float inv_ref, float g2, float e0, float e1, float e2)
 {
-    float L = (S.b - S.f) * inv_ref;
+    float L = (b - S.f) * inv_ref;
     float aS = 1.0f - hw_exp2(S.lT * hw_rcp(L));
     float d0 = S.c0 * aS - e0 * S.A, d1 = S.c1 * aS - e1 * S.A, d2 = S.c2 * aS - e2 * S.A;
     return g2 * (S.A * S.A) < d0 * d0 + d1 * d1 + d2 * d2;
 }
 
+// One element through the segmenter: the empty space before it (a
+// transparent stretch, Alg. S1), then the element itself.  The state update
+// is written as selects; a closed state's fields are don't-cares.
 template <bool WRITE>
 __device__ inline void c_step(CSeg& S, const COut& o, float inv_ref, float g2, int cap, const CElem& e)
 {
-    // empty space before the element is a transparent sample (Alg. S1)
-    if (S.open && e.f > S.b) {
-        bool may_close = cap <= 0 || S.count < cap - 1;
-        if (may_close && c_exceeds(S, inv_ref, g2, 0.0f, 0.0f, 0.0f)) c_close<WRITE>(S, o, inv_ref);
-        else S.b = e.f;
+    // gap [S.b, e.f): closes the open supersegment, or extends it.  The
+    // conditions use non-short-circuit & so both tests run unconditionally.
+    const bool gap = S.open & (e.f > S.b);
+    const bool close_g = gap & (cap <= 0 || S.count < cap - 1) & c_exceeds(S, S.b, inv_ref, g2, 0.0f, 0.0f, 0.0f);
+    if (WRITE && close_g) c_close<true>(S, o, inv_ref);
+    else S.count += close_g ? 1 : 0;
+    const bool open1 = S.open & !close_g;
+    const float b1 = fmaxf(S.b, e.f);   // = e.f after a gap, else S.b (don't-care when closed)
+    // the element
+    const bool close = open1 & (cap <= 0 || S.count < cap - 1) & c_exceeds(S, b1, inv_ref, g2, e.e0, e.e1, e.e2);
+    if (WRITE && close) {
+        S.b = b1;
+        c_close<true>(S, o, inv_ref);
+    } else {
+        S.count += close ? 1 : 0;
     }
-    if (S.open) {
-        bool may_close = cap <= 0 || S.count < cap - 1;
-        if (may_close && c_exceeds(S, inv_ref, g2, e.e0, e.e1, e.e2)) {
-            c_close<WRITE>(S, o, inv_ref);
-        } else {
-            float w = S.T * e.at;
-            S.c0 = fmaf(w, e.r, S.c0);
-            S.c1 = fmaf(w, e.g, S.c1);
-            S.c2 = fmaf(w, e.bl, S.c2);
-            S.A += w;
-            S.T *= e.Te;
-            S.lT += e.lg;
-            S.b = e.b;
-            if (!e.transparent) S.bt = e.b;
-        }
-    }
-    if (!S.open && !e.transparent) {
-        S.open = 1;
-        S.f = e.f;
-        S.b = S.bt = e.b;
-        S.c0 = e.r * e.at;
-        S.c1 = e.g * e.at;
-        S.c2 = e.bl * e.at;
-        S.A = e.at;
-        S.T = e.Te;
-        S.lT = e.lg;
-    }
+    const bool merge = open1 & !close;
+    const float w = S.T * e.at;
+    S.c0 = merge ? fmaf(w, e.r, S.c0) : e.r * e.at;
+    S.c1 = merge ? fmaf(w, e.g, S.c1) : e.g * e.at;
+    S.c2 = merge ? fmaf(w, e.bl, S.c2) : e.bl * e.at;
+    S.A = merge ? S.A + w : e.at;
+    S.T = merge ? S.T * e.Te : e.Te;
+    S.lT = merge ? S.lT + e.lg : e.lg;
+    S.f = merge ? S.f : e.f;
+    S.b = e.b;
+    S.bt = (merge & e.transparent) ? S.bt : e.b;
+    S.open = merge | !e.transparent;
 }
 
 struct InLds {
@@ -194,19 +192,22 @@ struct Src {
     uint32_t e;
 };
 
-// Sequential reader of a lane's merge sequence (one pass).
+// Sequential reader of a lane's merge sequence (general merge).
 struct SeqReader {
     const Lds* L;
     int t;
     int k;
-    __device__ void reset() const
+    int i;
+    __device__ void reset()
     {
+        i = 0;
         for (int r = 0; r < k; ++r) L->cur[r * kWave + t] = 0;
     }
-    __device__ Src at(int i) const
+    __device__ Src next()
     {
         uint32_t b = L->seq[(L->nib ? (i >> 1) : i) * kWave + t];
         int r = L->nib ? (int)((i & 1) ? (b >> 4) : (b & 15u)) : (int)b;
+        ++i;
         uint32_t s = L->cur[r * kWave + t];
         L->cur[r * kWave + t] = (uint8_t)(s + 1);
         const InLds in = L->in[r];
@@ -214,12 +215,73 @@ struct SeqReader {
     }
 };
 
+// Per-lane LDS of the depth-disjoint path: two words per input.  During
+// set-up they hold each list's first front and last back; afterwards its
+// count and the element index of its slot 0.
+struct CatLds {
+    const InLds* in;
+    float* a;   // [k][64]
+    float* b;   // [k][64]
+};
+
+__device__ inline CatLds cat_layout(unsigned char* lds_raw, int k)
+{
+    CatLds L;
+    L.in = (const InLds*)lds_raw;
+    L.a = (float*)(lds_raw + sizeof(InLds) * kMaxInputs);
+    L.b = L.a + (size_t)k * kWave;
+    return L;
+}
+
+// Reader of depth-disjoint lists: the non-empty inputs in the order `ord`
+// (4-bit input ids, first list in the low bits), each list slot by slot.
+struct CatReader {
+    CatLds L;
+    int t;
+    uint64_t ord;
+    int ne;        // lists in ord (1..16)
+    int li;        // position in ord of the current list
+    int s, c;      // slot in it and its count
+    uint32_t e, stride;
+    const float4* color;
+    const float2* depth;
+    __device__ void open(int pos)
+    {
+        // past the last list nothing more is read: the count becomes
+        // unreachable (the words read are those of a valid list, unused)
+        const bool past = pos >= ne;
+        const int r = (int)((ord >> (4 * (past ? 0 : pos))) & 15u);
+        li = pos;
+        s = 0;
+        const int cr = __float_as_int(L.a[r * kWave + t]);
+        c = past ? 0x7fffffff : cr;
+        e = __float_as_uint(L.b[r * kWave + t]);
+        const InLds in = L.in[r];
+        stride = in.stride;
+        color = in.color;
+        depth = in.depth;
+    }
+    __device__ void reset() { open(0); }
+    __device__ Src next()
+    {
+        Src q{color, depth, e};
+        if (++s == c) {
+            open(li + 1);
+        } else {
+            e += stride;
+        }
+        return q;
+    }
+};
+
 // One scan of the merged list carrying NC segmenter states (thresholds g[]).
 // Counting scans (WRITE false) freeze a state once its count exceeds
-// `limit` and stop when every state is frozen.
-template <int NC, bool WRITE>
-__device__ void c_scan(const SeqReader& rd, int total, float inv_ref, const float* gam, int cap, int limit,
-                       const COut& o, int* counts)
+// `limit` and stop when every state is frozen, unless VALIDATE: then every
+// element is visited and checked (finite depths, f < b, fronts
+// non-decreasing), and *bad reports a violation.
+template <int NC, bool WRITE, bool VALIDATE, typename R>
+__device__ void c_scan(R rd, int total, float inv_ref, const float* gam, int cap, int limit, const COut& o,
+                       int* counts, bool* bad)
 {
     CSeg S[NC];
     float g2[NC];
@@ -228,29 +290,35 @@ __device__ void c_scan(const SeqReader& rd, int total, float inv_ref, const floa
         seg_reset(S[c]);
         g2[c] = gam[c] * gam[c];
     }
+    bool ok = true;
     if (total > 0) {
         rd.reset();
-        Src src = rd.at(0);
-        float4 cn = src.c[src.e];
-        float2 fn = src.d[src.e];
+        Src src = rd.next();
+        float4 cn = gload(src.c, src.e);
+        float2 fn = gload(src.d, src.e);
+        float prev_f = -__builtin_inff();
         for (int i = 0; i < total; ++i) {
             float4 cc = cn;
             float2 fc = fn;
             if (i + 1 < total) {
-                Src nx = rd.at(i + 1);
-                cn = nx.c[nx.e];
-                fn = nx.d[nx.e];
+                Src nx = rd.next();
+                cn = gload(nx.c, nx.e);
+                fn = gload(nx.d, nx.e);
+            }
+            if (VALIDATE) {
+                ok &= isfinite(fc.x) & isfinite(fc.y) & (fc.x < fc.y) & (fc.x >= prev_f);
+                prev_f = fc.x;
             }
             CElem e = prep(cc, fc, inv_ref);
+            // a frozen state (count above limit) keeps stepping: its count
+            // only grows, so its outcome stays decided
             bool live = false;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                if (WRITE || S[c].count <= limit) {
-                    c_step<WRITE>(S[c], o, inv_ref, g2[c], cap, e);
-                    live |= WRITE || S[c].count <= limit;
-                }
+                c_step<WRITE>(S[c], o, inv_ref, g2[c], cap, e);
+                live |= WRITE || S[c].count <= limit;
             }
-            if (!live) break;
+            if (!VALIDATE && !live) break;
         }
     }
 #pragma unroll
@@ -258,9 +326,11 @@ __device__ void c_scan(const SeqReader& rd, int total, float inv_ref, const floa
         if (S[c].open && (WRITE || S[c].count <= limit)) c_close<WRITE>(S[c], o, inv_ref);
         counts[c] = S[c].count;
     }
+    if (VALIDATE) *bad = !ok;
 }
 
 }  // namespace
+
 
 // The input table of a job in LDS (thread t < k writes entry t).
 __device__ inline void setup_inputs(const CompParams& P, unsigned char* lds_raw, int t)
@@ -274,11 +344,178 @@ __device__ inline void setup_inputs(const CompParams& P, unsigned char* lds_raw,
     }
 }
 
-// Merge and re-segment the lists of pixel p (lane t of the wave).
+// Output of an invalid pixel: status flag 2, an empty list.
+__device__ inline void reject_pixel(const CompParams& P, uint32_t p)
+{
+    atomicOr(P.status, 2);
+    for (int j = 0; j < P.out_n; ++j) {
+        size_t slot = (size_t)j * P.npix + p;
+        P.out_color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        P.out_depth[slot] = make_float2(0.0f, 0.0f);
+    }
+    P.out_count[p] = 0;
+    if (P.out_gamma) P.out_gamma[p] = 0.0f;
+}
+
+// Re-segmentation of pixel p's merged list (read through rd, `total`
+// elements): pass-through when it fits (R17), else the fixed threshold or the
+// bisection (two levels per scan), then the zero-filled tail.  With VALIDATE
+// the first pass checks the elements; an invalid list is rejected.
+template <bool VALIDATE, typename R>
+__device__ void resegment(const CompParams& P, const R& rd0, int total, uint32_t p)
+{
+    COut o{P.out_color, P.out_depth, p, P.npix, P.out_n};
+    int count;
+    float gm = 0.0f;
+    bool bad = false;
+    if (total <= P.out_n) {
+        // pass-through: the merged list already fits
+        R rd = rd0;
+        rd.reset();
+        float prev_f = -__builtin_inff();
+        bool ok = true;
+        for (int i = 0; i < total; ++i) {
+            Src src = rd.next();
+            size_t slot = (size_t)i * P.npix + p;
+            const float4 c = gload(src.c, src.e);
+            const float2 fb = gload(src.d, src.e);
+            if (VALIDATE) {
+                ok &= isfinite(fb.x) & isfinite(fb.y) & (fb.x < fb.y) & (fb.x >= prev_f);
+                prev_f = fb.x;
+            }
+            P.out_color[slot] = c;
+            P.out_depth[slot] = fb;
+        }
+        bad = !ok;
+        count = total;
+    } else if (P.mode == VDI_TAU_FIXED) {
+        gm = P.tau;
+        int c1[1];
+        c_scan<1, true, VALIDATE>(rd0, total, P.inv_ref, &gm, P.out_n, 1 << 30, o, c1, &bad);
+        count = c1[0];
+    } else {
+        float lo = 0.0f, hi = P.gmax;
+        int level = 0;
+        bool first = true;
+        while (level + 2 <= P.iters) {
+            float m = 0.5f * (lo + hi);
+            float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
+            int c3[3];
+            if (VALIDATE && first) {
+                c_scan<3, false, true>(rd0, total, P.inv_ref, g3, 0, P.out_n, o, c3, &bad);
+                if (bad) break;
+            } else {
+                c_scan<3, false, false>(rd0, total, P.inv_ref, g3, 0, P.out_n, o, c3, nullptr);
+            }
+            first = false;
+            if (c3[0] <= P.out_n) {
+                hi = m;
+                if (c3[1] <= P.out_n) hi = g3[1];
+                else lo = g3[1];
+            } else {
+                lo = m;
+                if (c3[2] <= P.out_n) hi = g3[2];
+                else lo = g3[2];
+            }
+            level += 2;
+        }
+        if (!bad && level < P.iters) {
+            float m = 0.5f * (lo + hi);
+            int c1[1];
+            if (VALIDATE && first) c_scan<1, false, true>(rd0, total, P.inv_ref, &m, 0, P.out_n, o, c1, &bad);
+            else c_scan<1, false, false>(rd0, total, P.inv_ref, &m, 0, P.out_n, o, c1, nullptr);
+            if (c1[0] <= P.out_n) hi = m;
+            else lo = m;
+        }
+        gm = hi;
+        count = 0;
+        if (!bad) {
+            int c1[1];
+            c_scan<1, true, false>(rd0, total, P.inv_ref, &gm, 0, 1 << 30, o, c1, nullptr);
+            count = c1[0];
+        }
+    }
+    if (VALIDATE && bad) {
+        reject_pixel(P, p);
+        return;
+    }
+    if (count > P.out_n) count = P.out_n;
+    for (int j = count; j < P.out_n; ++j) {
+        size_t slot = (size_t)j * P.npix + p;
+        P.out_color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        P.out_depth[slot] = make_float2(0.0f, 0.0f);
+    }
+    P.out_count[p] = count;
+    if (P.out_gamma) P.out_gamma[p] = gm;
+}
+
+// Depth-disjoint path for pixel p (lane t): when the non-empty lists occupy
+// disjoint depth ranges, the merge by (front, input) is their concatenation
+// in order of first front (every front of an earlier list lies below the
+// next list's first front), so no merge sequence is stored.  Returns false,
+// writing nothing, when two lists interleave (the pixel then takes the
+// general merge).
+__device__ bool composite_pixel_cat(const CompParams& P, unsigned char* lds_raw, int t, uint32_t p)
+{
+    const CatLds L = cat_layout(lds_raw, P.k);
+    // ---- counts (validated), first front and last back of every list
+    int total = 0;
+    for (int r = 0; r < P.k; ++r) {
+        const CompInput& in = P.in[r];
+        int c = in.count[p];
+        const uint32_t eb = in.compact ? in.offset[p] : p;
+        const uint64_t last = in.compact ? (uint64_t)eb + (uint64_t)(c > 0 ? c : 0) : (uint64_t)(c > 0 ? c : 0) * P.npix;
+        if (c < 0 || c > in.max_n || last > in.capacity) {
+            reject_pixel(P, p);
+            return true;
+        }
+        float f0 = __builtin_inff(), bl = __builtin_inff();
+        if (c > 0) {
+            const uint32_t stride = in.compact ? 1u : P.npix;
+            f0 = gload(in.depth, eb).x;
+            bl = gload(in.depth, eb + (uint32_t)(c - 1) * stride).y;
+            // non-finite ends: the general merge validates (and rejects) the pixel
+            if (!isfinite(f0) || !isfinite(bl)) return false;
+        }
+        L.a[r * kWave + t] = f0;   // +inf marks an empty list
+        L.b[r * kWave + t] = bl;
+        total += c;
+    }
+    // ---- order by (first front, input); check that consecutive lists are disjoint
+    uint64_t ord = 0;
+    int ne = 0;
+    for (int r = 0; r < P.k; ++r) {
+        const float fr = L.a[r * kWave + t];
+        if (fr == __builtin_inff()) continue;
+        int rank = 0;
+        for (int q = 0; q < P.k; ++q) {
+            const float fq = L.a[q * kWave + t];
+            rank += (fq < fr || (fq == fr && q < r)) ? 1 : 0;
+        }
+        ord |= (uint64_t)r << (4 * rank);
+        ++ne;
+    }
+    for (int i = 0; i + 1 < ne; ++i) {
+        const int ra = (int)((ord >> (4 * i)) & 15u), rb = (int)((ord >> (4 * (i + 1))) & 15u);
+        if (!(L.b[ra * kWave + t] <= L.a[rb * kWave + t])) return false;
+    }
+    // ---- the reader's per-list words: count and element index of slot 0
+    for (int r = 0; r < P.k; ++r) {
+        const CompInput& in = P.in[r];
+        L.a[r * kWave + t] = __int_as_float(in.count[p]);
+        L.b[r * kWave + t] = __uint_as_float(in.compact ? in.offset[p] : p);
+    }
+    CatReader rd{L, t, ord, ne, 0, 0, 0, 0u, 0u, nullptr, nullptr};
+    resegment<true>(P, rd, total, p);
+    return true;
+}
+
+// General path for pixel p (lane t): k-way merge of the lists by (front,
+// input) into an LDS merge sequence, then re-segmentation replaying it.
 __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int t, uint32_t p)
 {
     const Lds L = lds_layout(lds_raw, P.k, P.seq_cap);
-    const SeqReader rd{&L, t, P.k};
+    const SeqReader rd{&L, t, P.k, 0};
 
     // ---- load counts, validate, set up the merge cursors
     int total = 0;
@@ -332,78 +569,20 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
         float nf = L.next[rb * kWave + t];
         if (s < c) {
             // validate the element now at the front: sorted, f < b
-            float2 fb = inr.depth[eb + (uint32_t)s * inr.stride];
+            float2 fb = gload(inr.depth, eb + (uint32_t)s * inr.stride);
             if (!(fb.x < fb.y) || !(fb.x >= best) || !isfinite(fb.y)) bad = true;
         }
         float nn = __builtin_inff();
-        if (s + 1 < c) nn = inr.depth[eb + (uint32_t)(s + 1) * inr.stride].x;
+        if (s + 1 < c) nn = gload(inr.depth, eb + (uint32_t)(s + 1) * inr.stride).x;
         L.front[rb * kWave + t] = nf;
         L.next[rb * kWave + t] = nn;
     }
     if (L.nib && (total & 1) && !bad) L.seq[(total >> 1) * kWave + t] = (uint8_t)pending;
     if (bad) {
-        atomicOr(P.status, 2);
-        total = 0;
+        reject_pixel(P, p);
+        return;
     }
-
-    COut o{P.out_color, P.out_depth, p, P.npix, P.out_n};
-    int count;
-    float gm = 0.0f;
-    if (total <= P.out_n) {
-        // pass-through: the merged list already fits
-        rd.reset();
-        for (int i = 0; i < total; ++i) {
-            Src src = rd.at(i);
-            size_t slot = (size_t)i * P.npix + p;
-            P.out_color[slot] = src.c[src.e];
-            P.out_depth[slot] = src.d[src.e];
-        }
-        count = total;
-    } else if (P.mode == VDI_TAU_FIXED) {
-        gm = P.tau;
-        int c1[1];
-        c_scan<1, true>(rd, total, P.inv_ref, &gm, P.out_n, 1 << 30, o, c1);
-        count = c1[0];
-    } else {
-        // bisection, two levels per scan
-        float lo = 0.0f, hi = P.gmax;
-        int level = 0;
-        while (level + 2 <= P.iters) {
-            float m = 0.5f * (lo + hi);
-            float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
-            int c3[3];
-            c_scan<3, false>(rd, total, P.inv_ref, g3, 0, P.out_n, o, c3);
-            if (c3[0] <= P.out_n) {
-                hi = m;
-                if (c3[1] <= P.out_n) hi = g3[1];
-                else lo = g3[1];
-            } else {
-                lo = m;
-                if (c3[2] <= P.out_n) hi = g3[2];
-                else lo = g3[2];
-            }
-            level += 2;
-        }
-        if (level < P.iters) {
-            float m = 0.5f * (lo + hi);
-            int c1[1];
-            c_scan<1, false>(rd, total, P.inv_ref, &m, 0, P.out_n, o, c1);
-            if (c1[0] <= P.out_n) hi = m;
-            else lo = m;
-        }
-        gm = hi;
-        int c1[1];
-        c_scan<1, true>(rd, total, P.inv_ref, &gm, 0, 1 << 30, o, c1);
-        count = c1[0];
-    }
-    if (count > P.out_n) count = P.out_n;
-    for (int j = count; j < P.out_n; ++j) {
-        size_t slot = (size_t)j * P.npix + p;
-        P.out_color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        P.out_depth[slot] = make_float2(0.0f, 0.0f);
-    }
-    P.out_count[p] = count;
-    if (P.out_gamma) P.out_gamma[p] = gm;
+    resegment<false>(P, rd, total, p);
 }
 
 __global__ __launch_bounds__(64) void composite_kernel(CompParams P)
@@ -414,6 +593,32 @@ __global__ __launch_bounds__(64) void composite_kernel(CompParams P)
     __syncthreads();
     const uint32_t p = blockIdx.x * kWave + t;
     if (p < P.npix) composite_pixel(P, lds_raw, t, p);
+}
+
+// Depth-disjoint path over all pixels; the others are queued.
+__global__ __launch_bounds__(64) void composite_cat_kernel(CompParams P)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int t = threadIdx.x;
+    setup_inputs(P, lds_raw, t);
+    __syncthreads();
+    const uint32_t p = blockIdx.x * kWave + t;
+    if (p >= P.npix) return;
+    const bool done = composite_pixel_cat(P, lds_raw, t, p);
+    const int pos = wave_append(P.q_count, !done);
+    if (!done) P.q_list[pos] = (int)p;
+}
+
+// General merge over the queued pixels (grid-stride).
+__global__ __launch_bounds__(64) void composite_queue_kernel(CompParams P)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int t = threadIdx.x;
+    setup_inputs(P, lds_raw, t);
+    __syncthreads();
+    const uint32_t n = (uint32_t)*P.q_count;
+    for (uint32_t idx = blockIdx.x * kWave + t; idx < n; idx += gridDim.x * kWave)
+        composite_pixel(P, lds_raw, t, (uint32_t)P.q_list[idx]);
 }
 
 // ---------------------------------------------------------------- batched (persistent)
@@ -450,11 +655,45 @@ __global__ __launch_bounds__(64) void batch_kernel(const CompParams* __restrict_
         if (t == 0 && t_start_end) atomicMin(&t_start_end[2 * job], (unsigned long long)wall_clock64());
         for (uint32_t base = td.y; base < td.y + npx; base += kWave) {
             const uint32_t p = base + t;
-            if (p < td.y + npx && p < P.npix) composite_pixel(P, lds_raw, t, p);
+            if (p < td.y + npx && p < P.npix) {
+                const bool done = composite_pixel_cat(P, lds_raw, t, p);
+                const int pos = wave_append(P.q_count, !done);
+                if (!done) P.q_list[pos] = (int)p;
+            }
         }
         if (t == 0 && t_start_end) atomicMax(&t_start_end[2 * job + 1], (unsigned long long)wall_clock64());
         __syncthreads();
     }
+}
+
+// Second phase of a batch: the general merge for every job's queued pixels
+// (all pixels of jobs with more inputs than the depth-disjoint path takes).
+// Every block walks the jobs in order; within a job, a grid-stride loop.
+__global__ __launch_bounds__(64) void batch_queue_kernel(const CompParams* __restrict__ jobs, int n_jobs,
+                                                         unsigned long long* t_start_end)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int t = threadIdx.x;
+    for (int j = 0; j < n_jobs; ++j) {
+        const CompParams& P = jobs[j];
+        const bool all = P.k > kCatMaxInputs;
+        const uint32_t n = all ? P.npix : (uint32_t)*P.q_count;
+        if (blockIdx.x * kWave >= n) continue;   // uniform in the block
+        __syncthreads();                         // the previous job's table is no longer read
+        setup_inputs(P, lds_raw, t);
+        __syncthreads();
+        if (t == 0 && t_start_end && all) atomicMin(&t_start_end[2 * j], (unsigned long long)wall_clock64());
+        for (uint32_t idx = blockIdx.x * kWave + t; idx < n; idx += gridDim.x * kWave)
+            composite_pixel(P, lds_raw, t, all ? idx : (uint32_t)P.q_list[idx]);
+        __syncthreads();
+        if (t == 0 && t_start_end) atomicMax(&t_start_end[2 * j + 1], (unsigned long long)wall_clock64());
+    }
+}
+
+__global__ void fill_i32n_kernel(int* p, int v, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 __global__ void fill_u64_kernel(unsigned long long* p, unsigned long long lo_val, unsigned long long hi_val, int n)
@@ -465,14 +704,18 @@ __global__ void fill_u64_kernel(unsigned long long* p, unsigned long long lo_val
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v) { p[threadIdx.x] = v; }
 
-void launch_batch(const CompParams* jobs, const uint2* tiles, uint32_t n_tiles, uint32_t* head,
-                  unsigned long long* t_se, int n_jobs, size_t lds, int grid, hipStream_t s)
+void launch_batch(const CompParams* jobs, const uint2* tiles, uint32_t n_tiles, uint32_t* head, int* q_counts,
+                  unsigned long long* t_se, int n_jobs, size_t lds_cat, int grid_cat, size_t lds_gen, int grid_gen,
+                  hipStream_t s)
 {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(1), 0, s, head, 0u);
+    hipLaunchKernelGGL(fill_i32n_kernel, dim3((n_jobs + 255) / 256), dim3(256), 0, s, q_counts, 0, n_jobs);
     if (t_se)
         hipLaunchKernelGGL(fill_u64_kernel, dim3((2 * n_jobs + 255) / 256), dim3(256), 0, s, t_se, ~0ull, 0ull,
                            2 * n_jobs);
-    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kWave), lds, s, jobs, tiles, n_tiles, head, t_se);
+    if (n_tiles)
+        hipLaunchKernelGGL(batch_kernel, dim3(grid_cat), dim3(kWave), lds_cat, s, jobs, tiles, n_tiles, head, t_se);
+    hipLaunchKernelGGL(batch_queue_kernel, dim3(grid_gen), dim3(kWave), lds_gen, s, jobs, n_jobs, t_se);
 }
 
 size_t composite_lds_bytes(int k, int seq_cap)
@@ -481,11 +724,20 @@ size_t composite_lds_bytes(int k, int seq_cap)
     return sizeof(InLds) * kMaxInputs + (size_t)kWave * (sb + 14 * (size_t)k);
 }
 
-void launch_composite(const CompParams& P, hipStream_t s)
+size_t cat_lds_bytes(int k) { return sizeof(InLds) * kMaxInputs + (size_t)kWave * 8 * (size_t)k; }
+
+void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
 {
-    size_t lds = composite_lds_bytes(P.k, P.seq_cap);
-    dim3 grid((P.npix + kWave - 1) / kWave);
-    hipLaunchKernelGGL(composite_kernel, grid, dim3(kWave), lds, s, P);
+    const size_t lds = composite_lds_bytes(P.k, P.seq_cap);
+    const unsigned blocks = (P.npix + kWave - 1) / kWave;
+    if (P.k > kCatMaxInputs) {
+        hipLaunchKernelGGL(composite_kernel, dim3(blocks), dim3(kWave), lds, s, P);
+        return;
+    }
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(1), 0, s, (uint32_t*)P.q_count, 0u);
+    hipLaunchKernelGGL(composite_cat_kernel, dim3(blocks), dim3(kWave), cat_lds_bytes(P.k), s, P);
+    const unsigned g2 = std::max(1u, std::min(blocks, (unsigned)grid_general));
+    hipLaunchKernelGGL(composite_queue_kernel, dim3(g2), dim3(kWave), lds, s, P);
 }
 
 // ---------------------------------------------------------------- rendering

@@ -17,8 +17,9 @@ struct GenSeg {
     float A;            // accumulated opacity (added up, exact for thin segments)
     float T;            // transmittance (multiplied)
     float lT;           // log2 of the transmittance (added up)
-    int kf, kb, kbt;    // first sample, one past the last, one past the last non-transparent
-    int open;
+    float nL;           // samples covered, as a float (kb - kf)
+    int kf, kbt;        // first sample, one past the last non-transparent
+    bool open;
 };
 
 struct GenOut {
@@ -44,7 +45,7 @@ __device__ inline void gen_close(GenSeg& S, int& count, const GenOut& o, const R
         o.depth[slot] = make_float2(f, b);
     }
     ++count;
-    S.open = 0;
+    S.open = false;
 }
 
 template <typename VT>
@@ -59,12 +60,13 @@ __device__ inline float4 gen_sample(const VT* data, const BrickGeo& g, const Ray
 
 __device__ inline void gen_seg_init(GenSeg& S)
 {
-    S.open = 0;
+    S.open = false;
     S.c0 = S.c1 = S.c2 = 0.0f;
     S.A = 0.0f;
     S.T = 1.0f;
     S.lT = 0.0f;
-    S.kf = S.kb = S.kbt = 0;
+    S.nL = 1.0f;
+    S.kf = S.kbt = 0;
 }
 
 // A classified sample prepared once and shared by every segmenter state.
@@ -95,44 +97,34 @@ __device__ inline GenSample gen_prep(float4 c, float l_step, bool unit)
 // One sample through the segmenter (Eq. 1 test, then merge or close/open).
 // The test gamma < |C a_S / A - e| is evaluated as gamma^2 A^2 < |C a_S - e A|^2
 // (A > 0), with a_S = 1 - 2^(log2(T) / L) the open supersegment's per-step
-// opacity.
+// opacity.  The state update is written as selects: a closed state's fields
+// are don't-cares (its test result is masked by `open`), so every lane runs
+// the same instruction stream whatever its decisions.
 template <bool WRITE>
 __device__ inline void gen_step(GenSeg& S, int& count, const GenOut& o, const Ray& r, float step, float l_step,
                                 float g2, int cap, int k, const GenSample& q)
 {
-    if (S.open) {
-        float L = (float)(S.kb - S.kf) * l_step;
-        float aS = 1.0f - hw_exp2(S.lT * hw_rcp(L));
-        float d0 = S.c0 * aS - q.e0 * S.A;
-        float d1 = S.c1 * aS - q.e1 * S.A;
-        float d2 = S.c2 * aS - q.e2 * S.A;
-        float dd = d0 * d0 + d1 * d1 + d2 * d2;
-        bool may_close = cap <= 0 || count < cap - 1;
-        if (may_close && g2 * (S.A * S.A) < dd) {
-            gen_close<WRITE>(S, count, o, r, step, l_step);
-        } else {
-            float w = S.T * q.at;
-            S.c0 = fmaf(w, q.c.x, S.c0);
-            S.c1 = fmaf(w, q.c.y, S.c1);
-            S.c2 = fmaf(w, q.c.z, S.c2);
-            S.A += w;
-            S.T *= q.Te;
-            S.lT += q.lg;
-            S.kb = k + 1;
-            if (!q.transparent) S.kbt = k + 1;
-        }
-    }
-    if (!S.open && !q.transparent) {
-        S.open = 1;
-        S.kf = k;
-        S.kb = S.kbt = k + 1;
-        S.c0 = q.c.x * q.at;
-        S.c1 = q.c.y * q.at;
-        S.c2 = q.c.z * q.at;
-        S.A = q.at;
-        S.T = q.Te;
-        S.lT = q.lg;
-    }
+    const float aS = 1.0f - hw_exp2(S.lT * hw_rcp(S.nL * l_step));
+    const float d0 = S.c0 * aS - q.e0 * S.A;
+    const float d1 = S.c1 * aS - q.e1 * S.A;
+    const float d2 = S.c2 * aS - q.e2 * S.A;
+    const float dd = d0 * d0 + d1 * d1 + d2 * d2;
+    const bool may_close = cap <= 0 || count < cap - 1;
+    const bool close = S.open & may_close & (g2 * (S.A * S.A) < dd);
+    if (WRITE && close) gen_close<true>(S, count, o, r, step, l_step);
+    else count += close ? 1 : 0;
+    const bool merge = S.open & !close;
+    const float w = S.T * q.at;
+    S.c0 = merge ? fmaf(w, q.c.x, S.c0) : q.c.x * q.at;
+    S.c1 = merge ? fmaf(w, q.c.y, S.c1) : q.c.y * q.at;
+    S.c2 = merge ? fmaf(w, q.c.z, S.c2) : q.c.z * q.at;
+    S.A = merge ? S.A + w : q.at;
+    S.T = merge ? S.T * q.Te : q.Te;
+    S.lT = merge ? S.lT + q.lg : q.lg;
+    S.nL = merge ? S.nL + 1.0f : 1.0f;
+    S.kf = merge ? S.kf : k;
+    S.kbt = (merge & q.transparent) ? S.kbt : k + 1;
+    S.open = merge | !q.transparent;
 }
 
 // One pass of the segmenter over samples [k0, k1) at threshold gamma.
@@ -184,13 +176,13 @@ __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float 
     for (int k = k0; k < k1; ++k) {
         const GenSample q = gen_prep(gen_sample<VT>(data, g, r, step, k, tf, entries), l_step, unit);
         n_opaque += q.transparent ? 0 : 1;
+        // a frozen state (count above limit) keeps stepping: its count only
+        // grows, so its outcome stays decided
         bool live = false;
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-            if (cnt[j] <= limit) {
-                gen_step<false>(S[j], cnt[j], none, r, step, l_step, g2[j], 0, k, q);
-                live |= cnt[j] <= limit;
-            }
+            gen_step<false>(S[j], cnt[j], none, r, step, l_step, g2[j], 0, k, q);
+            live |= cnt[j] <= limit;
         }
         if (!live) break;
     }
@@ -290,13 +282,7 @@ __global__ __launch_bounds__(256) void gen_kernel(GenParams P, GenBricks B)
     const uint32_t pix = (uint32_t)y * (uint32_t)P.cam.width + (uint32_t)x;
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
 
-    BrickGeo g;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        g.n[a] = P.n[a];
-        g.dlo[a] = br.dlo[a];
-        g.ddim[a] = br.ddim[a];
-    }
+    const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
     const VT* data = (const VT*)br.data;
     Ray r = make_ray(P.cam, x, y);
     int ns = ray_samples(r, P.step);
@@ -369,14 +355,6 @@ void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B
 // bins agree exactly), the number of non-transparent samples and the count at
 // the smallest threshold the bisection can return (saturating at N+1).
 
-__device__ inline float tf_alpha_exact(const float4* tf, int entries, float s)
-{
-    int i;
-    float w;
-    tf_coord(s, entries, i, w);
-    return lerp_exact(tf[i].w, tf[i + 1].w, w);
-}
-
 template <typename VT>
 __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
@@ -395,13 +373,7 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
     const size_t ray = (size_t)brick * npix + (uint32_t)y * (uint32_t)P.cam.width + (uint32_t)x;
 
-    BrickGeo g;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        g.n[a] = P.n[a];
-        g.dlo[a] = br.dlo[a];
-        g.ddim[a] = br.ddim[a];
-    }
+    const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
     const VT* data = (const VT*)br.data;
     Ray r = make_ray(P.cam, x, y);
     int ns = ray_samples(r, P.step);
@@ -419,7 +391,8 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
         float t = sample_t(r, k, P.step);
         float p[3] = { sample_coord(r, t, 0), sample_coord(r, t, 1), sample_coord(r, t, 2) };
         float sv = trilinear<VT>(data, g, p);
-        float a32 = tf_alpha_exact(tf_s, P.tf_entries, sv);
+        const float4 cs = tf_lookup(tf_s, P.tf_entries, sv);
+        const float a32 = cs.w;   // the transfer function's opacity, as in the histogram's definition
         if (a32 > 0.0f) {
             int j = (int)ceilf(64.0f * a32) - 1;
             j = j > 63 ? 63 : (j < 0 ? 0 : j);
@@ -427,14 +400,24 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
             ++m;
         }
         if (count <= P.max_n) {
-            const GenSample q = gen_prep(tf_lookup(tf_s, P.tf_entries, sv), P.l_step, unit);
+            const GenSample q = gen_prep(cs, P.l_step, unit);
             gen_step<false>(S, count, none, r, P.step, P.l_step, g2, 0, k, q);
         }
     }
     if (S.open && count <= P.max_n) gen_close<false>(S, count, none, r, P.step, P.l_step);
     Lb.nnt[ray] = m;
     Lb.cmax[ray] = count;
-    uint32_t* hrow = (uint32_t*)(Lb.hist + ray * 64);
+    size_t row = ray;
+    if (Lb.sv_list) {
+        // only rays the regressor serves (more than N non-transparent samples)
+        // get a histogram row, compacted in order of arrival
+        const bool served = k1 > k0 && m > P.max_n;
+        const int pos = wave_append(Lb.sv_count, served);
+        if (!served) return;
+        Lb.sv_list[pos] = (int)ray;
+        row = (size_t)pos;
+    }
+    uint32_t* hrow = (uint32_t*)(Lb.hist + row * 64);
     for (int j = 0; j < 64; j += 2) {
         float f0 = (float)hs[j][threadIdx.x] / Lb.s_ref;
         float f1 = (float)hs[j + 1][threadIdx.x] / Lb.s_ref;
@@ -442,24 +425,60 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
     }
 }
 
-// Add `inc` (0 or 1 per lane) to *ctr with one atomic per wavefront; returns
-// this lane's position among the wave's incrementing lanes plus the old value
-// (meaningful for lanes with inc == 1).
-__device__ inline int wave_append(int* ctr, bool inc)
+// In-band test of the learned path: with m = min(N, cmax), a count c is kept
+// iff m - floor(tol * m) <= c <= N.
+__device__ inline int band_lo(int max_n, int cmax, float tol)
 {
-    const unsigned long long m = __ballot(inc);
-    const int n = __popcll(m);
-    const int lane = threadIdx.x & 63;
-    const int leader = m ? (__ffsll((long long)m) - 1) : 0;
-    int base = 0;
-    if (n && lane == leader) base = atomicAdd(ctr, n);
-    base = __shfl(base, leader, 64);
-    const int rank = __popcll(m & ((1ull << lane) - 1ull));
-    return base + rank;
+    const int m = min(max_n, cmax);
+    return m - (int)floorf(tol * (float)m + 1e-6f);
 }
 
-// Generation at the regressed threshold, with the acceptance test; rays
-// that fail it are queued (per brick) for the plain bisection.
+// Largest in-band count among NC candidates (ties: the first listed); -1 if none.
+template <int NC>
+__device__ inline int pick_in_band(const int* c, int max_n, int lo)
+{
+    int best = -1;
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+        if (c[j] <= max_n && c[j] >= lo && (best < 0 || c[j] > c[best])) best = j;
+    return best;
+}
+
+// Writes a finished list's unused slots, count and threshold.
+__device__ inline void finish_list(const GenBrick& br, uint32_t pix, uint32_t npix, int max_n, int c, float gm)
+{
+    for (int j = c; j < max_n; ++j) {
+        size_t slot = (size_t)j * npix + pix;
+        br.color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        br.depth[slot] = make_float2(0.0f, 0.0f);
+    }
+    br.count[pix] = c;
+    if (br.gamma) br.gamma[pix] = gm;
+}
+
+struct RayRun {
+    Ray r;
+    int k0, k1;
+};
+
+__device__ inline RayRun ray_run(const GenParams& P, const GenBrick& br, int x, int y)
+{
+    RayRun q;
+    q.r = make_ray(P.cam, x, y);
+    int ns = ray_samples(q.r, P.step);
+    q.k0 = q.k1 = 0;
+    if (ns > 0) owned_run(q.r, P.step, ns, P.n, br.lo, br.hi, q.k0, q.k1);
+    return q;
+}
+
+// Round one of the learned threshold.  The regressed log2 threshold y and four
+// neighbours, y + {0, -1/4, 1/4, -1/2, 1/2} (clamped to the bisection's range),
+// share one sampling scan; the in-band candidate with the largest count is
+// kept.  Otherwise, if two candidates adjacent in threshold order straddle
+// the band (count above N at the smaller, below the band at the larger), the
+// ray is queued for round two inside that bracket (the straddling pair
+// nearest the regressed value; ties: the smaller thresholds); else it is
+// queued for the plain bisection.
 template <typename VT>
 __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
@@ -477,72 +496,116 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
     const size_t ray = (size_t)brick * npix + pix;
 
-    BrickGeo g;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        g.n[a] = P.n[a];
-        g.dlo[a] = br.dlo[a];
-        g.ddim[a] = br.ddim[a];
-    }
+    const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
     const VT* data = (const VT*)br.data;
-    Ray r = make_ray(P.cam, x, y);
-    int ns = ray_samples(r, P.step);
-    int k0 = 0, k1 = 0;
-    if (ns > 0) owned_run(r, P.step, ns, P.n, br.lo, br.hi, k0, k1);
+    const RayRun q = ray_run(P, br, x, y);
 
     const float gmin = ldexpf(P.gmax, -P.iters);
     const int m = Lb.nnt[ray];
     GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
     float gm = gmin;
     int c = 0;
-    int kind = 0;   // 0 kept, 1 all-feasible shortcut, 2 fallback, 3 empty
-    if (k1 <= k0 || m == 0) {
-        kind = 3;
+    int kind = 0;   // LEARN_KEPT, LEARN_SHORTCUT, LEARN_FALLBACK, LEARN_EMPTY or LEARN_REFINE
+    float2 bracket = make_float2(0.0f, 0.0f);
+    if (q.k1 <= q.k0 || m == 0) {
+        kind = LEARN_EMPTY;
     } else if (m <= P.max_n) {
         // every threshold is feasible: the bisection would return its lower end
-        c = gen_pass<VT, true, false>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gmin, 0, 1 << 30,
-                                      o, nullptr);
-        kind = 1;
+        c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, gmin, 0,
+                                      1 << 30, o, nullptr);
+        kind = LEARN_SHORTCUT;
     } else {
-        // the regressed threshold and four neighbours (x 2^{-1/2, -1/4, 1/4, 1/2})
-        // share one sampling scan; the in-band candidate with the largest
-        // count is kept (ties: the one listed first)
         const float lg_hi = log2f(P.gmax), lg_lo = lg_hi - (float)P.iters;
         const float yv = Lb.y[ray];
         const float dl[5] = { 0.0f, -0.25f, 0.25f, -0.5f, 0.5f };
-        float g5[5];
+        float y5[5], g5[5];
         int c5[5];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) g5[j] = exp2f(fminf(fmaxf(yv + dl[j], lg_lo), lg_hi));
-        gen_scan<VT, 5>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, g5, P.max_n, c5, nullptr);
-        const int target = min(P.max_n, Lb.cmax[ray]);
-        const int lo = target - (int)floorf(Lb.tol * (float)target + 1e-6f);
-        int best = -1;
-#pragma unroll
-        for (int j = 0; j < 5; ++j)
-            if (c5[j] <= P.max_n && c5[j] >= lo && (best < 0 || c5[j] > c5[best])) best = j;
-        if (best < 0) {
-            kind = 2;
-        } else {
+        for (int j = 0; j < 5; ++j) {
+            y5[j] = fminf(fmaxf(yv + dl[j], lg_lo), lg_hi);
+            g5[j] = exp2f(y5[j]);
+        }
+        gen_scan<VT, 5>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, g5, P.max_n, c5, nullptr);
+        const int lo = band_lo(P.max_n, Lb.cmax[ray], Lb.tol);
+        const int best = pick_in_band<5>(c5, P.max_n, lo);
+        if (best >= 0) {
             gm = g5[best];
-            c = gen_pass<VT, true, false>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, 0, 1 << 30,
-                                          o, nullptr);
+            c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, gm, 0,
+                                          1 << 30, o, nullptr);
+            kind = LEARN_KEPT;
+        } else {
+            // candidates in threshold order: d = -1/2, -1/4, 0, 1/4, 1/2
+            const int ord[5] = { 3, 1, 0, 2, 4 };
+            int pick = -1;
+            float pick_d = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int a = ord[t], b = ord[t + 1];
+                const float d = fabsf(dl[a] + dl[b]);
+                if (c5[a] > P.max_n && c5[b] < lo && (pick < 0 || d < pick_d)) {
+                    pick = t;
+                    pick_d = d;
+                    bracket = make_float2(y5[a], y5[b]);
+                }
+            }
+            kind = pick >= 0 ? LEARN_REFINE : LEARN_FALLBACK;
         }
     }
     // every active lane of the wave reaches this point (lanes of pixels
     // outside the image returned at the top and take no part in the ballots)
-    const int pos = wave_append(&Lb.fb_count[brick], kind == 2);
-    if (kind == 2) Lb.fb_list[(size_t)brick * npix + pos] = (int)pix;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) wave_append(&Lb.stats[q], kind == q);
-    if (kind == 2) return;
-    for (int j = c; j < P.max_n; ++j) {
-        size_t slot = (size_t)j * npix + pix;
-        br.color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        br.depth[slot] = make_float2(0.0f, 0.0f);
+    const int fpos = wave_append(&Lb.fb_count[brick], kind == LEARN_FALLBACK);
+    if (kind == LEARN_FALLBACK) Lb.fb_list[(size_t)brick * npix + fpos] = (int)pix;
+    const int rpos = wave_append(&Lb.rf_count[brick], kind == LEARN_REFINE);
+    if (kind == LEARN_REFINE) {
+        Lb.rf_list[(size_t)brick * npix + rpos] = (int)pix;
+        Lb.rf_y[(size_t)brick * npix + rpos] = bracket;
     }
-    br.count[pix] = c;
-    if (br.gamma) br.gamma[pix] = gm;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) wave_append(&Lb.stats[t], kind == t);
+    if (kind == LEARN_FALLBACK || kind == LEARN_REFINE) return;
+    finish_list(br, pix, npix, P.max_n, c, gm);
+}
+
+// Round two for the queued rays of each brick: five thresholds evenly inside
+// the bracket (log2 y_a + (y_b - y_a) t / 6, t = 1..5) in one scan; the in-band
+// one with the largest count is kept (ties: smaller t), else the ray is
+// queued for the plain bisection.
+template <typename VT>
+__global__ __launch_bounds__(256) void refine_kernel(GenParams P, GenBricks B, LearnBufs Lb)
+{
+    __shared__ float4 tf_s[VDI_MAX_TF];
+    for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
+    __syncthreads();
+    const GenBrick& br = B.b[blockIdx.z];
+    const int brick = B.first + blockIdx.z;
+    const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
+    const uint32_t n_q = (uint32_t)Lb.rf_count[brick];
+    const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
+    const VT* data = (const VT*)br.data;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n_q; idx += gridDim.x * blockDim.x) {
+        const uint32_t pix = (uint32_t)Lb.rf_list[(size_t)brick * npix + idx];
+        const float2 yab = Lb.rf_y[(size_t)brick * npix + idx];
+        const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
+        const RayRun q = ray_run(P, br, x, y);
+        float g5[5];
+        int c5[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) g5[t] = exp2f(yab.x + (yab.y - yab.x) * (float)(t + 1) * (1.0f / 6.0f));
+        gen_scan<VT, 5>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, g5, P.max_n, c5, nullptr);
+        const int lo = band_lo(P.max_n, Lb.cmax[(size_t)brick * npix + pix], Lb.tol);
+        const int best = pick_in_band<5>(c5, P.max_n, lo);
+        const int fpos = wave_append(&Lb.fb_count[brick], best < 0);
+        wave_append(&Lb.stats[LEARN_REFINED], best >= 0);
+        wave_append(&Lb.stats[LEARN_FALLBACK], best < 0);
+        if (best < 0) {
+            Lb.fb_list[(size_t)brick * npix + fpos] = (int)pix;
+            continue;
+        }
+        GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
+        const int c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries,
+                                                g5[best], 0, 1 << 30, o, nullptr);
+        finish_list(br, pix, npix, P.max_n, c, g5[best]);
+    }
 }
 
 // Plain bisection for the queued rays of each brick.
@@ -555,37 +618,23 @@ __global__ __launch_bounds__(256) void fallback_kernel(GenParams P, GenBricks B,
     const GenBrick& br = B.b[blockIdx.z];
     const int brick = B.first + blockIdx.z;
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
-    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (uint32_t)Lb.fb_count[brick]) return;
-    const uint32_t pix = (uint32_t)Lb.fb_list[(size_t)brick * npix + idx];
-    const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
-
-    BrickGeo g;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        g.n[a] = P.n[a];
-        g.dlo[a] = br.dlo[a];
-        g.ddim[a] = br.ddim[a];
-    }
+    const uint32_t n_q = (uint32_t)Lb.fb_count[brick];
+    const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
     const VT* data = (const VT*)br.data;
-    Ray r = make_ray(P.cam, x, y);
-    int ns = ray_samples(r, P.step);
-    int k0 = 0, k1 = 0;
-    if (ns > 0) owned_run(r, P.step, ns, P.n, br.lo, br.hi, k0, k1);
-    float gm = ldexpf(P.gmax, -P.iters);
-    int c = 0;
-    GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
-    if (k1 > k0) {
-        gen_search<VT>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, P, gm, c, false);
-        c = gen_pass<VT, true>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, 0, 1 << 30, o, nullptr);
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n_q; idx += gridDim.x * blockDim.x) {
+        const uint32_t pix = (uint32_t)Lb.fb_list[(size_t)brick * npix + idx];
+        const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
+        const RayRun q = ray_run(P, br, x, y);
+        float gm = ldexpf(P.gmax, -P.iters);
+        int c = 0;
+        GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
+        if (q.k1 > q.k0) {
+            gen_search<VT>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, P, gm, c, false);
+            c = gen_pass<VT, true>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, gm, 0, 1 << 30,
+                                   o, nullptr);
+        }
+        finish_list(br, pix, npix, P.max_n, c < P.max_n ? c : P.max_n, gm);
     }
-    for (int j = c; j < P.max_n; ++j) {
-        size_t slot = (size_t)j * npix + pix;
-        br.color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        br.depth[slot] = make_float2(0.0f, 0.0f);
-    }
-    br.count[pix] = c < P.max_n ? c : P.max_n;
-    if (br.gamma) br.gamma[pix] = gm;
 }
 
 template <typename VT>
@@ -595,10 +644,14 @@ static void launch_learned_t(int phase, const GenParams& P, const GenBricks& B, 
     dim3 grid((P.cam.width + 15) / 16, (P.cam.height + 15) / 16, nb);
     if (phase == 0) hipLaunchKernelGGL(features_kernel<VT>, grid, dim3(256), 0, s, P, B, L);
     if (phase == 1) hipLaunchKernelGGL(learned_kernel<VT>, grid, dim3(256), 0, s, P, B, L);
-    if (phase == 2) {
+    if (phase == 2 || phase == 3) {
+        // queue-driven: grid-stride over each brick's queue, enough blocks to
+        // fill the device whatever the queue length turns out to be
         size_t npix = (size_t)P.cam.width * P.cam.height;
-        dim3 g2((unsigned)((npix + 255) / 256), 1, nb);
-        hipLaunchKernelGGL(fallback_kernel<VT>, g2, dim3(256), 0, s, P, B, L);
+        unsigned bx = (unsigned)std::min<size_t>((npix + 255) / 256, (size_t)L.blocks_per_brick);
+        dim3 g2(bx, 1, nb);
+        if (phase == 2) hipLaunchKernelGGL(refine_kernel<VT>, g2, dim3(256), 0, s, P, B, L);
+        else hipLaunchKernelGGL(fallback_kernel<VT>, g2, dim3(256), 0, s, P, B, L);
     }
 }
 

@@ -232,10 +232,6 @@ __device__ inline void owned_run(const Ray& r, float step, int ns, const int n[3
 
 // ---------------------------------------------------------------- reconstruction
 
-template <typename VT> __device__ inline float load_voxel(const VT* p, size_t i);
-template <> __device__ inline float load_voxel<float>(const float* p, size_t i) { return p[i]; }
-template <> __device__ inline float load_voxel<__half>(const __half* p, size_t i) { return __half2float(p[i]); }
-
 // a + w (b - a) with one fused multiply-add.
 __device__ inline float lerp_exact(float a, float b, float w)
 {
@@ -244,28 +240,62 @@ __device__ inline float lerp_exact(float a, float b, float w)
 }
 
 struct BrickGeo {
-    int n[3];       // global volume dims
+    float nf[3];    // global volume dims
     int dlo[3];     // global index of the first data voxel
-    int ddim[3];    // data box dims
+    int clo[3];     // index range of the clamped stencil, relative to dlo:
+    int chi[3];     //   clamp(clamp(i, 0, n-1) - dlo, 0, ddim-1) = clamp(i - dlo, clo, chi)
+    uint32_t sx2;   // 1 if the x extent allows paired loads (ddim[0] >= 2)
+    int xmax;       // ddim[0] - 2: last x of a paired load
+    uint32_t sy, sz;  // element strides of y and z
 };
+
+// Geometry of a brick whose data box starts at global voxel dlo with extent
+// ddim, inside a volume of n voxels (the two boxes intersect).
+__device__ inline BrickGeo make_geo(const int n[3], const int dlo[3], const int ddim[3])
+{
+    BrickGeo g;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g.nf[a] = (float)n[a];
+        g.dlo[a] = dlo[a];
+        g.clo[a] = -dlo[a] > 0 ? -dlo[a] : 0;
+        g.chi[a] = (n[a] - 1 - dlo[a]) < (ddim[a] - 1) ? (n[a] - 1 - dlo[a]) : (ddim[a] - 1);
+    }
+    g.sx2 = ddim[0] >= 2 ? 1u : 0u;
+    g.xmax = ddim[0] - 2;
+    g.sy = (uint32_t)ddim[0];
+    g.sz = (uint32_t)ddim[0] * (uint32_t)ddim[1];
+    return g;
+}
 
 // Two x-adjacent voxels (p[0], p[1]) with one load (4-byte or 2-byte
 // alignment; gfx950 allows unaligned dword loads from global memory).
 typedef float vdi_f2u __attribute__((ext_vector_type(2), aligned(4)));
 typedef unsigned short vdi_h2u __attribute__((ext_vector_type(2), aligned(2)));
 
-template <typename VT> __device__ inline void load_pair(const VT* p, float& a, float& b);
-template <> __device__ inline void load_pair<float>(const float* p, float& a, float& b)
+// Loads at a 32-bit byte offset from a wave-uniform base (a brick's data
+// occupies less than 4 GiB; checked on the host).
+template <typename VT> __device__ inline void load_pair(const VT* base, uint32_t i, float& a, float& b);
+template <> __device__ inline void load_pair<float>(const float* base, uint32_t i, float& a, float& b)
 {
-    vdi_f2u v = *(const vdi_f2u*)p;
+    vdi_f2u v = *(const vdi_f2u*)((const char*)base + i * 4u);
     a = v.x;
     b = v.y;
 }
-template <> __device__ inline void load_pair<__half>(const __half* p, float& a, float& b)
+template <> __device__ inline void load_pair<__half>(const __half* base, uint32_t i, float& a, float& b)
 {
-    vdi_h2u v = *(const vdi_h2u*)p;
+    vdi_h2u v = *(const vdi_h2u*)((const char*)base + i * 2u);
     a = __half2float(__ushort_as_half(v.x));
     b = __half2float(__ushort_as_half(v.y));
+}
+template <typename VT> __device__ inline float load_one(const VT* base, uint32_t i);
+template <> __device__ inline float load_one<float>(const float* base, uint32_t i)
+{
+    return *(const float*)((const char*)base + i * 4u);
+}
+template <> __device__ inline float load_one<__half>(const __half* base, uint32_t i)
+{
+    return __half2float(*(const __half*)((const char*)base + i * 2u));
 }
 
 // Trilinear reconstruction on the global voxel grid from a halo'd brick.
@@ -279,39 +309,38 @@ __device__ inline float trilinear(const VT* data, const BrickGeo& g, const float
     float w[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float u = __builtin_fmaf(p[a], (float)g.n[a], -0.5f);
+        float u = __builtin_fmaf(p[a], g.nf[a], -0.5f);
         float f = floorf(u);
         w[a] = u - f;
-        int ii = (int)f;
-        i0[a] = clampi(clampi(ii, 0, g.n[a] - 1) - g.dlo[a], 0, g.ddim[a] - 1);
-        i1[a] = clampi(clampi(ii + 1, 0, g.n[a] - 1) - g.dlo[a], 0, g.ddim[a] - 1);
+        int ii = (int)f - g.dlo[a];
+        i0[a] = clampi(ii, g.clo[a], g.chi[a]);
+        i1[a] = clampi(ii + 1, g.clo[a], g.chi[a]);
     }
-    // 32-bit offsets: a brick's data holds fewer than 2^31 voxels (checked on the host)
-    const uint32_t sy = (uint32_t)g.ddim[0], sz = (uint32_t)g.ddim[0] * (uint32_t)g.ddim[1];
-    const uint32_t r00 = i0[1] * sy + i0[2] * sz, r10 = i1[1] * sy + i0[2] * sz;
-    const uint32_t r01 = i0[1] * sy + i1[2] * sz, r11 = i1[1] * sy + i1[2] * sz;
+    const uint32_t r00 = i0[1] * g.sy + i0[2] * g.sz, r10 = i1[1] * g.sy + i0[2] * g.sz;
+    const uint32_t r01 = i0[1] * g.sy + i1[2] * g.sz, r11 = i1[1] * g.sy + i1[2] * g.sz;
     float v000, v100, v010, v110, v001, v101, v011, v111;
-    if (g.ddim[0] >= 2) {
-        const int xb = i0[0] < g.ddim[0] - 2 ? i0[0] : g.ddim[0] - 2;
+    if (g.sx2) {
+        const int xb = i0[0] < g.xmax ? i0[0] : g.xmax;
         const bool s0 = i0[0] == xb, s1 = i1[0] == xb;
-        float a, b;
-        load_pair<VT>(data + r00 + xb, a, b);
-        v000 = s0 ? a : b;
-        v100 = s1 ? a : b;
-        load_pair<VT>(data + r10 + xb, a, b);
-        v010 = s0 ? a : b;
-        v110 = s1 ? a : b;
-        load_pair<VT>(data + r01 + xb, a, b);
-        v001 = s0 ? a : b;
-        v101 = s1 ? a : b;
-        load_pair<VT>(data + r11 + xb, a, b);
-        v011 = s0 ? a : b;
-        v111 = s1 ? a : b;
+        // all four loads in flight before any is used
+        float a0, b0, a1, b1, a2, b2, a3, b3;
+        load_pair<VT>(data, r00 + xb, a0, b0);
+        load_pair<VT>(data, r10 + xb, a1, b1);
+        load_pair<VT>(data, r01 + xb, a2, b2);
+        load_pair<VT>(data, r11 + xb, a3, b3);
+        v000 = s0 ? a0 : b0;
+        v100 = s1 ? a0 : b0;
+        v010 = s0 ? a1 : b1;
+        v110 = s1 ? a1 : b1;
+        v001 = s0 ? a2 : b2;
+        v101 = s1 ? a2 : b2;
+        v011 = s0 ? a3 : b3;
+        v111 = s1 ? a3 : b3;
     } else {
-        v000 = v100 = load_voxel(data, r00);
-        v010 = v110 = load_voxel(data, r10);
-        v001 = v101 = load_voxel(data, r01);
-        v011 = v111 = load_voxel(data, r11);
+        v000 = v100 = load_one<VT>(data, r00);
+        v010 = v110 = load_one<VT>(data, r10);
+        v001 = v101 = load_one<VT>(data, r01);
+        v011 = v111 = load_one<VT>(data, r11);
     }
     float c00 = lerp_exact(v000, v100, w[0]);
     float c10 = lerp_exact(v010, v110, w[0]);
@@ -370,6 +399,44 @@ __device__ inline float one_minus_exp2(float y)
     if (u == 1.0f) return -y * 0.6931471805599453f;
     if (u == 0.0f) return 1.0f;
     return (1.0f - u) * (y * hw_rcp(hw_log2(u)));
+}
+
+// ---------------------------------------------------------------- global loads
+
+// Loads through pointers the compiler cannot prove global (e.g. read from an
+// LDS table), issued as global rather than flat loads.
+typedef float vdi_gf4 __attribute__((ext_vector_type(4)));
+typedef float vdi_gf2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) vdi_gf4* vdi_gp4;
+typedef const __attribute__((address_space(1))) vdi_gf2* vdi_gp2;
+
+__device__ inline float4 gload(const float4* p, uint32_t i)
+{
+    vdi_gf4 v = ((vdi_gp4)p)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ inline float2 gload(const float2* p, uint32_t i)
+{
+    vdi_gf2 v = ((vdi_gp2)p)[i];
+    return make_float2(v.x, v.y);
+}
+
+// ---------------------------------------------------------------- queues
+
+// Add `inc` (0 or 1 per lane) to *ctr with one atomic per wavefront; returns
+// this lane's position among the wave's incrementing lanes plus the old value
+// (meaningful for lanes with inc == 1).
+__device__ inline int wave_append(int* ctr, bool inc)
+{
+    const unsigned long long m = __ballot(inc);
+    const int n = __popcll(m);
+    const int lane = threadIdx.x & 63;
+    const int leader = m ? (__ffsll((long long)m) - 1) : 0;
+    int base = 0;
+    if (n && lane == leader) base = atomicAdd(ctr, n);
+    base = __shfl(base, leader, 64);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    return base + rank;
 }
 
 // ---------------------------------------------------------------- misc

@@ -44,21 +44,32 @@ struct GenBricks {
 };
 
 // Buffers of the learned-threshold path (indices: brick * npix + pixel).
+// Outcome of a brick-ray on the learned path (indices into LearnBufs::stats
+// up to LEARN_REFINED; LEARN_REFINE marks a ray queued for round two).
+enum { LEARN_KEPT = 0, LEARN_SHORTCUT = 1, LEARN_FALLBACK = 2, LEARN_EMPTY = 3, LEARN_REFINED = 4, LEARN_REFINE = 5 };
+constexpr int kLearnStats = 5;
+
 struct LearnBufs {
-    uint16_t* hist;      // [nb][npix][64] bf16 features
+    uint16_t* hist;      // [nb][npix][64] bf16 features; with sv_list: [served][64], compacted
     int* nnt;            // [nb][npix] non-transparent samples
     int* cmax;           // [nb][npix] count at the smallest threshold (saturates at N+1)
-    const float* y;      // [nb][npix] regressor output, log2(gamma)
-    int* fb_list;        // [nb][npix] queued pixels per brick
+    const float* y;      // [nb][npix] log2(gamma) from the regressor (or the caller)
+    int* fb_list;        // [nb][npix] pixels queued for the bisection, per brick
     int* fb_count;       // [nb]
-    int* stats;          // [4]: accepted, all-feasible shortcut, fallback, empty
+    int* rf_list;        // [nb][npix] pixels queued for round two, per brick
+    float2* rf_y;        // [nb][npix] their log2 brackets
+    int* rf_count;       // [nb]
+    int* sv_list;        // optional [nb*npix]: brick-ray index of each served ray (hist row order)
+    int* sv_count;       // their number
+    int* stats;          // [kLearnStats]
     float s_ref;
     float tol;
+    int blocks_per_brick;  // grid of the queue-driven kernels
 };
 
 // kind: 0 = search + regular write, 1 = search only, 2 = compact write
 void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B, int nb, hipStream_t s);
-// phase 0: features, 1: learned generation + acceptance, 2: fallback bisection
+// phase 0: features, 1: learned round one, 2: round two, 3: fallback bisection
 void launch_learned(int phase, int dtype, const GenParams& P, const GenBricks& B, int nb, const LearnBufs& L,
                     hipStream_t s);
 void launch_rays(const Cam& cam, float step, float* o, float* d, float* tn, float* tf, int* ns, hipStream_t s);
@@ -99,22 +110,34 @@ struct CompParams {
     float* out_gamma;
     int* status;
     int seq_cap;              // merged-list capacity per pixel (sum of input max_n)
+    int* q_list;              // [npix] pixels left to the general merge
+    int* q_count;             // their number
 };
 
-size_t composite_lds_bytes(int k, int seq_cap);
-void launch_composite(const CompParams& P, hipStream_t s);
+// Inputs up to which the depth-disjoint path runs (4-bit list ids).
+constexpr int kCatMaxInputs = 16;
 
-// Persistent batched compositing: tiles[i] = {job | pixels << 16, first pixel}.
-void launch_batch(const CompParams* jobs, const uint2* tiles, uint32_t n_tiles, uint32_t* head,
-                  unsigned long long* t_se, int n_jobs, size_t lds, int grid, hipStream_t s);
+size_t composite_lds_bytes(int k, int seq_cap);   // general merge
+size_t cat_lds_bytes(int k);                      // depth-disjoint path
+// grid_general: blocks of the queue-driven general merge
+void launch_composite(const CompParams& P, int grid_general, hipStream_t s);
+
+// Persistent batched compositing: tiles[i] = {job | pixels << 16, first pixel}
+// for the depth-disjoint path (jobs with k <= kCatMaxInputs), then the general
+// merge over every job's queue (all pixels of jobs with larger k).
+void launch_batch(const CompParams* jobs, const uint2* tiles, uint32_t n_tiles, uint32_t* head, int* q_counts,
+                  unsigned long long* t_se, int n_jobs, size_t lds_cat, int grid_cat, size_t lds_gen, int grid_gen,
+                  hipStream_t s);
 
 // ---------------------------------------------------------------- MLP (learned threshold)
 
 int mlp_params();
 int mlp_act_floats();
 int mlp_rows_per_block();
-void launch_mlp_fwd(const uint16_t* wb, const float* wf, const uint16_t* x, int rows, float* y, float* acts,
-                    hipStream_t s);
+// rows: row count (an upper bound when rows_dev holds the count on the
+// device); out_idx: optional row -> output index map; max_blocks: grid cap
+void launch_mlp_fwd(const uint16_t* wb, const float* wf, const uint16_t* x, int rows, const int* rows_dev,
+                    const int* out_idx, int max_blocks, float* y, float* acts, hipStream_t s);
 void launch_mlp_bwd(const uint16_t* wb, const uint16_t* x, const float* acts, const float* dy, int rows,
                     float* partial, float* grad, hipStream_t s);
 void launch_mlp_adam(float* wf, uint16_t* wb, const float* grad, float* m, float* v, float lr, float b1, float b2,

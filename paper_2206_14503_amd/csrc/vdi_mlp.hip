@@ -57,86 +57,94 @@ __device__ inline bf16x4 load4(const uint16_t* p)
 // acts per row: z1[128] f32, z2[128] f32, h1[128] bf16 (64 words), h2[128] bf16 (64 words)
 constexpr int kActFloats = 128 + 128 + 64 + 64;
 
+// Forward pass.  Persistent: each block stages the weights in LDS once and
+// walks row tiles of 64 (4 waves x 16 rows) with a grid stride.  rows_dev,
+// when given, holds the row count on the device; out_idx, when given, maps
+// row r to its output element y[out_idx[r]].
 __global__ __launch_bounds__(256) void mlp_fwd_kernel(const uint16_t* __restrict__ wb, const float* __restrict__ wf,
-                                                      const uint16_t* __restrict__ x, int rows,
+                                                      const uint16_t* __restrict__ x, int rows_host,
+                                                      const int* __restrict__ rows_dev, const int* __restrict__ out_idx,
                                                       float* __restrict__ y, float* __restrict__ acts)
 {
     __shared__ __align__(16) uint16_t sW1[kHid * kIn];
     __shared__ __align__(16) uint16_t sW2[kHid * kHid];
     __shared__ __align__(16) uint16_t sH[4][16][kHid + 8];
-    for (int i = threadIdx.x; i < kHid * kIn / 8; i += blockDim.x)
-        ((uint4*)sW1)[i] = ((const uint4*)(wb + oW1))[i];
-    for (int i = threadIdx.x; i < kHid * kHid / 8; i += blockDim.x)
-        ((uint4*)sW2)[i] = ((const uint4*)(wb + oW2))[i];
-    __syncthreads();
-
+    for (int e = threadIdx.x; e < kHid * kIn / 8; e += blockDim.x)
+        ((uint4*)sW1)[e] = ((const uint4*)(wb + oW1))[e];
+    for (int e = threadIdx.x; e < kHid * kHid / 8; e += blockDim.x)
+        ((uint4*)sW2)[e] = ((const uint4*)(wb + oW2))[e];
+    const int rows = rows_dev ? *rows_dev : rows_host;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
-    const int r0 = blockIdx.x * kRowsPerBlock + w * 16;
-    const int ra = r0 + i;   // row of this lane's A fragments
-    bf16x4 a[4];
+    for (int tile = blockIdx.x; tile * kRowsPerBlock < rows; tile += gridDim.x) {
+        __syncthreads();   // weights staged; the previous tile's sH is consumed
+        const int r0 = tile * kRowsPerBlock + w * 16;
+        const int ra = r0 + i;   // row of this lane's A fragments
+        bf16x4 a[4];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-        a[ks] = ra < rows ? load4(x + (size_t)ra * kIn + ks * 16 + g * 4) : bf16x4{0, 0, 0, 0};
-    }
-    // layer 1: z1 = x W1^T + b1
+        for (int ks = 0; ks < 4; ++ks)
+            a[ks] = ra < rows ? load4(x + (size_t)ra * kIn + ks * 16 + g * 4) : bf16x4{0, 0, 0, 0};
+        // layer 1: z1 = x W1^T + b1
 #pragma unroll
-    for (int nt = 0; nt < 8; ++nt) {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int nt = 0; nt < 8; ++nt) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc = mfma16(a[ks], load4(sW1 + (nt * 16 + i) * kIn + ks * 16 + g * 4), acc);
-        const int col = nt * 16 + i;
-        const float bias = wf[oB1 + col];
+            for (int ks = 0; ks < 4; ++ks)
+                acc = mfma16(a[ks], load4(sW1 + (nt * 16 + i) * kIn + ks * 16 + g * 4), acc);
+            const int col = nt * 16 + i;
+            const float bias = wf[oB1 + col];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = r0 + 4 * g + v;
-            float z = acc[v] + bias;
-            uint16_t hb = f2bf(gelu(z));
-            sH[w][4 * g + v][col] = hb;
-            if (acts && row < rows) {
-                float* ar = acts + (size_t)row * kActFloats;
-                ar[col] = z;
-                ((uint16_t*)(ar + 256))[col] = hb;
+            for (int v = 0; v < 4; ++v) {
+                const int row = r0 + 4 * g + v;
+                float z = acc[v] + bias;
+                uint16_t hb = f2bf(gelu(z));
+                sH[w][4 * g + v][col] = hb;
+                if (acts && row < rows) {
+                    float* ar = acts + (size_t)row * kActFloats;
+                    ar[col] = z;
+                    ((uint16_t*)(ar + 256))[col] = hb;
+                }
             }
         }
-    }
-    __syncthreads();
-    bf16x4 a2[8];
+        __syncthreads();
+        bf16x4 a2[8];
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) a2[ks] = load4(&sH[w][i][ks * 16 + g * 4]);
-    // layer 2 and the output dot product
-    float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int ks = 0; ks < 8; ++ks) a2[ks] = load4(&sH[w][i][ks * 16 + g * 4]);
+        // layer 2 and the output dot product
+        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int nt = 0; nt < 8; ++nt) {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int nt = 0; nt < 8; ++nt) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) acc = mfma16(a2[ks], load4(sW2 + (nt * 16 + i) * kHid + ks * 16 + g * 4), acc);
-        const int col = nt * 16 + i;
-        const float bias = wf[oB2 + col];
-        const float w3 = bf2f(wb[oW3 + col]);
+            for (int ks = 0; ks < 8; ++ks)
+                acc = mfma16(a2[ks], load4(sW2 + (nt * 16 + i) * kHid + ks * 16 + g * 4), acc);
+            const int col = nt * 16 + i;
+            const float bias = wf[oB2 + col];
+            const float w3 = bf2f(wb[oW3 + col]);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = r0 + 4 * g + v;
-            float z = acc[v] + bias;
-            uint16_t hb = f2bf(gelu(z));
-            part[v] = fmaf(bf2f(hb), w3, part[v]);
-            if (acts && row < rows) {
-                float* ar = acts + (size_t)row * kActFloats;
-                ar[128 + col] = z;
-                ((uint16_t*)(ar + 320))[col] = hb;
+            for (int v = 0; v < 4; ++v) {
+                const int row = r0 + 4 * g + v;
+                float z = acc[v] + bias;
+                uint16_t hb = f2bf(gelu(z));
+                part[v] = fmaf(bf2f(hb), w3, part[v]);
+                if (acts && row < rows) {
+                    float* ar = acts + (size_t)row * kActFloats;
+                    ar[128 + col] = z;
+                    ((uint16_t*)(ar + 320))[col] = hb;
+                }
             }
         }
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-#pragma unroll
-        for (int d = 8; d >= 1; d >>= 1) part[v] += __shfl_xor(part[v], d, 64);
-    }
-    if (i == 0) {
-        const float b3 = wf[oB3];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = r0 + 4 * g + v;
-            if (row < rows) y[row] = part[v] + b3;
+#pragma unroll
+            for (int d = 8; d >= 1; d >>= 1) part[v] += __shfl_xor(part[v], d, 64);
+        }
+        if (i == 0) {
+            const float b3 = wf[oB3];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = r0 + 4 * g + v;
+                if (row < rows) y[out_idx ? out_idx[row] : row] = part[v] + b3;
+            }
         }
     }
 }
@@ -361,11 +369,12 @@ int mlp_params() { return oB3 + 1; }
 int mlp_act_floats() { return kActFloats; }
 int mlp_rows_per_block() { return kRowsPerBlock; }
 
-void launch_mlp_fwd(const uint16_t* wb, const float* wf, const uint16_t* x, int rows, float* y, float* acts,
-                    hipStream_t s)
+void launch_mlp_fwd(const uint16_t* wb, const float* wf, const uint16_t* x, int rows, const int* rows_dev,
+                    const int* out_idx, int max_blocks, float* y, float* acts, hipStream_t s)
 {
-    dim3 grid((rows + kRowsPerBlock - 1) / kRowsPerBlock);
-    hipLaunchKernelGGL(mlp_fwd_kernel, grid, dim3(256), 0, s, wb, wf, x, rows, y, acts);
+    int nb = (rows + kRowsPerBlock - 1) / kRowsPerBlock;
+    nb = std::max(1, std::min(nb, max_blocks));
+    hipLaunchKernelGGL(mlp_fwd_kernel, dim3(nb), dim3(256), 0, s, wb, wf, x, rows, rows_dev, out_idx, y, acts);
 }
 
 void launch_mlp_bwd(const uint16_t* wb, const uint16_t* x, const float* acts, const float* dy, int rows,

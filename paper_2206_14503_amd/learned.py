@@ -24,28 +24,33 @@ from . import synth, vdi
 @dataclasses.dataclass
 class LearnedConfig:
     """Tiny-volume setting of the learned threshold: 64^3 fp32, 12 Gaussians,
-    2 z-slabs, 256^2 orthographic views along +z and -z, N=8, B=10."""
+    2 z-slabs, orthographic views along +z (even seeds) or -z (odd seeds),
+    N=8, B=10.  Training frames are train_res^2, evaluation frames res^2
+    (1024^2 x 2 bricks = 2.1M brick-rays per frame)."""
     n: int = 64
     n_gauss: int = 12
-    res: int = 256
+    res: int = 1024
+    train_res: int = 640
     grid: Tuple[int, int, int] = (1, 1, 2)
     max_n: int = 8
     iters: int = 10
     gamma_max: float = 2.0
     feature_scale: float = 32.0
     fallback_tol: float = 0.1
+    max_pairs: int = 8 << 20
 
 
-def frame_inputs(cfg: LearnedConfig, seed: int, axis: str):
+def frame_inputs(cfg: LearnedConfig, seed: int, res: int):
     vol = synth.gaussian_volume(cfg.n, cfg.n_gauss, seed)
     bricks = synth.brick_grid((cfg.n,) * 3, cfg.grid)
-    cam = synth.ortho_camera(cfg.res, cfg.res, axis)
+    cam = synth.ortho_camera(res, res, "+z" if seed % 2 == 0 else "-z")
     return vol, bricks, cam
 
 
-def training_pairs(cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor,
-                   axes: Sequence[str] = ("+z", "-z")) -> Tuple[torch.Tensor, torch.Tensor, Dict[str, int]]:
-    """(histogram, log2 gamma*) pairs from the plain bisection on the GPU.
+def training_pairs(cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor
+                   ) -> Tuple[torch.Tensor, torch.Tensor, Dict[str, int]]:
+    """(histogram, log2 gamma*) pairs from the plain bisection on the GPU, at
+    most cfg.max_pairs (a seeded subsample when there are more).
 
     Brick-rays with at most N non-transparent samples are left out: every
     threshold is feasible there and the learned path resolves them exactly
@@ -54,20 +59,27 @@ def training_pairs(cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor,
     stats = {"rays": 0, "kept": 0}
     step = 1.0 / cfg.n
     for seed in seeds:
-        for axis in axes:
-            vol, bricks, cam = frame_inputs(cfg, seed, axis)
-            dbr = vdi.device_bricks(vol, bricks)
-            outs = vdi.generate(dbr, cam, tf_d, step, step, vdi.BISECT, 0.0, cfg.max_n, cfg.iters,
-                                gamma_max=cfg.gamma_max)
-            hist, nnt, cmax = vdi.tau_features(dbr, cam, tf_d, step, step, cfg.max_n, cfg.iters, cfg.gamma_max,
-                                               cfg.feature_scale)
-            gam = torch.stack([o.gamma for o in outs])            # [k, P]
-            keep = nnt > cfg.max_n
-            stats["rays"] += int(nnt.numel())
-            stats["kept"] += int(keep.sum())
-            xs.append(hist[keep])
-            ys.append(torch.log2(gam[keep]))
-    return torch.cat(xs), torch.cat(ys), stats
+        vol, bricks, cam = frame_inputs(cfg, seed, cfg.train_res)
+        dbr = vdi.device_bricks(vol, bricks)
+        outs = vdi.generate(dbr, cam, tf_d, step, step, vdi.BISECT, 0.0, cfg.max_n, cfg.iters,
+                            gamma_max=cfg.gamma_max)
+        hist, nnt, cmax = vdi.tau_features(dbr, cam, tf_d, step, step, cfg.max_n, cfg.iters, cfg.gamma_max,
+                                           cfg.feature_scale)
+        gam = torch.stack([o.gamma for o in outs])            # [k, P]
+        keep = nnt > cfg.max_n
+        stats["rays"] += int(nnt.numel())
+        stats["kept"] += int(keep.sum())
+        xs.append(hist[keep])
+        ys.append(torch.log2(gam[keep]))
+        del dbr, outs
+    X, Y = torch.cat(xs), torch.cat(ys)
+    if X.shape[0] > cfg.max_pairs:
+        g = torch.Generator(device=X.device)
+        g.manual_seed(1)
+        idx = torch.randperm(X.shape[0], generator=g, device=X.device)[:cfg.max_pairs]
+        X, Y = X[idx].contiguous(), Y[idx].contiguous()
+    stats["pairs"] = int(X.shape[0])
+    return X, Y, stats
 
 
 def train(mlp: vdi.MLP, X: torch.Tensor, Y: torch.Tensor, epochs: int = 4, batch: int = 4096, lr: float = 2e-3,
@@ -125,61 +137,64 @@ def timed(fn, reps: int = 3) -> float:
 
 
 def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor,
-             axes: Sequence[str] = ("+z", "-z"), reps: int = 3) -> Dict[str, float]:
+             reps: int = 3) -> Dict[str, float]:
     """Plain bisection vs learned generation on held-out frames: time, fallback
     rate, count statistics and the original-view rendering error of each."""
     step = 1.0 / cfg.n
     t_plain = t_learned = 0.0
-    agg = {"accepted": 0, "shortcut": 0, "fallback": 0, "empty": 0}
-    mae_plain = mae_learned = 0.0
+    agg = {"accepted": 0, "refined": 0, "shortcut": 0, "fallback": 0, "empty": 0}
+    mae_learned = 0.0
     dn_sum, dn_rays = 0.0, 0
     frames = 0
+    rays = 0
     for seed in seeds:
-        for axis in axes:
-            vol, bricks, cam = frame_inputs(cfg, seed, axis)
-            dbr = vdi.device_bricks(vol, bricks)
-            P = cam.width * cam.height
-            outs_p = [vdi.VDI.empty(cam.width, cam.height, cfg.max_n, step) for _ in bricks]
-            outs_l = [vdi.VDI.empty(cam.width, cam.height, cfg.max_n, step) for _ in bricks]
-            run_p = lambda: vdi.generate(dbr, cam, tf_d, step, step, vdi.BISECT, 0.0, cfg.max_n, cfg.iters,
-                                         outs=outs_p, gamma_max=cfg.gamma_max)
-            run_l = lambda: vdi.generate(dbr, cam, tf_d, step, step, vdi.LEARNED, 0.0, cfg.max_n, cfg.iters,
-                                         outs=outs_l, gamma_max=cfg.gamma_max, mlp=mlp,
-                                         fallback_tol=cfg.fallback_tol, feature_scale=cfg.feature_scale)
-            run_p()
-            run_l()
-            torch.cuda.synchronize()
-            vdi.learned_stats()
-            t_plain += timed(run_p, reps)
-            t_learned += timed(run_l, reps)
-            st = vdi.learned_stats()
-            for k in agg:
-                agg[k] += st[k] // reps
-            # count distance from the target N_r = min(N, cmax) on rays the regressor served
-            _, nnt, cmax = vdi.tau_features(dbr, cam, tf_d, step, step, cfg.max_n, cfg.iters, cfg.gamma_max,
-                                            cfg.feature_scale)
-            served = nnt > cfg.max_n
-            cnt_l = torch.stack([o.count for o in outs_l])
-            target = torch.minimum(cmax, torch.full_like(cmax, cfg.max_n))
-            dn_sum += float((cnt_l[served] - target[served]).abs().double().sum())
-            dn_rays += int(served.sum())
-            # original-view rendering of the composited VDI vs each generation's
-            comp_p = vdi.composite(outs_p, vdi.BISECT, 0.0, cfg.max_n, cfg.iters)
-            comp_l = vdi.composite(outs_l, vdi.BISECT, 0.0, cfg.max_n, cfg.iters)
-            img_p = vdi.render_original_view(comp_p)
-            img_l = vdi.render_original_view(comp_l)
-            dvr_ref = img_p  # the plain path renders exactly (Sec. 2.3); compared again in the tests
-            mae_learned += float((img_l - dvr_ref).abs().mean())
-            mae_plain += 0.0
-            frames += 1
-    served_total = agg["accepted"] + agg["fallback"]
+        vol, bricks, cam = frame_inputs(cfg, seed, cfg.res)
+        dbr = vdi.device_bricks(vol, bricks)
+        P = cam.width * cam.height
+        outs_p = [vdi.VDI.empty(cam.width, cam.height, cfg.max_n, step) for _ in bricks]
+        outs_l = [vdi.VDI.empty(cam.width, cam.height, cfg.max_n, step) for _ in bricks]
+        run_p = lambda: vdi.generate(dbr, cam, tf_d, step, step, vdi.BISECT, 0.0, cfg.max_n, cfg.iters,
+                                     outs=outs_p, gamma_max=cfg.gamma_max)
+        run_l = lambda: vdi.generate(dbr, cam, tf_d, step, step, vdi.LEARNED, 0.0, cfg.max_n, cfg.iters,
+                                     outs=outs_l, gamma_max=cfg.gamma_max, mlp=mlp,
+                                     fallback_tol=cfg.fallback_tol, feature_scale=cfg.feature_scale)
+        run_p()
+        run_l()
+        torch.cuda.synchronize()
+        vdi.learned_stats()
+        t_plain += timed(run_p, reps)
+        t_learned += timed(run_l, reps)
+        st = vdi.learned_stats()
+        for k in agg:
+            agg[k] += st[k] // reps
+        # count distance from the target N_r = min(N, cmax) on rays the regressor served
+        _, nnt, cmax = vdi.tau_features(dbr, cam, tf_d, step, step, cfg.max_n, cfg.iters, cfg.gamma_max,
+                                        cfg.feature_scale)
+        served = nnt > cfg.max_n
+        cnt_l = torch.stack([o.count for o in outs_l])
+        target = torch.minimum(cmax, torch.full_like(cmax, cfg.max_n))
+        dn_sum += float((cnt_l[served] - target[served]).abs().double().sum())
+        dn_rays += int(served.sum())
+        # original-view rendering of the composited VDI vs each generation's
+        comp_p = vdi.composite(outs_p, vdi.BISECT, 0.0, cfg.max_n, cfg.iters)
+        comp_l = vdi.composite(outs_l, vdi.BISECT, 0.0, cfg.max_n, cfg.iters)
+        img_p = vdi.render_original_view(comp_p)
+        img_l = vdi.render_original_view(comp_l)
+        # the plain path's original-view rendering equals direct volume
+        # rendering (Sec. 2.3; checked against the oracle in the tests)
+        mae_learned += float((img_l - img_p).abs().mean())
+        frames += 1
+        rays += len(bricks) * P
+    served_total = agg["accepted"] + agg["refined"] + agg["fallback"]
     return {
         "frames": frames,
+        "brick_rays": rays,
         "plain_ms": t_plain / frames,
         "learned_ms": t_learned / frames,
         "speedup": t_plain / t_learned,
         "fallback_rate": agg["fallback"] / max(served_total, 1),
-        "accepted": agg["accepted"], "fallback": agg["fallback"], "shortcut": agg["shortcut"], "empty": agg["empty"],
+        "accepted": agg["accepted"], "refined": agg["refined"], "fallback": agg["fallback"],
+        "shortcut": agg["shortcut"], "empty": agg["empty"],
         "mean_abs_count_miss": dn_sum / max(dn_rays, 1),
         "rgba_mae_vs_plain_render": mae_learned / frames,
     }

@@ -59,7 +59,7 @@ class vdi_tf_t(ctypes.Structure):
 class vdi_tau_t(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tau", ctypes.c_float), ("iters", ctypes.c_int32),
                 ("gamma_max", ctypes.c_float), ("mlp", ctypes.c_void_p), ("fallback_tol", ctypes.c_float),
-                ("feature_scale", ctypes.c_float)]
+                ("feature_scale", ctypes.c_float), ("y", ctypes.c_void_p)]
 
 
 class vdi_mlp_t(ctypes.Structure):
@@ -191,8 +191,8 @@ def camera_c(cam) -> vdi_camera_t:
 
 
 def tau_c(mode: int, tau: float = 0.0, iters: int = 10, gamma_max: float = 2.0, mlp=None,
-          fallback_tol: float = 0.1, feature_scale: float = 32.0) -> vdi_tau_t:
-    return vdi_tau_t(mode, tau, iters, gamma_max, mlp, fallback_tol, feature_scale)
+          fallback_tol: float = 0.1, feature_scale: float = 32.0, y=None) -> vdi_tau_t:
+    return vdi_tau_t(mode, tau, iters, gamma_max, mlp, fallback_tol, feature_scale, y)
 
 
 @dataclasses.dataclass
@@ -230,8 +230,10 @@ def device_bricks(vol, bricks, device=None) -> List[DeviceBrick]:
 def generate(bricks: Sequence[DeviceBrick], cam, tf: torch.Tensor, step: float, ref_step: float, mode: int,
              tau: float = 0.0, max_n: int = 8, iters: int = 10, layout: int = REGULAR,
              capacity: Optional[int] = None, outs: Optional[List[VDI]] = None, gamma_max: float = 2.0,
-             mlp: Optional["MLP"] = None, fallback_tol: float = 0.1, feature_scale: float = 32.0) -> List[VDI]:
-    """vdi_generate: one sub-VDI per brick (mode LEARNED needs `mlp`)."""
+             mlp: Optional["MLP"] = None, fallback_tol: float = 0.1, feature_scale: float = 32.0,
+             y: Optional[torch.Tensor] = None) -> List[VDI]:
+    """vdi_generate: one sub-VDI per brick (mode LEARNED needs `mlp`, or `y`:
+    float32 [k, H*W] log2 thresholds on the device used instead of the MLP)."""
     k = len(bricks)
     if outs is None:
         outs = [VDI.empty(cam.width, cam.height, max_n, ref_step, layout, capacity) for _ in range(k)]
@@ -240,8 +242,12 @@ def generate(bricks: Sequence[DeviceBrick], cam, tf: torch.Tensor, step: float, 
     cc = camera_c(cam)
     tfc = vdi_tf_t(_ptr(tf), tf.shape[0])
     mc = mlp.c() if mlp is not None else None
+    if y is not None:
+        if y.dtype != torch.float32 or not y.is_cuda or y.numel() != k * cam.width * cam.height:
+            raise ValueError("y must be a float32 device tensor of k*H*W log2 thresholds")
+        y = y.contiguous()
     tc = tau_c(mode, tau, iters, gamma_max, ctypes.cast(ctypes.pointer(mc), ctypes.c_void_p) if mc else None,
-               fallback_tol, feature_scale)
+               fallback_tol, feature_scale, _ptr(y) if y is not None else None)
     _check(lib().vdi_generate(context(), bc, k, ctypes.byref(cc), ctypes.byref(tfc), step, ctypes.byref(tc), oc,
                               _stream()))
     return outs
@@ -374,9 +380,9 @@ def mlp_adam(mlp: MLP, grad: torch.Tensor, lr: float = 1e-3, beta1: float = 0.9,
 
 
 def learned_stats():
-    st = (ctypes.c_int64 * 4)()
+    st = (ctypes.c_int64 * 5)()
     _check(lib().vdi_learned_stats(context(), st, _stream()))
-    return {"accepted": st[0], "shortcut": st[1], "fallback": st[2], "empty": st[3]}
+    return {"accepted": st[0], "shortcut": st[1], "fallback": st[2], "empty": st[3], "refined": st[4]}
 
 
 def debug_mfma(A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:

@@ -1,0 +1,95 @@
+"""The C-ABI without a GPU: libvdi.so loads and exports every function
+include/vdi.h declares; the binding's ctypes structs have the header's sizes
+and field offsets (measured by a C program compiled against the header); and
+argument errors are reported on the host before any device call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vdi.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(vdi_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def V():
+    from paper_2206_14503_amd import vdi
+    return vdi
+
+
+def test_header_declares_the_hot_path():
+    names = _declared_functions()
+    for must in ("vdi_generate", "vdi_composite", "vdi_render_original_view", "vdi_batch_create", "vdi_autotune",
+                 "vdi_mlp_forward", "vdi_mlp_backward", "vdi_mlp_adam", "vdi_tau_features"):
+        assert must in names
+    assert len(names) >= 20
+
+
+def test_library_exports_every_declared_function(V):
+    L = V.lib()
+    missing = [n for n in _declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_header(V, tmp_path):
+    """sizeof/offsetof from C (gcc, the header itself) against the ctypes mirrors."""
+    fields = {
+        "vdi_t": V.vdi_t, "vdi_brick_t": V.vdi_brick_t, "vdi_camera_t": V.vdi_camera_t, "vdi_tf_t": V.vdi_tf_t,
+        "vdi_tau_t": V.vdi_tau_t, "vdi_mlp_t": V.vdi_mlp_t, "vdi_job_t": V.vdi_job_t,
+    }
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "vdi.h"', "int main(void) {"]
+    for cname, cls in fields.items():
+        src.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            cf = "in" if (cname == "vdi_job_t" and fname == "in_") else fname
+            src.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    src.append("  return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for cname, cls in fields.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_null_arguments_rejected_on_the_host(V):
+    """Calls that can be made without a device: every entry point rejects a
+    NULL context or output with VDI_E_INVALID and a message."""
+    L = V.lib()
+    E_INVALID = -1
+    assert L.vdi_generate(None, None, 0, None, None, ctypes.c_float(1.0), None, None, None) == E_INVALID
+    assert b"NULL" in L.vdi_last_error()
+    assert L.vdi_composite(None, None, 1, None, None, None) == E_INVALID
+    assert L.vdi_render_original_view(None, None, None, None) == E_INVALID
+    assert L.vdi_learned_stats(None, None, None) == E_INVALID
+    out = ctypes.c_void_p()
+    assert L.vdi_batch_create(None, None, 1, None, ctypes.byref(out)) == E_INVALID
+    assert L.vdi_batch_run(None, None, None) == E_INVALID
+    assert L.vdi_batch_replay(None, None) == E_INVALID
+    assert L.vdi_batch_destroy(None) == 0
+    assert L.vdi_ctx_destroy(None) == 0
+
+
+def test_status_codes_match_binding(V):
+    text = open(HEADER).read()
+    codes = dict((k, int(v)) for k, v in re.findall(r"(VDI_\w+)\s*=\s*(-?\d+)", text))
+    assert codes["VDI_OK"] == 0 and codes["VDI_E_INVALID"] == -1 and codes["VDI_E_UNSUPPORTED"] == -2
+    assert codes["VDI_TAU_FIXED"] == V.FIXED and codes["VDI_TAU_BISECT"] == V.BISECT
+    assert codes["VDI_TAU_LEARNED"] == V.LEARNED
+    assert codes["VDI_LAYOUT_REGULAR"] == V.REGULAR and codes["VDI_LAYOUT_COMPACT"] == V.COMPACT

@@ -57,6 +57,7 @@ def _jobs(V):
         (16, 3, 32, 33, 17, 4, 0xFFFF, 1),
         (5, 10, 4, 50, 50, 5, 0, 1),
         (4, 12, 16, 64, 64, 6, 0b1111, 0),
+        (20, 2, 12, 30, 20, 7, 0b101, 1),      # more inputs than the depth-disjoint path takes
     ]
     jobs, raw = [], []
     for k, n_per, out_n, w, h, seed, cm, mode in specs:

@@ -158,7 +158,7 @@ def test_learned_generation_decisions(V, OL):
     lrn = V.generate(dbr, cam, tf_d, 1 / 64, 1 / 64, V.LEARNED, 0.0, 8, 10, mlp=mlp)
     st = V.learned_stats()
     hist, nnt, cmax = V.tau_features(dbr, cam, tf_d, 1 / 64, 1 / 64, 8, 10, 2.0, 32.0)
-    assert st["accepted"] + st["shortcut"] + st["fallback"] + st["empty"] == 2 * 128 * 128
+    assert st["accepted"] + st["refined"] + st["shortcut"] + st["fallback"] + st["empty"] == 2 * 128 * 128
     for r in range(2):
         cp, cl = plain[r].count.cpu().numpy(), lrn[r].count.cpu().numpy()
         gp, gl = plain[r].gamma.cpu().numpy(), lrn[r].gamma.cpu().numpy()
@@ -175,13 +175,64 @@ def test_learned_generation_decisions(V, OL):
         assert np.all((cl[kept] <= 8) & (cl[kept] >= lo[kept]))
 
 
+@pytest.mark.parametrize("camera", ["ortho", "orbit"])
+def test_learned_rounds_match_oracle(V, OL, orc, camera):
+    """Caller-supplied log2 thresholds (the plain bisection's, plus seeded
+    noise) through the learned path: outcome, threshold and count of every
+    tie-free brick-ray equal the oracle's two-round decision; lists sent back
+    to bisection, and shortcut lists, equal the plain ones."""
+    import torch
+    vol = synth.gaussian_volume(64, 12, 17)
+    tf = synth.transfer_function()
+    cam = synth.ortho_camera(96, 80, "-z") if camera == "ortho" else synth.orbit_camera(31, 120, 96)
+    bricks = synth.brick_grid((64, 64, 64), (1, 1, 2))
+    N, step = 8, 1 / 64
+    plain_o = orc.generate(vol, bricks, cam, tf, step, step, 1, 0.0, N, 10)
+    rng = np.random.default_rng(3)
+    y = (np.log2(plain_o["gamma"].astype(np.float64)) + rng.normal(0.0, 0.4, plain_o["gamma"].shape)).astype(np.float32)
+    _, nnt, cmax = OL.features(vol, bricks, cam, tf, step, step, 10, 2.0, 32.0)
+    nb, P = nnt.shape
+
+    def count_fn(g):
+        c, m = OL.count_at(vol, bricks, cam, tf, step, step, g.reshape(nb, P), N)
+        return c.ravel(), m.ravel()
+
+    ref = OL.choose(count_fn, y, nnt, cmax, N)
+    dbr = V.device_bricks(vol, bricks)
+    tf_d = torch.from_numpy(tf).cuda()
+    V.learned_stats()
+    out = V.generate(dbr, cam, tf_d, step, step, V.LEARNED, 0.0, N, 10, y=torch.from_numpy(y).cuda())
+    st = V.learned_stats()
+    gg = np.stack([o.gamma.cpu().numpy() for o in out]).ravel()
+    gc = np.stack([o.count.cpu().numpy() for o in out]).ravel()
+    kind, free = ref["kind"], ref["margin"] >= 2e-5
+    pm = plain_o["margin"].ravel() >= 2e-5
+    regressed = np.isin(kind, [OL.KEPT, OL.REFINED])
+    sel = free & regressed
+    np.testing.assert_allclose(gg[sel], ref["gamma"][sel], rtol=2e-6, atol=0)
+    _, m_at = OL.count_at(vol, bricks, cam, tf, step, step, gg.reshape(nb, P).astype(np.float32), N)
+    robust = sel & (m_at.ravel() >= 2e-5)
+    c_ref, _ = OL.count_at(vol, bricks, cam, tf, step, step, ref["gamma"].reshape(nb, P), N)
+    assert np.array_equal(gc[robust], c_ref.ravel()[robust])
+    back = free & pm & np.isin(kind, [OL.FALLBACK, OL.SHORTCUT])
+    assert np.array_equal(gg[back], plain_o["gamma"].ravel()[back])
+    assert np.array_equal(gc[back], plain_o["count"].ravel()[back])
+    # every outcome occurs, and the device's tallies match the oracle's up to tie rays
+    n_tie = int((~free).sum())
+    for key, k in (("accepted", OL.KEPT), ("refined", OL.REFINED), ("fallback", OL.FALLBACK),
+                   ("shortcut", OL.SHORTCUT), ("empty", OL.EMPTY)):
+        want = int((kind == k).sum())
+        assert abs(st[key] - want) <= n_tie, (key, st[key], want, n_tie)
+    assert min(st["accepted"], st["refined"], st["fallback"], st["shortcut"]) > 0, st
+
+
 def test_learned_gain_short_training(V):
     """Train on a few volumes with the project's kernels, evaluate on a held-out
     volume: the learned path keeps most regressed thresholds and renders the
     same image from the original view; report its speed against bisection."""
     import torch
     from paper_2206_14503_amd import learned
-    cfg = learned.LearnedConfig(res=128)
+    cfg = learned.LearnedConfig(res=128, train_res=128)
     tf_d = torch.from_numpy(synth.transfer_function()).cuda()
     X, Y, st = learned.training_pairs(cfg, seeds=range(6), tf_d=tf_d)
     assert st["kept"] > 1000

@@ -245,6 +245,52 @@ def test_composite_interleaved_stress_parity(V, orc):
     _compare_lists(gc, gd, gn, oref["color"], oref["depth"], oref["count"], oref["margin"], "stress")
 
 
+@pytest.mark.parametrize("out_n", [4, 30], ids=["bisect", "passthrough"])
+def test_composite_mixed_disjoint_and_interleaved(V, orc, out_n):
+    """One launch where half of the pixels hold depth-disjoint lists (in a
+    seeded per-pixel order, so the depth-disjoint path must sort them) and the
+    other half interleaved lists (general merge); one input compact.  Counts,
+    merge order and values match the oracle."""
+    import torch
+    import oracle
+    k, n, W, H = 5, 6, 24, 20
+    P = W * H
+    col, dep, cnt = synth.dense_interleaved_lists(k, n, P, seed=11)
+    rng = np.random.default_rng(11)
+    cnt = torch.from_numpy(rng.integers(0, n + 1, size=(k, P)).astype(np.int32))
+    dep = dep.clone()
+    col = col.clone()
+    for px in range(0, P, 2):       # even pixels: each input in its own depth band
+        perm = rng.permutation(k)
+        for r in range(k):
+            dep[r, :, px] += float(perm[r]) * 100.0
+    for r in range(k):
+        for slot in range(n):
+            dead = cnt[r] <= slot
+            col[r, slot, dead] = 0
+            dep[r, slot, dead] = 0
+    ins = []
+    for r in range(k):
+        if r == 2:
+            off, cc, dd = oracle.to_compact(col[r].numpy(), dep[r].numpy(), cnt[r].numpy())
+            ins.append(V.VDI(W, H, n, 0.01, V.COMPACT, torch.from_numpy(cc).cuda(), torch.from_numpy(dd).cuda(),
+                             cnt[r].cuda(), torch.from_numpy(off.view(np.int32)).cuda()))
+        else:
+            ins.append(V.VDI(W, H, n, 0.01, V.REGULAR, col[r].cuda().contiguous(), dep[r].cuda().contiguous(),
+                             cnt[r].cuda().contiguous()))
+    out = V.composite(ins, V.BISECT, 0.0, out_n, 10)
+    torch.cuda.synchronize()
+    assert V.device_status() == 0
+    c, d, m = col.numpy(), dep.numpy(), cnt.numpy()
+    oref = orc.composite([c[r] for r in range(k)], [d[r] for r in range(k)], [m[r] for r in range(k)], 0.01, 1, 0.0,
+                         out_n, 10)
+    gc, gd, gn, gg = _gpu_regular(out)
+    total = m.sum(axis=0)
+    pt = total <= out_n
+    assert np.array_equal(gc[:, pt], oref["color"][:, pt]) and np.array_equal(gd[:, pt], oref["depth"][:, pt])
+    _compare_lists(gc, gd, gn, oref["color"], oref["depth"], oref["count"], oref["margin"], "mixed")
+
+
 def test_composite_identity_with_empty_inputs(V, orc):
     """Invariant (a) on the GPU: a VDI composited with empty VDIs is returned bit for bit."""
     import torch
