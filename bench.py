@@ -28,10 +28,46 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# fp32 vector lanes: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one non-packed op per lane and cycle)
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+
+# sources of the composite kernels; a traffic figure measured on other sources is not reported
+COMPOSITE_SOURCES = ("paper_2206_14503_amd/csrc/vdi_composite.hip", "paper_2206_14503_amd/csrc/vdi_internal.h",
+                     "paper_2206_14503_amd/csrc/vdi_kernels.h")
+PMC_SUMMARY = "profiles/composite_fhd_pmc.md"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest(paths=COMPOSITE_SOURCES) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by the
+    factor a 1 GiB device copy gives), or None when there is none or it was
+    taken on other kernel sources."""
+    path = os.path.join(ROOT, PMC_SUMMARY)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    for line in open(path):
+        if line.startswith("pmc: "):
+            d = json.loads(line[5:])
+            if d.get("source_sha256") != source_digest():
+                return None, "kernel sources changed since the counters were taken"
+            k = d.get("kernels", {}).get(kernel)
+            if not k:
+                return None, f"no counters for {kernel}"
+            return (k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024.0, "measured"
+    return None, "no counter line"
 
 
 def composite_bytes(inputs, out_n, npix, counts_total):
@@ -158,8 +194,10 @@ def leg_fhd(args, result):
                           "algorithmic_bytes": cbytes, "ms": float(comp_ms.mean()), "achieved_GBps": comp_gbs,
                           "frac_hbm_peak": comp_gbs / HBM_PEAK_GBS},
     })
-    result["roofline"] = {"kernel": "composite_kernel", "bound": "hbm", "achieved": comp_gbs, "peak": HBM_PEAK_GBS,
-                          "unit": "GB/s", "frac": comp_gbs / HBM_PEAK_GBS, "traffic": None,
+    traffic, why = measured_traffic("composite_cat_kernel")
+    result["roofline"] = {"kernel": "composite_cat_kernel (composite stage)", "bound": "hbm", "achieved": comp_gbs,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": comp_gbs / HBM_PEAK_GBS,
+                          "traffic": traffic, "traffic_note": why, "algorithmic_bytes": cbytes,
                           "workload": w.name}
     return dict(w=w, vol=vol, bricks=bricks, tf=tf, cam=cam, step_len=step_len)
 

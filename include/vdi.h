@@ -265,20 +265,24 @@ typedef struct vdi_batch vdi_batch;
 
 /* Checks the jobs (as vdi_composite would), then uploads a device job table
  * and a tile queue: jobs ordered by decreasing estimated work (k*N*pixels),
- * each job's pixels cut into tiles whose size is read from `autotune_cache`
- * (a file written by vdi_autotune; NULL or no entry: 256 pixels) for the job's
- * (k bucket, N) with k buckets 1-4, 5-8, 9-32.  This is the only batch call
- * that allocates device memory; the job descriptors are copied, the VDIs they
- * point to must stay valid while the batch is used. */
+ * each job's image cut into 8x8-pixel blocks (one per wavefront) and the
+ * blocks into tiles of tile_pixels/64 blocks, tile_pixels read from
+ * `autotune_cache` (a file written by vdi_autotune; NULL or no entry: 256)
+ * for the job's (k bucket, N) with k buckets 1-4, 5-8, 9-32.  Jobs with more
+ * than 16 inputs, and pixels whose input lists interleave in depth, are
+ * composited by a second persistent kernel of the same run.  This is the only
+ * batch call that allocates device memory; the job descriptors are copied,
+ * the VDIs they point to must stay valid while the batch is used. */
 vdi_status vdi_batch_create(vdi_ctx *ctx, const vdi_job_t *jobs, int n_jobs, const char *autotune_cache,
                             vdi_batch **out);
 
 /* One persistent launch (grid sized to fill the device) whose blocks pull
- * tiles from a device counter until none is left; preceded by two small fill
- * kernels that reset the counter and t_start_end.  t_start_end: DEVICE
- * [2*n_jobs] or NULL; per job the earliest tile start and the latest tile end
- * in ticks of the device's constant-rate clock (see vdi_batch_info).  Neither
- * allocates nor synchronises, so it can be captured in a graph. */
+ * tiles from a device counter until none is left, then the persistent
+ * general-merge launch; preceded by small fill kernels that reset the
+ * counters and t_start_end.  t_start_end: DEVICE [2*n_jobs] or NULL; per job
+ * the earliest start and the latest end of its work in ticks of the device's
+ * constant-rate clock (see vdi_batch_info).  Neither allocates nor
+ * synchronises, so it can be captured in a graph. */
 vdi_status vdi_batch_run(vdi_batch *batch, uint64_t *t_start_end, void *stream);
 
 /* Captures vdi_batch_run(batch, t_start_end, stream) into a hipGraph (once;

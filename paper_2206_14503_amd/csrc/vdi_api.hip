@@ -429,6 +429,7 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     if (lds > 160 * 1024) return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", seq_cap);
     P.k = k;
     P.npix = (uint32_t)((size_t)out->width * out->height);
+    P.width = out->width;
     P.inv_ref = 1.0f / out->ref_step;
     P.mode = tau->mode;
     P.tau = tau->tau;

@@ -103,6 +103,7 @@ CompParams job_params(vdi_ctx* ctx, const vdi_job_t& j)
     }
     P.k = j.k;
     P.npix = (uint32_t)((size_t)j.out.width * j.out.height);
+    P.width = j.out.width;
     P.inv_ref = 1.0f / j.out.ref_step;
     P.mode = j.tau.mode;
     P.tau = j.tau.tau;
@@ -162,9 +163,12 @@ vdi_status create_impl(vdi_ctx* ctx, const vdi_job_t* jobs, int n_jobs, const Ti
             auto it = tiles_by_bucket.find({ k_bucket(hp[j].k), hp[j].out_n });
             tile = it != tiles_by_bucket.end() ? it->second : kDefaultTile;
         }
-        for (uint32_t p0 = 0; p0 < hp[j].npix; p0 += (uint32_t)tile) {
-            uint32_t np = std::min<uint32_t>((uint32_t)tile, hp[j].npix - p0);
-            tiles.push_back(make_uint2((uint32_t)j | (np << 16), p0));
+        // tile size in pixels -> whole 8x8 blocks (at least one)
+        const uint32_t per = std::max<uint32_t>(1u, (uint32_t)tile / 64u);
+        const uint32_t nblocks = ((uint32_t)(hp[j].width + 7) / 8u) * ((hp[j].npix / (uint32_t)hp[j].width + 7u) / 8u);
+        for (uint32_t b0 = 0; b0 < nblocks; b0 += per) {
+            uint32_t nb = std::min<uint32_t>(per, nblocks - b0);
+            tiles.push_back(make_uint2((uint32_t)j | (nb << 16), b0));
         }
     }
     BatchImpl* b = new BatchImpl();

@@ -332,6 +332,17 @@ __device__ void c_scan(R rd, int total, float inv_ref, const float* gam, int cap
 }  // namespace
 
 
+// Pixel of lane t in 8x8 block `blk` (row-major over the image); false
+// outside the image.
+__device__ inline bool block_pixel(const CompParams& P, uint32_t blk, int t, uint32_t& p)
+{
+    const uint32_t bx = ((uint32_t)P.width + 7u) >> 3;
+    const uint32_t x = (blk % bx) * 8u + (uint32_t)(t & 7), y = (blk / bx) * 8u + (uint32_t)(t >> 3);
+    const uint32_t h = P.npix / (uint32_t)P.width;
+    p = y * (uint32_t)P.width + x;
+    return x < (uint32_t)P.width && y < h;
+}
+
 // The input table of a job in LDS (thread t < k writes entry t).
 __device__ inline void setup_inputs(const CompParams& P, unsigned char* lds_raw, int t)
 {
@@ -591,8 +602,8 @@ __global__ __launch_bounds__(64) void composite_kernel(CompParams P)
     const int t = threadIdx.x;
     setup_inputs(P, lds_raw, t);
     __syncthreads();
-    const uint32_t p = blockIdx.x * kWave + t;
-    if (p < P.npix) composite_pixel(P, lds_raw, t, p);
+    uint32_t p;
+    if (block_pixel(P, blockIdx.x, t, p)) composite_pixel(P, lds_raw, t, p);
 }
 
 // Depth-disjoint path over all pixels; the others are queued.
@@ -602,8 +613,8 @@ __global__ __launch_bounds__(64) void composite_cat_kernel(CompParams P)
     const int t = threadIdx.x;
     setup_inputs(P, lds_raw, t);
     __syncthreads();
-    const uint32_t p = blockIdx.x * kWave + t;
-    if (p >= P.npix) return;
+    uint32_t p;
+    if (!block_pixel(P, blockIdx.x, t, p)) return;
     const bool done = composite_pixel_cat(P, lds_raw, t, p);
     const int pos = wave_append(P.q_count, !done);
     if (!done) P.q_list[pos] = (int)p;
@@ -643,9 +654,9 @@ __global__ __launch_bounds__(64) void batch_kernel(const CompParams* __restrict_
         const uint32_t tile = s_tile;
         __syncthreads();
         if (tile >= n_tiles) break;
-        const uint2 td = tiles[tile];          // x: job, y: first pixel
+        const uint2 td = tiles[tile];          // x: job | blocks << 16, y: first 8x8 block
         const int job = (int)(td.x & 0xffffu);
-        const uint32_t npx = td.x >> 16;       // pixels in the tile
+        const uint32_t nblk = td.x >> 16;      // blocks in the tile
         const CompParams& P = jobs[job];
         if (job != cur_job) {
             setup_inputs(P, lds_raw, t);
@@ -653,9 +664,9 @@ __global__ __launch_bounds__(64) void batch_kernel(const CompParams* __restrict_
         }
         __syncthreads();
         if (t == 0 && t_start_end) atomicMin(&t_start_end[2 * job], (unsigned long long)wall_clock64());
-        for (uint32_t base = td.y; base < td.y + npx; base += kWave) {
-            const uint32_t p = base + t;
-            if (p < td.y + npx && p < P.npix) {
+        for (uint32_t blk = td.y; blk < td.y + nblk; ++blk) {
+            uint32_t p;
+            if (block_pixel(P, blk, t, p)) {
                 const bool done = composite_pixel_cat(P, lds_raw, t, p);
                 const int pos = wave_append(P.q_count, !done);
                 if (!done) P.q_list[pos] = (int)p;
@@ -729,7 +740,7 @@ size_t cat_lds_bytes(int k) { return sizeof(InLds) * kMaxInputs + (size_t)kWave 
 void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
 {
     const size_t lds = composite_lds_bytes(P.k, P.seq_cap);
-    const unsigned blocks = (P.npix + kWave - 1) / kWave;
+    const unsigned blocks = ((unsigned)(P.width + 7) / 8u) * ((P.npix / (unsigned)P.width + 7u) / 8u);
     if (P.k > kCatMaxInputs) {
         hipLaunchKernelGGL(composite_kernel, dim3(blocks), dim3(kWave), lds, s, P);
         return;

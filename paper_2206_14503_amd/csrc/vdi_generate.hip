@@ -270,7 +270,7 @@ __device__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, floa
 template <typename VT, int KIND>
 __global__ __launch_bounds__(256) void gen_kernel(GenParams P, GenBricks B)
 {
-    __shared__ float4 tf_s[VDI_MAX_TF];
+    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
     for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
     __syncthreads();
 
@@ -332,13 +332,16 @@ __global__ __launch_bounds__(256) void gen_kernel(GenParams P, GenBricks B)
     if (br.gamma) br.gamma[pix] = gm;
 }
 
+// Dynamic LDS of the generation kernels: the transfer function's rows.
+static size_t tf_lds(const GenParams& P) { return sizeof(float4) * (size_t)P.tf_entries; }
+
 template <typename VT>
 static void launch_gen(int kind, const GenParams& P, const GenBricks& B, int nb, hipStream_t s)
 {
     dim3 grid((P.cam.width + 15) / 16, (P.cam.height + 15) / 16, nb);
-    if (kind == 0) hipLaunchKernelGGL((gen_kernel<VT, 0>), grid, dim3(256), 0, s, P, B);
-    if (kind == 1) hipLaunchKernelGGL((gen_kernel<VT, 1>), grid, dim3(256), 0, s, P, B);
-    if (kind == 2) hipLaunchKernelGGL((gen_kernel<VT, 2>), grid, dim3(256), 0, s, P, B);
+    if (kind == 0) hipLaunchKernelGGL((gen_kernel<VT, 0>), grid, dim3(256), tf_lds(P), s, P, B);
+    if (kind == 1) hipLaunchKernelGGL((gen_kernel<VT, 1>), grid, dim3(256), tf_lds(P), s, P, B);
+    if (kind == 2) hipLaunchKernelGGL((gen_kernel<VT, 2>), grid, dim3(256), tf_lds(P), s, P, B);
 }
 
 void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B, int nb, hipStream_t s)
@@ -358,7 +361,7 @@ void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B
 template <typename VT>
 __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
-    __shared__ float4 tf_s[VDI_MAX_TF];
+    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
     __shared__ uint16_t hs[64][256];
     for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
     for (int j = 0; j < 64; ++j) hs[j][threadIdx.x] = 0;
@@ -482,7 +485,7 @@ __device__ inline RayRun ray_run(const GenParams& P, const GenBrick& br, int x, 
 template <typename VT>
 __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
-    __shared__ float4 tf_s[VDI_MAX_TF];
+    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
     for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
     __syncthreads();
 
@@ -573,7 +576,7 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
 template <typename VT>
 __global__ __launch_bounds__(256) void refine_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
-    __shared__ float4 tf_s[VDI_MAX_TF];
+    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
     for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
     __syncthreads();
     const GenBrick& br = B.b[blockIdx.z];
@@ -612,7 +615,7 @@ __global__ __launch_bounds__(256) void refine_kernel(GenParams P, GenBricks B, L
 template <typename VT>
 __global__ __launch_bounds__(256) void fallback_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
-    __shared__ float4 tf_s[VDI_MAX_TF];
+    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
     for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
     __syncthreads();
     const GenBrick& br = B.b[blockIdx.z];
@@ -642,16 +645,16 @@ static void launch_learned_t(int phase, const GenParams& P, const GenBricks& B, 
                              hipStream_t s)
 {
     dim3 grid((P.cam.width + 15) / 16, (P.cam.height + 15) / 16, nb);
-    if (phase == 0) hipLaunchKernelGGL(features_kernel<VT>, grid, dim3(256), 0, s, P, B, L);
-    if (phase == 1) hipLaunchKernelGGL(learned_kernel<VT>, grid, dim3(256), 0, s, P, B, L);
+    if (phase == 0) hipLaunchKernelGGL(features_kernel<VT>, grid, dim3(256), tf_lds(P), s, P, B, L);
+    if (phase == 1) hipLaunchKernelGGL(learned_kernel<VT>, grid, dim3(256), tf_lds(P), s, P, B, L);
     if (phase == 2 || phase == 3) {
         // queue-driven: grid-stride over each brick's queue, enough blocks to
         // fill the device whatever the queue length turns out to be
         size_t npix = (size_t)P.cam.width * P.cam.height;
         unsigned bx = (unsigned)std::min<size_t>((npix + 255) / 256, (size_t)L.blocks_per_brick);
         dim3 g2(bx, 1, nb);
-        if (phase == 2) hipLaunchKernelGGL(refine_kernel<VT>, g2, dim3(256), 0, s, P, B, L);
-        else hipLaunchKernelGGL(fallback_kernel<VT>, g2, dim3(256), 0, s, P, B, L);
+        if (phase == 2) hipLaunchKernelGGL(refine_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
+        else hipLaunchKernelGGL(fallback_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
     }
 }
 

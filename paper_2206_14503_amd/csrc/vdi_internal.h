@@ -141,7 +141,8 @@ __device__ inline int ray_samples(const Ray& r, float step)
     return k;
 }
 
-__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+// clamp for lo <= hi (one max and one min)
+__device__ inline int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // Voxel index along axis a of the sample point (decides brick ownership).
 __device__ inline int voxel_of(float p, int n)
@@ -316,8 +317,11 @@ __device__ inline float trilinear(const VT* data, const BrickGeo& g, const float
         i0[a] = clampi(ii, g.clo[a], g.chi[a]);
         i1[a] = clampi(ii + 1, g.clo[a], g.chi[a]);
     }
-    const uint32_t r00 = i0[1] * g.sy + i0[2] * g.sz, r10 = i1[1] * g.sy + i0[2] * g.sz;
-    const uint32_t r01 = i0[1] * g.sy + i1[2] * g.sz, r11 = i1[1] * g.sy + i1[2] * g.sz;
+    // 24-bit multiplies: indices and strides are below 2^24 and every product
+    // below 2^30 (the data box is under 4 GiB)
+    const uint32_t y0 = __umul24((uint32_t)i0[1], g.sy), y1 = __umul24((uint32_t)i1[1], g.sy);
+    const uint32_t z0 = __umul24((uint32_t)i0[2], g.sz), z1 = __umul24((uint32_t)i1[2], g.sz);
+    const uint32_t r00 = y0 + z0, r10 = y1 + z0, r01 = y0 + z1, r11 = y1 + z1;
     float v000, v100, v010, v110, v001, v101, v011, v111;
     if (g.sx2) {
         const int xb = i0[0] < g.xmax ? i0[0] : g.xmax;
@@ -355,7 +359,7 @@ __device__ inline float trilinear(const VT* data, const BrickGeo& g, const float
 __device__ inline void tf_coord(float s, int entries, int& cell, float& w)
 {
 #pragma clang fp contract(off)
-    float sc = s < 0.0f ? 0.0f : (s > 1.0f ? 1.0f : s);
+    float sc = fminf(fmaxf(s, 0.0f), 1.0f);
     float q = sc * (float)(entries - 1);
     int i = (int)floorf(q);
     if (i > entries - 2) i = entries - 2;
@@ -382,23 +386,27 @@ __device__ inline float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ inline float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ inline float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// log2(1 - a) for a in [0, 1], accurate also for tiny a.
+// log2(1 - a) for a in [0, 1], accurate also for tiny a (the rounding of
+// u = 1 - a is undone by the factor a / (1 - u)).  Written without branches:
+// every lane evaluates all forms and selects.
 __device__ inline float log2_1m(float a)
 {
-    float u = 1.0f - a;
-    if (a >= 0.5f) return hw_log2(u);                 // 1 - a exact here
-    if (u == 1.0f) return -a * 1.4426950408889634f;   // a below half an ulp of 1
-    float d = 1.0f - u;                               // exact
-    return hw_log2(u) * (a * hw_rcp(d));
+    const float u = 1.0f - a;
+    const float lu = hw_log2(u);
+    const float d = 1.0f - u;                                   // exact
+    const float r = lu * (a * hw_rcp(d));
+    const float tiny = -a * 1.4426950408889634f;               // a below half an ulp of 1
+    return a >= 0.5f ? lu : (u == 1.0f ? tiny : r);            // 1 - a exact for a >= 1/2
 }
 
-// 1 - 2^y for y <= 0, accurate also for y near 0.
+// 1 - 2^y for y <= 0, accurate also for y near 0 (the rounding of u = 2^y is
+// undone by the factor y / log2(u)).  Without branches.
 __device__ inline float one_minus_exp2(float y)
 {
-    float u = hw_exp2(y);
-    if (u == 1.0f) return -y * 0.6931471805599453f;
-    if (u == 0.0f) return 1.0f;
-    return (1.0f - u) * (y * hw_rcp(hw_log2(u)));
+    const float u = hw_exp2(y);
+    const float r = (1.0f - u) * (y * hw_rcp(hw_log2(u)));
+    const float tiny = -y * 0.6931471805599453f;
+    return u == 1.0f ? tiny : (u == 0.0f ? 1.0f : r);
 }
 
 // ---------------------------------------------------------------- global loads

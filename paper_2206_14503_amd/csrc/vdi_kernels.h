@@ -98,6 +98,7 @@ struct CompParams {
     CompInput in[kMaxInputs];
     int k;
     uint32_t npix;
+    int width;                // image width (pixels are p = y * width + x)
     float inv_ref;
     int mode;
     float tau;
@@ -122,7 +123,9 @@ size_t cat_lds_bytes(int k);                      // depth-disjoint path
 // grid_general: blocks of the queue-driven general merge
 void launch_composite(const CompParams& P, int grid_general, hipStream_t s);
 
-// Persistent batched compositing: tiles[i] = {job | pixels << 16, first pixel}
+// Pixels are processed in 8x8 blocks, one per wavefront, numbered row-major
+// over the image (blocks_x = ceil(width / 8)).
+// Persistent batched compositing: tiles[i] = {job | blocks << 16, first block}
 // for the depth-disjoint path (jobs with k <= kCatMaxInputs), then the general
 // merge over every job's queue (all pixels of jobs with larger k).
 void launch_batch(const CompParams* jobs, const uint2* tiles, uint32_t n_tiles, uint32_t* head, int* q_counts,
