@@ -141,7 +141,8 @@ typedef struct {
  *           candidate with the largest count (ties: smaller t).  A list kept
  *           by neither round is regenerated by BISECT.  Lists with at most N
  *           non-transparent samples take the bisection's result directly
- *           (every threshold is feasible there).  Regular layout only. */
+ *           (every threshold is feasible there).  Regular layout only, at
+ *           most 16 bricks per call (else VDI_E_UNSUPPORTED). */
 typedef struct {
     int32_t mode;            /* vdi_tau_mode */
     float tau;

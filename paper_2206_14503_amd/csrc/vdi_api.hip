@@ -144,7 +144,7 @@ static void fill_i32(int* p, int v, size_t n, hipStream_t s)
 
 // Scratch layout of the learned path for nb bricks of npix pixels.
 struct LearnScratch {
-    size_t hist, nnt, cmax, y, list, cnt, rlist, ry, rcnt, svlist, svcnt, total;
+    size_t hist, nnt, cmax, y, list, cnt, rlist, ry, rcnt, svlist, svcnt, sclist, sccnt, total;
 };
 static LearnScratch learn_layout(size_t rays, int nb)
 {
@@ -161,7 +161,9 @@ static LearnScratch learn_layout(size_t rays, int nb)
     L.ry = take(rays * sizeof(float2));
     L.rcnt = take((size_t)nb * sizeof(int));
     L.svlist = take(rays * sizeof(int));
-    L.svcnt = take(sizeof(int));
+    L.svcnt = take((size_t)nb * sizeof(int));
+    L.sclist = take(rays * sizeof(int));
+    L.sccnt = take((size_t)nb * sizeof(int));
     L.total = o;
     return L;
 }
@@ -172,6 +174,8 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
     const size_t npix = (size_t)P.cam.width * P.cam.height;
     const size_t rays = npix * (size_t)k;
     if (rays >= ((size_t)1 << 31)) return fail(VDI_E_UNSUPPORTED, "too many brick-rays for the learned path");
+    if (k > kGenBricksPerLaunch)
+        return fail(VDI_E_UNSUPPORTED, "the learned path takes at most %d bricks per call", kGenBricksPerLaunch);
     LearnScratch Ls = learn_layout(rays, k);
     vdi_status st = ensure_scratch(ctx, Ls.total);
     if (st != VDI_OK) return st;
@@ -188,6 +192,8 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
     Lb.rf_count = (int*)(base + Ls.rcnt);
     Lb.sv_list = (int*)(base + Ls.svlist);
     Lb.sv_count = (int*)(base + Ls.svcnt);
+    Lb.sc_list = (int*)(base + Ls.sclist);
+    Lb.sc_count = (int*)(base + Ls.sccnt);
     Lb.stats = ctx->status + 4;
     Lb.s_ref = tau->feature_scale;
     Lb.tol = tau->fallback_tol;
@@ -196,7 +202,8 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
     if (tau->y) Lb.y = tau->y;
     fill_i32(Lb.fb_count, 0, (size_t)k, s);
     fill_i32(Lb.rf_count, 0, (size_t)k, s);
-    fill_i32(Lb.sv_count, 0, 1, s);
+    fill_i32(Lb.sv_count, 0, (size_t)k, s);
+    fill_i32(Lb.sc_count, 0, (size_t)k, s);
     for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
         int nb = std::min(k - r0, kGenBricksPerLaunch);
         GenBricks B = make_bricks(bricks, out, r0, nb);
@@ -204,12 +211,15 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
         if ((st = launched()) != VDI_OK) return st;
     }
     if (!tau->y) {
-        // the served rays' compacted histograms; y scattered back to brick-ray order
-        launch_mlp_fwd(mlp->w_bf16, mlp->w_f32, Lb.hist, (int)rays, Lb.sv_count, Lb.sv_list, ctx->num_cus * 3,
-                       (float*)(base + Ls.y), nullptr, s);
-        if ((st = launched()) != VDI_OK) return st;
+        // per brick: the served rays' compacted histograms; y scattered back to pixel order
+        for (int r = 0; r < k; ++r) {
+            launch_mlp_fwd(mlp->w_bf16, mlp->w_f32, Lb.hist + (size_t)r * npix * 64, (int)npix, Lb.sv_count + r,
+                           Lb.sv_list + (size_t)r * npix, ctx->num_cus * 3, (float*)(base + Ls.y) + (size_t)r * npix,
+                           nullptr, s);
+            if ((st = launched()) != VDI_OK) return st;
+        }
     }
-    for (int phase = 1; phase <= 3; ++phase) {
+    for (int phase = 1; phase <= 4; ++phase) {
         for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
             int nb = std::min(k - r0, kGenBricksPerLaunch);
             GenBricks B = make_bricks(bricks, out, r0, nb);
@@ -430,6 +440,11 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     P.k = k;
     P.npix = (uint32_t)((size_t)out->width * out->height);
     P.width = out->width;
+    // compact inputs: runs of 64 consecutive pixels (each list contiguous in
+    // pixel order); regular inputs: 8x8 squares
+    P.row_blocks = 0;
+    for (int r = 0; r < k; ++r)
+        if (in[r].layout == VDI_LAYOUT_COMPACT) P.row_blocks = 1;
     P.inv_ref = 1.0f / out->ref_step;
     P.mode = tau->mode;
     P.tau = tau->tau;

@@ -85,6 +85,17 @@ vdi_status check_job(const vdi_job_t& j, int idx)
     return VDI_OK;
 }
 
+// Compact inputs keep each pixel's list contiguous in pixel order, so 64
+// consecutive pixels read one contiguous stretch per input; slot-major
+// (regular) inputs read whole lines either way and 8x8 squares balance the
+// lanes' list lengths better.
+int row_blocks_for(const vdi_t* in, int k)
+{
+    for (int r = 0; r < k; ++r)
+        if (in[r].layout == VDI_LAYOUT_COMPACT) return 1;
+    return 0;
+}
+
 CompParams job_params(vdi_ctx* ctx, const vdi_job_t& j)
 {
     CompParams P;
@@ -104,6 +115,7 @@ CompParams job_params(vdi_ctx* ctx, const vdi_job_t& j)
     P.k = j.k;
     P.npix = (uint32_t)((size_t)j.out.width * j.out.height);
     P.width = j.out.width;
+    P.row_blocks = row_blocks_for(j.in, j.k);
     P.inv_ref = 1.0f / j.out.ref_step;
     P.mode = j.tau.mode;
     P.tau = j.tau.tau;
@@ -165,7 +177,7 @@ vdi_status create_impl(vdi_ctx* ctx, const vdi_job_t* jobs, int n_jobs, const Ti
         }
         // tile size in pixels -> whole 8x8 blocks (at least one)
         const uint32_t per = std::max<uint32_t>(1u, (uint32_t)tile / 64u);
-        const uint32_t nblocks = ((uint32_t)(hp[j].width + 7) / 8u) * ((hp[j].npix / (uint32_t)hp[j].width + 7u) / 8u);
+        const uint32_t nblocks = composite_blocks(hp[j]);
         for (uint32_t b0 = 0; b0 < nblocks; b0 += per) {
             uint32_t nb = std::min<uint32_t>(per, nblocks - b0);
             tiles.push_back(make_uint2((uint32_t)j | (nb << 16), b0));

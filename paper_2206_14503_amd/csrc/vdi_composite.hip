@@ -332,10 +332,13 @@ __device__ void c_scan(R rd, int total, float inv_ref, const float* gam, int cap
 }  // namespace
 
 
-// Pixel of lane t in 8x8 block `blk` (row-major over the image); false
-// outside the image.
+// Pixel of lane t in block `blk`; false outside the image.
 __device__ inline bool block_pixel(const CompParams& P, uint32_t blk, int t, uint32_t& p)
 {
+    if (P.row_blocks) {
+        p = blk * 64u + (uint32_t)t;
+        return p < P.npix;
+    }
     const uint32_t bx = ((uint32_t)P.width + 7u) >> 3;
     const uint32_t x = (blk % bx) * 8u + (uint32_t)(t & 7), y = (blk / bx) * 8u + (uint32_t)(t >> 3);
     const uint32_t h = P.npix / (uint32_t)P.width;
@@ -735,12 +738,18 @@ size_t composite_lds_bytes(int k, int seq_cap)
     return sizeof(InLds) * kMaxInputs + (size_t)kWave * (sb + 14 * (size_t)k);
 }
 
+uint32_t composite_blocks(const CompParams& P)
+{
+    if (P.row_blocks) return (P.npix + 63u) / 64u;
+    return ((uint32_t)(P.width + 7) / 8u) * ((P.npix / (uint32_t)P.width + 7u) / 8u);
+}
+
 size_t cat_lds_bytes(int k) { return sizeof(InLds) * kMaxInputs + (size_t)kWave * 8 * (size_t)k; }
 
 void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
 {
     const size_t lds = composite_lds_bytes(P.k, P.seq_cap);
-    const unsigned blocks = ((unsigned)(P.width + 7) / 8u) * ((P.npix / (unsigned)P.width + 7u) / 8u);
+    const unsigned blocks = composite_blocks(P);
     if (P.k > kCatMaxInputs) {
         hipLaunchKernelGGL(composite_kernel, dim3(blocks), dim3(kWave), lds, s, P);
         return;

@@ -194,9 +194,15 @@ __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float 
     if (n_opaque_out) *n_opaque_out = n_opaque;
 }
 
-// Threshold for one brick-ray and the count it yields.  The bisection runs
-// two levels per scan (midpoint m and both next-level midpoints) and replays
-// the sequential decisions, which it reproduces exactly.
+// Levels of the bisection the first scan speculates on.
+constexpr int kGeoLevels = 6;
+
+// Threshold for one brick-ray and the count it yields.  While every level is
+// feasible, the bisection's midpoints are gmax/2, gmax/4, ...: the first scan
+// carries states at the first kGeoLevels of them and replays the decisions up
+// to (and including) the first infeasible one.  The remaining levels run two
+// per scan (the midpoint m and both next-level midpoints).  Both reproduce
+// the sequential decisions exactly.
 template <typename VT>
 __device__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0,
                            int k1, const float4* tf, int entries, const GenParams& P, float& gamma_out,
@@ -213,21 +219,43 @@ __device__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, floa
     float lo = 0.0f, hi = P.gmax;
     int hi_count = -1;
     int level = 0;
+    {
+        float gg[kGeoLevels];
+        int cg[kGeoLevels];
+#pragma unroll
+        for (int l = 0; l < kGeoLevels; ++l) gg[l] = ldexpf(P.gmax, -(l + 1));
+        int n_opaque = 0;
+        gen_scan<VT, kGeoLevels>(data, g, r, step, l_step, k0, k1, tf, entries, gg, P.max_n, cg, &n_opaque);
+        if (n_opaque <= P.max_n) {
+            // every supersegment starts at a non-transparent sample, so a run
+            // with at most N of them is feasible at every threshold: all
+            // halvings move the upper bracket
+            gamma_out = ldexpf(P.gmax, -P.iters);
+            count_out = -1;
+            if (need_count)
+                count_out = gen_pass<VT, false>(data, g, r, step, l_step, k0, k1, tf, entries, gamma_out, 0, 1 << 30,
+                                                none, nullptr);
+            return;
+        }
+        const int lim = kGeoLevels < P.iters ? kGeoLevels : P.iters;
+        for (int l = 0; l < lim; ++l) {
+            const float m = 0.5f * (lo + hi);   // == gg[l] while every level so far was feasible
+            ++level;
+            if (cg[l] <= P.max_n) {
+                hi = m;
+                hi_count = cg[l];
+            } else {
+                lo = m;
+                break;
+            }
+        }
+    }
     while (level < P.iters) {
         float m = 0.5f * (lo + hi);
         if (level + 2 <= P.iters) {
             float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
             int c3[3];
-            int n_opaque = 0;
-            gen_scan<VT, 3>(data, g, r, step, l_step, k0, k1, tf, entries, g3, P.max_n, c3, &n_opaque);
-            // every supersegment starts at a non-transparent sample, so a run
-            // with at most N of them is feasible at every threshold: all
-            // halvings move the upper bracket
-            if (level == 0 && c3[0] <= P.max_n && c3[1] <= P.max_n && n_opaque <= P.max_n) {
-                hi = ldexpf(P.gmax, -P.iters);
-                hi_count = -1;
-                break;
-            }
+            gen_scan<VT, 3>(data, g, r, step, l_step, k0, k1, tf, entries, g3, P.max_n, c3, nullptr);
             if (c3[0] <= P.max_n) {
                 hi = m;
                 hi_count = c3[0];
@@ -358,6 +386,52 @@ void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B
 // bins agree exactly), the number of non-transparent samples and the count at
 // the smallest threshold the bisection can return (saturating at N+1).
 
+// In-band test of the learned path: with m = min(N, cmax), a count c is kept
+// iff m - floor(tol * m) <= c <= N.
+__device__ inline int band_lo(int max_n, int cmax, float tol)
+{
+    const int m = min(max_n, cmax);
+    return m - (int)floorf(tol * (float)m + 1e-6f);
+}
+
+// Largest in-band count among NC candidates (ties: the first listed); -1 if none.
+template <int NC>
+__device__ inline int pick_in_band(const int* c, int max_n, int lo)
+{
+    int best = -1;
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+        if (c[j] <= max_n && c[j] >= lo && (best < 0 || c[j] > c[best])) best = j;
+    return best;
+}
+
+// Writes a finished list's unused slots, count and threshold.
+__device__ inline void finish_list(const GenBrick& br, uint32_t pix, uint32_t npix, int max_n, int c, float gm)
+{
+    for (int j = c; j < max_n; ++j) {
+        size_t slot = (size_t)j * npix + pix;
+        br.color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        br.depth[slot] = make_float2(0.0f, 0.0f);
+    }
+    br.count[pix] = c;
+    if (br.gamma) br.gamma[pix] = gm;
+}
+
+struct RayRun {
+    Ray r;
+    int k0, k1;
+};
+
+__device__ inline RayRun ray_run(const GenParams& P, const GenBrick& br, int x, int y)
+{
+    RayRun q;
+    q.r = make_ray(P.cam, x, y);
+    int ns = ray_samples(q.r, P.step);
+    q.k0 = q.k1 = 0;
+    if (ns > 0) owned_run(q.r, P.step, ns, P.n, br.lo, br.hi, q.k0, q.k1);
+    return q;
+}
+
 template <typename VT>
 __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
@@ -412,13 +486,22 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
     Lb.cmax[ray] = count;
     size_t row = ray;
     if (Lb.sv_list) {
-        // only rays the regressor serves (more than N non-transparent samples)
-        // get a histogram row, compacted in order of arrival
-        const bool served = k1 > k0 && m > P.max_n;
-        const int pos = wave_append(Lb.sv_count, served);
+        // generation: an empty list is finished here; lists with at most N
+        // non-transparent samples (every threshold feasible) are queued for
+        // the write at the smallest threshold; only the rays the regressor
+        // serves get a histogram row, compacted per brick in order of arrival
+        const uint32_t pix = (uint32_t)(ray - (size_t)brick * npix);
+        const bool empty = k1 <= k0 || m == 0;
+        const bool served = !empty && m > P.max_n;
+        const bool shortcut = !empty && !served;
+        wave_append(&Lb.stats[LEARN_EMPTY], empty);
+        const int spos = wave_append(&Lb.sc_count[brick], shortcut);
+        const int pos = wave_append(&Lb.sv_count[brick], served);
+        if (empty) finish_list(br, pix, npix, P.max_n, 0, gmin);
+        if (shortcut) Lb.sc_list[(size_t)brick * npix + spos] = (int)pix;
         if (!served) return;
-        Lb.sv_list[pos] = (int)ray;
-        row = (size_t)pos;
+        Lb.sv_list[(size_t)brick * npix + pos] = (int)pix;
+        row = (size_t)brick * npix + (size_t)pos;
     }
     uint32_t* hrow = (uint32_t*)(Lb.hist + row * 64);
     for (int j = 0; j < 64; j += 2) {
@@ -426,52 +509,6 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
         float f1 = (float)hs[j + 1][threadIdx.x] / Lb.s_ref;
         hrow[j / 2] = (uint32_t)bf16_bits(f0) | ((uint32_t)bf16_bits(f1) << 16);
     }
-}
-
-// In-band test of the learned path: with m = min(N, cmax), a count c is kept
-// iff m - floor(tol * m) <= c <= N.
-__device__ inline int band_lo(int max_n, int cmax, float tol)
-{
-    const int m = min(max_n, cmax);
-    return m - (int)floorf(tol * (float)m + 1e-6f);
-}
-
-// Largest in-band count among NC candidates (ties: the first listed); -1 if none.
-template <int NC>
-__device__ inline int pick_in_band(const int* c, int max_n, int lo)
-{
-    int best = -1;
-#pragma unroll
-    for (int j = 0; j < NC; ++j)
-        if (c[j] <= max_n && c[j] >= lo && (best < 0 || c[j] > c[best])) best = j;
-    return best;
-}
-
-// Writes a finished list's unused slots, count and threshold.
-__device__ inline void finish_list(const GenBrick& br, uint32_t pix, uint32_t npix, int max_n, int c, float gm)
-{
-    for (int j = c; j < max_n; ++j) {
-        size_t slot = (size_t)j * npix + pix;
-        br.color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        br.depth[slot] = make_float2(0.0f, 0.0f);
-    }
-    br.count[pix] = c;
-    if (br.gamma) br.gamma[pix] = gm;
-}
-
-struct RayRun {
-    Ray r;
-    int k0, k1;
-};
-
-__device__ inline RayRun ray_run(const GenParams& P, const GenBrick& br, int x, int y)
-{
-    RayRun q;
-    q.r = make_ray(P.cam, x, y);
-    int ns = ray_samples(q.r, P.step);
-    q.k0 = q.k1 = 0;
-    if (ns > 0) owned_run(q.r, P.step, ns, P.n, br.lo, br.hi, q.k0, q.k1);
-    return q;
 }
 
 // Round one of the learned threshold.  The regressed log2 threshold y and four
@@ -491,34 +528,16 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
 
     const GenBrick& br = B.b[blockIdx.z];
     const int brick = B.first + blockIdx.z;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int x = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
-    const int y = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
-    if (x >= P.cam.width || y >= P.cam.height) return;
-    const uint32_t pix = (uint32_t)y * (uint32_t)P.cam.width + (uint32_t)x;
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
-    const size_t ray = (size_t)brick * npix + pix;
-
+    const uint32_t n_q = (uint32_t)Lb.sv_count[brick];
     const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
     const VT* data = (const VT*)br.data;
-    const RayRun q = ray_run(P, br, x, y);
-
-    const float gmin = ldexpf(P.gmax, -P.iters);
-    const int m = Lb.nnt[ray];
-    GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
-    float gm = gmin;
-    int c = 0;
-    int kind = 0;   // LEARN_KEPT, LEARN_SHORTCUT, LEARN_FALLBACK, LEARN_EMPTY or LEARN_REFINE
-    float2 bracket = make_float2(0.0f, 0.0f);
-    if (q.k1 <= q.k0 || m == 0) {
-        kind = LEARN_EMPTY;
-    } else if (m <= P.max_n) {
-        // every threshold is feasible: the bisection would return its lower end
-        c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, gmin, 0,
-                                      1 << 30, o, nullptr);
-        kind = LEARN_SHORTCUT;
-    } else {
-        const float lg_hi = log2f(P.gmax), lg_lo = lg_hi - (float)P.iters;
+    const float lg_hi = log2f(P.gmax), lg_lo = lg_hi - (float)P.iters;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n_q; idx += gridDim.x * blockDim.x) {
+        const uint32_t pix = (uint32_t)Lb.sv_list[(size_t)brick * npix + idx];
+        const size_t ray = (size_t)brick * npix + pix;
+        const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
+        const RayRun q = ray_run(P, br, x, y);
         const float yv = Lb.y[ray];
         const float dl[5] = { 0.0f, -0.25f, 0.25f, -0.5f, 0.5f };
         float y5[5], g5[5];
@@ -531,12 +550,9 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
         gen_scan<VT, 5>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, g5, P.max_n, c5, nullptr);
         const int lo = band_lo(P.max_n, Lb.cmax[ray], Lb.tol);
         const int best = pick_in_band<5>(c5, P.max_n, lo);
-        if (best >= 0) {
-            gm = g5[best];
-            c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, gm, 0,
-                                          1 << 30, o, nullptr);
-            kind = LEARN_KEPT;
-        } else {
+        int kind = LEARN_KEPT;
+        float2 bracket = make_float2(0.0f, 0.0f);
+        if (best < 0) {
             // candidates in threshold order: d = -1/2, -1/4, 0, 1/4, 1/2
             const int ord[5] = { 3, 1, 0, 2, 4 };
             int pick = -1;
@@ -553,20 +569,48 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
             }
             kind = pick >= 0 ? LEARN_REFINE : LEARN_FALLBACK;
         }
+        const int fpos = wave_append(&Lb.fb_count[brick], kind == LEARN_FALLBACK);
+        if (kind == LEARN_FALLBACK) Lb.fb_list[(size_t)brick * npix + fpos] = (int)pix;
+        const int rpos = wave_append(&Lb.rf_count[brick], kind == LEARN_REFINE);
+        if (kind == LEARN_REFINE) {
+            Lb.rf_list[(size_t)brick * npix + rpos] = (int)pix;
+            Lb.rf_y[(size_t)brick * npix + rpos] = bracket;
+        }
+        wave_append(&Lb.stats[LEARN_KEPT], kind == LEARN_KEPT);
+        wave_append(&Lb.stats[LEARN_FALLBACK], kind == LEARN_FALLBACK);
+        if (kind != LEARN_KEPT) continue;
+        GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
+        const int c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries,
+                                                g5[best], 0, 1 << 30, o, nullptr);
+        finish_list(br, pix, npix, P.max_n, c, g5[best]);
     }
-    // every active lane of the wave reaches this point (lanes of pixels
-    // outside the image returned at the top and take no part in the ballots)
-    const int fpos = wave_append(&Lb.fb_count[brick], kind == LEARN_FALLBACK);
-    if (kind == LEARN_FALLBACK) Lb.fb_list[(size_t)brick * npix + fpos] = (int)pix;
-    const int rpos = wave_append(&Lb.rf_count[brick], kind == LEARN_REFINE);
-    if (kind == LEARN_REFINE) {
-        Lb.rf_list[(size_t)brick * npix + rpos] = (int)pix;
-        Lb.rf_y[(size_t)brick * npix + rpos] = bracket;
+}
+
+// Lists with at most N non-transparent samples: the bisection's result is the
+// smallest threshold (every threshold is feasible), written directly.
+template <typename VT>
+__global__ __launch_bounds__(256) void shortcut_kernel(GenParams P, GenBricks B, LearnBufs Lb)
+{
+    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
+    for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
+    __syncthreads();
+    const GenBrick& br = B.b[blockIdx.z];
+    const int brick = B.first + blockIdx.z;
+    const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
+    const uint32_t n_q = (uint32_t)Lb.sc_count[brick];
+    const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
+    const VT* data = (const VT*)br.data;
+    const float gmin = ldexpf(P.gmax, -P.iters);
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n_q; idx += gridDim.x * blockDim.x) {
+        const uint32_t pix = (uint32_t)Lb.sc_list[(size_t)brick * npix + idx];
+        const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
+        const RayRun q = ray_run(P, br, x, y);
+        GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
+        const int c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, gmin,
+                                                0, 1 << 30, o, nullptr);
+        wave_append(&Lb.stats[LEARN_SHORTCUT], true);
+        finish_list(br, pix, npix, P.max_n, c, gmin);
     }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) wave_append(&Lb.stats[t], kind == t);
-    if (kind == LEARN_FALLBACK || kind == LEARN_REFINE) return;
-    finish_list(br, pix, npix, P.max_n, c, gm);
 }
 
 // Round two for the queued rays of each brick: five thresholds evenly inside
@@ -645,17 +689,19 @@ static void launch_learned_t(int phase, const GenParams& P, const GenBricks& B, 
                              hipStream_t s)
 {
     dim3 grid((P.cam.width + 15) / 16, (P.cam.height + 15) / 16, nb);
-    if (phase == 0) hipLaunchKernelGGL(features_kernel<VT>, grid, dim3(256), tf_lds(P), s, P, B, L);
-    if (phase == 1) hipLaunchKernelGGL(learned_kernel<VT>, grid, dim3(256), tf_lds(P), s, P, B, L);
-    if (phase == 2 || phase == 3) {
-        // queue-driven: grid-stride over each brick's queue, enough blocks to
-        // fill the device whatever the queue length turns out to be
-        size_t npix = (size_t)P.cam.width * P.cam.height;
-        unsigned bx = (unsigned)std::min<size_t>((npix + 255) / 256, (size_t)L.blocks_per_brick);
-        dim3 g2(bx, 1, nb);
-        if (phase == 2) hipLaunchKernelGGL(refine_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
-        else hipLaunchKernelGGL(fallback_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
+    if (phase == 0) {
+        hipLaunchKernelGGL(features_kernel<VT>, grid, dim3(256), tf_lds(P), s, P, B, L);
+        return;
     }
+    // queue-driven: grid-stride over each brick's queue, enough blocks to
+    // fill the device whatever the queue length turns out to be
+    size_t npix = (size_t)P.cam.width * P.cam.height;
+    unsigned bx = (unsigned)std::min<size_t>((npix + 255) / 256, (size_t)L.blocks_per_brick);
+    dim3 g2(bx, 1, nb);
+    if (phase == 1) hipLaunchKernelGGL(learned_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
+    if (phase == 2) hipLaunchKernelGGL(refine_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
+    if (phase == 3) hipLaunchKernelGGL(fallback_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
+    if (phase == 4) hipLaunchKernelGGL(shortcut_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
 }
 
 void launch_learned(int phase, int dtype, const GenParams& P, const GenBricks& B, int nb, const LearnBufs& L,

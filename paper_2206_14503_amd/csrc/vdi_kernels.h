@@ -59,8 +59,10 @@ struct LearnBufs {
     int* rf_list;        // [nb][npix] pixels queued for round two, per brick
     float2* rf_y;        // [nb][npix] their log2 brackets
     int* rf_count;       // [nb]
-    int* sv_list;        // optional [nb*npix]: brick-ray index of each served ray (hist row order)
-    int* sv_count;       // their number
+    int* sv_list;        // optional [nb][npix]: pixels the regressor serves, per brick (hist row order)
+    int* sv_count;       // [nb]
+    int* sc_list;        // [nb][npix]: pixels whose every threshold is feasible, per brick
+    int* sc_count;       // [nb]
     int* stats;          // [kLearnStats]
     float s_ref;
     float tol;
@@ -69,7 +71,8 @@ struct LearnBufs {
 
 // kind: 0 = search + regular write, 1 = search only, 2 = compact write
 void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B, int nb, hipStream_t s);
-// phase 0: features, 1: learned round one, 2: round two, 3: fallback bisection
+// phase 0: features (finishes empty lists, queues the others), 1: learned
+// round one, 2: round two, 3: fallback bisection, 4: all-feasible lists
 void launch_learned(int phase, int dtype, const GenParams& P, const GenBricks& B, int nb, const LearnBufs& L,
                     hipStream_t s);
 void launch_rays(const Cam& cam, float step, float* o, float* d, float* tn, float* tf, int* ns, hipStream_t s);
@@ -99,6 +102,7 @@ struct CompParams {
     int k;
     uint32_t npix;
     int width;                // image width (pixels are p = y * width + x)
+    int row_blocks;           // 1: a block is 64 consecutive pixels; 0: an 8x8 square
     float inv_ref;
     int mode;
     float tau;
@@ -122,9 +126,11 @@ size_t composite_lds_bytes(int k, int seq_cap);   // general merge
 size_t cat_lds_bytes(int k);                      // depth-disjoint path
 // grid_general: blocks of the queue-driven general merge
 void launch_composite(const CompParams& P, int grid_general, hipStream_t s);
+uint32_t composite_blocks(const CompParams& P);   // 64-pixel blocks of the image
 
-// Pixels are processed in 8x8 blocks, one per wavefront, numbered row-major
-// over the image (blocks_x = ceil(width / 8)).
+// Pixels are processed in blocks of 64, one per wavefront: 8x8 squares
+// numbered row-major over the image (blocks_x = ceil(width / 8)), or, with
+// row_blocks, runs of 64 consecutive pixels.
 // Persistent batched compositing: tiles[i] = {job | blocks << 16, first block}
 // for the depth-disjoint path (jobs with k <= kCatMaxInputs), then the general
 // merge over every job's queue (all pixels of jobs with larger k).

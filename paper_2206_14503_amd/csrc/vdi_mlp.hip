@@ -35,10 +35,33 @@ __device__ inline uint16_t f2bf(float x)
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU(z) = z * Phi(z) with the normal CDF Phi(z) = 1 - erfc(z / sqrt 2) / 2.
+// erfc(x) for x >= 0 by the rational approximation of Abramowitz and Stegun,
+// formula 7.1.26 (t = 1 / (1 + p x), erfc(x) = t (a1 + t (a2 + ... t a5)) exp(-x^2),
+// absolute error at most 1.5e-7), evaluated on |z| with Phi(-z) = 1 - Phi(z);
+// exp(-x^2) is also the density term of the derivative.
+__device__ inline void normal_parts(float z, float& cdf, float& pdf)
+{
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+    const float poly =
+        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+    const float e = __builtin_amdgcn_exp2f(-(x * x) * 1.4426950408889634f);   // exp(-x^2) = exp(-z^2 / 2)
+    const float half_erfc = 0.5f * poly * e;
+    cdf = z >= 0.0f ? 1.0f - half_erfc : half_erfc;
+    pdf = e * 0.39894228040143268f;                                          // 1 / sqrt(2 pi)
+}
+__device__ inline float gelu(float z)
+{
+    float c, d;
+    normal_parts(z, c, d);
+    return z * c;
+}
 __device__ inline float gelu_grad(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+    float c, d;
+    normal_parts(z, c, d);
+    return fmaf(z, d, c);
 }
 
 __device__ inline floatx4 mfma16(bf16x4 a, bf16x4 b, floatx4 c)
