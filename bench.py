@@ -2,8 +2,8 @@
 
 A step is one frame of the whole path on the FHD workload: generate the 8
 sub-VDIs of a 512^3 fp32 volume split into z-slabs (per-ray bisection of the
-threshold to N=20, compact layout), composite them into one N=20 VDI and render
-it from the original view.  The headline metric is composited VDI pixels per
+threshold to N=20, regular slot-major layout; --layout compact for the compact
+one), composite them into one N=20 VDI and render it from the original view.  The headline metric is composited VDI pixels per
 second of that step.  Further legs (same JSON line):
   large    -- 1024^3 fp16 volume in 16 bricks (4x2x2): generate + composite,
               and the composite alone on maximally interleaved dense lists
@@ -412,7 +412,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--layout", choices=["compact", "regular"], default="compact")
+    ap.add_argument("--layout", choices=["compact", "regular"], default="regular")
     ap.add_argument("--legs", default="fhd,large,learned,batched")
     ap.add_argument("--learn-seeds", type=int, default=32)
     ap.add_argument("--learn-epochs", type=int, default=8)

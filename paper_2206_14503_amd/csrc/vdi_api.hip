@@ -440,11 +440,10 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     P.k = k;
     P.npix = (uint32_t)((size_t)out->width * out->height);
     P.width = out->width;
-    // compact inputs: runs of 64 consecutive pixels (each list contiguous in
-    // pixel order); regular inputs: 8x8 squares
-    P.row_blocks = 0;
+    P.row_blocks = 1;
+    P.cache_bound = 0;
     for (int r = 0; r < k; ++r)
-        if (in[r].layout == VDI_LAYOUT_COMPACT) P.row_blocks = 1;
+        if (in[r].layout == VDI_LAYOUT_COMPACT) P.cache_bound = 1;
     P.inv_ref = 1.0f / out->ref_step;
     P.mode = tau->mode;
     P.tau = tau->tau;

@@ -85,11 +85,7 @@ vdi_status check_job(const vdi_job_t& j, int idx)
     return VDI_OK;
 }
 
-// Compact inputs keep each pixel's list contiguous in pixel order, so 64
-// consecutive pixels read one contiguous stretch per input; slot-major
-// (regular) inputs read whole lines either way and 8x8 squares balance the
-// lanes' list lengths better.
-int row_blocks_for(const vdi_t* in, int k)
+int any_compact(const vdi_t* in, int k)
 {
     for (int r = 0; r < k; ++r)
         if (in[r].layout == VDI_LAYOUT_COMPACT) return 1;
@@ -115,7 +111,8 @@ CompParams job_params(vdi_ctx* ctx, const vdi_job_t& j)
     P.k = j.k;
     P.npix = (uint32_t)((size_t)j.out.width * j.out.height);
     P.width = j.out.width;
-    P.row_blocks = row_blocks_for(j.in, j.k);
+    P.row_blocks = 1;
+    P.cache_bound = any_compact(j.in, j.k);
     P.inv_ref = 1.0f / j.out.ref_step;
     P.mode = j.tau.mode;
     P.tau = j.tau.tau;
@@ -159,7 +156,11 @@ vdi_status create_impl(vdi_ctx* ctx, const vdi_job_t* jobs, int n_jobs, const Ti
     for (int i = 0; i < n_jobs; ++i) {
         hp[i] = job_params(ctx, jobs[i]);
         lds_gen = std::max(lds_gen, composite_lds_bytes(hp[i].k, hp[i].seq_cap));
-        if (hp[i].k <= kCatMaxInputs) lds = std::max(lds, cat_lds_bytes(hp[i].k));
+        // compact inputs run at the general merge's occupancy (see launch_composite)
+        if (hp[i].k <= kCatMaxInputs)
+            lds = std::max(lds, hp[i].cache_bound ? std::max(cat_lds_bytes(hp[i].k),
+                                                             composite_lds_bytes(hp[i].k, hp[i].seq_cap))
+                                                  : cat_lds_bytes(hp[i].k));
         work[i] = (double)hp[i].k * hp[i].out_n * hp[i].npix;
         q_off[i] = q_total;
         q_total += hp[i].k <= kCatMaxInputs ? hp[i].npix : 0;

@@ -371,6 +371,10 @@ __device__ inline void reject_pixel(const CompParams& P, uint32_t p)
     if (P.out_gamma) P.out_gamma[p] = 0.0f;
 }
 
+// Levels of the compositing bisection its first scan speculates on (on the
+// FHD frame the composited threshold has median 2^-3.9).
+constexpr int kCompGeoLevels = 4;
+
 // Re-segmentation of pixel p's merged list (read through rd, `total`
 // elements): pass-through when it fits (R17), else the fixed threshold or the
 // bisection (two levels per scan), then the zero-filled tail.  With VALIDATE
@@ -410,18 +414,32 @@ __device__ void resegment(const CompParams& P, const R& rd0, int total, uint32_t
     } else {
         float lo = 0.0f, hi = P.gmax;
         int level = 0;
-        bool first = true;
-        while (level + 2 <= P.iters) {
+        {
+            // first scan: the midpoints gmax/2 .. gmax/16 the bisection tests
+            // while every level is feasible, replayed up to the first
+            // infeasible one (this scan also validates the list)
+            float gg[kCompGeoLevels];
+            int cg[kCompGeoLevels];
+#pragma unroll
+            for (int l = 0; l < kCompGeoLevels; ++l) gg[l] = ldexpf(P.gmax, -(l + 1));
+            c_scan<kCompGeoLevels, false, VALIDATE>(rd0, total, P.inv_ref, gg, 0, P.out_n, o, cg, &bad);
+            const int lim = kCompGeoLevels < P.iters ? kCompGeoLevels : P.iters;
+            for (int l = 0; l < lim && !bad; ++l) {
+                const float m = 0.5f * (lo + hi);
+                ++level;
+                if (cg[l] <= P.out_n) {
+                    hi = m;
+                } else {
+                    lo = m;
+                    break;
+                }
+            }
+        }
+        while (!bad && level + 2 <= P.iters) {
             float m = 0.5f * (lo + hi);
             float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
             int c3[3];
-            if (VALIDATE && first) {
-                c_scan<3, false, true>(rd0, total, P.inv_ref, g3, 0, P.out_n, o, c3, &bad);
-                if (bad) break;
-            } else {
-                c_scan<3, false, false>(rd0, total, P.inv_ref, g3, 0, P.out_n, o, c3, nullptr);
-            }
-            first = false;
+            c_scan<3, false, false>(rd0, total, P.inv_ref, g3, 0, P.out_n, o, c3, nullptr);
             if (c3[0] <= P.out_n) {
                 hi = m;
                 if (c3[1] <= P.out_n) hi = g3[1];
@@ -436,8 +454,7 @@ __device__ void resegment(const CompParams& P, const R& rd0, int total, uint32_t
         if (!bad && level < P.iters) {
             float m = 0.5f * (lo + hi);
             int c1[1];
-            if (VALIDATE && first) c_scan<1, false, true>(rd0, total, P.inv_ref, &m, 0, P.out_n, o, c1, &bad);
-            else c_scan<1, false, false>(rd0, total, P.inv_ref, &m, 0, P.out_n, o, c1, nullptr);
+            c_scan<1, false, false>(rd0, total, P.inv_ref, &m, 0, P.out_n, o, c1, nullptr);
             if (c1[0] <= P.out_n) hi = m;
             else lo = m;
         }
@@ -755,7 +772,13 @@ void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
         return;
     }
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(1), 0, s, (uint32_t*)P.q_count, 0u);
-    hipLaunchKernelGGL(composite_cat_kernel, dim3(blocks), dim3(kWave), cat_lds_bytes(P.k), s, P);
+    // Compact inputs: each lane walks its own contiguous list, reading 16 of
+    // every 128 bytes per step, so a line is reused over eight steps only if
+    // it stays cached; fewer resident waves (the general merge's LDS
+    // footprint) keep it cached, and measured faster.  Slot-major inputs use
+    // whole lines per step and prefer full occupancy.
+    const size_t lds_cat = P.cache_bound ? std::max(lds, cat_lds_bytes(P.k)) : cat_lds_bytes(P.k);
+    hipLaunchKernelGGL(composite_cat_kernel, dim3(blocks), dim3(kWave), lds_cat, s, P);
     const unsigned g2 = std::max(1u, std::min(blocks, (unsigned)grid_general));
     hipLaunchKernelGGL(composite_queue_kernel, dim3(g2), dim3(kWave), lds, s, P);
 }

@@ -103,6 +103,7 @@ struct CompParams {
     uint32_t npix;
     int width;                // image width (pixels are p = y * width + x)
     int row_blocks;           // 1: a block is 64 consecutive pixels; 0: an 8x8 square
+    int cache_bound;          // compact inputs: launch at the general merge's occupancy
     float inv_ref;
     int mode;
     float tau;

@@ -80,10 +80,17 @@ __device__ inline bf16x4 load4(const uint16_t* p)
 // acts per row: z1[128] f32, z2[128] f32, h1[128] bf16 (64 words), h2[128] bf16 (64 words)
 constexpr int kActFloats = 128 + 128 + 64 + 64;
 
-// Forward pass.  Persistent: each block stages the weights in LDS once and
-// walks row tiles of 64 (4 waves x 16 rows) with a grid stride.  rows_dev,
-// when given, holds the row count on the device; out_idx, when given, maps
-// row r to its output element y[out_idx[r]].
+// Forward pass.  Persistent: each block stages W1 and W2 in LDS once and
+// walks row tiles with a grid stride; a wave takes 32 rows per step (two
+// 16-row fragments sharing every weight fragment it reads).  Each layer is
+// computed transposed, Z^T = W X^T (A operand: a 16x16 weight tile, B: the
+// rows), so the accumulator a lane holds -- Z[row i][units 4g .. 4g+3] -- is
+// exactly the B fragment of the next layer after GELU and bf16 rounding: the
+// hidden activations never leave registers.  rows_dev, when given, holds the
+// row count on the device; out_idx, when given, maps row r to y[out_idx[r]].
+constexpr int kFwdRowsPerWave = 32;
+constexpr int kFwdRowsPerBlock = 4 * kFwdRowsPerWave;
+
 __global__ __launch_bounds__(256) void mlp_fwd_kernel(const uint16_t* __restrict__ wb, const float* __restrict__ wf,
                                                       const uint16_t* __restrict__ x, int rows_host,
                                                       const int* __restrict__ rows_dev, const int* __restrict__ out_idx,
@@ -91,83 +98,94 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const uint16_t* __restrict
 {
     __shared__ __align__(16) uint16_t sW1[kHid * kIn];
     __shared__ __align__(16) uint16_t sW2[kHid * kHid];
-    __shared__ __align__(16) uint16_t sH[4][16][kHid + 8];
     for (int e = threadIdx.x; e < kHid * kIn / 8; e += blockDim.x)
         ((uint4*)sW1)[e] = ((const uint4*)(wb + oW1))[e];
     for (int e = threadIdx.x; e < kHid * kHid / 8; e += blockDim.x)
         ((uint4*)sW2)[e] = ((const uint4*)(wb + oW2))[e];
+    __syncthreads();
     const int rows = rows_dev ? *rows_dev : rows_host;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
-    for (int tile = blockIdx.x; tile * kRowsPerBlock < rows; tile += gridDim.x) {
-        __syncthreads();   // weights staged; the previous tile's sH is consumed
-        const int r0 = tile * kRowsPerBlock + w * 16;
-        const int ra = r0 + i;   // row of this lane's A fragments
-        bf16x4 a[4];
+    const float b3 = wf[oB3];
+    for (int base = blockIdx.x * kFwdRowsPerBlock; base < rows; base += gridDim.x * kFwdRowsPerBlock) {
+        const int r0 = base + w * kFwdRowsPerWave;
+        int row[2];
+        bf16x4 xa[2][4];
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-            a[ks] = ra < rows ? load4(x + (size_t)ra * kIn + ks * 16 + g * 4) : bf16x4{0, 0, 0, 0};
-        // layer 1: z1 = x W1^T + b1
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt) {
-            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int tt = 0; tt < 2; ++tt) {
+            row[tt] = r0 + tt * 16 + i;
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks)
-                acc = mfma16(a[ks], load4(sW1 + (nt * 16 + i) * kIn + ks * 16 + g * 4), acc);
-            const int col = nt * 16 + i;
-            const float bias = wf[oB1 + col];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = r0 + 4 * g + v;
-                float z = acc[v] + bias;
-                uint16_t hb = f2bf(gelu(z));
-                sH[w][4 * g + v][col] = hb;
-                if (acts && row < rows) {
-                    float* ar = acts + (size_t)row * kActFloats;
-                    ar[col] = z;
-                    ((uint16_t*)(ar + 256))[col] = hb;
-                }
-            }
+                xa[tt][ks] = row[tt] < rows ? load4(x + (size_t)row[tt] * kIn + ks * 16 + g * 4) : bf16x4{0, 0, 0, 0};
         }
-        __syncthreads();
-        bf16x4 a2[8];
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) a2[ks] = load4(&sH[w][i][ks * 16 + g * 4]);
-        // layer 2 and the output dot product
-        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        // layer 1: Z1^T = W1 X^T; lane (g, i) gets units nt*16 + 4g .. +3 of row i
+        bf16x4 h1[2][8];
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) {
-            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            floatx4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
-            for (int ks = 0; ks < 8; ++ks)
-                acc = mfma16(a2[ks], load4(sW2 + (nt * 16 + i) * kHid + ks * 16 + g * 4), acc);
-            const int col = nt * 16 + i;
-            const float bias = wf[oB2 + col];
-            const float w3 = bf2f(wb[oW3 + col]);
+            for (int ks = 0; ks < 4; ++ks) {
+                const bf16x4 wa = load4(sW1 + (nt * 16 + i) * kIn + ks * 16 + g * 4);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = r0 + 4 * g + v;
-                float z = acc[v] + bias;
-                uint16_t hb = f2bf(gelu(z));
-                part[v] = fmaf(bf2f(hb), w3, part[v]);
-                if (acts && row < rows) {
-                    float* ar = acts + (size_t)row * kActFloats;
-                    ar[128 + col] = z;
-                    ((uint16_t*)(ar + 320))[col] = hb;
+                for (int tt = 0; tt < 2; ++tt) acc[tt] = mfma16(wa, xa[tt][ks], acc[tt]);
+            }
+            const int u0 = nt * 16 + 4 * g;
+            const float4 bias = *(const float4*)(wf + oB1 + u0);
+            const float bv[4] = { bias.x, bias.y, bias.z, bias.w };
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                float z[4];
+                uint16_t hb[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    z[v] = acc[tt][v] + bv[v];
+                    hb[v] = f2bf(gelu(z[v]));
+                }
+                h1[tt][nt] = bf16x4{(short)hb[0], (short)hb[1], (short)hb[2], (short)hb[3]};
+                if (acts && row[tt] < rows) {
+                    float* ar = acts + (size_t)row[tt] * kActFloats;
+                    *(float4*)(ar + u0) = make_float4(z[0], z[1], z[2], z[3]);
+                    *(bf16x4*)((uint16_t*)(ar + 256) + u0) = h1[tt][nt];
                 }
             }
         }
+        // layer 2: Z2^T = W2 H1^T, then y = w3 . GELU(Z2) + b3
+        float part[2] = {0.0f, 0.0f};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
+        for (int nt = 0; nt < 8; ++nt) {
+            floatx4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
-            for (int d = 8; d >= 1; d >>= 1) part[v] += __shfl_xor(part[v], d, 64);
-        }
-        if (i == 0) {
-            const float b3 = wf[oB3];
+            for (int ks = 0; ks < 8; ++ks) {
+                const bf16x4 wa = load4(sW2 + (nt * 16 + i) * kHid + ks * 16 + g * 4);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = r0 + 4 * g + v;
-                if (row < rows) y[out_idx ? out_idx[row] : row] = part[v] + b3;
+                for (int tt = 0; tt < 2; ++tt) acc[tt] = mfma16(wa, h1[tt][ks], acc[tt]);
             }
+            const int u0 = nt * 16 + 4 * g;
+            const float4 bias = *(const float4*)(wf + oB2 + u0);
+            const float bv[4] = { bias.x, bias.y, bias.z, bias.w };
+            const bf16x4 w3 = load4(wb + oW3 + u0);
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                float z[4];
+                uint16_t hb[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    z[v] = acc[tt][v] + bv[v];
+                    hb[v] = f2bf(gelu(z[v]));
+                    part[tt] = fmaf(bf2f(hb[v]), bf2f((uint16_t)w3[v]), part[tt]);
+                }
+                if (acts && row[tt] < rows) {
+                    float* ar = acts + (size_t)row[tt] * kActFloats;
+                    *(float4*)(ar + 128 + u0) = make_float4(z[0], z[1], z[2], z[3]);
+                    *(bf16x4*)((uint16_t*)(ar + 320) + u0) = bf16x4{(short)hb[0], (short)hb[1], (short)hb[2], (short)hb[3]};
+                }
+            }
+        }
+        // row i's 128 units are spread over the four lanes i, i+16, i+32, i+48
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            part[tt] += __shfl_xor(part[tt], 16, 64);
+            part[tt] += __shfl_xor(part[tt], 32, 64);
+            if (g == 0 && row[tt] < rows) y[out_idx ? out_idx[row[tt]] : row[tt]] = part[tt] + b3;
         }
     }
 }
@@ -395,7 +413,7 @@ int mlp_rows_per_block() { return kRowsPerBlock; }
 void launch_mlp_fwd(const uint16_t* wb, const float* wf, const uint16_t* x, int rows, const int* rows_dev,
                     const int* out_idx, int max_blocks, float* y, float* acts, hipStream_t s)
 {
-    int nb = (rows + kRowsPerBlock - 1) / kRowsPerBlock;
+    int nb = (rows + kFwdRowsPerBlock - 1) / kFwdRowsPerBlock;
     nb = std::max(1, std::min(nb, max_blocks));
     hipLaunchKernelGGL(mlp_fwd_kernel, dim3(nb), dim3(256), 0, s, wb, wf, x, rows, rows_dev, out_idx, y, acts);
 }
