@@ -8,8 +8,9 @@ second of that step.  Further legs (same JSON line):
   large    -- 1024^3 fp16 volume in 16 bricks (4x2x2): generate + composite,
               and the composite alone on maximally interleaved dense lists
               (16 x 20 supersegments per pixel), the HBM-bound case;
-  learned  -- learned vs plain threshold search on held-out tiny volumes
-              (regressor trained here with the project's kernels);
+  learned  -- learned vs plain threshold search on held-out tiny volumes (N=8)
+              and on held-out FHD-generator volumes (N=20), the regressor
+              trained here with the project's kernels;
   batched  -- 64 composites of mixed size, k and N in one persistent launch
               replayed from a hipGraph: jobs/s and per-job latency.
 Printed: ONE JSON line on stdout (progress goes to stderr).
@@ -273,14 +274,23 @@ def leg_large(args, result):
 # ---------------------------------------------------------------- learned threshold
 
 def leg_learned(args, result):
+    from paper_2206_14503_amd import learned
+
+    for cfg, key, seeds in ((learned.LearnedConfig(), "learned", range(100, 104)),
+                            (learned.LearnedConfig.fhd(), "learned_fhd", range(100, 102))):
+        if key == "learned_fhd" and not args.learn_fhd:
+            continue
+        learned_case(args, result, cfg, key, seeds)
+
+
+def learned_case(args, result, cfg, key, eval_seeds):
     import torch
     from paper_2206_14503_amd import learned, synth
 
-    cfg = learned.LearnedConfig()
     tf_d = torch.from_numpy(synth.transfer_function()).cuda()
     t0 = time.time()
     X, Y, st = learned.training_pairs(cfg, seeds=range(args.learn_seeds), tf_d=tf_d)
-    log(f"[bench] learned: {X.shape[0]} training pairs (of {st['kept']} served among {st['rays']} brick-rays) "
+    log(f"[bench] {key}: {X.shape[0]} training pairs (of {st['kept']} served among {st['rays']} brick-rays) "
         f"in {time.time() - t0:.1f}s")
     mlp = learned.init_mlp(0)
     t1 = time.time()
@@ -289,11 +299,11 @@ def leg_learned(args, result):
     t_train = time.time() - t1
     del X, Y
     torch.cuda.empty_cache()
-    ev_ = learned.evaluate(mlp, cfg, seeds=range(100, 104), tf_d=tf_d, reps=3)
-    log(f"[bench] learned vs plain: {ev_}")
-    result["learned"] = {"train_pairs": st["pairs"], "train_seconds": t_train, "final_loss": losses[-1],
-                         "eval_rays": ev_["brick_rays"], "workload": f"{cfg.n}^3 x {cfg.grid} bricks, "
-                         f"{cfg.res}^2 ortho views, N={cfg.max_n}", **ev_}
+    ev_ = learned.evaluate(mlp, cfg, seeds=eval_seeds, tf_d=tf_d, reps=3)
+    log(f"[bench] {key} vs plain: {ev_}")
+    result[key] = {"train_pairs": st["pairs"], "train_seconds": t_train, "final_loss": losses[-1],
+                   "eval_rays": ev_["brick_rays"], "workload": cfg.describe(), **ev_}
+    torch.cuda.empty_cache()
 
 
 # ---------------------------------------------------------------- batched composites
@@ -416,6 +426,8 @@ def main():
     ap.add_argument("--legs", default="fhd,large,learned,batched")
     ap.add_argument("--learn-seeds", type=int, default=32)
     ap.add_argument("--learn-epochs", type=int, default=8)
+    ap.add_argument("--no-learn-fhd", dest="learn_fhd", action="store_false",
+                    help="skip the learned threshold on FHD-generator volumes (N=20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a kernel of known traffic for counter scaling)")

@@ -218,7 +218,9 @@ typedef struct {
  * hist[(r*P + p)*64 + j] = bf16(#{non-transparent samples with opacity a in
  * (j/64, (j+1)/64]} / feature_scale), nnt[r*P + p] = number of non-transparent
  * samples, cmax[r*P + p] = min(count at threshold gamma_max*2^-iters, N+1).
- * tau supplies iters, gamma_max and feature_scale; N = max_n. */
+ * tau supplies iters, gamma_max and feature_scale; N = max_n.  The bins count
+ * to 65535: step must exceed sqrt(3)/65535 (else VDI_E_UNSUPPORTED; the same
+ * holds for vdi_generate in LEARNED mode). */
 vdi_status vdi_tau_features(vdi_ctx *ctx, const vdi_brick_t *bricks, int k, const vdi_camera_t *cam,
                             const vdi_tf_t *tf, float step, float ref_step, int max_n, const vdi_tau_t *tau,
                             uint16_t *hist, int32_t *nnt, int32_t *cmax, void *stream);

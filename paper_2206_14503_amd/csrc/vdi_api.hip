@@ -103,11 +103,12 @@ static vdi_status check_tau(const vdi_tau_t* tau, bool allow_learned)
     return VDI_OK;
 }
 
-static GenBricks make_bricks(const vdi_brick_t* bricks, vdi_t* out, int r0, int nb)
+static GenBricks make_bricks(const vdi_brick_t* bricks, vdi_t* out, int r0, int nb, int total)
 {
     GenBricks B;
     memset(&B, 0, sizeof B);
     B.first = r0;
+    B.total = total;
     for (int i = 0; i < nb; ++i) {
         const vdi_brick_t& b = bricks[r0 + i];
         GenBrick& g = B.b[i];
@@ -142,28 +143,29 @@ static void fill_i32(int* p, int v, size_t n, hipStream_t s)
     if (n) hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
 }
 
-// Scratch layout of the learned path for nb bricks of npix pixels.
+// Scratch layout of the learned path for nb bricks of npix pixels
+// (nblk 256-slot blocks per brick).
 struct LearnScratch {
-    size_t hist, nnt, cmax, y, list, cnt, rlist, ry, rcnt, svlist, svcnt, sclist, sccnt, total;
+    size_t hist, nnt, cmax, y, ry, hlist, hcnt, kind, qcnt, qoff, qlist, scan, total;
 };
-static LearnScratch learn_layout(size_t rays, int nb)
+static LearnScratch learn_layout(size_t rays, int nb, size_t nblk)
 {
     LearnScratch L;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t a = o; o += (bytes + 255) & ~(size_t)255; return a; };
+    const size_t nq = (size_t)nb * nblk;
     L.hist = take(rays * 64 * sizeof(uint16_t));
     L.nnt = take(rays * sizeof(int));
     L.cmax = take(rays * sizeof(int));
     L.y = take(rays * sizeof(float));
-    L.list = take(rays * sizeof(int));
-    L.cnt = take((size_t)nb * sizeof(int));
-    L.rlist = take(rays * sizeof(int));
     L.ry = take(rays * sizeof(float2));
-    L.rcnt = take((size_t)nb * sizeof(int));
-    L.svlist = take(rays * sizeof(int));
-    L.svcnt = take((size_t)nb * sizeof(int));
-    L.sclist = take(rays * sizeof(int));
-    L.sccnt = take((size_t)nb * sizeof(int));
+    L.hlist = take(rays * sizeof(int));
+    L.hcnt = take((size_t)nb * sizeof(int));
+    L.kind = take(nq * 256);
+    L.qcnt = take(kQueues * nq * sizeof(int));
+    L.qoff = take(kQueues * (nq + 1) * sizeof(uint32_t));
+    L.qlist = take(kQueues * rays * sizeof(int));
+    L.scan = take(scan_scratch_bytes(nq));
     L.total = o;
     return L;
 }
@@ -176,58 +178,63 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
     if (rays >= ((size_t)1 << 31)) return fail(VDI_E_UNSUPPORTED, "too many brick-rays for the learned path");
     if (k > kGenBricksPerLaunch)
         return fail(VDI_E_UNSUPPORTED, "the learned path takes at most %d bricks per call", kGenBricksPerLaunch);
-    LearnScratch Ls = learn_layout(rays, k);
+    const size_t nblk = (size_t)((P.cam.width + 15) / 16) * (size_t)((P.cam.height + 15) / 16);
+    const size_t nq = (size_t)k * nblk;
+    LearnScratch Ls = learn_layout(rays, k, nblk);
     vdi_status st = ensure_scratch(ctx, Ls.total);
     if (st != VDI_OK) return st;
     char* base = (char*)ctx->scratch;
     LearnBufs Lb;
+    memset(&Lb, 0, sizeof Lb);
     Lb.hist = (uint16_t*)(base + Ls.hist);
     Lb.nnt = (int*)(base + Ls.nnt);
     Lb.cmax = (int*)(base + Ls.cmax);
     Lb.y = (const float*)(base + Ls.y);
-    Lb.fb_list = (int*)(base + Ls.list);
-    Lb.fb_count = (int*)(base + Ls.cnt);
-    Lb.rf_list = (int*)(base + Ls.rlist);
     Lb.rf_y = (float2*)(base + Ls.ry);
-    Lb.rf_count = (int*)(base + Ls.rcnt);
-    Lb.sv_list = (int*)(base + Ls.svlist);
-    Lb.sv_count = (int*)(base + Ls.svcnt);
-    Lb.sc_list = (int*)(base + Ls.sclist);
-    Lb.sc_count = (int*)(base + Ls.sccnt);
+    Lb.hist_list = (int*)(base + Ls.hlist);
+    Lb.hist_count = (int*)(base + Ls.hcnt);
+    Lb.kind = (uint8_t*)(base + Ls.kind);
+    Lb.qcnt = (int*)(base + Ls.qcnt);
+    Lb.qoff = (uint32_t*)(base + Ls.qoff);
+    Lb.qlist = (int*)(base + Ls.qlist);
+    Lb.nblk = (int)nblk;
     Lb.stats = ctx->status + 4;
     Lb.s_ref = tau->feature_scale;
     Lb.tol = tau->fallback_tol;
-    Lb.blocks_per_brick = std::max(1, ctx->num_cus * 8 / std::min(k, kGenBricksPerLaunch));
+    Lb.blocks_per_brick = std::max(1, ctx->num_cus * 8 / k);
     const vdi_mlp_t* mlp = (const vdi_mlp_t*)tau->mlp;
     if (tau->y) Lb.y = tau->y;
-    fill_i32(Lb.fb_count, 0, (size_t)k, s);
-    fill_i32(Lb.rf_count, 0, (size_t)k, s);
-    fill_i32(Lb.sv_count, 0, (size_t)k, s);
-    fill_i32(Lb.sc_count, 0, (size_t)k, s);
-    for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
-        int nb = std::min(k - r0, kGenBricksPerLaunch);
-        GenBricks B = make_bricks(bricks, out, r0, nb);
-        launch_learned(0, dtype, P, B, nb, Lb, s);
-        if ((st = launched()) != VDI_OK) return st;
-    }
+    void* scan_scratch = base + Ls.scan;
+    GenBricks B = make_bricks(bricks, out, 0, k, k);
+    auto phase = [&](int ph) { launch_learned(ph, dtype, P, B, k, Lb, s); return launched(); };
+    // list q in slot order: scan its per-block counts, then place its rays
+    auto order = [&](int q) {
+        launch_scan(Lb.qcnt + (size_t)q * nq, Lb.qoff + (size_t)q * (nq + 1), nq, scan_scratch, s);
+        vdi_status e = launched();
+        if (e != VDI_OK) return e;
+        launch_compact(q, P, k, Lb, s);
+        return launched();
+    };
+    fill_i32(Lb.hist_count, 0, (size_t)k, s);
+    fill_i32(Lb.qcnt, 0, kQueues * nq, s);
+    if ((st = phase(0)) != VDI_OK) return st;
+    if ((st = order(Q_SERVED)) != VDI_OK) return st;
+    if ((st = order(Q_SHORT)) != VDI_OK) return st;
     if (!tau->y) {
         // per brick: the served rays' compacted histograms; y scattered back to pixel order
         for (int r = 0; r < k; ++r) {
-            launch_mlp_fwd(mlp->w_bf16, mlp->w_f32, Lb.hist + (size_t)r * npix * 64, (int)npix, Lb.sv_count + r,
-                           Lb.sv_list + (size_t)r * npix, ctx->num_cus * 3, (float*)(base + Ls.y) + (size_t)r * npix,
+            launch_mlp_fwd(mlp->w_bf16, mlp->w_f32, Lb.hist + (size_t)r * npix * 64, (int)npix, Lb.hist_count + r,
+                           Lb.hist_list + (size_t)r * npix, ctx->num_cus * 3, (float*)(base + Ls.y) + (size_t)r * npix,
                            nullptr, s);
             if ((st = launched()) != VDI_OK) return st;
         }
     }
-    for (int phase = 1; phase <= 4; ++phase) {
-        for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
-            int nb = std::min(k - r0, kGenBricksPerLaunch);
-            GenBricks B = make_bricks(bricks, out, r0, nb);
-            launch_learned(phase, dtype, P, B, nb, Lb, s);
-            if ((st = launched()) != VDI_OK) return st;
-        }
-    }
-    return VDI_OK;
+    if ((st = phase(1)) != VDI_OK) return st;   // round one
+    if ((st = phase(4)) != VDI_OK) return st;   // all-feasible lists
+    if ((st = order(Q_REFINE)) != VDI_OK) return st;
+    if ((st = phase(2)) != VDI_OK) return st;   // round two
+    if ((st = order(Q_FALLBACK)) != VDI_OK) return st;
+    return phase(3);                            // plain bisection
 }
 
 }  // namespace vdi
@@ -305,6 +312,8 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
         if (!tau->y && (!mlp || !mlp->w_bf16 || !mlp->w_f32))
             return fail(VDI_E_INVALID, "learned mode needs tau->mlp or tau->y");
         if (!(tau->feature_scale > 0.0f)) return fail(VDI_E_INVALID, "learned mode needs feature_scale > 0");
+        if (!(1.7320508f / step < 65535.0f))
+            return fail(VDI_E_UNSUPPORTED, "step too small for the learned path (histogram bins count to 65535)");
         if (!(tau->fallback_tol >= 0.0f && tau->fallback_tol < 1.0f))
             return fail(VDI_E_INVALID, "fallback_tol must be in [0, 1)");
     }
@@ -371,6 +380,7 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
         GenBricks B;
         memset(&B, 0, sizeof B);
         B.first = r0;
+        B.total = k;
         for (int i = 0; i < nb; ++i) {
             const vdi_brick_t& b = bricks[r0 + i];
             vdi_t& o = out[r0 + i];
@@ -495,6 +505,8 @@ vdi_status vdi_tau_features(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, cons
     if (k < 1 || cam->width <= 0 || cam->height <= 0) return fail(VDI_E_INVALID, "bad k or camera");
     if (!tf->rgba || tf->entries < 2 || tf->entries > VDI_MAX_TF) return fail(VDI_E_INVALID, "transfer function");
     if (!(step > 0.0f) || !(ref_step > 0.0f)) return fail(VDI_E_INVALID, "step and ref_step must be > 0");
+    if (!(1.7320508f / step < 65535.0f))
+        return fail(VDI_E_UNSUPPORTED, "step too small for the histogram (bins count to 65535)");
     if (max_n < 1 || max_n > VDI_MAX_N) return fail(VDI_E_INVALID, "max_n");
     if (tau->iters < 1 || tau->iters > 24 || !(tau->gamma_max > 1.7320509f) || !(tau->feature_scale > 0.0f))
         return fail(VDI_E_INVALID, "tau: iters, gamma_max or feature_scale");
@@ -536,7 +548,7 @@ vdi_status vdi_tau_features(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, cons
     hipStream_t s = (hipStream_t)stream;
     for (int r0 = 0; r0 < k; r0 += kGenBricksPerLaunch) {
         int nb = std::min(k - r0, kGenBricksPerLaunch);
-        GenBricks B = make_bricks(bricks, nullptr, r0, nb);
+        GenBricks B = make_bricks(bricks, nullptr, r0, nb, k);
         launch_learned(0, dtype, P, B, nb, Lb, s);
         vdi_status st = launched();
         if (st != VDI_OK) return st;

@@ -432,13 +432,56 @@ __device__ inline RayRun ray_run(const GenParams& P, const GenBrick& br, int x, 
     return q;
 }
 
+// Slot of pixel (x, y) in the launch order of the 2D generation kernels
+// (16x16 blocks, four 8x8 wavefront tiles each), and back.
+__device__ inline uint32_t slot_of(int x, int y, int gx)
+{
+    const uint32_t blk = (uint32_t)(y >> 4) * (uint32_t)gx + (uint32_t)(x >> 4);
+    const uint32_t wave = (uint32_t)(((y >> 3) & 1) * 2 + ((x >> 3) & 1));
+    const uint32_t lane = (uint32_t)((y & 7) * 8 + (x & 7));
+    return (blk << 8) + wave * 64u + lane;
+}
+
+__device__ inline void pixel_of_slot(uint32_t slot, int gx, int& x, int& y)
+{
+    const uint32_t blk = slot >> 8, t = slot & 255u, wave = t >> 6, lane = t & 63u;
+    x = (int)((blk % (uint32_t)gx) * 16u + (wave & 1u) * 8u + (lane & 7u));
+    y = (int)((blk / (uint32_t)gx) * 16u + (wave >> 1) * 8u + (lane >> 3));
+}
+
+// Rays of brick `brick` on list q: [begin, end) of Lb.qlist + q * lstride.
+struct ListSpan {
+    const int* list;
+    uint32_t begin, end;
+};
+
+__device__ inline ListSpan list_span(const LearnBufs& Lb, int q, int brick, int nb_total, uint32_t npix)
+{
+    const uint32_t* off = Lb.qoff + (size_t)q * ((size_t)nb_total * Lb.nblk + 1);
+    ListSpan s;
+    s.list = Lb.qlist + (size_t)q * (size_t)nb_total * npix;
+    s.begin = off[(size_t)brick * Lb.nblk];
+    s.end = off[(size_t)(brick + 1) * Lb.nblk];
+    return s;
+}
+
+// Puts pixel (x, y) of brick `brick` on list q (one atomic per ray).
+__device__ inline void put_on_list(const LearnBufs& Lb, int q, int brick, int nb_total, int x, int y, int gx)
+{
+    const uint32_t slot = slot_of(x, y, gx);
+    Lb.kind[(size_t)brick * ((size_t)Lb.nblk << 8) + slot] = (uint8_t)(1 + q);
+    atomicAdd(&Lb.qcnt[(size_t)q * nb_total * Lb.nblk + (size_t)brick * Lb.nblk + (slot >> 8)], 1);
+}
+
 template <typename VT>
 __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
     extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
-    __shared__ uint16_t hs[64][256];
+    // bins 2i and 2i+1 of a lane share one 32-bit word (low and high half), so
+    // consecutive lanes update consecutive words (no bank conflicts)
+    __shared__ uint32_t hs[32][256];
     for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
-    for (int j = 0; j < 64; ++j) hs[j][threadIdx.x] = 0;
+    for (int j = 0; j < 32; ++j) hs[j][threadIdx.x] = 0u;
     __syncthreads();
 
     const GenBrick& br = B.b[blockIdx.z];
@@ -446,7 +489,12 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int x = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
     const int y = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
-    if (x >= P.cam.width || y >= P.cam.height) return;
+    const uint32_t blk = blockIdx.y * gridDim.x + blockIdx.x;
+    const size_t slot = (size_t)brick * ((size_t)Lb.nblk << 8) + ((size_t)blk << 8) + threadIdx.x;
+    if (x >= P.cam.width || y >= P.cam.height) {
+        if (Lb.kind) Lb.kind[slot] = 0;
+        return;
+    }
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
     const size_t ray = (size_t)brick * npix + (uint32_t)y * (uint32_t)P.cam.width + (uint32_t)x;
 
@@ -473,7 +521,7 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
         if (a32 > 0.0f) {
             int j = (int)ceilf(64.0f * a32) - 1;
             j = j > 63 ? 63 : (j < 0 ? 0 : j);
-            hs[j][threadIdx.x] += 1;
+            hs[j >> 1][threadIdx.x] += (j & 1) ? 0x10000u : 1u;
             ++m;
         }
         if (count <= P.max_n) {
@@ -485,28 +533,33 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
     Lb.nnt[ray] = m;
     Lb.cmax[ray] = count;
     size_t row = ray;
-    if (Lb.sv_list) {
+    if (Lb.hist_list) {
         // generation: an empty list is finished here; lists with at most N
-        // non-transparent samples (every threshold feasible) are queued for
-        // the write at the smallest threshold; only the rays the regressor
-        // serves get a histogram row, compacted per brick in order of arrival
+        // non-transparent samples (every threshold feasible) go on the list of
+        // writes at the smallest threshold, the others on the regressor's list
+        // (both counted per 256-slot block); the served rays' histogram rows are
+        // compacted per brick in order of arrival (the regressor's order does
+        // not matter)
         const uint32_t pix = (uint32_t)(ray - (size_t)brick * npix);
         const bool empty = k1 <= k0 || m == 0;
         const bool served = !empty && m > P.max_n;
         const bool shortcut = !empty && !served;
+        Lb.kind[slot] = served ? (uint8_t)(1 + Q_SERVED) : (shortcut ? (uint8_t)(1 + Q_SHORT) : (uint8_t)0);
+        const int nb_total = B.total;
+        wave_count(&Lb.qcnt[(size_t)Q_SERVED * nb_total * Lb.nblk + (size_t)brick * Lb.nblk + blk], served);
+        wave_count(&Lb.qcnt[(size_t)Q_SHORT * nb_total * Lb.nblk + (size_t)brick * Lb.nblk + blk], shortcut);
         wave_append(&Lb.stats[LEARN_EMPTY], empty);
-        const int spos = wave_append(&Lb.sc_count[brick], shortcut);
-        const int pos = wave_append(&Lb.sv_count[brick], served);
+        const int pos = wave_append(&Lb.hist_count[brick], served);
         if (empty) finish_list(br, pix, npix, P.max_n, 0, gmin);
-        if (shortcut) Lb.sc_list[(size_t)brick * npix + spos] = (int)pix;
         if (!served) return;
-        Lb.sv_list[(size_t)brick * npix + pos] = (int)pix;
+        Lb.hist_list[(size_t)brick * npix + pos] = (int)pix;
         row = (size_t)brick * npix + (size_t)pos;
     }
     uint32_t* hrow = (uint32_t*)(Lb.hist + row * 64);
     for (int j = 0; j < 64; j += 2) {
-        float f0 = (float)hs[j][threadIdx.x] / Lb.s_ref;
-        float f1 = (float)hs[j + 1][threadIdx.x] / Lb.s_ref;
+        const uint32_t pair = hs[j >> 1][threadIdx.x];
+        float f0 = (float)(pair & 0xffffu) / Lb.s_ref;
+        float f1 = (float)(pair >> 16) / Lb.s_ref;
         hrow[j / 2] = (uint32_t)bf16_bits(f0) | ((uint32_t)bf16_bits(f1) << 16);
     }
 }
@@ -529,12 +582,14 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
     const GenBrick& br = B.b[blockIdx.z];
     const int brick = B.first + blockIdx.z;
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
-    const uint32_t n_q = (uint32_t)Lb.sv_count[brick];
+    const int gx = (P.cam.width + 15) / 16;
+    const ListSpan ls = list_span(Lb, Q_SERVED, brick, B.total, npix);
     const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
     const VT* data = (const VT*)br.data;
     const float lg_hi = log2f(P.gmax), lg_lo = lg_hi - (float)P.iters;
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n_q; idx += gridDim.x * blockDim.x) {
-        const uint32_t pix = (uint32_t)Lb.sv_list[(size_t)brick * npix + idx];
+    for (uint32_t idx = ls.begin + blockIdx.x * blockDim.x + threadIdx.x; idx < ls.end;
+         idx += gridDim.x * blockDim.x) {
+        const uint32_t pix = (uint32_t)ls.list[idx];
         const size_t ray = (size_t)brick * npix + pix;
         const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
         const RayRun q = ray_run(P, br, x, y);
@@ -569,12 +624,10 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
             }
             kind = pick >= 0 ? LEARN_REFINE : LEARN_FALLBACK;
         }
-        const int fpos = wave_append(&Lb.fb_count[brick], kind == LEARN_FALLBACK);
-        if (kind == LEARN_FALLBACK) Lb.fb_list[(size_t)brick * npix + fpos] = (int)pix;
-        const int rpos = wave_append(&Lb.rf_count[brick], kind == LEARN_REFINE);
+        if (kind == LEARN_FALLBACK) put_on_list(Lb, Q_FALLBACK, brick, B.total, x, y, gx);
         if (kind == LEARN_REFINE) {
-            Lb.rf_list[(size_t)brick * npix + rpos] = (int)pix;
-            Lb.rf_y[(size_t)brick * npix + rpos] = bracket;
+            put_on_list(Lb, Q_REFINE, brick, B.total, x, y, gx);
+            Lb.rf_y[ray] = bracket;
         }
         wave_append(&Lb.stats[LEARN_KEPT], kind == LEARN_KEPT);
         wave_append(&Lb.stats[LEARN_FALLBACK], kind == LEARN_FALLBACK);
@@ -597,12 +650,13 @@ __global__ __launch_bounds__(256) void shortcut_kernel(GenParams P, GenBricks B,
     const GenBrick& br = B.b[blockIdx.z];
     const int brick = B.first + blockIdx.z;
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
-    const uint32_t n_q = (uint32_t)Lb.sc_count[brick];
+    const ListSpan ls = list_span(Lb, Q_SHORT, brick, B.total, npix);
     const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
     const VT* data = (const VT*)br.data;
     const float gmin = ldexpf(P.gmax, -P.iters);
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n_q; idx += gridDim.x * blockDim.x) {
-        const uint32_t pix = (uint32_t)Lb.sc_list[(size_t)brick * npix + idx];
+    for (uint32_t idx = ls.begin + blockIdx.x * blockDim.x + threadIdx.x; idx < ls.end;
+         idx += gridDim.x * blockDim.x) {
+        const uint32_t pix = (uint32_t)ls.list[idx];
         const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
         const RayRun q = ray_run(P, br, x, y);
         GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
@@ -626,12 +680,14 @@ __global__ __launch_bounds__(256) void refine_kernel(GenParams P, GenBricks B, L
     const GenBrick& br = B.b[blockIdx.z];
     const int brick = B.first + blockIdx.z;
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
-    const uint32_t n_q = (uint32_t)Lb.rf_count[brick];
+    const int gx = (P.cam.width + 15) / 16;
+    const ListSpan ls = list_span(Lb, Q_REFINE, brick, B.total, npix);
     const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
     const VT* data = (const VT*)br.data;
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n_q; idx += gridDim.x * blockDim.x) {
-        const uint32_t pix = (uint32_t)Lb.rf_list[(size_t)brick * npix + idx];
-        const float2 yab = Lb.rf_y[(size_t)brick * npix + idx];
+    for (uint32_t idx = ls.begin + blockIdx.x * blockDim.x + threadIdx.x; idx < ls.end;
+         idx += gridDim.x * blockDim.x) {
+        const uint32_t pix = (uint32_t)ls.list[idx];
+        const float2 yab = Lb.rf_y[(size_t)brick * npix + pix];
         const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
         const RayRun q = ray_run(P, br, x, y);
         float g5[5];
@@ -641,11 +697,10 @@ __global__ __launch_bounds__(256) void refine_kernel(GenParams P, GenBricks B, L
         gen_scan<VT, 5>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, g5, P.max_n, c5, nullptr);
         const int lo = band_lo(P.max_n, Lb.cmax[(size_t)brick * npix + pix], Lb.tol);
         const int best = pick_in_band<5>(c5, P.max_n, lo);
-        const int fpos = wave_append(&Lb.fb_count[brick], best < 0);
         wave_append(&Lb.stats[LEARN_REFINED], best >= 0);
         wave_append(&Lb.stats[LEARN_FALLBACK], best < 0);
         if (best < 0) {
-            Lb.fb_list[(size_t)brick * npix + fpos] = (int)pix;
+            put_on_list(Lb, Q_FALLBACK, brick, B.total, x, y, gx);
             continue;
         }
         GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
@@ -665,11 +720,12 @@ __global__ __launch_bounds__(256) void fallback_kernel(GenParams P, GenBricks B,
     const GenBrick& br = B.b[blockIdx.z];
     const int brick = B.first + blockIdx.z;
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
-    const uint32_t n_q = (uint32_t)Lb.fb_count[brick];
+    const ListSpan ls = list_span(Lb, Q_FALLBACK, brick, B.total, npix);
     const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
     const VT* data = (const VT*)br.data;
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n_q; idx += gridDim.x * blockDim.x) {
-        const uint32_t pix = (uint32_t)Lb.fb_list[(size_t)brick * npix + idx];
+    for (uint32_t idx = ls.begin + blockIdx.x * blockDim.x + threadIdx.x; idx < ls.end;
+         idx += gridDim.x * blockDim.x) {
+        const uint32_t pix = (uint32_t)ls.list[idx];
         const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
         const RayRun q = ray_run(P, br, x, y);
         float gm = ldexpf(P.gmax, -P.iters);
@@ -682,6 +738,37 @@ __global__ __launch_bounds__(256) void fallback_kernel(GenParams P, GenBricks B,
         }
         finish_list(br, pix, npix, P.max_n, c < P.max_n ? c : P.max_n, gm);
     }
+}
+
+// Rays of list q in slot order: block b of brick z places its rays at the
+// scanned offset of (z, b) plus their rank among the block's slots.
+__global__ __launch_bounds__(256) void compact_kernel(int q, int width, int height, int nb_total, LearnBufs Lb)
+{
+    __shared__ int wsum[4];
+    const int brick = blockIdx.y;
+    const uint32_t blk = blockIdx.x;
+    const int gx = (width + 15) / 16;
+    const uint32_t npix = (uint32_t)width * (uint32_t)height;
+    const size_t slot = (size_t)brick * ((size_t)Lb.nblk << 8) + ((size_t)blk << 8) + threadIdx.x;
+    const bool on = Lb.kind[slot] == (uint8_t)(1 + q);
+    const unsigned long long m = __ballot(on);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int rank = __popcll(m & ((1ull << lane) - 1ull));
+    for (int w = 0; w < wave; ++w) rank += wsum[w];
+    if (!on) return;
+    const uint32_t* off = Lb.qoff + (size_t)q * ((size_t)nb_total * Lb.nblk + 1);
+    const uint32_t pos = off[(size_t)brick * Lb.nblk + blk] + (uint32_t)rank;
+    int x, y;
+    pixel_of_slot(((uint32_t)blk << 8) + threadIdx.x, gx, x, y);
+    Lb.qlist[(size_t)q * (size_t)nb_total * npix + pos] = y * width + x;
+}
+
+void launch_compact(int q, const GenParams& P, int nb, const LearnBufs& L, hipStream_t s)
+{
+    dim3 grid((unsigned)L.nblk, (unsigned)nb);
+    hipLaunchKernelGGL(compact_kernel, grid, dim3(256), 0, s, q, P.cam.width, P.cam.height, nb, L);
 }
 
 template <typename VT>

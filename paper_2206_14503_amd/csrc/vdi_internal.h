@@ -447,6 +447,15 @@ __device__ inline int wave_append(int* ctr, bool inc)
     return base + rank;
 }
 
+// Add the number of lanes with `inc` to *ctr (one atomic per wavefront).
+__device__ inline void wave_count(int* ctr, bool inc)
+{
+    const unsigned long long m = __ballot(inc);
+    const int lane = threadIdx.x & 63;
+    const int leader = m ? (__ffsll((long long)m) - 1) : 0;
+    if (m && lane == leader) atomicAdd(ctr, __popcll(m));
+}
+
 // ---------------------------------------------------------------- misc
 
 // fp32 -> bf16 bits, round to nearest even.

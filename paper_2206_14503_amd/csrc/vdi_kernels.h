@@ -41,6 +41,7 @@ constexpr int kGenBricksPerLaunch = 16;
 struct GenBricks {
     GenBrick b[kGenBricksPerLaunch];
     int first;           // index of b[0] among all bricks of the call
+    int total;           // bricks of the call
 };
 
 // Buffers of the learned-threshold path (indices: brick * npix + pixel).
@@ -49,32 +50,41 @@ struct GenBricks {
 enum { LEARN_KEPT = 0, LEARN_SHORTCUT = 1, LEARN_FALLBACK = 2, LEARN_EMPTY = 3, LEARN_REFINED = 4, LEARN_REFINE = 5 };
 constexpr int kLearnStats = 5;
 
+// Work lists of the learned path.  A slot numbers a ray in the launch order
+// of the 2D generation kernels: slot = (16x16-block index) * 256 + thread.
+// Each list holds its rays in slot order (image-tile order), so the waves of
+// the list-driven kernels sample neighbouring voxels: per 256-slot block the
+// producers count their rays, the counts are scanned, and a compaction kernel
+// places each ray at its block's offset plus its rank in the block.
+enum { Q_SERVED = 0, Q_SHORT = 1, Q_REFINE = 2, Q_FALLBACK = 3, kQueues = 4 };
+
 struct LearnBufs {
-    uint16_t* hist;      // [nb][npix][64] bf16 features; with sv_list: [served][64], compacted
+    uint16_t* hist;      // [nb][npix][64] bf16 features; with hist_list: per brick, compacted
     int* nnt;            // [nb][npix] non-transparent samples
     int* cmax;           // [nb][npix] count at the smallest threshold (saturates at N+1)
     const float* y;      // [nb][npix] log2(gamma) from the regressor (or the caller)
-    int* fb_list;        // [nb][npix] pixels queued for the bisection, per brick
-    int* fb_count;       // [nb]
-    int* rf_list;        // [nb][npix] pixels queued for round two, per brick
-    float2* rf_y;        // [nb][npix] their log2 brackets
-    int* rf_count;       // [nb]
-    int* sv_list;        // optional [nb][npix]: pixels the regressor serves, per brick (hist row order)
-    int* sv_count;       // [nb]
-    int* sc_list;        // [nb][npix]: pixels whose every threshold is feasible, per brick
-    int* sc_count;       // [nb]
+    float2* rf_y;        // [nb][npix] log2 bracket of rays sent to round two
+    int* hist_list;      // optional [nb][npix]: pixel of each compacted histogram row
+    int* hist_count;     // [nb]
+    uint8_t* kind;       // [nb][slots] 1 + the list a slot's ray is on (0: none)
+    int* qcnt;           // [kQueues][nb * nblk] rays per 256-slot block
+    uint32_t* qoff;      // [kQueues][nb * nblk + 1] exclusive scans of qcnt
+    int* qlist;          // [kQueues][nb * npix] pixels, per brick in slot order
+    int nblk;            // 256-slot blocks per brick
     int* stats;          // [kLearnStats]
     float s_ref;
     float tol;
-    int blocks_per_brick;  // grid of the queue-driven kernels
+    int blocks_per_brick;  // grid of the list-driven kernels
 };
 
 // kind: 0 = search + regular write, 1 = search only, 2 = compact write
 void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B, int nb, hipStream_t s);
-// phase 0: features (finishes empty lists, queues the others), 1: learned
+// phase 0: features (finishes empty lists, lists the others), 1: learned
 // round one, 2: round two, 3: fallback bisection, 4: all-feasible lists
 void launch_learned(int phase, int dtype, const GenParams& P, const GenBricks& B, int nb, const LearnBufs& L,
                     hipStream_t s);
+// Places the rays of list q (kind == 1 + q) at their offsets, in slot order.
+void launch_compact(int q, const GenParams& P, int nb, const LearnBufs& L, hipStream_t s);
 void launch_rays(const Cam& cam, float step, float* o, float* d, float* tn, float* tf, int* ns, hipStream_t s);
 
 // ---------------------------------------------------------------- scan

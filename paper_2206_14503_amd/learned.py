@@ -23,14 +23,21 @@ from . import synth, vdi
 
 @dataclasses.dataclass
 class LearnedConfig:
-    """Tiny-volume setting of the learned threshold: 64^3 fp32, 12 Gaussians,
-    2 z-slabs, orthographic views along +z (even seeds) or -z (odd seeds),
-    N=8, B=10.  Training frames are train_res^2, evaluation frames res^2
-    (1024^2 x 2 bricks = 2.1M brick-rays per frame)."""
+    """Setting of the learned threshold.
+
+    kind "tiny": the tiny volumes (64^3 fp32, 12 Gaussians, 2 z-slabs),
+    orthographic views along +z (even seeds) or -z (odd seeds), N=8, B=10.
+    Training frames are train_res, evaluation frames res (1024^2 x 2 bricks =
+    2.1M brick-rays per frame).
+
+    kind "fhd": the FHD generator (512^3 fp32, 200 Gaussians + noise, 8
+    z-slabs) under seeded orbit cameras, N=20 as in the FHD workload; the
+    rays are ten times longer and the 10% band spans three counts."""
+    kind: str = "tiny"
     n: int = 64
     n_gauss: int = 12
-    res: int = 1024
-    train_res: int = 640
+    res: Tuple[int, int] = (1024, 1024)
+    train_res: Tuple[int, int] = (640, 640)
     grid: Tuple[int, int, int] = (1, 1, 2)
     max_n: int = 8
     iters: int = 10
@@ -39,12 +46,27 @@ class LearnedConfig:
     fallback_tol: float = 0.1
     max_pairs: int = 8 << 20
 
+    @staticmethod
+    def fhd() -> "LearnedConfig":
+        return LearnedConfig(kind="fhd", n=512, n_gauss=200, res=(1920, 1080), train_res=(640, 360),
+                             grid=(1, 1, 8), max_n=20)
 
-def frame_inputs(cfg: LearnedConfig, seed: int, res: int):
-    vol = synth.gaussian_volume(cfg.n, cfg.n_gauss, seed)
+    def describe(self) -> str:
+        view = "ortho +-z" if self.kind == "tiny" else "orbit perspective"
+        return (f"{self.n}^3, {self.grid} bricks, {self.res[0]}x{self.res[1]} {view} views, N={self.max_n}")
+
+
+def frame_inputs(cfg: LearnedConfig, seed: int, res: Tuple[int, int]):
+    """Volume (host array for tiny, device tensor for fhd), bricks and camera of one frame."""
+    if cfg.kind == "tiny":
+        vol = synth.gaussian_volume(cfg.n, cfg.n_gauss, seed)
+        bricks = synth.brick_grid((cfg.n,) * 3, cfg.grid)
+        cam = synth.ortho_camera(res[0], res[1], "+z" if seed % 2 == 0 else "-z")
+        return vol, bricks, cam
+    w = dataclasses.replace(synth.fhd(seed), width=res[0], height=res[1])
+    vol = synth.workload_volume(w, device="cuda")
     bricks = synth.brick_grid((cfg.n,) * 3, cfg.grid)
-    cam = synth.ortho_camera(res, res, "+z" if seed % 2 == 0 else "-z")
-    return vol, bricks, cam
+    return vol, bricks, synth.camera_for(w)
 
 
 def training_pairs(cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor
@@ -71,7 +93,7 @@ def training_pairs(cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor
         stats["kept"] += int(keep.sum())
         xs.append(hist[keep])
         ys.append(torch.log2(gam[keep]))
-        del dbr, outs
+        del dbr, outs, vol
     X, Y = torch.cat(xs), torch.cat(ys)
     if X.shape[0] > cfg.max_pairs:
         g = torch.Generator(device=X.device)

@@ -232,7 +232,7 @@ def test_learned_gain_short_training(V):
     same image from the original view; report its speed against bisection."""
     import torch
     from paper_2206_14503_amd import learned
-    cfg = learned.LearnedConfig(res=128, train_res=128)
+    cfg = learned.LearnedConfig(res=(128, 128), train_res=(128, 128))
     tf_d = torch.from_numpy(synth.transfer_function()).cuda()
     X, Y, st = learned.training_pairs(cfg, seeds=range(6), tf_d=tf_d)
     assert st["kept"] > 1000
