@@ -48,7 +48,7 @@ typedef enum {
 } vdi_status;
 
 typedef enum { VDI_LAYOUT_REGULAR = 0, VDI_LAYOUT_COMPACT = 1 } vdi_layout;
-typedef enum { VDI_TAU_FIXED = 0, VDI_TAU_BISECT = 1, VDI_TAU_LEARNED = 2 } vdi_tau_mode;
+typedef enum { VDI_TAU_FIXED = 0, VDI_TAU_BISECT = 1, VDI_TAU_LEARNED = 2, VDI_TAU_BISECT_SEQ = 3 } vdi_tau_mode;
 typedef enum { VDI_F32 = 0, VDI_F16 = 1 } vdi_dtype;
 
 /* Limits of this build. */
@@ -124,7 +124,12 @@ typedef struct {
  *           last supersegment absorbs the rest of the ray).
  *  BISECT:  per list, `iters` halvings of [0, gamma_max]; a midpoint is
  *           feasible iff it yields at most max_n supersegments; the result is
- *           the upper bracket.
+ *           the upper bracket.  The search evaluates several midpoints per
+ *           sampling pass and replays the halvings from their counts.
+ *  BISECT_SEQ: (vdi_generate only) the same halvings with one midpoint per
+ *           sampling pass, as Sec. 2.4 describes the search; results are
+ *           identical to BISECT.  Kept as the baseline search the learned
+ *           threshold is measured against.
  *  LEARNED: (an extension beyond the paper) per list, y = output of the MLP
  *           `mlp` (a vdi_mlp_t*) on the list's 64-bin opacity histogram (see
  *           vdi_tau_features), or y from the caller's array `y`.  A count c is

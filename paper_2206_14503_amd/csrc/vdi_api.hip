@@ -94,9 +94,9 @@ static vdi_status check_tau(const vdi_tau_t* tau, bool allow_learned)
         if (!(tau->tau >= 0.0f)) return fail(VDI_E_INVALID, "fixed tau must be >= 0");
         return VDI_OK;
     }
-    if (tau->mode == VDI_TAU_LEARNED && !allow_learned)
-        return fail(VDI_E_UNSUPPORTED, "learned thresholds are not available for this operation");
-    if (tau->mode != VDI_TAU_BISECT && tau->mode != VDI_TAU_LEARNED)
+    if ((tau->mode == VDI_TAU_LEARNED || tau->mode == VDI_TAU_BISECT_SEQ) && !allow_learned)
+        return fail(VDI_E_UNSUPPORTED, "tau mode %d is only available for generation", tau->mode);
+    if (tau->mode != VDI_TAU_BISECT && tau->mode != VDI_TAU_LEARNED && tau->mode != VDI_TAU_BISECT_SEQ)
         return fail(VDI_E_INVALID, "unknown tau mode %d", tau->mode);
     if (tau->iters < 1 || tau->iters > 24) return fail(VDI_E_INVALID, "iters %d outside [1, 24]", tau->iters);
     if (!(tau->gamma_max > 1.7320509f)) return fail(VDI_E_INVALID, "gamma_max must exceed sqrt(3)");
@@ -445,7 +445,8 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
                                            : (uint64_t)in[r].max_n * (uint64_t)in[r].width * in[r].height;
         seq_cap += in[r].max_n;
     }
-    const size_t lds = composite_lds_bytes(k, seq_cap);
+    // the general merge stages merged lists in scratch (no merge sequence in LDS)
+    const size_t lds = composite_lds_bytes(k, seq_cap, true);
     if (lds > 160 * 1024) return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", seq_cap);
     P.k = k;
     P.npix = (uint32_t)((size_t)out->width * out->height);
@@ -466,12 +467,22 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     P.out_gamma = out->gamma;
     P.status = ctx->status;
     P.seq_cap = seq_cap;
-    // queue of pixels left to the general merge: [npix] + counter
-    if ((st = ensure_scratch(ctx, ((size_t)P.npix + 64) * sizeof(int))) != VDI_OK) return st;
-    P.q_count = (int*)ctx->scratch;
-    P.q_list = (int*)ctx->scratch + 64;
+    // scratch: the queue of pixels left to the general merge ([npix] +
+    // counter), then one staging slab per general-merge block (seq_cap * 64
+    // entries of 24 bytes), at most 1 GiB of slabs
     const int per_cu = std::max(1, std::min<int>((int)((160 * 1024) / (lds + 64)), 28));
-    launch_composite(P, ctx->num_cus * per_cu, (hipStream_t)stream);
+    const size_t slab = (size_t)seq_cap * 64;
+    size_t grid = (size_t)ctx->num_cus * per_cu;
+    grid = std::min<size_t>(grid, composite_blocks(P));
+    grid = std::max<size_t>(1, std::min<size_t>(grid, ((size_t)1 << 30) / (slab * 24)));
+    const size_t qbytes = (((size_t)P.npix + 64) * sizeof(int) + 255) & ~(size_t)255;
+    if ((st = ensure_scratch(ctx, qbytes + grid * slab * 24)) != VDI_OK) return st;
+    char* base = (char*)ctx->scratch;
+    P.q_count = (int*)base;
+    P.q_list = (int*)base + 64;
+    P.stage_c = (float4*)(base + qbytes);
+    P.stage_d = (float2*)(base + qbytes + grid * slab * sizeof(float4));
+    launch_composite(P, (int)grid, (hipStream_t)stream);
     return launched();
 }
 

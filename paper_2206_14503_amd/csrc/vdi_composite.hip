@@ -165,12 +165,13 @@ struct Lds {
 
 __device__ inline int seq_bytes(int k, int seq_cap) { return k <= 16 ? (seq_cap + 1) / 2 : seq_cap; }
 
-__device__ inline Lds lds_layout(unsigned char* lds_raw, int k, int seq_cap)
+// staged: the merged list goes to global memory, no merge sequence in LDS
+__device__ inline Lds lds_layout(unsigned char* lds_raw, int k, int seq_cap, bool staged)
 {
     Lds L;
     L.in = (const InLds*)lds_raw;
     unsigned char* q = lds_raw + sizeof(InLds) * kMaxInputs;
-    const int sb = (seq_bytes(k, seq_cap) + 3) & ~3;
+    const int sb = staged ? 0 : (seq_bytes(k, seq_cap) + 3) & ~3;
     L.seq = q;
     q += (size_t)sb * kWave;
     L.front = (float*)q;
@@ -212,6 +213,21 @@ struct SeqReader {
         L->cur[r * kWave + t] = (uint8_t)(s + 1);
         const InLds in = L->in[r];
         return Src{in.color, in.depth, L->ebase[r * kWave + t] + s * in.stride};
+    }
+};
+
+// Reader of a lane's merged list staged in global memory: element i at
+// [i * 64 + t], so the 64 lanes of a scan step read consecutive addresses.
+struct StageReader {
+    const float4* c;
+    const float2* d;
+    uint32_t t, e;
+    __device__ void reset() { e = t; }
+    __device__ Src next()
+    {
+        Src q{c, d, e};
+        e += kWave;
+        return q;
     }
 };
 
@@ -545,7 +561,7 @@ __device__ bool composite_pixel_cat(const CompParams& P, unsigned char* lds_raw,
 // input) into an LDS merge sequence, then re-segmentation replaying it.
 __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int t, uint32_t p)
 {
-    const Lds L = lds_layout(lds_raw, P.k, P.seq_cap);
+    const Lds L = lds_layout(lds_raw, P.k, P.seq_cap, false);
     const SeqReader rd{&L, t, P.k, 0};
 
     // ---- load counts, validate, set up the merge cursors
@@ -616,14 +632,105 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
     resegment<false>(P, rd, total, p);
 }
 
+// General path with the merged list staged in global memory (sc, sd: the
+// block's slab; lane t's element i at [i * 64 + t]).  The merge gathers each element once
+// and stores it (the store of step i is issued at step i + 1, and the front
+// of an input's element after next lands in LDS one step later, so the loads
+// overlap the next selection); every re-segmentation scan then reads whole
+// lines.  The first scan validates the merged list: it is non-decreasing in
+// front depth exactly when every input is.
+__device__ void composite_pixel_staged(const CompParams& P, unsigned char* lds_raw, int t, uint32_t p,
+                                       float4* sc, float2* sd)
+{
+    const Lds L = lds_layout(lds_raw, P.k, P.seq_cap, true);
+    int total = 0;
+    bool bad = false;
+    for (int r = 0; r < P.k; ++r) {
+        const CompInput& in = P.in[r];
+        int c = in.count[p];
+        if (c < 0 || c > in.max_n) { bad = true; c = 0; }
+        const uint32_t eb = in.compact ? in.offset[p] : p;
+        const uint64_t last = in.compact ? (uint64_t)eb + (uint64_t)c : (uint64_t)c * P.npix;
+        if (last > in.capacity) { bad = true; c = 0; }
+        const uint32_t stride = in.compact ? 1u : P.npix;
+        L.ebase[r * kWave + t] = eb;
+        L.cur[r * kWave + t] = 0;
+        L.cnt[r * kWave + t] = (uint8_t)c;
+        L.front[r * kWave + t] = c > 0 ? gload(in.depth, eb).x : __builtin_inff();
+        L.next[r * kWave + t] = c > 1 ? gload(in.depth, eb + stride).x : __builtin_inff();
+        total += c;
+    }
+    float4 pc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float2 pd = make_float2(0.0f, 0.0f);
+    float pn = __builtin_inff();
+    int pr = -1;
+    for (int i = 0; i < total && !bad; ++i) {
+        float best = __builtin_inff();
+        int rb = -1;
+        for (int r = 0; r < P.k; ++r) {
+            const float f = L.front[r * kWave + t];
+            if (f < best) { best = f; rb = r; }
+        }
+        // finish step i - 1: its element to the slab, its input's next front to LDS
+        if (pr >= 0) {
+            sc[(uint32_t)(i - 1) * kWave + t] = pc;
+            sd[(uint32_t)(i - 1) * kWave + t] = pd;
+            L.next[pr * kWave + t] = pn;
+        }
+        if (rb < 0) {
+            bad = true;   // elements left but no finite front (NaN depths)
+            break;
+        }
+        const int s = L.cur[rb * kWave + t];
+        L.cur[rb * kWave + t] = (uint8_t)(s + 1);
+        const int c = L.cnt[rb * kWave + t];
+        const InLds inr = L.in[rb];
+        const uint32_t eb = L.ebase[rb * kWave + t];
+        const uint32_t e = eb + (uint32_t)s * inr.stride;
+        pc = gload(inr.color, e);
+        pd = gload(inr.depth, e);
+        pn = (s + 2 < c) ? gload(inr.depth, eb + (uint32_t)(s + 2) * inr.stride).x : __builtin_inff();
+        pr = rb;
+        L.front[rb * kWave + t] = L.next[rb * kWave + t];
+    }
+    if (bad) {
+        reject_pixel(P, p);
+        return;
+    }
+    if (total > 0) {
+        sc[(uint32_t)(total - 1) * kWave + t] = pc;
+        sd[(uint32_t)(total - 1) * kWave + t] = pd;
+    }
+    const StageReader rd{sc, sd, (uint32_t)t, (uint32_t)t};
+    resegment<true>(P, rd, total, p);
+}
+
+// Slab of block b (lane t's element i at [i * 64 + t] of it).
+__device__ inline void stage_slab(const CompParams& P, uint32_t b, float4*& sc, float2*& sd)
+{
+    const size_t base = (size_t)b * (size_t)P.seq_cap * kWave;
+    sc = P.stage_c + base;
+    sd = P.stage_d + base;
+}
+
+// All pixels by the general merge (k above the depth-disjoint path's limit),
+// grid-stride over the 64-pixel blocks.
 __global__ __launch_bounds__(64) void composite_kernel(CompParams P)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int t = threadIdx.x;
     setup_inputs(P, lds_raw, t);
     __syncthreads();
-    uint32_t p;
-    if (block_pixel(P, blockIdx.x, t, p)) composite_pixel(P, lds_raw, t, p);
+    const uint32_t nblk = composite_blocks(P);
+    float4* sc = nullptr;
+    float2* sd = nullptr;
+    if (P.stage_c) stage_slab(P, blockIdx.x, sc, sd);
+    for (uint32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        uint32_t p;
+        if (!block_pixel(P, blk, t, p)) continue;
+        if (sc) composite_pixel_staged(P, lds_raw, t, p, sc, sd);
+        else composite_pixel(P, lds_raw, t, p);
+    }
 }
 
 // Depth-disjoint path over all pixels; the others are queued.
@@ -648,8 +755,13 @@ __global__ __launch_bounds__(64) void composite_queue_kernel(CompParams P)
     setup_inputs(P, lds_raw, t);
     __syncthreads();
     const uint32_t n = (uint32_t)*P.q_count;
-    for (uint32_t idx = blockIdx.x * kWave + t; idx < n; idx += gridDim.x * kWave)
-        composite_pixel(P, lds_raw, t, (uint32_t)P.q_list[idx]);
+    float4* sc = nullptr;
+    float2* sd = nullptr;
+    if (P.stage_c) stage_slab(P, blockIdx.x, sc, sd);
+    for (uint32_t idx = blockIdx.x * kWave + t; idx < n; idx += gridDim.x * kWave) {
+        if (sc) composite_pixel_staged(P, lds_raw, t, (uint32_t)P.q_list[idx], sc, sd);
+        else composite_pixel(P, lds_raw, t, (uint32_t)P.q_list[idx]);
+    }
 }
 
 // ---------------------------------------------------------------- batched (persistent)
@@ -749,26 +861,21 @@ void launch_batch(const CompParams* jobs, const uint2* tiles, uint32_t n_tiles, 
     hipLaunchKernelGGL(batch_queue_kernel, dim3(grid_gen), dim3(kWave), lds_gen, s, jobs, n_jobs, t_se);
 }
 
-size_t composite_lds_bytes(int k, int seq_cap)
+size_t composite_lds_bytes(int k, int seq_cap, bool staged)
 {
-    const size_t sb = ((size_t)(k <= 16 ? (seq_cap + 1) / 2 : seq_cap) + 3) & ~(size_t)3;
+    const size_t sb = staged ? 0 : ((size_t)(k <= 16 ? (seq_cap + 1) / 2 : seq_cap) + 3) & ~(size_t)3;
     return sizeof(InLds) * kMaxInputs + (size_t)kWave * (sb + 14 * (size_t)k);
-}
-
-uint32_t composite_blocks(const CompParams& P)
-{
-    if (P.row_blocks) return (P.npix + 63u) / 64u;
-    return ((uint32_t)(P.width + 7) / 8u) * ((P.npix / (uint32_t)P.width + 7u) / 8u);
 }
 
 size_t cat_lds_bytes(int k) { return sizeof(InLds) * kMaxInputs + (size_t)kWave * 8 * (size_t)k; }
 
 void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
 {
-    const size_t lds = composite_lds_bytes(P.k, P.seq_cap);
+    const size_t lds = composite_lds_bytes(P.k, P.seq_cap, P.stage_c != nullptr);
     const unsigned blocks = composite_blocks(P);
+    const unsigned g2 = std::max(1u, std::min(blocks, (unsigned)grid_general));
     if (P.k > kCatMaxInputs) {
-        hipLaunchKernelGGL(composite_kernel, dim3(blocks), dim3(kWave), lds, s, P);
+        hipLaunchKernelGGL(composite_kernel, dim3(P.stage_c ? g2 : blocks), dim3(kWave), lds, s, P);
         return;
     }
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(1), 0, s, (uint32_t*)P.q_count, 0u);
@@ -777,9 +884,9 @@ void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
     // it stays cached; fewer resident waves (the general merge's LDS
     // footprint) keep it cached, and measured faster.  Slot-major inputs use
     // whole lines per step and prefer full occupancy.
-    const size_t lds_cat = P.cache_bound ? std::max(lds, cat_lds_bytes(P.k)) : cat_lds_bytes(P.k);
+    const size_t lds_cat = P.cache_bound ? std::max(composite_lds_bytes(P.k, P.seq_cap), cat_lds_bytes(P.k))
+                                         : cat_lds_bytes(P.k);
     hipLaunchKernelGGL(composite_cat_kernel, dim3(blocks), dim3(kWave), lds_cat, s, P);
-    const unsigned g2 = std::max(1u, std::min(blocks, (unsigned)grid_general));
     hipLaunchKernelGGL(composite_queue_kernel, dim3(g2), dim3(kWave), lds, s, P);
 }
 

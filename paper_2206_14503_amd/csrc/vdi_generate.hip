@@ -48,14 +48,16 @@ __device__ inline void gen_close(GenSeg& S, int& count, const GenOut& o, const R
     S.open = false;
 }
 
+// Stencil loads of sample k, issued now and blended later: the sampling loops
+// run two samples ahead (a load past the end of the run re-reads the run's
+// last sample), so a sample's loads overlap the segmentation of the two
+// before it.
 template <typename VT>
-__device__ inline float4 gen_sample(const VT* data, const BrickGeo& g, const Ray& r, float step, int k,
-                                    const float4* tf, int entries)
+__device__ inline Taps gen_fetch(const VT* data, const BrickGeo& g, const Ray& r, float step, int k)
 {
     float t = sample_t(r, k, step);
     float p[3] = { sample_coord(r, t, 0), sample_coord(r, t, 1), sample_coord(r, t, 2) };
-    float s = trilinear<VT>(data, g, p);
-    return tf_lookup(tf, entries, s);
+    return trilinear_fetch<VT>(data, g, p);
 }
 
 __device__ inline void gen_seg_init(GenSeg& S)
@@ -141,11 +143,19 @@ __device__ int gen_pass(const VT* data, const BrickGeo& g, const Ray& r, float s
     gen_seg_init(S);
     int count = 0, n_opaque = 0;
     const bool unit = (l_step == 1.0f);
-    for (int k = k0; k < k1; ++k) {
-        const GenSample q = gen_prep(gen_sample<VT>(data, g, r, step, k, tf, entries), l_step, unit);
-        n_opaque += q.transparent ? 0 : 1;
-        gen_step<WRITE>(S, count, o, r, step, l_step, g2, cap, k, q);
-        if (EARLY && count > limit) break;
+    if (k1 > k0) {
+        const int kl = k1 - 1;
+        Taps ta = gen_fetch<VT>(data, g, r, step, k0);
+        Taps tb = gen_fetch<VT>(data, g, r, step, min(k0 + 1, kl));
+        for (int k = k0; k < k1; ++k) {
+            const Taps tc = gen_fetch<VT>(data, g, r, step, min(k + 2, kl));
+            const GenSample q = gen_prep(tf_lookup(tf, entries, trilinear_blend(ta)), l_step, unit);
+            ta = tb;
+            tb = tc;
+            n_opaque += q.transparent ? 0 : 1;
+            gen_step<WRITE>(S, count, o, r, step, l_step, g2, cap, k, q);
+            if (EARLY && count > limit) break;
+        }
     }
     if (S.open) gen_close<WRITE>(S, count, o, r, step, l_step);
     if (n_opaque_out) *n_opaque_out = n_opaque;
@@ -173,18 +183,26 @@ __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float 
     GenOut none{nullptr, nullptr, 0, 0, 0};
     const bool unit = (l_step == 1.0f);
     int n_opaque = 0;
-    for (int k = k0; k < k1; ++k) {
-        const GenSample q = gen_prep(gen_sample<VT>(data, g, r, step, k, tf, entries), l_step, unit);
-        n_opaque += q.transparent ? 0 : 1;
-        // a frozen state (count above limit) keeps stepping: its count only
-        // grows, so its outcome stays decided
-        bool live = false;
+    if (k1 > k0) {
+        const int kl = k1 - 1;
+        Taps ta = gen_fetch<VT>(data, g, r, step, k0);
+        Taps tb = gen_fetch<VT>(data, g, r, step, min(k0 + 1, kl));
+        for (int k = k0; k < k1; ++k) {
+            const Taps tc = gen_fetch<VT>(data, g, r, step, min(k + 2, kl));
+            const GenSample q = gen_prep(tf_lookup(tf, entries, trilinear_blend(ta)), l_step, unit);
+            ta = tb;
+            tb = tc;
+            n_opaque += q.transparent ? 0 : 1;
+            // a frozen state (count above limit) keeps stepping: its count only
+            // grows, so its outcome stays decided
+            bool live = false;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) {
-            gen_step<false>(S[j], cnt[j], none, r, step, l_step, g2[j], 0, k, q);
-            live |= cnt[j] <= limit;
+            for (int j = 0; j < NC; ++j) {
+                gen_step<false>(S[j], cnt[j], none, r, step, l_step, g2[j], 0, k, q);
+                live |= cnt[j] <= limit;
+            }
+            if (!live) break;
         }
-        if (!live) break;
     }
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
@@ -219,7 +237,20 @@ __device__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, floa
     float lo = 0.0f, hi = P.gmax;
     int hi_count = -1;
     int level = 0;
-    {
+    if (P.mode == VDI_TAU_BISECT_SEQ) {
+        // one midpoint per pass, in the order the halvings visit them
+        for (; level < P.iters; ++level) {
+            float m = 0.5f * (lo + hi);
+            int c1[1];
+            gen_scan<VT, 1>(data, g, r, step, l_step, k0, k1, tf, entries, &m, P.max_n, c1, nullptr);
+            if (c1[0] <= P.max_n) {
+                hi = m;
+                hi_count = c1[0];
+            } else {
+                lo = m;
+            }
+        }
+    } else {
         float gg[kGeoLevels];
         int cg[kGeoLevels];
 #pragma unroll
@@ -512,11 +543,17 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
     GenSeg S;
     gen_seg_init(S);
     int count = 0, m = 0;
+    const int kl = k1 > k0 ? k1 - 1 : k0;
+    Taps ta, tb;
+    if (k1 > k0) {
+        ta = gen_fetch<VT>(data, g, r, P.step, k0);
+        tb = gen_fetch<VT>(data, g, r, P.step, min(k0 + 1, kl));
+    }
     for (int k = k0; k < k1; ++k) {
-        float t = sample_t(r, k, P.step);
-        float p[3] = { sample_coord(r, t, 0), sample_coord(r, t, 1), sample_coord(r, t, 2) };
-        float sv = trilinear<VT>(data, g, p);
-        const float4 cs = tf_lookup(tf_s, P.tf_entries, sv);
+        const Taps tc = gen_fetch<VT>(data, g, r, P.step, min(k + 2, kl));
+        const float4 cs = tf_lookup(tf_s, P.tf_entries, trilinear_blend(ta));
+        ta = tb;
+        tb = tc;
         const float a32 = cs.w;   // the transfer function's opacity, as in the histogram's definition
         if (a32 > 0.0f) {
             int j = (int)ceilf(64.0f * a32) - 1;

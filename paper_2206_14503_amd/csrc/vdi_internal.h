@@ -299,20 +299,29 @@ template <> __device__ inline float load_one<__half>(const __half* base, uint32_
     return __half2float(*(const __half*)((const char*)base + i * 2u));
 }
 
-// Trilinear reconstruction on the global voxel grid from a halo'd brick.
-// Each of the four x-rows of the 2x2x2 stencil is read with one paired load
-// at xb = min(x0, dx-2), which stays inside the row also at clamped edges.
+// Trilinear reconstruction on the global voxel grid from a halo'd brick, in
+// two halves so that loops can issue the loads of a later sample before
+// blending an earlier one.  Each of the four x-rows of the 2x2x2 stencil is
+// read with one paired load at xb = min(x0, dx-2), which stays inside the row
+// also at clamped edges; every index is clamped to the data box, so the loads
+// stay in bounds for any position.
+struct Taps {
+    float a[4], b[4];   // rows (y0,z0), (y1,z0), (y0,z1), (y1,z1): voxels xb, xb+1
+    float w[3];         // blend weights
+    bool s0, s1;        // x0 (x1) is the row's first voxel
+};
+
 template <typename VT>
-__device__ inline float trilinear(const VT* data, const BrickGeo& g, const float p[3])
+__device__ inline Taps trilinear_fetch(const VT* data, const BrickGeo& g, const float p[3])
 {
 #pragma clang fp contract(off)
+    Taps t;
     int i0[3], i1[3];
-    float w[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float u = __builtin_fmaf(p[a], g.nf[a], -0.5f);
         float f = floorf(u);
-        w[a] = u - f;
+        t.w[a] = u - f;
         int ii = (int)f - g.dlo[a];
         i0[a] = clampi(ii, g.clo[a], g.chi[a]);
         i1[a] = clampi(ii + 1, g.clo[a], g.chi[a]);
@@ -322,37 +331,44 @@ __device__ inline float trilinear(const VT* data, const BrickGeo& g, const float
     const uint32_t y0 = __umul24((uint32_t)i0[1], g.sy), y1 = __umul24((uint32_t)i1[1], g.sy);
     const uint32_t z0 = __umul24((uint32_t)i0[2], g.sz), z1 = __umul24((uint32_t)i1[2], g.sz);
     const uint32_t r00 = y0 + z0, r10 = y1 + z0, r01 = y0 + z1, r11 = y1 + z1;
-    float v000, v100, v010, v110, v001, v101, v011, v111;
     if (g.sx2) {
         const int xb = i0[0] < g.xmax ? i0[0] : g.xmax;
-        const bool s0 = i0[0] == xb, s1 = i1[0] == xb;
-        // all four loads in flight before any is used
-        float a0, b0, a1, b1, a2, b2, a3, b3;
-        load_pair<VT>(data, r00 + xb, a0, b0);
-        load_pair<VT>(data, r10 + xb, a1, b1);
-        load_pair<VT>(data, r01 + xb, a2, b2);
-        load_pair<VT>(data, r11 + xb, a3, b3);
-        v000 = s0 ? a0 : b0;
-        v100 = s1 ? a0 : b0;
-        v010 = s0 ? a1 : b1;
-        v110 = s1 ? a1 : b1;
-        v001 = s0 ? a2 : b2;
-        v101 = s1 ? a2 : b2;
-        v011 = s0 ? a3 : b3;
-        v111 = s1 ? a3 : b3;
+        t.s0 = i0[0] == xb;
+        t.s1 = i1[0] == xb;
+        load_pair<VT>(data, r00 + xb, t.a[0], t.b[0]);
+        load_pair<VT>(data, r10 + xb, t.a[1], t.b[1]);
+        load_pair<VT>(data, r01 + xb, t.a[2], t.b[2]);
+        load_pair<VT>(data, r11 + xb, t.a[3], t.b[3]);
     } else {
-        v000 = v100 = load_one<VT>(data, r00);
-        v010 = v110 = load_one<VT>(data, r10);
-        v001 = v101 = load_one<VT>(data, r01);
-        v011 = v111 = load_one<VT>(data, r11);
+        t.s0 = t.s1 = true;
+        t.a[0] = t.b[0] = load_one<VT>(data, r00);
+        t.a[1] = t.b[1] = load_one<VT>(data, r10);
+        t.a[2] = t.b[2] = load_one<VT>(data, r01);
+        t.a[3] = t.b[3] = load_one<VT>(data, r11);
     }
-    float c00 = lerp_exact(v000, v100, w[0]);
-    float c10 = lerp_exact(v010, v110, w[0]);
-    float c01 = lerp_exact(v001, v101, w[0]);
-    float c11 = lerp_exact(v011, v111, w[0]);
-    float c0 = lerp_exact(c00, c10, w[1]);
-    float c1 = lerp_exact(c01, c11, w[1]);
-    return lerp_exact(c0, c1, w[2]);
+    return t;
+}
+
+__device__ inline float trilinear_blend(const Taps& t)
+{
+#pragma clang fp contract(off)
+    const float v000 = t.s0 ? t.a[0] : t.b[0], v100 = t.s1 ? t.a[0] : t.b[0];
+    const float v010 = t.s0 ? t.a[1] : t.b[1], v110 = t.s1 ? t.a[1] : t.b[1];
+    const float v001 = t.s0 ? t.a[2] : t.b[2], v101 = t.s1 ? t.a[2] : t.b[2];
+    const float v011 = t.s0 ? t.a[3] : t.b[3], v111 = t.s1 ? t.a[3] : t.b[3];
+    float c00 = lerp_exact(v000, v100, t.w[0]);
+    float c10 = lerp_exact(v010, v110, t.w[0]);
+    float c01 = lerp_exact(v001, v101, t.w[0]);
+    float c11 = lerp_exact(v011, v111, t.w[0]);
+    float c0 = lerp_exact(c00, c10, t.w[1]);
+    float c1 = lerp_exact(c01, c11, t.w[1]);
+    return lerp_exact(c0, c1, t.w[2]);
+}
+
+template <typename VT>
+__device__ inline float trilinear(const VT* data, const BrickGeo& g, const float p[3])
+{
+    return trilinear_blend(trilinear_fetch<VT>(data, g, p));
 }
 
 // Transfer-function cell and weight of scalar s.

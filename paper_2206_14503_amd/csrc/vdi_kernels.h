@@ -128,16 +128,26 @@ struct CompParams {
     int seq_cap;              // merged-list capacity per pixel (sum of input max_n)
     int* q_list;              // [npix] pixels left to the general merge
     int* q_count;             // their number
+    // optional staging of the general merge: per block a slab of seq_cap * 64
+    // entries where lane t's merged element i sits at [i * 64 + t]
+    float4* stage_c;
+    float2* stage_d;
 };
 
 // Inputs up to which the depth-disjoint path runs (4-bit list ids).
 constexpr int kCatMaxInputs = 16;
 
-size_t composite_lds_bytes(int k, int seq_cap);   // general merge
+size_t composite_lds_bytes(int k, int seq_cap, bool staged = false);   // general merge
 size_t cat_lds_bytes(int k);                      // depth-disjoint path
-// grid_general: blocks of the queue-driven general merge
+// grid_general: blocks of the queue-driven general merge (with staging, at
+// most the number of slabs)
 void launch_composite(const CompParams& P, int grid_general, hipStream_t s);
-uint32_t composite_blocks(const CompParams& P);   // 64-pixel blocks of the image
+// 64-pixel blocks of the image
+__host__ __device__ inline uint32_t composite_blocks(const CompParams& P)
+{
+    if (P.row_blocks) return (P.npix + 63u) / 64u;
+    return ((uint32_t)(P.width + 7) / 8u) * ((P.npix / (uint32_t)P.width + 7u) / 8u);
+}
 
 // Pixels are processed in blocks of 64, one per wavefront: 8x8 squares
 // numbered row-major over the image (blocks_x = ceil(width / 8)), or, with

@@ -161,9 +161,12 @@ def timed(fn, reps: int = 3) -> float:
 def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor,
              reps: int = 3) -> Dict[str, float]:
     """Plain bisection vs learned generation on held-out frames: time, fallback
-    rate, count statistics and the original-view rendering error of each."""
+    rate, count statistics and the original-view rendering error of each.  The
+    plain search is timed twice: speculative (several midpoints per pass, the
+    library's BISECT) and one midpoint per pass (BISECT_SEQ, the search as the
+    paper runs it); both give the same VDIs."""
     step = 1.0 / cfg.n
-    t_plain = t_learned = 0.0
+    t_plain = t_learned = t_seq = 0.0
     agg = {"accepted": 0, "refined": 0, "shortcut": 0, "fallback": 0, "empty": 0}
     mae_learned = 0.0
     dn_sum, dn_rays = 0.0, 0
@@ -180,10 +183,14 @@ def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch
         run_l = lambda: vdi.generate(dbr, cam, tf_d, step, step, vdi.LEARNED, 0.0, cfg.max_n, cfg.iters,
                                      outs=outs_l, gamma_max=cfg.gamma_max, mlp=mlp,
                                      fallback_tol=cfg.fallback_tol, feature_scale=cfg.feature_scale)
+        run_s = lambda: vdi.generate(dbr, cam, tf_d, step, step, vdi.BISECT_SEQ, 0.0, cfg.max_n, cfg.iters,
+                                     outs=outs_p, gamma_max=cfg.gamma_max)
+        run_s()
         run_p()
         run_l()
         torch.cuda.synchronize()
         vdi.learned_stats()
+        t_seq += timed(run_s, reps)
         t_plain += timed(run_p, reps)
         t_learned += timed(run_l, reps)
         st = vdi.learned_stats()
@@ -214,6 +221,8 @@ def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch
         "plain_ms": t_plain / frames,
         "learned_ms": t_learned / frames,
         "speedup": t_plain / t_learned,
+        "plain_seq_ms": t_seq / frames,
+        "speedup_vs_seq": t_seq / t_learned,
         "fallback_rate": agg["fallback"] / max(served_total, 1),
         "accepted": agg["accepted"], "refined": agg["refined"], "fallback": agg["fallback"],
         "shortcut": agg["shortcut"], "empty": agg["empty"],

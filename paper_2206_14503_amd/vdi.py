@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvdi.so")
 
 REGULAR, COMPACT = 0, 1
-FIXED, BISECT, LEARNED = 0, 1, 2
+FIXED, BISECT, LEARNED, BISECT_SEQ = 0, 1, 2, 3
 F32, F16 = 0, 1
 
 _STATUS = {0: "VDI_OK", -1: "VDI_E_INVALID", -2: "VDI_E_UNSUPPORTED", -3: "VDI_E_HIP", -4: "VDI_E_INPUT",

@@ -149,6 +149,26 @@ def test_generate_compact_matches_regular(V, mode):
         assert np.array_equal(_np(cmp_[r].gamma), _np(reg[r].gamma))
 
 
+@pytest.mark.parametrize("iters", [10, 3], ids=["iters10", "iters3"])
+def test_generate_sequential_bisection_identical(V, orc, iters):
+    """BISECT_SEQ (one midpoint per pass) and BISECT (several midpoints per
+    pass, decisions replayed) run the same halvings: identical VDIs and
+    thresholds, bit for bit, and both match the oracle's bisection."""
+    import torch
+    cam = synth.orbit_camera(10_012, 83, 57)
+    vol, tf, tf_d, cam, bricks, dbr = _tiny_setup(V, 1, grid=(1, 2, 2), cam=cam)
+    spec = V.generate(dbr, cam, tf_d, 1 / 64, 1 / 64, V.BISECT, 0.0, 6, iters)
+    seq = V.generate(dbr, cam, tf_d, 1 / 64, 1 / 64, V.BISECT_SEQ, 0.0, 6, iters)
+    torch.cuda.synchronize()
+    assert V.device_status() == 0
+    ref = orc.generate(vol, bricks, cam, tf, 1 / 64, 1 / 64, 1, 0.0, 6, iters)
+    for r in range(len(bricks)):
+        a, b = _gpu_regular(spec[r]), _gpu_regular(seq[r])
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+        _compare_lists(*b[:3], ref["color"][r], ref["depth"][r], ref["count"][r], ref["margin"][r], f"brick {r}")
+
+
 def test_generate_compact_capacity_overflow_flagged(V):
     import torch
     cam = synth.ortho_camera(64, 64, "+z")
@@ -245,6 +265,34 @@ def test_composite_interleaved_stress_parity(V, orc):
     _compare_lists(gc, gd, gn, oref["color"], oref["depth"], oref["count"], oref["margin"], "stress")
 
 
+@pytest.mark.parametrize("n,out_n", [(6, 10), (2, 48)], ids=["bisect", "passthrough"])
+def test_composite_many_inputs_ragged_parity(V, orc, n, out_n):
+    """k = 24 interleaved inputs (above the depth-disjoint path's 16), ragged
+    list lengths 0..n and a ragged last pixel block (300 pixels): the general
+    merge over every pixel."""
+    import torch
+    k, W, H = 24, 20, 15
+    P = W * H
+    col, dep, cnt = synth.dense_interleaved_lists(k, n, P, seed=7)
+    rng = np.random.default_rng(7)
+    cnt = torch.from_numpy(rng.integers(0, n + 1, size=(k, P)).astype(np.int32))
+    for r in range(k):
+        for j in range(n):
+            unused = cnt[r] <= j
+            col[r, j, unused] = 0.0
+            dep[r, j, unused] = 0.0
+    ins = [V.VDI(W, H, n, 0.01, V.REGULAR, col[r].cuda().contiguous(), dep[r].cuda().contiguous(),
+                 cnt[r].cuda().contiguous()) for r in range(k)]
+    out = V.composite(ins, V.BISECT, 0.0, out_n, 10)
+    torch.cuda.synchronize()
+    assert V.device_status() == 0
+    c, d, m = col.numpy(), dep.numpy(), cnt.numpy()
+    oref = orc.composite([c[r] for r in range(k)], [d[r] for r in range(k)], [m[r] for r in range(k)], 0.01, 1, 0.0,
+                         out_n, 10)
+    gc, gd, gn, gg = _gpu_regular(out)
+    _compare_lists(gc, gd, gn, oref["color"], oref["depth"], oref["count"], oref["margin"], f"k24 N{out_n}")
+
+
 @pytest.mark.parametrize("out_n", [4, 30], ids=["bisect", "passthrough"])
 def test_composite_mixed_disjoint_and_interleaved(V, orc, out_n):
     """One launch where half of the pixels hold depth-disjoint lists (in a
@@ -332,6 +380,8 @@ def test_api_argument_errors(V):
         V.composite([v, bad], V.BISECT, 0.0, 2, 10)
     with pytest.raises(V.VdiError):
         V.composite([v], V.BISECT, 0.0, 2, 0)
+    with pytest.raises(V.VdiError):
+        V.composite([v], V.BISECT_SEQ, 0.0, 2, 10)   # generation only
 
 
 # ---------------------------------------------------------------- rendering and end to end
