@@ -191,6 +191,7 @@ struct Src {
     const float4* c;
     const float2* d;
     uint32_t e;
+    bool join;   // first element of a list that follows another (depth-disjoint reader)
 };
 
 // Sequential reader of a lane's merge sequence (general merge).
@@ -212,7 +213,7 @@ struct SeqReader {
         uint32_t s = L->cur[r * kWave + t];
         L->cur[r * kWave + t] = (uint8_t)(s + 1);
         const InLds in = L->in[r];
-        return Src{in.color, in.depth, L->ebase[r * kWave + t] + s * in.stride};
+        return Src{in.color, in.depth, L->ebase[r * kWave + t] + s * in.stride, false};
     }
 };
 
@@ -225,7 +226,7 @@ struct StageReader {
     __device__ void reset() { e = t; }
     __device__ Src next()
     {
-        Src q{c, d, e};
+        Src q{c, d, e, false};
         e += kWave;
         return q;
     }
@@ -280,7 +281,7 @@ struct CatReader {
     __device__ void reset() { open(0); }
     __device__ Src next()
     {
-        Src q{color, depth, e};
+        Src q{color, depth, e, s == 0 && li > 0};
         if (++s == c) {
             open(li + 1);
         } else {
@@ -290,11 +291,21 @@ struct CatReader {
     }
 };
 
+// Validation of the next element of a merged list: finite depths, f < b,
+// fronts non-decreasing; where a depth-disjoint reader joins two lists the
+// front must increase strictly (equal fronts would merge by input index,
+// which the concatenation does not follow).
+__device__ inline bool elem_ok(float2 fb, float prev_f, bool join)
+{
+    return isfinite(fb.x) & isfinite(fb.y) & (fb.x < fb.y) & (join ? fb.x > prev_f : fb.x >= prev_f);
+}
+
 // One scan of the merged list carrying NC segmenter states (thresholds g[]).
 // Counting scans (WRITE false) freeze a state once its count exceeds
 // `limit` and stop when every state is frozen, unless VALIDATE: then every
 // element is visited and checked (finite depths, f < b, fronts
-// non-decreasing), and *bad reports a violation.
+// non-decreasing) up to the first violation, which ends the scan and is
+// reported in *bad.
 template <int NC, bool WRITE, bool VALIDATE, typename R>
 __device__ void c_scan(R rd, int total, float inv_ref, const float* gam, int cap, int limit, const COut& o,
                        int* counts, bool* bad)
@@ -312,17 +323,20 @@ __device__ void c_scan(R rd, int total, float inv_ref, const float* gam, int cap
         Src src = rd.next();
         float4 cn = gload(src.c, src.e);
         float2 fn = gload(src.d, src.e);
+        bool jn = src.join;
         float prev_f = -__builtin_inff();
         for (int i = 0; i < total; ++i) {
             float4 cc = cn;
             float2 fc = fn;
+            const bool jc = jn;
             if (i + 1 < total) {
                 Src nx = rd.next();
                 cn = gload(nx.c, nx.e);
                 fn = gload(nx.d, nx.e);
+                jn = nx.join;
             }
             if (VALIDATE) {
-                ok &= isfinite(fc.x) & isfinite(fc.y) & (fc.x < fc.y) & (fc.x >= prev_f);
+                ok &= elem_ok(fc, prev_f, jc);
                 prev_f = fc.x;
             }
             CElem e = prep(cc, fc, inv_ref);
@@ -334,7 +348,8 @@ __device__ void c_scan(R rd, int total, float inv_ref, const float* gam, int cap
                 c_step<WRITE>(S[c], o, inv_ref, g2[c], cap, e);
                 live |= WRITE || S[c].count <= limit;
             }
-            if (!VALIDATE && !live) break;
+            // a failed validation decides the pass (its counts are unused)
+            if (VALIDATE ? !ok : !live) break;
         }
     }
 #pragma unroll
@@ -394,9 +409,10 @@ constexpr int kCompGeoLevels = 4;
 // Re-segmentation of pixel p's merged list (read through rd, `total`
 // elements): pass-through when it fits (R17), else the fixed threshold or the
 // bisection (two levels per scan), then the zero-filled tail.  With VALIDATE
-// the first pass checks the elements; an invalid list is rejected.
+// the first pass checks the elements and returns false, with the pixel's
+// output incomplete, if one fails.
 template <bool VALIDATE, typename R>
-__device__ void resegment(const CompParams& P, const R& rd0, int total, uint32_t p)
+__device__ bool resegment(const CompParams& P, const R& rd0, int total, uint32_t p)
 {
     COut o{P.out_color, P.out_depth, p, P.npix, P.out_n};
     int count;
@@ -414,8 +430,9 @@ __device__ void resegment(const CompParams& P, const R& rd0, int total, uint32_t
             const float4 c = gload(src.c, src.e);
             const float2 fb = gload(src.d, src.e);
             if (VALIDATE) {
-                ok &= isfinite(fb.x) & isfinite(fb.y) & (fb.x < fb.y) & (fb.x >= prev_f);
+                ok &= elem_ok(fb, prev_f, src.join);
                 prev_f = fb.x;
+                if (!ok) break;
             }
             P.out_color[slot] = c;
             P.out_depth[slot] = fb;
@@ -482,10 +499,7 @@ __device__ void resegment(const CompParams& P, const R& rd0, int total, uint32_t
             count = c1[0];
         }
     }
-    if (VALIDATE && bad) {
-        reject_pixel(P, p);
-        return;
-    }
+    if (VALIDATE && bad) return false;
     if (count > P.out_n) count = P.out_n;
     for (int j = count; j < P.out_n; ++j) {
         size_t slot = (size_t)j * P.npix + p;
@@ -494,18 +508,20 @@ __device__ void resegment(const CompParams& P, const R& rd0, int total, uint32_t
     }
     P.out_count[p] = count;
     if (P.out_gamma) P.out_gamma[p] = gm;
+    return true;
 }
 
-// Depth-disjoint path for pixel p (lane t): when the non-empty lists occupy
-// disjoint depth ranges, the merge by (front, input) is their concatenation
-// in order of first front (every front of an earlier list lies below the
-// next list's first front), so no merge sequence is stored.  Returns false,
-// writing nothing, when two lists interleave (the pixel then takes the
-// general merge).
+// Depth-disjoint path for pixel p (lane t): when every front of a list lies
+// below the first front of the list after it in order of first front, the
+// merge by (front, input) is the lists' concatenation in that order, so no
+// merge sequence is stored.  The first scan checks this (fronts increasing
+// across each join) together with the elements themselves; on a failure it
+// returns false and the pixel takes the general merge, which validates it
+// and rewrites its whole output.
 __device__ bool composite_pixel_cat(const CompParams& P, unsigned char* lds_raw, int t, uint32_t p)
 {
     const CatLds L = cat_layout(lds_raw, P.k);
-    // ---- counts (validated), first front and last back of every list
+    // ---- counts (validated) and first front of every list
     int total = 0;
     for (int r = 0; r < P.k; ++r) {
         const CompInput& in = P.in[r];
@@ -516,19 +532,16 @@ __device__ bool composite_pixel_cat(const CompParams& P, unsigned char* lds_raw,
             reject_pixel(P, p);
             return true;
         }
-        float f0 = __builtin_inff(), bl = __builtin_inff();
+        float f0 = __builtin_inff();
         if (c > 0) {
-            const uint32_t stride = in.compact ? 1u : P.npix;
             f0 = gload(in.depth, eb).x;
-            bl = gload(in.depth, eb + (uint32_t)(c - 1) * stride).y;
-            // non-finite ends: the general merge validates (and rejects) the pixel
-            if (!isfinite(f0) || !isfinite(bl)) return false;
+            // a non-finite front: the general merge validates (and rejects) the pixel
+            if (!isfinite(f0)) return false;
         }
         L.a[r * kWave + t] = f0;   // +inf marks an empty list
-        L.b[r * kWave + t] = bl;
         total += c;
     }
-    // ---- order by (first front, input); check that consecutive lists are disjoint
+    // ---- order by (first front, input)
     uint64_t ord = 0;
     int ne = 0;
     for (int r = 0; r < P.k; ++r) {
@@ -542,10 +555,6 @@ __device__ bool composite_pixel_cat(const CompParams& P, unsigned char* lds_raw,
         ord |= (uint64_t)r << (4 * rank);
         ++ne;
     }
-    for (int i = 0; i + 1 < ne; ++i) {
-        const int ra = (int)((ord >> (4 * i)) & 15u), rb = (int)((ord >> (4 * (i + 1))) & 15u);
-        if (!(L.b[ra * kWave + t] <= L.a[rb * kWave + t])) return false;
-    }
     // ---- the reader's per-list words: count and element index of slot 0
     for (int r = 0; r < P.k; ++r) {
         const CompInput& in = P.in[r];
@@ -553,8 +562,7 @@ __device__ bool composite_pixel_cat(const CompParams& P, unsigned char* lds_raw,
         L.b[r * kWave + t] = __uint_as_float(in.compact ? in.offset[p] : p);
     }
     CatReader rd{L, t, ord, ne, 0, 0, 0, 0u, 0u, nullptr, nullptr};
-    resegment<true>(P, rd, total, p);
-    return true;
+    return resegment<true>(P, rd, total, p);
 }
 
 // General path for pixel p (lane t): k-way merge of the lists by (front,
@@ -702,7 +710,7 @@ __device__ void composite_pixel_staged(const CompParams& P, unsigned char* lds_r
         sd[(uint32_t)(total - 1) * kWave + t] = pd;
     }
     const StageReader rd{sc, sd, (uint32_t)t, (uint32_t)t};
-    resegment<true>(P, rd, total, p);
+    if (!resegment<true>(P, rd, total, p)) reject_pixel(P, p);
 }
 
 // Slab of block b (lane t's element i at [i * 64 + t] of it).
