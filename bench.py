@@ -7,7 +7,8 @@ one), composite them into one N=20 VDI and render it from the original view.  Th
 second of that step.  Further legs (same JSON line):
   large    -- 1024^3 fp16 volume in 16 bricks (4x2x2): generate + composite,
               and the composite alone on maximally interleaved dense lists
-              (16 x 20 supersegments per pixel), the HBM-bound case;
+              (16 x 20 supersegments per pixel, 16.6 GB of input);
+  dense    -- only that dense composite (implied by large);
   learned  -- learned vs plain threshold search on held-out tiny volumes (N=8)
               and on held-out FHD-generator volumes (N=20), the regressor
               trained here with the project's kernels;
@@ -242,8 +243,21 @@ def leg_large(args, result):
            "frac_hbm_peak": gbs / HBM_PEAK_GBS, "composited_pixels_per_s": P / (np.median(c_ms) * 1e-3)}
     del subs, dbr
     torch.cuda.empty_cache()
+    result["large"] = res
+    leg_dense(args, result)
 
-    # dense maximally interleaved lists: 16 inputs x 20 supersegments per pixel
+
+def leg_dense(args, result):
+    """The large share's composite on dense maximally interleaved lists:
+    16 inputs x 20 supersegments per pixel (16.6 GB of input), N = 20."""
+    import numpy as np
+    import torch
+    from paper_2206_14503_amd import synth, vdi
+
+    w = synth.large(args.seed)
+    cam = synth.camera_for(w)
+    P = cam.width * cam.height
+    res = result.setdefault("large", {"workload": w.name})
     k, n = 16, 20
     color = torch.empty((k, n, P, 4), dtype=torch.float32, device="cuda")
     depth = torch.empty((k, n, P, 2), dtype=torch.float32, device="cuda")
@@ -266,7 +280,6 @@ def leg_large(args, result):
     res["dense_interleaved"] = {"k": k, "n_per_input": n, "composite_ms": float(np.median(c2)),
                                 "algorithmic_bytes": b2, "achieved_GBps": gbs2, "frac_hbm_peak": gbs2 / HBM_PEAK_GBS,
                                 "composited_pixels_per_s": P / (np.median(c2) * 1e-3)}
-    result["large"] = res
     del color, depth, ins, out2
     torch.cuda.empty_cache()
 
@@ -453,6 +466,8 @@ def main():
     fhd = leg_fhd(args, result)
     if "large" in legs:
         leg_large(args, result)
+    elif "dense" in legs:
+        leg_dense(args, result)
     if "learned" in legs:
         leg_learned(args, result)
     if "batched" in legs:

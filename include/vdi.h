@@ -273,8 +273,8 @@ typedef struct vdi_batch vdi_batch;
 
 /* Checks the jobs (as vdi_composite would), then uploads a device job table
  * and a tile queue: jobs ordered by decreasing estimated work (k*N*pixels),
- * each job's image cut into 8x8-pixel blocks (one per wavefront) and the
- * blocks into tiles of tile_pixels/64 blocks, tile_pixels read from
+ * each job's image cut into blocks of 64 consecutive pixels (one per
+ * wavefront) and the blocks into tiles of tile_pixels/64 blocks, tile_pixels read from
  * `autotune_cache` (a file written by vdi_autotune; NULL or no entry: 256)
  * for the job's (k bucket, N) with k buckets 1-4, 5-8, 9-32.  Jobs with more
  * than 16 inputs, and pixels whose input lists interleave in depth, are

@@ -176,7 +176,7 @@ vdi_status create_impl(vdi_ctx* ctx, const vdi_job_t* jobs, int n_jobs, const Ti
             auto it = tiles_by_bucket.find({ k_bucket(hp[j].k), hp[j].out_n });
             tile = it != tiles_by_bucket.end() ? it->second : kDefaultTile;
         }
-        // tile size in pixels -> whole 8x8 blocks (at least one)
+        // tile size in pixels -> whole 64-pixel blocks (at least one)
         const uint32_t per = std::max<uint32_t>(1u, (uint32_t)tile / 64u);
         const uint32_t nblocks = composite_blocks(hp[j]);
         for (uint32_t b0 = 0; b0 < nblocks; b0 += per) {
