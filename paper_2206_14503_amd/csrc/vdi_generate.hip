@@ -48,16 +48,54 @@ __device__ inline void gen_close(GenSeg& S, int& count, const GenOut& o, const R
     S.open = false;
 }
 
-// Stencil loads of sample k, issued now and blended later: the sampling loops
-// run two samples ahead (a load past the end of the run re-reads the run's
-// last sample), so a sample's loads overlap the segmentation of the two
-// before it.
-template <typename VT>
+// Stencil loads of sample k, issued now and blended later.
+template <typename VT, bool PAIRED>
 __device__ inline Taps gen_fetch(const VT* data, const BrickGeo& g, const Ray& r, float step, int k)
 {
     float t = sample_t(r, k, step);
     float p[3] = { sample_coord(r, t, 0), sample_coord(r, t, 1), sample_coord(r, t, 2) };
-    return trilinear_fetch<VT>(data, g, p);
+    return trilinear_fetch<VT, PAIRED>(data, g, p);
+}
+
+// Calls body(k, value) for the samples k of [k0, k1) in order until it
+// returns false.  The stencil loads run SLOTS samples ahead: SLOTS stencil
+// slots in rotation (the loop unrolled by SLOTS), each refilled with the
+// sample SLOTS places on right after its blend, so no slot is copied and a
+// sample's loads overlap the work on the samples before it.  A load past the
+// run re-reads its last sample (every stencil index is clamped to the
+// brick's data box, so it stays in bounds).
+template <typename VT, bool PAIRED, int SLOTS, typename F>
+__device__ inline void for_samples_t(const VT* data, const BrickGeo& g, const Ray& r, float step, int k0, int k1,
+                                     F& body)
+{
+    static_assert(SLOTS == 2 || SLOTS == 3, "two or three stencil slots");
+    const int kl = k1 - 1;
+    Taps t0 = gen_fetch<VT, PAIRED>(data, g, r, step, k0);
+    Taps t1 = gen_fetch<VT, PAIRED>(data, g, r, step, min(k0 + 1, kl));
+    Taps t2;
+    if (SLOTS == 3) t2 = gen_fetch<VT, PAIRED>(data, g, r, step, min(k0 + 2, kl));
+    for (int k = k0;;) {
+        float v = trilinear_blend(t0);
+        t0 = gen_fetch<VT, PAIRED>(data, g, r, step, min(k + SLOTS, kl));
+        if (!body(k, v) || ++k >= k1) break;
+        v = trilinear_blend(t1);
+        t1 = gen_fetch<VT, PAIRED>(data, g, r, step, min(k + SLOTS, kl));
+        if (!body(k, v) || ++k >= k1) break;
+        if (SLOTS == 3) {
+            v = trilinear_blend(t2);
+            t2 = gen_fetch<VT, PAIRED>(data, g, r, step, min(k + SLOTS, kl));
+            if (!body(k, v) || ++k >= k1) break;
+        }
+    }
+}
+
+template <typename VT, int SLOTS = 3, typename F>
+__device__ inline void for_samples(const VT* data, const BrickGeo& g, const Ray& r, float step, int k0, int k1,
+                                   F&& body)
+{
+    if (k1 <= k0) return;
+    if (g.sx2) for_samples_t<VT, true, SLOTS>(data, g, r, step, k0, k1, body);
+    else for_samples_t<VT, false, SLOTS>(data, g, r, step, k0, k1, body);
 }
 
 __device__ inline void gen_seg_init(GenSeg& S)
@@ -143,20 +181,12 @@ __device__ int gen_pass(const VT* data, const BrickGeo& g, const Ray& r, float s
     gen_seg_init(S);
     int count = 0, n_opaque = 0;
     const bool unit = (l_step == 1.0f);
-    if (k1 > k0) {
-        const int kl = k1 - 1;
-        Taps ta = gen_fetch<VT>(data, g, r, step, k0);
-        Taps tb = gen_fetch<VT>(data, g, r, step, min(k0 + 1, kl));
-        for (int k = k0; k < k1; ++k) {
-            const Taps tc = gen_fetch<VT>(data, g, r, step, min(k + 2, kl));
-            const GenSample q = gen_prep(tf_lookup(tf, entries, trilinear_blend(ta)), l_step, unit);
-            ta = tb;
-            tb = tc;
-            n_opaque += q.transparent ? 0 : 1;
-            gen_step<WRITE>(S, count, o, r, step, l_step, g2, cap, k, q);
-            if (EARLY && count > limit) break;
-        }
-    }
+    for_samples<VT>(data, g, r, step, k0, k1, [&](int k, float v) {
+        const GenSample q = gen_prep(tf_lookup(tf, entries, v), l_step, unit);
+        n_opaque += q.transparent ? 0 : 1;
+        gen_step<WRITE>(S, count, o, r, step, l_step, g2, cap, k, q);
+        return !(EARLY && count > limit);
+    });
     if (S.open) gen_close<WRITE>(S, count, o, r, step, l_step);
     if (n_opaque_out) *n_opaque_out = n_opaque;
     return count;
@@ -183,27 +213,20 @@ __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float 
     GenOut none{nullptr, nullptr, 0, 0, 0};
     const bool unit = (l_step == 1.0f);
     int n_opaque = 0;
-    if (k1 > k0) {
-        const int kl = k1 - 1;
-        Taps ta = gen_fetch<VT>(data, g, r, step, k0);
-        Taps tb = gen_fetch<VT>(data, g, r, step, min(k0 + 1, kl));
-        for (int k = k0; k < k1; ++k) {
-            const Taps tc = gen_fetch<VT>(data, g, r, step, min(k + 2, kl));
-            const GenSample q = gen_prep(tf_lookup(tf, entries, trilinear_blend(ta)), l_step, unit);
-            ta = tb;
-            tb = tc;
-            n_opaque += q.transparent ? 0 : 1;
-            // a frozen state (count above limit) keeps stepping: its count only
-            // grows, so its outcome stays decided
-            bool live = false;
+    // many states: two stencil slots, to keep the states in registers
+    for_samples<VT, (NC >= 6 ? 2 : 3)>(data, g, r, step, k0, k1, [&](int k, float v) {
+        const GenSample q = gen_prep(tf_lookup(tf, entries, v), l_step, unit);
+        n_opaque += q.transparent ? 0 : 1;
+        // a frozen state (count above limit) keeps stepping: its count only
+        // grows, so its outcome stays decided
+        bool live = false;
 #pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                gen_step<false>(S[j], cnt[j], none, r, step, l_step, g2[j], 0, k, q);
-                live |= cnt[j] <= limit;
-            }
-            if (!live) break;
+        for (int j = 0; j < NC; ++j) {
+            gen_step<false>(S[j], cnt[j], none, r, step, l_step, g2[j], 0, k, q);
+            live |= cnt[j] <= limit;
         }
-    }
+        return live;
+    });
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
         if (S[j].open && cnt[j] <= limit) gen_close<false>(S[j], cnt[j], none, r, step, l_step);
@@ -222,7 +245,7 @@ constexpr int kGeoLevels = 6;
 // per scan (the midpoint m and both next-level midpoints).  Both reproduce
 // the sequential decisions exactly.
 template <typename VT>
-__device__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0,
+__device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0,
                            int k1, const float4* tf, int entries, const GenParams& P, float& gamma_out,
                            int& count_out, bool need_count)
 {
@@ -543,17 +566,8 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
     GenSeg S;
     gen_seg_init(S);
     int count = 0, m = 0;
-    const int kl = k1 > k0 ? k1 - 1 : k0;
-    Taps ta, tb;
-    if (k1 > k0) {
-        ta = gen_fetch<VT>(data, g, r, P.step, k0);
-        tb = gen_fetch<VT>(data, g, r, P.step, min(k0 + 1, kl));
-    }
-    for (int k = k0; k < k1; ++k) {
-        const Taps tc = gen_fetch<VT>(data, g, r, P.step, min(k + 2, kl));
-        const float4 cs = tf_lookup(tf_s, P.tf_entries, trilinear_blend(ta));
-        ta = tb;
-        tb = tc;
+    for_samples<VT>(data, g, r, P.step, k0, k1, [&](int k, float v) {
+        const float4 cs = tf_lookup(tf_s, P.tf_entries, v);
         const float a32 = cs.w;   // the transfer function's opacity, as in the histogram's definition
         if (a32 > 0.0f) {
             int j = (int)ceilf(64.0f * a32) - 1;
@@ -565,7 +579,8 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
             const GenSample q = gen_prep(cs, P.l_step, unit);
             gen_step<false>(S, count, none, r, P.step, P.l_step, g2, 0, k, q);
         }
-    }
+        return true;
+    });
     if (S.open && count <= P.max_n) gen_close<false>(S, count, none, r, P.step, P.l_step);
     Lb.nnt[ray] = m;
     Lb.cmax[ray] = count;

@@ -311,7 +311,9 @@ struct Taps {
     bool s0, s1;        // x0 (x1) is the row's first voxel
 };
 
-template <typename VT>
+// PAIRED: the brick's data box is at least two voxels wide in x (g.sx2); a
+// loop over samples picks the variant once, outside the loop.
+template <typename VT, bool PAIRED>
 __device__ inline Taps trilinear_fetch(const VT* data, const BrickGeo& g, const float p[3])
 {
 #pragma clang fp contract(off)
@@ -331,7 +333,7 @@ __device__ inline Taps trilinear_fetch(const VT* data, const BrickGeo& g, const 
     const uint32_t y0 = __umul24((uint32_t)i0[1], g.sy), y1 = __umul24((uint32_t)i1[1], g.sy);
     const uint32_t z0 = __umul24((uint32_t)i0[2], g.sz), z1 = __umul24((uint32_t)i1[2], g.sz);
     const uint32_t r00 = y0 + z0, r10 = y1 + z0, r01 = y0 + z1, r11 = y1 + z1;
-    if (g.sx2) {
+    if (PAIRED) {
         const int xb = i0[0] < g.xmax ? i0[0] : g.xmax;
         t.s0 = i0[0] == xb;
         t.s1 = i1[0] == xb;
@@ -368,7 +370,8 @@ __device__ inline float trilinear_blend(const Taps& t)
 template <typename VT>
 __device__ inline float trilinear(const VT* data, const BrickGeo& g, const float p[3])
 {
-    return trilinear_blend(trilinear_fetch<VT>(data, g, p));
+    return g.sx2 ? trilinear_blend(trilinear_fetch<VT, true>(data, g, p))
+                 : trilinear_blend(trilinear_fetch<VT, false>(data, g, p));
 }
 
 // Transfer-function cell and weight of scalar s.
