@@ -124,6 +124,43 @@ def test_generate_perspective_parity(V, orc, grid, dtype, res):
         _compare_lists(gc, gd, gn, ref["color"][r], ref["depth"][r], ref["count"][r], ref["margin"][r], f"brick {r}")
 
 
+@pytest.mark.parametrize("ratio,mode", [(0.6, 1), (1.5, 1), (0.75, 0)], ids=["short-bisect", "long-bisect", "short-fixed"])
+def test_generate_step_differs_from_ref_parity(V, orc, ratio, mode):
+    """Sampling distance different from the reference distance (Sec. 2.4's
+    length-adjusted opacity, R7): per-sample opacity 1 - (1 - a)^(step/ref),
+    supersegment lengths in units of ref, on a perspective view."""
+    import torch
+    cam = synth.orbit_camera(10_013, 71, 53)
+    vol, tf, tf_d, cam, bricks, dbr = _tiny_setup(V, mode, grid=(1, 2, 2), cam=cam)
+    step, ref_step = ratio / 64, 1 / 64
+    outs = V.generate(dbr, cam, tf_d, step, ref_step, mode, 0.05, 8, 10)
+    torch.cuda.synchronize()
+    assert V.device_status() == 0
+    ref = orc.generate(vol, bricks, cam, tf, step, ref_step, mode, 0.05, 8, 10)
+    for r in range(len(bricks)):
+        gc, gd, gn, gg = _gpu_regular(outs[r])
+        _compare_lists(gc, gd, gn, ref["color"][r], ref["depth"][r], ref["count"][r], ref["margin"][r],
+                       f"brick {r} step/ref {ratio}")
+
+
+@pytest.mark.parametrize("max_n,mode", [(1, 1), (1, 0), (64, 1)], ids=["N1-bisect", "N1-fixed", "N64-bisect"])
+def test_generate_extreme_n_parity(V, orc, max_n, mode):
+    """The smallest and largest supersegment budgets (N = 1: one supersegment
+    per list; N = VDI_MAX_N = 64)."""
+    import torch
+    cam = synth.orbit_camera(10_014, 45, 38)
+    vol, tf, tf_d, cam, bricks, dbr = _tiny_setup(V, mode, grid=(1, 1, 2), cam=cam)
+    outs = V.generate(dbr, cam, tf_d, 1 / 64, 1 / 64, mode, 0.05, max_n, 10)
+    torch.cuda.synchronize()
+    assert V.device_status() == 0
+    ref = orc.generate(vol, bricks, cam, tf, 1 / 64, 1 / 64, mode, 0.05, max_n, 10)
+    for r in range(len(bricks)):
+        gc, gd, gn, gg = _gpu_regular(outs[r])
+        assert gn.max() <= max_n
+        _compare_lists(gc, gd, gn, ref["color"][r], ref["depth"][r], ref["count"][r], ref["margin"][r],
+                       f"brick {r} N {max_n}")
+
+
 @pytest.mark.parametrize("mode", [0, 1], ids=["fixed", "bisect"])
 def test_generate_compact_matches_regular(V, mode):
     """Compact layout (Sec. 4): offsets are the exclusive prefix sum of the
