@@ -450,8 +450,6 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     if (lds > 160 * 1024) return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", seq_cap);
     P.k = k;
     P.npix = (uint32_t)((size_t)out->width * out->height);
-    P.width = out->width;
-    P.row_blocks = 1;
     P.cache_bound = 0;
     for (int r = 0; r < k; ++r)
         if (in[r].layout == VDI_LAYOUT_COMPACT) P.cache_bound = 1;

@@ -110,8 +110,6 @@ CompParams job_params(vdi_ctx* ctx, const vdi_job_t& j)
     }
     P.k = j.k;
     P.npix = (uint32_t)((size_t)j.out.width * j.out.height);
-    P.width = j.out.width;
-    P.row_blocks = 1;
     P.cache_bound = any_compact(j.in, j.k);
     P.inv_ref = 1.0f / j.out.ref_step;
     P.mode = j.tau.mode;

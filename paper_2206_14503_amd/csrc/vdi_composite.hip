@@ -363,18 +363,11 @@ __device__ void c_scan(R rd, int total, float inv_ref, const float* gam, int cap
 }  // namespace
 
 
-// Pixel of lane t in block `blk`; false outside the image.
+// Pixel of lane t in block `blk` (64 consecutive pixels); false past the image.
 __device__ inline bool block_pixel(const CompParams& P, uint32_t blk, int t, uint32_t& p)
 {
-    if (P.row_blocks) {
-        p = blk * 64u + (uint32_t)t;
-        return p < P.npix;
-    }
-    const uint32_t bx = ((uint32_t)P.width + 7u) >> 3;
-    const uint32_t x = (blk % bx) * 8u + (uint32_t)(t & 7), y = (blk / bx) * 8u + (uint32_t)(t >> 3);
-    const uint32_t h = P.npix / (uint32_t)P.width;
-    p = y * (uint32_t)P.width + x;
-    return x < (uint32_t)P.width && y < h;
+    p = blk * 64u + (uint32_t)t;
+    return p < P.npix;
 }
 
 // The input table of a job in LDS (thread t < k writes entry t).
@@ -794,7 +787,7 @@ __global__ __launch_bounds__(64) void batch_kernel(const CompParams* __restrict_
         const uint32_t tile = s_tile;
         __syncthreads();
         if (tile >= n_tiles) break;
-        const uint2 td = tiles[tile];          // x: job | blocks << 16, y: first 8x8 block
+        const uint2 td = tiles[tile];          // x: job | blocks << 16, y: first 64-pixel block
         const int job = (int)(td.x & 0xffffu);
         const uint32_t nblk = td.x >> 16;      // blocks in the tile
         const CompParams& P = jobs[job];

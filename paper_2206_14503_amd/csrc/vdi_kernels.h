@@ -111,8 +111,6 @@ struct CompParams {
     CompInput in[kMaxInputs];
     int k;
     uint32_t npix;
-    int width;                // image width (pixels are p = y * width + x)
-    int row_blocks;           // 1: a block is 64 consecutive pixels; 0: an 8x8 square
     int cache_bound;          // compact inputs: launch at the general merge's occupancy
     float inv_ref;
     int mode;
@@ -142,16 +140,9 @@ size_t cat_lds_bytes(int k);                      // depth-disjoint path
 // grid_general: blocks of the queue-driven general merge (with staging, at
 // most the number of slabs)
 void launch_composite(const CompParams& P, int grid_general, hipStream_t s);
-// 64-pixel blocks of the image
-__host__ __device__ inline uint32_t composite_blocks(const CompParams& P)
-{
-    if (P.row_blocks) return (P.npix + 63u) / 64u;
-    return ((uint32_t)(P.width + 7) / 8u) * ((P.npix / (uint32_t)P.width + 7u) / 8u);
-}
+// Blocks of 64 consecutive pixels (one per wavefront) covering the image.
+__host__ __device__ inline uint32_t composite_blocks(const CompParams& P) { return (P.npix + 63u) / 64u; }
 
-// Pixels are processed in blocks of 64, one per wavefront: 8x8 squares
-// numbered row-major over the image (blocks_x = ceil(width / 8)), or, with
-// row_blocks, runs of 64 consecutive pixels.
 // Persistent batched compositing: tiles[i] = {job | blocks << 16, first block}
 // for the depth-disjoint path (jobs with k <= kCatMaxInputs), then the general
 // merge over every job's queue (all pixels of jobs with larger k).

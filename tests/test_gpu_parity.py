@@ -302,13 +302,14 @@ def test_composite_interleaved_stress_parity(V, orc):
     _compare_lists(gc, gd, gn, oref["color"], oref["depth"], oref["count"], oref["margin"], "stress")
 
 
-@pytest.mark.parametrize("n,out_n", [(6, 10), (2, 48)], ids=["bisect", "passthrough"])
-def test_composite_many_inputs_ragged_parity(V, orc, n, out_n):
-    """k = 24 interleaved inputs (above the depth-disjoint path's 16), ragged
-    list lengths 0..n and a ragged last pixel block (300 pixels): the general
-    merge over every pixel."""
+@pytest.mark.parametrize("k,n,out_n", [(24, 6, 10), (24, 2, 48), (32, 4, 12)],
+                         ids=["k24-bisect", "k24-passthrough", "k32-bisect"])
+def test_composite_many_inputs_ragged_parity(V, orc, k, n, out_n):
+    """k = 24 and k = VDI_MAX_INPUTS = 32 interleaved inputs (above the
+    depth-disjoint path's 16), ragged list lengths 0..n and a ragged last
+    pixel block (300 pixels): the general merge over every pixel."""
     import torch
-    k, W, H = 24, 20, 15
+    W, H = 20, 15
     P = W * H
     col, dep, cnt = synth.dense_interleaved_lists(k, n, P, seed=7)
     rng = np.random.default_rng(7)
@@ -327,7 +328,7 @@ def test_composite_many_inputs_ragged_parity(V, orc, n, out_n):
     oref = orc.composite([c[r] for r in range(k)], [d[r] for r in range(k)], [m[r] for r in range(k)], 0.01, 1, 0.0,
                          out_n, 10)
     gc, gd, gn, gg = _gpu_regular(out)
-    _compare_lists(gc, gd, gn, oref["color"], oref["depth"], oref["count"], oref["margin"], f"k24 N{out_n}")
+    _compare_lists(gc, gd, gn, oref["color"], oref["depth"], oref["count"], oref["margin"], f"k{k} N{out_n}")
 
 
 @pytest.mark.parametrize("out_n", [4, 30], ids=["bisect", "passthrough"])
