@@ -621,9 +621,9 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
 // share one sampling scan; the in-band candidate with the largest count is
 // kept.  Otherwise, if two candidates adjacent in threshold order straddle
 // the band (count above N at the smaller, below the band at the larger), the
-// ray is queued for round two inside that bracket (the straddling pair
+// ray goes on the list for round two inside that bracket (the straddling pair
 // nearest the regressed value; ties: the smaller thresholds); else it is
-// queued for the plain bisection.
+// put on the list for the plain bisection.
 template <typename VT>
 __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
@@ -719,10 +719,10 @@ __global__ __launch_bounds__(256) void shortcut_kernel(GenParams P, GenBricks B,
     }
 }
 
-// Round two for the queued rays of each brick: five thresholds evenly inside
+// Round two for the listed rays of each brick: five thresholds evenly inside
 // the bracket (log2 y_a + (y_b - y_a) t / 6, t = 1..5) in one scan; the in-band
 // one with the largest count is kept (ties: smaller t), else the ray is
-// queued for the plain bisection.
+// put on the list for the plain bisection.
 template <typename VT>
 __global__ __launch_bounds__(256) void refine_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
@@ -762,7 +762,7 @@ __global__ __launch_bounds__(256) void refine_kernel(GenParams P, GenBricks B, L
     }
 }
 
-// Plain bisection for the queued rays of each brick.
+// Plain bisection for the listed rays of each brick.
 template <typename VT>
 __global__ __launch_bounds__(256) void fallback_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
@@ -832,8 +832,8 @@ static void launch_learned_t(int phase, const GenParams& P, const GenBricks& B, 
         hipLaunchKernelGGL(features_kernel<VT>, grid, dim3(256), tf_lds(P), s, P, B, L);
         return;
     }
-    // queue-driven: grid-stride over each brick's queue, enough blocks to
-    // fill the device whatever the queue length turns out to be
+    // list-driven: grid-stride over each brick's span of the list, enough
+    // blocks to fill the device whatever the list length turns out to be
     size_t npix = (size_t)P.cam.width * P.cam.height;
     unsigned bx = (unsigned)std::min<size_t>((npix + 255) / 256, (size_t)L.blocks_per_brick);
     dim3 g2(bx, 1, nb);

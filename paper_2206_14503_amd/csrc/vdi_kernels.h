@@ -44,9 +44,8 @@ struct GenBricks {
     int total;           // bricks of the call
 };
 
-// Buffers of the learned-threshold path (indices: brick * npix + pixel).
 // Outcome of a brick-ray on the learned path (indices into LearnBufs::stats
-// up to LEARN_REFINED; LEARN_REFINE marks a ray queued for round two).
+// up to LEARN_REFINED; LEARN_REFINE marks a ray listed for round two).
 enum { LEARN_KEPT = 0, LEARN_SHORTCUT = 1, LEARN_FALLBACK = 2, LEARN_EMPTY = 3, LEARN_REFINED = 4, LEARN_REFINE = 5 };
 constexpr int kLearnStats = 5;
 
@@ -58,6 +57,7 @@ constexpr int kLearnStats = 5;
 // places each ray at its block's offset plus its rank in the block.
 enum { Q_SERVED = 0, Q_SHORT = 1, Q_REFINE = 2, Q_FALLBACK = 3, kQueues = 4 };
 
+// Buffers of the learned-threshold path (per-ray arrays indexed brick * npix + pixel).
 struct LearnBufs {
     uint16_t* hist;      // [nb][npix][64] bf16 features; with hist_list: per brick, compacted
     int* nnt;            // [nb][npix] non-transparent samples
