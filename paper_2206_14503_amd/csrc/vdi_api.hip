@@ -231,10 +231,8 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
     }
     if ((st = phase(1)) != VDI_OK) return st;   // round one
     if ((st = phase(4)) != VDI_OK) return st;   // all-feasible lists
-    if ((st = order(Q_REFINE)) != VDI_OK) return st;
-    if ((st = phase(2)) != VDI_OK) return st;   // round two
-    if ((st = order(Q_FALLBACK)) != VDI_OK) return st;
-    return phase(3);                            // plain bisection
+    if ((st = order(Q_TAIL)) != VDI_OK) return st;
+    return phase(2);                            // round two and the plain bisection
 }
 
 }  // namespace vdi

@@ -676,10 +676,11 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
             }
             kind = pick >= 0 ? LEARN_REFINE : LEARN_FALLBACK;
         }
-        if (kind == LEARN_FALLBACK) put_on_list(Lb, Q_FALLBACK, brick, B.total, x, y, gx);
-        if (kind == LEARN_REFINE) {
-            put_on_list(Lb, Q_REFINE, brick, B.total, x, y, gx);
-            Lb.rf_y[ray] = bracket;
+        if (kind != LEARN_KEPT) {
+            // the tail list: round two inside the bracket, or (no bracket: NaN)
+            // the plain bisection
+            put_on_list(Lb, Q_TAIL, brick, B.total, x, y, gx);
+            Lb.rf_y[ray] = kind == LEARN_REFINE ? bracket : make_float2(__builtin_nanf(""), __builtin_nanf(""));
         }
         wave_append(&Lb.stats[LEARN_KEPT], kind == LEARN_KEPT);
         wave_append(&Lb.stats[LEARN_FALLBACK], kind == LEARN_FALLBACK);
@@ -719,12 +720,14 @@ __global__ __launch_bounds__(256) void shortcut_kernel(GenParams P, GenBricks B,
     }
 }
 
-// Round two for the listed rays of each brick: five thresholds evenly inside
-// the bracket (log2 y_a + (y_b - y_a) t / 6, t = 1..5) in one scan; the in-band
-// one with the largest count is kept (ties: smaller t), else the ray is
-// put on the list for the plain bisection.
+// The rays round one did not keep, from one list: round two for those with a
+// straddling bracket (five thresholds evenly inside it, log2 y_a + (y_b - y_a)
+// t / 6 for t = 1..5, in one scan; the in-band one with the largest count is
+// kept, ties: smaller t), then, in the same thread, the plain bisection for
+// every ray still without a threshold, and the write.  Rays of both kinds
+// share the launch, so the bisections of round-one rejects overlap round two.
 template <typename VT>
-__global__ __launch_bounds__(256) void refine_kernel(GenParams P, GenBricks B, LearnBufs Lb)
+__global__ __launch_bounds__(256) void tail_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
     extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
     for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
@@ -732,62 +735,43 @@ __global__ __launch_bounds__(256) void refine_kernel(GenParams P, GenBricks B, L
     const GenBrick& br = B.b[blockIdx.z];
     const int brick = B.first + blockIdx.z;
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
-    const int gx = (P.cam.width + 15) / 16;
-    const ListSpan ls = list_span(Lb, Q_REFINE, brick, B.total, npix);
+    const ListSpan ls = list_span(Lb, Q_TAIL, brick, B.total, npix);
     const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
     const VT* data = (const VT*)br.data;
     for (uint32_t idx = ls.begin + blockIdx.x * blockDim.x + threadIdx.x; idx < ls.end;
          idx += gridDim.x * blockDim.x) {
         const uint32_t pix = (uint32_t)ls.list[idx];
-        const float2 yab = Lb.rf_y[(size_t)brick * npix + pix];
+        const size_t ray = (size_t)brick * npix + pix;
+        const float2 yab = Lb.rf_y[ray];
         const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
         const RayRun q = ray_run(P, br, x, y);
-        float g5[5];
-        int c5[5];
+        const bool round2 = yab.x < yab.y;   // false for the NaN of round-one rejects
+        float gm = 0.0f;
+        int best = -1;
+        if (round2) {
+            float g5[5];
+            int c5[5];
 #pragma unroll
-        for (int t = 0; t < 5; ++t) g5[t] = exp2f(yab.x + (yab.y - yab.x) * (float)(t + 1) * (1.0f / 6.0f));
-        gen_scan<VT, 5>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, g5, P.max_n, c5, nullptr);
-        const int lo = band_lo(P.max_n, Lb.cmax[(size_t)brick * npix + pix], Lb.tol);
-        const int best = pick_in_band<5>(c5, P.max_n, lo);
+            for (int t = 0; t < 5; ++t) g5[t] = exp2f(yab.x + (yab.y - yab.x) * (float)(t + 1) * (1.0f / 6.0f));
+            gen_scan<VT, 5>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, g5, P.max_n, c5,
+                            nullptr);
+            best = pick_in_band<5>(c5, P.max_n, band_lo(P.max_n, Lb.cmax[ray], Lb.tol));
+#pragma unroll
+            for (int t = 0; t < 5; ++t) gm = t == best ? g5[t] : gm;
+        }
         wave_append(&Lb.stats[LEARN_REFINED], best >= 0);
-        wave_append(&Lb.stats[LEARN_FALLBACK], best < 0);
-        if (best < 0) {
-            put_on_list(Lb, Q_FALLBACK, brick, B.total, x, y, gx);
-            continue;
-        }
-        GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
-        const int c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries,
-                                                g5[best], 0, 1 << 30, o, nullptr);
-        finish_list(br, pix, npix, P.max_n, c, g5[best]);
-    }
-}
-
-// Plain bisection for the listed rays of each brick.
-template <typename VT>
-__global__ __launch_bounds__(256) void fallback_kernel(GenParams P, GenBricks B, LearnBufs Lb)
-{
-    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
-    for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
-    __syncthreads();
-    const GenBrick& br = B.b[blockIdx.z];
-    const int brick = B.first + blockIdx.z;
-    const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
-    const ListSpan ls = list_span(Lb, Q_FALLBACK, brick, B.total, npix);
-    const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
-    const VT* data = (const VT*)br.data;
-    for (uint32_t idx = ls.begin + blockIdx.x * blockDim.x + threadIdx.x; idx < ls.end;
-         idx += gridDim.x * blockDim.x) {
-        const uint32_t pix = (uint32_t)ls.list[idx];
-        const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
-        const RayRun q = ray_run(P, br, x, y);
-        float gm = ldexpf(P.gmax, -P.iters);
+        wave_append(&Lb.stats[LEARN_FALLBACK], round2 & (best < 0));   // round one counted its own
         int c = 0;
-        GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
-        if (q.k1 > q.k0) {
-            gen_search<VT>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, P, gm, c, false);
-            c = gen_pass<VT, true>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, gm, 0, 1 << 30,
-                                   o, nullptr);
+        if (best < 0) {
+            gm = ldexpf(P.gmax, -P.iters);
+            if (q.k1 > q.k0)
+                gen_search<VT>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, P, gm, c, false);
         }
+        GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
+        c = 0;
+        if (q.k1 > q.k0)
+            c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, gm, 0,
+                                          1 << 30, o, nullptr);
         finish_list(br, pix, npix, P.max_n, c < P.max_n ? c : P.max_n, gm);
     }
 }
@@ -838,8 +822,7 @@ static void launch_learned_t(int phase, const GenParams& P, const GenBricks& B, 
     unsigned bx = (unsigned)std::min<size_t>((npix + 255) / 256, (size_t)L.blocks_per_brick);
     dim3 g2(bx, 1, nb);
     if (phase == 1) hipLaunchKernelGGL(learned_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
-    if (phase == 2) hipLaunchKernelGGL(refine_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
-    if (phase == 3) hipLaunchKernelGGL(fallback_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
+    if (phase == 2) hipLaunchKernelGGL(tail_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
     if (phase == 4) hipLaunchKernelGGL(shortcut_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
 }
 

@@ -55,7 +55,7 @@ constexpr int kLearnStats = 5;
 // the list-driven kernels sample neighbouring voxels: per 256-slot block the
 // producers count their rays, the counts are scanned, and a compaction kernel
 // places each ray at its block's offset plus its rank in the block.
-enum { Q_SERVED = 0, Q_SHORT = 1, Q_REFINE = 2, Q_FALLBACK = 3, kQueues = 4 };
+enum { Q_SERVED = 0, Q_SHORT = 1, Q_TAIL = 2, kQueues = 3 };
 
 // Buffers of the learned-threshold path (per-ray arrays indexed brick * npix + pixel).
 struct LearnBufs {
@@ -63,7 +63,7 @@ struct LearnBufs {
     int* nnt;            // [nb][npix] non-transparent samples
     int* cmax;           // [nb][npix] count at the smallest threshold (saturates at N+1)
     const float* y;      // [nb][npix] log2(gamma) from the regressor (or the caller)
-    float2* rf_y;        // [nb][npix] log2 bracket of rays sent to round two
+    float2* rf_y;        // [nb][npix] log2 bracket of rays sent to round two (NaN: bisection)
     int* hist_list;      // optional [nb][npix]: pixel of each compacted histogram row
     int* hist_count;     // [nb]
     uint8_t* kind;       // [nb][slots] 1 + the list a slot's ray is on (0: none)
@@ -80,7 +80,8 @@ struct LearnBufs {
 // kind: 0 = search + regular write, 1 = search only, 2 = compact write
 void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B, int nb, hipStream_t s);
 // phase 0: features (finishes empty lists, lists the others), 1: learned
-// round one, 2: round two, 3: fallback bisection, 4: all-feasible lists
+// round one, 2: the tail (round two, then the plain bisection), 4: the
+// all-feasible list
 void launch_learned(int phase, int dtype, const GenParams& P, const GenBricks& B, int nb, const LearnBufs& L,
                     hipStream_t s);
 // Places the rays of list q (kind == 1 + q) at their offsets, in slot order.
