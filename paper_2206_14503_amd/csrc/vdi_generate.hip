@@ -197,9 +197,12 @@ __device__ int gen_pass(const VT* data, const BrickGeo& g, const Ray& r, float s
 // computed once and fed to every state.  A state freezes once its count
 // exceeds `limit`; the scan ends when all are frozen.  n_opaque counts the
 // non-transparent samples seen (complete only if the scan ran to the end).
+// kspan (optional) receives the first non-transparent sample seen, one past
+// the last one, and whether the scan ran to k1 (1) or stopped early (0).
 template <typename VT, int NC>
 __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0, int k1,
-                         const float4* tf, int entries, const float* gam, int limit, int* counts, int* n_opaque_out)
+                         const float4* tf, int entries, const float* gam, int limit, int* counts, int* n_opaque_out,
+                         int* kspan = nullptr)
 {
     GenSeg S[NC];
     int cnt[NC];
@@ -213,10 +216,16 @@ __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float 
     GenOut none{nullptr, nullptr, 0, 0, 0};
     const bool unit = (l_step == 1.0f);
     int n_opaque = 0;
+    int kf = k1, ke = k0, kdone = k0;
     // many states: two stencil slots, to keep the states in registers
     for_samples<VT, (NC >= 6 ? 2 : 3)>(data, g, r, step, k0, k1, [&](int k, float v) {
         const GenSample q = gen_prep(tf_lookup(tf, entries, v), l_step, unit);
         n_opaque += q.transparent ? 0 : 1;
+        if (kspan) {
+            kf = q.transparent ? kf : min(kf, k);
+            ke = q.transparent ? ke : k + 1;
+            kdone = k + 1;
+        }
         // a frozen state (count above limit) keeps stepping: its count only
         // grows, so its outcome stays decided
         bool live = false;
@@ -233,6 +242,11 @@ __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float 
         counts[j] = cnt[j];
     }
     if (n_opaque_out) *n_opaque_out = n_opaque;
+    if (kspan) {
+        kspan[0] = kf;
+        kspan[1] = ke;
+        kspan[2] = kdone == k1 ? 1 : 0;
+    }
 }
 
 // Levels of the bisection the first scan speculates on.
@@ -245,8 +259,8 @@ constexpr int kGeoLevels = 6;
 // per scan (the midpoint m and both next-level midpoints).  Both reproduce
 // the sequential decisions exactly.
 template <typename VT>
-__device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0,
-                           int k1, const float4* tf, int entries, const GenParams& P, float& gamma_out,
+__device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int& k0,
+                           int& k1, const float4* tf, int entries, const GenParams& P, float& gamma_out,
                            int& count_out, bool need_count)
 {
     GenOut none{nullptr, nullptr, 0, 0, 0};
@@ -279,7 +293,16 @@ __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, co
 #pragma unroll
         for (int l = 0; l < kGeoLevels; ++l) gg[l] = ldexpf(P.gmax, -(l + 1));
         int n_opaque = 0;
-        gen_scan<VT, kGeoLevels>(data, g, r, step, l_step, k0, k1, tf, entries, gg, P.max_n, cg, &n_opaque);
+        int ks[3];
+        gen_scan<VT, kGeoLevels>(data, g, r, step, l_step, k0, k1, tf, entries, gg, P.max_n, cg, &n_opaque, ks);
+        // later passes (and the caller's write) cover [first non-transparent
+        // sample, one past the last): before it every state stays closed and
+        // untouched, after it neither the count nor the stored lists change
+        // (a trailing close emits the supersegment the end would emit)
+        if (n_opaque > 0) {
+            k0 = ks[0];
+            if (ks[2]) k1 = ks[1];
+        }
         if (n_opaque <= P.max_n) {
             // every supersegment starts at a non-transparent sample, so a run
             // with at most N of them is feasible at every threshold: all
@@ -761,17 +784,16 @@ __global__ __launch_bounds__(256) void tail_kernel(GenParams P, GenBricks B, Lea
         }
         wave_append(&Lb.stats[LEARN_REFINED], best >= 0);
         wave_append(&Lb.stats[LEARN_FALLBACK], round2 & (best < 0));   // round one counted its own
-        int c = 0;
+        int c = 0, k0 = q.k0, k1 = q.k1;
         if (best < 0) {
             gm = ldexpf(P.gmax, -P.iters);
-            if (q.k1 > q.k0)
-                gen_search<VT>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, P, gm, c, false);
+            if (k1 > k0) gen_search<VT>(data, g, q.r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, P, gm, c, false);
         }
         GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
         c = 0;
-        if (q.k1 > q.k0)
-            c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, gm, 0,
-                                          1 << 30, o, nullptr);
+        if (k1 > k0)
+            c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, 0, 1 << 30, o,
+                                          nullptr);
         finish_list(br, pix, npix, P.max_n, c < P.max_n ? c : P.max_n, gm);
     }
 }
