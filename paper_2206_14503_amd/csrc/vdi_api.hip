@@ -146,7 +146,7 @@ static void fill_i32(int* p, int v, size_t n, hipStream_t s)
 // Scratch layout of the learned path for nb bricks of npix pixels
 // (nblk 256-slot blocks per brick).
 struct LearnScratch {
-    size_t hist, nnt, cmax, y, ry, hlist, hcnt, kind, qcnt, qoff, qlist, scan, total;
+    size_t hist, nnt, cmax, y, ry, span, hlist, hcnt, kind, qcnt, qoff, qlist, scan, total;
 };
 static LearnScratch learn_layout(size_t rays, int nb, size_t nblk)
 {
@@ -159,6 +159,7 @@ static LearnScratch learn_layout(size_t rays, int nb, size_t nblk)
     L.cmax = take(rays * sizeof(int));
     L.y = take(rays * sizeof(float));
     L.ry = take(rays * sizeof(float2));
+    L.span = take(rays * sizeof(int2));
     L.hlist = take(rays * sizeof(int));
     L.hcnt = take((size_t)nb * sizeof(int));
     L.kind = take(nq * 256);
@@ -191,6 +192,7 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
     Lb.cmax = (int*)(base + Ls.cmax);
     Lb.y = (const float*)(base + Ls.y);
     Lb.rf_y = (float2*)(base + Ls.ry);
+    Lb.span = (int2*)(base + Ls.span);
     Lb.hist_list = (int*)(base + Ls.hlist);
     Lb.hist_count = (int*)(base + Ls.hcnt);
     Lb.kind = (uint8_t*)(base + Ls.kind);

@@ -499,13 +499,17 @@ struct RayRun {
     int k0, k1;
 };
 
-__device__ inline RayRun ray_run(const GenParams& P, const GenBrick& br, int x, int y)
+// A listed ray of the learned path: its samples from the first to the last
+// non-transparent one, as the feature scan found them (before that span every
+// segmenter state stays closed and untouched, after it neither a count nor a
+// stored list changes).
+__device__ inline RayRun listed_ray(const GenParams& P, const LearnBufs& Lb, size_t ray, int x, int y)
 {
     RayRun q;
     q.r = make_ray(P.cam, x, y);
-    int ns = ray_samples(q.r, P.step);
-    q.k0 = q.k1 = 0;
-    if (ns > 0) owned_run(q.r, P.step, ns, P.n, br.lo, br.hi, q.k0, q.k1);
+    const int2 sp = Lb.span[ray];
+    q.k0 = sp.x;
+    q.k1 = sp.y;
     return q;
 }
 
@@ -589,9 +593,12 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
     GenSeg S;
     gen_seg_init(S);
     int count = 0, m = 0;
+    int kf = k1, ke = k0;
     for_samples<VT>(data, g, r, P.step, k0, k1, [&](int k, float v) {
         const float4 cs = tf_lookup(tf_s, P.tf_entries, v);
         const float a32 = cs.w;   // the transfer function's opacity, as in the histogram's definition
+        kf = a32 > 0.0f ? min(kf, k) : kf;
+        ke = a32 > 0.0f ? k + 1 : ke;
         if (a32 > 0.0f) {
             int j = (int)ceilf(64.0f * a32) - 1;
             j = j > 63 ? 63 : (j < 0 ? 0 : j);
@@ -626,6 +633,7 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
         wave_append(&Lb.stats[LEARN_EMPTY], empty);
         const int pos = wave_append(&Lb.hist_count[brick], served);
         if (empty) finish_list(br, pix, npix, P.max_n, 0, gmin);
+        else Lb.span[ray] = make_int2(kf, ke);
         if (!served) return;
         Lb.hist_list[(size_t)brick * npix + pos] = (int)pix;
         row = (size_t)brick * npix + (size_t)pos;
@@ -667,7 +675,7 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
         const uint32_t pix = (uint32_t)ls.list[idx];
         const size_t ray = (size_t)brick * npix + pix;
         const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
-        const RayRun q = ray_run(P, br, x, y);
+        const RayRun q = listed_ray(P, Lb, ray, x, y);
         const float yv = Lb.y[ray];
         const float dl[5] = { 0.0f, -0.25f, 0.25f, -0.5f, 0.5f };
         float y5[5], g5[5];
@@ -734,7 +742,7 @@ __global__ __launch_bounds__(256) void shortcut_kernel(GenParams P, GenBricks B,
          idx += gridDim.x * blockDim.x) {
         const uint32_t pix = (uint32_t)ls.list[idx];
         const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
-        const RayRun q = ray_run(P, br, x, y);
+        const RayRun q = listed_ray(P, Lb, (size_t)brick * npix + pix, x, y);
         GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
         const int c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, gmin,
                                                 0, 1 << 30, o, nullptr);
@@ -767,7 +775,7 @@ __global__ __launch_bounds__(256) void tail_kernel(GenParams P, GenBricks B, Lea
         const size_t ray = (size_t)brick * npix + pix;
         const float2 yab = Lb.rf_y[ray];
         const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
-        const RayRun q = ray_run(P, br, x, y);
+        const RayRun q = listed_ray(P, Lb, ray, x, y);
         const bool round2 = yab.x < yab.y;   // false for the NaN of round-one rejects
         float gm = 0.0f;
         int best = -1;

@@ -64,6 +64,7 @@ struct LearnBufs {
     int* cmax;           // [nb][npix] count at the smallest threshold (saturates at N+1)
     const float* y;      // [nb][npix] log2(gamma) from the regressor (or the caller)
     float2* rf_y;        // [nb][npix] log2 bracket of rays sent to round two (NaN: bisection)
+    int2* span;          // [nb][npix] first non-transparent sample, one past the last (listed rays)
     int* hist_list;      // optional [nb][npix]: pixel of each compacted histogram row
     int* hist_count;     // [nb]
     uint8_t* kind;       // [nb][slots] 1 + the list a slot's ray is on (0: none)
