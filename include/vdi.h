@@ -41,7 +41,7 @@ extern "C" {
 typedef enum {
     VDI_OK = 0,
     VDI_E_INVALID = -1,     /* bad argument or shape */
-    VDI_E_UNSUPPORTED = -2, /* valid but not supported by this build (limits below) */
+    VDI_E_UNSUPPORTED = -2, /* valid but beyond this library's limits (below) */
     VDI_E_HIP = -3,         /* a HIP runtime call failed */
     VDI_E_INPUT = -4,       /* input data violates a precondition (checked on the device; see vdi_ctx_device_status) */
     VDI_E_CAPACITY = -5     /* a compact output does not fit its capacity */
@@ -51,7 +51,7 @@ typedef enum { VDI_LAYOUT_REGULAR = 0, VDI_LAYOUT_COMPACT = 1 } vdi_layout;
 typedef enum { VDI_TAU_FIXED = 0, VDI_TAU_BISECT = 1, VDI_TAU_LEARNED = 2, VDI_TAU_BISECT_SEQ = 3 } vdi_tau_mode;
 typedef enum { VDI_F32 = 0, VDI_F16 = 1 } vdi_dtype;
 
-/* Limits of this build. */
+/* Limits of this library. */
 #define VDI_MAX_INPUTS 32   /* k in vdi_composite */
 #define VDI_MAX_N 64        /* N, supersegments per list */
 #define VDI_MAX_TF 1024     /* transfer-function entries */
