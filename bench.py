@@ -348,14 +348,12 @@ def leg_batched(args, result):
     for (wd, ht, k, n) in specs:
         out = vdi.VDI.empty(wd, ht, n, step_len, vdi.REGULAR)
         jobs.append(vdi.Job(pool[(wd, ht, n)][:k], out, mode=vdi.BISECT, iters=10))
-    outdir = os.path.join(ROOT, "gpurun_out")
-    cache = os.path.join(outdir, "autotune_tiles.txt") if os.path.isdir(outdir) else None
-    t_tune = None
-    if cache:
-        t1 = time.time()
-        vdi.autotune(jobs, cache)
-        t_tune = time.time() - t1
-        log(f"[bench] batched: autotuned tile sizes in {t_tune:.1f}s -> {open(cache).read().strip()}")
+    import tempfile
+    cache = os.path.join(tempfile.gettempdir(), f"vdi_autotune_tiles_{os.getpid()}.txt")
+    t1 = time.time()
+    vdi.autotune(jobs, cache)
+    t_tune = time.time() - t1
+    log(f"[bench] batched: autotuned tile sizes in {t_tune:.1f}s -> {open(cache).read().strip()}")
     b = vdi.Batch(jobs, autotune_cache=cache)
     info = b.info()
     s = torch.cuda.Stream()
