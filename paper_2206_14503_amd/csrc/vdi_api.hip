@@ -473,13 +473,22 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     size_t grid = (size_t)ctx->num_cus * per_cu;
     grid = std::min<size_t>(grid, composite_blocks(P));
     grid = std::max<size_t>(1, std::min<size_t>(grid, ((size_t)1 << 30) / (slab * 24)));
+    // then the block order of the depth-disjoint pass (order and bucket per
+    // block)
     const size_t qbytes = (((size_t)P.npix + 64) * sizeof(int) + 255) & ~(size_t)255;
-    if ((st = ensure_scratch(ctx, qbytes + grid * slab * 24)) != VDI_OK) return st;
+    const size_t nblk = composite_blocks(P);
+    const size_t obytes = (2 * nblk * sizeof(uint32_t) + 255) & ~(size_t)255;
+    if ((st = ensure_scratch(ctx, qbytes + obytes + grid * slab * 24)) != VDI_OK) return st;
     char* base = (char*)ctx->scratch;
     P.q_count = (int*)base;
     P.q_list = (int*)base + 64;
-    P.stage_c = (float4*)(base + qbytes);
-    P.stage_d = (float2*)(base + qbytes + grid * slab * sizeof(float4));
+    // slot-major inputs only: a block of compact inputs reads one stretch of
+    // each input, next to its neighbours' stretches, and loses that locality
+    // out of image order (measured slower)
+    P.order = P.cache_bound ? nullptr : (uint32_t*)(base + qbytes);
+    P.bucket = (uint32_t*)(base + qbytes) + nblk;
+    P.stage_c = (float4*)(base + qbytes + obytes);
+    P.stage_d = (float2*)(base + qbytes + obytes + grid * slab * sizeof(float4));
     launch_composite(P, (int)grid, (hipStream_t)stream);
     return launched();
 }

@@ -742,7 +742,8 @@ __global__ __launch_bounds__(64) void composite_cat_kernel(CompParams P)
     setup_inputs(P, lds_raw, t);
     __syncthreads();
     uint32_t p;
-    if (!block_pixel(P, blockIdx.x, t, p)) return;
+    const uint32_t blk = P.order ? P.order[blockIdx.x] : blockIdx.x;
+    if (!block_pixel(P, blk, t, p)) return;
     const bool done = composite_pixel_cat(P, lds_raw, t, p);
     const int pos = wave_append(P.q_count, !done);
     if (!done) P.q_list[pos] = (int)p;
@@ -870,6 +871,55 @@ size_t composite_lds_bytes(int k, int seq_cap, bool staged)
 
 size_t cat_lds_bytes(int k) { return sizeof(InLds) * kMaxInputs + (size_t)kWave * 8 * (size_t)k; }
 
+// ---------------------------------------------------------------- block order
+//
+// A wavefront lasts as long as its longest merged list, and the blocks of
+// long lists cluster in the image.  Dispatched in image order, the last of
+// them start late and run on a nearly empty device; dispatched longest
+// first, the short ones fill in behind them.  Blocks are bucketed by their
+// longest merged list (bucket 0: lists that pass through, then steps of 8
+// elements) and the order lists the buckets from the longest down.
+
+__device__ inline uint32_t order_bucket(const CompParams& P, uint32_t blk)
+{
+    const uint32_t p = blk * 64u + (threadIdx.x & 63u);
+    int tot = 0;
+    if (p < P.npix)
+        for (int r = 0; r < P.k; ++r) tot += max(0, min(P.in[r].count[p], P.in[r].max_n));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tot = max(tot, __shfl_xor(tot, o));
+    const int b = tot <= P.out_n ? 0 : 1 + ((tot - P.out_n - 1) >> 3);
+    return (uint32_t)min(b, kOrderBuckets - 1);
+}
+
+__global__ __launch_bounds__(64) void order_count_kernel(CompParams P)
+{
+    const uint32_t b = order_bucket(P, blockIdx.x);
+    if (threadIdx.x == 0) P.bucket[blockIdx.x] = b;
+}
+
+// One block: a counting sort of the blocks by bucket, longest bucket first
+// (LDS counters; the order within a bucket is arbitrary).
+__global__ __launch_bounds__(1024) void order_sort_kernel(CompParams P, uint32_t blocks)
+{
+    __shared__ uint32_t cnt[kOrderBuckets];
+    const uint32_t t = threadIdx.x;
+    if (t < kOrderBuckets) cnt[t] = 0u;
+    __syncthreads();
+    for (uint32_t i = t; i < blocks; i += blockDim.x) atomicAdd(&cnt[P.bucket[i]], 1u);
+    __syncthreads();
+    if (t == 0) {
+        uint32_t o = 0;
+        for (int b = kOrderBuckets - 1; b >= 0; --b) {
+            const uint32_t c = cnt[b];
+            cnt[b] = o;
+            o += c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < blocks; i += blockDim.x) P.order[atomicAdd(&cnt[P.bucket[i]], 1u)] = i;
+}
+
 void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
 {
     const size_t lds = composite_lds_bytes(P.k, P.seq_cap, P.stage_c != nullptr);
@@ -887,6 +937,10 @@ void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
     // whole lines per step and prefer full occupancy.
     const size_t lds_cat = P.cache_bound ? std::max(composite_lds_bytes(P.k, P.seq_cap), cat_lds_bytes(P.k))
                                          : cat_lds_bytes(P.k);
+    if (P.order) {
+        hipLaunchKernelGGL(order_count_kernel, dim3(blocks), dim3(kWave), 0, s, P);
+        hipLaunchKernelGGL(order_sort_kernel, dim3(1), dim3(1024), 0, s, P, blocks);
+    }
     hipLaunchKernelGGL(composite_cat_kernel, dim3(blocks), dim3(kWave), lds_cat, s, P);
     hipLaunchKernelGGL(composite_queue_kernel, dim3(g2), dim3(kWave), lds, s, P);
 }

@@ -132,7 +132,12 @@ struct CompParams {
     // entries where lane t's merged element i sits at [i * 64 + t]
     float4* stage_c;
     float2* stage_d;
+    // optional order of the 64-pixel blocks for the depth-disjoint pass
+    // (longest merged list first), and its work space (a bucket per block)
+    uint32_t* order;
+    uint32_t* bucket;
 };
+constexpr int kOrderBuckets = 64;
 
 // Inputs up to which the depth-disjoint path runs (4-bit list ids).
 constexpr int kCatMaxInputs = 16;
