@@ -94,33 +94,41 @@ __device__ inline void c_close(CSeg& S, const COut& o, float inv_ref)
     S.open = false;
 }
 
-// Eq. 1 test: gamma < |C a_S / A - e| with a_S = 1 - 2^(log2(T) / L) the
-// open supersegment's per-step opacity over L = (b - f) / ref, evaluated as
-// gamma^2 A^2 < |C a_S - e A|^2 (A > 0).
-__device__ inline bool c_exceeds(const CSeg& S, float b, float inv_ref, float g2, float e0, float e1, float e2)
+// Per-step opacity a_S = 1 - 2^(log2(T) / L) of the open supersegment
+// extended to depth b, over L = (b - f) / ref.
+__device__ inline float seg_alpha(const CSeg& S, float b, float inv_ref)
 {
-    float L = (b - S.f) * inv_ref;
-    float aS = 1.0f - hw_exp2(S.lT * hw_rcp(L));
+    return 1.0f - hw_exp2(S.lT * hw_rcp((b - S.f) * inv_ref));
+}
+
+// Eq. 1 test: gamma < |C a_S / A - e|, evaluated as
+// gamma^2 A^2 < |C a_S - e A|^2 (A > 0).
+__device__ inline bool c_exceeds(const CSeg& S, float aS, float g2, float e0, float e1, float e2)
+{
     float d0 = S.c0 * aS - e0 * S.A, d1 = S.c1 * aS - e1 * S.A, d2 = S.c2 * aS - e2 * S.A;
     return g2 * (S.A * S.A) < d0 * d0 + d1 * d1 + d2 * d2;
 }
 
 // One element through the segmenter: the empty space before it (a
-// transparent stretch, Alg. S1), then the element itself.  The state update
-// is written as selects; a closed state's fields are don't-cares.
+// transparent stretch, Alg. S1), then the element itself.  a0 is the open
+// supersegment's a_S over its current extent (the gap test's), a1 its a_S
+// extended to the element's front (the element test's; a1 = a0 where there
+// is no gap).  The state update is written as selects; a closed state's
+// fields are don't-cares.
 template <bool WRITE>
-__device__ inline void c_step(CSeg& S, const COut& o, float inv_ref, float g2, int cap, const CElem& e)
+__device__ inline void c_step(CSeg& S, const COut& o, float inv_ref, float g2, int cap, const CElem& e, float a0,
+                              float a1)
 {
     // gap [S.b, e.f): closes the open supersegment, or extends it.  The
     // conditions use non-short-circuit & so both tests run unconditionally.
     const bool gap = S.open & (e.f > S.b);
-    const bool close_g = gap & (cap <= 0 || S.count < cap - 1) & c_exceeds(S, S.b, inv_ref, g2, 0.0f, 0.0f, 0.0f);
+    const bool close_g = gap & (cap <= 0 || S.count < cap - 1) & c_exceeds(S, a0, g2, 0.0f, 0.0f, 0.0f);
     if (WRITE && close_g) c_close<true>(S, o, inv_ref);
     else S.count += close_g ? 1 : 0;
     const bool open1 = S.open & !close_g;
     const float b1 = fmaxf(S.b, e.f);   // = e.f after a gap, else S.b (don't-care when closed)
     // the element
-    const bool close = open1 & (cap <= 0 || S.count < cap - 1) & c_exceeds(S, b1, inv_ref, g2, e.e0, e.e1, e.e2);
+    const bool close = open1 & (cap <= 0 || S.count < cap - 1) & c_exceeds(S, a1, g2, e.e0, e.e1, e.e2);
     if (WRITE && close) {
         S.b = b1;
         c_close<true>(S, o, inv_ref);
@@ -340,12 +348,27 @@ __device__ void c_scan(R rd, int total, float inv_ref, const float* gam, int cap
                 prev_f = fc.x;
             }
             CElem e = prep(cc, fc, inv_ref);
+            // a_S of every state; the one extended to the element's front
+            // differs only after a gap, which most lanes see in few steps,
+            // so it is computed only where some state of the lane has one
+            float a0[NC], a1[NC];
+            bool gap = false;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                a0[c] = seg_alpha(S[c], S[c].b, inv_ref);
+                a1[c] = a0[c];
+                gap |= S[c].open & (e.f > S[c].b);
+            }
+            if (gap) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) a1[c] = seg_alpha(S[c], fmaxf(S[c].b, e.f), inv_ref);
+            }
             // a frozen state (count above limit) keeps stepping: its count
             // only grows, so its outcome stays decided
             bool live = false;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                c_step<WRITE>(S[c], o, inv_ref, g2[c], cap, e);
+                c_step<WRITE>(S[c], o, inv_ref, g2[c], cap, e, a0[c], a1[c]);
                 live |= WRITE || S[c].count <= limit;
             }
             // a failed validation decides the pass (its counts are unused)
