@@ -173,7 +173,7 @@ __device__ inline void gen_step(GenSeg& S, int& count, const GenOut& o, const Ra
 // cap > 0 saturates after cap-1 closes (fixed-threshold mode).
 template <typename VT, bool WRITE, bool EARLY = !WRITE>
 __device__ int gen_pass(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0,
-                        int k1, const float4* tf, int entries, float gamma, int cap, int limit, const GenOut& o,
+                        int k1, const TfCell* tf, int entries, float gamma, int cap, int limit, const GenOut& o,
                         int* n_opaque_out)
 {
     const float g2 = gamma * gamma;
@@ -201,7 +201,7 @@ __device__ int gen_pass(const VT* data, const BrickGeo& g, const Ray& r, float s
 // the last one, and whether the scan ran to k1 (1) or stopped early (0).
 template <typename VT, int NC>
 __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0, int k1,
-                         const float4* tf, int entries, const float* gam, int limit, int* counts, int* n_opaque_out,
+                         const TfCell* tf, int entries, const float* gam, int limit, int* counts, int* n_opaque_out,
                          int* kspan = nullptr)
 {
     GenSeg S[NC];
@@ -260,7 +260,7 @@ constexpr int kGeoLevels = 6;
 // the sequential decisions exactly.
 template <typename VT>
 __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int& k0,
-                           int& k1, const float4* tf, int entries, const GenParams& P, float& gamma_out,
+                           int& k1, const TfCell* tf, int entries, const GenParams& P, float& gamma_out,
                            int& count_out, bool need_count)
 {
     GenOut none{nullptr, nullptr, 0, 0, 0};
@@ -375,8 +375,8 @@ __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, co
 template <typename VT, int KIND>
 __global__ __launch_bounds__(256) void gen_kernel(GenParams P, GenBricks B)
 {
-    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
-    for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
+    extern __shared__ TfCell tf_s[];   // P.tf_entries - 1 cells, sized at launch
+    tf_stage(tf_s, P.tf, P.tf_entries, threadIdx.x, blockDim.x);
     __syncthreads();
 
     const GenBrick& br = B.b[blockIdx.z];
@@ -437,16 +437,31 @@ __global__ __launch_bounds__(256) void gen_kernel(GenParams P, GenBricks B)
     if (br.gamma) br.gamma[pix] = gm;
 }
 
-// Dynamic LDS of the generation kernels: the transfer function's rows.
-static size_t tf_lds(const GenParams& P) { return sizeof(float4) * (size_t)P.tf_entries; }
+// Dynamic LDS of the generation kernels: the transfer function's cells, and
+// for bricks whose data box exceeds one XCD's 4 MB L2, at least a third of a
+// CU's 160 KB, which holds each CU to two 256-thread blocks (two waves per
+// SIMD).  The registers allow three: on bricks that fit in L2 (64^3 volumes)
+// three were 20% faster; on 64 MB bricks 2% faster on an FHD frame but 12%
+// slower on a grazing view, where more resident waves evict each other's
+// stencil lines.
+template <typename VT>
+static size_t tf_lds(const GenParams& P, const GenBricks& B, int nb)
+{
+    const size_t cells = sizeof(TfCell) * (size_t)(P.tf_entries - 1);
+    size_t box = 0;
+    for (int i = 0; i < nb; ++i)
+        box = std::max(box, sizeof(VT) * (size_t)B.b[i].ddim[0] * B.b[i].ddim[1] * B.b[i].ddim[2]);
+    const size_t two_blocks = (size_t)160 * 1024 / 3 + 1024;
+    return box > ((size_t)4 << 20) ? std::max(cells, two_blocks) : cells;
+}
 
 template <typename VT>
 static void launch_gen(int kind, const GenParams& P, const GenBricks& B, int nb, hipStream_t s)
 {
     dim3 grid((P.cam.width + 15) / 16, (P.cam.height + 15) / 16, nb);
-    if (kind == 0) hipLaunchKernelGGL((gen_kernel<VT, 0>), grid, dim3(256), tf_lds(P), s, P, B);
-    if (kind == 1) hipLaunchKernelGGL((gen_kernel<VT, 1>), grid, dim3(256), tf_lds(P), s, P, B);
-    if (kind == 2) hipLaunchKernelGGL((gen_kernel<VT, 2>), grid, dim3(256), tf_lds(P), s, P, B);
+    if (kind == 0) hipLaunchKernelGGL((gen_kernel<VT, 0>), grid, dim3(256), tf_lds<VT>(P, B, nb), s, P, B);
+    if (kind == 1) hipLaunchKernelGGL((gen_kernel<VT, 1>), grid, dim3(256), tf_lds<VT>(P, B, nb), s, P, B);
+    if (kind == 2) hipLaunchKernelGGL((gen_kernel<VT, 2>), grid, dim3(256), tf_lds<VT>(P, B, nb), s, P, B);
 }
 
 void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B, int nb, hipStream_t s)
@@ -557,11 +572,11 @@ __device__ inline void put_on_list(const LearnBufs& Lb, int q, int brick, int nb
 template <typename VT>
 __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
-    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
+    extern __shared__ TfCell tf_s[];   // P.tf_entries - 1 cells, sized at launch
     // bins 2i and 2i+1 of a lane share one 32-bit word (low and high half), so
     // consecutive lanes update consecutive words (no bank conflicts)
     __shared__ uint32_t hs[32][256];
-    for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
+    tf_stage(tf_s, P.tf, P.tf_entries, threadIdx.x, blockDim.x);
     for (int j = 0; j < 32; ++j) hs[j][threadIdx.x] = 0u;
     __syncthreads();
 
@@ -658,8 +673,8 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
 template <typename VT>
 __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
-    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
-    for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
+    extern __shared__ TfCell tf_s[];   // P.tf_entries - 1 cells, sized at launch
+    tf_stage(tf_s, P.tf, P.tf_entries, threadIdx.x, blockDim.x);
     __syncthreads();
 
     const GenBrick& br = B.b[blockIdx.z];
@@ -728,8 +743,8 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
 template <typename VT>
 __global__ __launch_bounds__(256) void shortcut_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
-    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
-    for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
+    extern __shared__ TfCell tf_s[];   // P.tf_entries - 1 cells, sized at launch
+    tf_stage(tf_s, P.tf, P.tf_entries, threadIdx.x, blockDim.x);
     __syncthreads();
     const GenBrick& br = B.b[blockIdx.z];
     const int brick = B.first + blockIdx.z;
@@ -760,8 +775,8 @@ __global__ __launch_bounds__(256) void shortcut_kernel(GenParams P, GenBricks B,
 template <typename VT>
 __global__ __launch_bounds__(256) void tail_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
-    extern __shared__ float4 tf_s[];   // P.tf_entries rows, sized at launch
-    for (int i = threadIdx.x; i < P.tf_entries; i += blockDim.x) tf_s[i] = P.tf[i];
+    extern __shared__ TfCell tf_s[];   // P.tf_entries - 1 cells, sized at launch
+    tf_stage(tf_s, P.tf, P.tf_entries, threadIdx.x, blockDim.x);
     __syncthreads();
     const GenBrick& br = B.b[blockIdx.z];
     const int brick = B.first + blockIdx.z;
@@ -843,7 +858,7 @@ static void launch_learned_t(int phase, const GenParams& P, const GenBricks& B, 
 {
     dim3 grid((P.cam.width + 15) / 16, (P.cam.height + 15) / 16, nb);
     if (phase == 0) {
-        hipLaunchKernelGGL(features_kernel<VT>, grid, dim3(256), tf_lds(P), s, P, B, L);
+        hipLaunchKernelGGL(features_kernel<VT>, grid, dim3(256), tf_lds<VT>(P, B, nb), s, P, B, L);
         return;
     }
     // list-driven: grid-stride over each brick's span of the list, enough
@@ -851,9 +866,9 @@ static void launch_learned_t(int phase, const GenParams& P, const GenBricks& B, 
     size_t npix = (size_t)P.cam.width * P.cam.height;
     unsigned bx = (unsigned)std::min<size_t>((npix + 255) / 256, (size_t)L.blocks_per_brick);
     dim3 g2(bx, 1, nb);
-    if (phase == 1) hipLaunchKernelGGL(learned_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
-    if (phase == 2) hipLaunchKernelGGL(tail_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
-    if (phase == 4) hipLaunchKernelGGL(shortcut_kernel<VT>, g2, dim3(256), tf_lds(P), s, P, B, L);
+    if (phase == 1) hipLaunchKernelGGL(learned_kernel<VT>, g2, dim3(256), tf_lds<VT>(P, B, nb), s, P, B, L);
+    if (phase == 2) hipLaunchKernelGGL(tail_kernel<VT>, g2, dim3(256), tf_lds<VT>(P, B, nb), s, P, B, L);
+    if (phase == 4) hipLaunchKernelGGL(shortcut_kernel<VT>, g2, dim3(256), tf_lds<VT>(P, B, nb), s, P, B, L);
 }
 
 void launch_learned(int phase, int dtype, const GenParams& P, const GenBricks& B, int nb, const LearnBufs& L,

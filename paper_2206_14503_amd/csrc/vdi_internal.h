@@ -144,6 +144,15 @@ __device__ inline int ray_samples(const Ray& r, float step)
 // clamp for lo <= hi (one max and one min)
 __device__ inline int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// clampi for lo <= hi (then the clamp is the median of the three) in one
+// instruction; lo is wave-uniform.
+__device__ inline int clamp_med3(int v, int lo, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(v), "s"(lo), "v"(hi));
+    return r;
+}
+
 // Voxel index along axis a of the sample point (decides brick ownership).
 __device__ inline int voxel_of(float p, int n)
 {
@@ -240,6 +249,12 @@ __device__ inline float lerp_exact(float a, float b, float w)
     return __builtin_fmaf(w, d, a);
 }
 
+// (1 - w) a + w b, exactly a at w = 0 and exactly b at w = 1.
+__device__ inline float lerp_ends(float a, float b, float w)
+{
+    return __builtin_fmaf(w, b, __builtin_fmaf(-w, a, a));
+}
+
 struct BrickGeo {
     float nf[3];    // global volume dims
     int dlo[3];     // global index of the first data voxel
@@ -307,8 +322,7 @@ template <> __device__ inline float load_one<__half>(const __half* base, uint32_
 // stay in bounds for any position.
 struct Taps {
     float a[4], b[4];   // rows (y0,z0), (y1,z0), (y0,z1), (y1,z1): voxels xb, xb+1
-    float w[3];         // blend weights
-    bool s0, s1;        // x0 (x1) is the row's first voxel
+    float w[3];         // blend weights; w[0] is 0 (1) where both x taps are voxel xb (xb+1)
 };
 
 // PAIRED: the brick's data box is at least two voxels wide in x (g.sx2); a
@@ -325,8 +339,8 @@ __device__ inline Taps trilinear_fetch(const VT* data, const BrickGeo& g, const 
         float f = floorf(u);
         t.w[a] = u - f;
         int ii = (int)f - g.dlo[a];
-        i0[a] = clampi(ii, g.clo[a], g.chi[a]);
-        i1[a] = clampi(ii + 1, g.clo[a], g.chi[a]);
+        i0[a] = clamp_med3(ii, g.clo[a], g.chi[a]);
+        i1[a] = clamp_med3(ii + 1, g.clo[a], g.chi[a]);
     }
     // 24-bit multiplies: indices and strides are below 2^24 and every product
     // below 2^30 (the data box is under 4 GiB)
@@ -335,14 +349,15 @@ __device__ inline Taps trilinear_fetch(const VT* data, const BrickGeo& g, const 
     const uint32_t r00 = y0 + z0, r10 = y1 + z0, r01 = y0 + z1, r11 = y1 + z1;
     if (PAIRED) {
         const int xb = i0[0] < g.xmax ? i0[0] : g.xmax;
-        t.s0 = i0[0] == xb;
-        t.s1 = i1[0] == xb;
+        // x0 is voxel xb, else xb + 1 (the data box's last voxel, x1 = x0);
+        // x1 is voxel xb + 1 unless clamped onto x0
+        t.w[0] = i0[0] == xb ? (i1[0] == xb ? 0.0f : t.w[0]) : 1.0f;
         load_pair<VT>(data, r00 + xb, t.a[0], t.b[0]);
         load_pair<VT>(data, r10 + xb, t.a[1], t.b[1]);
         load_pair<VT>(data, r01 + xb, t.a[2], t.b[2]);
         load_pair<VT>(data, r11 + xb, t.a[3], t.b[3]);
     } else {
-        t.s0 = t.s1 = true;
+        t.w[0] = 0.0f;
         t.a[0] = t.b[0] = load_one<VT>(data, r00);
         t.a[1] = t.b[1] = load_one<VT>(data, r10);
         t.a[2] = t.b[2] = load_one<VT>(data, r01);
@@ -354,14 +369,10 @@ __device__ inline Taps trilinear_fetch(const VT* data, const BrickGeo& g, const 
 __device__ inline float trilinear_blend(const Taps& t)
 {
 #pragma clang fp contract(off)
-    const float v000 = t.s0 ? t.a[0] : t.b[0], v100 = t.s1 ? t.a[0] : t.b[0];
-    const float v010 = t.s0 ? t.a[1] : t.b[1], v110 = t.s1 ? t.a[1] : t.b[1];
-    const float v001 = t.s0 ? t.a[2] : t.b[2], v101 = t.s1 ? t.a[2] : t.b[2];
-    const float v011 = t.s0 ? t.a[3] : t.b[3], v111 = t.s1 ? t.a[3] : t.b[3];
-    float c00 = lerp_exact(v000, v100, t.w[0]);
-    float c10 = lerp_exact(v010, v110, t.w[0]);
-    float c01 = lerp_exact(v001, v101, t.w[0]);
-    float c11 = lerp_exact(v011, v111, t.w[0]);
+    float c00 = lerp_ends(t.a[0], t.b[0], t.w[0]);
+    float c10 = lerp_ends(t.a[1], t.b[1], t.w[0]);
+    float c01 = lerp_ends(t.a[2], t.b[2], t.w[0]);
+    float c11 = lerp_ends(t.a[3], t.b[3], t.w[0]);
     float c0 = lerp_exact(c00, c10, t.w[1]);
     float c1 = lerp_exact(c01, c11, t.w[1]);
     return lerp_exact(c0, c1, t.w[2]);
@@ -386,14 +397,30 @@ __device__ inline void tf_coord(float s, int entries, int& cell, float& w)
     w = q - (float)i;
 }
 
-__device__ inline float4 tf_lookup(const float4* tf, int entries, float s)
+// The transfer function as the kernels stage it: per cell i (0 <= i <
+// entries - 1) its lower row and the difference to the row above.
+struct TfCell {
+    float4 lo, d;
+};
+
+// Cells of the rows tf[0 .. entries), by the threads of a block (stride n).
+__device__ inline void tf_stage(TfCell* cells, const float4* tf, int entries, int t, int n)
+{
+    for (int i = t; i < entries - 1; i += n) {
+        const float4 lo = tf[i], hi = tf[i + 1];
+        cells[i].lo = lo;
+        cells[i].d = make_float4(hi.x - lo.x, hi.y - lo.y, hi.z - lo.z, hi.w - lo.w);
+    }
+}
+
+__device__ inline float4 tf_lookup(const TfCell* tf, int entries, float s)
 {
     int i;
     float w;
     tf_coord(s, entries, i, w);
-    float4 lo = tf[i], hi = tf[i + 1];
-    return make_float4(fmaf(w, hi.x - lo.x, lo.x), fmaf(w, hi.y - lo.y, lo.y),
-                       fmaf(w, hi.z - lo.z, lo.z), fmaf(w, hi.w - lo.w, lo.w));
+    const TfCell c = tf[i];
+    return make_float4(fmaf(w, c.d.x, c.lo.x), fmaf(w, c.d.y, c.lo.y), fmaf(w, c.d.z, c.lo.z),
+                       fmaf(w, c.d.w, c.lo.w));
 }
 
 // ---------------------------------------------------------------- fast math
