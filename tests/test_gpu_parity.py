@@ -161,6 +161,31 @@ def test_generate_extreme_n_parity(V, orc, max_n, mode):
                        f"brick {r} N {max_n}")
 
 
+@pytest.mark.parametrize("nx,dtype", [(1, "f32"), (2, "f32"), (3, "f16")], ids=["x1", "x2", "x3-f16"])
+def test_generate_thin_volume_parity(V, orc, nx, dtype):
+    """Volumes one to three voxels wide in x: a one-voxel data box (single
+    loads) and the x edges where both taps of a stencil row fall on one voxel
+    (the first voxel below x = 0.5, the last above x = nx - 0.5)."""
+    import torch
+    vol = np.ascontiguousarray(synth.gaussian_volume(24, 6, 3)[:, :, :nx])
+    if dtype == "f16":
+        vol = vol.astype(np.float16)
+    tf = synth.transfer_function()
+    cam = synth.orbit_camera(10_020 + nx, 40, 30)
+    bricks = synth.brick_grid((nx, 24, 24), (1, 1, 2))
+    dbr = V.device_bricks(vol, bricks)
+    tf_d = torch.from_numpy(tf).cuda()
+    outs = V.generate(dbr, cam, tf_d, 1 / 24, 1 / 24, 1, 0.0, 8, 10)
+    torch.cuda.synchronize()
+    assert V.device_status() == 0
+    ref = orc.generate(vol, bricks, cam, tf, 1 / 24, 1 / 24, 1, 0.0, 8, 10)
+    for r in range(len(bricks)):
+        gc, gd, gn, gg = _gpu_regular(outs[r])
+        assert (gn > 0).sum() > 100
+        _compare_lists(gc, gd, gn, ref["color"][r], ref["depth"][r], ref["count"][r], ref["margin"][r],
+                       f"brick {r} nx {nx}")
+
+
 @pytest.mark.parametrize("mode", [0, 1], ids=["fixed", "bisect"])
 def test_generate_compact_matches_regular(V, mode):
     """Compact layout (Sec. 4): offsets are the exclusive prefix sum of the
