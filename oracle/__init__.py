@@ -68,11 +68,13 @@ def lib():
         L.orc_ray_info.argtypes = [ctypes.POINTER(Camera), ctypes.c_int, f32, P, P, P, P]
         L.orc_stream.argtypes = [P, ctypes.c_int, P, P, P, ctypes.POINTER(Camera), P, ctypes.c_int, f32,
                                  ctypes.c_int, P, ctypes.c_int, P]
+        L.orc_novel_view.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, f32,
+                                     ctypes.POINTER(Camera), ctypes.POINTER(Camera), f32, P, ctypes.c_int]
         L.orc_trilinear.argtypes = [P, ctypes.c_int, P, P]
         L.orc_trilinear.restype = f64
         L.orc_classify.argtypes = [P, ctypes.c_int, f32, P]
         L.orc_classify.restype = None
-        for name in ("orc_generate", "orc_composite", "orc_render_ov", "orc_dvr", "orc_seg",
+        for name in ("orc_generate", "orc_composite", "orc_render_ov", "orc_novel_view", "orc_dvr", "orc_seg",
                      "orc_ray_info", "orc_stream"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -174,6 +176,31 @@ def render_ov(color: np.ndarray, depth: np.ndarray, count: np.ndarray, ref: floa
     rc = lib().orc_render_ov(_ptr(color), _ptr(depth), _ptr(count), max_n, npix, ref, _ptr(rgba), nthreads)
     if rc != 0:
         raise RuntimeError("orc_render_ov failed")
+    return rgba
+
+
+def novel_view(color: np.ndarray, depth: np.ndarray, count: np.ndarray, ref: float, vdi_cam, view, step: float,
+               offset: Optional[np.ndarray] = None, nthreads: int = 0) -> np.ndarray:
+    """Premultiplied RGBA [view pixels, 4] (fp64) of a VDI rendered from camera
+    `view` (the VDI as a piecewise-constant field over its camera's pixel
+    frusta, sampled on each new ray's grid).  Regular layout: color [N, P, 4],
+    depth [N, P, 2]; compact (offset given): color [M, 4], depth [M, 2], pixel
+    q's list at offset[q]."""
+    color = np.ascontiguousarray(color, dtype=np.float32)
+    depth = np.ascontiguousarray(depth, dtype=np.float32)
+    count = np.ascontiguousarray(count, dtype=np.int32)
+    if offset is None:
+        max_n = color.shape[0]
+        off = None
+    else:
+        max_n = max(int(count.max()) if count.size else 1, 1)
+        off = np.ascontiguousarray(offset, dtype=np.uint32)
+    rgba = np.zeros((view.width * view.height, 4), np.float64)
+    vc, nv = _cam(vdi_cam), _cam(view)
+    rc = lib().orc_novel_view(_ptr(color), _ptr(depth), _ptr(count), _ptr(off), max_n, vdi_cam.width,
+                              vdi_cam.height, ref, ctypes.byref(vc), ctypes.byref(nv), step, _ptr(rgba), nthreads)
+    if rc != 0:
+        raise RuntimeError("orc_novel_view failed")
     return rgba
 
 
