@@ -199,6 +199,29 @@ vdi_status vdi_composite(vdi_ctx *ctx, const vdi_t *in, int k, const vdi_tau_t *
  * their total opacities.  rgba: [H*W][4] premultiplied, fp32. */
 vdi_status vdi_render_original_view(vdi_ctx *ctx, const vdi_t *vdi, float *rgba, void *stream);
 
+/* Rendering from another viewpoint (Sec. 7 renders VDIs at viewpoint
+ * deviations from the viewpoint of generation and compares them with DVR;
+ * the rendering method itself is prior work the paper cites).  The VDI,
+ * generated through camera vdi_cam, is read as the piecewise-constant field
+ * it encodes: supersegment j of pixel q fills the part of q's view frustum
+ * between its front and back depths with its colour and per-ref_step
+ * opacity, and nothing lies outside the supersegments.  Each ray of `view`
+ * is sampled like a generation ray (midpoints of [tn + k step, tn + (k+1)
+ * step) from its entry into [0,1]^3); a sample point belongs to the vdi_cam
+ * pixel whose frustum contains it, at the depth the VDI measures (distance
+ * from the eye, perspective; along fwd from the image plane, orthographic),
+ * both decided in fp64.  A sample inside supersegment (rgb, a) adds colour
+ * rgb with opacity 1 - (1 - a)^(step/ref_step) (Eq. 2), front to back.
+ *   vdi_cam: the VDI's generation camera (same width and height as the VDI;
+ *            fwd, right and up orthogonal).  Lists must be front to back with
+ *            disjoint [front, back) intervals, as generated or composited.
+ *   view:    the new camera; rgba: [view H*W][4] premultiplied fp32 (device).
+ *   step:    sampling distance of the new rays (world units, > 0).
+ * A list with a count outside [0, max_n] (or past a compact VDI's capacity)
+ * is read as empty and sets device status flag 2. */
+vdi_status vdi_render_novel_view(vdi_ctx *ctx, const vdi_t *vdi, const vdi_camera_t *vdi_cam,
+                                 const vdi_camera_t *view, float step, float *rgba, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Learned threshold (an extension beyond the paper: a regressor replaces the
  * per-ray bisection of Sec. 2.4).

@@ -506,6 +506,37 @@ vdi_status vdi_render_original_view(vdi_ctx* ctx, const vdi_t* v, float* rgba, v
     return launched();
 }
 
+vdi_status vdi_render_novel_view(vdi_ctx* ctx, const vdi_t* v, const vdi_camera_t* vdi_cam, const vdi_camera_t* view,
+                                 float step, float* rgba, void* stream)
+{
+    if (!ctx || !vdi_cam || !view || !rgba) return fail(VDI_E_INVALID, "NULL argument");
+    vdi_status st = check_vdi(v, "vdi", true);
+    if (st != VDI_OK) return st;
+    if (vdi_cam->width != v->width || vdi_cam->height != v->height)
+        return fail(VDI_E_INVALID, "vdi_cam is %dx%d, the VDI %dx%d", vdi_cam->width, vdi_cam->height, v->width,
+                    v->height);
+    if (view->width <= 0 || view->height <= 0) return fail(VDI_E_INVALID, "bad view size");
+    if (!(step > 0.0f)) return fail(VDI_E_INVALID, "step must be > 0");
+    if (!(1.7320508f / step < 16777216.0f)) return fail(VDI_E_UNSUPPORTED, "step too small");
+    NovelParams N;
+    N.view = to_cam(view);
+    N.vcam = to_cam(vdi_cam);
+    N.color = (const float4*)v->color;
+    N.depth = (const float2*)v->depth;
+    N.count = v->count;
+    const bool compact = v->layout == VDI_LAYOUT_COMPACT;
+    N.offset = compact ? v->offset : nullptr;
+    N.npix = (uint32_t)((size_t)v->width * v->height);
+    N.capacity = compact ? v->capacity : (uint64_t)v->max_n * N.npix;
+    N.max_n = v->max_n;
+    N.step = step;
+    N.l = step / v->ref_step;
+    N.rgba = (float4*)rgba;
+    N.status = ctx->status;
+    launch_novel(N, (hipStream_t)stream);
+    return launched();
+}
+
 vdi_status vdi_debug_rays(vdi_ctx* ctx, const vdi_camera_t* cam, float step, float* o, float* d, float* tn,
                           float* tf, int32_t* nsamples, void* stream)
 {

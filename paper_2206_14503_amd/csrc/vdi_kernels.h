@@ -174,6 +174,23 @@ void launch_mfma_probe(const uint16_t* A, const uint16_t* B, float* D, hipStream
 
 // ---------------------------------------------------------------- rendering
 
+// A VDI rendered from camera `view` (the VDI generated through camera `vcam`).
+struct NovelParams {
+    Cam view, vcam;
+    const float4* color;
+    const float2* depth;
+    const int* count;
+    const uint32_t* offset;   // compact only
+    uint64_t capacity;        // entries color/depth hold
+    int max_n;
+    uint32_t npix;            // VDI pixels
+    float step;               // sampling distance of the new rays
+    float l;                  // step / ref_step
+    float4* rgba;             // [view pixels]
+    int* status;
+};
+void launch_novel(const NovelParams& N, hipStream_t s);
+
 void launch_render(const float4* color, const float2* depth, const int* count, const uint32_t* offset,
                    uint64_t capacity, int max_n, uint32_t npix, float inv_ref, float4* rgba, int* status,
                    hipStream_t s);

@@ -245,10 +245,12 @@ def perspective_camera(eye, target, width: int, height: int, fovy_deg: float = 6
 
 
 def orbit_camera(seed: int, width: int, height: int, radius: float = 1.8,
-                 max_elev_deg: float = 30.0, fovy_deg: float = 60.0) -> Camera:
-    """Perspective camera on a seeded orbit about the box centre, looking at it."""
+                 max_elev_deg: float = 30.0, fovy_deg: float = 60.0, turn_deg: float = 0.0) -> Camera:
+    """Perspective camera on a seeded orbit about the box centre, looking at it;
+    turn_deg moves it along the orbit (azimuth) by that angle, a viewpoint
+    deviation about the box centre."""
     rng = np.random.default_rng(seed)
-    az = rng.uniform(0.0, 2.0 * math.pi)
+    az = rng.uniform(0.0, 2.0 * math.pi) + math.radians(turn_deg)
     el = math.radians(rng.uniform(-max_elev_deg, max_elev_deg))
     c = np.array([0.5, 0.5, 0.5])
     eye = c + radius * np.array([math.cos(el) * math.sin(az), math.sin(el), math.cos(el) * math.cos(az)])

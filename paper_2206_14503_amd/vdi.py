@@ -90,6 +90,8 @@ def lib():
                                    ctypes.POINTER(vdi_t), P]
         L.vdi_composite.argtypes = [P, ctypes.POINTER(vdi_t), I, ctypes.POINTER(vdi_tau_t), ctypes.POINTER(vdi_t), P]
         L.vdi_render_original_view.argtypes = [P, ctypes.POINTER(vdi_t), P, P]
+        L.vdi_render_novel_view.argtypes = [P, ctypes.POINTER(vdi_t), ctypes.POINTER(vdi_camera_t),
+                                            ctypes.POINTER(vdi_camera_t), ctypes.c_float, P, P]
         L.vdi_debug_rays.argtypes = [P, ctypes.POINTER(vdi_camera_t), ctypes.c_float, P, P, P, P, P, P]
         L.vdi_tau_features.argtypes = [P, ctypes.POINTER(vdi_brick_t), I, ctypes.POINTER(vdi_camera_t),
                                        ctypes.POINTER(vdi_tf_t), ctypes.c_float, ctypes.c_float, I,
@@ -101,8 +103,8 @@ def lib():
         L.vdi_learned_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), P]
         L.vdi_debug_mfma.argtypes = [P, P, P, P, P]
         for name in ("vdi_ctx_create", "vdi_ctx_destroy", "vdi_ctx_device_status", "vdi_generate", "vdi_composite",
-                     "vdi_render_original_view", "vdi_debug_rays", "vdi_tau_features", "vdi_mlp_forward",
-                     "vdi_mlp_backward", "vdi_mlp_adam", "vdi_learned_stats", "vdi_debug_mfma"):
+                     "vdi_render_original_view", "vdi_render_novel_view", "vdi_debug_rays", "vdi_tau_features",
+                     "vdi_mlp_forward", "vdi_mlp_backward", "vdi_mlp_adam", "vdi_learned_stats", "vdi_debug_mfma"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -273,6 +275,17 @@ def render_original_view(v: VDI, out: Optional[torch.Tensor] = None) -> torch.Te
         out = torch.empty((v.npix, 4), dtype=torch.float32, device=v.color.device)
     vc = v.c()
     _check(lib().vdi_render_original_view(context(), ctypes.byref(vc), _ptr(out), _stream()))
+    return out
+
+
+def render_novel_view(v: VDI, vdi_cam, view, step: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """vdi_render_novel_view: the VDI (generated through vdi_cam) seen from
+    camera `view`; premultiplied RGBA [view H*W, 4]."""
+    if out is None:
+        out = torch.empty((view.width * view.height, 4), dtype=torch.float32, device=v.color.device)
+    vc, c0, c1 = v.c(), camera_c(vdi_cam), camera_c(view)
+    _check(lib().vdi_render_novel_view(context(), ctypes.byref(vc), ctypes.byref(c0), ctypes.byref(c1), step,
+                                       _ptr(out), _stream()))
     return out
 
 

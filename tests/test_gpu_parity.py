@@ -474,3 +474,77 @@ def test_end_to_end_equals_dvr(V, orc, grid, mode, out_n):
     ref = orc.dvr(vol, cam, tf, 1 / 64, 1 / 64)
     assert np.abs(img - ref).max() <= ATOL
     assert int(comp.count.max()) <= out_n
+
+
+# ---------------------------------------------------------------- novel-view rendering
+
+def _oracle_composited(orc, cam, seed=0):
+    vol, tf, bricks, ref = _oracle_inputs(orc, (1, 1, 2), cam, mode=1, seed=seed)
+    return orc.composite([ref["color"][r] for r in range(2)], [ref["depth"][r] for r in range(2)],
+                         [ref["count"][r] for r in range(2)], 1 / 64, 1, 0.0, 8, 10)
+
+
+@pytest.mark.parametrize("vcam,view,step", [
+    (synth.orbit_camera(10_040, 64, 48), synth.orbit_camera(10_040, 56, 40, turn_deg=10.0), 1 / 64),
+    (synth.orbit_camera(10_041, 64, 48), synth.orbit_camera(10_041, 64, 48), 1 / 64),
+    (synth.orbit_camera(10_042, 48, 48), synth.orbit_camera(10_042, 40, 30, turn_deg=50.0), 1 / 48),
+    (synth.ortho_camera(64, 64, "+z"), synth.orbit_camera(10_043, 50, 38), 1 / 80),
+], ids=["persp-10deg", "persp-own-view", "persp-50deg-coarse-ragged", "ortho-vdi-fine"])
+def test_render_novel_view_parity(V, orc, vcam, view, step):
+    """A composited VDI (the oracle's, uploaded) rendered from another
+    viewpoint: the pixel and supersegment of every sample are fp64 decisions
+    taken identically on both sides, so the images agree within ATOL."""
+    import torch
+    c = _oracle_composited(orc, vcam)
+    v = V.VDI(vcam.width, vcam.height, 8, 1 / 64, V.REGULAR, torch.from_numpy(c["color"]).cuda(),
+              torch.from_numpy(c["depth"]).cuda(), torch.from_numpy(c["count"]).cuda(), None, None)
+    g = _np(V.render_novel_view(v, vcam, view, step))
+    torch.cuda.synchronize()
+    assert V.device_status() == 0
+    ref = orc.novel_view(c["color"], c["depth"], c["count"], 1 / 64, vcam, view, step)
+    assert (ref[:, 3] > 0.01).sum() > 100
+    err = np.abs(g - ref).max()
+    assert err <= ATOL, f"max |gpu - oracle| {err:.3g}"
+
+
+def test_render_novel_view_compact_parity(V, orc):
+    """The same lists in the compact layout (offsets), against the oracle."""
+    import torch
+    vcam = synth.orbit_camera(10_044, 48, 40)
+    c = _oracle_composited(orc, vcam)
+    cnt = c["count"]
+    P = cnt.size
+    off = np.zeros(P + 1, np.int64)
+    off[1:] = np.cumsum(cnt)
+    m = int(off[-1])
+    cc = np.zeros((m, 4), np.float32)
+    dd = np.zeros((m, 2), np.float32)
+    for q in range(P):
+        cc[off[q]:off[q + 1]] = c["color"][:cnt[q], q]
+        dd[off[q]:off[q + 1]] = c["depth"][:cnt[q], q]
+    v = V.VDI(vcam.width, vcam.height, 8, 1 / 64, V.COMPACT, torch.from_numpy(cc).cuda(),
+              torch.from_numpy(dd).cuda(), torch.from_numpy(cnt).cuda(),
+              torch.from_numpy(off.astype(np.int32)).cuda(), None)
+    view = synth.orbit_camera(10_044, 44, 36, turn_deg=-25.0)
+    g = _np(V.render_novel_view(v, vcam, view, 1 / 64))
+    torch.cuda.synchronize()
+    assert V.device_status() == 0
+    ref = orc.novel_view(cc, dd, cnt, 1 / 64, vcam, view, 1 / 64, offset=off[:-1].astype(np.uint32))
+    assert (ref[:, 3] > 0.01).sum() > 100
+    assert np.abs(g - ref).max() <= ATOL
+
+
+def test_render_novel_view_from_own_camera_equals_original_view(V, orc):
+    """A GPU-generated and composited VDI seen from its own camera on its own
+    grid equals its original-view rendering (up to the fp32 depths)."""
+    import torch
+    vcam = synth.orbit_camera(10_045, 64, 48)
+    vol, tf, tf_d, cam, bricks, dbr = _tiny_setup(V, 1, grid=(1, 1, 2), cam=vcam)
+    outs = V.generate(dbr, vcam, tf_d, 1 / 64, 1 / 64, 1, 0.0, 8, 10)
+    comp = V.composite(outs, 1, 0.0, 8, 10)
+    ov = _np(V.render_original_view(comp))
+    nv = _np(V.render_novel_view(comp, vcam, vcam, 1 / 64))
+    torch.cuda.synchronize()
+    assert V.device_status() == 0
+    assert (ov[:, 3] > 0.01).sum() > 100
+    assert np.abs(nv - ov).max() <= 2e-5
