@@ -5,6 +5,8 @@ sub-VDIs of a 512^3 fp32 volume split into z-slabs (per-ray bisection of the
 threshold to N=20, regular slot-major layout; --layout compact for the compact
 one), composite them into one N=20 VDI and render it from the original view.  The headline metric is composited VDI pixels per
 second of that step.  Further legs (same JSON line):
+  novel    -- that composited VDI rendered at 5, 20 and 50 degrees from its
+              viewpoint: time per frame, SSIM and PSNR against DVR there;
   large    -- 1024^3 fp16 volume in 16 bricks (4x2x2): generate + composite,
               and the composite alone on maximally interleaved dense lists
               (16 x 20 supersegments per pixel, 16.6 GB of input);
@@ -16,7 +18,7 @@ second of that step.  Further legs (same JSON line):
               replayed from a hipGraph: jobs/s and per-job latency.
 Printed: ONE JSON line on stdout (progress goes to stderr).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--legs fhd,large,learned,batched]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--legs fhd,novel,large,learned,batched]
 """
 from __future__ import annotations
 
@@ -201,7 +203,38 @@ def leg_fhd(args, result):
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": comp_gbs / HBM_PEAK_GBS,
                           "traffic": traffic, "traffic_note": why, "algorithmic_bytes": cbytes,
                           "workload": w.name}
-    return dict(w=w, vol=vol, bricks=bricks, tf=tf, cam=cam, step_len=step_len)
+    return dict(w=w, vol=vol, bricks=bricks, tf=tf, cam=cam, step_len=step_len, dbr=dbr, tf_d=tf_d, out=out)
+
+
+# ---------------------------------------------------------------- novel viewpoints
+
+def leg_novel(args, result, fhd):
+    """The composited FHD VDI rendered at viewpoint deviations about its
+    generation viewpoint (Sec. 7): time per frame, and SSIM and PSNR against
+    DVR at the new viewpoint, which is the original-view rendering of a VDI
+    generated there (equal to DVR of the same samples, Sec. 2.3)."""
+    import torch
+    from paper_2206_14503_amd import quality, synth, vdi
+
+    w, cam, step_len, dbr, tf_d, v0 = fhd["w"], fhd["cam"], fhd["step_len"], fhd["dbr"], fhd["tf_d"], fhd["out"]
+    out = {}
+    for deg in (5.0, 20.0, 50.0):
+        view = synth.orbit_camera(10_000 + w.seed, cam.width, cam.height, turn_deg=deg)
+        img = torch.empty((view.width * view.height, 4), dtype=torch.float32, device="cuda")
+        fn = lambda: vdi.render_novel_view(v0, cam, view, step_len, out=img)
+        fn()
+        torch.cuda.synchronize()
+        ms = float(timed_ms(fn, 5).mean())
+        subs = vdi.generate(dbr, view, tf_d, step_len, step_len, vdi.BISECT, 0.0, w.max_n, w.iters)
+        gt = vdi.render_original_view(vdi.composite(subs, vdi.BISECT, 0.0, w.max_n, w.iters))
+        a, b = img.cpu().numpy(), gt.cpu().numpy()
+        del subs, gt
+        s, p = quality.ssim(a, b, height=view.height), quality.psnr(a, b, height=view.height)
+        out[f"{deg:g}deg"] = {"ms": ms, "mpix_per_s": view.width * view.height / ms / 1e3, "ssim_vs_dvr": s,
+                              "psnr_vs_dvr_db": p}
+        log(f"[bench] novel view at {deg:g} deg: {ms:.3f} ms; SSIM {s:.4f}, PSNR {p:.2f} dB vs DVR")
+    result["novel_view"] = {"workload": f"{w.name} VDI rendered at {cam.width}x{cam.height}, deviations about the "
+                                        f"box centre along the orbit", **out}
 
 
 # ---------------------------------------------------------------- large one-GPU share
@@ -434,7 +467,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--layout", choices=["compact", "regular"], default="regular")
-    ap.add_argument("--legs", default="fhd,large,learned,batched")
+    ap.add_argument("--legs", default="fhd,novel,large,learned,batched")
     ap.add_argument("--learn-seeds", type=int, default=32)
     ap.add_argument("--learn-epochs", type=int, default=8)
     ap.add_argument("--no-learn-fhd", dest="learn_fhd", action="store_false",
@@ -462,6 +495,8 @@ def main():
         log("[bench] copy calibration: 3 x 1 GiB device-to-device copies")
         del src, dst
     fhd = leg_fhd(args, result)
+    if "novel" in legs:
+        leg_novel(args, result, fhd)
     if "large" in legs:
         leg_large(args, result)
     elif "dense" in legs:
