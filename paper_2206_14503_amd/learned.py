@@ -159,12 +159,16 @@ def timed(fn, reps: int = 3) -> float:
 
 
 def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor,
-             reps: int = 3) -> Dict[str, float]:
+             reps: int = 3, novel_deg: float = 20.0) -> Dict[str, float]:
     """Plain bisection vs learned generation on held-out frames: time, fallback
     rate, count statistics and the original-view rendering error of each.  The
     plain search is timed twice: speculative (several midpoints per pass, the
     library's BISECT) and one midpoint per pass (BISECT_SEQ, the search as the
-    paper runs it); both give the same VDIs."""
+    paper runs it); both give the same VDIs.  On the FHD-generator frames
+    (orbit cameras) both composited VDIs are also rendered novel_deg degrees
+    along the orbit and compared with DVR there by SSIM and PSNR, which is
+    what the threshold choice costs in quality."""
+    from . import quality
     step = 1.0 / cfg.n
     t_plain = t_learned = t_seq = 0.0
     agg = {"accepted": 0, "refined": 0, "shortcut": 0, "fallback": 0, "empty": 0}
@@ -172,6 +176,8 @@ def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch
     dn_sum, dn_rays = 0.0, 0
     frames = 0
     rays = 0
+    q_sums = {"ssim_plain": 0.0, "ssim_learned": 0.0, "psnr_plain": 0.0, "psnr_learned": 0.0}
+    q_frames = 0
     for seed in seeds:
         vol, bricks, cam = frame_inputs(cfg, seed, cfg.res)
         dbr = vdi.device_bricks(vol, bricks)
@@ -212,6 +218,18 @@ def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch
         # the plain path's original-view rendering equals direct volume
         # rendering (Sec. 2.3; checked against the oracle in the tests)
         mae_learned += float((img_l - img_p).abs().mean())
+        if cfg.kind == "fhd":
+            w = dataclasses.replace(synth.fhd(seed), width=cfg.res[0], height=cfg.res[1])
+            view = synth.orbit_camera(10_000 + w.seed, cam.width, cam.height, turn_deg=novel_deg)
+            outs_g = vdi.generate(dbr, view, tf_d, step, step, vdi.BISECT, 0.0, cfg.max_n, cfg.iters,
+                                  gamma_max=cfg.gamma_max)
+            gt = vdi.render_original_view(vdi.composite(outs_g, vdi.BISECT, 0.0, cfg.max_n, cfg.iters)).cpu().numpy()
+            del outs_g
+            for key, comp in (("plain", comp_p), ("learned", comp_l)):
+                nv = vdi.render_novel_view(comp, cam, view, step).cpu().numpy()
+                q_sums["ssim_" + key] += quality.ssim(nv, gt, height=view.height)
+                q_sums["psnr_" + key] += quality.psnr(nv, gt, height=view.height)
+            q_frames += 1
         frames += 1
         rays += len(bricks) * P
     served_total = agg["accepted"] + agg["refined"] + agg["fallback"]
@@ -228,4 +246,5 @@ def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch
         "shortcut": agg["shortcut"], "empty": agg["empty"],
         "mean_abs_count_miss": dn_sum / max(dn_rays, 1),
         "rgba_mae_vs_plain_render": mae_learned / frames,
+        **({f"{k}_{novel_deg:g}deg_vs_dvr": v / q_frames for k, v in q_sums.items()} if q_frames else {}),
     }
