@@ -57,7 +57,7 @@ def lib():
         i32, f32, f64 = ctypes.c_int32, ctypes.c_float, ctypes.c_double
         L.orc_generate.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_int, ctypes.POINTER(Camera), P, ctypes.c_int,
                                    f32, f32, ctypes.c_int, f32, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
-                                   P, P, P, P, P, P, ctypes.c_int]
+                                   P, P, P, P, P, P, P, P, ctypes.c_int]
         L.orc_composite.argtypes = [ctypes.c_int, P, P, P, ctypes.c_int, ctypes.c_int, f32, ctypes.c_int, f32,
                                     ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, ctypes.c_int]
         L.orc_render_ov.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, f32, P, ctypes.c_int]
@@ -101,8 +101,12 @@ def _dims(vol: np.ndarray) -> np.ndarray:
 
 def generate(vol: np.ndarray, bricks: Sequence, cam, tf: np.ndarray, step: float, ref: float,
              mode: int, tau: float, max_n: int, iters: int = 10,
-             pixels: Optional[np.ndarray] = None, nthreads: int = 0) -> Dict[str, np.ndarray]:
-    """Generate one regular sub-VDI per brick over `pixels` (default: all)."""
+             pixels: Optional[np.ndarray] = None, nthreads: int = 0, owner: Optional[np.ndarray] = None,
+             ranks: Optional[Sequence[int]] = None) -> Dict[str, np.ndarray]:
+    """Generate one regular sub-VDI per brick over `pixels` (default: all).
+    owner: optional rank per voxel ([nz, ny, nx] uint8, like the volume) with
+    ranks[r] brick r's rank: brick r owns the samples whose voxel lies in its
+    box and carries its rank (non-convex domains; bisection modes only)."""
     vol, dt = _vol(vol)
     n = _dims(vol)
     nb = len(bricks)
@@ -123,11 +127,15 @@ def generate(vol: np.ndarray, bricks: Sequence, cam, tf: np.ndarray, step: float
         "margin": np.zeros((nb, npix), np.float64),
         "contiguous": np.zeros((nb, npix), np.int32),
     }
+    own = None if owner is None else np.ascontiguousarray(owner, dtype=np.uint8)
+    rk = None if ranks is None else np.ascontiguousarray(ranks, dtype=np.int32)
+    if own is not None:
+        assert own.shape == vol.shape and rk is not None and len(rk) == nb
     c = _cam(cam)
     rc = lib().orc_generate(_ptr(vol), dt, _ptr(n), _ptr(lo), _ptr(hi), nb, ctypes.byref(c), _ptr(tf),
                             tf.shape[0], step, ref, mode, tau, max_n, iters, _ptr(px), npix,
                             _ptr(out["color"]), _ptr(out["depth"]), _ptr(out["count"]), _ptr(out["gamma"]),
-                            _ptr(out["margin"]), _ptr(out["contiguous"]), nthreads)
+                            _ptr(out["margin"]), _ptr(out["contiguous"]), _ptr(own), _ptr(rk), nthreads)
     if rc != 0:
         raise RuntimeError(f"orc_generate failed ({rc})")
     return out

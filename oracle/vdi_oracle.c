@@ -374,12 +374,15 @@ static int ray_samples(const orc_ray *r, float step)
     return k;
 }
 
-/* Owned sample stream of one brick along one ray.  Returns the element count;
- * *contiguous is cleared if the owned samples are not one run (the stream is
- * then cut at the first discontinuity: a supersegment must end where the ray
- * leaves the domain, Sec. 5.3). */
-static int brick_stream(const orc_volume *vol, const int32_t *lo, const int32_t *hi,
-                        const orc_ray *r, const float *tf, int entries, float step,
+/* Owned sample stream of one brick along one ray.  A brick owns a sample
+ * whose voxel lies in its box [lo, hi) and, when an owner map is given (one
+ * rank per voxel, x fastest: arbitrary, possibly non-convex domains, Sec. 5.3),
+ * carries the brick's rank there.  Returns the element count; *contiguous is
+ * cleared if the owned samples are not one run (the segmenter then ends the
+ * open supersegment at each discontinuity: a supersegment must end where the
+ * ray leaves the domain, Sec. 5.3). */
+static int brick_stream(const orc_volume *vol, const int32_t *lo, const int32_t *hi, const uint8_t *owner,
+                        int rank, const orc_ray *r, const float *tf, int entries, float step,
                         orc_elem *e, int cap, int *contiguous, float *a32_out)
 {
     int ns = ray_samples(r, step), n = 0, last = -2;
@@ -390,6 +393,7 @@ static int brick_stream(const orc_volume *vol, const int32_t *lo, const int32_t 
         sample_point(r, k, step, p);
         voxel_of(vol, p, v);
         if (!brick_owns(lo, hi, v)) continue;
+        if (owner && owner[((size_t)v[2] * vol->n[1] + v[1]) * vol->n[0] + v[0]] != rank) continue;
         if (last >= 0 && k != last + 1) *contiguous = 0;
         last = k;
         if (n >= cap) break;
@@ -430,6 +434,10 @@ static void set_threads(int nthreads)
  *   color [nb][max_n][npix][4], depth [nb][max_n][npix][2] (zero beyond count),
  *   count [nb][npix], gamma [nb][npix], margin [nb][npix] (may be NULL),
  *   contiguous [nb][npix] (may be NULL).
+ * owner (may be NULL): rank of every voxel [nz][ny][nx], ranks [nb] the
+ * bricks' ranks (bisection only).  The count is what the segmenter emits:
+ * with an owner map a ray can enter a domain more often than N times, and the
+ * stored list then holds the first max_n supersegments.
  * Returns 0, or -1 on bad arguments. */
 int orc_generate(const void *vol_data, int vol_dtype, const int32_t *n,
                  const int32_t *brick_lo, const int32_t *brick_hi, int nb,
@@ -437,10 +445,12 @@ int orc_generate(const void *vol_data, int vol_dtype, const int32_t *n,
                  float step, float ref, int mode, float tau, int max_n, int iters,
                  const int32_t *pixels, int npix,
                  float *color, float *depth, int32_t *count, float *gamma,
-                 double *margin, int32_t *contiguous, int nthreads)
+                 double *margin, int32_t *contiguous, const uint8_t *owner, const int32_t *ranks,
+                 int nthreads)
 {
     if (!vol_data || !n || nb <= 0 || !cam || !tf || entries < 2 || max_n <= 0 || npix < 0)
         return -1;
+    if (owner && (!ranks || mode == ORC_FIXED)) return -1;
     orc_volume vol = { vol_data, vol_dtype, { n[0], n[1], n[2] } };
     int cap = max_samples(step);
     set_threads(nthreads);
@@ -456,8 +466,8 @@ int orc_generate(const void *vol_data, int vol_dtype, const int32_t *n,
             int pix = pixels ? pixels[q] : (int)q;
             orc_ray ray = make_ray(cam, pix % cam->width, pix / cam->width);
             int contig;
-            int ne = ray.hit ? brick_stream(&vol, brick_lo + 3 * r, brick_hi + 3 * r, &ray, tf, entries,
-                                            step, e, cap, &contig, NULL) : 0;
+            int ne = ray.hit ? brick_stream(&vol, brick_lo + 3 * r, brick_hi + 3 * r, owner, owner ? ranks[r] : 0,
+                                            &ray, tf, entries, step, e, cap, &contig, NULL) : 0;
             if (!ray.hit) contig = 1;
             double g, mg = INFINITY;
             orc_segrun R;
@@ -831,7 +841,7 @@ int orc_stream(const void *vol_data, int vol_dtype, const int32_t *n, const int3
     if (!r.hit) return 0;
     orc_elem *e = (orc_elem *)malloc(sizeof(orc_elem) * (size_t)cap);
     int contig;
-    int ne = brick_stream(&vol, lo, hi, &r, tf, entries, step, e, cap, &contig, a32);
+    int ne = brick_stream(&vol, lo, hi, NULL, 0, &r, tf, entries, step, e, cap, &contig, a32);
     for (int i = 0; i < ne; ++i) {
         elems[6 * i] = e[i].f;
         elems[6 * i + 1] = e[i].b;
@@ -901,7 +911,7 @@ int orc_features(const void *vol_data, int vol_dtype, const int32_t *n,
             int pix = pixels ? pixels[q] : (int)q;
             orc_ray ray = make_ray(cam, pix % cam->width, pix / cam->width);
             int contig = 1;
-            int ne = ray.hit ? brick_stream(&vol, brick_lo + 3 * r, brick_hi + 3 * r, &ray, tf, entries,
+            int ne = ray.hit ? brick_stream(&vol, brick_lo + 3 * r, brick_hi + 3 * r, NULL, 0, &ray, tf, entries,
                                             step, e, cap, &contig, a32) : 0;
             int bins[64];
             memset(bins, 0, sizeof bins);
@@ -949,7 +959,7 @@ int orc_count_at(const void *vol_data, int vol_dtype, const int32_t *n,
             int pix = pixels ? pixels[q] : (int)q;
             orc_ray ray = make_ray(cam, pix % cam->width, pix / cam->width);
             int contig = 1;
-            int ne = ray.hit ? brick_stream(&vol, brick_lo + 3 * r, brick_hi + 3 * r, &ray, tf, entries,
+            int ne = ray.hit ? brick_stream(&vol, brick_lo + 3 * r, brick_hi + 3 * r, NULL, 0, &ray, tf, entries,
                                             step, e, cap, &contig, NULL) : 0;
             size_t o = (size_t)r * npix + q;
             orc_segrun R = { gamma[o], 0, 0, ref, limit, NULL, 0, 0, 0.0 };
