@@ -91,13 +91,24 @@ typedef struct {
  * data covers the global box [data_lo, data_lo + data_dim), x fastest.  The
  * data box must contain [lo-1, hi+1) clipped to the volume, so that samples
  * the brick owns reconstruct exactly as on the whole volume.  A data box must
- * hold less than 4 GiB (else VDI_E_UNSUPPORTED: split into more bricks). */
+ * hold less than 4 GiB (else VDI_E_UNSUPPORTED: split into more bricks).
+ * Arbitrary, possibly non-convex domains (Sec. 5.3): with `owner` set (a
+ * DEVICE array of one byte per voxel of the whole volume, x fastest), the
+ * brick owns only the voxels of [lo, hi) where owner == rank, so [lo, hi)
+ * is the bounding box of its domain.  A ray may then leave the domain and
+ * enter it again; every supersegment ends where the ray leaves.  Owner maps
+ * need a bisection threshold mode (FIXED and LEARNED return
+ * VDI_E_UNSUPPORTED), and a ray entering a domain more often than N times
+ * keeps its first N supersegments (device status flag 4).  owner = NULL:
+ * the box alone decides. */
 typedef struct {
     const void *data;
     int32_t dtype;           /* vdi_dtype */
     int32_t full_dim[3];     /* global nx, ny, nz */
     int32_t lo[3], hi[3];
     int32_t data_lo[3], data_dim[3];
+    const uint8_t *owner;    /* optional rank per voxel [nz][ny][nx] */
+    int32_t rank;            /* this brick's rank in owner */
 } vdi_brick_t;
 
 /* Shared camera (Sec. 5.1: every brick casts the same rays).  For pixel

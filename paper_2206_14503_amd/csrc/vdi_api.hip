@@ -113,6 +113,8 @@ static GenBricks make_bricks(const vdi_brick_t* bricks, vdi_t* out, int r0, int 
         const vdi_brick_t& b = bricks[r0 + i];
         GenBrick& g = B.b[i];
         g.data = b.data;
+        g.owner = b.owner;
+        g.rank = b.rank;
         if (out) {
             vdi_t& o = out[r0 + i];
             g.color = (float4*)o.color;
@@ -323,6 +325,9 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
         const vdi_brick_t& b = bricks[r];
         if (!b.data) return fail(VDI_E_INVALID, "brick %d: data is NULL", r);
         if (b.dtype != dtype) return fail(VDI_E_INVALID, "bricks must share one dtype");
+        if (b.owner && (b.rank < 0 || b.rank > 255)) return fail(VDI_E_INVALID, "brick %d: rank must be 0..255", r);
+        if (b.owner && tau->mode != VDI_TAU_BISECT && tau->mode != VDI_TAU_BISECT_SEQ)
+            return fail(VDI_E_UNSUPPORTED, "brick %d: owner maps need a bisection threshold mode", r);
         for (int a = 0; a < 3; ++a) {
             if (b.full_dim[a] != bricks[0].full_dim[a] || b.full_dim[a] < 1)
                 return fail(VDI_E_INVALID, "brick %d: full_dim mismatch", r);
@@ -386,6 +391,8 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
             vdi_t& o = out[r0 + i];
             GenBrick& g = B.b[i];
             g.data = b.data;
+            g.owner = b.owner;
+            g.rank = b.rank;
             g.color = (float4*)o.color;
             g.depth = (float2*)o.depth;
             g.count = o.count;
@@ -563,6 +570,7 @@ vdi_status vdi_tau_features(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, cons
     for (int r = 0; r < k; ++r) {
         const vdi_brick_t& b = bricks[r];
         if (!b.data || b.dtype != dtype) return fail(VDI_E_INVALID, "brick %d: data/dtype", r);
+        if (b.owner) return fail(VDI_E_UNSUPPORTED, "brick %d: owner maps are not supported by the learned path", r);
         for (int a = 0; a < 3; ++a) {
             int n = b.full_dim[a];
             if (n != bricks[0].full_dim[a] || b.lo[a] < 0 || b.hi[a] > n || b.lo[a] >= b.hi[a])

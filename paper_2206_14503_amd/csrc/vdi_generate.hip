@@ -171,7 +171,7 @@ __device__ inline void gen_step(GenSeg& S, int& count, const GenOut& o, const Ra
 // Returns the supersegment count.  With EARLY the pass stops as soon as the
 // count exceeds `limit` (its outcome "more than limit" is then decided).
 // cap > 0 saturates after cap-1 closes (fixed-threshold mode).
-template <typename VT, bool WRITE, bool EARLY = !WRITE>
+template <typename VT, bool WRITE, bool EARLY = !WRITE, bool MASK = false>
 __device__ int gen_pass(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0,
                         int k1, const TfCell* tf, int entries, float gamma, int cap, int limit, const GenOut& o,
                         int* n_opaque_out)
@@ -182,6 +182,11 @@ __device__ int gen_pass(const VT* data, const BrickGeo& g, const Ray& r, float s
     int count = 0, n_opaque = 0;
     const bool unit = (l_step == 1.0f);
     for_samples<VT>(data, g, r, step, k0, k1, [&](int k, float v) {
+        if (MASK && g.own && !owns_sample(g, r, step, k)) {
+            // the ray is outside the domain: an open supersegment ends here
+            if (S.open) gen_close<WRITE>(S, count, o, r, step, l_step);
+            return !(EARLY && count > limit);
+        }
         const GenSample q = gen_prep(tf_lookup(tf, entries, v), l_step, unit);
         n_opaque += q.transparent ? 0 : 1;
         gen_step<WRITE>(S, count, o, r, step, l_step, g2, cap, k, q);
@@ -199,7 +204,7 @@ __device__ int gen_pass(const VT* data, const BrickGeo& g, const Ray& r, float s
 // non-transparent samples seen (complete only if the scan ran to the end).
 // kspan (optional) receives the first non-transparent sample seen, one past
 // the last one, and whether the scan ran to k1 (1) or stopped early (0).
-template <typename VT, int NC>
+template <typename VT, int NC, bool MASK = false>
 __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int k0, int k1,
                          const TfCell* tf, int entries, const float* gam, int limit, int* counts, int* n_opaque_out,
                          int* kspan = nullptr)
@@ -219,6 +224,17 @@ __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float 
     int kf = k1, ke = k0, kdone = k0;
     // many states: two stencil slots, to keep the states in registers
     for_samples<VT, (NC >= 6 ? 2 : 3)>(data, g, r, step, k0, k1, [&](int k, float v) {
+        if (MASK && g.own && !owns_sample(g, r, step, k)) {
+            // outside the domain: every open supersegment ends here
+            bool live = false;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                if (S[j].open) gen_close<false>(S[j], cnt[j], none, r, step, l_step);
+                live |= cnt[j] <= limit;
+            }
+            if (kspan) kdone = k + 1;
+            return live;
+        }
         const GenSample q = gen_prep(tf_lookup(tf, entries, v), l_step, unit);
         n_opaque += q.transparent ? 0 : 1;
         if (kspan) {
@@ -258,7 +274,7 @@ constexpr int kGeoLevels = 6;
 // to (and including) the first infeasible one.  The remaining levels run two
 // per scan (the midpoint m and both next-level midpoints).  Both reproduce
 // the sequential decisions exactly.
-template <typename VT>
+template <typename VT, bool MASK = false>
 __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step, int& k0,
                            int& k1, const TfCell* tf, int entries, const GenParams& P, float& gamma_out,
                            int& count_out, bool need_count)
@@ -266,7 +282,7 @@ __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, co
     GenOut none{nullptr, nullptr, 0, 0, 0};
     if (P.mode == VDI_TAU_FIXED) {
         gamma_out = P.tau;
-        count_out = need_count ? gen_pass<VT, false>(data, g, r, step, l_step, k0, k1, tf, entries, P.tau,
+        count_out = need_count ? gen_pass<VT, false, true, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, P.tau,
                                                      P.max_n, 1 << 30, none, nullptr)
                                : -1;
         return;
@@ -279,7 +295,7 @@ __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, co
         for (; level < P.iters; ++level) {
             float m = 0.5f * (lo + hi);
             int c1[1];
-            gen_scan<VT, 1>(data, g, r, step, l_step, k0, k1, tf, entries, &m, P.max_n, c1, nullptr);
+            gen_scan<VT, 1, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, &m, P.max_n, c1, nullptr);
             if (c1[0] <= P.max_n) {
                 hi = m;
                 hi_count = c1[0];
@@ -294,7 +310,7 @@ __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, co
         for (int l = 0; l < kGeoLevels; ++l) gg[l] = ldexpf(P.gmax, -(l + 1));
         int n_opaque = 0;
         int ks[3];
-        gen_scan<VT, kGeoLevels>(data, g, r, step, l_step, k0, k1, tf, entries, gg, P.max_n, cg, &n_opaque, ks);
+        gen_scan<VT, kGeoLevels, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, gg, P.max_n, cg, &n_opaque, ks);
         // later passes (and the caller's write) cover [first non-transparent
         // sample, one past the last): before it every state stays closed and
         // untouched, after it neither the count nor the stored lists change
@@ -310,7 +326,7 @@ __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, co
             gamma_out = ldexpf(P.gmax, -P.iters);
             count_out = -1;
             if (need_count)
-                count_out = gen_pass<VT, false>(data, g, r, step, l_step, k0, k1, tf, entries, gamma_out, 0, 1 << 30,
+                count_out = gen_pass<VT, false, true, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, gamma_out, 0, 1 << 30,
                                                 none, nullptr);
             return;
         }
@@ -332,7 +348,7 @@ __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, co
         if (level + 2 <= P.iters) {
             float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
             int c3[3];
-            gen_scan<VT, 3>(data, g, r, step, l_step, k0, k1, tf, entries, g3, P.max_n, c3, nullptr);
+            gen_scan<VT, 3, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, g3, P.max_n, c3, nullptr);
             if (c3[0] <= P.max_n) {
                 hi = m;
                 hi_count = c3[0];
@@ -354,7 +370,7 @@ __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, co
             level += 2;
         } else {
             int c1[1];
-            gen_scan<VT, 1>(data, g, r, step, l_step, k0, k1, tf, entries, &m, P.max_n, c1, nullptr);
+            gen_scan<VT, 1, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, &m, P.max_n, c1, nullptr);
             if (c1[0] <= P.max_n) {
                 hi = m;
                 hi_count = c1[0];
@@ -366,13 +382,13 @@ __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, co
     }
     gamma_out = hi;
     if (need_count && hi_count < 0)
-        hi_count = gen_pass<VT, false>(data, g, r, step, l_step, k0, k1, tf, entries, hi, 0, 1 << 30, none,
+        hi_count = gen_pass<VT, false, true, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, hi, 0, 1 << 30, none,
                                        nullptr);
     count_out = hi_count;
 }
 
 // kind: 0 = search + regular write, 1 = search only (count + gamma), 2 = compact write
-template <typename VT, int KIND>
+template <typename VT, int KIND, bool MASK>
 __global__ __launch_bounds__(256) void gen_kernel(GenParams P, GenBricks B)
 {
     extern __shared__ TfCell tf_s[];   // P.tf_entries - 1 cells, sized at launch
@@ -387,7 +403,11 @@ __global__ __launch_bounds__(256) void gen_kernel(GenParams P, GenBricks B)
     const uint32_t pix = (uint32_t)y * (uint32_t)P.cam.width + (uint32_t)x;
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
 
-    const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
+    BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
+    if (MASK) {
+        g.own = br.owner;
+        g.rank = br.rank;
+    }
     const VT* data = (const VT*)br.data;
     Ray r = make_ray(P.cam, x, y);
     int ns = ray_samples(r, P.step);
@@ -398,7 +418,12 @@ __global__ __launch_bounds__(256) void gen_kernel(GenParams P, GenBricks B)
     if (KIND == 1) {
         float gm = empty_gamma;
         int c = 0;
-        if (k1 > k0) gen_search<VT>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, P, gm, c, true);
+        if (k1 > k0) gen_search<VT, MASK>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, P, gm, c, true);
+        if (MASK && c > P.max_n) {
+            // more domain entries than N: the list keeps the first N
+            atomicOr(P.status, 4);
+            c = P.max_n;
+        }
         br.count[pix] = c;
         br.gamma[pix] = gm;
         return;
@@ -413,7 +438,7 @@ __global__ __launch_bounds__(256) void gen_kernel(GenParams P, GenBricks B)
         GenOut o{br.color, br.depth, off, 1, lim};
         if (c > 0 && lim > 0) {
             int cap = P.mode == VDI_TAU_FIXED ? P.max_n : 0;
-            gen_pass<VT, true>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, cap, 1 << 30, o,
+            gen_pass<VT, true, false, MASK>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, cap, 1 << 30, o,
                                nullptr);
         }
         return;
@@ -423,9 +448,9 @@ __global__ __launch_bounds__(256) void gen_kernel(GenParams P, GenBricks B)
     int c = 0;
     GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
     if (k1 > k0) {
-        gen_search<VT>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, P, gm, c, false);
+        gen_search<VT, MASK>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, P, gm, c, false);
         int cap = P.mode == VDI_TAU_FIXED ? P.max_n : 0;
-        c = gen_pass<VT, true>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, cap, 1 << 30, o,
+        c = gen_pass<VT, true, false, MASK>(data, g, r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, cap, 1 << 30, o,
                                nullptr);
     }
     for (int j = c; j < P.max_n; ++j) {
@@ -433,6 +458,8 @@ __global__ __launch_bounds__(256) void gen_kernel(GenParams P, GenBricks B)
         br.color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         br.depth[slot] = make_float2(0.0f, 0.0f);
     }
+    // more domain entries than N (owner maps): the list keeps the first N
+    if (MASK && c > P.max_n) atomicOr(P.status, 4);
     br.count[pix] = c < P.max_n ? c : P.max_n;
     if (br.gamma) br.gamma[pix] = gm;
 }
@@ -459,9 +486,18 @@ template <typename VT>
 static void launch_gen(int kind, const GenParams& P, const GenBricks& B, int nb, hipStream_t s)
 {
     dim3 grid((P.cam.width + 15) / 16, (P.cam.height + 15) / 16, nb);
-    if (kind == 0) hipLaunchKernelGGL((gen_kernel<VT, 0>), grid, dim3(256), tf_lds<VT>(P, B, nb), s, P, B);
-    if (kind == 1) hipLaunchKernelGGL((gen_kernel<VT, 1>), grid, dim3(256), tf_lds<VT>(P, B, nb), s, P, B);
-    if (kind == 2) hipLaunchKernelGGL((gen_kernel<VT, 2>), grid, dim3(256), tf_lds<VT>(P, B, nb), s, P, B);
+    bool mask = false;
+    for (int i = 0; i < nb; ++i) mask |= B.b[i].owner != nullptr;
+    const size_t lds = tf_lds<VT>(P, B, nb);
+    if (mask) {
+        if (kind == 0) hipLaunchKernelGGL((gen_kernel<VT, 0, true>), grid, dim3(256), lds, s, P, B);
+        if (kind == 1) hipLaunchKernelGGL((gen_kernel<VT, 1, true>), grid, dim3(256), lds, s, P, B);
+        if (kind == 2) hipLaunchKernelGGL((gen_kernel<VT, 2, true>), grid, dim3(256), lds, s, P, B);
+        return;
+    }
+    if (kind == 0) hipLaunchKernelGGL((gen_kernel<VT, 0, false>), grid, dim3(256), lds, s, P, B);
+    if (kind == 1) hipLaunchKernelGGL((gen_kernel<VT, 1, false>), grid, dim3(256), lds, s, P, B);
+    if (kind == 2) hipLaunchKernelGGL((gen_kernel<VT, 2, false>), grid, dim3(256), lds, s, P, B);
 }
 
 void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B, int nb, hipStream_t s)

@@ -263,6 +263,9 @@ struct BrickGeo {
     uint32_t sx2;   // 1 if the x extent allows paired loads (ddim[0] >= 2)
     int xmax;       // ddim[0] - 2: last x of a paired load
     uint32_t sy, sz;  // element strides of y and z
+    const uint8_t* own;  // optional rank per voxel of the whole volume (non-convex domains)
+    int rank;
+    int vn[3];           // global volume dims (voxel index of a sample)
 };
 
 // Geometry of a brick whose data box starts at global voxel dlo with extent
@@ -281,7 +284,22 @@ __device__ inline BrickGeo make_geo(const int n[3], const int dlo[3], const int 
     g.xmax = ddim[0] - 2;
     g.sy = (uint32_t)ddim[0];
     g.sz = (uint32_t)ddim[0] * (uint32_t)ddim[1];
+    g.own = nullptr;
+    g.rank = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) g.vn[a] = n[a];
     return g;
+}
+
+// Whether the brick's owner map gives sample k of ray r to it (the voxel of
+// the sample point decides, as for box ownership).
+__device__ inline bool owns_sample(const BrickGeo& g, const Ray& r, float step, int k)
+{
+    const float t = sample_t(r, k, step);
+    const int vx = voxel_of(sample_coord(r, t, 0), g.vn[0]);
+    const int vy = voxel_of(sample_coord(r, t, 1), g.vn[1]);
+    const int vz = voxel_of(sample_coord(r, t, 2), g.vn[2]);
+    return g.own[((size_t)vz * (size_t)g.vn[1] + (size_t)vy) * (size_t)g.vn[0] + (size_t)vx] == (uint8_t)g.rank;
 }
 
 // Two x-adjacent voxels (p[0], p[1]) with one load (4-byte or 2-byte

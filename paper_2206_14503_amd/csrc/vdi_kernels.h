@@ -32,6 +32,8 @@ struct GenBrick {
     int* count;
     float* gamma;
     const uint32_t* offset;
+    const uint8_t* owner;     // optional rank per voxel of the whole volume
+    int rank;
     uint64_t capacity;
     int lo[3], hi[3];
     int dlo[3], ddim[3];

@@ -43,7 +43,7 @@ class vdi_t(ctypes.Structure):
 class vdi_brick_t(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("full_dim", ctypes.c_int32 * 3),
                 ("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3), ("data_lo", ctypes.c_int32 * 3),
-                ("data_dim", ctypes.c_int32 * 3)]
+                ("data_dim", ctypes.c_int32 * 3), ("owner", ctypes.c_void_p), ("rank", ctypes.c_int32)]
 
 
 class vdi_camera_t(ctypes.Structure):
@@ -205,25 +205,36 @@ class DeviceBrick:
     hi: Sequence[int]
     data_lo: Sequence[int]
     full_dim: Sequence[int]
+    owner: Optional[torch.Tensor] = None   # [nz, ny, nx] uint8 rank per voxel (non-convex domains)
+    rank: int = 0
 
     def c(self) -> vdi_brick_t:
         dz, dy, dx = self.data.shape
         dt = F16 if self.data.dtype == torch.float16 else F32
         i3 = lambda v: (ctypes.c_int32 * 3)(*[int(x) for x in v])
         return vdi_brick_t(_ptr(self.data), dt, i3(self.full_dim), i3(self.lo), i3(self.hi), i3(self.data_lo),
-                           i3((dx, dy, dz)))
+                           i3((dx, dy, dz)), _ptr(self.owner), int(self.rank))
 
 
-def device_bricks(vol, bricks, device=None) -> List[DeviceBrick]:
-    """Copy each brick's halo'd block of a [nz, ny, nx] volume (numpy or torch) to the device."""
+def device_bricks(vol, bricks, device=None, owner=None, ranks=None) -> List[DeviceBrick]:
+    """Copy each brick's halo'd block of a [nz, ny, nx] volume (numpy or torch) to
+    the device.  owner: optional [nz, ny, nx] uint8 rank per voxel (copied once
+    to the device) with ranks[r] brick r's rank (non-convex domains)."""
     import numpy as np
     dev = device or torch.device("cuda", torch.cuda.current_device())
     nz, ny, nx = vol.shape
+    own = None
+    if owner is not None:
+        own = torch.from_numpy(np.ascontiguousarray(owner, dtype=np.uint8)) if isinstance(owner, np.ndarray) \
+            else owner.to(torch.uint8)
+        own = own.to(dev).contiguous()
+        assert tuple(own.shape) == (nz, ny, nx) and ranks is not None and len(ranks) == len(bricks)
     out = []
-    for b in bricks:
+    for i, b in enumerate(bricks):
         blk = vol[b.data_lo[2]:b.data_hi[2], b.data_lo[1]:b.data_hi[1], b.data_lo[0]:b.data_hi[0]]
         t = torch.from_numpy(np.ascontiguousarray(blk)) if isinstance(blk, np.ndarray) else blk
-        out.append(DeviceBrick(t.to(dev).contiguous(), b.lo, b.hi, b.data_lo, (nx, ny, nz)))
+        out.append(DeviceBrick(t.to(dev).contiguous(), b.lo, b.hi, b.data_lo, (nx, ny, nz), own,
+                               int(ranks[i]) if own is not None else 0))
     return out
 
 
