@@ -7,6 +7,8 @@ one), composite them into one N=20 VDI and render it from the original view.  Th
 second of that step.  Further legs (same JSON line):
   novel    -- that composited VDI rendered at 5, 20 and 50 degrees from its
               viewpoint: time per frame, SSIM and PSNR against DVR there;
+  masks    -- the FHD volume on 8 non-convex domains (wavy z-slabs, owner map):
+              generate + composite, rendering checked against the slab one;
   large    -- 1024^3 fp16 volume in 16 bricks (4x2x2): generate + composite,
               and the composite alone on maximally interleaved dense lists
               (16 x 20 supersegments per pixel, 16.6 GB of input);
@@ -18,7 +20,7 @@ second of that step.  Further legs (same JSON line):
               replayed from a hipGraph: jobs/s and per-job latency.
 Printed: ONE JSON line on stdout (progress goes to stderr).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--legs fhd,novel,large,learned,batched]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--legs fhd,novel,masks,large,learned,batched]
 """
 from __future__ import annotations
 
@@ -204,6 +206,44 @@ def leg_fhd(args, result):
                           "traffic": traffic, "traffic_note": why, "algorithmic_bytes": cbytes,
                           "workload": w.name}
     return dict(w=w, vol=vol, bricks=bricks, tf=tf, cam=cam, step_len=step_len, dbr=dbr, tf_d=tf_d, out=out)
+
+
+# ---------------------------------------------------------------- non-convex domains
+
+def leg_masks(args, result, fhd):
+    """The FHD volume on 8 non-convex domains (z-slabs with wavy interfaces,
+    Sec. 5.3): generation through the owner map, compositing (interleaved
+    lists take the general merge) and the original-view rendering, which must
+    equal the slab decomposition's (both are DVR of the same samples)."""
+    import numpy as np
+    import torch
+    from paper_2206_14503_amd import synth, vdi
+
+    w, cam, step_len, tf_d, v0 = fhd["w"], fhd["cam"], fhd["step_len"], fhd["tf_d"], fhd["out"]
+    owner, bricks, ranks = synth.wavy_slab_owner(w.n, 8, 16, w.seed)
+    dbr = vdi.device_bricks(fhd["vol"], bricks, owner=owner, ranks=ranks)
+    P = cam.width * cam.height
+    subs = [vdi.VDI.empty(cam.width, cam.height, w.max_n, step_len) for _ in bricks]
+    out = vdi.VDI.empty(cam.width, cam.height, w.max_n, step_len, vdi.REGULAR)
+    gen = lambda: vdi.generate(dbr, cam, tf_d, step_len, step_len, vdi.BISECT, 0.0, w.max_n, w.iters, outs=subs)
+    comp = lambda: vdi.composite(subs, vdi.BISECT, 0.0, w.max_n, w.iters, out=out)
+    gen()
+    comp()
+    torch.cuda.synchronize()
+    flags = vdi.device_status()
+    gen_ms = float(timed_ms(gen, 5).mean())
+    comp_ms = float(timed_ms(comp, 5).mean())
+    img = vdi.render_original_view(out)
+    ref = vdi.render_original_view(v0)
+    err = float((img - ref).abs().max())
+    torch.cuda.synchronize()
+    log(f"[bench] non-convex: generate {gen_ms:.3f} ms, composite {comp_ms:.3f} ms; "
+        f"max |render - slab render| {err:.2g}; device flags {flags}")
+    result["non_convex"] = {"workload": f"{w.name} volume on 8 wavy z-slab domains (interfaces displaced up to 32 "
+                                        f"voxels)", "generate_ms": gen_ms, "composite_ms": comp_ms,
+                            "pixels_per_s": P / ((gen_ms + comp_ms) / 1e3), "render_vs_slabs_max_abs": err,
+                            "device_flags": flags}
+    del dbr, subs, out
 
 
 # ---------------------------------------------------------------- novel viewpoints
@@ -467,7 +507,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--layout", choices=["compact", "regular"], default="regular")
-    ap.add_argument("--legs", default="fhd,novel,large,learned,batched")
+    ap.add_argument("--legs", default="fhd,novel,masks,large,learned,batched")
     ap.add_argument("--learn-seeds", type=int, default=32)
     ap.add_argument("--learn-epochs", type=int, default=8)
     ap.add_argument("--no-learn-fhd", dest="learn_fhd", action="store_false",
@@ -497,6 +537,8 @@ def main():
     fhd = leg_fhd(args, result)
     if "novel" in legs:
         leg_novel(args, result, fhd)
+    if "masks" in legs:
+        leg_masks(args, result, fhd)
     if "large" in legs:
         leg_large(args, result)
     elif "dense" in legs:

@@ -190,6 +190,36 @@ def brick_grid(n: Sequence[int], grid: Sequence[int], halo: int = 1) -> List[Bri
     return out
 
 
+def wavy_slab_owner(n: int, slabs: int, amplitude: int, seed: int):
+    """Non-convex decomposition of an n^3 volume into `slabs` z-slabs whose
+    interfaces are displaced per (x, y) column by a smooth seeded wave of up
+    to `amplitude` voxels (as the domains of a simulation that moves its
+    interfaces), and each domain's bricks: the bounding box of its voxels with
+    a one-voxel halo.  Returns (owner [n, n, n] uint8 (z, y, x), bricks, ranks)."""
+    rng = np.random.default_rng(seed)
+    x = (np.arange(n) + 0.5) / n
+    cuts = []
+    for i in range(1, slabs):
+        a = rng.uniform(0.5, 1.0, 2) * amplitude
+        f = rng.uniform(1.0, 3.0, 2)
+        ph = rng.uniform(0.0, 2.0 * math.pi, 2)
+        wave = (a[0] * np.sin(2 * math.pi * f[0] * x[None, :] + ph[0]) +
+                a[1] * np.sin(2 * math.pi * f[1] * x[:, None] + ph[1]))   # [y, x]
+        cuts.append(np.clip(np.round(n * i / slabs + wave), 1, n - 1).astype(np.int64))
+    z = np.arange(n)[:, None, None]
+    owner = np.zeros((n, n, n), np.uint8)
+    for c in cuts:
+        owner += (z >= c[None, :, :]).astype(np.uint8)
+    bricks = []
+    for r in range(slabs):
+        zs = np.nonzero((owner == r).any(axis=(1, 2)))[0]
+        lo, hi = (0, 0, int(zs.min())), (n, n, int(zs.max()) + 1)
+        dlo = tuple(max(l - 1, 0) for l in lo)
+        dhi = tuple(min(h + 1, n) for h in hi)
+        bricks.append(Brick(lo, hi, dlo, dhi))
+    return owner, bricks, list(range(slabs))
+
+
 def brick_data(vol, b: Brick):
     """The halo'd block of `vol` ([z, y, x]) a brick holds, as a contiguous copy."""
     blk = vol[b.data_lo[2]:b.data_hi[2], b.data_lo[1]:b.data_hi[1], b.data_lo[0]:b.data_hi[0]]
