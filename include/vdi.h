@@ -349,8 +349,10 @@ vdi_status vdi_autotune(vdi_ctx *ctx, const vdi_job_t *jobs, int n_jobs, const c
 /* Device-side status of the context since the last call to this function
  * (synchronises `stream` first): bit 0 = a compact output overflowed its
  * capacity, bit 1 = a composite input list was invalid (count outside
- * [0, max_n], f >= b, or fronts not sorted; such pixels are written empty).
- * Clears the flags. */
+ * [0, max_n], f >= b, or fronts not sorted; such pixels are written empty;
+ * also a list the novel-view rendering read as empty), bit 2 = a ray entered
+ * a brick's owner-map domain more often than N times (its list keeps the
+ * first N supersegments).  Clears the flags. */
 vdi_status vdi_ctx_device_status(vdi_ctx *ctx, int32_t *flags, void *stream);
 
 /* Diagnostic: the fp32 ray of each pixel as the kernels compute it.
