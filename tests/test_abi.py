@@ -28,7 +28,7 @@ def V():
 def test_header_declares_the_hot_path():
     names = _declared_functions()
     for must in ("vdi_generate", "vdi_composite", "vdi_render_original_view", "vdi_batch_create", "vdi_autotune",
-                 "vdi_mlp_forward", "vdi_mlp_backward", "vdi_mlp_adam", "vdi_tau_features"):
+                 "vdi_mlp_forward", "vdi_mlp_backward", "vdi_mlp_adam", "vdi_tau_features", "vdi_render_novel_view"):
         assert must in names
     assert len(names) >= 20
 
@@ -77,6 +77,7 @@ def test_null_arguments_rejected_on_the_host(V):
     assert b"NULL" in L.vdi_last_error()
     assert L.vdi_composite(None, None, 1, None, None, None) == E_INVALID
     assert L.vdi_render_original_view(None, None, None, None) == E_INVALID
+    assert L.vdi_render_novel_view(None, None, None, None, ctypes.c_float(1.0), None, None) == E_INVALID
     assert L.vdi_learned_stats(None, None, None) == E_INVALID
     out = ctypes.c_void_p()
     assert L.vdi_batch_create(None, None, 1, None, ctypes.byref(out)) == E_INVALID
