@@ -54,14 +54,17 @@ def test_box_partition_as_owner_map_is_the_box_path(V):
             assert torch.equal(getattr(x, t), getattr(y, t)), t
 
 
-@pytest.mark.parametrize("block,ranks,seed,mode", [(8, 2, None, 1), (6, 3, 11, 1), (8, 4, 12, 3)],
-                         ids=["checker8-2ranks", "random6-3ranks", "random8-4ranks-seq"])
-def test_non_convex_generate_parity(V, orc, block, ranks, seed, mode):
+@pytest.mark.parametrize("block,ranks,seed,mode,dtype", [(8, 2, None, 1, "f32"), (6, 3, 11, 1, "f32"),
+                                                         (8, 4, 12, 3, "f32"), (5, 2, 14, 1, "f16")],
+                         ids=["checker8-2ranks", "random6-3ranks", "random8-4ranks-seq", "random5-2ranks-f16"])
+def test_non_convex_generate_parity(V, orc, block, ranks, seed, mode, dtype):
     """Each rank's sub-VDI against the oracle (mode 3: one midpoint per pass,
     the oracle's bisection as is)."""
     import torch
     n = 64
     vol = synth.gaussian_volume(n, 12, 1)
+    if dtype == "f16":
+        vol = vol.astype(np.float16)
     tf = synth.transfer_function()
     tf_d = torch.from_numpy(tf).cuda()
     cam = synth.orbit_camera(10_061, 64, 48)

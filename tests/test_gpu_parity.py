@@ -489,7 +489,8 @@ def _oracle_composited(orc, cam, seed=0):
     (synth.orbit_camera(10_041, 64, 48), synth.orbit_camera(10_041, 64, 48), 1 / 64),
     (synth.orbit_camera(10_042, 48, 48), synth.orbit_camera(10_042, 40, 30, turn_deg=50.0), 1 / 48),
     (synth.ortho_camera(64, 64, "+z"), synth.orbit_camera(10_043, 50, 38), 1 / 80),
-], ids=["persp-10deg", "persp-own-view", "persp-50deg-coarse-ragged", "ortho-vdi-fine"])
+    (synth.orbit_camera(10_046, 64, 48), synth.ortho_camera(40, 40, "-z"), 1 / 64),
+], ids=["persp-10deg", "persp-own-view", "persp-50deg-coarse-ragged", "ortho-vdi-fine", "persp-vdi-ortho-view"])
 def test_render_novel_view_parity(V, orc, vcam, view, step):
     """A composited VDI (the oracle's, uploaded) rendered from another
     viewpoint: the pixel and supersegment of every sample are fp64 decisions
