@@ -658,7 +658,7 @@ int orc_render_ov(const float *color, const float *depth, const int32_t *count, 
  * a fixed operation order, no fused operations. */
 typedef struct {
     double e[3], f[3], r[3], u[3];
-    double ff, rr, uu;
+    double ff, irr, iuu;     /* |fwd|^2, 1/|right|^2, 1/|up|^2 */
     int ortho, W, H;
 } orc_proj;
 
@@ -674,8 +674,8 @@ static orc_proj make_proj(const orc_camera *c)
         P.u[a] = c->up[a];
     }
     P.ff = dot3(P.f, P.f);
-    P.rr = dot3(P.r, P.r);
-    P.uu = dot3(P.u, P.u);
+    P.irr = 1.0 / dot3(P.r, P.r);
+    P.iuu = 1.0 / dot3(P.u, P.u);
     P.ortho = c->ortho;
     P.W = c->width;
     P.H = c->height;
@@ -693,13 +693,14 @@ static int project(const orc_proj *P, const float p[3], int *q, double *depth)
     const double vf = dot3(v, P->f), vr = dot3(v, P->r), vu = dot3(v, P->u);
     double sx, sy;
     if (P->ortho) {
-        sx = vr / P->rr;
-        sy = vu / P->uu;
+        sx = vr * P->irr;
+        sy = vu * P->iuu;
         *depth = vf;
     } else {
         if (!(vf > 0.0)) return 0;
-        sx = (vr * P->ff) / (vf * P->rr);
-        sy = (vu * P->ff) / (vf * P->uu);
+        const double w = P->ff / vf;
+        sx = (vr * w) * P->irr;
+        sy = (vu * w) * P->iuu;
         *depth = dot3(v, v);
     }
     const double fx = floor(((sx + 1.0) * 0.5) * (double)P->W);

@@ -24,7 +24,7 @@ namespace {
 
 struct Proj {
     double e[3], f[3], r[3], u[3];
-    double ff, rr, uu;
+    double ff, irr, iuu;   // |fwd|^2, 1/|right|^2, 1/|up|^2
     int ortho, W, H;
 };
 
@@ -45,8 +45,8 @@ __device__ inline Proj make_proj(const Cam& c)
         P.u[a] = c.up[a];
     }
     P.ff = dot3d(P.f, P.f);
-    P.rr = dot3d(P.r, P.r);
-    P.uu = dot3d(P.u, P.u);
+    P.irr = 1.0 / dot3d(P.r, P.r);
+    P.iuu = 1.0 / dot3d(P.u, P.u);
     P.ortho = c.ortho;
     P.W = c.width;
     P.H = c.height;
@@ -65,13 +65,14 @@ __device__ inline bool project(const Proj& P, const float p[3], int& q, double& 
     const double vf = dot3d(v, P.f), vr = dot3d(v, P.r), vu = dot3d(v, P.u);
     double sx, sy;
     if (P.ortho) {
-        sx = vr / P.rr;
-        sy = vu / P.uu;
+        sx = vr * P.irr;
+        sy = vu * P.iuu;
         depth = vf;
     } else {
         if (!(vf > 0.0)) return false;
-        sx = (vr * P.ff) / (vf * P.rr);
-        sy = (vu * P.ff) / (vf * P.uu);
+        const double w = P.ff / vf;
+        sx = (vr * w) * P.irr;
+        sy = (vu * w) * P.iuu;
         depth = dot3d(v, v);
     }
     const double fx = floor(((sx + 1.0) * 0.5) * (double)P.W);
