@@ -67,3 +67,20 @@ def test_non_convex_domains_composite_to_dvr(orc, block, ranks, seed):
     ref = orc.dvr(vol, cam, tf, 1 / n, 1 / n)
     assert (ref[:, 3] > 0.05).sum() > 100
     assert np.abs(img - ref).max() <= 1e-6
+
+
+def test_wavy_slab_domains_partition_the_volume():
+    """The non-convex workload's domains: every voxel has one rank, each
+    brick's box bounds its domain, its data box adds the one-voxel halo, and
+    the interfaces are not planes (the domains are not boxes)."""
+    n = 48
+    owner, bricks, ranks = synth.wavy_slab_owner(n, 4, 6, 3)
+    assert owner.shape == (n, n, n) and owner.dtype == np.uint8
+    assert set(np.unique(owner)) == set(ranks)
+    for r, b in zip(ranks, bricks):
+        z, y, x = np.nonzero(owner == r)
+        assert (x.min(), y.min(), z.min()) == tuple(b.lo) and (x.max() + 1, y.max() + 1, z.max() + 1) == tuple(b.hi)
+        assert all(max(l - 1, 0) == dl for l, dl in zip(b.lo, b.data_lo))
+        assert all(min(h + 1, n) == dh for h, dh in zip(b.hi, b.data_hi))
+        box = owner[b.lo[2]:b.hi[2], b.lo[1]:b.hi[1], b.lo[0]:b.hi[0]]
+        assert (box != r).any()
