@@ -47,6 +47,43 @@ def _cam(c) -> Camera:
                   (ctypes.c_float * 3)(*c.right), (ctypes.c_float * 3)(*c.up), int(c.width), int(c.height))
 
 
+# Near-tie band of the Eq. 1 decisions: an fp32 evaluation of the distance
+# may take the other branch where |d - gamma| < TIE * max(1, L / 128), L the
+# open supersegment's element count (see vdi_oracle.c).  Lists whose decisions
+# meet such near ties carry every outcome the near ties admit.
+TIE = 2e-5
+
+
+class Alts(ctypes.Structure):
+    _fields_ = [("ray", ctypes.c_void_p), ("count", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
+                ("color", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("cap", ctypes.c_int32),
+                ("n", ctypes.c_int32)]
+
+
+def _alloc_alts(cap: int, max_n: int):
+    cap = max(int(cap), 1)
+    a = {"ray": np.zeros(cap, np.int32), "count": np.zeros(cap, np.int32), "gamma": np.zeros(cap, np.float32),
+         "color": np.zeros((cap, max_n, 4), np.float32), "depth": np.zeros((cap, max_n, 2), np.float32)}
+    st = Alts(a["ray"].ctypes.data, a["count"].ctypes.data, a["gamma"].ctypes.data, a["color"].ctypes.data,
+              a["depth"].ctypes.data, cap, 0)
+    return a, st
+
+
+def _with_alts(call, rays: int, max_n: int):
+    """Run call(alts_struct) with a buffer for alternative outcomes, growing
+    it when the oracle reports it too small (-3); returns (rc, alts) with the
+    alternatives trimmed to those written."""
+    cap = max(64, rays // 16)
+    while True:
+        a, st = _alloc_alts(cap, max_n)
+        rc = call(ctypes.byref(st))
+        if rc == -3:
+            cap = int(st.n) + 16
+            continue
+        n = min(int(st.n), cap)
+        return rc, {k: v[:n] for k, v in a.items()}
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -57,14 +94,17 @@ def lib():
         i32, f32, f64 = ctypes.c_int32, ctypes.c_float, ctypes.c_double
         L.orc_generate.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_int, ctypes.POINTER(Camera), P, ctypes.c_int,
                                    f32, f32, ctypes.c_int, f32, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
-                                   P, P, P, P, P, P, P, P, ctypes.c_int]
+                                   P, P, P, P, P, P, P, P, f64, P, P, ctypes.c_int]
         L.orc_composite.argtypes = [ctypes.c_int, P, P, P, ctypes.c_int, ctypes.c_int, f32, ctypes.c_int, f32,
-                                    ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, ctypes.c_int]
+                                    ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, f64, P, P, ctypes.c_int]
         L.orc_render_ov.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, f32, P, ctypes.c_int]
         L.orc_dvr.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(Camera), P, ctypes.c_int, f32, f32, P,
                               ctypes.c_int, P, ctypes.c_int]
         L.orc_seg.argtypes = [P, ctypes.c_int, ctypes.c_int, f64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                               ctypes.c_int, f64, P, ctypes.c_int, P, P]
+        L.orc_seg_outcomes.argtypes = [P, ctypes.c_int, ctypes.c_int, f64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       f64, f64, P, P, P, ctypes.c_int]
+        L.orc_seg_outcomes.restype = ctypes.c_int
         L.orc_ray_info.argtypes = [ctypes.POINTER(Camera), ctypes.c_int, f32, P, P, P, P]
         L.orc_stream.argtypes = [P, ctypes.c_int, P, P, P, ctypes.POINTER(Camera), P, ctypes.c_int, f32,
                                  ctypes.c_int, P, ctypes.c_int, P]
@@ -102,11 +142,14 @@ def _dims(vol: np.ndarray) -> np.ndarray:
 def generate(vol: np.ndarray, bricks: Sequence, cam, tf: np.ndarray, step: float, ref: float,
              mode: int, tau: float, max_n: int, iters: int = 10,
              pixels: Optional[np.ndarray] = None, nthreads: int = 0, owner: Optional[np.ndarray] = None,
-             ranks: Optional[Sequence[int]] = None) -> Dict[str, np.ndarray]:
+             ranks: Optional[Sequence[int]] = None, tie: float = TIE) -> Dict[str, np.ndarray]:
     """Generate one regular sub-VDI per brick over `pixels` (default: all).
     owner: optional rank per voxel ([nz, ny, nx] uint8, like the volume) with
     ranks[r] brick r's rank: brick r owns the samples whose voxel lies in its
-    box and carries its rank (non-convex domains; bisection modes only)."""
+    box and carries its rank (non-convex domains; bisection modes only).
+    Besides the fp64 outcome, "nout" [nb, npix] holds each list's number of
+    outcomes under near ties (negative: not all enumerated) and "alts" the
+    others (ray = r * npix + q)."""
     vol, dt = _vol(vol)
     n = _dims(vol)
     nb = len(bricks)
@@ -126,16 +169,19 @@ def generate(vol: np.ndarray, bricks: Sequence, cam, tf: np.ndarray, step: float
         "gamma": np.zeros((nb, npix), np.float32),
         "margin": np.zeros((nb, npix), np.float64),
         "contiguous": np.zeros((nb, npix), np.int32),
+        "nout": np.zeros((nb, npix), np.int32),
     }
     own = None if owner is None else np.ascontiguousarray(owner, dtype=np.uint8)
     rk = None if ranks is None else np.ascontiguousarray(ranks, dtype=np.int32)
     if own is not None:
         assert own.shape == vol.shape and rk is not None and len(rk) == nb
     c = _cam(cam)
-    rc = lib().orc_generate(_ptr(vol), dt, _ptr(n), _ptr(lo), _ptr(hi), nb, ctypes.byref(c), _ptr(tf),
-                            tf.shape[0], step, ref, mode, tau, max_n, iters, _ptr(px), npix,
-                            _ptr(out["color"]), _ptr(out["depth"]), _ptr(out["count"]), _ptr(out["gamma"]),
-                            _ptr(out["margin"]), _ptr(out["contiguous"]), _ptr(own), _ptr(rk), nthreads)
+    call = lambda alts: lib().orc_generate(
+        _ptr(vol), dt, _ptr(n), _ptr(lo), _ptr(hi), nb, ctypes.byref(c), _ptr(tf), tf.shape[0], step, ref, mode,
+        tau, max_n, iters, _ptr(px), npix, _ptr(out["color"]), _ptr(out["depth"]), _ptr(out["count"]),
+        _ptr(out["gamma"]), _ptr(out["margin"]), _ptr(out["contiguous"]), _ptr(own), _ptr(rk), tie,
+        _ptr(out["nout"]), alts, nthreads)
+    rc, out["alts"] = _with_alts(call, nb * npix, max_n)
     if rc != 0:
         raise RuntimeError(f"orc_generate failed ({rc})")
     return out
@@ -143,8 +189,9 @@ def generate(vol: np.ndarray, bricks: Sequence, cam, tf: np.ndarray, step: float
 
 def composite(colors: Sequence[np.ndarray], depths: Sequence[np.ndarray], counts: Sequence[np.ndarray],
               ref: float, mode: int, tau: float, out_n: int, iters: int = 10,
-              want_order: bool = False, nthreads: int = 0) -> Dict[str, np.ndarray]:
-    """Composite k regular lists ([in_n, npix, 4], [in_n, npix, 2], [npix]) into one."""
+              want_order: bool = False, nthreads: int = 0, tie: float = TIE) -> Dict[str, np.ndarray]:
+    """Composite k regular lists ([in_n, npix, 4], [in_n, npix, 2], [npix]) into one.
+    "nout" and "alts" as for generate (ray = pixel)."""
     k = len(colors)
     in_n, npix = colors[0].shape[0], colors[0].shape[1]
     cs = [np.ascontiguousarray(c, dtype=np.float32) for c in colors]
@@ -159,11 +206,14 @@ def composite(colors: Sequence[np.ndarray], depths: Sequence[np.ndarray], counts
         "count": np.zeros((npix,), np.int32),
         "gamma": np.zeros((npix,), np.float32),
         "margin": np.zeros((npix,), np.float64),
+        "nout": np.zeros((npix,), np.int32),
     }
     order = np.zeros((npix, k * in_n), np.int32) if want_order else None
-    rc = lib().orc_composite(k, arr(cs), arr(ds), arr(ns), in_n, npix, ref, mode, tau, out_n, iters,
-                             _ptr(out["color"]), _ptr(out["depth"]), _ptr(out["count"]), _ptr(out["gamma"]),
-                             _ptr(out["margin"]), _ptr(order), nthreads)
+    call = lambda alts: lib().orc_composite(
+        k, arr(cs), arr(ds), arr(ns), in_n, npix, ref, mode, tau, out_n, iters, _ptr(out["color"]),
+        _ptr(out["depth"]), _ptr(out["count"]), _ptr(out["gamma"]), _ptr(out["margin"]), _ptr(order), tie,
+        _ptr(out["nout"]), alts, nthreads)
+    rc, out["alts"] = _with_alts(call, npix, out_n)
     if rc == -2:
         raise ValueError("composite input is not a valid depth-sorted supersegment list")
     if rc != 0:
@@ -243,6 +293,22 @@ def seg(elems: np.ndarray, mode: int, gamma: float = 0.0, cap: int = 0, max_n: i
     c = lib().orc_seg(_ptr(elems), n, mode, gamma, cap, max_n, iters, int(gaps), ref, _ptr(out), max_out,
                       _ptr(g), _ptr(m))
     return out[:min(c, max_out)], c, float(g[0]), float(m[0])
+
+
+def seg_outcomes(elems: np.ndarray, mode: int, gamma: float = 0.0, max_n: int = 8, iters: int = 10,
+                 gaps: bool = False, ref: float = 1.0, tie: float = TIE, max_outcomes: int = 256):
+    """Every outcome of segmenting explicit elements [n, 6] when each near-tie
+    Eq. 1 decision may go either way: a list of (count, gamma, supersegments
+    [min(count, max_n), 6]), the fp64 outcome first, and whether the
+    enumeration was complete."""
+    elems = np.ascontiguousarray(elems, dtype=np.float64).reshape(-1, 6)
+    counts = np.zeros(max_outcomes, np.int32)
+    gammas = np.zeros(max_outcomes, np.float64)
+    lists = np.zeros((max_outcomes, max_n, 6), np.float64)
+    no = lib().orc_seg_outcomes(_ptr(elems), elems.shape[0], mode, gamma, max_n, iters, int(gaps), ref, tie,
+                                _ptr(counts), _ptr(gammas), _ptr(lists), max_outcomes)
+    tot = min(abs(no), max_outcomes)
+    return [(int(counts[i]), float(gammas[i]), lists[i, :min(int(counts[i]), max_n)]) for i in range(tot)], no > 0
 
 
 def ray_info(cam, pix: int, step: float):

@@ -237,24 +237,55 @@ typedef struct { double f, b, rgb[3], a; } orc_elem;
 
 typedef struct { double f, b, rgb[3], a; } orc_sseg;
 
+/* Near-tie decisions.  An implementation that evaluates the Eq. 1 distance
+ * in fp32 can take the other branch of a decision whose fp64 distance lies
+ * within its rounding error of gamma.  Such a decision is a near tie when
+ * |d - gamma| < tie * max(1, L / 128), L the number of elements the open
+ * supersegment holds (the fp32 error of its accumulated colour grows with L).
+ * A run can force the outcomes of its first near ties (to enumerate every
+ * outcome a near tie admits); it records the natural outcome of each. */
+#define ORC_MAXNEAR 12
+
 typedef struct {
     double gamma;
     int cap;            /* >0: saturate after cap-1 closes (fixed mode) */
     int gaps;           /* insert transparent gap elements (compositing) */
     double ref;
-    int count_limit;    /* margins are only recorded while count <= limit */
+    int count_limit;    /* decisions are recorded only while count <= limit */
+    double tie;         /* near-tie band (0: none) */
+    const signed char *force;   /* outcomes (1 = close) of the first nforce near ties */
+    int nforce;
     /* outputs */
     orc_sseg *out;       /* may be NULL */
     int max_out;
     int count;
     double margin;      /* min |distance - gamma| over recorded decisions */
+    int nnear;          /* near ties met */
+    signed char natural[ORC_MAXNEAR];   /* their outcomes at the fp64 distance */
 } orc_segrun;
+
+static orc_segrun segrun(double gamma, int cap, int gaps, double ref, int limit, double tie, orc_sseg *out,
+                         int max_out)
+{
+    orc_segrun R;
+    memset(&R, 0, sizeof R);
+    R.gamma = gamma;
+    R.cap = cap;
+    R.gaps = gaps;
+    R.ref = ref;
+    R.count_limit = limit;
+    R.tie = tie;
+    R.out = out;
+    R.max_out = max_out;
+    return R;
+}
 
 typedef struct {
     int open;
     double f, b, bt;
     double C[3];        /* premultiplied colour accumulated front to back */
     double T;           /* transmittance of the open supersegment */
+    int nel;            /* elements it holds */
 } orc_state;
 
 static void seg_close(orc_state *S, orc_segrun *R)
@@ -291,17 +322,27 @@ static void seg_step(orc_state *S, orc_segrun *R, const orc_elem *e)
         }
         double d = sqrt(d2);
         int may_close = R->cap <= 0 || R->count < R->cap - 1;
+        int close = may_close && R->gamma < d;
         if (may_close && R->count <= R->count_limit) {
             double m = fabs(d - R->gamma);
             if (m < R->margin) R->margin = m;
+            double band = R->tie * (S->nel > 128 ? S->nel / 128.0 : 1.0);
+            if (m < band) {
+                int i = R->nnear++;
+                if (i < ORC_MAXNEAR) {
+                    R->natural[i] = (signed char)close;
+                    if (i < R->nforce) close = R->force[i];
+                }
+            }
         }
-        if (may_close && R->gamma < d) {
+        if (close) {
             seg_close(S, R);
         } else {
             for (int ch = 0; ch < 3; ++ch) S->C[ch] += S->T * e->rgb[ch] * at;
             S->T *= 1.0 - at;
             S->b = e->b;
             if (!transparent) S->bt = e->b;
+            S->nel += 1;
         }
     }
     if (!S->open && !transparent) {
@@ -310,6 +351,7 @@ static void seg_step(orc_state *S, orc_segrun *R, const orc_elem *e)
         S->b = S->bt = e->b;
         for (int ch = 0; ch < 3; ++ch) S->C[ch] = e->rgb[ch] * at;
         S->T = 1.0 - at;
+        S->nel = 1;
     }
 }
 
@@ -319,6 +361,7 @@ static void seg_run(const orc_elem *e, int n, orc_segrun *R)
     memset(&S, 0, sizeof S);
     R->count = 0;
     R->margin = INFINITY;
+    R->nnear = 0;
     for (int i = 0; i < n; ++i) {
         if (S.open && e[i].f > S.b) {
             if (R->gaps) {
@@ -344,13 +387,202 @@ static double bisect(const orc_elem *e, int n, int max_n, int iters, double gmax
     double lo = 0.0, hi = gmax, mg = INFINITY;
     for (int it = 0; it < iters; ++it) {
         double m = 0.5 * (lo + hi);
-        orc_segrun R = { m, 0, gaps, ref, max_n, NULL, 0, 0, 0.0 };
+        orc_segrun R = segrun(m, 0, gaps, ref, max_n, 0.0, NULL, 0);
         seg_run(e, n, &R);
         if (R.margin < mg) mg = R.margin;
         if (R.count <= max_n) hi = m; else lo = m;
     }
     *margin = mg;
     return hi;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Outcomes under near ties                                                 */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_MAXLEAF 32   /* outcomes of one pass */
+#define ORC_MAXPATH 8    /* bisection paths */
+
+typedef struct { signed char f[ORC_MAXNEAR]; int n; } orc_forcing;
+
+/* Every outcome of one pass (the run template R0) when each near-tie decision
+ * may go either way: a depth-first walk over the near ties, the first leaf
+ * being the run with every decision at its fp64 outcome.  Leaf i's count goes
+ * to counts[i] and, when lists != NULL, its supersegments to
+ * lists[i * R0.max_out ...].  Returns the number of leaves, negated when the
+ * walk is incomplete (more than ORC_MAXNEAR near ties on a path or more than
+ * ORC_MAXLEAF leaves). */
+static int pass_outcomes(const orc_elem *e, int n, orc_segrun R0, orc_sseg *lists, int *counts, double *margin)
+{
+    orc_forcing stack[ORC_MAXLEAF];
+    int sp = 0, nl = 0, incomplete = 0;
+    stack[sp].n = 0;
+    sp = 1;
+    while (sp > 0) {
+        orc_forcing F = stack[--sp];
+        if (nl == ORC_MAXLEAF) { incomplete = 1; break; }
+        orc_segrun R = R0;
+        R.force = F.f;
+        R.nforce = F.n;
+        R.out = lists ? lists + (size_t)nl * (size_t)R0.max_out : NULL;
+        seg_run(e, n, &R);
+        if (nl == 0 && margin) *margin = R.margin;
+        counts[nl++] = R.count;
+        if (R.nnear > ORC_MAXNEAR) incomplete = 1;
+        int m = R.nnear < ORC_MAXNEAR ? R.nnear : ORC_MAXNEAR;
+        /* the other outcome at each near tie past the forced ones, pushed
+         * last-first so that the walk visits them in path order */
+        for (int i = m - 1; i >= F.n; --i) {
+            if (sp == ORC_MAXLEAF) { incomplete = 1; break; }
+            orc_forcing G;
+            G.n = i + 1;
+            for (int j = 0; j < F.n; ++j) G.f[j] = F.f[j];
+            for (int j = F.n; j < i; ++j) G.f[j] = R.natural[j];
+            G.f[i] = (signed char)!R.natural[i];
+            stack[sp++] = G;
+        }
+    }
+    return incomplete ? -nl : nl;
+}
+
+/* Thresholds the bisection reaches when every near tie of its passes may go
+ * either way: paths split where a pass admits both a feasible and an
+ * infeasible count.  gammas[0] is the fp64 path's result.  Returns the number
+ * of paths, negated when incomplete.  *margin: the fp64 path's minimum
+ * |d - gamma| over its recorded decisions. */
+static int bisect_paths(const orc_elem *e, int n, int max_n, int iters, double gmax, int gaps, double ref,
+                        double tie, double *gammas, double *margin)
+{
+    double plo[ORC_MAXPATH], phi[ORC_MAXPATH];
+    int np = 1, incomplete = 0;
+    int counts[ORC_MAXLEAF];
+    plo[0] = 0.0;
+    phi[0] = gmax;
+    double mg = INFINITY;
+    for (int it = 0; it < iters; ++it) {
+        int np0 = np;
+        for (int p = 0; p < np0; ++p) {
+            double m = 0.5 * (plo[p] + phi[p]), pm = INFINITY;
+            orc_segrun R0 = segrun(m, 0, gaps, ref, max_n, tie, NULL, 0);
+            int nl = pass_outcomes(e, n, R0, NULL, counts, &pm);
+            if (nl < 0) { incomplete = 1; nl = -nl; }
+            if (p == 0 && pm < mg) mg = pm;
+            int feas = counts[0] <= max_n, other = 0;
+            for (int i = 1; i < nl; ++i)
+                if ((counts[i] <= max_n) != feas) other = 1;
+            if (other) {
+                if (np < ORC_MAXPATH) {
+                    /* the second path takes the other feasibility */
+                    plo[np] = feas ? m : plo[p];
+                    phi[np] = feas ? phi[p] : m;
+                    ++np;
+                } else {
+                    incomplete = 1;
+                }
+            }
+            if (feas) phi[p] = m; else plo[p] = m;
+        }
+    }
+    for (int p = 0; p < np; ++p) gammas[p] = phi[p];
+    *margin = mg;
+    return incomplete ? -np : np;
+}
+
+/* Alternative outcomes of the lists computed under near ties (beside the
+ * fp64 outcome, which goes to the regular outputs).  Entry i: list `ray`,
+ * its count, threshold and first max_n supersegments (zero-filled). */
+typedef struct {
+    int32_t *ray;
+    int32_t *count;
+    float *gamma;
+    float *color;       /* [cap][max_n][4] */
+    float *depth;       /* [cap][max_n][2] */
+    int32_t cap;
+    int32_t n;          /* entries wanted (may exceed cap: then the call fails) */
+} orc_alts;
+
+static int same_list(const orc_sseg *a, const orc_sseg *b, int n)
+{
+    for (int j = 0; j < n; ++j) {
+        if ((float)a[j].f != (float)b[j].f || (float)a[j].b != (float)b[j].b || (float)a[j].a != (float)b[j].a)
+            return 0;
+        for (int ch = 0; ch < 3; ++ch)
+            if ((float)a[j].rgb[ch] != (float)b[j].rgb[ch]) return 0;
+    }
+    return 1;
+}
+
+static void put_alt(orc_alts *A, int ray, int count, double gamma, const orc_sseg *s, int max_n)
+{
+    int i;
+#pragma omp atomic capture
+    i = A->n++;
+    if (i >= A->cap) return;
+    A->ray[i] = ray;
+    A->count[i] = count;
+    A->gamma[i] = (float)gamma;
+    int c = count < max_n ? count : max_n;
+    for (int j = 0; j < max_n; ++j) {
+        float *co = A->color + ((size_t)i * max_n + j) * 4;
+        float *de = A->depth + ((size_t)i * max_n + j) * 2;
+        if (j < c) {
+            for (int ch = 0; ch < 3; ++ch) co[ch] = (float)s[j].rgb[ch];
+            co[3] = (float)s[j].a;
+            de[0] = (float)s[j].f;
+            de[1] = (float)s[j].b;
+        } else {
+            memset(co, 0, 4 * sizeof(float));
+            memset(de, 0, 2 * sizeof(float));
+        }
+    }
+}
+
+/* Threshold and list(s) of one stream: the fp64 outcome in (*gamma, *count,
+ * s[0 .. max_out)) and, in A (when not NULL), every other outcome the near ties
+ * admit.  mode FIXED: Seg(gamma = tau) saturating at max_out; BISECT: the
+ * bisection over Seg.  Returns the number of distinct outcomes (1: the list
+ * is decided), negated when the enumeration was incomplete.  work: room for
+ * ORC_MAXLEAF * max_out supersegments. */
+static int segment_outcomes(const orc_elem *e, int n, int mode, double tau, int max_out, int iters, int gaps,
+                            double ref, double tie, orc_sseg *s, orc_sseg *work, int ray, orc_alts *A,
+                            double *gamma, int *count, double *margin)
+{
+    double gammas[ORC_MAXPATH], mg = INFINITY;
+    int np = 1, incomplete = 0;
+    if (mode == ORC_FIXED) {
+        gammas[0] = tau;
+    } else {
+        np = bisect_paths(e, n, max_out, iters, 2.0, gaps, ref, tie, gammas, &mg);
+        if (np < 0) { incomplete = 1; np = -np; }
+    }
+    int counts[ORC_MAXLEAF], nout = 0;
+    for (int p = 0; p < np; ++p) {
+        double fm = INFINITY;
+        orc_segrun R0 = segrun(gammas[p], mode == ORC_FIXED ? max_out : 0, gaps, ref, max_out, tie, NULL, max_out);
+        int nl = pass_outcomes(e, n, R0, work, counts, &fm);
+        if (nl < 0) { incomplete = 1; nl = -nl; }
+        if (p == 0 && fm < mg) mg = fm;
+        for (int i = 0; i < nl; ++i) {
+            const orc_sseg *li = work + (size_t)i * max_out;
+            int ci = counts[i] < max_out ? counts[i] : max_out;
+            if (p == 0 && i == 0) {
+                memcpy(s, li, sizeof(orc_sseg) * (size_t)ci);
+                *gamma = gammas[0];
+                *count = counts[0];
+                nout = 1;
+                continue;
+            }
+            /* distinct from the fp64 outcome and from earlier leaves of this path */
+            int dup = gammas[p] == *gamma && counts[i] == *count && same_list(li, s, ci);
+            for (int q = 0; q < i && !dup; ++q)
+                dup = counts[q] == counts[i] && same_list(work + (size_t)q * max_out, li, ci);
+            if (dup) continue;
+            ++nout;
+            if (A) put_alt(A, ray, counts[i], gammas[p], li, max_out);
+        }
+    }
+    *margin = mg;
+    return incomplete ? -nout : nout;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -434,11 +666,16 @@ static void set_threads(int nthreads)
  *   color [nb][max_n][npix][4], depth [nb][max_n][npix][2] (zero beyond count),
  *   count [nb][npix], gamma [nb][npix], margin [nb][npix] (may be NULL),
  *   contiguous [nb][npix] (may be NULL).
+ * Near ties (tie > 0, see above): nout [nb][npix] (may be NULL) receives the
+ * number of distinct outcomes of each list (1: decided; negative: the
+ * enumeration was incomplete) and alts (may be NULL) the outcomes beside the
+ * fp64 one, with ray = r * npix + q.
  * owner (may be NULL): rank of every voxel [nz][ny][nx], ranks [nb] the
  * bricks' ranks (bisection only).  The count is what the segmenter emits:
  * with an owner map a ray can enter a domain more often than N times, and the
  * stored list then holds the first max_n supersegments.
- * Returns 0, or -1 on bad arguments. */
+ * Returns 0, -1 on bad arguments, -3 if alts is too small (alts->n then holds
+ * the number of entries needed). */
 int orc_generate(const void *vol_data, int vol_dtype, const int32_t *n,
                  const int32_t *brick_lo, const int32_t *brick_hi, int nb,
                  const orc_camera *cam, const float *tf, int entries,
@@ -446,7 +683,7 @@ int orc_generate(const void *vol_data, int vol_dtype, const int32_t *n,
                  const int32_t *pixels, int npix,
                  float *color, float *depth, int32_t *count, float *gamma,
                  double *margin, int32_t *contiguous, const uint8_t *owner, const int32_t *ranks,
-                 int nthreads)
+                 double tie, int32_t *nout, orc_alts *alts, int nthreads)
 {
     if (!vol_data || !n || nb <= 0 || !cam || !tf || entries < 2 || max_n <= 0 || npix < 0)
         return -1;
@@ -455,10 +692,12 @@ int orc_generate(const void *vol_data, int vol_dtype, const int32_t *n,
     int cap = max_samples(step);
     set_threads(nthreads);
     size_t P = (size_t)npix;
+    if (alts) alts->n = 0;
 #pragma omp parallel
     {
         orc_elem *e = (orc_elem *)malloc(sizeof(orc_elem) * (size_t)cap);
         orc_sseg *s = (orc_sseg *)malloc(sizeof(orc_sseg) * (size_t)max_n);
+        orc_sseg *work = (orc_sseg *)malloc(sizeof(orc_sseg) * (size_t)max_n * ORC_MAXLEAF);
 #pragma omp for schedule(dynamic, 64)
         for (long long job = 0; job < (long long)nb * npix; ++job) {
             int r = (int)(job / npix);
@@ -469,18 +708,11 @@ int orc_generate(const void *vol_data, int vol_dtype, const int32_t *n,
             int ne = ray.hit ? brick_stream(&vol, brick_lo + 3 * r, brick_hi + 3 * r, owner, owner ? ranks[r] : 0,
                                             &ray, tf, entries, step, e, cap, &contig, NULL) : 0;
             if (!ray.hit) contig = 1;
-            double g, mg = INFINITY;
-            orc_segrun R;
-            if (mode == ORC_FIXED) {
-                g = tau;
-                R = (orc_segrun){ g, max_n, 0, ref, max_n, s, max_n, 0, 0.0 };
-            } else {
-                g = bisect(e, ne, max_n, iters, 2.0, 0, ref, &mg);
-                R = (orc_segrun){ g, 0, 0, ref, max_n, s, max_n, 0, 0.0 };
-            }
-            seg_run(e, ne, &R);
-            if (R.margin < mg) mg = R.margin;
-            int c = R.count < max_n ? R.count : max_n;
+            double g, mg;
+            int cnt;
+            int no = segment_outcomes(e, ne, mode, tau, max_n, iters, 0, ref, tie, s, work, (int)job, alts, &g,
+                                      &cnt, &mg);
+            int c = cnt < max_n ? cnt : max_n;
             for (int j = 0; j < max_n; ++j) {
                 size_t o = ((size_t)r * max_n + j) * P + q;
                 if (j < c) {
@@ -493,14 +725,17 @@ int orc_generate(const void *vol_data, int vol_dtype, const int32_t *n,
                     memset(depth + 2 * o, 0, 2 * sizeof(float));
                 }
             }
-            count[(size_t)r * P + q] = R.count;
+            count[(size_t)r * P + q] = cnt;
             if (gamma) gamma[(size_t)r * P + q] = (float)g;
             if (margin) margin[(size_t)r * P + q] = mg;
             if (contiguous) contiguous[(size_t)r * P + q] = contig;
+            if (nout) nout[(size_t)r * P + q] = no;
         }
         free(e);
         free(s);
+        free(work);
     }
+    if (alts && alts->n > alts->cap) return -3;
     return 0;
 }
 
@@ -514,25 +749,27 @@ int orc_generate(const void *vol_data, int vol_dtype, const int32_t *n,
  * depth_k [in_n][npix][2], count_k [npix].
  * Outputs: color [out_n][npix][4], depth [out_n][npix][2], count, gamma,
  * margin (may be NULL), order [npix][k*in_n] (may be NULL): merged order as
- * rank*65536 + slot, -1 padded.
+ * rank*65536 + slot, -1 padded; nout and alts as for generation (ray = q).
  * Returns 0; -1 on bad arguments; -2 if an input list is not sorted by front
- * depth, has f >= b, or a count outside [0, in_n]. */
+ * depth, has f >= b, or a count outside [0, in_n]; -3 if alts is too small. */
 int orc_composite(int k, const float *const *colors, const float *const *depths,
                   const int32_t *const *counts, int in_n, int npix, float ref,
                   int mode, float tau, int out_n, int iters,
                   float *color, float *depth, int32_t *count, float *gamma,
-                  double *margin, int32_t *order, int nthreads)
+                  double *margin, int32_t *order, double tie, int32_t *nout, orc_alts *alts, int nthreads)
 {
     if (k <= 0 || in_n <= 0 || out_n <= 0 || npix < 0) return -1;
     set_threads(nthreads);
     size_t P = (size_t)npix;
     int bad = 0;
+    if (alts) alts->n = 0;
 #pragma omp parallel
     {
         int cap = k * in_n;
         orc_elem *e = (orc_elem *)malloc(sizeof(orc_elem) * (size_t)cap);
         int32_t *rk = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
         orc_sseg *s = (orc_sseg *)malloc(sizeof(orc_sseg) * (size_t)out_n);
+        orc_sseg *work = (orc_sseg *)malloc(sizeof(orc_sseg) * (size_t)out_n * ORC_MAXLEAF);
 #pragma omp for schedule(dynamic, 64)
         for (long long qq = 0; qq < npix; ++qq) {
             size_t q = (size_t)qq;
@@ -568,7 +805,7 @@ int orc_composite(int k, const float *const *colors, const float *const *depths,
             if (order)
                 for (int j = 0; j < cap; ++j) order[q * (size_t)cap + j] = j < n ? rk[j] : -1;
             double g = 0.0, mg = INFINITY;
-            int c;
+            int c, no = 1;
             if (n <= out_n) {
                 /* pass-through */
                 for (int j = 0; j < n; ++j) {
@@ -579,17 +816,10 @@ int orc_composite(int k, const float *const *colors, const float *const *depths,
                 }
                 c = n;
             } else {
-                orc_segrun R;
-                if (mode == ORC_FIXED) {
-                    g = tau;
-                    R = (orc_segrun){ g, out_n, 1, ref, out_n, s, out_n, 0, 0.0 };
-                } else {
-                    g = bisect(e, n, out_n, iters, 2.0, 1, ref, &mg);
-                    R = (orc_segrun){ g, 0, 1, ref, out_n, s, out_n, 0, 0.0 };
-                }
-                seg_run(e, n, &R);
-                if (R.margin < mg) mg = R.margin;
-                c = R.count < out_n ? R.count : out_n;
+                int cnt;
+                no = segment_outcomes(e, n, mode, tau, out_n, iters, 1, ref, tie, s, work, (int)q, alts, &g, &cnt,
+                                      &mg);
+                c = cnt < out_n ? cnt : out_n;
             }
             for (int j = 0; j < out_n; ++j) {
                 size_t o = (size_t)j * P + q;
@@ -606,12 +836,16 @@ int orc_composite(int k, const float *const *colors, const float *const *depths,
             count[q] = c;
             if (gamma) gamma[q] = (float)g;
             if (margin) margin[q] = mg;
+            if (nout) nout[q] = no;
         }
         free(e);
         free(rk);
         free(s);
+        free(work);
     }
-    return bad ? -2 : 0;
+    if (bad) return -2;
+    if (alts && alts->n > alts->cap) return -3;
+    return 0;
 }
 
 /* Rendering from the viewpoint of generation (Sec. 2.3): each stored
@@ -804,8 +1038,8 @@ int orc_seg(const double *elems, int n, int mode, double gamma, int cap, int max
     }
     double g = gamma, mg = INFINITY;
     if (mode == ORC_BISECT) g = bisect(e, n, max_n, iters, 2.0, gaps, ref, &mg);
-    orc_segrun R = { g, mode == ORC_FIXED ? cap : 0, gaps, ref, mode == ORC_FIXED ? (cap > 0 ? cap : n) : max_n,
-                     s, max_out, 0, 0.0 };
+    orc_segrun R = segrun(g, mode == ORC_FIXED ? cap : 0, gaps, ref,
+                          mode == ORC_FIXED ? (cap > 0 ? cap : n) : max_n, 0.0, s, max_out);
     seg_run(e, n, &R);
     if (R.margin < mg) mg = R.margin;
     int c = R.count < max_out ? R.count : max_out;
@@ -820,6 +1054,63 @@ int orc_seg(const double *elems, int n, int mode, double gamma, int cap, int max
     free(e);
     free(s);
     return R.count;
+}
+
+/* Every outcome of one explicit stream under near ties (for unit tests):
+ * elems [n][6] as for orc_seg; mode FIXED (gamma, saturating at max_n) or
+ * BISECT (max_n, iters).  Outcome i: counts[i], gammas[i] and lists
+ * [i][max_n][6]; outcome 0 is the fp64 one.  Returns the number of outcomes
+ * (at most max_outcomes are stored), negated when the enumeration was cut
+ * short. */
+int orc_seg_outcomes(const double *elems, int n, int mode, double gamma, int max_n, int iters, int gaps,
+                     double ref, double tie, int32_t *counts, double *gammas, double *lists, int max_outcomes)
+{
+    orc_elem *e = (orc_elem *)malloc(sizeof(orc_elem) * (size_t)(n > 0 ? n : 1));
+    orc_sseg *s = (orc_sseg *)malloc(sizeof(orc_sseg) * (size_t)max_n);
+    orc_sseg *work = (orc_sseg *)malloc(sizeof(orc_sseg) * (size_t)max_n * ORC_MAXLEAF);
+    int cap = ORC_MAXLEAF * ORC_MAXPATH;
+    float *ac = (float *)malloc(sizeof(float) * (size_t)cap * max_n * 4);
+    float *ad = (float *)malloc(sizeof(float) * (size_t)cap * max_n * 2);
+    int32_t *ar = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    int32_t *acnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    float *ag = (float *)malloc(sizeof(float) * (size_t)cap);
+    orc_alts A = { ar, acnt, ag, ac, ad, cap, 0 };
+    for (int i = 0; i < n; ++i) {
+        e[i].f = elems[6 * i];
+        e[i].b = elems[6 * i + 1];
+        for (int ch = 0; ch < 3; ++ch) e[i].rgb[ch] = elems[6 * i + 2 + ch];
+        e[i].a = elems[6 * i + 5];
+    }
+    double g, mg;
+    int cnt;
+    int no = segment_outcomes(e, n, mode, gamma, max_n, iters, gaps, ref, tie, s, work, 0, &A, &g, &cnt, &mg);
+    int tot = no < 0 ? -no : no;
+    for (int i = 0; i < tot && i < max_outcomes; ++i) {
+        double *o = lists + (size_t)i * max_n * 6;
+        if (i == 0) {
+            counts[0] = cnt;
+            gammas[0] = g;
+            int c = cnt < max_n ? cnt : max_n;
+            for (int j = 0; j < max_n; ++j) {
+                o[6 * j] = j < c ? s[j].f : 0.0;
+                o[6 * j + 1] = j < c ? s[j].b : 0.0;
+                for (int ch = 0; ch < 3; ++ch) o[6 * j + 2 + ch] = j < c ? s[j].rgb[ch] : 0.0;
+                o[6 * j + 5] = j < c ? s[j].a : 0.0;
+            }
+        } else {
+            counts[i] = acnt[i - 1];
+            gammas[i] = ag[i - 1];
+            for (int j = 0; j < max_n; ++j) {
+                const float *co = ac + ((size_t)(i - 1) * max_n + j) * 4, *de = ad + ((size_t)(i - 1) * max_n + j) * 2;
+                o[6 * j] = de[0];
+                o[6 * j + 1] = de[1];
+                for (int ch = 0; ch < 3; ++ch) o[6 * j + 2 + ch] = co[ch];
+                o[6 * j + 5] = co[3];
+            }
+        }
+    }
+    free(e); free(s); free(work); free(ac); free(ad); free(ar); free(acnt); free(ag);
+    return no;
 }
 
 /* Per-pixel sample streams for tests: number of samples of each ray and the
@@ -928,7 +1219,7 @@ int orc_features(const void *vol_data, int vol_dtype, const int32_t *n,
             size_t o = (size_t)r * npix + q;
             for (int j = 0; j < 64; ++j) hist[o * 64 + j] = bf16_round((float)bins[j] / s_ref);
             nnt[o] = m;
-            orc_segrun R = { gmin, 0, 0, ref, 1 << 30, NULL, 0, 0, 0.0 };
+            orc_segrun R = segrun(gmin, 0, 0, ref, 1 << 30, 0.0, NULL, 0);
             seg_run(e, ne, &R);
             cmax[o] = R.count;
         }
@@ -963,7 +1254,7 @@ int orc_count_at(const void *vol_data, int vol_dtype, const int32_t *n,
             int ne = ray.hit ? brick_stream(&vol, brick_lo + 3 * r, brick_hi + 3 * r, NULL, 0, &ray, tf, entries,
                                             step, e, cap, &contig, NULL) : 0;
             size_t o = (size_t)r * npix + q;
-            orc_segrun R = { gamma[o], 0, 0, ref, limit, NULL, 0, 0, 0.0 };
+            orc_segrun R = segrun(gamma[o], 0, 0, ref, limit, 0.0, NULL, 0);
             seg_run(e, ne, &R);
             count[o] = R.count;
             if (margin) margin[o] = R.margin;

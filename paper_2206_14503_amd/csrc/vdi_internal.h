@@ -249,12 +249,6 @@ __device__ inline float lerp_exact(float a, float b, float w)
     return __builtin_fmaf(w, d, a);
 }
 
-// (1 - w) a + w b, exactly a at w = 0 and exactly b at w = 1.
-__device__ inline float lerp_ends(float a, float b, float w)
-{
-    return __builtin_fmaf(w, b, __builtin_fmaf(-w, a, a));
-}
-
 struct BrickGeo {
     float nf[3];    // global volume dims
     int dlo[3];     // global index of the first data voxel
@@ -340,7 +334,8 @@ template <> __device__ inline float load_one<__half>(const __half* base, uint32_
 // stay in bounds for any position.
 struct Taps {
     float a[4], b[4];   // rows (y0,z0), (y1,z0), (y0,z1), (y1,z1): voxels xb, xb+1
-    float w[3];         // blend weights; w[0] is 0 (1) where both x taps are voxel xb (xb+1)
+    float w[3];         // blend weights; w[0] is 0 where both x taps are one voxel
+    bool hi;            // both x taps are voxel xb+1 (the data box's last x)
 };
 
 // PAIRED: the brick's data box is at least two voxels wide in x (g.sx2); a
@@ -368,14 +363,18 @@ __device__ inline Taps trilinear_fetch(const VT* data, const BrickGeo& g, const 
     if (PAIRED) {
         const int xb = i0[0] < g.xmax ? i0[0] : g.xmax;
         // x0 is voxel xb, else xb + 1 (the data box's last voxel, x1 = x0);
-        // x1 is voxel xb + 1 unless clamped onto x0
-        t.w[0] = i0[0] == xb ? (i1[0] == xb ? 0.0f : t.w[0]) : 1.0f;
+        // x1 is voxel xb + 1 unless clamped onto x0.  Where both taps are one
+        // voxel the row's value is that voxel: weight 0 on the lerp based at
+        // it (the blend bases the lerp at b where `hi`)
+        t.hi = i0[0] != xb;
+        t.w[0] = (i0[0] == xb && i1[0] != xb) ? t.w[0] : 0.0f;
         load_pair<VT>(data, r00 + xb, t.a[0], t.b[0]);
         load_pair<VT>(data, r10 + xb, t.a[1], t.b[1]);
         load_pair<VT>(data, r01 + xb, t.a[2], t.b[2]);
         load_pair<VT>(data, r11 + xb, t.a[3], t.b[3]);
     } else {
         t.w[0] = 0.0f;
+        t.hi = false;
         t.a[0] = t.b[0] = load_one<VT>(data, r00);
         t.a[1] = t.b[1] = load_one<VT>(data, r10);
         t.a[2] = t.b[2] = load_one<VT>(data, r01);
@@ -384,13 +383,22 @@ __device__ inline Taps trilinear_fetch(const VT* data, const BrickGeo& g, const 
     return t;
 }
 
+// The x lerps are a + w (b - a) with one rounding, as every lerp of the
+// reconstruction; a row whose taps are one voxel v gives exactly v (weight 0
+// on base v).
+__device__ inline float lerp_x(const Taps& t, int row)
+{
+    const float d = t.b[row] - t.a[row];
+    return __builtin_fmaf(t.w[0], d, t.hi ? t.b[row] : t.a[row]);
+}
+
 __device__ inline float trilinear_blend(const Taps& t)
 {
 #pragma clang fp contract(off)
-    float c00 = lerp_ends(t.a[0], t.b[0], t.w[0]);
-    float c10 = lerp_ends(t.a[1], t.b[1], t.w[0]);
-    float c01 = lerp_ends(t.a[2], t.b[2], t.w[0]);
-    float c11 = lerp_ends(t.a[3], t.b[3], t.w[0]);
+    float c00 = lerp_x(t, 0);
+    float c10 = lerp_x(t, 1);
+    float c01 = lerp_x(t, 2);
+    float c11 = lerp_x(t, 3);
     float c0 = lerp_exact(c00, c10, t.w[1]);
     float c1 = lerp_exact(c01, c11, t.w[1]);
     return lerp_exact(c0, c1, t.w[2]);

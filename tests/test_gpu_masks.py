@@ -7,7 +7,8 @@ import pytest
 
 from paper_2206_14503_amd import synth
 from conftest import gpu_available
-from test_gpu_parity import ATOL, _compare_lists, _gpu_regular, _np
+from parity import ATOL, check_lists
+from test_gpu_parity import _gpu_regular, _np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="no GPU")]
 
@@ -78,8 +79,7 @@ def test_non_convex_generate_parity(V, orc, block, ranks, seed, mode, dtype):
     assert (ref["contiguous"] == 0).sum() > 200
     for r in range(ranks):
         gc, gd, gn, gg = _gpu_regular(outs[r])
-        _compare_lists(gc, gd, gn, ref["color"][r], ref["depth"][r], ref["count"][r], ref["margin"][r],
-                       f"rank {r}")
+        check_lists((gc, gd, gn, gg), ref, f"rank {r}", brick=r)
 
 
 def test_non_convex_composite_equals_dvr(V, orc):
@@ -144,8 +144,7 @@ def test_more_domain_entries_than_n_keeps_the_first_n(V, orc):
     assert (ref["count"] > 2).sum() > 100
     for r in range(2):
         gc, gd, gn, gg = _gpu_regular(outs[r])
-        _compare_lists(gc, gd, gn, ref["color"][r], ref["depth"][r], np.minimum(ref["count"][r], 2),
-                       ref["margin"][r], f"rank {r}")
+        check_lists((gc, gd, gn, gg), ref, f"rank {r}", brick=r)
 
 
 def test_owner_maps_need_a_bisection_mode(V):
