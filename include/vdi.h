@@ -13,11 +13,15 @@
  *
  * Conventions for every entry point:
  *  - All data pointers are DEVICE pointers unless stated otherwise; the caller
- *    allocates and owns them.  The library owns only its context (scratch
- *    memory, kept between calls and grown when a larger problem arrives;
- *    growing it synchronises the device).  The scratch is shared by all calls
- *    on a context: calls on different streams of one context must not run
- *    concurrently.
+ *    allocates and owns them.  An op that needs device scratch memory (its
+ *    workspace, sized by vdi_workspace_size) takes it from the context: either
+ *    a caller-owned block set with vdi_ctx_set_workspace (the op then never
+ *    allocates, and fails with VDI_E_WORKSPACE if the block is too small), or
+ *    the context's own block, grown when a larger problem arrives (growing it
+ *    synchronises the device and allocates, so reserve it beforehand with
+ *    vdi_ctx_reserve_workspace where a call must not allocate, e.g. under
+ *    graph capture).  The workspace is shared by all calls on a context:
+ *    calls on different streams of one context must not run concurrently.
  *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
  *    Work is enqueued on it and the call returns without synchronising.
  *  - Shape and argument errors are detected on the host before any launch and
@@ -44,7 +48,8 @@ typedef enum {
     VDI_E_UNSUPPORTED = -2, /* valid but beyond this library's limits (below) */
     VDI_E_HIP = -3,         /* a HIP runtime call failed */
     VDI_E_INPUT = -4,       /* input data violates a precondition (checked on the device; see vdi_ctx_device_status) */
-    VDI_E_CAPACITY = -5     /* a compact output does not fit its capacity */
+    VDI_E_CAPACITY = -5,    /* a compact output does not fit its capacity */
+    VDI_E_WORKSPACE = -6    /* the caller's workspace is smaller than the call needs */
 } vdi_status;
 
 typedef enum { VDI_LAYOUT_REGULAR = 0, VDI_LAYOUT_COMPACT = 1 } vdi_layout;
@@ -176,6 +181,38 @@ typedef struct {
 vdi_status vdi_ctx_create(vdi_ctx **out, int device);
 vdi_status vdi_ctx_destroy(vdi_ctx *ctx);
 const char *vdi_last_error(void);
+
+/* Workspace (device scratch memory) of an op, for the shape it is called
+ * with; 0 when the op needs none.  Ops whose workspace is known from this
+ * shape: VDI_OP_GENERATE (vdi_generate: width, height = camera size, k
+ * bricks, layout of the outputs, tau_mode), VDI_OP_COMPOSITE (vdi_composite:
+ * width, height, k inputs, in_max_n_sum = sum of the inputs' max_n),
+ * VDI_OP_MLP_BACKWARD (vdi_mlp_backward: rows).  Other ops need none.  The
+ * bytes depend on the device (its compute-unit count) but not on the data. */
+typedef enum { VDI_OP_GENERATE = 0, VDI_OP_COMPOSITE = 1, VDI_OP_MLP_BACKWARD = 2 } vdi_op;
+typedef struct {
+    int32_t op;              /* vdi_op */
+    int32_t width, height;
+    int32_t k;
+    int32_t layout;          /* GENERATE: vdi_layout of the outputs */
+    int32_t tau_mode;        /* GENERATE: vdi_tau_mode */
+    int32_t in_max_n_sum;    /* COMPOSITE */
+    int32_t rows;            /* MLP_BACKWARD */
+} vdi_shape_t;
+vdi_status vdi_workspace_size(vdi_ctx *ctx, const vdi_shape_t *shape, size_t *bytes);
+
+/* Caller-owned workspace: a DEVICE block of `bytes` (256-byte aligned) that
+ * every later op on ctx uses as its scratch memory instead of allocating;
+ * it must stay valid until replaced.  The context's own block is freed.
+ * workspace = NULL returns to the context's own, growing block.
+ * Synchronises the device. */
+vdi_status vdi_ctx_set_workspace(vdi_ctx *ctx, void *workspace, size_t bytes);
+
+/* Grows the context's own workspace to at least `bytes` now (allocates and
+ * synchronises the device if it grows), so that later ops of that size
+ * neither allocate nor synchronise.  VDI_E_INVALID while a caller workspace
+ * is set. */
+vdi_status vdi_ctx_reserve_workspace(vdi_ctx *ctx, size_t bytes);
 
 /* Sub-VDI generation (Sec. 5.1, Sec. 4, Eq. 1).  For each brick r < k, every
  * pixel's ray is sampled front to back on the global sample grid (sample i

@@ -40,7 +40,15 @@ vdi_status launched()
 
 vdi_status ensure_scratch(vdi_ctx* ctx, size_t bytes)
 {
+    if (ctx->user_ws) {
+        if (bytes > ctx->user_ws_bytes)
+            return fail(VDI_E_WORKSPACE, "the call needs %zu bytes of workspace, %zu were set", bytes,
+                        ctx->user_ws_bytes);
+        return VDI_OK;
+    }
     if (bytes <= ctx->scratch_bytes) return VDI_OK;
+    // growing the library's own scratch: the old block may still be read by
+    // work in flight on any stream
     if (ctx->scratch) {
         VDI_HIP_CHECK(hipDeviceSynchronize());
         VDI_HIP_CHECK(hipFree(ctx->scratch));
@@ -52,6 +60,8 @@ vdi_status ensure_scratch(vdi_ctx* ctx, size_t bytes)
     ctx->scratch_bytes = sz;
     return VDI_OK;
 }
+
+char* ws_base(vdi_ctx* ctx) { return (char*)(ctx->user_ws ? ctx->user_ws : ctx->scratch); }
 
 static Cam to_cam(const vdi_camera_t* c)
 {
@@ -81,8 +91,13 @@ static vdi_status check_vdi(const vdi_t* v, const char* what, bool allow_compact
     if (v->layout == VDI_LAYOUT_COMPACT) {
         if (!allow_compact) return fail(VDI_E_INVALID, "%s must use the regular layout", what);
         if (!v->offset) return fail(VDI_E_INVALID, "%s: compact layout needs offset", what);
+        // the kernels address entries with 32-bit offsets
+        if (v->capacity >= ((uint64_t)1 << 32))
+            return fail(VDI_E_UNSUPPORTED, "%s: compact capacity of 2^32 entries or more", what);
     } else if (v->layout != VDI_LAYOUT_REGULAR) {
         return fail(VDI_E_INVALID, "%s: unknown layout %d", what, v->layout);
+    } else if ((uint64_t)v->max_n * (uint64_t)v->width * (uint64_t)v->height >= ((uint64_t)1 << 32)) {
+        return fail(VDI_E_UNSUPPORTED, "%s: max_n * width * height of 2^32 entries or more", what);
     }
     return VDI_OK;
 }
@@ -173,6 +188,50 @@ static LearnScratch learn_layout(size_t rays, int nb, size_t nblk)
     return L;
 }
 
+// Workspace bytes of vdi_generate: the learned path's buffers; for compact
+// outputs a gamma plane per brick of a launch and the prefix-sum partials.
+static size_t generate_ws_bytes(int k, int width, int height, bool compact, bool learned)
+{
+    const size_t npix = (size_t)width * height;
+    if (learned) {
+        const size_t nblk = (size_t)((width + 15) / 16) * (size_t)((height + 15) / 16);
+        return learn_layout(npix * (size_t)k, k, nblk).total;
+    }
+    if (compact) return npix * sizeof(float) * kGenBricksPerLaunch + scan_scratch_bytes(npix) + 256;
+    return 0;
+}
+
+// Workspace of vdi_mlp_backward: one partial gradient per block of rows.
+static size_t mlp_bwd_ws_bytes(int rows)
+{
+    const size_t nb = ((size_t)rows + mlp_rows_per_block() - 1) / mlp_rows_per_block();
+    return nb * mlp_params() * sizeof(float);
+}
+
+// Workspace of vdi_composite: the queue of pixels left to the general merge
+// ([npix] + counter), the block order of the depth-disjoint pass (order and
+// bucket per block), then one staging slab per general-merge block (seq_cap
+// * 64 entries of 24 bytes), at most 2 GiB of slabs (on the dense
+// interleaved case 2 GiB, about four waves per SIMD, were 5% faster than
+// 1 GiB and as fast as 4 GiB).
+struct CompWs {
+    size_t qbytes, obytes, grid, slab, total;
+};
+static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int seq_cap, size_t lds)
+{
+    CompWs W;
+    const size_t nblk = (npix + 63) / 64;
+    const int per_cu = std::max(1, std::min<int>((int)((160 * 1024) / (lds + 64)), 28));
+    W.slab = (size_t)seq_cap * 64;
+    W.grid = (size_t)ctx->num_cus * per_cu;
+    W.grid = std::min<size_t>(W.grid, nblk);
+    W.grid = std::max<size_t>(1, std::min<size_t>(W.grid, ((size_t)1 << 31) / (W.slab * 24)));
+    W.qbytes = ((npix + 64) * sizeof(int) + 255) & ~(size_t)255;
+    W.obytes = (2 * nblk * sizeof(uint32_t) + 255) & ~(size_t)255;
+    W.total = W.qbytes + W.obytes + W.grid * W.slab * 24;
+    return W;
+}
+
 static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const GenParams& P,
                                    const vdi_tau_t* tau, vdi_t* out, int dtype, hipStream_t s)
 {
@@ -184,9 +243,9 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
     const size_t nblk = (size_t)((P.cam.width + 15) / 16) * (size_t)((P.cam.height + 15) / 16);
     const size_t nq = (size_t)k * nblk;
     LearnScratch Ls = learn_layout(rays, k, nblk);
-    vdi_status st = ensure_scratch(ctx, Ls.total);
+    vdi_status st = ensure_scratch(ctx, generate_ws_bytes(k, P.cam.width, P.cam.height, false, true));
     if (st != VDI_OK) return st;
-    char* base = (char*)ctx->scratch;
+    char* base = ws_base(ctx);
     LearnBufs Lb;
     memset(&Lb, 0, sizeof Lb);
     Lb.hist = (uint16_t*)(base + Ls.hist);
@@ -239,6 +298,67 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
     return phase(2);                            // round two and the plain bisection
 }
 
+// Checks the arguments of a composite and fills its parameter block (all
+// but the scratch pointers).
+static vdi_status composite_params(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* tau, vdi_t* out,
+                                   CompParams& P)
+{
+    if (!ctx || !in || !out) return fail(VDI_E_INVALID, "NULL argument");
+    if (k < 1 || k > VDI_MAX_INPUTS) return fail(VDI_E_INVALID, "k=%d outside [1, %d]", k, VDI_MAX_INPUTS);
+    vdi_status st = check_tau(tau, false);
+    if (st != VDI_OK) return st;
+    if ((st = check_vdi(out, "out", false)) != VDI_OK) return st;
+    memset(&P, 0, sizeof P);
+    int seq_cap = 0;
+    for (int r = 0; r < k; ++r) {
+        if ((st = check_vdi(&in[r], "in", true)) != VDI_OK) return st;
+        if (in[r].width != out->width || in[r].height != out->height)
+            return fail(VDI_E_INVALID, "in[%d] is %dx%d, out %dx%d", r, in[r].width, in[r].height, out->width,
+                        out->height);
+        if (in[r].ref_step != out->ref_step) return fail(VDI_E_INVALID, "in[%d].ref_step differs from out", r);
+        P.in[r].color = (const float4*)in[r].color;
+        P.in[r].depth = (const float2*)in[r].depth;
+        P.in[r].count = in[r].count;
+        P.in[r].offset = in[r].offset;
+        P.in[r].max_n = in[r].max_n;
+        P.in[r].compact = in[r].layout == VDI_LAYOUT_COMPACT;
+        P.in[r].capacity = P.in[r].compact ? in[r].capacity
+                                           : (uint64_t)in[r].max_n * (uint64_t)in[r].width * in[r].height;
+        seq_cap += in[r].max_n;
+    }
+    P.k = k;
+    P.npix = (uint32_t)((size_t)out->width * out->height);
+    P.cache_bound = 0;
+    for (int r = 0; r < k; ++r)
+        if (in[r].layout == VDI_LAYOUT_COMPACT) P.cache_bound = 1;
+    P.inv_ref = 1.0f / out->ref_step;
+    P.mode = tau->mode;
+    P.tau = tau->tau;
+    P.iters = tau->iters;
+    P.gmax = tau->gamma_max;
+    P.out_n = out->max_n;
+    P.out_color = (float4*)out->color;
+    P.out_depth = (float2*)out->depth;
+    P.out_count = out->count;
+    P.out_gamma = out->gamma;
+    P.status = ctx->status;
+    P.seq_cap = seq_cap;
+    return VDI_OK;
+}
+
+// The composite's queue ([64] counter words, then [npix] pixels) and block
+// order ([nblk] order, [nblk] bucket) at base; qbytes as composite_ws gives.
+static void composite_queues(CompParams& P, char* base, size_t qbytes)
+{
+    P.q_count = (int*)base;
+    P.q_list = (int*)base + 64;
+    // slot-major inputs only: a block of compact inputs reads one stretch of
+    // each input, next to its neighbours' stretches, and loses that locality
+    // out of image order (measured slower)
+    P.order = P.cache_bound ? nullptr : (uint32_t*)(base + qbytes);
+    P.bucket = (uint32_t*)(base + qbytes) + composite_blocks(P);
+}
+
 }  // namespace vdi
 
 using namespace vdi;
@@ -263,6 +383,8 @@ vdi_status vdi_ctx_create(vdi_ctx** out, int device)
     c->device = device;
     c->scratch = nullptr;
     c->scratch_bytes = 0;
+    c->user_ws = nullptr;
+    c->user_ws_bytes = 0;
     c->num_cus = prop.multiProcessorCount;
     snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
     hipError_t e = hipMalloc(&c->status, 64);
@@ -278,12 +400,69 @@ vdi_status vdi_ctx_create(vdi_ctx** out, int device)
 vdi_status vdi_ctx_destroy(vdi_ctx* ctx)
 {
     if (!ctx) return VDI_OK;
-    hipSetDevice(ctx->device);
-    hipDeviceSynchronize();
-    if (ctx->scratch) hipFree(ctx->scratch);
-    if (ctx->status) hipFree(ctx->status);
+    // teardown: errors are not reported (the context is gone either way)
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->status) (void)hipFree(ctx->status);
     delete ctx;
     return VDI_OK;
+}
+
+vdi_status vdi_workspace_size(vdi_ctx* ctx, const vdi_shape_t* shape, size_t* bytes)
+{
+    if (!ctx || !shape || !bytes) return fail(VDI_E_INVALID, "NULL argument");
+    *bytes = 0;
+    switch (shape->op) {
+    case VDI_OP_GENERATE: {
+        if (shape->width <= 0 || shape->height <= 0 || shape->k < 1) return fail(VDI_E_INVALID, "bad width/height/k");
+        const bool learned = shape->tau_mode == VDI_TAU_LEARNED;
+        const bool compact = shape->layout == VDI_LAYOUT_COMPACT;
+        if (learned && compact) return fail(VDI_E_UNSUPPORTED, "learned thresholds need the regular layout");
+        *bytes = generate_ws_bytes(shape->k, shape->width, shape->height, compact, learned);
+        return VDI_OK;
+    }
+    case VDI_OP_COMPOSITE: {
+        if (shape->width <= 0 || shape->height <= 0 || shape->k < 1 || shape->k > VDI_MAX_INPUTS)
+            return fail(VDI_E_INVALID, "bad width/height/k");
+        if (shape->in_max_n_sum < shape->k || shape->in_max_n_sum > shape->k * VDI_MAX_N)
+            return fail(VDI_E_INVALID, "in_max_n_sum %d outside [k, k*%d]", shape->in_max_n_sum, VDI_MAX_N);
+        const size_t lds = composite_lds_bytes(shape->k, shape->in_max_n_sum, true);
+        if (lds > 160 * 1024) return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", shape->in_max_n_sum);
+        *bytes = composite_ws(ctx, (size_t)shape->width * shape->height, shape->in_max_n_sum, lds).total;
+        return VDI_OK;
+    }
+    case VDI_OP_MLP_BACKWARD:
+        if (shape->rows <= 0) return fail(VDI_E_INVALID, "rows must be > 0");
+        *bytes = mlp_bwd_ws_bytes(shape->rows);
+        return VDI_OK;
+    default:
+        return fail(VDI_E_INVALID, "unknown op %d", shape->op);
+    }
+}
+
+vdi_status vdi_ctx_set_workspace(vdi_ctx* ctx, void* workspace, size_t bytes)
+{
+    if (!ctx) return fail(VDI_E_INVALID, "ctx is NULL");
+    if (workspace && ((uintptr_t)workspace & 255) != 0) return fail(VDI_E_INVALID, "workspace must be 256-byte aligned");
+    VDI_HIP_CHECK(hipSetDevice(ctx->device));
+    VDI_HIP_CHECK(hipDeviceSynchronize());
+    if (workspace && ctx->scratch) {
+        VDI_HIP_CHECK(hipFree(ctx->scratch));
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+    }
+    ctx->user_ws = workspace;
+    ctx->user_ws_bytes = workspace ? bytes : 0;
+    return VDI_OK;
+}
+
+vdi_status vdi_ctx_reserve_workspace(vdi_ctx* ctx, size_t bytes)
+{
+    if (!ctx) return fail(VDI_E_INVALID, "ctx is NULL");
+    if (ctx->user_ws) return fail(VDI_E_INVALID, "the context uses a caller workspace");
+    VDI_HIP_CHECK(hipSetDevice(ctx->device));
+    return ensure_scratch(ctx, bytes);
 }
 
 vdi_status vdi_ctx_device_status(vdi_ctx* ctx, int32_t* flags, void* stream)
@@ -372,11 +551,10 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
     P.status = ctx->status;
 
     // compact outputs without a gamma plane borrow scratch for it
-    size_t gamma_bytes = 0, scan_bytes = 0;
+    size_t gamma_bytes = 0;
     if (compact) {
         gamma_bytes = npix * sizeof(float) * kGenBricksPerLaunch;
-        scan_bytes = scan_scratch_bytes(npix);
-        st = ensure_scratch(ctx, gamma_bytes + scan_bytes + 256);
+        st = ensure_scratch(ctx, generate_ws_bytes(k, cam->width, cam->height, true, false));
         if (st != VDI_OK) return st;
     }
     if (learned) return generate_learned(ctx, bricks, k, P, tau, out, dtype, s);
@@ -397,7 +575,7 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
             g.depth = (float2*)o.depth;
             g.count = o.count;
             g.gamma = o.gamma;
-            if (compact && !g.gamma) g.gamma = (float*)ctx->scratch + (size_t)i * npix;
+            if (compact && !g.gamma) g.gamma = (float*)ws_base(ctx) + (size_t)i * npix;
             g.offset = o.offset;
             g.capacity = o.capacity;
             for (int a = 0; a < 3; ++a) {
@@ -415,7 +593,7 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
         // compact (Sec. 4): search -> prefix sum of counts -> write at offsets
         launch_generate(1, dtype, P, B, nb, s);
         if ((st = launched()) != VDI_OK) return st;
-        void* scan_scratch = (char*)ctx->scratch + gamma_bytes;
+        void* scan_scratch = ws_base(ctx) + gamma_bytes;
         for (int i = 0; i < nb; ++i) {
             launch_scan(out[r0 + i].count, out[r0 + i].offset, npix, scan_scratch, s);
             if ((st = launched()) != VDI_OK) return st;
@@ -428,77 +606,19 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
 
 vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* tau, vdi_t* out, void* stream)
 {
-    if (!ctx || !in || !out) return fail(VDI_E_INVALID, "NULL argument");
-    if (k < 1 || k > VDI_MAX_INPUTS) return fail(VDI_E_INVALID, "k=%d outside [1, %d]", k, VDI_MAX_INPUTS);
-    vdi_status st = check_tau(tau, false);
-    if (st != VDI_OK) return st;
-    if ((st = check_vdi(out, "out", false)) != VDI_OK) return st;
     CompParams P;
-    memset(&P, 0, sizeof P);
-    int seq_cap = 0;
-    for (int r = 0; r < k; ++r) {
-        if ((st = check_vdi(&in[r], "in", true)) != VDI_OK) return st;
-        if (in[r].width != out->width || in[r].height != out->height)
-            return fail(VDI_E_INVALID, "in[%d] is %dx%d, out %dx%d", r, in[r].width, in[r].height, out->width,
-                        out->height);
-        if (in[r].ref_step != out->ref_step) return fail(VDI_E_INVALID, "in[%d].ref_step differs from out", r);
-        P.in[r].color = (const float4*)in[r].color;
-        P.in[r].depth = (const float2*)in[r].depth;
-        P.in[r].count = in[r].count;
-        P.in[r].offset = in[r].offset;
-        P.in[r].max_n = in[r].max_n;
-        P.in[r].compact = in[r].layout == VDI_LAYOUT_COMPACT;
-        P.in[r].capacity = P.in[r].compact ? in[r].capacity
-                                           : (uint64_t)in[r].max_n * (uint64_t)in[r].width * in[r].height;
-        seq_cap += in[r].max_n;
-    }
+    vdi_status st = composite_params(ctx, in, k, tau, out, P);
+    if (st != VDI_OK) return st;
     // the general merge stages merged lists in scratch (no merge sequence in LDS)
-    const size_t lds = composite_lds_bytes(k, seq_cap, true);
-    if (lds > 160 * 1024) return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", seq_cap);
-    P.k = k;
-    P.npix = (uint32_t)((size_t)out->width * out->height);
-    P.cache_bound = 0;
-    for (int r = 0; r < k; ++r)
-        if (in[r].layout == VDI_LAYOUT_COMPACT) P.cache_bound = 1;
-    P.inv_ref = 1.0f / out->ref_step;
-    P.mode = tau->mode;
-    P.tau = tau->tau;
-    P.iters = tau->iters;
-    P.gmax = tau->gamma_max;
-    P.out_n = out->max_n;
-    P.out_color = (float4*)out->color;
-    P.out_depth = (float2*)out->depth;
-    P.out_count = out->count;
-    P.out_gamma = out->gamma;
-    P.status = ctx->status;
-    P.seq_cap = seq_cap;
-    // scratch: the queue of pixels left to the general merge ([npix] +
-    // counter), then one staging slab per general-merge block (seq_cap * 64
-    // entries of 24 bytes), at most 2 GiB of slabs (on the dense interleaved
-    // case 2 GiB, about four waves per SIMD, were 5% faster than 1 GiB and
-    // as fast as 4 GiB)
-    const int per_cu = std::max(1, std::min<int>((int)((160 * 1024) / (lds + 64)), 28));
-    const size_t slab = (size_t)seq_cap * 64;
-    size_t grid = (size_t)ctx->num_cus * per_cu;
-    grid = std::min<size_t>(grid, composite_blocks(P));
-    grid = std::max<size_t>(1, std::min<size_t>(grid, ((size_t)1 << 31) / (slab * 24)));
-    // then the block order of the depth-disjoint pass (order and bucket per
-    // block)
-    const size_t qbytes = (((size_t)P.npix + 64) * sizeof(int) + 255) & ~(size_t)255;
-    const size_t nblk = composite_blocks(P);
-    const size_t obytes = (2 * nblk * sizeof(uint32_t) + 255) & ~(size_t)255;
-    if ((st = ensure_scratch(ctx, qbytes + obytes + grid * slab * 24)) != VDI_OK) return st;
-    char* base = (char*)ctx->scratch;
-    P.q_count = (int*)base;
-    P.q_list = (int*)base + 64;
-    // slot-major inputs only: a block of compact inputs reads one stretch of
-    // each input, next to its neighbours' stretches, and loses that locality
-    // out of image order (measured slower)
-    P.order = P.cache_bound ? nullptr : (uint32_t*)(base + qbytes);
-    P.bucket = (uint32_t*)(base + qbytes) + nblk;
-    P.stage_c = (float4*)(base + qbytes + obytes);
-    P.stage_d = (float2*)(base + qbytes + obytes + grid * slab * sizeof(float4));
-    launch_composite(P, (int)grid, (hipStream_t)stream);
+    const size_t lds = composite_lds_bytes(k, P.seq_cap, true);
+    if (lds > 160 * 1024) return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", P.seq_cap);
+    const CompWs W = composite_ws(ctx, P.npix, P.seq_cap, lds);
+    if ((st = ensure_scratch(ctx, W.total)) != VDI_OK) return st;
+    char* base = ws_base(ctx);
+    composite_queues(P, base, W.qbytes);
+    P.stage_c = (float4*)(base + W.qbytes + W.obytes);
+    P.stage_d = (float2*)(base + W.qbytes + W.obytes + W.grid * W.slab * sizeof(float4));
+    launch_composite(P, (int)W.grid, (hipStream_t)stream);
     return launched();
 }
 
@@ -642,10 +762,9 @@ vdi_status vdi_mlp_backward(vdi_ctx* ctx, const vdi_mlp_t* mlp, const uint16_t* 
     vdi_status st = check_mlp(mlp);
     if (st != VDI_OK) return st;
     if (rows <= 0) return fail(VDI_E_INVALID, "rows must be > 0");
-    int nb = (rows + mlp_rows_per_block() - 1) / mlp_rows_per_block();
-    st = ensure_scratch(ctx, (size_t)nb * mlp_params() * sizeof(float));
+    st = ensure_scratch(ctx, mlp_bwd_ws_bytes(rows));
     if (st != VDI_OK) return st;
-    launch_mlp_bwd(mlp->w_bf16, x, acts, dy, rows, (float*)ctx->scratch, grad, (hipStream_t)stream);
+    launch_mlp_bwd(mlp->w_bf16, x, acts, dy, rows, (float*)ws_base(ctx), grad, (hipStream_t)stream);
     return launched();
 }
 

@@ -20,8 +20,10 @@
 struct vdi_ctx {
     int device;
     int* status;          // device words: [0] flags, [4..7] learned-path counters
-    void* scratch;        // grown on demand, kept until destroy
+    void* scratch;        // library-owned scratch: grown on demand, kept until destroy
     size_t scratch_bytes;
+    void* user_ws;        // caller-owned workspace (vdi_ctx_set_workspace); when set, ops use it
+    size_t user_ws_bytes; // and never allocate
     int num_cus;
     char arch[64];
 };
@@ -33,7 +35,10 @@ namespace vdi {
 void set_error(const char* fmt, ...);
 vdi_status fail(vdi_status st, const char* fmt, ...);
 vdi_status launched();                       // VDI_E_HIP if the last launch failed
+// Workspace of an op: the caller's (VDI_E_WORKSPACE if smaller than bytes) or
+// the library's own, grown when too small; ws_base() is its start.
 vdi_status ensure_scratch(struct ::vdi_ctx* ctx, size_t bytes);
+char* ws_base(struct ::vdi_ctx* ctx);
 
 #define VDI_HIP_CHECK(expr)                                                          \
     do {                                                                             \

@@ -22,7 +22,7 @@ FIXED, BISECT, LEARNED, BISECT_SEQ = 0, 1, 2, 3
 F32, F16 = 0, 1
 
 _STATUS = {0: "VDI_OK", -1: "VDI_E_INVALID", -2: "VDI_E_UNSUPPORTED", -3: "VDI_E_HIP", -4: "VDI_E_INPUT",
-           -5: "VDI_E_CAPACITY"}
+           -5: "VDI_E_CAPACITY", -6: "VDI_E_WORKSPACE"}
 
 
 class VdiError(RuntimeError):
@@ -60,6 +60,15 @@ class vdi_tau_t(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tau", ctypes.c_float), ("iters", ctypes.c_int32),
                 ("gamma_max", ctypes.c_float), ("mlp", ctypes.c_void_p), ("fallback_tol", ctypes.c_float),
                 ("feature_scale", ctypes.c_float), ("y", ctypes.c_void_p)]
+
+
+class vdi_shape_t(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("tau_mode", ctypes.c_int32), ("in_max_n_sum", ctypes.c_int32),
+                ("rows", ctypes.c_int32)]
+
+
+OP_GENERATE, OP_COMPOSITE, OP_MLP_BACKWARD = 0, 1, 2
 
 
 class vdi_mlp_t(ctypes.Structure):
@@ -102,6 +111,11 @@ def lib():
                                    ctypes.c_float, ctypes.c_float, P]
         L.vdi_learned_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), P]
         L.vdi_debug_mfma.argtypes = [P, P, P, P, P]
+        L.vdi_workspace_size.argtypes = [P, ctypes.POINTER(vdi_shape_t), ctypes.POINTER(ctypes.c_size_t)]
+        L.vdi_ctx_set_workspace.argtypes = [P, P, ctypes.c_size_t]
+        L.vdi_ctx_reserve_workspace.argtypes = [P, ctypes.c_size_t]
+        for name in ("vdi_workspace_size", "vdi_ctx_set_workspace", "vdi_ctx_reserve_workspace"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("vdi_ctx_create", "vdi_ctx_destroy", "vdi_ctx_device_status", "vdi_generate", "vdi_composite",
                      "vdi_render_original_view", "vdi_render_novel_view", "vdi_debug_rays", "vdi_tau_features",
                      "vdi_mlp_forward", "vdi_mlp_backward", "vdi_mlp_adam", "vdi_learned_stats", "vdi_debug_mfma"):
@@ -136,6 +150,36 @@ def _ptr(t: Optional[torch.Tensor]):
         return None
     assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous"
     return ctypes.c_void_p(t.data_ptr())
+
+
+def workspace_size(op: int, width: int = 0, height: int = 0, k: int = 0, layout: int = REGULAR,
+                   tau_mode: int = BISECT, in_max_n_sum: int = 0, rows: int = 0) -> int:
+    """Bytes of device scratch memory the op needs at this shape (vdi_workspace_size)."""
+    sh = vdi_shape_t(op, width, height, k, layout, tau_mode, in_max_n_sum, rows)
+    n = ctypes.c_size_t()
+    _check(lib().vdi_workspace_size(context(), ctypes.byref(sh), ctypes.byref(n)))
+    return int(n.value)
+
+
+_workspace = {}
+
+
+def set_workspace(ws: Optional[torch.Tensor]):
+    """Make `ws` (a device uint8 tensor, kept referenced here) the workspace of
+    every later op on this device's context; None returns to the context's own."""
+    dev = torch.cuda.current_device()
+    if ws is None:
+        _check(lib().vdi_ctx_set_workspace(context(), None, 0))
+        _workspace.pop(dev, None)
+        return
+    assert ws.is_cuda and ws.is_contiguous() and ws.dtype == torch.uint8
+    _check(lib().vdi_ctx_set_workspace(context(), _ptr(ws), ws.numel()))
+    _workspace[dev] = ws
+
+
+def reserve_workspace(nbytes: int):
+    """Grow the context's own workspace to nbytes now (vdi_ctx_reserve_workspace)."""
+    _check(lib().vdi_ctx_reserve_workspace(context(), int(nbytes)))
 
 
 # ---------------------------------------------------------------- Python-side VDI

@@ -28,7 +28,8 @@ def V():
 def test_header_declares_the_hot_path():
     names = _declared_functions()
     for must in ("vdi_generate", "vdi_composite", "vdi_render_original_view", "vdi_batch_create", "vdi_autotune",
-                 "vdi_mlp_forward", "vdi_mlp_backward", "vdi_mlp_adam", "vdi_tau_features", "vdi_render_novel_view"):
+                 "vdi_mlp_forward", "vdi_mlp_backward", "vdi_mlp_adam", "vdi_tau_features", "vdi_render_novel_view",
+                 "vdi_workspace_size", "vdi_ctx_set_workspace", "vdi_ctx_reserve_workspace"):
         assert must in names
     assert len(names) >= 20
 
@@ -43,7 +44,7 @@ def test_struct_layouts_match_header(V, tmp_path):
     """sizeof/offsetof from C (gcc, the header itself) against the ctypes mirrors."""
     fields = {
         "vdi_t": V.vdi_t, "vdi_brick_t": V.vdi_brick_t, "vdi_camera_t": V.vdi_camera_t, "vdi_tf_t": V.vdi_tf_t,
-        "vdi_tau_t": V.vdi_tau_t, "vdi_mlp_t": V.vdi_mlp_t, "vdi_job_t": V.vdi_job_t,
+        "vdi_tau_t": V.vdi_tau_t, "vdi_mlp_t": V.vdi_mlp_t, "vdi_job_t": V.vdi_job_t, "vdi_shape_t": V.vdi_shape_t,
     }
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "vdi.h"', "int main(void) {"]
     for cname, cls in fields.items():
