@@ -242,6 +242,22 @@ vdi_status vdi_generate(vdi_ctx *ctx, const vdi_brick_t *bricks, int k, const vd
 vdi_status vdi_composite(vdi_ctx *ctx, const vdi_t *in, int k, const vdi_tau_t *tau, vdi_t *out,
                          void *stream);
 
+/* vdi_composite for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same composite, with its scratch (the queue of pixels left to the
+ * general merge and the block order) in a fixed device array of the library,
+ * 32 MiB per device, held until the process ends, instead of the context's
+ * workspace.  It calls no allocator.  The general merge then keeps each
+ * pixel's merge sequence in LDS instead of staging merged lists.  The output
+ * equals vdi_composite's bit for bit.  Limits: 4*(H*W + 64) + 8*ceil(H*W/64)
+ * bytes of scratch must fit in 32 MiB (about 8.1 million pixels), and the
+ * merged lists' capacity (sum of the inputs' max_n) must leave the merge
+ * sequence room in LDS; beyond either VDI_E_UNSUPPORTED.  Every call on a
+ * device shares that device's array (also across contexts): calls that
+ * overlap on one device race, so serialise them (one stream, or events). */
+vdi_status vdi_composite_noalloc(vdi_ctx *ctx, const vdi_t *in, int k, const vdi_tau_t *tau, vdi_t *out,
+                                 void *stream);
+
 /* Rendering from the viewpoint of generation (Sec. 2.3): per pixel, the
  * supersegments are composited front to back with the over operator using
  * their total opacities.  rgba: [H*W][4] premultiplied, fp32. */

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "vdi_internal.h"
@@ -62,6 +63,33 @@ vdi_status ensure_scratch(vdi_ctx* ctx, size_t bytes)
 }
 
 char* ws_base(vdi_ctx* ctx) { return (char*)(ctx->user_ws ? ctx->user_ws : ctx->scratch); }
+
+// Scratch of vdi_composite_noalloc: a fixed device array (each device holds
+// its own copy until the process ends).  Its name is a host-side stand-in in
+// host code; the kernels get the device address that hipGetSymbolAddress
+// returns for the current device, looked up once per device at context set-up.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_mu;
+static void* g_static_ptr[kMaxDevices];
+
+// Device address of `scratch` on `device` (current); VDI_E_HIP if the lookup fails.
+static vdi_status static_scratch_ptr(int device, void** ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(VDI_E_UNSUPPORTED, "device %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(VDI_E_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_static_ptr[device] = p;
+    }
+    *ptr = g_static_ptr[device];
+    return VDI_OK;
+}
 
 static Cam to_cam(const vdi_camera_t* c)
 {
@@ -379,8 +407,12 @@ vdi_status vdi_ctx_create(vdi_ctx** out, int device)
     VDI_HIP_CHECK(hipGetDeviceProperties(&prop, device));
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(VDI_E_UNSUPPORTED, "libvdi is built for gfx950, device is %s", prop.gcnArchName);
+    void* sptr = nullptr;
+    vdi_status sst = static_scratch_ptr(device, &sptr);
+    if (sst != VDI_OK) return sst;
     vdi_ctx* c = new vdi_ctx();
     c->device = device;
+    c->static_scratch = sptr;
     c->scratch = nullptr;
     c->scratch_bytes = 0;
     c->user_ws = nullptr;
@@ -618,6 +650,28 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     composite_queues(P, base, W.qbytes);
     P.stage_c = (float4*)(base + W.qbytes + W.obytes);
     P.stage_d = (float2*)(base + W.qbytes + W.obytes + W.grid * W.slab * sizeof(float4));
+    launch_composite(P, (int)W.grid, (hipStream_t)stream);
+    return launched();
+}
+
+vdi_status vdi_composite_noalloc(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* tau, vdi_t* out,
+                                 void* stream)
+{
+    CompParams P;
+    vdi_status st = composite_params(ctx, in, k, tau, out, P);
+    if (st != VDI_OK) return st;
+    // no staging slabs: the general merge keeps its merge sequence in LDS
+    const size_t lds = composite_lds_bytes(k, P.seq_cap, false);
+    if (lds > 160 * 1024)
+        return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large for the merge sequence in LDS", P.seq_cap);
+    const CompWs W = composite_ws(ctx, P.npix, P.seq_cap, lds);
+    const size_t need = W.qbytes + W.obytes;
+    if (need > kStaticScratchBytes)
+        return fail(VDI_E_UNSUPPORTED, "%u pixels need %zu bytes of scratch, more than the fixed %zu", P.npix, need,
+                    kStaticScratchBytes);
+    composite_queues(P, (char*)ctx->static_scratch, W.qbytes);
+    P.stage_c = nullptr;
+    P.stage_d = nullptr;
     launch_composite(P, (int)W.grid, (hipStream_t)stream);
     return launched();
 }

@@ -24,6 +24,7 @@ struct vdi_ctx {
     size_t scratch_bytes;
     void* user_ws;        // caller-owned workspace (vdi_ctx_set_workspace); when set, ops use it
     size_t user_ws_bytes; // and never allocate
+    void* static_scratch; // device address of the fixed scratch array on this device
     int num_cus;
     char arch[64];
 };

@@ -98,6 +98,9 @@ def lib():
                                    ctypes.POINTER(vdi_tf_t), ctypes.c_float, ctypes.POINTER(vdi_tau_t),
                                    ctypes.POINTER(vdi_t), P]
         L.vdi_composite.argtypes = [P, ctypes.POINTER(vdi_t), I, ctypes.POINTER(vdi_tau_t), ctypes.POINTER(vdi_t), P]
+        L.vdi_composite_noalloc.argtypes = [P, ctypes.POINTER(vdi_t), I, ctypes.POINTER(vdi_tau_t),
+                                            ctypes.POINTER(vdi_t), P]
+        L.vdi_composite_noalloc.restype = ctypes.c_int
         L.vdi_render_original_view.argtypes = [P, ctypes.POINTER(vdi_t), P, P]
         L.vdi_render_novel_view.argtypes = [P, ctypes.POINTER(vdi_t), ctypes.POINTER(vdi_camera_t),
                                             ctypes.POINTER(vdi_camera_t), ctypes.c_float, P, P]
@@ -311,8 +314,9 @@ def generate(bricks: Sequence[DeviceBrick], cam, tf: torch.Tensor, step: float, 
 
 
 def composite(vdis: Sequence[VDI], mode: int, tau: float = 0.0, max_n: int = 8, iters: int = 10,
-              out: Optional[VDI] = None, gamma_max: float = 2.0) -> VDI:
-    """vdi_composite: k-way merge + re-segmentation into one regular VDI."""
+              out: Optional[VDI] = None, gamma_max: float = 2.0, noalloc: bool = False) -> VDI:
+    """vdi_composite: k-way merge + re-segmentation into one regular VDI
+    (noalloc: vdi_composite_noalloc, scratch in the library's fixed array)."""
     k = len(vdis)
     v0 = vdis[0]
     if out is None:
@@ -320,7 +324,8 @@ def composite(vdis: Sequence[VDI], mode: int, tau: float = 0.0, max_n: int = 8, 
     ic = (vdi_t * k)(*[v.c() for v in vdis])
     oc = out.c()
     tc = tau_c(mode, tau, iters, gamma_max)
-    _check(lib().vdi_composite(context(), ic, k, ctypes.byref(tc), ctypes.byref(oc), _stream()))
+    fn = lib().vdi_composite_noalloc if noalloc else lib().vdi_composite
+    _check(fn(context(), ic, k, ctypes.byref(tc), ctypes.byref(oc), _stream()))
     return out
 
 
