@@ -280,11 +280,26 @@ static orc_segrun segrun(double gamma, int cap, int gaps, double ref, int limit,
     return R;
 }
 
+/* 1 - 2^y for y <= 0, accurate also for y near 0 (expm1); 1 at y = -inf. */
+static double one_minus_pow2(double y)
+{
+    return -expm1(y * 0.69314718055994530942);
+}
+
+/* log2(1 - a) for a in [0, 1], accurate also for small a (log1p); -inf at a = 1. */
+static double log2_1m(double a)
+{
+    return log1p(-a) / 0.69314718055994530942;
+}
+
 typedef struct {
     int open;
     double f, b, bt;
     double C[3];        /* premultiplied colour accumulated front to back */
-    double T;           /* transmittance of the open supersegment */
+    double lT;          /* log2 of the transmittance of the open supersegment
+                           (the product of its elements' Eq. 2 factors, in log
+                           form so that it holds transmittances below fp64's
+                           range; -inf when an element is opaque) */
     int nel;            /* elements it holds */
 } orc_state;
 
@@ -292,12 +307,12 @@ static void seg_close(orc_state *S, orc_segrun *R)
 {
     if (R->out && R->count < R->max_out) {
         orc_sseg *o = &R->out[R->count];
-        double A = 1.0 - S->T;
+        double A = one_minus_pow2(S->lT);
         o->f = S->f;
         o->b = S->bt;
         for (int ch = 0; ch < 3; ++ch) o->rgb[ch] = A > 0.0 ? S->C[ch] / A : 0.0;
         /* opacity per reference step over the stored extent [f, bt] */
-        o->a = 1.0 - pow(S->T, R->ref / (S->bt - S->f));
+        o->a = one_minus_pow2(S->lT * (R->ref / (S->bt - S->f)));
     }
     R->count += 1;
     S->open = 0;
@@ -309,11 +324,16 @@ static void seg_step(orc_state *S, orc_segrun *R, const orc_elem *e)
 {
     int transparent = (e->a == 0.0);
     double l = (e->b - e->f) / R->ref;
-    double at = transparent ? 0.0 : 1.0 - pow(1.0 - e->a, l);   /* Eq. 2 */
+    /* Eq. 2: the element's transmittance (1 - a)^l (as log2, l log2(1 - a)),
+     * and its opacity one minus that.  The transmittance is kept as computed,
+     * not as 1 - opacity, which rounds to 0 once (1 - a)^l is below half an
+     * ulp of 1. */
+    double le = transparent ? 0.0 : l * log2_1m(e->a);
+    double at = one_minus_pow2(le);
     if (S->open) {
         double L = (S->b - S->f) / R->ref;
-        double A = 1.0 - S->T;
-        double aS = 1.0 - pow(S->T, 1.0 / L);
+        double A = one_minus_pow2(S->lT);
+        double aS = one_minus_pow2(S->lT / L);
         double d2 = 0.0;
         for (int ch = 0; ch < 3; ++ch) {
             double repS = A > 0.0 ? S->C[ch] / A * aS : 0.0;
@@ -338,8 +358,9 @@ static void seg_step(orc_state *S, orc_segrun *R, const orc_elem *e)
         if (close) {
             seg_close(S, R);
         } else {
-            for (int ch = 0; ch < 3; ++ch) S->C[ch] += S->T * e->rgb[ch] * at;
-            S->T *= 1.0 - at;
+            double T = exp2(S->lT);
+            for (int ch = 0; ch < 3; ++ch) S->C[ch] += T * e->rgb[ch] * at;
+            S->lT += le;
             S->b = e->b;
             if (!transparent) S->bt = e->b;
             S->nel += 1;
@@ -350,7 +371,7 @@ static void seg_step(orc_state *S, orc_segrun *R, const orc_elem *e)
         S->f = e->f;
         S->b = S->bt = e->b;
         for (int ch = 0; ch < 3; ++ch) S->C[ch] = e->rgb[ch] * at;
-        S->T = 1.0 - at;
+        S->lT = le;
         S->nel = 1;
     }
 }

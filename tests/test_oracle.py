@@ -213,6 +213,25 @@ def test_segmenter_constant_run_is_one_segment(orc):
         np.testing.assert_allclose(segs[0], [0, 50, 0.3, 0.6, 0.1, 0.25], atol=1e-12)
 
 
+@pytest.mark.parametrize("a,l", [(0.25, 1.0), (0.98992, 13.0), (0.999999, 40.0), (1.0, 7.0)],
+                         ids=["plain", "near-opaque-long", "opaque-beyond-fp64", "opaque"])
+def test_segmenter_single_element_keeps_its_opacity(orc, a, l):
+    """A supersegment holding one element (or a constant run of it) stores that
+    element: its transmittance is (1 - a)^l (Eq. 2), and the per-unit opacity
+    over its length l is 1 - ((1 - a)^l)^(1/l) = a (R13).  Near-opaque long
+    elements have (1 - a)^l far below an ulp of 1, where 1 - (Eq. 2 opacity)
+    would round the transmittance to 0 and the stored opacity to 1."""
+    one = np.array([[2.0, 2.0 + l, 0.6, 0.3, 0.1, a]], float)
+    for gaps in (False, True):
+        segs, count, _, _ = orc.seg(one, orc.FIXED, gamma=5.0, gaps=gaps)
+        assert count == 1
+        np.testing.assert_allclose(segs[0], one[0], rtol=1e-12, atol=0)
+    run = np.array([[2.0 + i * l, 2.0 + (i + 1) * l, 0.6, 0.3, 0.1, a] for i in range(3)], float)
+    segs, count, _, _ = orc.seg(run, orc.FIXED, gamma=5.0, gaps=True)
+    assert count == 1
+    np.testing.assert_allclose(segs[0], [2.0, 2.0 + 3 * l, 0.6, 0.3, 0.1, a], rtol=1e-12, atol=0)
+
+
 def test_segmenter_every_sample_lands_in_exactly_one_segment(orc):
     """Rendering the supersegments equals the DVR of the samples for any gamma
     (associativity of over, Sec. 2.3), and segments are ordered and disjoint."""
