@@ -1,23 +1,29 @@
 """Benchmark of the VDI hot path on one MI355X.
 
-A step is one frame of the whole path on the FHD workload: generate the 8
-sub-VDIs of a 512^3 fp32 volume split into z-slabs (per-ray bisection of the
-threshold to N=20, regular slot-major layout; --layout compact for the compact
-one), composite them into one N=20 VDI and render it from the original view.  The headline metric is composited VDI pixels per
-second of that step.  Further legs (same JSON line):
+Headline (the step): the composite of the large one-GPU share on dense,
+maximally interleaved inputs -- 16 regular sub-VDIs of 1920x1080 pixels with
+20 supersegments per pixel each (15.9 GB), depth-merged and re-segmented by
+the per-pixel bisection into one N=20 VDI, then rendered from the original
+view.  The metric is composited VDI pixels per second of that step, with the
+composite's algorithmic bytes against the 8 TB/s HBM peak.  Further legs
+(same JSON line):
+  fhd      -- the FHD frame: generate the 8 sub-VDIs of a 512^3 fp32 volume in
+              z-slabs (per-ray bisection to N=20), composite, render; per-stage
+              times, the composite's HBM roofline and the generation kernel's
+              VALU roofline;
   novel    -- that composited VDI rendered at 5, 20 and 50 degrees from its
               viewpoint: time per frame, SSIM and PSNR against DVR there;
   masks    -- the FHD volume on 8 non-convex domains (wavy z-slabs, owner map):
               generate + composite, rendering checked against the slab one;
-  large    -- 1024^3 fp16 volume in 16 bricks (4x2x2): generate + composite,
-              and the composite alone on maximally interleaved dense lists
-              (16 x 20 supersegments per pixel, 16.6 GB of input);
-  dense    -- only that dense composite (implied by large);
+  large    -- 1024^3 fp16 volume in 16 bricks (4x2x2): generate + composite;
   learned  -- learned vs plain threshold search on held-out tiny volumes (N=8)
               and on held-out FHD-generator volumes (N=20), the regressor
               trained here with the project's kernels;
   batched  -- 64 composites of mixed size, k and N in one persistent launch
               replayed from a hipGraph: jobs/s and per-job latency.
+The CPU baseline is the oracle on a seeded pixel sample of the headline frame
+(all host threads), its lists compared with the GPU's; the same comparison
+runs on a sample of the FHD frame (generation and composite).
 Printed: ONE JSON line on stdout (progress goes to stderr).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--legs fhd,novel,masks,large,learned,batched]
@@ -34,13 +40,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# fp32 vector lanes: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one non-packed op per lane and cycle)
-VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# fp32 vector issue: 256 CUs x 4 SIMDs x 32 lanes per cycle x 2.4 GHz = 78.6e12
+# lane-instructions/s (157.3 TFLOP/s counting an FMA as two)
+VALU_PEAK_TLANE = 256 * 4 * 32 * 2.4e9 / 1e12
 
-# sources of the composite kernels; a traffic figure measured on other sources is not reported
+# sources of the kernels; a counter figure measured on other sources is not reported
 COMPOSITE_SOURCES = ("paper_2206_14503_amd/csrc/vdi_composite.hip", "paper_2206_14503_amd/csrc/vdi_internal.h",
                      "paper_2206_14503_amd/csrc/vdi_kernels.h")
-PMC_SUMMARY = "profiles/composite_fhd_pmc.md"
+GENERATE_SOURCES = ("paper_2206_14503_amd/csrc/vdi_generate.hip", "paper_2206_14503_amd/csrc/vdi_internal.h",
+                    "paper_2206_14503_amd/csrc/vdi_kernels.h")
+DENSE_PMC = "profiles/composite_dense_pmc.md"
+FHD_PMC = "profiles/composite_fhd_pmc.md"
+GEN_SQ = "profiles/generate_fhd_sq.md"
 
 
 def log(*a):
@@ -56,24 +67,55 @@ def source_digest(paths=COMPOSITE_SOURCES) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by the
-    factor a 1 GiB device copy gives), or None when there is none or it was
-    taken on other kernel sources."""
-    path = os.path.join(ROOT, PMC_SUMMARY)
+def counter_line(summary: str, sources):
+    """The `pmc: {json}` line of a committed rocprofv3 counter summary, or
+    (None, why) when there is none or it was taken on other kernel sources."""
+    path = os.path.join(ROOT, summary)
     if not os.path.exists(path):
-        return None, "no counter summary"
+        return None, f"no counter summary {summary}"
     for line in open(path):
         if line.startswith("pmc: "):
             d = json.loads(line[5:])
-            if d.get("source_sha256") != source_digest():
+            if d.get("source_sha256") != source_digest(sources):
                 return None, "kernel sources changed since the counters were taken"
-            k = d.get("kernels", {}).get(kernel)
-            if not k:
-                return None, f"no counters for {kernel}"
-            return (k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024.0, "measured"
+            return d, "measured"
     return None, "no counter line"
+
+
+def measured_traffic(kernel: str, summary: str = DENSE_PMC):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by the
+    factor a 1 GiB device copy gives), or None with the reason."""
+    d, why = counter_line(summary, COMPOSITE_SOURCES)
+    if d is None:
+        return None, why
+    k = d.get("kernels", {}).get(kernel)
+    if not k or "fetch_kib" not in k:
+        return None, f"no traffic counters for {kernel}"
+    return (k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024.0, "measured"
+
+
+def measured_valu(kernel: str, summary: str = GEN_SQ):
+    """VALU wave-instructions per launch of `kernel` (SQ_INSTS_VALU) from a
+    committed counter summary, or None with the reason."""
+    d, why = counter_line(summary, GENERATE_SOURCES)
+    if d is None:
+        return None, why
+    k = d.get("kernels", {}).get(kernel)
+    if not k or "valu_insts" not in k:
+        return None, f"no VALU counters for {kernel}"
+    return float(k["valu_insts"]), "measured"
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def composite_bytes(inputs, out_n, npix, counts_total):
@@ -108,7 +150,102 @@ def timed_ms(fn, reps):
     return np.array(out)
 
 
-# ---------------------------------------------------------------- FHD (headline)
+# ---------------------------------------------------------------- headline: dense composite
+
+DENSE_KERNEL = "composite_queue_kernel"
+
+
+def leg_dense(args, result):
+    """The step: composite 16 dense interleaved sub-VDIs (20 supersegments per
+    pixel each, 1920x1080) into one N=20 VDI and render it.  Returns a seeded
+    pixel sample of the inputs and of the GPU's output for the oracle."""
+    import numpy as np
+    import torch
+    from paper_2206_14503_amd import synth, vdi
+
+    w = synth.large(args.seed)
+    cam = synth.camera_for(w)
+    P = cam.width * cam.height
+    k, n, ref = 16, 20, 0.01
+    t0 = time.time()
+    color, depth, count = synth.dense_frame(k, n, P, seed=args.seed)
+    ins = [vdi.VDI(cam.width, cam.height, n, ref, vdi.REGULAR, color[r], depth[r], count[r]) for r in range(k)]
+    out = vdi.VDI.empty(cam.width, cam.height, n, ref, vdi.REGULAR)
+    img = torch.empty((P, 4), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    log(f"[bench] dense: {k} inputs x {n} supersegments per pixel, {cam.width}x{cam.height}, N={n}; "
+        f"inputs ready in {time.time() - t0:.1f}s")
+
+    def step(marks=None):
+        if marks is not None:
+            marks[0].record()
+        vdi.composite(ins, vdi.BISECT, 0.0, n, 10, out=out)
+        if marks is not None:
+            marks[1].record()
+        vdi.render_original_view(out, img)
+        if marks is not None:
+            marks[2].record()
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] dense warmup step {i + 1}/{args.warmup} done")
+    flags = vdi.device_status()
+    if flags:
+        raise RuntimeError(f"device status flags {flags} after warmup")
+    marks = [[ev() for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    start, stop = ev(), ev()
+    start.record()
+    for i in range(args.steps):
+        step(marks[i])
+    stop.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    ms_step = total_ms / args.steps
+    comp_ms = np.array([m[0].elapsed_time(m[1]) for m in marks])
+    rend_ms = np.array([m[1].elapsed_time(m[2]) for m in marks])
+    cbytes = composite_bytes(ins, n, P, k * n * P)
+    gbs = cbytes / (comp_ms.mean() * 1e-3) / 1e9
+    log(f"[bench] dense: {args.steps} steps, {ms_step:.3f} ms/step; composite {comp_ms.mean():.3f} ms "
+        f"({gbs:.0f} GB/s algorithmic, {100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak), render {rend_ms.mean():.3f} ms")
+    result.update({
+        "metric": "composited VDI pixels/s (k ranks, N supersegs) + % HBM peak; learned vs plain τ speedup",
+        "value": P * args.steps / (total_ms * 1e-3),
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "large-dense-16x20-1920x1080-N20", "inputs": k, "supersegments_per_input": n,
+                   "width": cam.width, "height": cam.height, "max_n": n, "iters": 10, "tau_mode": "bisect",
+                   "layout": "regular", "interleaving": "maximal (seeded shuffle of 320 disjoint cells)",
+                   "seed": args.seed},
+        "stages_ms": {"composite": float(comp_ms.mean()), "render": float(rend_ms.mean())},
+    })
+    traffic, why = measured_traffic(DENSE_KERNEL, DENSE_PMC)
+    result["roofline"] = {"kernel": f"{DENSE_KERNEL} (composite call)", "bound": "hbm", "achieved": gbs,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                          "traffic_note": why, "algorithmic_bytes": cbytes,
+                          "workload": result["config"]["workload"]}
+    # a seeded sample for the oracle: inputs and the GPU's output at those pixels
+    px = np.sort(np.random.default_rng(4242).choice(P, size=min(P, args.sample_px), replace=False))
+    idx = torch.from_numpy(px).long().cuda()
+    sample = {"px": px, "color": color[:, :, idx].cpu().numpy(), "depth": depth[:, :, idx].cpu().numpy(),
+              "count": count[:, idx].cpu().numpy(), "k": k, "n": n, "ref": ref,
+              "gpu": (out.color[:, idx].cpu().numpy(), out.depth[:, idx].cpu().numpy(),
+                      out.count[idx].cpu().numpy(), out.gamma[idx].cpu().numpy())}
+    del ins, out, color, depth, count, img
+    torch.cuda.empty_cache()
+    return sample
+
+
+# ---------------------------------------------------------------- FHD frame
 
 def leg_fhd(args, result):
     import numpy as np
@@ -177,35 +314,40 @@ def leg_fhd(args, result):
     log(f"[bench] composite: {counts_total} input supersegments, {out_total} output; algorithmic "
         f"{cbytes / 1e9:.3f} GB -> {comp_gbs:.1f} GB/s ({100 * comp_gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
 
-    value = P * args.steps / (total_ms * 1e-3)
-    result.update({
-        "metric": "composited VDI pixels/s (k ranks, N supersegs) + % HBM peak; learned vs plain τ speedup",
-        "value": value,
-        "unit": "pixels/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": w.name, "volume": f"{w.n}^3 {w.vol_dtype}", "bricks": len(bricks),
-                   "grid": list(w.grid), "width": cam.width, "height": cam.height, "max_n": w.max_n,
-                   "iters": w.iters, "tau_mode": w.mode, "layout": args.layout, "seed": w.seed},
+    traffic, why = measured_traffic("composite_cat_kernel", FHD_PMC)
+    valu, vwhy = measured_valu("gen_kernel<float, 0, false>", GEN_SQ)
+    gen_t = float(gen_ms.mean()) * 1e-3
+    fhd = {
+        "workload": w.name, "volume": f"{w.n}^3 {w.vol_dtype}", "bricks": len(bricks), "grid": list(w.grid),
+        "width": cam.width, "height": cam.height, "max_n": w.max_n, "iters": w.iters, "tau_mode": w.mode,
+        "layout": args.layout, "steps": args.steps, "ms_per_step": ms_step,
+        "pixels_per_s": P * args.steps / (total_ms * 1e-3),
         "stages_ms": {"generate": float(gen_ms.mean()), "composite": float(comp_ms.mean()),
                       "render": float(rend_ms.mean())},
-        "composite_fhd": {"input_supersegments": counts_total, "output_supersegments": out_total,
-                          "algorithmic_bytes": cbytes, "ms": float(comp_ms.mean()), "achieved_GBps": comp_gbs,
-                          "frac_hbm_peak": comp_gbs / HBM_PEAK_GBS},
-    })
-    traffic, why = measured_traffic("composite_cat_kernel")
-    result["roofline"] = {"kernel": "composite_cat_kernel (composite stage)", "bound": "hbm", "achieved": comp_gbs,
-                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": comp_gbs / HBM_PEAK_GBS,
-                          "traffic": traffic, "traffic_note": why, "algorithmic_bytes": cbytes,
-                          "workload": w.name}
-    return dict(w=w, vol=vol, bricks=bricks, tf=tf, cam=cam, step_len=step_len, dbr=dbr, tf_d=tf_d, out=out)
+        "composite": {"input_supersegments": counts_total, "output_supersegments": out_total,
+                      "algorithmic_bytes": cbytes, "ms": float(comp_ms.mean()), "achieved_GBps": comp_gbs,
+                      "frac_hbm_peak": comp_gbs / HBM_PEAK_GBS},
+        "roofline_composite": {"kernel": "composite_cat_kernel (composite call)", "bound": "hbm",
+                               "achieved": comp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": comp_gbs / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": why,
+                               "algorithmic_bytes": cbytes},
+        # generation is bound by its VALU issue (the volume is re-read from
+        # cache): lane-instructions per second against the fp32 vector issue peak
+        "roofline_generate": {"kernel": "gen_kernel<float, 0, false> (generate call)", "bound": "alu",
+                              "achieved": None if valu is None else valu * 64 / gen_t / 1e12,
+                              "peak": VALU_PEAK_TLANE, "unit": "T VALU lane-instructions/s",
+                              "frac": None if valu is None else valu * 64 / gen_t / 1e12 / VALU_PEAK_TLANE,
+                              "valu_wave_instructions": valu, "counter_note": vwhy},
+    }
+    result["fhd"] = fhd
+    # a seeded sample for the oracle: the GPU's sub-VDIs and composite there
+    px = np.sort(np.random.default_rng(2525).choice(P, size=min(P, args.fhd_sample_px), replace=False))
+    idx = torch.from_numpy(px).long().cuda()
+    cols = lambda v: (v.color[:, idx].cpu().numpy(), v.depth[:, idx].cpu().numpy(), v.count[idx].cpu().numpy(),
+                      v.gamma[idx].cpu().numpy())
+    sample = {"px": px, "subs": [cols(v) for v in subs] if layout == vdi.REGULAR else None, "out": cols(out)}
+    return dict(w=w, vol=vol, bricks=bricks, tf=tf, cam=cam, step_len=step_len, dbr=dbr, tf_d=tf_d, out=out,
+                sample=sample)
 
 
 # ---------------------------------------------------------------- non-convex domains
@@ -317,44 +459,6 @@ def leg_large(args, result):
     del subs, dbr
     torch.cuda.empty_cache()
     result["large"] = res
-    leg_dense(args, result)
-
-
-def leg_dense(args, result):
-    """The large share's composite on dense maximally interleaved lists:
-    16 inputs x 20 supersegments per pixel (16.6 GB of input), N = 20."""
-    import numpy as np
-    import torch
-    from paper_2206_14503_amd import synth, vdi
-
-    w = synth.large(args.seed)
-    cam = synth.camera_for(w)
-    P = cam.width * cam.height
-    res = result.setdefault("large", {"workload": w.name})
-    k, n = 16, 20
-    color = torch.empty((k, n, P, 4), dtype=torch.float32, device="cuda")
-    depth = torch.empty((k, n, P, 2), dtype=torch.float32, device="cuda")
-    chunk = 1 << 17
-    for p0 in range(0, P, chunk):
-        p1 = min(P, p0 + chunk)
-        c, d, _ = synth.dense_interleaved_lists(k, n, p1 - p0, seed=args.seed * 1000 + p0 // chunk, device="cuda")
-        color[:, :, p0:p1] = c
-        depth[:, :, p0:p1] = d
-    cnt = torch.full((k, P), n, dtype=torch.int32, device="cuda")
-    ins = [vdi.VDI(cam.width, cam.height, n, 0.01, vdi.REGULAR, color[r], depth[r], cnt[r]) for r in range(k)]
-    out2 = vdi.VDI.empty(cam.width, cam.height, n, 0.01, vdi.REGULAR)
-    comp2 = lambda: vdi.composite(ins, vdi.BISECT, 0.0, n, 10, out=out2)
-    comp2()
-    torch.cuda.synchronize()
-    c2 = timed_ms(comp2, 3)
-    b2 = composite_bytes(ins, n, P, k * n * P)
-    gbs2 = b2 / (np.median(c2) * 1e-3) / 1e9
-    log(f"[bench] large dense interleaved: composite {np.median(c2):.3f} ms, {b2 / 1e9:.2f} GB, {gbs2:.0f} GB/s")
-    res["dense_interleaved"] = {"k": k, "n_per_input": n, "composite_ms": float(np.median(c2)),
-                                "algorithmic_bytes": b2, "achieved_GBps": gbs2, "frac_hbm_peak": gbs2 / HBM_PEAK_GBS,
-                                "composited_pixels_per_s": P / (np.median(c2) * 1e-3)}
-    del color, depth, ins, out2
-    torch.cuda.empty_cache()
 
 
 # ---------------------------------------------------------------- learned threshold
@@ -467,37 +571,77 @@ def leg_batched(args, result):
 
 # ---------------------------------------------------------------- CPU baseline
 
-def cpu_baseline(w, vol, bricks, tf, cam, step_len, target_s):
-    """The oracle on a bounded, seeded sample of the same frame's pixels:
-    generate all bricks' lists for those pixels, then composite them.  Pixels
-    per second of the oracle on the host threads it was given."""
+def _parity_summary(st):
+    return {k: v for k, v in st.items() if k != "fp64_mask"}
+
+
+def cpu_baseline(dense, fhd, args):
+    """The oracle on a bounded, seeded sample of the headline frame's pixels
+    (all host threads): composited pixels per second, and its lists compared
+    with the GPU's at those pixels.  Then the same comparison (untimed) on a
+    sample of the FHD frame: every brick's generated lists, and the composite
+    at the pixels whose generated lists all took the oracle's fp64 outcome."""
     import numpy as np
     import oracle
-    host_vol = vol.float().cpu().numpy() if w.vol_dtype == "f32" else vol.cpu().numpy()
-    rng = np.random.default_rng(12345)
-    P = cam.width * cam.height
+    from oracle.parity import check_lists
     cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
-    mode = oracle.BISECT if w.mode == "bisect" else oracle.FIXED
+    k, n, ref = dense["k"], dense["n"], dense["ref"]
 
     def run(npx):
-        px = np.sort(rng.choice(P, size=npx, replace=False)).astype(np.int32)
+        c, d, m = dense["color"][:, :, :npx], dense["depth"][:, :, :npx], dense["count"][:, :npx]
         t = time.time()
-        g = oracle.generate(host_vol, bricks, cam, tf, step_len, step_len, mode, w.tau, w.max_n, w.iters, pixels=px,
-                            nthreads=cores)
-        k = len(bricks)
-        oracle.composite([g["color"][r] for r in range(k)], [g["depth"][r] for r in range(k)],
-                         [g["count"][r] for r in range(k)], step_len, mode, w.tau, w.max_n, w.iters, nthreads=cores)
-        return time.time() - t
+        o = oracle.composite([c[r] for r in range(k)], [d[r] for r in range(k)], [m[r] for r in range(k)], ref,
+                             oracle.BISECT, 0.0, n, 10, nthreads=cores)
+        return time.time() - t, o
 
-    npx = 4096
-    t = run(npx)
-    npx2 = int(min(P, max(npx, npx * target_s / max(t, 1e-3))))
+    total = len(dense["px"])
+    npx = min(1024, total)
+    t, o = run(npx)
+    npx2 = int(min(total, max(npx, npx * args.cpu_seconds / max(t, 1e-3))))
     if npx2 > npx:
-        npx, t = npx2, run(npx2)
-    log(f"[bench] cpu baseline: oracle on {npx} sampled pixels took {t:.2f}s with {cores} threads")
-    return {"value": npx / t, "unit": "pixels/s", "cores": cores, "kind": "oracle",
-            "sample": f"{npx} seeded random pixels of the same FHD frame (generate all {len(bricks)} bricks + "
-                      f"composite)", "seconds": t}
+        npx = npx2
+        t, o = run(npx)
+    g = tuple(x[..., :npx, :] if x.ndim == 3 else x[:npx] for x in dense["gpu"])
+    st = check_lists(g, o, "dense sample", strict=False)
+    log(f"[bench] cpu baseline: oracle composite of {npx} sampled pixels in {t:.2f}s with {cores} threads; "
+        f"vs GPU: {_parity_summary(st)}")
+    res = {"value": npx / t, "unit": "pixels/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"{npx} seeded random pixels of the headline frame (16 x 20 interleaved supersegments each, "
+                     f"merge + bisection to N=20)", "seconds": t, "parity_vs_gpu": _parity_summary(st)}
+    if fhd is not None and fhd["sample"]["subs"] is not None:
+        w, cam, step_len = fhd["w"], fhd["cam"], fhd["step_len"]
+        px = fhd["sample"]["px"].astype(np.int32)
+        host = fhd["vol"].float().cpu().numpy()
+        t0 = time.time()
+        gen = oracle.generate(host, fhd["bricks"], cam, fhd["tf"], step_len, step_len, oracle.BISECT, 0.0, w.max_n,
+                              w.iters, pixels=px, nthreads=cores)
+        kb = len(fhd["bricks"])
+        sts = [check_lists(fhd["sample"]["subs"][r], gen, f"fhd brick {r}", brick=r, strict=False, masks=True)
+               for r in range(kb)]
+        clean = np.logical_and.reduce([s_["fp64_mask"] for s_ in sts])
+        oc = oracle.composite([gen["color"][r] for r in range(kb)], [gen["depth"][r] for r in range(kb)],
+                              [gen["count"][r] for r in range(kb)], step_len, oracle.BISECT, 0.0, w.max_n, w.iters,
+                              nthreads=cores)
+        sel = np.nonzero(clean)[0]
+        gsel = tuple(x[:, sel] if x.ndim == 3 else x[sel] for x in fhd["sample"]["out"])
+        osel = {key: (v[:, sel] if key in ("color", "depth") else v[sel]) for key, v in oc.items()
+                if key in ("color", "depth", "count", "gamma", "nout")}
+        alts = oc["alts"]
+        keep = np.isin(alts["ray"], sel)
+        remap = np.full(len(px), -1, np.int64)
+        remap[sel] = np.arange(len(sel))
+        osel["alts"] = {key: v[keep] for key, v in alts.items()}
+        osel["alts"]["ray"] = remap[alts["ray"][keep]].astype(np.int32)
+        cst = check_lists(gsel, osel, "fhd composite", strict=False)
+        gen_sum = {key: int(sum(s_[key] for s_ in sts)) for key in ("lists", "nonempty", "fp64_outcome",
+                                                                     "near_tie_outcome", "several_outcomes",
+                                                                     "unresolved_incomplete", "mismatch")}
+        res["fhd_parity_vs_gpu"] = {"sample_pixels": int(len(px)), "generate": gen_sum,
+                                    "composite": _parity_summary(cst),
+                                    "composite_pixels_skipped": int(len(px) - len(sel)),
+                                    "seconds": time.time() - t0}
+        log(f"[bench] fhd sample vs oracle: {res['fhd_parity_vs_gpu']}")
+    return res
 
 
 def main():
@@ -506,8 +650,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--layout", choices=["compact", "regular"], default="regular")
-    ap.add_argument("--legs", default="fhd,novel,masks,large,learned,batched")
+    ap.add_argument("--layout", choices=["compact", "regular"], default="regular",
+                    help="layout of the FHD leg's sub-VDIs")
+    ap.add_argument("--legs", default="fhd,novel,masks,large,learned,batched",
+                    help="legs after the headline (novel and masks need fhd)")
     ap.add_argument("--learn-seeds", type=int, default=32)
     ap.add_argument("--learn-epochs", type=int, default=8)
     ap.add_argument("--no-learn-fhd", dest="learn_fhd", action="store_false",
@@ -516,6 +662,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a kernel of known traffic for counter scaling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--sample-px", type=int, default=65536, help="headline pixels kept for the oracle")
+    ap.add_argument("--fhd-sample-px", type=int, default=16384, help="FHD pixels compared with the oracle")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -534,22 +682,22 @@ def main():
         torch.cuda.synchronize()
         log("[bench] copy calibration: 3 x 1 GiB device-to-device copies")
         del src, dst
-    fhd = leg_fhd(args, result)
-    if "novel" in legs:
-        leg_novel(args, result, fhd)
-    if "masks" in legs:
-        leg_masks(args, result, fhd)
+    dense = leg_dense(args, result)
+    fhd = None
+    if "fhd" in legs:
+        fhd = leg_fhd(args, result)
+        if "novel" in legs:
+            leg_novel(args, result, fhd)
+        if "masks" in legs:
+            leg_masks(args, result, fhd)
     if "large" in legs:
         leg_large(args, result)
-    elif "dense" in legs:
-        leg_dense(args, result)
     if "learned" in legs:
         leg_learned(args, result)
     if "batched" in legs:
         leg_batched(args, result)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(fhd["w"], fhd["vol"], fhd["bricks"], fhd["tf"], fhd["cam"],
-                                              fhd["step_len"], args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(dense, fhd, args)
         result["cpu_baseline"]["gpu_over_cpu"] = result["value"] / result["cpu_baseline"]["value"]
     print(json.dumps(result), flush=True)
 

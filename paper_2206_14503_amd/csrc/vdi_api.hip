@@ -238,26 +238,40 @@ static size_t mlp_bwd_ws_bytes(int rows)
 
 // Workspace of vdi_composite: the queue of pixels left to the general merge
 // ([npix] + counter), the block order of the depth-disjoint pass (order and
-// bucket per block), then one staging slab per general-merge block (seq_cap
-// * 64 entries of 24 bytes), at most 2 GiB of slabs (on the dense
-// interleaved case 2 GiB, about four waves per SIMD, were 5% faster than
-// 1 GiB and as fast as 4 GiB).
+// bucket per block), then the ordered general merge's chunk: staging slabs,
+// merge orders and list lengths for up to 2 GiB of slabs (the queue is
+// processed in as many chunks as it takes).  Merged-list capacities above
+// kOrderedMaxCap (and the allocation-free entry point) take the general merge
+// with its merge sequence in LDS instead, without staging.
 struct CompWs {
-    size_t qbytes, obytes, grid, slab, total;
+    size_t qbytes, obytes, grid, total;
+    uint32_t chunk;
 };
-static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int seq_cap, size_t lds)
+static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, bool staged)
 {
     CompWs W;
     const size_t nblk = (npix + 63) / 64;
+    const size_t lds = composite_lds_bytes(k, seq_cap, false);
     const int per_cu = std::max(1, std::min<int>((int)((160 * 1024) / (lds + 64)), 28));
-    W.slab = (size_t)seq_cap * 64;
-    W.grid = (size_t)ctx->num_cus * per_cu;
-    W.grid = std::min<size_t>(W.grid, nblk);
-    W.grid = std::max<size_t>(1, std::min<size_t>(W.grid, ((size_t)1 << 31) / (W.slab * 24)));
+    W.grid = std::max<size_t>(1, std::min<size_t>((size_t)ctx->num_cus * per_cu, nblk));
     W.qbytes = ((npix + 64) * sizeof(int) + 255) & ~(size_t)255;
     W.obytes = (2 * nblk * sizeof(uint32_t) + 255) & ~(size_t)255;
-    W.total = W.qbytes + W.obytes + W.grid * W.slab * 24;
+    W.chunk = staged ? ordered_chunk(seq_cap, (size_t)2 << 30, (uint32_t)npix) : 0u;
+    W.total = W.qbytes + W.obytes + (W.chunk ? ordered_ws_bytes(seq_cap, W.chunk) : 0);
     return W;
+}
+
+// The ordered merge's buffers at base (ordered_ws_bytes(seq_cap, chunk) bytes).
+static void composite_ordered(CompParams& P, char* base, uint32_t chunk)
+{
+    const size_t c = chunk, cap = P.seq_cap;
+    P.chunk = chunk;
+    P.stage_c = (float4*)base;
+    P.stage_d = (float2*)(base + c * cap * sizeof(float4));
+    char* q = base + c * cap * (sizeof(float4) + sizeof(float2));
+    P.seq = (uint16_t*)q;
+    q += (c * cap * sizeof(uint16_t) + 255) & ~(size_t)255;
+    P.qtot = (int*)q;
 }
 
 static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const GenParams& P,
@@ -459,9 +473,9 @@ vdi_status vdi_workspace_size(vdi_ctx* ctx, const vdi_shape_t* shape, size_t* by
             return fail(VDI_E_INVALID, "bad width/height/k");
         if (shape->in_max_n_sum < shape->k || shape->in_max_n_sum > shape->k * VDI_MAX_N)
             return fail(VDI_E_INVALID, "in_max_n_sum %d outside [k, k*%d]", shape->in_max_n_sum, VDI_MAX_N);
-        const size_t lds = composite_lds_bytes(shape->k, shape->in_max_n_sum, true);
-        if (lds > 160 * 1024) return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", shape->in_max_n_sum);
-        *bytes = composite_ws(ctx, (size_t)shape->width * shape->height, shape->in_max_n_sum, lds).total;
+        if (composite_lds_bytes(shape->k, shape->in_max_n_sum, false) > 160 * 1024)
+            return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", shape->in_max_n_sum);
+        *bytes = composite_ws(ctx, (size_t)shape->width * shape->height, shape->k, shape->in_max_n_sum, true).total;
         return VDI_OK;
     }
     case VDI_OP_MLP_BACKWARD:
@@ -641,15 +655,13 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     CompParams P;
     vdi_status st = composite_params(ctx, in, k, tau, out, P);
     if (st != VDI_OK) return st;
-    // the general merge stages merged lists in scratch (no merge sequence in LDS)
-    const size_t lds = composite_lds_bytes(k, P.seq_cap, true);
-    if (lds > 160 * 1024) return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", P.seq_cap);
-    const CompWs W = composite_ws(ctx, P.npix, P.seq_cap, lds);
+    if (composite_lds_bytes(k, P.seq_cap, false) > 160 * 1024)
+        return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", P.seq_cap);
+    const CompWs W = composite_ws(ctx, P.npix, k, P.seq_cap, true);
     if ((st = ensure_scratch(ctx, W.total)) != VDI_OK) return st;
     char* base = ws_base(ctx);
     composite_queues(P, base, W.qbytes);
-    P.stage_c = (float4*)(base + W.qbytes + W.obytes);
-    P.stage_d = (float2*)(base + W.qbytes + W.obytes + W.grid * W.slab * sizeof(float4));
+    if (W.chunk) composite_ordered(P, base + W.qbytes + W.obytes, W.chunk);
     launch_composite(P, (int)W.grid, (hipStream_t)stream);
     return launched();
 }
@@ -661,17 +673,14 @@ vdi_status vdi_composite_noalloc(vdi_ctx* ctx, const vdi_t* in, int k, const vdi
     vdi_status st = composite_params(ctx, in, k, tau, out, P);
     if (st != VDI_OK) return st;
     // no staging slabs: the general merge keeps its merge sequence in LDS
-    const size_t lds = composite_lds_bytes(k, P.seq_cap, false);
-    if (lds > 160 * 1024)
+    if (composite_lds_bytes(k, P.seq_cap, false) > 160 * 1024)
         return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large for the merge sequence in LDS", P.seq_cap);
-    const CompWs W = composite_ws(ctx, P.npix, P.seq_cap, lds);
+    const CompWs W = composite_ws(ctx, P.npix, k, P.seq_cap, false);
     const size_t need = W.qbytes + W.obytes;
     if (need > kStaticScratchBytes)
         return fail(VDI_E_UNSUPPORTED, "%u pixels need %zu bytes of scratch, more than the fixed %zu", P.npix, need,
                     kStaticScratchBytes);
     composite_queues(P, (char*)ctx->static_scratch, W.qbytes);
-    P.stage_c = nullptr;
-    P.stage_d = nullptr;
     launch_composite(P, (int)W.grid, (hipStream_t)stream);
     return launched();
 }

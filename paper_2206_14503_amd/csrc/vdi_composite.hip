@@ -656,85 +656,228 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
     resegment<false>(P, rd, total, p);
 }
 
-// General path with the merged list staged in global memory (sc, sd: the
-// block's slab; lane t's element i at [i * 64 + t]).  The merge gathers each element once
-// and stores it (the store of step i is issued at step i + 1, and the front
-// of an input's element after next lands in LDS one step later, so the loads
-// overlap the next selection); every re-segmentation scan then reads whole
-// lines.  The first scan validates the merged list: it is non-decreasing in
-// front depth exactly when every input is.
-__device__ void composite_pixel_staged(const CompParams& P, unsigned char* lds_raw, int t, uint32_t p,
-                                       float4* sc, float2* sd)
+// ---------------------------------------------------------------- ordered general merge
+//
+// The queue of pixels the depth-disjoint path left (or every pixel when k is
+// above its limit) is processed in chunks, each by three kernels:
+//   1. merge_order_kernel: the merge order of every entry's lists by (front,
+//      input), from the fronts alone (16 entries per wavefront, 4 lanes per
+//      entry, each lane the lists r = lane mod 4, r + 4, ...; the lists'
+//      fronts in LDS; validates every element);
+//   2. merge_stage_kernel: per tile of 8 entries (consecutive pixels when the
+//      queue holds whole blocks) the elements are read in whole lines into
+//      LDS and written to the staging slab in merge order, again in whole
+//      lines (the 8 entries are adjacent columns of a slab row);
+//   3. composite_staged_kernel: one lane per entry, the re-segmentation scans
+//      over the slab (each scan step of a wavefront reads whole rows).
+// Per-lane gathers from the inputs' slot-major planes, where a lane's 16
+// bytes come with a line its neighbours need at other times, are avoided.
+
+constexpr int kOrdEntries = 16;   // entries per merge_order_kernel wavefront
+constexpr int kStageTile = 8;     // entries per merge_stage_kernel block
+
+// First slot of input r in an entry's row of merged-list capacity (the
+// inputs' max_n in order).
+__device__ inline int input_base(const CompParams& P, int r)
 {
-    const Lds L = lds_layout(lds_raw, P.k, P.seq_cap, true);
-    int total = 0;
-    bool bad = false;
-    for (int r = 0; r < P.k; ++r) {
-        const CompInput& in = P.in[r];
-        int c = in.count[p];
-        if (c < 0 || c > in.max_n) { bad = true; c = 0; }
-        const uint32_t eb = in.compact ? in.offset[p] : p;
-        const uint64_t last = in.compact ? (uint64_t)eb + (uint64_t)c : (uint64_t)c * P.npix;
-        if (last > in.capacity) { bad = true; c = 0; }
-        const uint32_t stride = in.compact ? 1u : P.npix;
-        L.ebase[r * kWave + t] = eb;
-        L.cur[r * kWave + t] = 0;
-        L.cnt[r * kWave + t] = (uint8_t)c;
-        L.front[r * kWave + t] = c > 0 ? gload(in.depth, eb).x : __builtin_inff();
-        L.next[r * kWave + t] = c > 1 ? gload(in.depth, eb + stride).x : __builtin_inff();
-        total += c;
-    }
-    float4 pc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float2 pd = make_float2(0.0f, 0.0f);
-    float pn = __builtin_inff();
-    int pr = -1;
-    for (int i = 0; i < total && !bad; ++i) {
-        float best = __builtin_inff();
-        int rb = -1;
-        for (int r = 0; r < P.k; ++r) {
-            const float f = L.front[r * kWave + t];
-            if (f < best) { best = f; rb = r; }
-        }
-        // finish step i - 1: its element to the slab, its input's next front to LDS
-        if (pr >= 0) {
-            sc[(uint32_t)(i - 1) * kWave + t] = pc;
-            sd[(uint32_t)(i - 1) * kWave + t] = pd;
-            L.next[pr * kWave + t] = pn;
-        }
-        if (rb < 0) {
-            bad = true;   // elements left but no finite front (NaN depths)
-            break;
-        }
-        const int s = L.cur[rb * kWave + t];
-        L.cur[rb * kWave + t] = (uint8_t)(s + 1);
-        const int c = L.cnt[rb * kWave + t];
-        const InLds inr = L.in[rb];
-        const uint32_t eb = L.ebase[rb * kWave + t];
-        const uint32_t e = eb + (uint32_t)s * inr.stride;
-        pc = gload(inr.color, e);
-        pd = gload(inr.depth, e);
-        pn = (s + 2 < c) ? gload(inr.depth, eb + (uint32_t)(s + 2) * inr.stride).x : __builtin_inff();
-        pr = rb;
-        L.front[rb * kWave + t] = L.next[rb * kWave + t];
-    }
-    if (bad) {
-        reject_pixel(P, p);
-        return;
-    }
-    if (total > 0) {
-        sc[(uint32_t)(total - 1) * kWave + t] = pc;
-        sd[(uint32_t)(total - 1) * kWave + t] = pd;
-    }
-    const StageReader rd{sc, sd, (uint32_t)t, (uint32_t)t};
-    if (!resegment<true>(P, rd, total, p)) reject_pixel(P, p);
+    int b = 0;
+    for (int q = 0; q < r; ++q) b += P.in[q].max_n;
+    return b;
 }
 
-// Slab of block b (lane t's element i at [i * 64 + t] of it).
-__device__ inline void stage_slab(const CompParams& P, uint32_t b, float4*& sc, float2*& sd)
+// Lexicographic minimum of (front, input) across the 4 lanes of an entry.
+__device__ inline void quad_min(float& f, int& r)
 {
-    const size_t base = (size_t)b * (size_t)P.seq_cap * kWave;
-    sc = P.stage_c + base;
-    sd = P.stage_d + base;
+#pragma unroll
+    for (int m = 1; m <= 2; m <<= 1) {
+        const float of = __shfl_xor(f, m, 64);
+        const int orr = __shfl_xor(r, m, 64);
+        const bool take = (of < f) | ((of == f) & (orr < r));
+        f = take ? of : f;
+        r = take ? orr : r;
+    }
+}
+
+// J: lists per lane (k <= 4 J).
+template <int J>
+__global__ __launch_bounds__(64) void merge_order_kernel(CompParams P, uint32_t e0)
+{
+    extern __shared__ __align__(16) float fr[];      // [16][seq_cap] fronts, entry rows
+    const int t = threadIdx.x, ql = t >> 2, sub = t & 3;
+    const uint32_t le = blockIdx.x * kOrdEntries + ql;
+    const uint32_t nq = (uint32_t)*P.q_count;
+    const bool active = le < P.chunk && e0 + le < nq;
+    const uint32_t p = active ? (uint32_t)P.q_list[e0 + le] : 0u;
+    float* F = fr + ql * P.seq_cap;
+    int cnt[J], base[J], cur[J];
+    float hf[J], nf[J];
+    bool bad = false;
+    int tot = 0;
+    // ---- counts, fronts into LDS, validation (finite, f < b, sorted per list)
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int r = sub + 4 * j;
+        cnt[j] = 0;
+        base[j] = 0;
+        if (r < P.k && active) {
+            const CompInput& in = P.in[r];
+            int c = in.count[p];
+            const uint32_t eb = in.compact ? in.offset[p] : p;
+            const uint64_t last = in.compact ? (uint64_t)eb + (uint64_t)(c > 0 ? c : 0)
+                                             : (uint64_t)(c > 0 ? c : 0) * P.npix;
+            if (c < 0 || c > in.max_n || last > in.capacity) {
+                bad = true;
+                c = 0;
+            }
+            const uint32_t stride = in.compact ? 1u : P.npix;
+            const int b0 = input_base(P, r);
+            float prev = -__builtin_inff();
+            for (int s_ = 0; s_ < c; ++s_) {
+                const float2 fb = gload(in.depth, eb + (uint32_t)s_ * stride);
+                bad |= !(isfinite(fb.x) & isfinite(fb.y) & (fb.x < fb.y) & (fb.x >= prev));
+                prev = fb.x;
+                F[b0 + s_] = fb.x;
+            }
+            cnt[j] = c;
+            base[j] = b0;
+            tot += c;
+        }
+    }
+    // the entry's total and validity over its 4 lanes
+    tot += __shfl_xor(tot, 1, 64);
+    tot += __shfl_xor(tot, 2, 64);
+    int badi = bad ? 1 : 0;
+    badi |= __shfl_xor(badi, 1, 64);
+    badi |= __shfl_xor(badi, 2, 64);
+    if (badi) tot = 0;
+    if (active && sub == 0) {
+        P.qtot[le] = badi ? -1 : tot;
+        if (badi) reject_pixel(P, p);
+    }
+    // ---- merge: each step the lane's smallest head, then the entry's; the
+    // lane owning the winner records (input, slot) and advances.  A lane
+    // reads back only fronts it wrote itself.
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        cur[j] = 0;
+        hf[j] = cnt[j] > 0 ? F[base[j]] : __builtin_inff();
+        nf[j] = cnt[j] > 1 ? F[base[j] + 1] : __builtin_inff();
+    }
+    int wmax = tot;
+#pragma unroll
+    for (int m = 4; m < 64; m <<= 1) wmax = max(wmax, __shfl_xor(wmax, m, 64));
+    uint16_t* seq = P.seq + (size_t)(le >> 3) * P.seq_cap * 8 + (le & 7);
+    for (int i = 0; i < wmax; ++i) {
+        float bf = __builtin_inff();
+        int bj = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const bool lt = hf[j] < bf;
+            bf = lt ? hf[j] : bf;
+            bj = lt ? j : bj;
+        }
+        int br = bf < __builtin_inff() ? sub + 4 * bj : 0x7fff;
+        quad_min(bf, br);
+        const bool own = (i < tot) & ((br & 3) == sub) & (br < 0x7fff);
+        if (own) {
+            const int jw = br >> 2;
+            int sw = 0;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                if (j == jw) {
+                    sw = cur[j];
+                    cur[j] = sw + 1;
+                    hf[j] = nf[j];
+                    nf[j] = sw + 2 < cnt[j] ? F[base[j] + sw + 2] : __builtin_inff();
+                }
+            }
+            seq[(size_t)i * 8] = (uint16_t)((br << 6) | sw);
+        }
+    }
+}
+
+// One block of 256 threads per tile of 8 chunk entries.
+__global__ __launch_bounds__(256) void merge_stage_kernel(CompParams P, uint32_t e0)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int cntS[kStageTile][kMaxInputs];
+    __shared__ uint32_t ebS[kStageTile][kMaxInputs];
+    __shared__ int baseS[kMaxInputs];
+    __shared__ uint8_t rinS[kOrderedMaxCap];
+    __shared__ int totS[kStageTile];
+    const int t = threadIdx.x;
+    const int cap = P.seq_cap;
+    float4* Ec = (float4*)lds_raw;                         // [cap][8]
+    float2* Ed = (float2*)(lds_raw + (size_t)cap * kStageTile * sizeof(float4));
+    const uint32_t le0 = blockIdx.x * kStageTile;
+    const uint32_t nq = (uint32_t)*P.q_count;
+    if (t < kStageTile) {
+        const uint32_t le = le0 + t;
+        totS[t] = (le < P.chunk && e0 + le < nq) ? P.qtot[le] : -1;
+    }
+    if (t < P.k) {
+        const int b = input_base(P, t);
+        baseS[t] = b;
+        for (int s_ = 0; s_ < P.in[t].max_n; ++s_) rinS[b + s_] = (uint8_t)t;
+    }
+    __syncthreads();
+    if (t < kStageTile * P.k) {
+        const int q = t / P.k, r = t - q * P.k;
+        int c = 0;
+        uint32_t eb = 0;
+        if (totS[q] > 0) {
+            const uint32_t p = (uint32_t)P.q_list[e0 + le0 + q];
+            c = P.in[r].count[p];   // validated by merge_order_kernel
+            eb = P.in[r].compact ? P.in[r].offset[p] : p;
+        }
+        cntS[q][r] = c;
+        ebS[q][r] = eb;
+    }
+    __syncthreads();
+    // elements into LDS: (slot row, entry) with the entry fastest, so the 8
+    // entries of a row read one line of each slot-major plane
+    for (int idx = t; idx < cap * kStageTile; idx += 256) {
+        const int q = idx & 7, rs = idx >> 3;
+        const int r = rinS[rs];
+        const int s_ = rs - baseS[r];
+        if (s_ < cntS[q][r]) {
+            const CompInput& in = P.in[r];
+            const uint32_t e = ebS[q][r] + (uint32_t)s_ * (in.compact ? 1u : P.npix);
+            Ec[idx] = gload(in.color, e);
+            Ed[idx] = gload(in.depth, e);
+        }
+    }
+    __syncthreads();
+    int tmax = 0;
+#pragma unroll
+    for (int q = 0; q < kStageTile; ++q) tmax = max(tmax, totS[q]);
+    // merged order out: slab row i, columns of the 8 entries
+    const uint16_t* seq = P.seq + (size_t)(le0 >> 3) * cap * 8;
+    const size_t slab = (size_t)(le0 >> 6) * cap * 64 + (le0 & 63);
+    for (int idx = t; idx < tmax * kStageTile; idx += 256) {
+        const int q = idx & 7, i = idx >> 3;
+        if (i < totS[q]) {
+            const uint32_t code = seq[(size_t)i * 8 + q];
+            const int rs = baseS[code >> 6] + (int)(code & 63u);
+            P.stage_c[slab + (size_t)i * 64 + q] = Ec[rs * kStageTile + q];
+            P.stage_d[slab + (size_t)i * 64 + q] = Ed[rs * kStageTile + q];
+        }
+    }
+}
+
+// One wavefront per group of 64 chunk entries: re-segmentation over the slab.
+__global__ __launch_bounds__(64) void composite_staged_kernel(CompParams P, uint32_t e0)
+{
+    const int t = threadIdx.x;
+    const uint32_t le = blockIdx.x * 64 + t;
+    const uint32_t nq = (uint32_t)*P.q_count;
+    if (le >= P.chunk || e0 + le >= nq) return;
+    const int tot = P.qtot[le];
+    if (tot < 0) return;
+    const uint32_t p = (uint32_t)P.q_list[e0 + le];
+    const size_t slab = (size_t)blockIdx.x * P.seq_cap * 64;
+    const StageReader rd{P.stage_c + slab, P.stage_d + slab, (uint32_t)t, (uint32_t)t};
+    resegment<false>(P, rd, tot, p);
 }
 
 // All pixels by the general merge (k above the depth-disjoint path's limit),
@@ -746,15 +889,20 @@ __global__ __launch_bounds__(64) void composite_kernel(CompParams P)
     setup_inputs(P, lds_raw, t);
     __syncthreads();
     const uint32_t nblk = composite_blocks(P);
-    float4* sc = nullptr;
-    float2* sd = nullptr;
-    if (P.stage_c) stage_slab(P, blockIdx.x, sc, sd);
     for (uint32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         uint32_t p;
         if (!block_pixel(P, blk, t, p)) continue;
-        if (sc) composite_pixel_staged(P, lds_raw, t, p, sc, sd);
-        else composite_pixel(P, lds_raw, t, p);
+        composite_pixel(P, lds_raw, t, p);
     }
+}
+
+// Every pixel to the general merge's queue (k above the depth-disjoint
+// path's limit).
+__global__ void queue_all_kernel(CompParams P)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.npix) P.q_list[i] = (int)i;
+    if (i == 0) *P.q_count = (int)P.npix;
 }
 
 // Depth-disjoint path over all pixels; the others are queued.
@@ -780,13 +928,8 @@ __global__ __launch_bounds__(64) void composite_queue_kernel(CompParams P)
     setup_inputs(P, lds_raw, t);
     __syncthreads();
     const uint32_t n = (uint32_t)*P.q_count;
-    float4* sc = nullptr;
-    float2* sd = nullptr;
-    if (P.stage_c) stage_slab(P, blockIdx.x, sc, sd);
-    for (uint32_t idx = blockIdx.x * kWave + t; idx < n; idx += gridDim.x * kWave) {
-        if (sc) composite_pixel_staged(P, lds_raw, t, (uint32_t)P.q_list[idx], sc, sd);
-        else composite_pixel(P, lds_raw, t, (uint32_t)P.q_list[idx]);
-    }
+    for (uint32_t idx = blockIdx.x * kWave + t; idx < n; idx += gridDim.x * kWave)
+        composite_pixel(P, lds_raw, t, (uint32_t)P.q_list[idx]);
 }
 
 // ---------------------------------------------------------------- batched (persistent)
@@ -943,13 +1086,55 @@ __global__ __launch_bounds__(1024) void order_sort_kernel(CompParams P, uint32_t
     for (uint32_t i = t; i < blocks; i += blockDim.x) P.order[atomicAdd(&cnt[P.bucket[i]], 1u)] = i;
 }
 
+uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix)
+{
+    if (seq_cap > kOrderedMaxCap) return 0;
+    const size_t per = (size_t)seq_cap * (sizeof(float4) + sizeof(float2) + sizeof(uint16_t)) + sizeof(int);
+    size_t c = bytes / per;
+    const size_t all = ((size_t)npix + 63) & ~(size_t)63;
+    c = std::min(c, all) & ~(size_t)63;
+    return (uint32_t)c;
+}
+
+size_t ordered_ws_bytes(int seq_cap, uint32_t chunk)
+{
+    const size_t c = chunk;
+    const size_t stage = c * seq_cap * (sizeof(float4) + sizeof(float2));
+    const size_t seq = (c * seq_cap * sizeof(uint16_t) + 255) & ~(size_t)255;
+    const size_t tot = (c * sizeof(int) + 255) & ~(size_t)255;
+    return stage + seq + tot;
+}
+
+static size_t stage_lds_bytes(int seq_cap) { return (size_t)seq_cap * kStageTile * (sizeof(float4) + sizeof(float2)); }
+
+// The ordered general merge over the queue, chunk by chunk (every kernel
+// reads the queue length on the device; entries past it exit at once).
+static void launch_ordered(const CompParams& P, hipStream_t s)
+{
+    const uint32_t c = P.chunk;
+    const size_t lds_ord = (size_t)kOrdEntries * P.seq_cap * sizeof(float);
+    for (uint32_t e0 = 0; e0 < P.npix; e0 += c) {
+        if (P.k <= 16)
+            hipLaunchKernelGGL(merge_order_kernel<4>, dim3(c / kOrdEntries), dim3(64), lds_ord, s, P, e0);
+        else
+            hipLaunchKernelGGL(merge_order_kernel<8>, dim3(c / kOrdEntries), dim3(64), lds_ord, s, P, e0);
+        hipLaunchKernelGGL(merge_stage_kernel, dim3(c / kStageTile), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
+        hipLaunchKernelGGL(composite_staged_kernel, dim3(c / 64), dim3(64), 0, s, P, e0);
+    }
+}
+
 void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
 {
-    const size_t lds = composite_lds_bytes(P.k, P.seq_cap, P.stage_c != nullptr);
+    const size_t lds = composite_lds_bytes(P.k, P.seq_cap, false);
     const unsigned blocks = composite_blocks(P);
     const unsigned g2 = std::max(1u, std::min(blocks, (unsigned)grid_general));
     if (P.k > kCatMaxInputs) {
-        hipLaunchKernelGGL(composite_kernel, dim3(P.stage_c ? g2 : blocks), dim3(kWave), lds, s, P);
+        if (P.chunk) {
+            hipLaunchKernelGGL(queue_all_kernel, dim3((P.npix + 255) / 256), dim3(256), 0, s, P);
+            launch_ordered(P, s);
+        } else {
+            hipLaunchKernelGGL(composite_kernel, dim3(blocks), dim3(kWave), lds, s, P);
+        }
         return;
     }
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(1), 0, s, (uint32_t*)P.q_count, 0u);
@@ -965,7 +1150,10 @@ void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
         hipLaunchKernelGGL(order_sort_kernel, dim3(1), dim3(1024), 0, s, P, blocks);
     }
     hipLaunchKernelGGL(composite_cat_kernel, dim3(blocks), dim3(kWave), lds_cat, s, P);
-    hipLaunchKernelGGL(composite_queue_kernel, dim3(g2), dim3(kWave), lds, s, P);
+    if (P.chunk)
+        launch_ordered(P, s);
+    else
+        hipLaunchKernelGGL(composite_queue_kernel, dim3(g2), dim3(kWave), lds, s, P);
 }
 
 // ---------------------------------------------------------------- rendering

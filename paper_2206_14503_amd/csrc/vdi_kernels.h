@@ -130,8 +130,14 @@ struct CompParams {
     int seq_cap;              // merged-list capacity per pixel (sum of input max_n)
     int* q_list;              // [npix] pixels left to the general merge
     int* q_count;             // their number
-    // optional staging of the general merge: per block a slab of seq_cap * 64
-    // entries where lane t's merged element i sits at [i * 64 + t]
+    // optional ordered general merge, in chunks of `chunk` queue entries
+    // (a multiple of 64): the merge order of each entry's lists, then its
+    // merged list staged for the re-segmentation scans; per group of 64
+    // entries a slab of seq_cap * 64 elements, entry t's element i at
+    // [i * 64 + t]
+    uint32_t chunk;           // 0: no staging (merge sequence in LDS)
+    uint16_t* seq;            // [chunk / 8][seq_cap][8]: input << 6 | slot
+    int* qtot;                // [chunk]: merged-list length (-1: rejected)
     float4* stage_c;
     float2* stage_d;
     // optional order of the 64-pixel blocks for the depth-disjoint pass
@@ -145,6 +151,12 @@ constexpr int kOrderBuckets = 64;
 constexpr int kCatMaxInputs = 16;
 
 size_t composite_lds_bytes(int k, int seq_cap, bool staged = false);   // general merge
+// Merged-list capacity up to which the ordered general merge runs.
+constexpr int kOrderedMaxCap = 512;
+// Queue entries per chunk of the ordered merge for a staging budget of
+// `bytes` (0 if seq_cap exceeds kOrderedMaxCap); workspace of one chunk.
+uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix);
+size_t ordered_ws_bytes(int seq_cap, uint32_t chunk);
 size_t cat_lds_bytes(int k);                      // depth-disjoint path
 // grid_general: blocks of the queue-driven general merge (with staging, at
 // most the number of slabs)

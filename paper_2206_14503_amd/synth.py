@@ -325,6 +325,22 @@ def dense_interleaved_lists(k: int, n_per: int, npix: int, seed: int, depth_rang
     return color, depth, count
 
 
+def dense_frame(k: int, n_per: int, npix: int, seed: int, device: str = "cuda", chunk: int = 1 << 17):
+    """dense_interleaved_lists for a whole frame, generated in pixel chunks of
+    `chunk` (chunk c seeded seed*1000 + c) into preallocated slot-major
+    tensors: color [k, n_per, npix, 4], depth [k, n_per, npix, 2], count [k, npix]."""
+    import torch
+    color = torch.empty((k, n_per, npix, 4), dtype=torch.float32, device=device)
+    depth = torch.empty((k, n_per, npix, 2), dtype=torch.float32, device=device)
+    for p0 in range(0, npix, chunk):
+        p1 = min(npix, p0 + chunk)
+        c, d, _ = dense_interleaved_lists(k, n_per, p1 - p0, seed=seed * 1000 + p0 // chunk, device=device)
+        color[:, :, p0:p1] = c
+        depth[:, :, p0:p1] = d
+    count = torch.full((k, npix), n_per, dtype=torch.int32, device=device)
+    return color, depth, count
+
+
 # --------------------------------------------------------------------------
 # Workload presets
 # --------------------------------------------------------------------------

@@ -40,19 +40,33 @@ def _summary(tmp_path, digest, kernels):
     return str(p)
 
 
-def test_measured_traffic_reads_matching_summary(tmp_path, monkeypatch):
+def test_measured_traffic_reads_matching_summary(tmp_path):
     k = {"composite_cat_kernel": {"fetch_kib": 100.0, "write_kib": 50.0, "dispatches": 3}}
-    monkeypatch.setattr(bench, "PMC_SUMMARY", _summary(tmp_path, bench.source_digest(), k))
-    b, why = bench.measured_traffic("composite_cat_kernel")
+    path = _summary(tmp_path, bench.source_digest(bench.COMPOSITE_SOURCES), k)
+    b, why = bench.measured_traffic("composite_cat_kernel", path)
     assert why == "measured" and b == pytest.approx((100.0 * 2.0 + 50.0) * 1024.0)
-    b, why = bench.measured_traffic("gen_kernel")
-    assert b is None and "no counters" in why
+    b, why = bench.measured_traffic("gen_kernel", path)
+    assert b is None and "no traffic counters" in why
 
 
-def test_measured_traffic_refuses_other_sources(tmp_path, monkeypatch):
+def test_measured_traffic_refuses_other_sources(tmp_path):
     k = {"composite_cat_kernel": {"fetch_kib": 1.0, "write_kib": 1.0, "dispatches": 1}}
-    monkeypatch.setattr(bench, "PMC_SUMMARY", _summary(tmp_path, "0" * 64, k))
-    b, why = bench.measured_traffic("composite_cat_kernel")
+    path = _summary(tmp_path, "0" * 64, k)
+    b, why = bench.measured_traffic("composite_cat_kernel", path)
     assert b is None and "changed" in why
-    monkeypatch.setattr(bench, "PMC_SUMMARY", str(tmp_path / "missing.md"))
-    assert bench.measured_traffic("composite_cat_kernel")[0] is None
+    assert bench.measured_traffic("composite_cat_kernel", str(tmp_path / "missing.md"))[0] is None
+
+
+def test_measured_valu_reads_generation_summary(tmp_path):
+    k = {"gen_kernel<float, 0, false>": {"valu_insts": 1.5e9, "dispatches": 2}}
+    path = _summary(tmp_path, bench.source_digest(bench.GENERATE_SOURCES), k)
+    v, why = bench.measured_valu("gen_kernel<float, 0, false>", path)
+    assert why == "measured" and v == pytest.approx(1.5e9)
+    # a composite digest does not vouch for the generation kernel's sources
+    path = _summary(tmp_path, bench.source_digest(bench.COMPOSITE_SOURCES), k)
+    assert bench.measured_valu("gen_kernel<float, 0, false>", path)[0] is None
+
+
+def test_valu_peak_from_unit_counts():
+    # 256 CUs x 4 SIMDs x 32 fp32 lanes per cycle x 2.4 GHz; twice that is the 157.3 TFLOP/s (FMA = 2)
+    assert bench.VALU_PEAK_TLANE == pytest.approx(78.6, rel=1e-3)

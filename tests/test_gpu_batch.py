@@ -9,7 +9,7 @@ import pytest
 
 from paper_2206_14503_amd import synth
 from conftest import gpu_available
-from parity import check_lists
+from oracle.parity import check_lists
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="no GPU")]
 

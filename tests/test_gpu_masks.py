@@ -7,7 +7,7 @@ import pytest
 
 from paper_2206_14503_amd import synth
 from conftest import gpu_available
-from parity import ATOL, check_lists
+from oracle.parity import ATOL, check_lists
 from test_gpu_parity import _gpu_regular, _np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="no GPU")]
