@@ -244,8 +244,9 @@ static size_t mlp_bwd_ws_bytes(int rows)
 // kOrderedMaxCap (and the allocation-free entry point) take the general merge
 // with its merge sequence in LDS instead, without staging.
 struct CompWs {
-    size_t qbytes, obytes, grid, total;
+    size_t qbytes, obytes, grid, total, buf;
     uint32_t chunk;
+    int nbuf;          // ordered-merge buffers: 2 when the queue can span several chunks
 };
 static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, bool staged)
 {
@@ -257,7 +258,9 @@ static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, 
     W.qbytes = ((npix + 64) * sizeof(int) + 255) & ~(size_t)255;
     W.obytes = (2 * nblk * sizeof(uint32_t) + 255) & ~(size_t)255;
     W.chunk = staged ? ordered_chunk(seq_cap, (size_t)2 << 30, (uint32_t)npix) : 0u;
-    W.total = W.qbytes + W.obytes + (W.chunk ? ordered_ws_bytes(seq_cap, W.chunk) : 0);
+    W.nbuf = W.chunk == 0 ? 0 : (W.chunk < npix ? 2 : 1);
+    W.buf = W.chunk ? ordered_ws_bytes(seq_cap, W.chunk) : 0;
+    W.total = W.qbytes + W.obytes + W.nbuf * W.buf;
     return W;
 }
 
@@ -272,6 +275,8 @@ static void composite_ordered(CompParams& P, char* base, uint32_t chunk)
     P.seq = (uint16_t*)q;
     q += (c * cap * sizeof(uint16_t) + 255) & ~(size_t)255;
     P.qtot = (int*)q;
+    q += (c * sizeof(int) + 255) & ~(size_t)255;
+    P.ghat = (float*)q;
 }
 
 static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const GenParams& P,
@@ -427,6 +432,17 @@ vdi_status vdi_ctx_create(vdi_ctx** out, int device)
     vdi_ctx* c = new vdi_ctx();
     c->device = device;
     c->static_scratch = sptr;
+    c->aux = nullptr;
+    for (int i = 0; i < 5; ++i) c->ev[i] = nullptr;
+    hipError_t es = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    for (int i = 0; i < 5 && es == hipSuccess; ++i) es = hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming);
+    if (es != hipSuccess) {
+        for (int i = 0; i < 5; ++i)
+            if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+        if (c->aux) (void)hipStreamDestroy(c->aux);
+        delete c;
+        return fail(VDI_E_HIP, "stream/event creation failed: %s", hipGetErrorString(es));
+    }
     c->scratch = nullptr;
     c->scratch_bytes = 0;
     c->user_ws = nullptr;
@@ -436,6 +452,8 @@ vdi_status vdi_ctx_create(vdi_ctx** out, int device)
     hipError_t e = hipMalloc(&c->status, 64);
     if (e == hipSuccess) e = hipMemset(c->status, 0, 64);
     if (e != hipSuccess) {
+        for (int i = 0; i < 5; ++i) (void)hipEventDestroy(c->ev[i]);
+        (void)hipStreamDestroy(c->aux);
         delete c;
         return fail(VDI_E_HIP, "status allocation failed: %s", hipGetErrorString(e));
     }
@@ -451,6 +469,9 @@ vdi_status vdi_ctx_destroy(vdi_ctx* ctx)
     (void)hipDeviceSynchronize();
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->status) (void)hipFree(ctx->status);
+    for (int i = 0; i < 5; ++i)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     delete ctx;
     return VDI_OK;
 }
@@ -662,7 +683,17 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     char* base = ws_base(ctx);
     composite_queues(P, base, W.qbytes);
     if (W.chunk) composite_ordered(P, base + W.qbytes + W.obytes, W.chunk);
-    launch_composite(P, (int)W.grid, (hipStream_t)stream);
+    if (W.nbuf == 2) {
+        CompParams P2 = P;
+        composite_ordered(P2, base + W.qbytes + W.obytes + W.buf, W.chunk);
+        OrderedSync sync;
+        sync.aux = ctx->aux;
+        for (int i = 0; i < 5; ++i) sync.ev[i] = ctx->ev[i];
+        sync.P2 = &P2;
+        launch_composite(P, (int)W.grid, (hipStream_t)stream, &sync);
+    } else {
+        launch_composite(P, (int)W.grid, (hipStream_t)stream);
+    }
     return launched();
 }
 

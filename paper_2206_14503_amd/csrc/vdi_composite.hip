@@ -314,10 +314,17 @@ __device__ inline bool elem_ok(float2 fb, float prev_f, bool join)
 // element is visited and checked (finite depths, f < b, fronts
 // non-decreasing) up to the first violation, which ends the scan and is
 // reported in *bad.
+// Elements a scan keeps in flight ahead of the one it processes: the staged
+// slabs are streamed from memory, where one element ahead leaves a wavefront
+// waiting on every load; the other readers gather through the cache.
+template <typename R> struct ScanDepth { static constexpr int D = 1; };
+template <> struct ScanDepth<StageReader> { static constexpr int D = 4; };
+
 template <int NC, bool WRITE, bool VALIDATE, typename R>
 __device__ void c_scan(R rd, int total, float inv_ref, const float* gam, int cap, int limit, const COut& o,
                        int* counts, bool* bad)
 {
+    constexpr int D = ScanDepth<R>::D;
     CSeg S[NC];
     float g2[NC];
 #pragma unroll
@@ -328,51 +335,71 @@ __device__ void c_scan(R rd, int total, float inv_ref, const float* gam, int cap
     bool ok = true;
     if (total > 0) {
         rd.reset();
-        Src src = rd.next();
-        float4 cn = gload(src.c, src.e);
-        float2 fn = gload(src.d, src.e);
-        bool jn = src.join;
+        // ring of the next D elements (slot j holds element i0 + j)
+        float4 rc[D];
+        float2 rf[D];
+        bool rj[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            rc[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            rf[j] = make_float2(0.0f, 1.0f);
+            rj[j] = false;
+            if (j < total) {
+                const Src src = rd.next();
+                rc[j] = gload(src.c, src.e);
+                rf[j] = gload(src.d, src.e);
+                rj[j] = src.join;
+            }
+        }
         float prev_f = -__builtin_inff();
-        for (int i = 0; i < total; ++i) {
-            float4 cc = cn;
-            float2 fc = fn;
-            const bool jc = jn;
-            if (i + 1 < total) {
-                Src nx = rd.next();
-                cn = gload(nx.c, nx.e);
-                fn = gload(nx.d, nx.e);
-                jn = nx.join;
-            }
-            if (VALIDATE) {
-                ok &= elem_ok(fc, prev_f, jc);
-                prev_f = fc.x;
-            }
-            CElem e = prep(cc, fc, inv_ref);
-            // a_S of every state; the one extended to the element's front
-            // differs only after a gap, which most lanes see in few steps,
-            // so it is computed only where some state of the lane has one
-            float a0[NC], a1[NC];
-            bool gap = false;
+        bool stop = false;
+        for (int i0 = 0; i0 < total && !stop; i0 += D) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                a0[c] = seg_alpha(S[c], S[c].b, inv_ref);
-                a1[c] = a0[c];
-                gap |= S[c].open & (e.f > S[c].b);
-            }
-            if (gap) {
+            for (int j = 0; j < D; ++j) {
+                const int i = i0 + j;
+                if (i < total && !stop) {
+                    const float4 cc = rc[j];
+                    const float2 fc = rf[j];
+                    const bool jc = rj[j];
+                    if (i + D < total) {
+                        const Src nx = rd.next();
+                        rc[j] = gload(nx.c, nx.e);
+                        rf[j] = gload(nx.d, nx.e);
+                        rj[j] = nx.join;
+                    }
+                    if (VALIDATE) {
+                        ok &= elem_ok(fc, prev_f, jc);
+                        prev_f = fc.x;
+                    }
+                    CElem e = prep(cc, fc, inv_ref);
+                    // a_S of every state; the one extended to the element's
+                    // front differs only after a gap, which most lanes see in
+                    // few steps, so it is computed only where some state of
+                    // the lane has one
+                    float a0[NC], a1[NC];
+                    bool gap = false;
 #pragma unroll
-                for (int c = 0; c < NC; ++c) a1[c] = seg_alpha(S[c], fmaxf(S[c].b, e.f), inv_ref);
-            }
-            // a frozen state (count above limit) keeps stepping: its count
-            // only grows, so its outcome stays decided
-            bool live = false;
+                    for (int c = 0; c < NC; ++c) {
+                        a0[c] = seg_alpha(S[c], S[c].b, inv_ref);
+                        a1[c] = a0[c];
+                        gap |= S[c].open & (e.f > S[c].b);
+                    }
+                    if (gap) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                c_step<WRITE>(S[c], o, inv_ref, g2[c], cap, e, a0[c], a1[c]);
-                live |= WRITE || S[c].count <= limit;
+                        for (int c = 0; c < NC; ++c) a1[c] = seg_alpha(S[c], fmaxf(S[c].b, e.f), inv_ref);
+                    }
+                    // a frozen state (count above limit) keeps stepping: its
+                    // count only grows, so its outcome stays decided
+                    bool live = false;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        c_step<WRITE>(S[c], o, inv_ref, g2[c], cap, e, a0[c], a1[c]);
+                        live |= WRITE || S[c].count <= limit;
+                    }
+                    // a failed validation decides the pass (its counts are unused)
+                    stop = VALIDATE ? !ok : !live;
+                }
             }
-            // a failed validation decides the pass (its counts are unused)
-            if (VALIDATE ? !ok : !live) break;
         }
     }
 #pragma unroll
@@ -418,17 +445,24 @@ __device__ inline void reject_pixel(const CompParams& P, uint32_t p)
     if (P.out_gamma) P.out_gamma[p] = 0.0f;
 }
 
-// Levels of the compositing bisection its first scan speculates on (on the
-// FHD frame the composited threshold has median 2^-3.9).
-constexpr int kCompGeoLevels = 4;
+// Levels of the compositing bisection its first scan speculates on: along
+// the path toward a predicted threshold where there is one (the staged
+// general merge), else along the all-feasible path gmax/2, gmax/4, ... (on
+// the FHD frame the composited threshold has median 2^-3.9).
+template <typename R> struct FirstLevels { static constexpr int L = 4; };
+template <> struct FirstLevels<StageReader> { static constexpr int L = 6; };
 
 // Re-segmentation of pixel p's merged list (read through rd, `total`
 // elements): pass-through when it fits (R17), else the fixed threshold or the
-// bisection (two levels per scan), then the zero-filled tail.  With VALIDATE
-// the first pass checks the elements and returns false, with the pixel's
-// output incomplete, if one fails.
+// bisection, then the zero-filled tail.  The bisection's first scan carries
+// the midpoints of its first levels along the path toward `ghat` (a predicted
+// threshold; 0 or NaN: the all-feasible path), and its decisions are replayed
+// up to the first one the prediction got wrong; later scans carry two levels
+// (the midpoint and both of the next level's).  The result is the bisection's
+// whatever ghat is.  With VALIDATE the first pass checks the elements and
+// returns false, with the pixel's output incomplete, if one fails.
 template <bool VALIDATE, typename R>
-__device__ bool resegment(const CompParams& P, const R& rd0, int total, uint32_t p)
+__device__ bool resegment(const CompParams& P, const R& rd0, int total, uint32_t p, float ghat = 0.0f)
 {
     COut o{P.out_color, P.out_depth, p, P.npix, P.out_n};
     int count;
@@ -464,24 +498,32 @@ __device__ bool resegment(const CompParams& P, const R& rd0, int total, uint32_t
         float lo = 0.0f, hi = P.gmax;
         int level = 0;
         {
-            // first scan: the midpoints gmax/2 .. gmax/16 the bisection tests
-            // while every level is feasible, replayed up to the first
-            // infeasible one (this scan also validates the list)
-            float gg[kCompGeoLevels];
-            int cg[kCompGeoLevels];
+            // first scan: the midpoints of the first levels along the
+            // predicted path (predicted feasible iff the midpoint is at least
+            // ghat), replayed up to the first level decided otherwise (this
+            // scan also validates the list)
+            constexpr int L = FirstLevels<R>::L;
+            float gg[L];
+            bool pf[L];
+            int cg[L];
+            float plo = 0.0f, phi = P.gmax;
 #pragma unroll
-            for (int l = 0; l < kCompGeoLevels; ++l) gg[l] = ldexpf(P.gmax, -(l + 1));
-            c_scan<kCompGeoLevels, false, VALIDATE>(rd0, total, P.inv_ref, gg, 0, P.out_n, o, cg, &bad);
-            const int lim = kCompGeoLevels < P.iters ? kCompGeoLevels : P.iters;
+            for (int l = 0; l < L; ++l) {
+                const float m = 0.5f * (plo + phi);
+                gg[l] = m;
+                pf[l] = !(ghat > m);
+                plo = pf[l] ? plo : m;
+                phi = pf[l] ? m : phi;
+            }
+            c_scan<L, false, VALIDATE>(rd0, total, P.inv_ref, gg, 0, P.out_n, o, cg, &bad);
+            const int lim = L < P.iters ? L : P.iters;
             for (int l = 0; l < lim && !bad; ++l) {
                 const float m = 0.5f * (lo + hi);
                 ++level;
-                if (cg[l] <= P.out_n) {
-                    hi = m;
-                } else {
-                    lo = m;
-                    break;
-                }
+                const bool feasible = cg[l] <= P.out_n;
+                if (feasible) hi = m;
+                else lo = m;
+                if (feasible != pf[l]) break;
             }
         }
         while (!bad && level + 2 <= P.iters) {
@@ -675,6 +717,11 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
 
 constexpr int kOrdEntries = 16;   // entries per merge_order_kernel wavefront
 constexpr int kStageTile = 8;     // entries per merge_stage_kernel block
+constexpr int kStageBatch = 8;    // loads a merge_stage_kernel thread keeps in flight
+// Threshold prediction: consecutive-operand distances binned by log2 over
+// [kPredLo, kPredHi).
+constexpr int kPredBins = 64;
+constexpr float kPredLo = -8.0f, kPredHi = 1.0f;
 
 // First slot of input r in an entry's row of merged-list capacity (the
 // inputs' max_n in order).
@@ -685,18 +732,30 @@ __device__ inline int input_base(const CompParams& P, int r)
     return b;
 }
 
-// Lexicographic minimum of (front, input) across the 4 lanes of an entry.
+// Lexicographic minimum of (front, input) across the 4 lanes of an entry
+// (DPP quad permutations: lane ^ 1, then lane ^ 2).
+template <int CTRL>
+__device__ inline int quad_swap(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
 __device__ inline void quad_min(float& f, int& r)
 {
-#pragma unroll
-    for (int m = 1; m <= 2; m <<= 1) {
-        const float of = __shfl_xor(f, m, 64);
-        const int orr = __shfl_xor(r, m, 64);
-        const bool take = (of < f) | ((of == f) & (orr < r));
-        f = take ? of : f;
-        r = take ? orr : r;
-    }
+    float of = __int_as_float(quad_swap<0xB1>(__float_as_int(f)));
+    int orr = quad_swap<0xB1>(r);
+    bool take = (of < f) | ((of == f) & (orr < r));
+    f = take ? of : f;
+    r = take ? orr : r;
+    of = __int_as_float(quad_swap<0x4E>(__float_as_int(f)));
+    orr = quad_swap<0x4E>(r);
+    take = (of < f) | ((of == f) & (orr < r));
+    f = take ? of : f;
+    r = take ? orr : r;
 }
+
+// Depth loads a merge_order_kernel lane keeps in flight while reading its
+// lists' fronts.
+constexpr int kOrdBatch = 8;
 
 // J: lists per lane (k <= 4 J).
 template <int J>
@@ -732,11 +791,19 @@ __global__ __launch_bounds__(64) void merge_order_kernel(CompParams P, uint32_t 
             const uint32_t stride = in.compact ? 1u : P.npix;
             const int b0 = input_base(P, r);
             float prev = -__builtin_inff();
-            for (int s_ = 0; s_ < c; ++s_) {
-                const float2 fb = gload(in.depth, eb + (uint32_t)s_ * stride);
-                bad |= !(isfinite(fb.x) & isfinite(fb.y) & (fb.x < fb.y) & (fb.x >= prev));
-                prev = fb.x;
-                F[b0 + s_] = fb.x;
+            for (int s0 = 0; s0 < c; s0 += kOrdBatch) {
+                float2 fb[kOrdBatch];
+#pragma unroll
+                for (int u = 0; u < kOrdBatch; ++u)
+                    if (s0 + u < c) fb[u] = gload(in.depth, eb + (uint32_t)(s0 + u) * stride);
+#pragma unroll
+                for (int u = 0; u < kOrdBatch; ++u) {
+                    if (s0 + u < c) {
+                        bad |= !(isfinite(fb[u].x) & isfinite(fb[u].y) & (fb[u].x < fb[u].y) & (fb[u].x >= prev));
+                        prev = fb[u].x;
+                        F[b0 + s0 + u] = fb[u].x;
+                    }
+                }
             }
             cnt[j] = c;
             base[j] = b0;
@@ -744,18 +811,21 @@ __global__ __launch_bounds__(64) void merge_order_kernel(CompParams P, uint32_t 
         }
     }
     // the entry's total and validity over its 4 lanes
-    tot += __shfl_xor(tot, 1, 64);
-    tot += __shfl_xor(tot, 2, 64);
+    tot += quad_swap<0xB1>(tot);
+    tot += quad_swap<0x4E>(tot);
     int badi = bad ? 1 : 0;
-    badi |= __shfl_xor(badi, 1, 64);
-    badi |= __shfl_xor(badi, 2, 64);
+    badi |= quad_swap<0xB1>(badi);
+    badi |= quad_swap<0x4E>(badi);
     if (badi) tot = 0;
     if (active && sub == 0) {
         P.qtot[le] = badi ? -1 : tot;
         if (badi) reject_pixel(P, p);
     }
     // ---- merge: each step the lane's smallest head, then the entry's; the
-    // lane owning the winner records (input, slot) and advances.  A lane
+    // lane owning the winner records (input, slot) and advances.  Each list
+    // keeps its head and next front in registers; the front after next is
+    // read from LDS when the list advances and merged into the registers a
+    // step later, so the read's latency overlaps the next selection.  A lane
     // reads back only fronts it wrote itself.
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -767,7 +837,11 @@ __global__ __launch_bounds__(64) void merge_order_kernel(CompParams P, uint32_t 
 #pragma unroll
     for (int m = 4; m < 64; m <<= 1) wmax = max(wmax, __shfl_xor(wmax, m, 64));
     uint16_t* seq = P.seq + (size_t)(le >> 3) * P.seq_cap * 8 + (le & 7);
+    int pj = -1;                          // list whose front after next is pending
+    float pv = __builtin_inff();          // that front
     for (int i = 0; i < wmax; ++i) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) nf[j] = j == pj ? pv : nf[j];
         float bf = __builtin_inff();
         int bj = 0;
 #pragma unroll
@@ -779,20 +853,20 @@ __global__ __launch_bounds__(64) void merge_order_kernel(CompParams P, uint32_t 
         int br = bf < __builtin_inff() ? sub + 4 * bj : 0x7fff;
         quad_min(bf, br);
         const bool own = (i < tot) & ((br & 3) == sub) & (br < 0x7fff);
-        if (own) {
-            const int jw = br >> 2;
-            int sw = 0;
+        const int jw = own ? br >> 2 : -1;
+        int sw = 0, bw = 0, cw = 0;
 #pragma unroll
-            for (int j = 0; j < J; ++j) {
-                if (j == jw) {
-                    sw = cur[j];
-                    cur[j] = sw + 1;
-                    hf[j] = nf[j];
-                    nf[j] = sw + 2 < cnt[j] ? F[base[j] + sw + 2] : __builtin_inff();
-                }
-            }
-            seq[(size_t)i * 8] = (uint16_t)((br << 6) | sw);
+        for (int j = 0; j < J; ++j) {
+            const bool w = j == jw;
+            sw = w ? cur[j] : sw;
+            bw = w ? base[j] : bw;
+            cw = w ? cnt[j] : cw;
+            hf[j] = w ? nf[j] : hf[j];
+            cur[j] += w ? 1 : 0;
         }
+        pj = jw;
+        pv = (own & (sw + 2 < cw)) ? F[bw + sw + 2] : __builtin_inff();
+        if (own) seq[(size_t)i * 8] = (uint16_t)((br << 6) | sw);
     }
 }
 
@@ -805,6 +879,8 @@ __global__ __launch_bounds__(256) void merge_stage_kernel(CompParams P, uint32_t
     __shared__ int baseS[kMaxInputs];
     __shared__ uint8_t rinS[kOrderedMaxCap];
     __shared__ int totS[kStageTile];
+    __shared__ uint16_t codeS[kOrderedMaxCap * kStageTile];
+    __shared__ uint32_t histS[kStageTile * kPredBins];
     const int t = threadIdx.x;
     const int cap = P.seq_cap;
     float4* Ec = (float4*)lds_raw;                         // [cap][8]
@@ -835,33 +911,100 @@ __global__ __launch_bounds__(256) void merge_stage_kernel(CompParams P, uint32_t
     }
     __syncthreads();
     // elements into LDS: (slot row, entry) with the entry fastest, so the 8
-    // entries of a row read one line of each slot-major plane
-    for (int idx = t; idx < cap * kStageTile; idx += 256) {
-        const int q = idx & 7, rs = idx >> 3;
-        const int r = rinS[rs];
-        const int s_ = rs - baseS[r];
-        if (s_ < cntS[q][r]) {
-            const CompInput& in = P.in[r];
-            const uint32_t e = ebS[q][r] + (uint32_t)s_ * (in.compact ? 1u : P.npix);
-            Ec[idx] = gload(in.color, e);
-            Ed[idx] = gload(in.depth, e);
+    // entries of a row read one line of each slot-major plane; each thread
+    // keeps kStageBatch loads in flight
+    const int n_el = cap * kStageTile;
+    for (int b0 = 0; b0 < n_el; b0 += 256 * kStageBatch) {
+        float4 c[kStageBatch];
+        float2 d[kStageBatch];
+        bool v[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int idx = b0 + t + 256 * u;
+            v[u] = false;
+            if (idx < n_el) {
+                const int q = idx & 7, rs = idx >> 3;
+                const int r = rinS[rs];
+                const int s_ = rs - baseS[r];
+                if (s_ < cntS[q][r]) {
+                    const CompInput& in = P.in[r];
+                    const uint32_t e = ebS[q][r] + (uint32_t)s_ * (in.compact ? 1u : P.npix);
+                    c[u] = gload(in.color, e);
+                    d[u] = gload(in.depth, e);
+                    v[u] = true;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            if (v[u]) {
+                const int idx = b0 + t + 256 * u;
+                Ec[idx] = c[u];
+                Ed[idx] = d[u];
+            }
         }
     }
-    __syncthreads();
     int tmax = 0;
 #pragma unroll
     for (int q = 0; q < kStageTile; ++q) tmax = max(tmax, totS[q]);
-    // merged order out: slab row i, columns of the 8 entries
+    // the merge order of the 8 entries into LDS
     const uint16_t* seq = P.seq + (size_t)(le0 >> 3) * cap * 8;
-    const size_t slab = (size_t)(le0 >> 6) * cap * 64 + (le0 & 63);
-    for (int idx = t; idx < tmax * kStageTile; idx += 256) {
-        const int q = idx & 7, i = idx >> 3;
-        if (i < totS[q]) {
-            const uint32_t code = seq[(size_t)i * 8 + q];
-            const int rs = baseS[code >> 6] + (int)(code & 63u);
-            P.stage_c[slab + (size_t)i * 64 + q] = Ec[rs * kStageTile + q];
-            P.stage_d[slab + (size_t)i * 64 + q] = Ed[rs * kStageTile + q];
+    const int n_out = tmax * kStageTile;
+    for (int b0 = 0; b0 < n_out; b0 += 256 * kStageBatch) {
+        uint16_t code[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int idx = b0 + t + 256 * u;
+            const int q = idx & 7, i = idx >> 3;
+            code[u] = (idx < n_out && i < totS[q]) ? seq[(size_t)i * 8 + q] : (uint16_t)0xffffu;
         }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int idx = b0 + t + 256 * u;
+            if (idx < n_out) codeS[idx] = code[u];
+        }
+    }
+    for (int i = t; i < kStageTile * kPredBins; i += 256) histS[i] = 0u;
+    __syncthreads();
+    // merged order out: slab row i, columns of the 8 entries; and the
+    // distances between consecutive elements' per-step premultiplied colours
+    // (the Eq. 1 operands), binned by log2 for the threshold prediction
+    const size_t slab = (size_t)(le0 >> 6) * cap * 64 + (le0 & 63);
+    for (int idx = t; idx < n_out; idx += 256) {
+        const uint32_t code = codeS[idx];
+        if (code == 0xffffu) continue;
+        const int q = idx & 7, i = idx >> 3;
+        const int rs = baseS[code >> 6] + (int)(code & 63u);
+        const float4 c = Ec[rs * kStageTile + q];
+        P.stage_c[slab + (size_t)i * 64 + q] = c;
+        P.stage_d[slab + (size_t)i * 64 + q] = Ed[rs * kStageTile + q];
+        if (i > 0) {
+            const uint32_t pc = codeS[idx - kStageTile];
+            const float4 c0 = Ec[(baseS[pc >> 6] + (int)(pc & 63u)) * kStageTile + q];
+            const float d0 = c.x * c.w - c0.x * c0.w, d1 = c.y * c.w - c0.y * c0.w, d2 = c.z * c.w - c0.z * c0.w;
+            const float l2 = 0.5f * hw_log2(d0 * d0 + d1 * d1 + d2 * d2);
+            const float x = (l2 - kPredLo) * (kPredBins / (kPredHi - kPredLo));
+            const int bin = x > 0.0f ? min((int)x, kPredBins - 1) : 0;
+            atomicAdd(&histS[q * kPredBins + bin], 1u);
+        }
+    }
+    __syncthreads();
+    // predicted threshold: the out_n-th largest distance (a supersegment
+    // ends roughly where consecutive operands differ by more than gamma),
+    // interpolated inside its bin
+    if (t < kStageTile && totS[t] > P.out_n && P.ghat) {
+        uint32_t cum = 0;
+        float lg = kPredLo;
+        for (int b = kPredBins - 1; b >= 0; --b) {
+            const uint32_t c = histS[t * kPredBins + b];
+            if (cum + c >= (uint32_t)P.out_n) {
+                const float frac = ((float)(P.out_n - cum) - 0.5f) / (float)c;
+                lg = kPredLo + ((float)(b + 1) - frac) * ((kPredHi - kPredLo) / kPredBins);
+                break;
+            }
+            cum += c;
+        }
+        P.ghat[le0 + t] = hw_exp2(lg);
     }
 }
 
@@ -877,7 +1020,7 @@ __global__ __launch_bounds__(64) void composite_staged_kernel(CompParams P, uint
     const uint32_t p = (uint32_t)P.q_list[e0 + le];
     const size_t slab = (size_t)blockIdx.x * P.seq_cap * 64;
     const StageReader rd{P.stage_c + slab, P.stage_d + slab, (uint32_t)t, (uint32_t)t};
-    resegment<false>(P, rd, tot, p);
+    resegment<false>(P, rd, tot, p, P.ghat ? P.ghat[le] : 0.0f);
 }
 
 // All pixels by the general merge (k above the depth-disjoint path's limit),
@@ -1089,7 +1232,8 @@ __global__ __launch_bounds__(1024) void order_sort_kernel(CompParams P, uint32_t
 uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix)
 {
     if (seq_cap > kOrderedMaxCap) return 0;
-    const size_t per = (size_t)seq_cap * (sizeof(float4) + sizeof(float2) + sizeof(uint16_t)) + sizeof(int);
+    const size_t per = (size_t)seq_cap * (sizeof(float4) + sizeof(float2) + sizeof(uint16_t)) + sizeof(int) +
+                       sizeof(float);
     size_t c = bytes / per;
     const size_t all = ((size_t)npix + 63) & ~(size_t)63;
     c = std::min(c, all) & ~(size_t)63;
@@ -1102,28 +1246,60 @@ size_t ordered_ws_bytes(int seq_cap, uint32_t chunk)
     const size_t stage = c * seq_cap * (sizeof(float4) + sizeof(float2));
     const size_t seq = (c * seq_cap * sizeof(uint16_t) + 255) & ~(size_t)255;
     const size_t tot = (c * sizeof(int) + 255) & ~(size_t)255;
-    return stage + seq + tot;
+    const size_t gh = (c * sizeof(float) + 255) & ~(size_t)255;
+    return stage + seq + tot + gh;
 }
 
 static size_t stage_lds_bytes(int seq_cap) { return (size_t)seq_cap * kStageTile * (sizeof(float4) + sizeof(float2)); }
 
-// The ordered general merge over the queue, chunk by chunk (every kernel
-// reads the queue length on the device; entries past it exit at once).
-static void launch_ordered(const CompParams& P, hipStream_t s)
+static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s)
 {
     const uint32_t c = P.chunk;
     const size_t lds_ord = (size_t)kOrdEntries * P.seq_cap * sizeof(float);
-    for (uint32_t e0 = 0; e0 < P.npix; e0 += c) {
-        if (P.k <= 16)
-            hipLaunchKernelGGL(merge_order_kernel<4>, dim3(c / kOrdEntries), dim3(64), lds_ord, s, P, e0);
-        else
-            hipLaunchKernelGGL(merge_order_kernel<8>, dim3(c / kOrdEntries), dim3(64), lds_ord, s, P, e0);
-        hipLaunchKernelGGL(merge_stage_kernel, dim3(c / kStageTile), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
-        hipLaunchKernelGGL(composite_staged_kernel, dim3(c / 64), dim3(64), 0, s, P, e0);
-    }
+    if (P.k <= 16)
+        hipLaunchKernelGGL(merge_order_kernel<4>, dim3(c / kOrdEntries), dim3(64), lds_ord, s, P, e0);
+    else
+        hipLaunchKernelGGL(merge_order_kernel<8>, dim3(c / kOrdEntries), dim3(64), lds_ord, s, P, e0);
+    hipLaunchKernelGGL(merge_stage_kernel, dim3(c / kStageTile), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
 }
 
-void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
+// The ordered general merge over the queue, chunk by chunk (every kernel
+// reads the queue length on the device; entries past it exit at once).  With
+// two buffers, chunk c + 1 is ordered and staged on the second stream while
+// chunk c is re-segmented.
+static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync* sync)
+{
+    const uint32_t c = P.chunk;
+    if (!sync || !sync->P2) {
+        for (uint32_t e0 = 0; e0 < P.npix; e0 += c) {
+            launch_order_stage(P, e0, s);
+            hipLaunchKernelGGL(composite_staged_kernel, dim3(c / 64), dim3(64), 0, s, P, e0);
+        }
+        return;
+    }
+    const CompParams* buf[2] = {&P, sync->P2};
+    const uint32_t n = (P.npix + c - 1) / c;
+    // fork: the second stream starts after the caller's work so far
+    (void)hipEventRecord(sync->ev[0], s);
+    (void)hipStreamWaitEvent(sync->aux, sync->ev[0], 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        const int b = (int)(i & 1u);
+        // staging chunk i into buffer b waits until chunk i - 2 (same buffer)
+        // has been re-segmented
+        if (i >= 2) (void)hipStreamWaitEvent(sync->aux, sync->ev[3 + b], 0);
+        launch_order_stage(*buf[b], i * c, sync->aux);
+        (void)hipEventRecord(sync->ev[1 + b], sync->aux);
+        // re-segmenting chunk i waits for its staging
+        (void)hipStreamWaitEvent(s, sync->ev[1 + b], 0);
+        hipLaunchKernelGGL(composite_staged_kernel, dim3(c / 64), dim3(64), 0, s, *buf[b], i * c);
+        (void)hipEventRecord(sync->ev[3 + b], s);
+    }
+    // join: the second stream's work precedes everything after this call
+    (void)hipEventRecord(sync->ev[0], sync->aux);
+    (void)hipStreamWaitEvent(s, sync->ev[0], 0);
+}
+
+void launch_composite(const CompParams& P, int grid_general, hipStream_t s, const OrderedSync* sync)
 {
     const size_t lds = composite_lds_bytes(P.k, P.seq_cap, false);
     const unsigned blocks = composite_blocks(P);
@@ -1131,7 +1307,7 @@ void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
     if (P.k > kCatMaxInputs) {
         if (P.chunk) {
             hipLaunchKernelGGL(queue_all_kernel, dim3((P.npix + 255) / 256), dim3(256), 0, s, P);
-            launch_ordered(P, s);
+            launch_ordered(P, s, sync);
         } else {
             hipLaunchKernelGGL(composite_kernel, dim3(blocks), dim3(kWave), lds, s, P);
         }
@@ -1151,7 +1327,7 @@ void launch_composite(const CompParams& P, int grid_general, hipStream_t s)
     }
     hipLaunchKernelGGL(composite_cat_kernel, dim3(blocks), dim3(kWave), lds_cat, s, P);
     if (P.chunk)
-        launch_ordered(P, s);
+        launch_ordered(P, s, sync);
     else
         hipLaunchKernelGGL(composite_queue_kernel, dim3(g2), dim3(kWave), lds, s, P);
 }

@@ -25,6 +25,8 @@ struct vdi_ctx {
     void* user_ws;        // caller-owned workspace (vdi_ctx_set_workspace); when set, ops use it
     size_t user_ws_bytes; // and never allocate
     void* static_scratch; // device address of the fixed scratch array on this device
+    hipStream_t aux;      // second stream of the ordered general merge (fork/join with the caller's)
+    hipEvent_t ev[5];     // its fork/join events
     int num_cus;
     char arch[64];
 };

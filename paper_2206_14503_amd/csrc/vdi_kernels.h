@@ -138,6 +138,7 @@ struct CompParams {
     uint32_t chunk;           // 0: no staging (merge sequence in LDS)
     uint16_t* seq;            // [chunk / 8][seq_cap][8]: input << 6 | slot
     int* qtot;                // [chunk]: merged-list length (-1: rejected)
+    float* ghat;              // [chunk]: predicted threshold (speculation only; NULL: none)
     float4* stage_c;
     float2* stage_d;
     // optional order of the 64-pixel blocks for the depth-disjoint pass
@@ -158,9 +159,18 @@ constexpr int kOrderedMaxCap = 512;
 uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix);
 size_t ordered_ws_bytes(int seq_cap, uint32_t chunk);
 size_t cat_lds_bytes(int k);                      // depth-disjoint path
-// grid_general: blocks of the queue-driven general merge (with staging, at
-// most the number of slabs)
-void launch_composite(const CompParams& P, int grid_general, hipStream_t s);
+// The ordered general merge runs the merge-order and staging kernels of
+// chunk c + 1 on a second stream while the re-segmentation of chunk c runs on
+// the caller's (two staging buffers, P and P2 differing only in them), joined
+// back by events: ev[0] fork, ev[1..2] staging done per buffer, ev[3..4]
+// re-segmentation done per buffer.
+struct OrderedSync {
+    hipStream_t aux;
+    hipEvent_t ev[5];
+    const CompParams* P2;   // the second buffer (NULL: one buffer, one stream)
+};
+// grid_general: blocks of the queue-driven general merge without staging
+void launch_composite(const CompParams& P, int grid_general, hipStream_t s, const OrderedSync* sync = nullptr);
 // Blocks of 64 consecutive pixels (one per wavefront) covering the image.
 __host__ __device__ inline uint32_t composite_blocks(const CompParams& P) { return (P.npix + 63u) / 64u; }
 

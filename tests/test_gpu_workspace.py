@@ -108,3 +108,44 @@ def test_graph_capture_after_workspace_query(V, layout):
         del g
     finally:
         V.set_workspace(None)
+
+
+def test_graph_capture_of_multi_chunk_general_merge(V):
+    """A general merge spanning several chunks (its staging runs on a second
+    stream forked from and joined back to the caller's): captured in a graph
+    and replayed, equal to the eager run and to the allocation-free path (no
+    staging) bit for bit."""
+    from paper_2206_14503_amd import synth
+    k, n, W, H = 16, 20, 640, 480
+    c, d, cnt = synth.dense_frame(k, n, W * H, seed=9)
+    ins = [V.VDI(W, H, n, 0.01, V.REGULAR, c[r], d[r], cnt[r]) for r in range(k)]
+    need = V.workspace_size(V.OP_COMPOSITE, W, H, k, in_max_n_sum=k * n)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    V.set_workspace(ws)
+    try:
+        out = V.VDI.empty(W, H, n, 0.01, V.REGULAR)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            V.composite(ins, V.BISECT, 0.0, n, 10, out=out)
+        s.synchronize()
+        ref = V.VDI(W, H, n, 0.01, V.REGULAR, out.color.clone(), out.depth.clone(), out.count.clone(),
+                    None, out.gamma.clone())
+        alt = V.composite(ins, V.BISECT, 0.0, n, 10, noalloc=True)
+        torch.cuda.synchronize()
+        assert torch.equal(alt.color, ref.color) and torch.equal(alt.depth, ref.depth)
+        assert torch.equal(alt.count, ref.count) and torch.equal(alt.gamma, ref.gamma)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            V.composite(ins, V.BISECT, 0.0, n, 10, out=out)
+        for rep in range(2):
+            out.color.zero_()
+            out.count.fill_(-1)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert _same(out, ref), f"replay {rep} differs from the eager run"
+        assert V.device_status() == 0
+        del g
+    finally:
+        V.set_workspace(None)
