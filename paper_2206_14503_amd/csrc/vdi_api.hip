@@ -390,6 +390,7 @@ static vdi_status composite_params(vdi_ctx* ctx, const vdi_t* in, int k, const v
     P.out_gamma = out->gamma;
     P.status = ctx->status;
     P.seq_cap = seq_cap;
+    P.num_cus = ctx->num_cus;
     return VDI_OK;
 }
 
@@ -682,10 +683,12 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     if ((st = ensure_scratch(ctx, W.total)) != VDI_OK) return st;
     char* base = ws_base(ctx);
     composite_queues(P, base, W.qbytes);
-    if (W.chunk) composite_ordered(P, base + W.qbytes + W.obytes, W.chunk);
+    // the ordered merge's buffers after the queue and the block order
+    char* obase = base + W.qbytes + W.obytes;
+    if (W.chunk) composite_ordered(P, obase, W.chunk);
     if (W.nbuf == 2) {
         CompParams P2 = P;
-        composite_ordered(P2, base + W.qbytes + W.obytes + W.buf, W.chunk);
+        composite_ordered(P2, obase + W.buf, W.chunk);
         OrderedSync sync;
         sync.aux = ctx->aux;
         for (int i = 0; i < 5; ++i) sync.ev[i] = ctx->ev[i];

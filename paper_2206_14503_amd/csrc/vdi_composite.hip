@@ -569,6 +569,17 @@ __device__ bool resegment(const CompParams& P, const R& rd0, int total, uint32_t
     return true;
 }
 
+// The depth-disjoint reader's per-list words of pixel p: count and element
+// index of slot 0.
+__device__ inline void cat_words(const CompParams& P, const CatLds& L, int t, uint32_t p)
+{
+    for (int r = 0; r < P.k; ++r) {
+        const CompInput& in = P.in[r];
+        L.a[r * kWave + t] = __int_as_float(in.count[p]);
+        L.b[r * kWave + t] = __uint_as_float(in.compact ? in.offset[p] : p);
+    }
+}
+
 // Depth-disjoint path for pixel p (lane t): when every front of a list lies
 // below the first front of the list after it in order of first front, the
 // merge by (front, input) is the lists' concatenation in that order, so no
@@ -613,12 +624,19 @@ __device__ bool composite_pixel_cat(const CompParams& P, unsigned char* lds_raw,
         ord |= (uint64_t)r << (4 * rank);
         ++ne;
     }
-    // ---- the reader's per-list words: count and element index of slot 0
-    for (int r = 0; r < P.k; ++r) {
+    // ---- lists that interleave in depth (some front of a list at or above
+    // the first front of the list after it): the general merge
+    float prev_last = -__builtin_inff();
+    for (int i = 0; i < ne; ++i) {
+        const int r = (int)((ord >> (4 * i)) & 15u);
         const CompInput& in = P.in[r];
-        L.a[r * kWave + t] = __int_as_float(in.count[p]);
-        L.b[r * kWave + t] = __uint_as_float(in.compact ? in.offset[p] : p);
+        const uint32_t eb = in.compact ? in.offset[p] : p;
+        const int c = in.count[p];
+        if (!(L.a[r * kWave + t] > prev_last)) return false;
+        prev_last = gload(in.depth, eb + (uint32_t)(c - 1) * (in.compact ? 1u : P.npix)).x;
     }
+    // ---- the reader's per-list words: count and element index of slot 0
+    cat_words(P, L, t, p);
     CatReader rd{L, t, ord, ne, 0, 0, 0, 0u, 0u, nullptr, nullptr};
     return resegment<true>(P, rd, total, p);
 }
@@ -759,12 +777,10 @@ constexpr int kOrdBatch = 8;
 
 // J: lists per lane (k <= 4 J).
 template <int J>
-__global__ __launch_bounds__(64) void merge_order_kernel(CompParams P, uint32_t e0)
+__device__ void merge_order_group(const CompParams& P, uint32_t e0, uint32_t grp, float* fr, uint32_t nq)
 {
-    extern __shared__ __align__(16) float fr[];      // [16][seq_cap] fronts, entry rows
     const int t = threadIdx.x, ql = t >> 2, sub = t & 3;
-    const uint32_t le = blockIdx.x * kOrdEntries + ql;
-    const uint32_t nq = (uint32_t)*P.q_count;
+    const uint32_t le = grp * kOrdEntries + ql;
     const bool active = le < P.chunk && e0 + le < nq;
     const uint32_t p = active ? (uint32_t)P.q_list[e0 + le] : 0u;
     float* F = fr + ql * P.seq_cap;
@@ -870,23 +886,45 @@ __global__ __launch_bounds__(64) void merge_order_kernel(CompParams P, uint32_t 
     }
 }
 
-// One block of 256 threads per tile of 8 chunk entries.
-__global__ __launch_bounds__(256) void merge_stage_kernel(CompParams P, uint32_t e0)
+// Persistent: blocks take groups of 16 chunk entries until the chunk or the
+// queue ends.
+template <int J>
+__global__ __launch_bounds__(64) void merge_order_kernel(CompParams P, uint32_t e0)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    __shared__ int cntS[kStageTile][kMaxInputs];
-    __shared__ uint32_t ebS[kStageTile][kMaxInputs];
-    __shared__ int baseS[kMaxInputs];
-    __shared__ uint8_t rinS[kOrderedMaxCap];
-    __shared__ int totS[kStageTile];
-    __shared__ uint16_t codeS[kOrderedMaxCap * kStageTile];
-    __shared__ uint32_t histS[kStageTile * kPredBins];
+    extern __shared__ __align__(16) float fr[];      // [16][seq_cap] fronts, entry rows
+    const uint32_t nq = (uint32_t)*P.q_count;
+    const uint32_t groups = P.chunk / kOrdEntries;
+    for (uint32_t g = blockIdx.x; g < groups && e0 + g * kOrdEntries < nq; g += gridDim.x)
+        merge_order_group<J>(P, e0, g, fr, nq);
+}
+
+// LDS of merge_stage_kernel besides the tile's elements.
+struct StageLds {
+    int cntS[kStageTile][kMaxInputs];
+    uint32_t ebS[kStageTile][kMaxInputs];
+    int baseS[kMaxInputs];
+    uint8_t rinS[kOrderedMaxCap];
+    int totS[kStageTile];
+    uint16_t codeS[kOrderedMaxCap * kStageTile];
+    uint32_t histS[kStageTile * kPredBins];
+};
+
+// One tile of 8 chunk entries by a block of 256 threads.
+__device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile, unsigned char* lds_raw,
+                                 StageLds& S, uint32_t nq)
+{
+    int(&cntS)[kStageTile][kMaxInputs] = S.cntS;
+    uint32_t(&ebS)[kStageTile][kMaxInputs] = S.ebS;
+    int* baseS = S.baseS;
+    uint8_t* rinS = S.rinS;
+    int* totS = S.totS;
+    uint16_t* codeS = S.codeS;
+    uint32_t* histS = S.histS;
     const int t = threadIdx.x;
     const int cap = P.seq_cap;
     float4* Ec = (float4*)lds_raw;                         // [cap][8]
     float2* Ed = (float2*)(lds_raw + (size_t)cap * kStageTile * sizeof(float4));
-    const uint32_t le0 = blockIdx.x * kStageTile;
-    const uint32_t nq = (uint32_t)*P.q_count;
+    const uint32_t le0 = tile * kStageTile;
     if (t < kStageTile) {
         const uint32_t le = le0 + t;
         totS[t] = (le < P.chunk && e0 + le < nq) ? P.qtot[le] : -1;
@@ -1006,21 +1044,38 @@ __global__ __launch_bounds__(256) void merge_stage_kernel(CompParams P, uint32_t
         }
         P.ghat[le0 + t] = hw_exp2(lg);
     }
+    __syncthreads();   // the next tile reuses the LDS
 }
 
-// One wavefront per group of 64 chunk entries: re-segmentation over the slab.
+// Persistent: blocks take tiles of 8 chunk entries until the chunk or the
+// queue ends.
+__global__ __launch_bounds__(256) void merge_stage_kernel(CompParams P, uint32_t e0)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ StageLds S;
+    const uint32_t nq = (uint32_t)*P.q_count;
+    const uint32_t tiles = P.chunk / kStageTile;
+    for (uint32_t tl = blockIdx.x; tl < tiles && e0 + tl * kStageTile < nq; tl += gridDim.x)
+        merge_stage_tile(P, e0, tl, lds_raw, S, nq);
+}
+
+// Persistent, one wavefront per group of 64 chunk entries at a time:
+// re-segmentation over the slab.
 __global__ __launch_bounds__(64) void composite_staged_kernel(CompParams P, uint32_t e0)
 {
     const int t = threadIdx.x;
-    const uint32_t le = blockIdx.x * 64 + t;
     const uint32_t nq = (uint32_t)*P.q_count;
-    if (le >= P.chunk || e0 + le >= nq) return;
-    const int tot = P.qtot[le];
-    if (tot < 0) return;
-    const uint32_t p = (uint32_t)P.q_list[e0 + le];
-    const size_t slab = (size_t)blockIdx.x * P.seq_cap * 64;
-    const StageReader rd{P.stage_c + slab, P.stage_d + slab, (uint32_t)t, (uint32_t)t};
-    resegment<false>(P, rd, tot, p, P.ghat ? P.ghat[le] : 0.0f);
+    const uint32_t groups = P.chunk / 64;
+    for (uint32_t g = blockIdx.x; g < groups && e0 + g * 64 < nq; g += gridDim.x) {
+        const uint32_t le = g * 64 + t;
+        if (e0 + le >= nq) continue;
+        const int tot = P.qtot[le];
+        if (tot < 0) continue;
+        const uint32_t p = (uint32_t)P.q_list[e0 + le];
+        const size_t slab = (size_t)g * P.seq_cap * 64;
+        const StageReader rd{P.stage_c + slab, P.stage_d + slab, (uint32_t)t, (uint32_t)t};
+        resegment<false>(P, rd, tot, p, P.ghat ? P.ghat[le] : 0.0f);
+    }
 }
 
 // All pixels by the general merge (k above the depth-disjoint path's limit),
@@ -1252,15 +1307,23 @@ size_t ordered_ws_bytes(int seq_cap, uint32_t chunk)
 
 static size_t stage_lds_bytes(int seq_cap) { return (size_t)seq_cap * kStageTile * (sizeof(float4) + sizeof(float2)); }
 
+// Grids of the persistent ordered-merge kernels: enough blocks to fill the
+// device (and no more than the chunk has work for).
+static unsigned ord_grid(const CompParams& P, uint32_t units, int per_cu)
+{
+    return std::max(1u, std::min(units, (unsigned)(P.num_cus * per_cu)));
+}
+
 static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s)
 {
     const uint32_t c = P.chunk;
     const size_t lds_ord = (size_t)kOrdEntries * P.seq_cap * sizeof(float);
+    const unsigned g1 = ord_grid(P, c / kOrdEntries, 16), g2 = ord_grid(P, c / kStageTile, 4);
     if (P.k <= 16)
-        hipLaunchKernelGGL(merge_order_kernel<4>, dim3(c / kOrdEntries), dim3(64), lds_ord, s, P, e0);
+        hipLaunchKernelGGL(merge_order_kernel<4>, dim3(g1), dim3(64), lds_ord, s, P, e0);
     else
-        hipLaunchKernelGGL(merge_order_kernel<8>, dim3(c / kOrdEntries), dim3(64), lds_ord, s, P, e0);
-    hipLaunchKernelGGL(merge_stage_kernel, dim3(c / kStageTile), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
+        hipLaunchKernelGGL(merge_order_kernel<8>, dim3(g1), dim3(64), lds_ord, s, P, e0);
+    hipLaunchKernelGGL(merge_stage_kernel, dim3(g2), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
 }
 
 // The ordered general merge over the queue, chunk by chunk (every kernel
@@ -1273,7 +1336,7 @@ static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync
     if (!sync || !sync->P2) {
         for (uint32_t e0 = 0; e0 < P.npix; e0 += c) {
             launch_order_stage(P, e0, s);
-            hipLaunchKernelGGL(composite_staged_kernel, dim3(c / 64), dim3(64), 0, s, P, e0);
+            hipLaunchKernelGGL(composite_staged_kernel, dim3(ord_grid(P, c / 64, 20)), dim3(64), 0, s, P, e0);
         }
         return;
     }
@@ -1291,7 +1354,7 @@ static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync
         (void)hipEventRecord(sync->ev[1 + b], sync->aux);
         // re-segmenting chunk i waits for its staging
         (void)hipStreamWaitEvent(s, sync->ev[1 + b], 0);
-        hipLaunchKernelGGL(composite_staged_kernel, dim3(c / 64), dim3(64), 0, s, *buf[b], i * c);
+        hipLaunchKernelGGL(composite_staged_kernel, dim3(ord_grid(P, c / 64, 20)), dim3(64), 0, s, *buf[b], i * c);
         (void)hipEventRecord(sync->ev[3 + b], s);
     }
     // join: the second stream's work precedes everything after this call

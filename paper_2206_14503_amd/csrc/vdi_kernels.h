@@ -139,6 +139,7 @@ struct CompParams {
     uint16_t* seq;            // [chunk / 8][seq_cap][8]: input << 6 | slot
     int* qtot;                // [chunk]: merged-list length (-1: rejected)
     float* ghat;              // [chunk]: predicted threshold (speculation only; NULL: none)
+    int num_cus;              // compute units of the device (grid sizes of the persistent kernels)
     float4* stage_c;
     float2* stage_d;
     // optional order of the 64-pixel blocks for the depth-disjoint pass
