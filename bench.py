@@ -496,6 +496,33 @@ def learned_case(args, result, cfg, key, eval_seeds):
     torch.cuda.empty_cache()
 
 
+def leg_learned_composite(args, result):
+    """The compositing bisection's first scan steered by a regressor trained
+    here (on dense interleaved frames of other seeds) against the default
+    out_n-th-largest-distance rule, on the headline frame: same output, time
+    of each."""
+    import torch
+    from paper_2206_14503_amd import learned, synth, vdi
+    t0 = time.time()
+    X, Y, st = learned.composite_training_pairs(seeds=range(900, 900 + args.learn_seeds // 4))
+    mlp = learned.init_mlp(0)
+    losses = learned.train(mlp, X, Y, epochs=args.learn_epochs, batch=4096, lr=2e-3)
+    t_train = time.time() - t0
+    del X, Y
+    w = synth.large(args.seed)
+    cam = synth.camera_for(w)
+    P = cam.width * cam.height
+    color, depth, count = synth.dense_frame(16, 20, P, seed=args.seed)
+    ins = [vdi.VDI(cam.width, cam.height, 20, 0.01, vdi.REGULAR, color[r], depth[r], count[r]) for r in range(16)]
+    ev_ = learned.evaluate_composite(mlp, ins, 20, reps=3)
+    log(f"[bench] learned composite: {st['pairs']} training pairs, loss {losses[-1]:.4f}, {t_train:.1f}s; {ev_}")
+    result["learned_composite"] = {"workload": "large-dense-16x20-1920x1080-N20 (the headline frame)",
+                                   "train_pairs": st["pairs"], "train_seconds": t_train, "final_loss": losses[-1],
+                                   **ev_}
+    del ins, color, depth, count
+    torch.cuda.empty_cache()
+
+
 # ---------------------------------------------------------------- batched composites
 
 def leg_batched(args, result):
@@ -694,6 +721,7 @@ def main():
         leg_large(args, result)
     if "learned" in legs:
         leg_learned(args, result)
+        leg_learned_composite(args, result)
     if "batched" in legs:
         leg_batched(args, result)
     if not args.no_cpu_baseline:

@@ -174,6 +174,9 @@ typedef struct {
     float feature_scale;     /* LEARNED: histogram counts are divided by this (s_ref) */
     const float *y;          /* LEARNED: optional device array [k][H*W] of log2 thresholds
                                 used instead of the MLP's output (NULL: run the MLP) */
+    uint16_t *features;      /* vdi_composite: optional DEVICE output [H*W][64] bf16, the
+                                threshold-prediction features of every pixel the general
+                                merge re-segmented (others left unwritten; see below) */
 } vdi_tau_t;
 
 /* Context: one per device and thread of use.  vdi_ctx_create makes `device`
@@ -236,7 +239,16 @@ vdi_status vdi_generate(vdi_ctx *ctx, const vdi_brick_t *bricks, int k, const vd
  * entries it is written unchanged; otherwise each entry is treated as a
  * sample of its own length with opacity corrected by Eq. 2, empty space
  * between entries as transparent samples, and the list is re-segmented with
- * the Eq. 1 criterion and a threshold chosen per `tau` (FIXED or BISECT).
+ * the Eq. 1 criterion and a threshold chosen per `tau` (FIXED, BISECT or
+ * LEARNED).  BISECT and LEARNED give the same result, the bisection's: on
+ * pixels whose lists interleave in depth (the general merge), the first scan
+ * of the bisection evaluates the midpoints along the path toward a predicted
+ * threshold, from a 64-bin histogram of log2 of the distances between
+ * consecutive merged elements' per-step premultiplied colours (bins over
+ * [-8, 1), counts divided by out->max_n): BISECT predicts the out->max_n-th
+ * largest distance, LEARNED the MLP tau->mlp's output (log2 threshold; an
+ * extension beyond the paper, trained on such histograms; see vdi_mlp_*).
+ * tau->features, if set, receives those histograms (bf16) per pixel.
  * All inputs share width, height and ref_step with out; out must be regular.
  * Inputs may mix layouts.  k in [1, VDI_MAX_INPUTS]. */
 vdi_status vdi_composite(vdi_ctx *ctx, const vdi_t *in, int k, const vdi_tau_t *tau, vdi_t *out,
@@ -332,6 +344,18 @@ vdi_status vdi_mlp_backward(vdi_ctx *ctx, const vdi_mlp_t *mlp, const uint16_t *
  * refreshes w_bf16. */
 vdi_status vdi_mlp_adam(vdi_ctx *ctx, vdi_mlp_t *mlp, const float *grad, float *m, float *v, int step, float lr,
                         float beta1, float beta2, float eps, void *stream);
+
+/* Training step of the regressor (log2 thresholds): dy[i] = scale * (y[i] -
+ * log2(gamma[i])) for i < rows (gamma > 0, e.g. the plain bisection's
+ * thresholds), the gradient of 0.5 * sum (y - log2 gamma)^2 times scale; if
+ * loss_part is not NULL, loss_part[b] = that loss over rows [256 b, 256 b +
+ * 256) in fp64, summed in a fixed order ((rows + 255) / 256 entries). */
+vdi_status vdi_mlp_mse(vdi_ctx *ctx, const float *y, const float *gamma, int rows, float scale, float *dy,
+                       double *loss_part, void *stream);
+
+/* w_bf16 = bf16(w_f32) (round to nearest even), e.g. after loading the fp32
+ * master parameters. */
+vdi_status vdi_mlp_pack(vdi_ctx *ctx, vdi_mlp_t *mlp, void *stream);
 
 /* Counts of the learned path since the last call (synchronises `stream`):
  * stats[0] lists kept in round one, [1] lists taking the all-feasible

@@ -271,3 +271,49 @@ def count_at(vol, bricks, cam, tf, step: float, ref: float, gamma: np.ndarray, l
     if rc != 0:
         raise RuntimeError("orc_count_at failed")
     return count, margin
+
+
+# ---------------------------------------------------------------- compositing features
+#
+# Threshold prediction for the compositing bisection (an extension beyond the
+# paper: Sec. 5.2 runs the per-pixel search again in compositing).  For each
+# pixel whose merged list is longer than out_n: the distances between
+# consecutive merged elements' per-step premultiplied colours (rgb * a, the
+# Eq. 1 operands), binned by 0.5 log2 of the squared distance over [-8, 1) in
+# 64 bins (below the range: bin 0; above: bin 63), counts divided by out_n.
+
+PRED_BINS, PRED_LO, PRED_HI = 64, -8.0, 1.0
+
+
+def composite_features(colors, depths, counts, out_n: int):
+    """Features [npix, 64] (fp64, before bf16 rounding) and a mask of the
+    pixels that have them; also the per-pixel number of distances within
+    1e-4 (in log2) of a bin boundary, where an fp32 evaluation may bin the
+    distance on the other side."""
+    k = len(colors)
+    npix = colors[0].shape[1]
+    feats = np.zeros((npix, PRED_BINS))
+    have = np.zeros(npix, bool)
+    near = np.zeros(npix, np.int64)
+    width = (PRED_HI - PRED_LO) / PRED_BINS
+    for p in range(npix):
+        el = []
+        for r in range(k):
+            for j in range(int(counts[r][p])):
+                # merge key (front, input); the slot keeps each list's order
+                el.append((float(depths[r][j, p, 0]), r, j))
+        if len(el) <= out_n:
+            continue
+        el.sort()
+        rep = np.array([colors[r][j, p, :3].astype(np.float64) * float(colors[r][j, p, 3]) for _, r, j in el])
+        d2 = ((rep[1:] - rep[:-1]) ** 2).sum(axis=1)
+        with np.errstate(divide="ignore"):
+            l2 = 0.5 * np.log2(d2)
+        x = (l2 - PRED_LO) / width
+        b = np.where(x > 0, np.minimum(np.floor(np.where(np.isfinite(x), x, 0)), PRED_BINS - 1), 0).astype(int)
+        np.add.at(feats[p], b, 1.0)
+        xf = np.where(np.isfinite(x), x, -1.0)
+        frac = np.abs(xf - np.round(xf)) * width
+        near[p] = int(np.sum((frac < 1e-4) & (xf > 0.5) & (xf < PRED_BINS - 0.5)))
+        have[p] = True
+    return feats / out_n, have, near

@@ -277,6 +277,8 @@ static void composite_ordered(CompParams& P, char* base, uint32_t chunk)
     P.qtot = (int*)q;
     q += (c * sizeof(int) + 255) & ~(size_t)255;
     P.ghat = (float*)q;
+    q += (c * sizeof(float) + 255) & ~(size_t)255;
+    P.feat = P.mlp_wb ? (uint16_t*)q : nullptr;
 }
 
 static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const GenParams& P,
@@ -352,8 +354,13 @@ static vdi_status composite_params(vdi_ctx* ctx, const vdi_t* in, int k, const v
 {
     if (!ctx || !in || !out) return fail(VDI_E_INVALID, "NULL argument");
     if (k < 1 || k > VDI_MAX_INPUTS) return fail(VDI_E_INVALID, "k=%d outside [1, %d]", k, VDI_MAX_INPUTS);
-    vdi_status st = check_tau(tau, false);
+    if (!tau) return fail(VDI_E_INVALID, "tau is NULL");
+    if (tau->mode == VDI_TAU_BISECT_SEQ) return fail(VDI_E_UNSUPPORTED, "BISECT_SEQ is only available for generation");
+    vdi_status st = check_tau(tau, tau->mode == VDI_TAU_LEARNED);
     if (st != VDI_OK) return st;
+    const vdi_mlp_t* mlp = (const vdi_mlp_t*)tau->mlp;
+    if (tau->mode == VDI_TAU_LEARNED && (!mlp || !mlp->w_bf16 || !mlp->w_f32))
+        return fail(VDI_E_INVALID, "learned compositing needs tau->mlp");
     if ((st = check_vdi(out, "out", false)) != VDI_OK) return st;
     memset(&P, 0, sizeof P);
     int seq_cap = 0;
@@ -391,6 +398,12 @@ static vdi_status composite_params(vdi_ctx* ctx, const vdi_t* in, int k, const v
     P.status = ctx->status;
     P.seq_cap = seq_cap;
     P.num_cus = ctx->num_cus;
+    P.feat_out = tau->features;
+    if (tau->mode == VDI_TAU_LEARNED) {
+        P.mode = VDI_TAU_BISECT;
+        P.mlp_wb = mlp->w_bf16;
+        P.mlp_wf = mlp->w_f32;
+    }
     return VDI_OK;
 }
 
@@ -873,6 +886,24 @@ vdi_status vdi_mlp_adam(vdi_ctx* ctx, vdi_mlp_t* mlp, const float* grad, float* 
     if (st != VDI_OK) return st;
     if (step < 1) return fail(VDI_E_INVALID, "step must be >= 1");
     launch_mlp_adam(mlp->w_f32, mlp->w_bf16, grad, m, v, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+    return launched();
+}
+
+vdi_status vdi_mlp_mse(vdi_ctx* ctx, const float* y, const float* gamma, int rows, float scale, float* dy,
+                       double* loss_part, void* stream)
+{
+    if (!ctx || !y || !gamma || !dy) return fail(VDI_E_INVALID, "NULL argument");
+    if (rows <= 0) return fail(VDI_E_INVALID, "rows must be > 0");
+    launch_mlp_mse(y, gamma, rows, scale, dy, loss_part, (hipStream_t)stream);
+    return launched();
+}
+
+vdi_status vdi_mlp_pack(vdi_ctx* ctx, vdi_mlp_t* mlp, void* stream)
+{
+    if (!ctx) return fail(VDI_E_INVALID, "NULL argument");
+    vdi_status st = check_mlp(mlp);
+    if (st != VDI_OK) return st;
+    launch_mlp_pack(mlp->w_f32, mlp->w_bf16, (hipStream_t)stream);
     return launched();
 }
 

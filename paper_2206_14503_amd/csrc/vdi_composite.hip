@@ -1027,10 +1027,23 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
         }
     }
     __syncthreads();
+    // features: the histogram over the out_n (the MLP's input, and an
+    // optional per-pixel copy)
+    if (P.feat || P.feat_out) {
+        const float inv_n = 1.0f / (float)P.out_n;
+        for (int idx = t; idx < kStageTile * kPredBins; idx += 256) {
+            const int q = idx / kPredBins, b = idx - q * kPredBins;
+            if (totS[q] > P.out_n) {
+                const uint16_t v = bf16_bits((float)histS[idx] * inv_n);
+                if (P.feat) P.feat[(size_t)(le0 + q) * kPredBins + b] = v;
+                if (P.feat_out) P.feat_out[(size_t)P.q_list[e0 + le0 + q] * kPredBins + b] = v;
+            }
+        }
+    }
     // predicted threshold: the out_n-th largest distance (a supersegment
     // ends roughly where consecutive operands differ by more than gamma),
-    // interpolated inside its bin
-    if (t < kStageTile && totS[t] > P.out_n && P.ghat) {
+    // interpolated inside its bin; with the MLP, its output replaces it
+    if (t < kStageTile && totS[t] > P.out_n && P.ghat && !P.mlp_wb) {
         uint32_t cum = 0;
         float lg = kPredLo;
         for (int b = kPredBins - 1; b >= 0; --b) {
@@ -1074,7 +1087,8 @@ __global__ __launch_bounds__(64) void composite_staged_kernel(CompParams P, uint
         const uint32_t p = (uint32_t)P.q_list[e0 + le];
         const size_t slab = (size_t)g * P.seq_cap * 64;
         const StageReader rd{P.stage_c + slab, P.stage_d + slab, (uint32_t)t, (uint32_t)t};
-        resegment<false>(P, rd, tot, p, P.ghat ? P.ghat[le] : 0.0f);
+        const float gh = P.ghat ? (P.mlp_wb ? hw_exp2(P.ghat[le]) : P.ghat[le]) : 0.0f;
+        resegment<false>(P, rd, tot, p, gh);
     }
 }
 
@@ -1288,7 +1302,7 @@ uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix)
 {
     if (seq_cap > kOrderedMaxCap) return 0;
     const size_t per = (size_t)seq_cap * (sizeof(float4) + sizeof(float2) + sizeof(uint16_t)) + sizeof(int) +
-                       sizeof(float);
+                       sizeof(float) + kPredBins * sizeof(uint16_t);
     size_t c = bytes / per;
     const size_t all = ((size_t)npix + 63) & ~(size_t)63;
     c = std::min(c, all) & ~(size_t)63;
@@ -1302,7 +1316,8 @@ size_t ordered_ws_bytes(int seq_cap, uint32_t chunk)
     const size_t seq = (c * seq_cap * sizeof(uint16_t) + 255) & ~(size_t)255;
     const size_t tot = (c * sizeof(int) + 255) & ~(size_t)255;
     const size_t gh = (c * sizeof(float) + 255) & ~(size_t)255;
-    return stage + seq + tot + gh;
+    const size_t ft = c * kPredBins * sizeof(uint16_t);
+    return stage + seq + tot + gh + ft;
 }
 
 static size_t stage_lds_bytes(int seq_cap) { return (size_t)seq_cap * kStageTile * (sizeof(float4) + sizeof(float2)); }
@@ -1324,6 +1339,10 @@ static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s)
     else
         hipLaunchKernelGGL(merge_order_kernel<8>, dim3(g1), dim3(64), lds_ord, s, P, e0);
     hipLaunchKernelGGL(merge_stage_kernel, dim3(g2), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
+    // the MLP's log2 threshold for every entry of the chunk (entries past
+    // the queue get one too, unused)
+    if (P.mlp_wb)
+        launch_mlp_fwd(P.mlp_wb, P.mlp_wf, P.feat, (int)c, nullptr, nullptr, P.num_cus * 3, P.ghat, nullptr, s);
 }
 
 // The ordered general merge over the queue, chunk by chunk (every kernel

@@ -138,7 +138,12 @@ struct CompParams {
     uint32_t chunk;           // 0: no staging (merge sequence in LDS)
     uint16_t* seq;            // [chunk / 8][seq_cap][8]: input << 6 | slot
     int* qtot;                // [chunk]: merged-list length (-1: rejected)
-    float* ghat;              // [chunk]: predicted threshold (speculation only; NULL: none)
+    float* ghat;              // [chunk]: predicted threshold (speculation only; NULL: none),
+                              // as log2 when predicted by the MLP (mlp_wb set)
+    uint16_t* feat;           // [chunk][64]: prediction features (bf16), the MLP's input
+    uint16_t* feat_out;       // optional [npix][64]: the same per pixel (training pairs)
+    const uint16_t* mlp_wb;   // LEARNED: the threshold MLP (bf16 weights, fp32 master)
+    const float* mlp_wf;
     int num_cus;              // compute units of the device (grid sizes of the persistent kernels)
     float4* stage_c;
     float2* stage_d;
@@ -196,6 +201,9 @@ void launch_mlp_bwd(const uint16_t* wb, const uint16_t* x, const float* acts, co
 void launch_mlp_adam(float* wf, uint16_t* wb, const float* grad, float* m, float* v, float lr, float b1, float b2,
                      float eps, int step, hipStream_t s);
 void launch_mfma_probe(const uint16_t* A, const uint16_t* B, float* D, hipStream_t s);
+void launch_mlp_mse(const float* y, const float* gamma, int rows, float scale, float* dy, double* loss_part,
+                    hipStream_t s);
+void launch_mlp_pack(const float* wf, uint16_t* wb, hipStream_t s);
 
 // ---------------------------------------------------------------- rendering
 

@@ -391,6 +391,37 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ wf, u
     wb[p] = f2bf(nw);
 }
 
+// Gradient of the regression loss 0.5 * sum_i (y_i - log2(gamma_i))^2 with
+// respect to y, scaled: dy_i = scale * (y_i - log2(gamma_i)); per block of 256
+// rows the loss summed in fp64 in a fixed order (for reporting).
+__global__ __launch_bounds__(256) void mlp_mse_kernel(const float* __restrict__ y, const float* __restrict__ gamma,
+                                                      int rows, float scale, float* __restrict__ dy,
+                                                      double* __restrict__ loss_part)
+{
+    __shared__ double ls[256];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double l = 0.0;
+    if (i < rows) {
+        const float d = y[i] - log2f(gamma[i]);
+        dy[i] = d * scale;
+        l = 0.5 * (double)d * (double)d;
+    }
+    ls[threadIdx.x] = l;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) ls[threadIdx.x] += ls[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss_part) loss_part[blockIdx.x] = ls[0];
+}
+
+// The bf16 copy of the fp32 master parameters (round to nearest even).
+__global__ __launch_bounds__(256) void mlp_pack_kernel(const float* __restrict__ wf, uint16_t* __restrict__ wb)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p <= oB3) wb[p] = f2bf(wf[p]);
+}
+
 // One 16x16x16 product through the matrix core, for checking the fragment layout.
 __global__ void mfma_probe_kernel(const uint16_t* A, const uint16_t* B, float* D)
 {
@@ -432,6 +463,18 @@ void launch_mlp_adam(float* wf, uint16_t* wb, const float* grad, float* m, float
     float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
     hipLaunchKernelGGL(mlp_adam_kernel, dim3((oB3 + 1 + 255) / 256), dim3(256), 0, s, wf, wb, grad, m, v, lr, b1,
                        b2, eps, c1, c2);
+}
+
+void launch_mlp_mse(const float* y, const float* gamma, int rows, float scale, float* dy, double* loss_part,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_mse_kernel, dim3((rows + 255) / 256), dim3(256), 0, s, y, gamma, rows, scale, dy,
+                       loss_part);
+}
+
+void launch_mlp_pack(const float* wf, uint16_t* wb, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_pack_kernel, dim3((oB3 + 1 + 255) / 256), dim3(256), 0, s, wf, wb);
 }
 
 void launch_mfma_probe(const uint16_t* A, const uint16_t* B, float* D, hipStream_t s)

@@ -71,8 +71,9 @@ def frame_inputs(cfg: LearnedConfig, seed: int, res: Tuple[int, int]):
 
 def training_pairs(cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor
                    ) -> Tuple[torch.Tensor, torch.Tensor, Dict[str, int]]:
-    """(histogram, log2 gamma*) pairs from the plain bisection on the GPU, at
-    most cfg.max_pairs (a seeded subsample when there are more).
+    """(histogram, gamma*) pairs from the plain bisection on the GPU, at most
+    cfg.max_pairs (a seeded subsample when there are more); the regressor's
+    target is log2 gamma* (taken in the loss kernel).
 
     Brick-rays with at most N non-transparent samples are left out: every
     threshold is feasible there and the learned path resolves them exactly
@@ -92,7 +93,7 @@ def training_pairs(cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor
         stats["rays"] += int(nnt.numel())
         stats["kept"] += int(keep.sum())
         xs.append(hist[keep])
-        ys.append(torch.log2(gam[keep]))
+        ys.append(gam[keep])
         del dbr, outs, vol
     X, Y = torch.cat(xs), torch.cat(ys)
     if X.shape[0] > cfg.max_pairs:
@@ -105,27 +106,30 @@ def training_pairs(cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor
 
 
 def train(mlp: vdi.MLP, X: torch.Tensor, Y: torch.Tensor, epochs: int = 4, batch: int = 4096, lr: float = 2e-3,
-          seed: int = 0, log=None) -> List[float]:
-    """Adam on 0.5*mean squared error of log2(gamma); returns per-epoch mean loss."""
-    g = torch.Generator(device=X.device)
-    g.manual_seed(seed)
+          seed: int = 0, log=None, start_epoch: int = 0) -> List[float]:
+    """Adam on 0.5 * mean squared error of log2(gamma) (Y holds gamma*);
+    returns per-epoch mean loss.  Epoch e draws its batch order from seed + e
+    and halves the rate every two epochs, so training resumed at start_epoch
+    from a checkpoint taken after epoch start_epoch - 1 continues exactly."""
+    import numpy as np
     R = X.shape[0]
     hist = []
-    for ep in range(epochs):
+    for ep in range(start_epoch, epochs):
+        g = torch.Generator(device=X.device)
+        g.manual_seed(seed + ep)
         perm = torch.randperm(R, generator=g, device=X.device)
-        tot = torch.zeros((), dtype=torch.float64, device=X.device)
-        nb = 0
+        parts = []
         for b0 in range(0, R - batch + 1, batch):
             idx = perm[b0:b0 + batch]
             xb = X[idx].contiguous()
-            tb = Y[idx]
+            tb = Y[idx].contiguous()
             y, acts = vdi.mlp_forward(mlp, xb, want_acts=True)
-            d = y - tb
-            tot += 0.5 * (d.double() ** 2).mean()
-            grad = vdi.mlp_backward(mlp, xb, acts, d / batch)
+            dy, lp = vdi.mlp_mse(y, tb, 1.0 / batch)
+            parts.append(lp)
+            grad = vdi.mlp_backward(mlp, xb, acts, dy)
             vdi.mlp_adam(mlp, grad, lr=lr * (0.5 ** (ep // 2)))
-            nb += 1
-        hist.append(float(tot) / max(nb, 1))
+        loss = float(np.sum([p.cpu().numpy().sum() for p in parts])) / max(len(parts) * batch, 1)
+        hist.append(loss)
         if log:
             log(f"[learned] epoch {ep + 1}/{epochs}: loss {hist[-1]:.4f}")
     return hist
@@ -248,3 +252,41 @@ def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch
         "rgba_mae_vs_plain_render": mae_learned / frames,
         **({f"{k}_{novel_deg:g}deg_vs_dvr": v / q_frames for k, v in q_sums.items()} if q_frames else {}),
     }
+
+
+# ---------------------------------------------------------------- compositing
+
+def composite_training_pairs(seeds: Sequence[int], k: int = 16, n: int = 20, out_n: int = 20,
+                             width: int = 512, height: int = 256
+                             ) -> Tuple[torch.Tensor, torch.Tensor, Dict[str, int]]:
+    """(features, gamma*) pairs of the compositing bisection: for maximally
+    interleaved inputs of k lists of n supersegments per pixel (the dense
+    stress generator, seeded), the general merge's prediction features and
+    the plain bisection's threshold of every pixel it re-segmented."""
+    xs, ys = [], []
+    P = width * height
+    for seed in seeds:
+        c, d, cnt = synth.dense_interleaved_lists(k, n, P, seed=seed, device="cuda")
+        ins = [vdi.VDI(width, height, n, 0.01, vdi.REGULAR, c[r].contiguous(), d[r].contiguous(),
+                       cnt[r].contiguous()) for r in range(k)]
+        feat = torch.zeros((P, 64), dtype=torch.int16, device="cuda")
+        out = vdi.composite(ins, vdi.BISECT, 0.0, out_n, 10, features=feat)
+        keep = cnt.sum(dim=0) > out_n
+        xs.append(feat[keep])
+        ys.append(out.gamma[keep])
+        del ins, c, d, out
+    X, Y = torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
+    return X, Y, {"pairs": int(X.shape[0])}
+
+
+def evaluate_composite(mlp: vdi.MLP, ins: Sequence[vdi.VDI], out_n: int, reps: int = 5) -> Dict[str, float]:
+    """The composite of `ins` with the bisection's first scan steered by the
+    out_n-th-largest-distance rule (BISECT) and by the regressor (LEARNED):
+    median time of each and whether the outputs are identical (they must be)."""
+    a = vdi.composite(ins, vdi.BISECT, 0.0, out_n, 10)
+    b = vdi.composite(ins, vdi.LEARNED, 0.0, out_n, 10, mlp=mlp)
+    torch.cuda.synchronize()
+    same = all(torch.equal(getattr(a, f), getattr(b, f)) for f in ("color", "depth", "count", "gamma"))
+    t_p = timed(lambda: vdi.composite(ins, vdi.BISECT, 0.0, out_n, 10, out=a), reps)
+    t_l = timed(lambda: vdi.composite(ins, vdi.LEARNED, 0.0, out_n, 10, out=b, mlp=mlp), reps)
+    return {"bisect_ms": t_p, "learned_ms": t_l, "speedup": t_p / t_l, "identical": bool(same)}

@@ -59,7 +59,7 @@ class vdi_tf_t(ctypes.Structure):
 class vdi_tau_t(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tau", ctypes.c_float), ("iters", ctypes.c_int32),
                 ("gamma_max", ctypes.c_float), ("mlp", ctypes.c_void_p), ("fallback_tol", ctypes.c_float),
-                ("feature_scale", ctypes.c_float), ("y", ctypes.c_void_p)]
+                ("feature_scale", ctypes.c_float), ("y", ctypes.c_void_p), ("features", ctypes.c_void_p)]
 
 
 class vdi_shape_t(ctypes.Structure):
@@ -114,6 +114,10 @@ def lib():
                                    ctypes.c_float, ctypes.c_float, P]
         L.vdi_learned_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), P]
         L.vdi_debug_mfma.argtypes = [P, P, P, P, P]
+        L.vdi_mlp_mse.argtypes = [P, P, P, I, ctypes.c_float, P, P, P]
+        L.vdi_mlp_pack.argtypes = [P, ctypes.POINTER(vdi_mlp_t), P]
+        for name in ("vdi_mlp_mse", "vdi_mlp_pack"):
+            getattr(L, name).restype = ctypes.c_int
         L.vdi_workspace_size.argtypes = [P, ctypes.POINTER(vdi_shape_t), ctypes.POINTER(ctypes.c_size_t)]
         L.vdi_ctx_set_workspace.argtypes = [P, P, ctypes.c_size_t]
         L.vdi_ctx_reserve_workspace.argtypes = [P, ctypes.c_size_t]
@@ -241,7 +245,7 @@ def camera_c(cam) -> vdi_camera_t:
 
 def tau_c(mode: int, tau: float = 0.0, iters: int = 10, gamma_max: float = 2.0, mlp=None,
           fallback_tol: float = 0.1, feature_scale: float = 32.0, y=None) -> vdi_tau_t:
-    return vdi_tau_t(mode, tau, iters, gamma_max, mlp, fallback_tol, feature_scale, y)
+    return vdi_tau_t(mode, tau, iters, gamma_max, mlp, fallback_tol, feature_scale, y, None)
 
 
 @dataclasses.dataclass
@@ -314,16 +318,24 @@ def generate(bricks: Sequence[DeviceBrick], cam, tf: torch.Tensor, step: float, 
 
 
 def composite(vdis: Sequence[VDI], mode: int, tau: float = 0.0, max_n: int = 8, iters: int = 10,
-              out: Optional[VDI] = None, gamma_max: float = 2.0, noalloc: bool = False) -> VDI:
+              out: Optional[VDI] = None, gamma_max: float = 2.0, noalloc: bool = False,
+              mlp: Optional["MLP"] = None, features: Optional[torch.Tensor] = None) -> VDI:
     """vdi_composite: k-way merge + re-segmentation into one regular VDI
-    (noalloc: vdi_composite_noalloc, scratch in the library's fixed array)."""
+    (noalloc: vdi_composite_noalloc, scratch in the library's fixed array).
+    mode LEARNED needs `mlp` (the threshold predictor of the general merge;
+    same result as BISECT); features: optional int16 [H*W, 64] device tensor
+    receiving the prediction features (bf16 bits) of general-merge pixels."""
     k = len(vdis)
     v0 = vdis[0]
     if out is None:
         out = VDI.empty(v0.width, v0.height, max_n, v0.ref_step, REGULAR)
     ic = (vdi_t * k)(*[v.c() for v in vdis])
     oc = out.c()
-    tc = tau_c(mode, tau, iters, gamma_max)
+    mc = mlp.c() if mlp is not None else None
+    tc = tau_c(mode, tau, iters, gamma_max, ctypes.cast(ctypes.pointer(mc), ctypes.c_void_p) if mc else None)
+    if features is not None:
+        assert features.is_cuda and features.is_contiguous() and features.numel() == out.npix * 64
+        tc.features = features.data_ptr()
     fn = lib().vdi_composite_noalloc if noalloc else lib().vdi_composite
     _check(fn(context(), ic, k, ctypes.byref(tc), ctypes.byref(oc), _stream()))
     return out
@@ -378,10 +390,30 @@ class MLP:
     def __init__(self, w_f32: torch.Tensor):
         assert w_f32.shape == (MLP_PARAMS,) and w_f32.dtype == torch.float32 and w_f32.is_cuda
         self.w_f32 = w_f32.contiguous()
-        self.w_bf16 = self.w_f32.to(torch.bfloat16).view(torch.int16).contiguous()
+        self.w_bf16 = torch.empty((MLP_PARAMS,), dtype=torch.int16, device=w_f32.device)
         self.m = torch.zeros_like(self.w_f32)
         self.v = torch.zeros_like(self.w_f32)
         self.step = 0
+        mc = self.c()
+        _check(lib().vdi_mlp_pack(context(), ctypes.byref(mc), _stream()))
+
+    def save(self, path: str):
+        """Checkpoint: fp32 master parameters, Adam moments and step (safetensors)."""
+        from safetensors.torch import save_file
+        save_file({"w_f32": self.w_f32.cpu(), "m": self.m.cpu(), "v": self.v.cpu(),
+                   "step": torch.tensor([self.step], dtype=torch.int64)}, path)
+
+    @staticmethod
+    def load(path: str, device=None) -> "MLP":
+        """Resume from a checkpoint written by save()."""
+        from safetensors.torch import load_file
+        d = load_file(path)
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        mlp = MLP(d["w_f32"].to(dev))
+        mlp.m.copy_(d["m"].to(dev))
+        mlp.v.copy_(d["v"].to(dev))
+        mlp.step = int(d["step"][0])
+        return mlp
 
     def c(self) -> vdi_mlp_t:
         return vdi_mlp_t(_ptr(self.w_bf16), _ptr(self.w_f32))
@@ -450,6 +482,16 @@ def mlp_adam(mlp: MLP, grad: torch.Tensor, lr: float = 1e-3, beta1: float = 0.9,
     mc = mlp.c()
     _check(lib().vdi_mlp_adam(context(), ctypes.byref(mc), _ptr(grad), _ptr(mlp.m), _ptr(mlp.v), mlp.step, lr,
                               beta1, beta2, eps, _stream()))
+
+
+def mlp_mse(y: torch.Tensor, gamma: torch.Tensor, scale: float):
+    """vdi_mlp_mse: dy = scale * (y - log2 gamma) and the per-block loss sums
+    (fp64, 0.5 (y - log2 gamma)^2 over each 256 rows)."""
+    rows = y.numel()
+    dy = torch.empty_like(y)
+    parts = torch.empty(((rows + 255) // 256,), dtype=torch.float64, device=y.device)
+    _check(lib().vdi_mlp_mse(context(), _ptr(y), _ptr(gamma), rows, scale, _ptr(dy), _ptr(parts), _stream()))
+    return dy, parts
 
 
 def learned_stats():

@@ -243,3 +243,96 @@ def test_learned_gain_short_training(V):
     print("learned vs plain:", ev)
     assert ev["rgba_mae_vs_plain_render"] <= 1e-3
     assert ev["accepted"] > 0
+
+
+def test_mlp_mse_gradient_and_loss(V):
+    """The training step's loss kernel: dy = scale (y - log2 gamma) and the
+    per-256-row loss sums of 0.5 (y - log2 gamma)^2, against fp64 numpy."""
+    import torch
+    rng = np.random.default_rng(21)
+    rows = 1000
+    y = rng.normal(-4.0, 1.5, rows).astype(np.float32)
+    gam = np.exp2(rng.uniform(-9.0, 1.0, rows)).astype(np.float32)
+    dy, parts = V.mlp_mse(torch.from_numpy(y).cuda(), torch.from_numpy(gam).cuda(), 1.0 / 64)
+    d = y.astype(np.float64) - np.log2(gam.astype(np.float64))
+    np.testing.assert_allclose(dy.cpu().numpy(), d / 64, rtol=1e-6, atol=1e-7)
+    p = parts.cpu().numpy()
+    assert p.shape == ((rows + 255) // 256,)
+    want = [0.5 * (d[i:i + 256] ** 2).sum() for i in range(0, rows, 256)]
+    np.testing.assert_allclose(p, want, rtol=1e-5)
+
+
+def test_mlp_checkpoint_resume_equals_continuous(V, tmp_path):
+    """Training resumed from a checkpoint (fp32 weights, Adam moments, step)
+    after two epochs reaches the same parameters, bit for bit, as four epochs
+    in one run."""
+    import torch
+    from paper_2206_14503_amd import learned
+    rng = np.random.default_rng(3)
+    R = 8192
+    X = torch.from_numpy(rng.integers(0, 40, (R, 64)).astype(np.float32) / 32.0).cuda()
+    X = X.to(torch.bfloat16).view(torch.int16).contiguous()
+    Y = torch.from_numpy(np.exp2(rng.uniform(-8.0, 0.0, R)).astype(np.float32)).cuda()
+    a = learned.init_mlp(5)
+    la = learned.train(a, X, Y, epochs=4, batch=1024, lr=2e-3)
+    b = learned.init_mlp(5)
+    lb = learned.train(b, X, Y, epochs=2, batch=1024, lr=2e-3)
+    path = str(tmp_path / "mlp.safetensors")
+    b.save(path)
+    c = V.MLP.load(path)
+    lc = learned.train(c, X, Y, epochs=4, batch=1024, lr=2e-3, start_epoch=2)
+    torch.cuda.synchronize()
+    assert c.step == a.step == 4 * (R // 1024)
+    for name in ("w_f32", "m", "v", "w_bf16"):
+        assert torch.equal(getattr(a, name), getattr(c, name)), name
+    assert lb + lc == la
+
+
+def _interleaved_inputs(V, k, n, W, H, seed):
+    cc, dd, cnt = synth.dense_interleaved_lists(k, n, W * H, seed=seed, device="cuda")
+    ins = [V.VDI(W, H, n, 0.01, V.REGULAR, cc[r].contiguous(), dd[r].contiguous(), cnt[r].contiguous())
+           for r in range(k)]
+    return ins, cc.cpu().numpy(), dd.cpu().numpy(), cnt.cpu().numpy()
+
+
+def test_composite_features_match_oracle(V, OL):
+    """The compositing threshold-prediction features (64-bin histogram of
+    log2 consecutive-operand distances, over N) against the oracle's, up to
+    distances within 1e-4 of a bin boundary in log2 (the kernels take log2 in
+    fp32 with the hardware instruction)."""
+    import torch
+    k, n, W, H, N = 6, 8, 40, 30, 10
+    ins, c, d, m = _interleaved_inputs(V, k, n, W, H, 31)
+    feat = torch.full((W * H, 64), -1, dtype=torch.int16, device="cuda")
+    V.composite(ins, V.BISECT, 0.0, N, 10, features=feat)
+    torch.cuda.synchronize()
+    g = feat.view(torch.bfloat16).float().cpu().numpy().astype(np.float64)
+    f, have, near = OL.composite_features([c[r] for r in range(k)], [d[r] for r in range(k)],
+                                          [m[r] for r in range(k)], N)
+    assert have.all()
+    o = OL.bf16(f)
+    diff = np.abs(g - o).sum(axis=1) * N
+    assert np.all(diff <= 2 * near + 1e-6), (diff.max(), near[diff.argmax()])
+    assert np.array_equal(g[near == 0], o[near == 0])
+
+
+@pytest.mark.parametrize("seed", [0, 7])
+def test_learned_composite_equals_bisection(V, orc, seed):
+    """LEARNED compositing steers only the bisection's first scan: for any
+    regressor (here untrained weights) the composite equals BISECT's bit for
+    bit, and the oracle's."""
+    import torch
+    from paper_2206_14503_amd import learned
+    from oracle.parity import check_lists
+    k, n, W, H, N = 8, 10, 48, 40, 12
+    ins, c, d, m = _interleaved_inputs(V, k, n, W, H, 40 + seed)
+    mlp = learned.init_mlp(seed)
+    a = V.composite(ins, V.BISECT, 0.0, N, 10)
+    b = V.composite(ins, V.LEARNED, 0.0, N, 10, mlp=mlp)
+    torch.cuda.synchronize()
+    for name in ("color", "depth", "count", "gamma"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+    oref = orc.composite([c[r] for r in range(k)], [d[r] for r in range(k)], [m[r] for r in range(k)], 0.01,
+                         orc.BISECT, 0.0, N, 10)
+    check_lists((b.color.cpu().numpy(), b.depth.cpu().numpy(), b.count.cpu().numpy(), b.gamma.cpu().numpy()),
+                oref, "learned composite")

@@ -169,3 +169,28 @@ def test_choose_band_uses_cmax_target():
 
     out = L.choose(count_fn, np.float32([-3.0]), nnt=np.array([30]), cmax=np.array([5]), max_n=8)
     assert out["kind"][0] == L.KEPT and out["gamma"][0] == np.float32(2.0 ** -3.25)
+
+
+def test_composite_features_hand_example():
+    """Two interleaved lists of three elements, N = 2: merged by front the
+    per-step colours are 0, 0.5, 0.5, 1, 1, 1.5 (red only), so the five
+    consecutive distances are 0.5, 0, 0.5, 0, 0.5: three in the bin of
+    log2 0.5 = -1 (bin floor((-1 + 8) / (9 / 64)) = 49), two zeros in bin 0;
+    counts divided by N.  The second pixel (empty lists) has no features, nor
+    would a pixel whose merged list fits N."""
+    from oracle import learned as OL
+    c = [np.zeros((3, 2, 4), np.float32) for _ in range(2)]
+    d = [np.zeros((3, 2, 2), np.float32) for _ in range(2)]
+    for r in range(2):
+        for j in range(3):
+            c[r][j, 0] = [0.5 * (r + j), 0.0, 0.0, 1.0]
+            d[r][j, 0] = [2 * j + r, 2 * j + r + 0.5]
+    cnt = [np.array([3, 0]), np.array([3, 0])]
+    f, have, near = OL.composite_features(c, d, cnt, 2)
+    assert have.tolist() == [True, False]
+    want = np.zeros(64)
+    want[49], want[0] = 3 / 2, 2 / 2
+    np.testing.assert_array_equal(f[0], want)
+    assert near[0] == 0
+    f6, have6, _ = OL.composite_features(c, d, cnt, 6)
+    assert not have6.any()
