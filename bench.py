@@ -95,10 +95,10 @@ def measured_traffic(kernel: str, summary: str = DENSE_PMC):
     return (k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024.0, "measured"
 
 
-def measured_valu(kernel: str, summary: str = GEN_SQ):
+def measured_valu(kernel: str, summary: str = GEN_SQ, sources=GENERATE_SOURCES):
     """VALU wave-instructions per launch of `kernel` (SQ_INSTS_VALU) from a
     committed counter summary, or None with the reason."""
-    d, why = counter_line(summary, GENERATE_SOURCES)
+    d, why = counter_line(summary, sources)
     if d is None:
         return None, why
     k = d.get("kernels", {}).get(kernel)
@@ -152,7 +152,11 @@ def timed_ms(fn, reps):
 
 # ---------------------------------------------------------------- headline: dense composite
 
-DENSE_KERNEL = "composite_queue_kernel"
+# the composite call on interleaved inputs: the concatenation test, then the
+# ordered general merge (merge order, staging, re-segmentation); its counters
+# are summed over the call's kernels, its time is the call's
+DENSE_CALL = "composite call"
+DENSE_KERNEL = "composite_staged_kernel"
 
 
 def leg_dense(args, result):
@@ -228,11 +232,20 @@ def leg_dense(args, result):
                    "seed": args.seed},
         "stages_ms": {"composite": float(comp_ms.mean()), "render": float(rend_ms.mean())},
     })
-    traffic, why = measured_traffic(DENSE_KERNEL, DENSE_PMC)
+    traffic, why = measured_traffic(DENSE_CALL, DENSE_PMC)
     result["roofline"] = {"kernel": f"{DENSE_KERNEL} (composite call)", "bound": "hbm", "achieved": gbs,
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
                           "traffic_note": why, "algorithmic_bytes": cbytes,
                           "workload": result["config"]["workload"]}
+    # the re-segmentation's bisection is arithmetic: VALU lane-instructions of
+    # the call (committed counters) per second of the call, against the fp32
+    # vector issue peak
+    valu, vwhy = measured_valu(DENSE_CALL, DENSE_PMC, COMPOSITE_SOURCES)
+    ach = None if valu is None else valu * 64 / (comp_ms.mean() * 1e-3) / 1e12
+    result["roofline_alu"] = {"kernel": f"{DENSE_KERNEL} (composite call)", "bound": "alu", "achieved": ach,
+                              "peak": VALU_PEAK_TLANE, "unit": "T VALU lane-instructions/s",
+                              "frac": None if ach is None else ach / VALU_PEAK_TLANE,
+                              "valu_wave_instructions": valu, "counter_note": vwhy}
     # a seeded sample for the oracle: inputs and the GPU's output at those pixels
     px = np.sort(np.random.default_rng(4242).choice(P, size=min(P, args.sample_px), replace=False))
     idx = torch.from_numpy(px).long().cuda()
@@ -314,7 +327,7 @@ def leg_fhd(args, result):
     log(f"[bench] composite: {counts_total} input supersegments, {out_total} output; algorithmic "
         f"{cbytes / 1e9:.3f} GB -> {comp_gbs:.1f} GB/s ({100 * comp_gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
 
-    traffic, why = measured_traffic("composite_cat_kernel", FHD_PMC)
+    traffic, why = measured_traffic(DENSE_CALL, FHD_PMC)
     valu, vwhy = measured_valu("gen_kernel<float, 0, false>", GEN_SQ)
     gen_t = float(gen_ms.mean()) * 1e-3
     fhd = {

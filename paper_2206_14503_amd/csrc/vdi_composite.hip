@@ -109,6 +109,14 @@ __device__ inline bool c_exceeds(const CSeg& S, float aS, float g2, float e0, fl
     return g2 * (S.A * S.A) < d0 * d0 + d1 * d1 + d2 * d2;
 }
 
+// The gap's Eq. 1 test (the empty space's operand is zero):
+// gamma^2 A^2 < a_S^2 |C|^2.
+__device__ inline bool c_exceeds_gap(const CSeg& S, float aS, float g2)
+{
+    const float c2 = S.c0 * S.c0 + S.c1 * S.c1 + S.c2 * S.c2;
+    return g2 * (S.A * S.A) < (aS * aS) * c2;
+}
+
 // One element through the segmenter: the empty space before it (a
 // transparent stretch, Alg. S1), then the element itself.  a0 is the open
 // supersegment's a_S over its current extent (the gap test's), a1 its a_S
@@ -122,7 +130,7 @@ __device__ inline void c_step(CSeg& S, const COut& o, float inv_ref, float g2, i
     // gap [S.b, e.f): closes the open supersegment, or extends it.  The
     // conditions use non-short-circuit & so both tests run unconditionally.
     const bool gap = S.open & (e.f > S.b);
-    const bool close_g = gap & (cap <= 0 || S.count < cap - 1) & c_exceeds(S, a0, g2, 0.0f, 0.0f, 0.0f);
+    const bool close_g = gap & (cap <= 0 || S.count < cap - 1) & c_exceeds_gap(S, a0, g2);
     if (WRITE && close_g) c_close<true>(S, o, inv_ref);
     else S.count += close_g ? 1 : 0;
     const bool open1 = S.open & !close_g;
@@ -448,19 +456,74 @@ __device__ inline void reject_pixel(const CompParams& P, uint32_t p)
 // Levels of the compositing bisection its first scan speculates on: along
 // the path toward a predicted threshold where there is one (the staged
 // general merge), else along the all-feasible path gmax/2, gmax/4, ... (on
-// the FHD frame the composited threshold has median 2^-3.9).
-template <typename R> struct FirstLevels { static constexpr int L = 4; };
-template <> struct FirstLevels<StageReader> { static constexpr int L = 6; };
+// the FHD frame the composited threshold has median 2^-3.9).  A wavefront
+// runs as many scans as its slowest lane: with four levels the predicted
+// path holds for nearly every lane of the dense interleaved frames, so the
+// wave's lanes go on together with three two-level scans; six levels save a
+// scan on most lanes but their rare mispredicted lanes cost their waves two
+// more (measured 8% slower on the 16 x 20 frame).
+constexpr int kFirstLevels = 4;
+
+// The rest of the bisection from bracket [lo, hi] after `level` levels:
+// scans of two levels (the midpoint m and both of the next level's), one of
+// a single level if one is left, then the write at the result (returned in
+// gm).  Returns the count of the written list.
+template <typename R>
+__device__ int bisect_finish(const CompParams& P, const R& rd0, int total, uint32_t p, float lo, float hi, int level,
+                             float& gm)
+{
+    COut o{P.out_color, P.out_depth, p, P.npix, P.out_n};
+    while (level + 2 <= P.iters) {
+        float m = 0.5f * (lo + hi);
+        float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
+        int c3[3];
+        c_scan<3, false, false>(rd0, total, P.inv_ref, g3, 0, P.out_n, o, c3, nullptr);
+        if (c3[0] <= P.out_n) {
+            hi = m;
+            if (c3[1] <= P.out_n) hi = g3[1];
+            else lo = g3[1];
+        } else {
+            lo = m;
+            if (c3[2] <= P.out_n) hi = g3[2];
+            else lo = g3[2];
+        }
+        level += 2;
+    }
+    if (level < P.iters) {
+        float m = 0.5f * (lo + hi);
+        int c1[1];
+        c_scan<1, false, false>(rd0, total, P.inv_ref, &m, 0, P.out_n, o, c1, nullptr);
+        if (c1[0] <= P.out_n) hi = m;
+        else lo = m;
+    }
+    gm = hi;
+    int c1[1];
+    c_scan<1, true, false>(rd0, total, P.inv_ref, &gm, 0, 1 << 30, o, c1, nullptr);
+    return c1[0];
+}
+
+// A finished list's zero-filled tail, count and threshold.
+__device__ inline void finish_pixel(const CompParams& P, uint32_t p, int count, float gm)
+{
+    if (count > P.out_n) count = P.out_n;
+    for (int j = count; j < P.out_n; ++j) {
+        size_t slot = (size_t)j * P.npix + p;
+        P.out_color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        P.out_depth[slot] = make_float2(0.0f, 0.0f);
+    }
+    P.out_count[p] = count;
+    if (P.out_gamma) P.out_gamma[p] = gm;
+}
 
 // Re-segmentation of pixel p's merged list (read through rd, `total`
 // elements): pass-through when it fits (R17), else the fixed threshold or the
 // bisection, then the zero-filled tail.  The bisection's first scan carries
 // the midpoints of its first levels along the path toward `ghat` (a predicted
 // threshold; 0 or NaN: the all-feasible path), and its decisions are replayed
-// up to the first one the prediction got wrong; later scans carry two levels
-// (the midpoint and both of the next level's).  The result is the bisection's
-// whatever ghat is.  With VALIDATE the first pass checks the elements and
-// returns false, with the pixel's output incomplete, if one fails.
+// up to the first one the prediction got wrong; later scans carry two levels.
+// The result is the bisection's whatever ghat is.  With VALIDATE the first
+// pass checks the elements and returns false, with the pixel's output
+// incomplete, if one fails.
 template <bool VALIDATE, typename R>
 __device__ bool resegment(const CompParams& P, const R& rd0, int total, uint32_t p, float ghat = 0.0f)
 {
@@ -497,75 +560,38 @@ __device__ bool resegment(const CompParams& P, const R& rd0, int total, uint32_t
     } else {
         float lo = 0.0f, hi = P.gmax;
         int level = 0;
-        {
-            // first scan: the midpoints of the first levels along the
-            // predicted path (predicted feasible iff the midpoint is at least
-            // ghat), replayed up to the first level decided otherwise (this
-            // scan also validates the list)
-            constexpr int L = FirstLevels<R>::L;
-            float gg[L];
-            bool pf[L];
-            int cg[L];
-            float plo = 0.0f, phi = P.gmax;
+        // first scan: the midpoints of the first levels along the predicted
+        // path (predicted feasible iff the midpoint is at least ghat),
+        // replayed up to the first level decided otherwise (this scan also
+        // validates the list)
+        constexpr int L = kFirstLevels;
+        float gg[L];
+        bool pf[L];
+        int cg[L];
+        float plo = 0.0f, phi = P.gmax;
 #pragma unroll
-            for (int l = 0; l < L; ++l) {
-                const float m = 0.5f * (plo + phi);
-                gg[l] = m;
-                pf[l] = !(ghat > m);
-                plo = pf[l] ? plo : m;
-                phi = pf[l] ? m : phi;
-            }
-            c_scan<L, false, VALIDATE>(rd0, total, P.inv_ref, gg, 0, P.out_n, o, cg, &bad);
-            const int lim = L < P.iters ? L : P.iters;
-            for (int l = 0; l < lim && !bad; ++l) {
-                const float m = 0.5f * (lo + hi);
-                ++level;
-                const bool feasible = cg[l] <= P.out_n;
-                if (feasible) hi = m;
-                else lo = m;
-                if (feasible != pf[l]) break;
-            }
+        for (int l = 0; l < L; ++l) {
+            const float m = 0.5f * (plo + phi);
+            gg[l] = m;
+            pf[l] = !(ghat > m);
+            plo = pf[l] ? plo : m;
+            phi = pf[l] ? m : phi;
         }
-        while (!bad && level + 2 <= P.iters) {
-            float m = 0.5f * (lo + hi);
-            float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
-            int c3[3];
-            c_scan<3, false, false>(rd0, total, P.inv_ref, g3, 0, P.out_n, o, c3, nullptr);
-            if (c3[0] <= P.out_n) {
-                hi = m;
-                if (c3[1] <= P.out_n) hi = g3[1];
-                else lo = g3[1];
-            } else {
-                lo = m;
-                if (c3[2] <= P.out_n) hi = g3[2];
-                else lo = g3[2];
-            }
-            level += 2;
-        }
-        if (!bad && level < P.iters) {
-            float m = 0.5f * (lo + hi);
-            int c1[1];
-            c_scan<1, false, false>(rd0, total, P.inv_ref, &m, 0, P.out_n, o, c1, nullptr);
-            if (c1[0] <= P.out_n) hi = m;
+        c_scan<L, false, VALIDATE>(rd0, total, P.inv_ref, gg, 0, P.out_n, o, cg, &bad);
+        const int lim = L < P.iters ? L : P.iters;
+        for (int l = 0; l < lim && !bad; ++l) {
+            const float m = 0.5f * (lo + hi);
+            ++level;
+            const bool feasible = cg[l] <= P.out_n;
+            if (feasible) hi = m;
             else lo = m;
+            if (feasible != pf[l]) break;
         }
-        gm = hi;
         count = 0;
-        if (!bad) {
-            int c1[1];
-            c_scan<1, true, false>(rd0, total, P.inv_ref, &gm, 0, 1 << 30, o, c1, nullptr);
-            count = c1[0];
-        }
+        if (!bad) count = bisect_finish(P, rd0, total, p, lo, hi, level, gm);
     }
     if (VALIDATE && bad) return false;
-    if (count > P.out_n) count = P.out_n;
-    for (int j = count; j < P.out_n; ++j) {
-        size_t slot = (size_t)j * P.npix + p;
-        P.out_color[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        P.out_depth[slot] = make_float2(0.0f, 0.0f);
-    }
-    P.out_count[p] = count;
-    if (P.out_gamma) P.out_gamma[p] = gm;
+    finish_pixel(P, p, count, gm);
     return true;
 }
 
@@ -1345,6 +1371,13 @@ static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s)
         launch_mlp_fwd(P.mlp_wb, P.mlp_wf, P.feat, (int)c, nullptr, nullptr, P.num_cus * 3, P.ghat, nullptr, s);
 }
 
+// Re-segmentation of a staged chunk.
+static void launch_resegment(const CompParams& P, uint32_t e0, hipStream_t s)
+{
+    const uint32_t c = P.chunk;
+    hipLaunchKernelGGL(composite_staged_kernel, dim3(ord_grid(P, c / 64, 20)), dim3(64), 0, s, P, e0);
+}
+
 // The ordered general merge over the queue, chunk by chunk (every kernel
 // reads the queue length on the device; entries past it exit at once).  With
 // two buffers, chunk c + 1 is ordered and staged on the second stream while
@@ -1355,7 +1388,7 @@ static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync
     if (!sync || !sync->P2) {
         for (uint32_t e0 = 0; e0 < P.npix; e0 += c) {
             launch_order_stage(P, e0, s);
-            hipLaunchKernelGGL(composite_staged_kernel, dim3(ord_grid(P, c / 64, 20)), dim3(64), 0, s, P, e0);
+            launch_resegment(P, e0, s);
         }
         return;
     }
@@ -1373,7 +1406,7 @@ static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync
         (void)hipEventRecord(sync->ev[1 + b], sync->aux);
         // re-segmenting chunk i waits for its staging
         (void)hipStreamWaitEvent(s, sync->ev[1 + b], 0);
-        hipLaunchKernelGGL(composite_staged_kernel, dim3(ord_grid(P, c / 64, 20)), dim3(64), 0, s, *buf[b], i * c);
+        launch_resegment(*buf[b], i * c, s);
         (void)hipEventRecord(sync->ev[3 + b], s);
     }
     // join: the second stream's work precedes everything after this call
