@@ -87,9 +87,14 @@ def _with_alts(call, rays: int, max_n: int):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-            build()
-        L = ctypes.CDLL(_LIB_PATH)
+        # VDI_ORACLE_LIBRARY: another build of the same source (the
+        # sanitizer test loads an AddressSanitizer/UBSan build this way)
+        path = os.environ.get("VDI_ORACLE_LIBRARY")
+        if not path:
+            path = _LIB_PATH
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+                build()
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i32, f32, f64 = ctypes.c_int32, ctypes.c_float, ctypes.c_double
         L.orc_generate.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_int, ctypes.POINTER(Camera), P, ctypes.c_int,

@@ -83,12 +83,15 @@ _lib = None
 
 
 def lib():
-    """Load libvdi.so (raises if it has not been built)."""
+    """Load libvdi.so (raises if it has not been built).  VDI_LIBRARY names
+    another build of the same sources (the sanitizer test loads a build
+    with host-side AddressSanitizer/UBSan this way)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2206_14503_amd.build`")
-        L = ctypes.CDLL(LIB_PATH)
+        path = os.environ.get("VDI_LIBRARY") or LIB_PATH
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with `python -m paper_2206_14503_amd.build`")
+        L = ctypes.CDLL(path)
         P, I = ctypes.c_void_p, ctypes.c_int
         L.vdi_last_error.restype = ctypes.c_char_p
         L.vdi_ctx_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), I]
