@@ -146,31 +146,26 @@ typedef struct {
  *           sampling pass, as Sec. 2.4 describes the search; results are
  *           identical to BISECT.  Kept as the baseline search the learned
  *           threshold is measured against.
- *  LEARNED: (an extension beyond the paper) per list, y = output of the MLP
- *           `mlp` (a vdi_mlp_t*) on the list's 64-bin opacity histogram (see
- *           vdi_tau_features), or y from the caller's array `y`.  A count c is
- *           in band if m - floor(fallback_tol*m) <= c <= N with m = min(N,
- *           cmax) (cmax: the count at the smallest bisection threshold).
- *           Round one counts gamma = 2^y_d, y_d = clamp(y + d) to
- *           [log2(gamma_max) - iters, log2(gamma_max)], d in {0, -1/4, 1/4,
- *           -1/2, 1/2}, in one scan and keeps the in-band candidate with the
- *           largest count (ties: first listed).  Without one, if candidates
- *           adjacent in threshold order straddle the band (count > N at the
- *           smaller y_a, < the band at the larger y_b; the pair with the
- *           smallest |d_a + d_b|, ties: smaller), round two counts
- *           2^(y_a + (y_b - y_a) t/6), t = 1..5, and keeps its in-band
- *           candidate with the largest count (ties: smaller t).  A list kept
- *           by neither round is regenerated by BISECT.  Lists with at most N
- *           non-transparent samples take the bisection's result directly
- *           (every threshold is feasible there).  Regular layout only, at
- *           most 16 bricks per call (else VDI_E_UNSUPPORTED). */
+ *  LEARNED: (an extension beyond the paper) the bisection of BISECT, its
+ *           later scans steered by a regressed threshold; the result is
+ *           BISECT's whatever the regressor says.  Per list, y = output of the
+ *           MLP `mlp` (a vdi_mlp_t*) on the list's 64-bin opacity histogram
+ *           (see vdi_tau_features), or y from the caller's array `y`.  The
+ *           feature pass is also the bisection's first scan (states at
+ *           gamma_max/2 ... gamma_max/64, as BISECT's); the next scan carries
+ *           the midpoints of up to five further levels along the path toward
+ *           2^y, its decisions are replayed up to the first one that differs
+ *           from the path, and any levels left run as in BISECT.  Lists with
+ *           at most N non-transparent samples take the bisection's result
+ *           directly (every threshold is feasible there).  Regular layout
+ *           only, at most 16 bricks per call (else VDI_E_UNSUPPORTED). */
 typedef struct {
     int32_t mode;            /* vdi_tau_mode */
     float tau;
     int32_t iters;           /* B, 1..24 */
     float gamma_max;         /* > sqrt(3), normally 2 */
     const void *mlp;         /* LEARNED: const vdi_mlp_t* */
-    float fallback_tol;      /* LEARNED: 0.1 */
+    float fallback_tol;      /* unused (kept for the layout) */
     float feature_scale;     /* LEARNED: histogram counts are divided by this (s_ref) */
     const float *y;          /* LEARNED: optional device array [k][H*W] of log2 thresholds
                                 used instead of the MLP's output (NULL: run the MLP) */
@@ -358,9 +353,10 @@ vdi_status vdi_mlp_mse(vdi_ctx *ctx, const float *y, const float *gamma, int row
 vdi_status vdi_mlp_pack(vdi_ctx *ctx, vdi_mlp_t *mlp, void *stream);
 
 /* Counts of the learned path since the last call (synchronises `stream`):
- * stats[0] lists kept in round one, [1] lists taking the all-feasible
- * shortcut, [2] fallbacks to bisection, [3] empty lists, [4] lists kept in
- * round two.  stats holds 5 entries.  Clears them. */
+ * stats[0] lists whose steered scan settled every remaining level, [1] lists
+ * taking the all-feasible shortcut, [2] always 0, [3] empty lists, [4] lists
+ * that needed further scans after the steered one.  stats holds 5 entries.
+ * Clears them. */
 vdi_status vdi_learned_stats(vdi_ctx *ctx, int64_t *stats, void *stream);
 
 /* Diagnostic: D = A B for 16x16 bf16 A, B (row-major) through one matrix-core

@@ -1,5 +1,7 @@
 """Oracle for the learned threshold (an extension beyond the paper: a small
-MLP replaces the per-ray bisection of Sec. 2.4).
+MLP predicts the threshold the per-ray bisection of Sec. 2.4 finds, and the
+prediction steers the order of the bisection's scans; the result stays the
+bisection's, so the generation's expected output is the oracle's BISECT).
 
 TEST INFRASTRUCTURE (see oracle/__init__.py).
 
@@ -119,104 +121,6 @@ def adam(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         vh = v[k] / (1 - b2 ** step)
         out[k] = (params[k].astype(np.float64) - lr * mh / (np.sqrt(vh) + eps)).astype(np.float32)
     return out
-
-
-KEPT, SHORTCUT, FALLBACK, EMPTY, REFINED = 0, 1, 2, 3, 4
-ROUND1 = (0.0, -0.25, 0.25, -0.5, 0.5)
-
-
-def _pick_in_band(counts, max_n, lo):
-    """Index of the largest in-band count per ray (ties: first listed), -1 if none."""
-    best = np.full(counts.shape[1], -1)
-    bestc = np.full(counts.shape[1], -1)
-    for j in range(counts.shape[0]):
-        ok = (counts[j] <= max_n) & (counts[j] >= lo) & (counts[j] > bestc)
-        best[ok] = j
-        bestc[ok] = counts[j][ok]
-    return best
-
-
-def choose(count_fn, y, nnt, cmax, max_n: int, iters: int = 10, gmax: float = 2.0, tol: float = 0.1,
-           nonempty=None):
-    """The learned path's decision for every brick-ray: outcome, threshold and
-    the smallest |distance - gamma| over the counting runs that decided it.
-
-    count_fn(gamma [R] float32) -> (count [R], margin [R]) counts at per-ray
-    thresholds.  y: float32 log2 thresholds.  Round one tries y + d for the
-    offsets in ROUND1, clamped to [log2(gmax) - iters, log2(gmax)], and keeps
-    the in-band candidate with the largest count; round two tries five evenly
-    spaced thresholds strictly inside the nearest pair of adjacent round-one
-    candidates that straddles the band.  Thresholds are 2^y rounded to fp32.
-    """
-    y = np.asarray(y, np.float32).ravel()
-    nnt = np.asarray(nnt).ravel()
-    cmax = np.asarray(cmax).ravel()
-    R = y.size
-    ne = np.ones(R, bool) if nonempty is None else np.asarray(nonempty, bool).ravel()
-    kind = np.full(R, FALLBACK)
-    kind[~ne | (nnt == 0)] = EMPTY
-    short = ne & (nnt > 0) & (nnt <= max_n)
-    kind[short] = SHORTCUT
-    gamma = np.full(R, np.float32(gmax * 2.0 ** -iters), np.float32)
-    margin = np.full(R, np.inf)
-    served = ne & (nnt > max_n)
-    lo = np.minimum(max_n, cmax)
-    lo = lo - np.floor(tol * lo + 1e-6).astype(lo.dtype)
-    lg_hi = np.float32(math.log2(gmax))
-    lg_lo = np.float32(lg_hi - np.float32(iters))
-    y5 = np.stack([np.minimum(np.maximum(y + np.float32(d), lg_lo), lg_hi) for d in ROUND1])
-    g5 = np.exp2(y5.astype(np.float64)).astype(np.float32)
-    c5 = np.zeros((5, R), np.int64)
-    for j in range(5):
-        c, m = count_fn(g5[j])
-        c5[j] = c
-        margin = np.where(served, np.minimum(margin, m), margin)
-    best = _pick_in_band(c5, max_n, lo)
-    keep1 = served & (best >= 0)
-    kind[keep1] = KEPT
-    gamma[keep1] = g5[best[keep1], np.nonzero(keep1)[0]]
-    # round two: adjacent pairs in threshold order straddling the band
-    order = (3, 1, 0, 2, 4)
-    need = served & ~keep1
-    ya = np.zeros(R, np.float32)
-    yb = np.zeros(R, np.float32)
-    picked = np.zeros(R, bool)
-    pick_d = np.full(R, np.inf)
-    for t in range(4):
-        a, b = order[t], order[t + 1]
-        d = abs(ROUND1[a] + ROUND1[b])
-        ok = need & (c5[a] > max_n) & (c5[b] < lo) & (d < pick_d)
-        ya[ok], yb[ok] = y5[a][ok], y5[b][ok]
-        pick_d[ok] = d
-        picked |= ok
-    sixth = np.float32(1.0) / np.float32(6.0)
-    c2 = np.zeros((5, R), np.int64)
-    g2 = np.zeros((5, R), np.float32)
-    if picked.any():
-        for t in range(5):
-            yt = ya + (yb - ya) * np.float32(t + 1) * sixth
-            g2[t] = np.exp2(yt.astype(np.float64)).astype(np.float32)
-            c, m = count_fn(np.where(picked, g2[t], np.float32(gmax)))
-            c2[t] = c
-            margin = np.where(picked, np.minimum(margin, m), margin)
-    best2 = _pick_in_band(c2, max_n, lo)
-    keep2 = picked & (best2 >= 0)
-    kind[keep2] = REFINED
-    gamma[keep2] = g2[best2[keep2], np.nonzero(keep2)[0]]
-    return {"kind": kind, "gamma": gamma, "margin": margin}
-
-
-def predict_gamma(y, iters: int = 10, gmax: float = 2.0):
-    """gamma = 2^clamp(y, log2(gmax)-iters, log2(gmax))."""
-    lo, hi = math.log2(gmax) - iters, math.log2(gmax)
-    return np.exp2(np.clip(np.asarray(y, np.float64), lo, hi))
-
-
-def accept(count, cmax, max_n: int, tol: float = 0.1):
-    """A learned threshold is kept iff m - floor(tol*m) <= count <= N with m = min(N, cmax)."""
-    m = np.minimum(max_n, cmax)
-    lo = m - np.floor(tol * m + 1e-6)
-    return (count <= max_n) & (count >= lo)
 
 
 def features(vol, bricks, cam, tf, step: float, ref: float, iters: int = 10, gmax: float = 2.0,

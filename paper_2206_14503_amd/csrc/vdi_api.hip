@@ -301,7 +301,10 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
     Lb.nnt = (int*)(base + Ls.nnt);
     Lb.cmax = (int*)(base + Ls.cmax);
     Lb.y = (const float*)(base + Ls.y);
-    Lb.rf_y = (float2*)(base + Ls.ry);
+    // the generation path keeps each served ray's first-scan bracket and
+    // levels (the count at the smallest threshold is for the features only)
+    Lb.bracket = (float2*)(base + Ls.ry);
+    Lb.level = (int*)(base + Ls.cmax);
     Lb.span = (int2*)(base + Ls.span);
     Lb.hist_list = (int*)(base + Ls.hlist);
     Lb.hist_count = (int*)(base + Ls.hcnt);
@@ -312,7 +315,6 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
     Lb.nblk = (int)nblk;
     Lb.stats = ctx->status + 4;
     Lb.s_ref = tau->feature_scale;
-    Lb.tol = tau->fallback_tol;
     Lb.blocks_per_brick = std::max(1, ctx->num_cus * 8 / k);
     const vdi_mlp_t* mlp = (const vdi_mlp_t*)tau->mlp;
     if (tau->y) Lb.y = tau->y;
@@ -341,10 +343,8 @@ static vdi_status generate_learned(vdi_ctx* ctx, const vdi_brick_t* bricks, int 
             if ((st = launched()) != VDI_OK) return st;
         }
     }
-    if ((st = phase(1)) != VDI_OK) return st;   // round one
-    if ((st = phase(4)) != VDI_OK) return st;   // all-feasible lists
-    if ((st = order(Q_TAIL)) != VDI_OK) return st;
-    return phase(2);                            // round two and the plain bisection
+    if ((st = phase(1)) != VDI_OK) return st;   // the steered rest of the bisection, and the write
+    return phase(4);                            // all-feasible lists
 }
 
 // Checks the arguments of a composite and fills its parameter block (all
@@ -576,8 +576,6 @@ vdi_status vdi_generate(vdi_ctx* ctx, const vdi_brick_t* bricks, int k, const vd
         if (!(tau->feature_scale > 0.0f)) return fail(VDI_E_INVALID, "learned mode needs feature_scale > 0");
         if (!(1.7320508f / step < 65535.0f))
             return fail(VDI_E_UNSUPPORTED, "step too small for the learned path (histogram bins count to 65535)");
-        if (!(tau->fallback_tol >= 0.0f && tau->fallback_tol < 1.0f))
-            return fail(VDI_E_INVALID, "fallback_tol must be in [0, 1)");
     }
     const int dtype = bricks[0].dtype;
     if (dtype != VDI_F32 && dtype != VDI_F16) return fail(VDI_E_INVALID, "brick dtype %d", dtype);

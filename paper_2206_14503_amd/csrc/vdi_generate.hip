@@ -268,6 +268,54 @@ __device__ void gen_scan(const VT* data, const BrickGeo& g, const Ray& r, float 
 // Levels of the bisection the first scan speculates on.
 constexpr int kGeoLevels = 6;
 
+// The bisection's levels after `level` from bracket [lo, hi]: two per scan
+// (the midpoint m and both of the next level's), the last alone if one is
+// left.  hi_count receives the count at the final hi where a scan measured it.
+template <typename VT, bool MASK = false>
+__device__ __forceinline__ void search_rest(const VT* data, const BrickGeo& g, const Ray& r, float step, float l_step,
+                                            int k0, int k1, const TfCell* tf, int entries, const GenParams& P,
+                                            float& lo, float& hi, int level, int& hi_count)
+{
+    while (level < P.iters) {
+        float m = 0.5f * (lo + hi);
+        if (level + 2 <= P.iters) {
+            float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
+            int c3[3];
+            gen_scan<VT, 3, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, g3, P.max_n, c3, nullptr);
+            if (c3[0] <= P.max_n) {
+                hi = m;
+                hi_count = c3[0];
+                if (c3[1] <= P.max_n) {
+                    hi = g3[1];
+                    hi_count = c3[1];
+                } else {
+                    lo = g3[1];
+                }
+            } else {
+                lo = m;
+                if (c3[2] <= P.max_n) {
+                    hi = g3[2];
+                    hi_count = c3[2];
+                } else {
+                    lo = g3[2];
+                }
+            }
+            level += 2;
+        } else {
+            int c1[1];
+            gen_scan<VT, 1, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, &m, P.max_n, c1, nullptr);
+            if (c1[0] <= P.max_n) {
+                hi = m;
+                hi_count = c1[0];
+            } else {
+                lo = m;
+            }
+            level += 1;
+        }
+    }
+}
+
+
 // Threshold for one brick-ray and the count it yields.  While every level is
 // feasible, the bisection's midpoints are gmax/2, gmax/4, ...: the first scan
 // carries states at the first kGeoLevels of them and replays the decisions up
@@ -343,43 +391,7 @@ __device__ __forceinline__ void gen_search(const VT* data, const BrickGeo& g, co
             }
         }
     }
-    while (level < P.iters) {
-        float m = 0.5f * (lo + hi);
-        if (level + 2 <= P.iters) {
-            float g3[3] = { m, 0.5f * (lo + m), 0.5f * (m + hi) };
-            int c3[3];
-            gen_scan<VT, 3, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, g3, P.max_n, c3, nullptr);
-            if (c3[0] <= P.max_n) {
-                hi = m;
-                hi_count = c3[0];
-                if (c3[1] <= P.max_n) {
-                    hi = g3[1];
-                    hi_count = c3[1];
-                } else {
-                    lo = g3[1];
-                }
-            } else {
-                lo = m;
-                if (c3[2] <= P.max_n) {
-                    hi = g3[2];
-                    hi_count = c3[2];
-                } else {
-                    lo = g3[2];
-                }
-            }
-            level += 2;
-        } else {
-            int c1[1];
-            gen_scan<VT, 1, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, &m, P.max_n, c1, nullptr);
-            if (c1[0] <= P.max_n) {
-                hi = m;
-                hi_count = c1[0];
-            } else {
-                lo = m;
-            }
-            level += 1;
-        }
-    }
+    search_rest<VT, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, P, lo, hi, level, hi_count);
     gamma_out = hi;
     if (need_count && hi_count < 0)
         hi_count = gen_pass<VT, false, true, MASK>(data, g, r, step, l_step, k0, k1, tf, entries, hi, 0, 1 << 30, none,
@@ -508,30 +520,13 @@ void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B
 
 // ---------------------------------------------------------------- learned threshold
 //
-// The regressor of the learned path needs per brick-ray features: a 64-bin
+// The regressor of the learned path reads per brick-ray features: a 64-bin
 // histogram of the sample opacities (bin j: a in (j/64, (j+1)/64], the opacity
 // from the transfer function in the same fixed-order fp32 as the oracle, so
-// bins agree exactly), the number of non-transparent samples and the count at
-// the smallest threshold the bisection can return (saturating at N+1).
-
-// In-band test of the learned path: with m = min(N, cmax), a count c is kept
-// iff m - floor(tol * m) <= c <= N.
-__device__ inline int band_lo(int max_n, int cmax, float tol)
-{
-    const int m = min(max_n, cmax);
-    return m - (int)floorf(tol * (float)m + 1e-6f);
-}
-
-// Largest in-band count among NC candidates (ties: the first listed); -1 if none.
-template <int NC>
-__device__ inline int pick_in_band(const int* c, int max_n, int lo)
-{
-    int best = -1;
-#pragma unroll
-    for (int j = 0; j < NC; ++j)
-        if (c[j] <= max_n && c[j] >= lo && (best < 0 || c[j] > c[best])) best = j;
-    return best;
-}
+// bins agree exactly).  On the generation path the feature pass is also the
+// bisection's first scan (the states at gmax/2 ... gmax/2^6 of the all-feasible
+// path): the regressed threshold then steers the scans that settle the
+// remaining levels, and every ray ends with the bisection's own result.
 
 // Writes a finished list's unused slots, count and threshold.
 __device__ inline void finish_list(const GenBrick& br, uint32_t pix, uint32_t npix, int max_n, int c, float gm)
@@ -597,15 +592,13 @@ __device__ inline ListSpan list_span(const LearnBufs& Lb, int q, int brick, int 
     return s;
 }
 
-// Puts pixel (x, y) of brick `brick` on list q (one atomic per ray).
-__device__ inline void put_on_list(const LearnBufs& Lb, int q, int brick, int nb_total, int x, int y, int gx)
-{
-    const uint32_t slot = slot_of(x, y, gx);
-    Lb.kind[(size_t)brick * ((size_t)Lb.nblk << 8) + slot] = (uint8_t)(1 + q);
-    atomicAdd(&Lb.qcnt[(size_t)q * nb_total * Lb.nblk + (size_t)brick * Lb.nblk + (slot >> 8)], 1);
-}
-
-template <typename VT>
+// Feature pass.  SEARCH (generation): the sampling scan also carries the
+// bisection's first scan (kGeoLevels states on the all-feasible path, as the
+// plain search's) and keeps the bracket its decisions leave; empty lists are
+// finished here, lists with at most N non-transparent samples go on the
+// all-feasible list, the others on the regressor's list.  Without SEARCH
+// (features only): the count at the smallest threshold instead.
+template <typename VT, bool SEARCH>
 __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
     extern __shared__ TfCell tf_s[];   // P.tf_entries - 1 cells, sized at launch
@@ -638,14 +631,23 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
     if (ns > 0) owned_run(r, P.step, ns, P.n, br.lo, br.hi, k0, k1);
 
     const float gmin = ldexpf(P.gmax, -P.iters);
-    const float g2 = gmin * gmin;
     const bool unit = (P.l_step == 1.0f);
     GenOut none{nullptr, nullptr, 0, 0, 0};
-    GenSeg S;
-    gen_seg_init(S);
-    int count = 0, m = 0;
+    constexpr int NS = SEARCH ? kGeoLevels : 1;
+    GenSeg S[NS];
+    int cnt[NS];
+    float g2[NS];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+        gen_seg_init(S[c]);
+        cnt[c] = 0;
+        const float gc = SEARCH ? ldexpf(P.gmax, -(c + 1)) : gmin;
+        g2[c] = gc * gc;
+    }
+    int m = 0;
     int kf = k1, ke = k0;
-    for_samples<VT>(data, g, r, P.step, k0, k1, [&](int k, float v) {
+    bool live = true;   // SEARCH: some state's count is still at most N
+    for_samples<VT, (SEARCH ? 2 : 3)>(data, g, r, P.step, k0, k1, [&](int k, float v) {
         const float4 cs = tf_lookup(tf_s, P.tf_entries, v);
         const float a32 = cs.w;   // the transfer function's opacity, as in the histogram's definition
         kf = a32 > 0.0f ? min(kf, k) : kf;
@@ -656,23 +658,37 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
             hs[j >> 1][threadIdx.x] += (j & 1) ? 0x10000u : 1u;
             ++m;
         }
-        if (count <= P.max_n) {
+        if (SEARCH) {
+            // every state steps while one is live (a frozen one's count only
+            // grows, its decision stays made); once all are frozen, where the
+            // plain search's scan ends, only the histogram goes on
+            if (live) {
+                const GenSample q = gen_prep(cs, P.l_step, unit);
+                live = false;
+#pragma unroll
+                for (int c = 0; c < NS; ++c) {
+                    gen_step<false>(S[c], cnt[c], none, r, P.step, P.l_step, g2[c], 0, k, q);
+                    live |= cnt[c] <= P.max_n;
+                }
+            }
+        } else if (cnt[0] <= P.max_n) {
             const GenSample q = gen_prep(cs, P.l_step, unit);
-            gen_step<false>(S, count, none, r, P.step, P.l_step, g2, 0, k, q);
+            gen_step<false>(S[0], cnt[0], none, r, P.step, P.l_step, g2[0], 0, k, q);
         }
         return true;
     });
-    if (S.open && count <= P.max_n) gen_close<false>(S, count, none, r, P.step, P.l_step);
+#pragma unroll
+    for (int c = 0; c < NS; ++c)
+        if (S[c].open && cnt[c] <= P.max_n) gen_close<false>(S[c], cnt[c], none, r, P.step, P.l_step);
     Lb.nnt[ray] = m;
-    Lb.cmax[ray] = count;
+    if (!SEARCH) Lb.cmax[ray] = cnt[0];
     size_t row = ray;
-    if (Lb.hist_list) {
-        // generation: an empty list is finished here; lists with at most N
-        // non-transparent samples (every threshold feasible) go on the list of
-        // writes at the smallest threshold, the others on the regressor's list
-        // (both counted per 256-slot block); the served rays' histogram rows are
-        // compacted per brick in order of arrival (the regressor's order does
-        // not matter)
+    if (SEARCH) {
+        // empty lists are finished here; lists with at most N non-transparent
+        // samples (every threshold feasible) go on the list of writes at the
+        // smallest threshold, the others on the regressor's list with the
+        // first scan's bracket (both counted per 256-slot block); the served
+        // rays' histogram rows are compacted per brick in order of arrival
         const uint32_t pix = (uint32_t)(ray - (size_t)brick * npix);
         const bool empty = k1 <= k0 || m == 0;
         const bool served = !empty && m > P.max_n;
@@ -686,6 +702,21 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
         if (empty) finish_list(br, pix, npix, P.max_n, 0, gmin);
         else Lb.span[ray] = make_int2(kf, ke);
         if (!served) return;
+        // the first scan's decisions, up to and including the first infeasible level
+        float lo = 0.0f, hi = P.gmax;
+        int level = 0;
+        const int lim = kGeoLevels < P.iters ? kGeoLevels : P.iters;
+#pragma unroll
+        for (int l = 0; l < NS; ++l) {
+            if (l < lim && (l == 0 || lo == 0.0f)) {
+                const float mid = 0.5f * (lo + hi);
+                ++level;
+                if (cnt[l] <= P.max_n) hi = mid;
+                else lo = mid;
+            }
+        }
+        Lb.level[ray] = level;
+        Lb.bracket[ray] = make_float2(lo, hi);
         Lb.hist_list[(size_t)brick * npix + pos] = (int)pix;
         row = (size_t)brick * npix + (size_t)pos;
     }
@@ -698,14 +729,15 @@ __global__ __launch_bounds__(256) void features_kernel(GenParams P, GenBricks B,
     }
 }
 
-// Round one of the learned threshold.  The regressed log2 threshold y and four
-// neighbours, y + {0, -1/4, 1/4, -1/2, 1/2} (clamped to the bisection's range),
-// share one sampling scan; the in-band candidate with the largest count is
-// kept.  Otherwise, if two candidates adjacent in threshold order straddle
-// the band (count above N at the smaller, below the band at the larger), the
-// ray goes on the list for round two inside that bracket (the straddling pair
-// nearest the regressed value; ties: the smaller thresholds); else it is
-// put on the list for the plain bisection.
+// Levels of the bisection the regressed threshold's scan speculates on.
+constexpr int kPredLevels = 5;
+
+// The rest of a served ray's bisection.  From the first scan's bracket, one
+// scan carries the midpoints of the next levels along the path toward the
+// regressed threshold 2^y (predicted feasible iff the midpoint is at least
+// it), and its decisions are replayed up to the first one the prediction got
+// wrong; any levels left run as in the plain search, then the write at the
+// result.  The result is the bisection's whatever y is.
 template <typename VT>
 __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, LearnBufs Lb)
 {
@@ -716,61 +748,52 @@ __global__ __launch_bounds__(256) void learned_kernel(GenParams P, GenBricks B, 
     const GenBrick& br = B.b[blockIdx.z];
     const int brick = B.first + blockIdx.z;
     const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
-    const int gx = (P.cam.width + 15) / 16;
     const ListSpan ls = list_span(Lb, Q_SERVED, brick, B.total, npix);
     const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
     const VT* data = (const VT*)br.data;
-    const float lg_hi = log2f(P.gmax), lg_lo = lg_hi - (float)P.iters;
     for (uint32_t idx = ls.begin + blockIdx.x * blockDim.x + threadIdx.x; idx < ls.end;
          idx += gridDim.x * blockDim.x) {
         const uint32_t pix = (uint32_t)ls.list[idx];
         const size_t ray = (size_t)brick * npix + pix;
         const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
         const RayRun q = listed_ray(P, Lb, ray, x, y);
-        const float yv = Lb.y[ray];
-        const float dl[5] = { 0.0f, -0.25f, 0.25f, -0.5f, 0.5f };
-        float y5[5], g5[5];
-        int c5[5];
+        const float2 br0 = Lb.bracket[ray];
+        float lo = br0.x, hi = br0.y;
+        int level = Lb.level[ray];
+        const float gp = exp2f(Lb.y[ray]);
+        float gg[kPredLevels];
+        bool pf[kPredLevels];
+        int cg[kPredLevels];
+        float plo = lo, phi = hi;
 #pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            y5[j] = fminf(fmaxf(yv + dl[j], lg_lo), lg_hi);
-            g5[j] = exp2f(y5[j]);
+        for (int l = 0; l < kPredLevels; ++l) {
+            const float m = 0.5f * (plo + phi);
+            gg[l] = m;
+            pf[l] = !(gp > m);
+            plo = pf[l] ? plo : m;
+            phi = pf[l] ? m : phi;
         }
-        gen_scan<VT, 5>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, g5, P.max_n, c5, nullptr);
-        const int lo = band_lo(P.max_n, Lb.cmax[ray], Lb.tol);
-        const int best = pick_in_band<5>(c5, P.max_n, lo);
-        int kind = LEARN_KEPT;
-        float2 bracket = make_float2(0.0f, 0.0f);
-        if (best < 0) {
-            // candidates in threshold order: d = -1/2, -1/4, 0, 1/4, 1/2
-            const int ord[5] = { 3, 1, 0, 2, 4 };
-            int pick = -1;
-            float pick_d = 0.0f;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int a = ord[t], b = ord[t + 1];
-                const float d = fabsf(dl[a] + dl[b]);
-                if (c5[a] > P.max_n && c5[b] < lo && (pick < 0 || d < pick_d)) {
-                    pick = t;
-                    pick_d = d;
-                    bracket = make_float2(y5[a], y5[b]);
-                }
+        const int nl = min(kPredLevels, P.iters - level);
+        if (nl > 0) {
+            gen_scan<VT, kPredLevels>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, gg, P.max_n,
+                                      cg, nullptr);
+            for (int l = 0; l < nl; ++l) {
+                const float m = 0.5f * (lo + hi);
+                ++level;
+                const bool feasible = cg[l] <= P.max_n;
+                if (feasible) hi = m;
+                else lo = m;
+                if (feasible != pf[l]) break;
             }
-            kind = pick >= 0 ? LEARN_REFINE : LEARN_FALLBACK;
         }
-        if (kind != LEARN_KEPT) {
-            // the tail list: round two inside the bracket, or (no bracket: NaN)
-            // the plain bisection
-            put_on_list(Lb, Q_TAIL, brick, B.total, x, y, gx);
-            Lb.rf_y[ray] = kind == LEARN_REFINE ? bracket : make_float2(__builtin_nanf(""), __builtin_nanf(""));
-        }
-        wave_append(&Lb.stats[LEARN_KEPT], kind == LEARN_KEPT);
-        wave_append(&Lb.stats[LEARN_FALLBACK], kind == LEARN_FALLBACK);
-        if (kind != LEARN_KEPT) continue;
+        wave_append(&Lb.stats[LEARN_KEPT], level >= P.iters);
+        wave_append(&Lb.stats[LEARN_REFINED], level < P.iters);
+        int hc = -1;
+        search_rest<VT>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, P, lo, hi, level, hc);
         GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
-        const int c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries,
-                                                g5[best], 0, 1 << 30, o, nullptr);
-        finish_list(br, pix, npix, P.max_n, c, g5[best]);
+        const int c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, hi, 0,
+                                                1 << 30, o, nullptr);
+        finish_list(br, pix, npix, P.max_n, c < P.max_n ? c : P.max_n, hi);
     }
 }
 
@@ -799,61 +822,6 @@ __global__ __launch_bounds__(256) void shortcut_kernel(GenParams P, GenBricks B,
                                                 0, 1 << 30, o, nullptr);
         wave_append(&Lb.stats[LEARN_SHORTCUT], true);
         finish_list(br, pix, npix, P.max_n, c, gmin);
-    }
-}
-
-// The rays round one did not keep, from one list: round two for those with a
-// straddling bracket (five thresholds evenly inside it, log2 y_a + (y_b - y_a)
-// t / 6 for t = 1..5, in one scan; the in-band one with the largest count is
-// kept, ties: smaller t), then, in the same thread, the plain bisection for
-// every ray still without a threshold, and the write.  Rays of both kinds
-// share the launch, so the bisections of round-one rejects overlap round two.
-template <typename VT>
-__global__ __launch_bounds__(256) void tail_kernel(GenParams P, GenBricks B, LearnBufs Lb)
-{
-    extern __shared__ TfCell tf_s[];   // P.tf_entries - 1 cells, sized at launch
-    tf_stage(tf_s, P.tf, P.tf_entries, threadIdx.x, blockDim.x);
-    __syncthreads();
-    const GenBrick& br = B.b[blockIdx.z];
-    const int brick = B.first + blockIdx.z;
-    const uint32_t npix = (uint32_t)P.cam.width * (uint32_t)P.cam.height;
-    const ListSpan ls = list_span(Lb, Q_TAIL, brick, B.total, npix);
-    const BrickGeo g = make_geo(P.n, br.dlo, br.ddim);
-    const VT* data = (const VT*)br.data;
-    for (uint32_t idx = ls.begin + blockIdx.x * blockDim.x + threadIdx.x; idx < ls.end;
-         idx += gridDim.x * blockDim.x) {
-        const uint32_t pix = (uint32_t)ls.list[idx];
-        const size_t ray = (size_t)brick * npix + pix;
-        const float2 yab = Lb.rf_y[ray];
-        const int x = (int)(pix % (uint32_t)P.cam.width), y = (int)(pix / (uint32_t)P.cam.width);
-        const RayRun q = listed_ray(P, Lb, ray, x, y);
-        const bool round2 = yab.x < yab.y;   // false for the NaN of round-one rejects
-        float gm = 0.0f;
-        int best = -1;
-        if (round2) {
-            float g5[5];
-            int c5[5];
-#pragma unroll
-            for (int t = 0; t < 5; ++t) g5[t] = exp2f(yab.x + (yab.y - yab.x) * (float)(t + 1) * (1.0f / 6.0f));
-            gen_scan<VT, 5>(data, g, q.r, P.step, P.l_step, q.k0, q.k1, tf_s, P.tf_entries, g5, P.max_n, c5,
-                            nullptr);
-            best = pick_in_band<5>(c5, P.max_n, band_lo(P.max_n, Lb.cmax[ray], Lb.tol));
-#pragma unroll
-            for (int t = 0; t < 5; ++t) gm = t == best ? g5[t] : gm;
-        }
-        wave_append(&Lb.stats[LEARN_REFINED], best >= 0);
-        wave_append(&Lb.stats[LEARN_FALLBACK], round2 & (best < 0));   // round one counted its own
-        int c = 0, k0 = q.k0, k1 = q.k1;
-        if (best < 0) {
-            gm = ldexpf(P.gmax, -P.iters);
-            if (k1 > k0) gen_search<VT>(data, g, q.r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, P, gm, c, false);
-        }
-        GenOut o{br.color, br.depth, pix, npix, (uint32_t)P.max_n};
-        c = 0;
-        if (k1 > k0)
-            c = gen_pass<VT, true, false>(data, g, q.r, P.step, P.l_step, k0, k1, tf_s, P.tf_entries, gm, 0, 1 << 30, o,
-                                          nullptr);
-        finish_list(br, pix, npix, P.max_n, c < P.max_n ? c : P.max_n, gm);
     }
 }
 
@@ -894,7 +862,8 @@ static void launch_learned_t(int phase, const GenParams& P, const GenBricks& B, 
 {
     dim3 grid((P.cam.width + 15) / 16, (P.cam.height + 15) / 16, nb);
     if (phase == 0) {
-        hipLaunchKernelGGL(features_kernel<VT>, grid, dim3(256), tf_lds<VT>(P, B, nb), s, P, B, L);
+        if (L.hist_list) hipLaunchKernelGGL((features_kernel<VT, true>), grid, dim3(256), tf_lds<VT>(P, B, nb), s, P, B, L);
+        else hipLaunchKernelGGL((features_kernel<VT, false>), grid, dim3(256), tf_lds<VT>(P, B, nb), s, P, B, L);
         return;
     }
     // list-driven: grid-stride over each brick's span of the list, enough
@@ -903,7 +872,6 @@ static void launch_learned_t(int phase, const GenParams& P, const GenBricks& B, 
     unsigned bx = (unsigned)std::min<size_t>((npix + 255) / 256, (size_t)L.blocks_per_brick);
     dim3 g2(bx, 1, nb);
     if (phase == 1) hipLaunchKernelGGL(learned_kernel<VT>, g2, dim3(256), tf_lds<VT>(P, B, nb), s, P, B, L);
-    if (phase == 2) hipLaunchKernelGGL(tail_kernel<VT>, g2, dim3(256), tf_lds<VT>(P, B, nb), s, P, B, L);
     if (phase == 4) hipLaunchKernelGGL(shortcut_kernel<VT>, g2, dim3(256), tf_lds<VT>(P, B, nb), s, P, B, L);
 }
 

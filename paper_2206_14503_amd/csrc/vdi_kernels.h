@@ -46,9 +46,11 @@ struct GenBricks {
     int total;           // bricks of the call
 };
 
-// Outcome of a brick-ray on the learned path (indices into LearnBufs::stats
-// up to LEARN_REFINED; LEARN_REFINE marks a ray listed for round two).
-enum { LEARN_KEPT = 0, LEARN_SHORTCUT = 1, LEARN_FALLBACK = 2, LEARN_EMPTY = 3, LEARN_REFINED = 4, LEARN_REFINE = 5 };
+// Outcome of a brick-ray on the learned path (indices into LearnBufs::stats):
+// the regressed threshold's scan settled every level left (KEPT) or more
+// scans followed (REFINED); at most N non-transparent samples (SHORTCUT); no
+// sample (EMPTY).  FALLBACK stays 0 (every ray ends with the bisection's result).
+enum { LEARN_KEPT = 0, LEARN_SHORTCUT = 1, LEARN_FALLBACK = 2, LEARN_EMPTY = 3, LEARN_REFINED = 4 };
 constexpr int kLearnStats = 5;
 
 // Work lists of the learned path.  A slot numbers a ray in the launch order
@@ -57,15 +59,16 @@ constexpr int kLearnStats = 5;
 // the list-driven kernels sample neighbouring voxels: per 256-slot block the
 // producers count their rays, the counts are scanned, and a compaction kernel
 // places each ray at its block's offset plus its rank in the block.
-enum { Q_SERVED = 0, Q_SHORT = 1, Q_TAIL = 2, kQueues = 3 };
+enum { Q_SERVED = 0, Q_SHORT = 1, kQueues = 2 };
 
 // Buffers of the learned-threshold path (per-ray arrays indexed brick * npix + pixel).
 struct LearnBufs {
     uint16_t* hist;      // [nb][npix][64] bf16 features; with hist_list: per brick, compacted
     int* nnt;            // [nb][npix] non-transparent samples
-    int* cmax;           // [nb][npix] count at the smallest threshold (saturates at N+1)
+    int* cmax;           // [nb][npix] features only: count at the smallest threshold (saturates at N+1)
+    int* level;          // [nb][npix] generation: bisection levels the first scan settled
+    float2* bracket;     // [nb][npix] generation: the bisection's bracket (lo, hi) after them
     const float* y;      // [nb][npix] log2(gamma) from the regressor (or the caller)
-    float2* rf_y;        // [nb][npix] log2 bracket of rays sent to round two (NaN: bisection)
     int2* span;          // [nb][npix] first non-transparent sample, one past the last (listed rays)
     int* hist_list;      // optional [nb][npix]: pixel of each compacted histogram row
     int* hist_count;     // [nb]
@@ -76,15 +79,14 @@ struct LearnBufs {
     int nblk;            // 256-slot blocks per brick
     int* stats;          // [kLearnStats]
     float s_ref;
-    float tol;
     int blocks_per_brick;  // grid of the list-driven kernels
 };
 
 // kind: 0 = search + regular write, 1 = search only, 2 = compact write
 void launch_generate(int kind, int dtype, const GenParams& P, const GenBricks& B, int nb, hipStream_t s);
-// phase 0: features (finishes empty lists, lists the others), 1: learned
-// round one, 2: the tail (round two, then the plain bisection), 4: the
-// all-feasible list
+// phase 0: features and the bisection's first scan (finishes empty lists,
+// lists the others), 1: the rest of the bisection steered by the regressed
+// threshold, with the write, 4: the all-feasible list
 void launch_learned(int phase, int dtype, const GenParams& P, const GenBricks& B, int nb, const LearnBufs& L,
                     hipStream_t s);
 // Places the rays of list q (kind == 1 + q) at their offsets, in slot order.

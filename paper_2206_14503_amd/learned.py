@@ -32,7 +32,7 @@ class LearnedConfig:
 
     kind "fhd": the FHD generator (512^3 fp32, 200 Gaussians + noise, 8
     z-slabs) under seeded orbit cameras, N=20 as in the FHD workload; the
-    rays are ten times longer and the 10% band spans three counts."""
+    rays are ten times longer."""
     kind: str = "tiny"
     n: int = 64
     n_gauss: int = 12
@@ -43,7 +43,6 @@ class LearnedConfig:
     iters: int = 10
     gamma_max: float = 2.0
     feature_scale: float = 32.0
-    fallback_tol: float = 0.1
     max_pairs: int = 8 << 20
 
     @staticmethod
@@ -163,25 +162,25 @@ def timed(fn, reps: int = 3) -> float:
 
 
 def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch.Tensor,
-             reps: int = 3, novel_deg: float = 20.0) -> Dict[str, float]:
-    """Plain bisection vs learned generation on held-out frames: time, fallback
-    rate, count statistics and the original-view rendering error of each.  The
-    plain search is timed twice: speculative (several midpoints per pass, the
-    library's BISECT) and one midpoint per pass (BISECT_SEQ, the search as the
-    paper runs it); both give the same VDIs.  On the FHD-generator frames
-    (orbit cameras) both composited VDIs are also rendered novel_deg degrees
-    along the orbit and compared with DVR there by SSIM and PSNR, which is
-    what the threshold choice costs in quality."""
-    from . import quality
+             reps: int = 3) -> Dict[str, float]:
+    """Plain bisection vs learned generation on held-out frames: time, the
+    share of served lists whose steered scan settled every remaining level,
+    and whether the VDIs are identical (they must be: the learned path only
+    reorders the bisection's scans).  The learned path is also timed with the
+    exact threshold supplied as the regressed one (log2 of the bisection's
+    result, a hair below it, so every steered decision is right): the ceiling
+    any regressor can reach.  The plain search is timed twice:
+    speculative (several midpoints per pass, the library's BISECT) and one
+    midpoint per pass (BISECT_SEQ, the search as the paper runs it); both give
+    the same VDIs.  The original-view renderings of the composited VDIs are
+    compared as well."""
     step = 1.0 / cfg.n
-    t_plain = t_learned = t_seq = 0.0
-    agg = {"accepted": 0, "refined": 0, "shortcut": 0, "fallback": 0, "empty": 0}
+    t_plain = t_learned = t_seq = t_exact = 0.0
+    agg = {"kept": 0, "refined": 0, "shortcut": 0, "empty": 0}
     mae_learned = 0.0
-    dn_sum, dn_rays = 0.0, 0
+    identical = True
     frames = 0
     rays = 0
-    q_sums = {"ssim_plain": 0.0, "ssim_learned": 0.0, "psnr_plain": 0.0, "psnr_learned": 0.0}
-    q_frames = 0
     for seed in seeds:
         vol, bricks, cam = frame_inputs(cfg, seed, cfg.res)
         dbr = vdi.device_bricks(vol, bricks)
@@ -191,8 +190,7 @@ def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch
         run_p = lambda: vdi.generate(dbr, cam, tf_d, step, step, vdi.BISECT, 0.0, cfg.max_n, cfg.iters,
                                      outs=outs_p, gamma_max=cfg.gamma_max)
         run_l = lambda: vdi.generate(dbr, cam, tf_d, step, step, vdi.LEARNED, 0.0, cfg.max_n, cfg.iters,
-                                     outs=outs_l, gamma_max=cfg.gamma_max, mlp=mlp,
-                                     fallback_tol=cfg.fallback_tol, feature_scale=cfg.feature_scale)
+                                     outs=outs_l, gamma_max=cfg.gamma_max, mlp=mlp, feature_scale=cfg.feature_scale)
         run_s = lambda: vdi.generate(dbr, cam, tf_d, step, step, vdi.BISECT_SEQ, 0.0, cfg.max_n, cfg.iters,
                                      outs=outs_p, gamma_max=cfg.gamma_max)
         run_s()
@@ -206,37 +204,22 @@ def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch
         st = vdi.learned_stats()
         for k in agg:
             agg[k] += st[k] // reps
-        # count distance from the target N_r = min(N, cmax) on rays the regressor served
-        _, nnt, cmax = vdi.tau_features(dbr, cam, tf_d, step, step, cfg.max_n, cfg.iters, cfg.gamma_max,
-                                        cfg.feature_scale)
-        served = nnt > cfg.max_n
-        cnt_l = torch.stack([o.count for o in outs_l])
-        target = torch.minimum(cmax, torch.full_like(cmax, cfg.max_n))
-        dn_sum += float((cnt_l[served] - target[served]).abs().double().sum())
-        dn_rays += int(served.sum())
-        # original-view rendering of the composited VDI vs each generation's
+        y_exact = torch.log2(torch.stack([o.gamma for o in outs_p]).double() * (1.0 - 1e-4)).float().contiguous()
+        run_e = lambda: vdi.generate(dbr, cam, tf_d, step, step, vdi.LEARNED, 0.0, cfg.max_n, cfg.iters,
+                                     outs=outs_l, gamma_max=cfg.gamma_max, y=y_exact,
+                                     feature_scale=cfg.feature_scale)
+        run_e()
+        t_exact += timed(run_e, reps)
+        vdi.learned_stats()
+        for a, b in zip(outs_p, outs_l):
+            identical &= bool(torch.equal(a.count, b.count) and torch.equal(a.gamma, b.gamma)
+                              and torch.equal(a.color, b.color) and torch.equal(a.depth, b.depth))
         comp_p = vdi.composite(outs_p, vdi.BISECT, 0.0, cfg.max_n, cfg.iters)
         comp_l = vdi.composite(outs_l, vdi.BISECT, 0.0, cfg.max_n, cfg.iters)
-        img_p = vdi.render_original_view(comp_p)
-        img_l = vdi.render_original_view(comp_l)
-        # the plain path's original-view rendering equals direct volume
-        # rendering (Sec. 2.3; checked against the oracle in the tests)
-        mae_learned += float((img_l - img_p).abs().mean())
-        if cfg.kind == "fhd":
-            w = dataclasses.replace(synth.fhd(seed), width=cfg.res[0], height=cfg.res[1])
-            view = synth.orbit_camera(10_000 + w.seed, cam.width, cam.height, turn_deg=novel_deg)
-            outs_g = vdi.generate(dbr, view, tf_d, step, step, vdi.BISECT, 0.0, cfg.max_n, cfg.iters,
-                                  gamma_max=cfg.gamma_max)
-            gt = vdi.render_original_view(vdi.composite(outs_g, vdi.BISECT, 0.0, cfg.max_n, cfg.iters)).cpu().numpy()
-            del outs_g
-            for key, comp in (("plain", comp_p), ("learned", comp_l)):
-                nv = vdi.render_novel_view(comp, cam, view, step).cpu().numpy()
-                q_sums["ssim_" + key] += quality.ssim(nv, gt, height=view.height)
-                q_sums["psnr_" + key] += quality.psnr(nv, gt, height=view.height)
-            q_frames += 1
+        mae_learned += float((vdi.render_original_view(comp_l) - vdi.render_original_view(comp_p)).abs().mean())
         frames += 1
         rays += len(bricks) * P
-    served_total = agg["accepted"] + agg["refined"] + agg["fallback"]
+    served = agg["kept"] + agg["refined"]
     return {
         "frames": frames,
         "brick_rays": rays,
@@ -245,12 +228,12 @@ def evaluate(mlp: vdi.MLP, cfg: LearnedConfig, seeds: Sequence[int], tf_d: torch
         "speedup": t_plain / t_learned,
         "plain_seq_ms": t_seq / frames,
         "speedup_vs_seq": t_seq / t_learned,
-        "fallback_rate": agg["fallback"] / max(served_total, 1),
-        "accepted": agg["accepted"], "refined": agg["refined"], "fallback": agg["fallback"],
-        "shortcut": agg["shortcut"], "empty": agg["empty"],
-        "mean_abs_count_miss": dn_sum / max(dn_rays, 1),
+        "exact_threshold_ms": t_exact / frames,
+        "speedup_exact_threshold": t_plain / t_exact,
+        "kept_rate": agg["kept"] / max(served, 1),
+        **agg,
+        "identical_to_plain": identical,
         "rgba_mae_vs_plain_render": mae_learned / frames,
-        **({f"{k}_{novel_deg:g}deg_vs_dvr": v / q_frames for k, v in q_sums.items()} if q_frames else {}),
     }
 
 

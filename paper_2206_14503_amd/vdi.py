@@ -500,7 +500,7 @@ def mlp_mse(y: torch.Tensor, gamma: torch.Tensor, scale: float):
 def learned_stats():
     st = (ctypes.c_int64 * 5)()
     _check(lib().vdi_learned_stats(context(), st, _stream()))
-    return {"accepted": st[0], "shortcut": st[1], "fallback": st[2], "empty": st[3], "refined": st[4]}
+    return {"kept": st[0], "shortcut": st[1], "fallback": st[2], "empty": st[3], "refined": st[4]}
 
 
 def debug_mfma(A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:

@@ -139,10 +139,18 @@ def test_features_match_oracle(V, OL):
     assert np.array_equal(cmax.cpu().numpy()[free], np.minimum(c_ref, 9)[free])
 
 
-def test_learned_generation_decisions(V, OL):
-    """With an arbitrary regressor, every list is either kept at the regressed
-    threshold (count inside the band) or equal to the plain bisection's list;
-    the all-feasible shortcut gives the bisection's result exactly."""
+def _same_lists(a, b):
+    return (np.array_equal(a.count.cpu().numpy(), b.count.cpu().numpy())
+            and np.array_equal(a.gamma.cpu().numpy(), b.gamma.cpu().numpy())
+            and np.array_equal(a.color.cpu().numpy(), b.color.cpu().numpy())
+            and np.array_equal(a.depth.cpu().numpy(), b.depth.cpu().numpy()))
+
+
+def test_learned_generation_equals_bisection(V, OL):
+    """With an arbitrary regressor (random weights, output shifted), the
+    learned path's VDIs equal the plain bisection's bit for bit: the
+    regressed threshold only orders the scans.  The tallies split the
+    brick-rays by their non-transparent samples."""
     import torch
     vol = synth.gaussian_volume(64, 12, 5)
     tf = synth.transfer_function()
@@ -157,30 +165,25 @@ def test_learned_generation_decisions(V, OL):
     V.learned_stats()
     lrn = V.generate(dbr, cam, tf_d, 1 / 64, 1 / 64, V.LEARNED, 0.0, 8, 10, mlp=mlp)
     st = V.learned_stats()
-    hist, nnt, cmax = V.tau_features(dbr, cam, tf_d, 1 / 64, 1 / 64, 8, 10, 2.0, 32.0)
-    assert st["accepted"] + st["refined"] + st["shortcut"] + st["fallback"] + st["empty"] == 2 * 128 * 128
     for r in range(2):
-        cp, cl = plain[r].count.cpu().numpy(), lrn[r].count.cpu().numpy()
-        gp, gl = plain[r].gamma.cpu().numpy(), lrn[r].gamma.cpu().numpy()
-        n, cm = nnt[r].cpu().numpy(), cmax[r].cpu().numpy()
-        same = gl == gp
-        # lists not served by the regressor, or sent back to bisection, equal the plain ones bit for bit
-        eq = same & (cl == cp)
-        assert np.all(eq[n <= 8])
-        col_p, col_l = plain[r].color.cpu().numpy(), lrn[r].color.cpu().numpy()
-        assert np.array_equal(col_p[:, eq], col_l[:, eq])
-        kept = ~same
-        m = np.minimum(8, cm)
-        lo = m - np.floor(0.1 * m + 1e-6)
-        assert np.all((cl[kept] <= 8) & (cl[kept] >= lo[kept]))
+        assert _same_lists(plain[r], lrn[r]), r
+    _, nnt, _ = V.tau_features(dbr, cam, tf_d, 1 / 64, 1 / 64, 8, 10, 2.0, 32.0)
+    n = nnt.cpu().numpy()
+    assert st["kept"] + st["refined"] == int((n > 8).sum())
+    assert st["shortcut"] == int(((n > 0) & (n <= 8)).sum())
+    assert st["fallback"] == 0
+    assert sum(st.values()) == 2 * 128 * 128
 
 
 @pytest.mark.parametrize("camera", ["ortho", "orbit"])
-def test_learned_rounds_match_oracle(V, OL, orc, camera):
-    """Caller-supplied log2 thresholds (the plain bisection's, plus seeded
-    noise) through the learned path: outcome, threshold and count of every
-    tie-free brick-ray equal the oracle's two-round decision; lists sent back
-    to bisection, and shortcut lists, equal the plain ones."""
+def test_learned_steering_with_any_threshold(V, orc, camera):
+    """Caller-supplied log2 thresholds steer the scans: the plain bisection's
+    own threshold (a hair below it, so every predicted decision is right),
+    the same with seeded noise, and extreme values (NaN, +-inf, far outside
+    the range).  Every run equals the plain bisection bit for bit, and on
+    tie-free brick-rays the oracle's bisection (threshold and count).  With
+    the exact threshold no served list needs a scan beyond the steered one
+    unless more than five levels were left after the first scan."""
     import torch
     vol = synth.gaussian_volume(64, 12, 17)
     tf = synth.transfer_function()
@@ -188,51 +191,43 @@ def test_learned_rounds_match_oracle(V, OL, orc, camera):
     bricks = synth.brick_grid((64, 64, 64), (1, 1, 2))
     N, step = 8, 1 / 64
     plain_o = orc.generate(vol, bricks, cam, tf, step, step, 1, 0.0, N, 10)
-    rng = np.random.default_rng(3)
-    y = (np.log2(plain_o["gamma"].astype(np.float64)) + rng.normal(0.0, 0.4, plain_o["gamma"].shape)).astype(np.float32)
-    _, nnt, cmax = OL.features(vol, bricks, cam, tf, step, step, 10, 2.0, 32.0)
-    nb, P = nnt.shape
-
-    def count_fn(g):
-        c, m = OL.count_at(vol, bricks, cam, tf, step, step, g.reshape(nb, P), N)
-        return c.ravel(), m.ravel()
-
-    ref = OL.choose(count_fn, y, nnt, cmax, N)
     dbr = V.device_bricks(vol, bricks)
     tf_d = torch.from_numpy(tf).cuda()
-    V.learned_stats()
-    out = V.generate(dbr, cam, tf_d, step, step, V.LEARNED, 0.0, N, 10, y=torch.from_numpy(y).cuda())
-    st = V.learned_stats()
-    gg = np.stack([o.gamma.cpu().numpy() for o in out]).ravel()
-    gc = np.stack([o.count.cpu().numpy() for o in out]).ravel()
-    kind, free = ref["kind"], ref["margin"] >= 2e-5
-    pm = plain_o["margin"].ravel() >= 2e-5
-    regressed = np.isin(kind, [OL.KEPT, OL.REFINED])
-    sel = free & regressed
-    np.testing.assert_allclose(gg[sel], ref["gamma"][sel], rtol=2e-6, atol=0)
-    _, m_at = OL.count_at(vol, bricks, cam, tf, step, step, gg.reshape(nb, P).astype(np.float32), N)
-    robust = sel & (m_at.ravel() >= 2e-5)
-    c_ref, _ = OL.count_at(vol, bricks, cam, tf, step, step, ref["gamma"].reshape(nb, P), N)
-    assert np.array_equal(gc[robust], c_ref.ravel()[robust])
-    back = free & pm & np.isin(kind, [OL.FALLBACK, OL.SHORTCUT])
-    assert np.array_equal(gg[back], plain_o["gamma"].ravel()[back])
-    assert np.array_equal(gc[back], plain_o["count"].ravel()[back])
-    # every outcome occurs, and the device's tallies match the oracle's up to tie rays
-    n_tie = int((~free).sum())
-    for key, k in (("accepted", OL.KEPT), ("refined", OL.REFINED), ("fallback", OL.FALLBACK),
-                   ("shortcut", OL.SHORTCUT), ("empty", OL.EMPTY)):
-        want = int((kind == k).sum())
-        assert abs(st[key] - want) <= n_tie, (key, st[key], want, n_tie)
-    assert min(st["accepted"], st["refined"], st["fallback"], st["shortcut"]) > 0, st
+    plain = V.generate(dbr, cam, tf_d, step, step, V.BISECT, 0.0, N, 10)
+    g_star = np.stack([o.gamma.cpu().numpy() for o in plain]).astype(np.float64)
+    rng = np.random.default_rng(3)
+    exact = np.log2(g_star * (1.0 - 1e-4)).astype(np.float32)
+    noisy = (exact + rng.normal(0.0, 0.4, exact.shape)).astype(np.float32)
+    wild = rng.choice(np.float32([np.nan, np.inf, -np.inf, 40.0, -40.0, 0.0]), exact.shape).astype(np.float32)
+    free = plain_o["margin"] >= 2e-5
+    for name, y in (("exact", exact), ("noisy", noisy), ("wild", wild)):
+        V.learned_stats()
+        out = V.generate(dbr, cam, tf_d, step, step, V.LEARNED, 0.0, N, 10, y=torch.from_numpy(y).cuda())
+        st = V.learned_stats()
+        for r in range(len(bricks)):
+            assert _same_lists(plain[r], out[r]), (name, r)
+        gg = np.stack([o.gamma.cpu().numpy() for o in out])
+        gc = np.stack([o.count.cpu().numpy() for o in out])
+        assert np.array_equal(gg[free], plain_o["gamma"][free]), name
+        assert np.array_equal(gc[free], plain_o["count"][free]), name
+        if name == "exact":
+            assert st["kept"] > 0
+            exact_st = st
+        if name == "noisy":
+            assert st["kept"] + st["refined"] == exact_st["kept"] + exact_st["refined"]
+            assert st["kept"] <= exact_st["kept"]
 
 
 def test_learned_gain_short_training(V):
-    """Train on a few volumes with the project's kernels, evaluate on a held-out
-    volume: the learned path keeps most regressed thresholds and renders the
-    same image from the original view; report its speed against bisection."""
+    """Train on a few small frames with the project's kernels, evaluate on a
+    held-out frame of the config-4 size (1024^2, two bricks): the learned
+    path gives the plain bisection's VDIs and is faster than the search as
+    the paper runs it (one midpoint per pass); its speed against the
+    speculative search, and the ceiling with the exact threshold, are
+    reported (the bench records them)."""
     import torch
     from paper_2206_14503_amd import learned
-    cfg = learned.LearnedConfig(res=(128, 128), train_res=(128, 128))
+    cfg = learned.LearnedConfig(train_res=(128, 128))
     tf_d = torch.from_numpy(synth.transfer_function()).cuda()
     X, Y, st = learned.training_pairs(cfg, seeds=range(6), tf_d=tf_d)
     assert st["kept"] > 1000
@@ -241,8 +236,10 @@ def test_learned_gain_short_training(V):
     assert losses[-1] < 0.5 * losses[0]
     ev = learned.evaluate(mlp, cfg, seeds=[100], tf_d=tf_d, reps=3)
     print("learned vs plain:", ev)
-    assert ev["rgba_mae_vs_plain_render"] <= 1e-3
-    assert ev["accepted"] > 0
+    assert ev["identical_to_plain"]
+    assert ev["rgba_mae_vs_plain_render"] == 0.0
+    assert ev["kept"] > 0
+    assert ev["speedup_vs_seq"] > 1.0
 
 
 def test_mlp_mse_gradient_and_loss(V):

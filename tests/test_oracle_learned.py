@@ -112,65 +112,6 @@ def test_features_histogram_counts(L, orc):
             assert np.array_equal(np.bincount(bins, minlength=64), hist[r, p].astype(int))
 
 
-def test_accept_band(L):
-    """m = min(N, cmax); kept iff m - floor(0.1 m) <= n <= N."""
-    N = 20
-    cm = np.array([30, 30, 30, 30, 5, 5, 5, 8])
-    n = np.array([20, 18, 17, 21, 5, 4, 6, 8])
-    assert L.accept(n, cm, N).tolist() == [True, True, False, False, True, False, True, True]
-    assert L.accept(np.array([8, 7]), np.array([40, 40]), 8).tolist() == [True, False]
-
-
-def _step_counts(edges, counts):
-    """count(gamma) = counts[i] for log2(gamma) in [edges[i-1], edges[i]) (a step function)."""
-    def fn(g):
-        lg = np.log2(np.asarray(g, np.float64))
-        return np.asarray(counts)[np.searchsorted(edges, lg, side="right")], np.full(lg.shape, 1.0)
-    return fn
-
-
-def test_choose_round_one_and_two_by_hand(L):
-    """Hand-derived outcomes on step-function count curves (N = 8, cmax large -> band {8}).
-    Ray 0: the band [2^-5, 2^-4.9) holds the candidate y-1/2 = -5 -> kept at 2^-5.
-    Ray 1: band [2^-4.7, 2^-4.65) lies between the candidates -4.75 (12) and -4.5 (5);
-           round two tries -4.75 + t/24: t=1 -> -4.708 (12), t=2 -> -4.667 (8) -> kept.
-    Ray 2: counts 12 below 2^-3 and 3 above: no band anywhere -> fallback.
-    Ray 3: every candidate gives 12 (> N), no straddling pair -> fallback.
-    Ray 4: 4 non-transparent samples -> shortcut at 2^-9."""
-    curves = [([-5.0, -4.9], [12, 8, 5]), ([-4.7, -4.65], [12, 8, 5]), ([-3.0], [12, 3]), ([5.0], [12, 3]),
-              ([-9.5], [12, 3])]
-    y = np.float32([-4.5, -4.5, -3.0, -4.0, -2.0])
-
-    def count_fn(g):
-        c = np.zeros(len(g), np.int64)
-        for i, (e, v) in enumerate(curves):
-            c[i] = _step_counts(np.array(e), v)(np.array([g[i]]))[0][0]
-        return c, np.ones(len(g))
-
-    out = L.choose(count_fn, y, nnt=np.array([40, 40, 40, 40, 4]), cmax=np.array([9, 9, 9, 9, 4]), max_n=8)
-    assert out["kind"].tolist() == [L.KEPT, L.REFINED, L.FALLBACK, L.FALLBACK, L.SHORTCUT]
-    assert out["gamma"][0] == np.float32(2.0 ** -5)
-    y2 = np.float32(-4.75) + (np.float32(-4.5) - np.float32(-4.75)) * np.float32(2) * (np.float32(1) / np.float32(6))
-    assert abs(float(y2) - (-4.75 + 2 * 0.25 / 6)) < 1e-6
-    assert out["gamma"][1] == np.float32(2.0 ** float(y2))
-    assert out["gamma"][4] == np.float32(2.0 ** -9)
-
-
-def test_choose_band_uses_cmax_target():
-    """With cmax = 5 < N the target is 5 (band [5 - floor(0.5), 8] = [5, 8]); the
-    largest in-band count wins, ties go to the first listed candidate."""
-    import oracle.learned as L
-    counts = {0.0: 6, -0.25: 7, 0.25: 5, -0.5: 9, 0.5: 4}
-
-    def count_fn(g):
-        lg = float(np.log2(np.float64(g[0])))
-        d = min(counts, key=lambda k: abs(k - (lg + 3.0)))
-        return np.array([counts[d]]), np.ones(1)
-
-    out = L.choose(count_fn, np.float32([-3.0]), nnt=np.array([30]), cmax=np.array([5]), max_n=8)
-    assert out["kind"][0] == L.KEPT and out["gamma"][0] == np.float32(2.0 ** -3.25)
-
-
 def test_composite_features_hand_example():
     """Two interleaved lists of three elements, N = 2: merged by front the
     per-step colours are 0, 0.5, 0.5, 1, 1, 1.5 (red only), so the five
