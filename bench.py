@@ -702,7 +702,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a kernel of known traffic for counter scaling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
-    ap.add_argument("--sample-px", type=int, default=65536, help="headline pixels kept for the oracle")
+    ap.add_argument("--sample-px", type=int, default=786432, help="headline pixels kept for the oracle")
     ap.add_argument("--fhd-sample-px", type=int, default=16384, help="FHD pixels compared with the oracle")
     args = ap.parse_args()
 

@@ -245,7 +245,13 @@ vdi_status vdi_generate(vdi_ctx *ctx, const vdi_brick_t *bricks, int k, const vd
  * extension beyond the paper, trained on such histograms; see vdi_mlp_*).
  * tau->features, if set, receives those histograms (bf16) per pixel.
  * All inputs share width, height and ref_step with out; out must be regular.
- * Inputs may mix layouts.  k in [1, VDI_MAX_INPUTS]. */
+ * Inputs may mix layouts.  k in [1, VDI_MAX_INPUTS].
+ * Streams: when the general merge's pixels span several staging chunks, the
+ * call forks work onto a second stream of the context (the next chunk's merge
+ * beside the current chunk's re-segmentation) after an event on `stream`, and
+ * joins it back into `stream` with an event before returning; work enqueued
+ * on `stream` afterwards runs after all of it (also under graph capture).
+ * Calls on different streams of one context must not overlap. */
 vdi_status vdi_composite(vdi_ctx *ctx, const vdi_t *in, int k, const vdi_tau_t *tau, vdi_t *out,
                          void *stream);
 
