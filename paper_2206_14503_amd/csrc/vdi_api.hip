@@ -272,8 +272,6 @@ static void composite_ordered(CompParams& P, char* base, uint32_t chunk)
     P.stage_c = (float4*)base;
     P.stage_d = (float2*)(base + c * cap * sizeof(float4));
     char* q = base + c * cap * (sizeof(float4) + sizeof(float2));
-    P.seq = (uint16_t*)q;
-    q += (c * cap * sizeof(uint16_t) + 255) & ~(size_t)255;
     P.qtot = (int*)q;
     q += (c * sizeof(int) + 255) & ~(size_t)255;
     P.ghat = (float*)q;

@@ -745,23 +745,24 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
 // ---------------------------------------------------------------- ordered general merge
 //
 // The queue of pixels the depth-disjoint path left (or every pixel when k is
-// above its limit) is processed in chunks, each by three kernels:
-//   1. merge_order_kernel: the merge order of every entry's lists by (front,
-//      input), from the fronts alone (16 entries per wavefront, 4 lanes per
-//      entry, each lane the lists r = lane mod 4, r + 4, ...; the lists'
-//      fronts in LDS; validates every element);
-//   2. merge_stage_kernel: per tile of 8 entries (consecutive pixels when the
+// above its limit) is processed in chunks, each by two kernels:
+//   1. merge_stage_kernel: per tile of 8 entries (consecutive pixels when the
 //      queue holds whole blocks) the elements are read in whole lines into
-//      LDS and written to the staging slab in merge order, again in whole
-//      lines (the 8 entries are adjacent columns of a slab row);
-//   3. composite_staged_kernel: one lane per entry, the re-segmentation scans
+//      LDS and validated; each entry's lists are merged by (front, input) in
+//      LDS by a tree of pairwise merges (inputs 2i and 2i+1, then pairs of
+//      those, ...), each pairwise merge cut into equal output ranges for its
+//      threads by a co-rank search (merge path); the merged lists are written
+//      to the staging slab in order, in whole lines (the 8 entries are
+//      adjacent columns of a slab row), with the threshold-prediction
+//      features;
+//   2. composite_staged_kernel: one lane per entry, the re-segmentation scans
 //      over the slab (each scan step of a wavefront reads whole rows).
 // Per-lane gathers from the inputs' slot-major planes, where a lane's 16
 // bytes come with a line its neighbours need at other times, are avoided.
 
-constexpr int kOrdEntries = 16;   // entries per merge_order_kernel wavefront
 constexpr int kStageTile = 8;     // entries per merge_stage_kernel block
 constexpr int kStageBatch = 8;    // loads a merge_stage_kernel thread keeps in flight
+constexpr int kStageLanes = 32;   // threads per entry in the merge (256 / kStageTile)
 // Threshold prediction: consecutive-operand distances binned by log2 over
 // [kPredLo, kPredHi).
 constexpr int kPredBins = 64;
@@ -776,164 +777,57 @@ __device__ inline int input_base(const CompParams& P, int r)
     return b;
 }
 
-// Lexicographic minimum of (front, input) across the 4 lanes of an entry
-// (DPP quad permutations: lane ^ 1, then lane ^ 2).
-template <int CTRL>
-__device__ inline int quad_swap(int v)
-{
-    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
-}
-__device__ inline void quad_min(float& f, int& r)
-{
-    float of = __int_as_float(quad_swap<0xB1>(__float_as_int(f)));
-    int orr = quad_swap<0xB1>(r);
-    bool take = (of < f) | ((of == f) & (orr < r));
-    f = take ? of : f;
-    r = take ? orr : r;
-    of = __int_as_float(quad_swap<0x4E>(__float_as_int(f)));
-    orr = quad_swap<0x4E>(r);
-    take = (of < f) | ((of == f) & (orr < r));
-    f = take ? of : f;
-    r = take ? orr : r;
-}
-
-// Depth loads a merge_order_kernel lane keeps in flight while reading its
-// lists' fronts.
-constexpr int kOrdBatch = 8;
-
-// J: lists per lane (k <= 4 J).
-template <int J>
-__device__ void merge_order_group(const CompParams& P, uint32_t e0, uint32_t grp, float* fr, uint32_t nq)
-{
-    const int t = threadIdx.x, ql = t >> 2, sub = t & 3;
-    const uint32_t le = grp * kOrdEntries + ql;
-    const bool active = le < P.chunk && e0 + le < nq;
-    const uint32_t p = active ? (uint32_t)P.q_list[e0 + le] : 0u;
-    float* F = fr + ql * P.seq_cap;
-    int cnt[J], base[J], cur[J];
-    float hf[J], nf[J];
-    bool bad = false;
-    int tot = 0;
-    // ---- counts, fronts into LDS, validation (finite, f < b, sorted per list)
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int r = sub + 4 * j;
-        cnt[j] = 0;
-        base[j] = 0;
-        if (r < P.k && active) {
-            const CompInput& in = P.in[r];
-            int c = in.count[p];
-            const uint32_t eb = in.compact ? in.offset[p] : p;
-            const uint64_t last = in.compact ? (uint64_t)eb + (uint64_t)(c > 0 ? c : 0)
-                                             : (uint64_t)(c > 0 ? c : 0) * P.npix;
-            if (c < 0 || c > in.max_n || last > in.capacity) {
-                bad = true;
-                c = 0;
-            }
-            const uint32_t stride = in.compact ? 1u : P.npix;
-            const int b0 = input_base(P, r);
-            float prev = -__builtin_inff();
-            for (int s0 = 0; s0 < c; s0 += kOrdBatch) {
-                float2 fb[kOrdBatch];
-#pragma unroll
-                for (int u = 0; u < kOrdBatch; ++u)
-                    if (s0 + u < c) fb[u] = gload(in.depth, eb + (uint32_t)(s0 + u) * stride);
-#pragma unroll
-                for (int u = 0; u < kOrdBatch; ++u) {
-                    if (s0 + u < c) {
-                        bad |= !(isfinite(fb[u].x) & isfinite(fb[u].y) & (fb[u].x < fb[u].y) & (fb[u].x >= prev));
-                        prev = fb[u].x;
-                        F[b0 + s0 + u] = fb[u].x;
-                    }
-                }
-            }
-            cnt[j] = c;
-            base[j] = b0;
-            tot += c;
-        }
-    }
-    // the entry's total and validity over its 4 lanes
-    tot += quad_swap<0xB1>(tot);
-    tot += quad_swap<0x4E>(tot);
-    int badi = bad ? 1 : 0;
-    badi |= quad_swap<0xB1>(badi);
-    badi |= quad_swap<0x4E>(badi);
-    if (badi) tot = 0;
-    if (active && sub == 0) {
-        P.qtot[le] = badi ? -1 : tot;
-        if (badi) reject_pixel(P, p);
-    }
-    // ---- merge: each step the lane's smallest head, then the entry's; the
-    // lane owning the winner records (input, slot) and advances.  Each list
-    // keeps its head and next front in registers; the front after next is
-    // read from LDS when the list advances and merged into the registers a
-    // step later, so the read's latency overlaps the next selection.  A lane
-    // reads back only fronts it wrote itself.
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        cur[j] = 0;
-        hf[j] = cnt[j] > 0 ? F[base[j]] : __builtin_inff();
-        nf[j] = cnt[j] > 1 ? F[base[j] + 1] : __builtin_inff();
-    }
-    int wmax = tot;
-#pragma unroll
-    for (int m = 4; m < 64; m <<= 1) wmax = max(wmax, __shfl_xor(wmax, m, 64));
-    uint16_t* seq = P.seq + (size_t)(le >> 3) * P.seq_cap * 8 + (le & 7);
-    int pj = -1;                          // list whose front after next is pending
-    float pv = __builtin_inff();          // that front
-    for (int i = 0; i < wmax; ++i) {
-#pragma unroll
-        for (int j = 0; j < J; ++j) nf[j] = j == pj ? pv : nf[j];
-        float bf = __builtin_inff();
-        int bj = 0;
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const bool lt = hf[j] < bf;
-            bf = lt ? hf[j] : bf;
-            bj = lt ? j : bj;
-        }
-        int br = bf < __builtin_inff() ? sub + 4 * bj : 0x7fff;
-        quad_min(bf, br);
-        const bool own = (i < tot) & ((br & 3) == sub) & (br < 0x7fff);
-        const int jw = own ? br >> 2 : -1;
-        int sw = 0, bw = 0, cw = 0;
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const bool w = j == jw;
-            sw = w ? cur[j] : sw;
-            bw = w ? base[j] : bw;
-            cw = w ? cnt[j] : cw;
-            hf[j] = w ? nf[j] : hf[j];
-            cur[j] += w ? 1 : 0;
-        }
-        pj = jw;
-        pv = (own & (sw + 2 < cw)) ? F[bw + sw + 2] : __builtin_inff();
-        if (own) seq[(size_t)i * 8] = (uint16_t)((br << 6) | sw);
-    }
-}
-
-// Persistent: blocks take groups of 16 chunk entries until the chunk or the
-// queue ends.
-template <int J>
-__global__ __launch_bounds__(64) void merge_order_kernel(CompParams P, uint32_t e0)
-{
-    extern __shared__ __align__(16) float fr[];      // [16][seq_cap] fronts, entry rows
-    const uint32_t nq = (uint32_t)*P.q_count;
-    const uint32_t groups = P.chunk / kOrdEntries;
-    for (uint32_t g = blockIdx.x; g < groups && e0 + g * kOrdEntries < nq; g += gridDim.x)
-        merge_order_group<J>(P, e0, g, fr, nq);
-}
-
 // LDS of merge_stage_kernel besides the tile's elements.
 struct StageLds {
     int cntS[kStageTile][kMaxInputs];
     uint32_t ebS[kStageTile][kMaxInputs];
+    int preS[kStageTile][kMaxInputs + 1];   // exclusive prefix of the counts (merge positions)
     int baseS[kMaxInputs];
     uint8_t rinS[kOrderedMaxCap];
     int totS[kStageTile];
-    uint16_t codeS[kOrderedMaxCap * kStageTile];
+    int badS[kStageTile];
     uint32_t histS[kStageTile * kPredBins];
 };
+
+// Element row of an entry's element (the merge buffers hold rows: input
+// base + slot) and its front.
+__device__ inline float row_front(const float2* Ed, int row, int q) { return Ed[row * kStageTile + q].x; }
+
+// Merge of the sorted runs A = src[a0, a1) and B = src[a1, b1) (rows of
+// entry q; an element of A precedes one of B on equal fronts: A holds the
+// lower inputs) into dst[a0, b1): thread j of `tpm` writes the outputs
+// [d0, d1) of the merged run, starting where a co-rank search over A places
+// output d0.
+__device__ inline void merge_path(const uint16_t* src, uint16_t* dst, const float2* Ed, int q, int a0, int a1, int b1,
+                                  int j, int tpm)
+{
+    const int a = a1 - a0, b = b1 - a1, n = a + b;
+    const int d0 = (int)(((long long)j * n) / tpm), d1 = (int)(((long long)(j + 1) * n) / tpm);
+    if (d0 >= d1) return;
+    // i = how many of the first d0 outputs come from A
+    int lo = max(0, d0 - b), hi = min(d0, a);
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        // A[mid] before B[d0 - mid - 1]: more than mid outputs come from A
+        if (row_front(Ed, src[a0 + mid], q) <= row_front(Ed, src[a1 + d0 - mid - 1], q)) lo = mid + 1;
+        else hi = mid;
+    }
+    int ia = lo, ib = d0 - lo;
+    float fa = ia < a ? row_front(Ed, src[a0 + ia], q) : 0.0f;
+    float fb = ib < b ? row_front(Ed, src[a1 + ib], q) : 0.0f;
+    for (int d = d0; d < d1; ++d) {
+        const bool take_a = ia < a && (ib >= b || fa <= fb);
+        if (take_a) {
+            dst[a0 + d] = src[a0 + ia];
+            ++ia;
+            if (ia < a) fa = row_front(Ed, src[a0 + ia], q);
+        } else {
+            dst[a0 + d] = src[a1 + ib];
+            ++ib;
+            if (ib < b) fb = row_front(Ed, src[a1 + ib], q);
+        }
+    }
+}
 
 // One tile of 8 chunk entries by a block of 256 threads.
 __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile, unsigned char* lds_raw,
@@ -941,39 +835,57 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
 {
     int(&cntS)[kStageTile][kMaxInputs] = S.cntS;
     uint32_t(&ebS)[kStageTile][kMaxInputs] = S.ebS;
+    int(&preS)[kStageTile][kMaxInputs + 1] = S.preS;
     int* baseS = S.baseS;
     uint8_t* rinS = S.rinS;
     int* totS = S.totS;
-    uint16_t* codeS = S.codeS;
+    int* badS = S.badS;
     uint32_t* histS = S.histS;
     const int t = threadIdx.x;
     const int cap = P.seq_cap;
     float4* Ec = (float4*)lds_raw;                         // [cap][8]
     float2* Ed = (float2*)(lds_raw + (size_t)cap * kStageTile * sizeof(float4));
+    uint16_t* mb0 = (uint16_t*)(lds_raw + (size_t)cap * kStageTile * (sizeof(float4) + sizeof(float2)));  // [8][cap]
+    uint16_t* mb1 = mb0 + (size_t)cap * kStageTile;
     const uint32_t le0 = tile * kStageTile;
-    if (t < kStageTile) {
-        const uint32_t le = le0 + t;
-        totS[t] = (le < P.chunk && e0 + le < nq) ? P.qtot[le] : -1;
-    }
+    if (t < kStageTile) badS[t] = 0;
     if (t < P.k) {
         const int b = input_base(P, t);
         baseS[t] = b;
         for (int s_ = 0; s_ < P.in[t].max_n; ++s_) rinS[b + s_] = (uint8_t)t;
     }
-    __syncthreads();
+    // counts, validated (an entry past the queue has none)
     if (t < kStageTile * P.k) {
         const int q = t / P.k, r = t - q * P.k;
+        const uint32_t le = le0 + q;
         int c = 0;
         uint32_t eb = 0;
-        if (totS[q] > 0) {
-            const uint32_t p = (uint32_t)P.q_list[e0 + le0 + q];
-            c = P.in[r].count[p];   // validated by merge_order_kernel
-            eb = P.in[r].compact ? P.in[r].offset[p] : p;
+        if (le < P.chunk && e0 + le < nq) {
+            const uint32_t p = (uint32_t)P.q_list[e0 + le];
+            const CompInput& in = P.in[r];
+            c = in.count[p];
+            eb = in.compact ? in.offset[p] : p;
+            const uint64_t last = in.compact ? (uint64_t)eb + (uint64_t)(c > 0 ? c : 0)
+                                             : (uint64_t)(c > 0 ? c : 0) * P.npix;
+            if (c < 0 || c > in.max_n || last > in.capacity) {
+                atomicOr(&badS[q], 1);
+                c = 0;
+            }
         }
         cntS[q][r] = c;
         ebS[q][r] = eb;
     }
     __syncthreads();
+    if (t < kStageTile) {
+        const uint32_t le = le0 + t;
+        int acc = 0;
+        for (int r = 0; r < P.k; ++r) {
+            preS[t][r] = acc;
+            acc += cntS[t][r];
+        }
+        preS[t][P.k] = acc;
+        totS[t] = (le < P.chunk && e0 + le < nq) ? acc : -1;
+    }
     // elements into LDS: (slot row, entry) with the entry fastest, so the 8
     // entries of a row read one line of each slot-major plane; each thread
     // keeps kStageBatch loads in flight
@@ -1008,43 +920,72 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
             }
         }
     }
-    int tmax = 0;
-#pragma unroll
-    for (int q = 0; q < kStageTile; ++q) tmax = max(tmax, totS[q]);
-    // the merge order of the 8 entries into LDS
-    const uint16_t* seq = P.seq + (size_t)(le0 >> 3) * cap * 8;
-    const int n_out = tmax * kStageTile;
-    for (int b0 = 0; b0 < n_out; b0 += 256 * kStageBatch) {
-        uint16_t code[kStageBatch];
-#pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = b0 + t + 256 * u;
-            const int q = idx & 7, i = idx >> 3;
-            code[u] = (idx < n_out && i < totS[q]) ? seq[(size_t)i * 8 + q] : (uint16_t)0xffffu;
+    __syncthreads();
+    // validation (finite depths, f < b, fronts non-decreasing along each
+    // list) and the merge's initial runs: each input's rows in order
+    for (int idx = t; idx < n_el; idx += 256) {
+        const int q = idx & 7, rs = idx >> 3;
+        const int r = rinS[rs];
+        const int s_ = rs - baseS[r];
+        if (s_ < cntS[q][r]) {
+            const float2 d = Ed[idx];
+            bool ok = isfinite(d.x) & isfinite(d.y) & (d.x < d.y);
+            if (s_ > 0) ok &= d.x >= Ed[idx - kStageTile].x;
+            if (!ok) atomicOr(&badS[q], 1);
+            mb0[q * cap + preS[q][r] + s_] = (uint16_t)rs;
         }
-#pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = b0 + t + 256 * u;
-            if (idx < n_out) codeS[idx] = code[u];
+    }
+    __syncthreads();
+    // pairwise merge tree: at level l the runs are the merged lists of
+    // 2^(l-1) consecutive inputs; each run pair (lower inputs first) is
+    // merged by kStageLanes / (number of pairs) threads of its entry
+    uint16_t* src = mb0;
+    {
+        const int q = t / kStageLanes, j = t - q * kStageLanes;
+        int kp = 1;
+        while (kp < P.k) kp <<= 1;
+        uint16_t* dst = mb1;
+        for (int w = 1; w < kp; w <<= 1) {   // w: inputs per run before this level
+            const int pairs = kp / (2 * w);
+            const int tpm = kStageLanes / pairs;
+            const int m = j / tpm, jj = j - m * tpm;
+            const int r0 = m * 2 * w;
+            const int a0 = preS[q][min(r0, P.k)], a1 = preS[q][min(r0 + w, P.k)], b1 = preS[q][min(r0 + 2 * w, P.k)];
+            if (totS[q] > 0) merge_path(src + q * cap, dst + q * cap, Ed, q, a0, a1, b1, jj, tpm);
+            __syncthreads();
+            uint16_t* tmp = src;
+            src = dst;
+            dst = tmp;
         }
+    }
+    // the merged rows are in src; the entries' lengths (-1: rejected)
+    if (t < kStageTile) {
+        const uint32_t le = le0 + t;
+        if (totS[t] >= 0) {
+            P.qtot[le] = badS[t] ? -1 : totS[t];
+            if (badS[t]) reject_pixel(P, (uint32_t)P.q_list[e0 + le]);
+        }
+        if (badS[t]) totS[t] = -1;
     }
     for (int i = t; i < kStageTile * kPredBins; i += 256) histS[i] = 0u;
     __syncthreads();
     // merged order out: slab row i, columns of the 8 entries; and the
     // distances between consecutive elements' per-step premultiplied colours
     // (the Eq. 1 operands), binned by log2 for the threshold prediction
+    int tmax = 0;
+#pragma unroll
+    for (int e = 0; e < kStageTile; ++e) tmax = max(tmax, totS[e]);
+    const int n_out = tmax * kStageTile;
     const size_t slab = (size_t)(le0 >> 6) * cap * 64 + (le0 & 63);
     for (int idx = t; idx < n_out; idx += 256) {
-        const uint32_t code = codeS[idx];
-        if (code == 0xffffu) continue;
         const int q = idx & 7, i = idx >> 3;
-        const int rs = baseS[code >> 6] + (int)(code & 63u);
+        if (i >= totS[q]) continue;
+        const int rs = src[q * cap + i];
         const float4 c = Ec[rs * kStageTile + q];
         P.stage_c[slab + (size_t)i * 64 + q] = c;
         P.stage_d[slab + (size_t)i * 64 + q] = Ed[rs * kStageTile + q];
         if (i > 0) {
-            const uint32_t pc = codeS[idx - kStageTile];
-            const float4 c0 = Ec[(baseS[pc >> 6] + (int)(pc & 63u)) * kStageTile + q];
+            const float4 c0 = Ec[src[q * cap + i - 1] * kStageTile + q];
             const float d0 = c.x * c.w - c0.x * c0.w, d1 = c.y * c.w - c0.y * c0.w, d2 = c.z * c.w - c0.z * c0.w;
             const float l2 = 0.5f * hw_log2(d0 * d0 + d1 * d1 + d2 * d2);
             const float x = (l2 - kPredLo) * (kPredBins / (kPredHi - kPredLo));
@@ -1327,8 +1268,8 @@ __global__ __launch_bounds__(1024) void order_sort_kernel(CompParams P, uint32_t
 uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix)
 {
     if (seq_cap > kOrderedMaxCap) return 0;
-    const size_t per = (size_t)seq_cap * (sizeof(float4) + sizeof(float2) + sizeof(uint16_t)) + sizeof(int) +
-                       sizeof(float) + kPredBins * sizeof(uint16_t);
+    const size_t per = (size_t)seq_cap * (sizeof(float4) + sizeof(float2)) + sizeof(int) + sizeof(float) +
+                       kPredBins * sizeof(uint16_t);
     size_t c = bytes / per;
     const size_t all = ((size_t)npix + 63) & ~(size_t)63;
     c = std::min(c, all) & ~(size_t)63;
@@ -1339,14 +1280,18 @@ size_t ordered_ws_bytes(int seq_cap, uint32_t chunk)
 {
     const size_t c = chunk;
     const size_t stage = c * seq_cap * (sizeof(float4) + sizeof(float2));
-    const size_t seq = (c * seq_cap * sizeof(uint16_t) + 255) & ~(size_t)255;
     const size_t tot = (c * sizeof(int) + 255) & ~(size_t)255;
     const size_t gh = (c * sizeof(float) + 255) & ~(size_t)255;
     const size_t ft = c * kPredBins * sizeof(uint16_t);
-    return stage + seq + tot + gh + ft;
+    return stage + tot + gh + ft;
 }
 
-static size_t stage_lds_bytes(int seq_cap) { return (size_t)seq_cap * kStageTile * (sizeof(float4) + sizeof(float2)); }
+// Dynamic LDS of merge_stage_kernel: the tile's elements and the two merge
+// buffers of element rows.
+static size_t stage_lds_bytes(int seq_cap)
+{
+    return (size_t)seq_cap * kStageTile * (sizeof(float4) + sizeof(float2) + 2 * sizeof(uint16_t));
+}
 
 // Grids of the persistent ordered-merge kernels: enough blocks to fill the
 // device (and no more than the chunk has work for).
@@ -1358,12 +1303,7 @@ static unsigned ord_grid(const CompParams& P, uint32_t units, int per_cu)
 static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s)
 {
     const uint32_t c = P.chunk;
-    const size_t lds_ord = (size_t)kOrdEntries * P.seq_cap * sizeof(float);
-    const unsigned g1 = ord_grid(P, c / kOrdEntries, 16), g2 = ord_grid(P, c / kStageTile, 4);
-    if (P.k <= 16)
-        hipLaunchKernelGGL(merge_order_kernel<4>, dim3(g1), dim3(64), lds_ord, s, P, e0);
-    else
-        hipLaunchKernelGGL(merge_order_kernel<8>, dim3(g1), dim3(64), lds_ord, s, P, e0);
+    const unsigned g2 = ord_grid(P, c / kStageTile, 4);
     hipLaunchKernelGGL(merge_stage_kernel, dim3(g2), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
     // the MLP's log2 threshold for every entry of the chunk (entries past
     // the queue get one too, unused)

@@ -133,12 +133,10 @@ struct CompParams {
     int* q_list;              // [npix] pixels left to the general merge
     int* q_count;             // their number
     // optional ordered general merge, in chunks of `chunk` queue entries
-    // (a multiple of 64): the merge order of each entry's lists, then its
-    // merged list staged for the re-segmentation scans; per group of 64
-    // entries a slab of seq_cap * 64 elements, entry t's element i at
-    // [i * 64 + t]
+    // (a multiple of 64): each entry's merged list staged for the
+    // re-segmentation scans; per group of 64 entries a slab of seq_cap * 64
+    // elements, entry t's element i at [i * 64 + t]
     uint32_t chunk;           // 0: no staging (merge sequence in LDS)
-    uint16_t* seq;            // [chunk / 8][seq_cap][8]: input << 6 | slot
     int* qtot;                // [chunk]: merged-list length (-1: rejected)
     float* ghat;              // [chunk]: predicted threshold (speculation only; NULL: none),
                               // as log2 when predicted by the MLP (mlp_wb set)
