@@ -453,16 +453,22 @@ __device__ inline void reject_pixel(const CompParams& P, uint32_t p)
     if (P.out_gamma) P.out_gamma[p] = 0.0f;
 }
 
-// Levels of the compositing bisection its first scan speculates on: along
-// the path toward a predicted threshold where there is one (the staged
-// general merge), else along the all-feasible path gmax/2, gmax/4, ... (on
-// the FHD frame the composited threshold has median 2^-3.9).  A wavefront
-// runs as many scans as its slowest lane: with four levels the predicted
-// path holds for nearly every lane of the dense interleaved frames, so the
-// wave's lanes go on together with three two-level scans; six levels save a
-// scan on most lanes but their rare mispredicted lanes cost their waves two
-// more (measured 8% slower on the 16 x 20 frame).
-constexpr int kFirstLevels = 4;
+// Levels of the compositing bisection its first scan speculates on.  With a
+// predicted threshold (the staged general merge) the scan follows the path
+// toward it for four levels: a wavefront runs as many scans as its slowest
+// lane, and with four levels the predicted path holds for nearly every lane
+// of the dense interleaved frames, so the wave's lanes go on together with
+// three two-level scans; six levels save a scan on most lanes but their rare
+// mispredicted lanes cost their waves two more (measured 8% slower on the
+// 16 x 20 frame).  Without one (depth-disjoint lists) it follows the
+// all-feasible path gmax/2, gmax/4, ... for six levels: on the FHD frame the
+// composited threshold has median 2^-3.9, so the first infeasible level is
+// mostly the fifth (6% faster than four levels there, 2% slower on the large
+// frame's shorter lists).  The general merge without staging (batches, the
+// allocation-free entry point) has no prediction and interleaved lists,
+// whose thresholds are large: four levels on the all-feasible path.
+template <typename R> struct FirstLevels { static constexpr int L = 4; };
+template <> struct FirstLevels<CatReader> { static constexpr int L = 6; };
 
 // The rest of the bisection from bracket [lo, hi] after `level` levels:
 // scans of two levels (the midpoint m and both of the next level's), one of
@@ -564,7 +570,7 @@ __device__ bool resegment(const CompParams& P, const R& rd0, int total, uint32_t
         // path (predicted feasible iff the midpoint is at least ghat),
         // replayed up to the first level decided otherwise (this scan also
         // validates the list)
-        constexpr int L = kFirstLevels;
+        constexpr int L = FirstLevels<R>::L;
         float gg[L];
         bool pf[L];
         int cg[L];
