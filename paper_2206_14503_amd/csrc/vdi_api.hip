@@ -255,7 +255,9 @@ static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, 
     const size_t lds = composite_lds_bytes(k, seq_cap, false);
     const int per_cu = std::max(1, std::min<int>((int)((160 * 1024) / (lds + 64)), 28));
     W.grid = std::max<size_t>(1, std::min<size_t>((size_t)ctx->num_cus * per_cu, nblk));
-    W.qbytes = ((npix + 64) * sizeof(int) + 255) & ~(size_t)255;
+    // counters and queue; staged: the deferral list (pixel, levels, bracket)
+    W.qbytes = (((npix + 64) + (staged ? 2 * npix : 0)) * sizeof(int) + (staged ? npix * sizeof(float2) : 0) + 255) &
+               ~(size_t)255;
     W.obytes = (2 * nblk * sizeof(uint32_t) + 255) & ~(size_t)255;
     W.chunk = staged ? ordered_chunk(seq_cap, (size_t)2 << 30, (uint32_t)npix) : 0u;
     W.nbuf = W.chunk == 0 ? 0 : (W.chunk < npix ? 2 : 1);
@@ -272,6 +274,8 @@ static void composite_ordered(CompParams& P, char* base, uint32_t chunk)
     P.stage_c = (float4*)base;
     P.stage_d = (float2*)(base + c * cap * sizeof(float4));
     char* q = base + c * cap * (sizeof(float4) + sizeof(float2));
+    P.seq = (uint16_t*)q;
+    q += (c * cap * sizeof(uint16_t) + 255) & ~(size_t)255;
     P.qtot = (int*)q;
     q += (c * sizeof(int) + 255) & ~(size_t)255;
     P.ghat = (float*)q;
@@ -405,12 +409,20 @@ static vdi_status composite_params(vdi_ctx* ctx, const vdi_t* in, int k, const v
     return VDI_OK;
 }
 
-// The composite's queue ([64] counter words, then [npix] pixels) and block
-// order ([nblk] order, [nblk] bucket) at base; qbytes as composite_ws gives.
-static void composite_queues(CompParams& P, char* base, size_t qbytes)
+// The composite's queue ([64] counter words, then [npix] pixels), with
+// `staged` the deferral list after it ([npix] pixels, [npix] levels, [npix]
+// brackets; its counter the second word), and the block order ([nblk]
+// order, [nblk] bucket) at base; qbytes as composite_ws gives.
+static void composite_queues(CompParams& P, char* base, size_t qbytes, bool staged)
 {
     P.q_count = (int*)base;
     P.q_list = (int*)base + 64;
+    if (staged) {
+        P.dq_count = (int*)base + 1;
+        P.dq_pix = P.q_list + P.npix;
+        P.dq_lv = P.dq_pix + P.npix;
+        P.dq_br = (float2*)(P.dq_lv + P.npix);
+    }
     // slot-major inputs only: a block of compact inputs reads one stretch of
     // each input, next to its neighbours' stretches, and loses that locality
     // out of image order (measured slower)
@@ -691,7 +703,7 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     const CompWs W = composite_ws(ctx, P.npix, k, P.seq_cap, true);
     if ((st = ensure_scratch(ctx, W.total)) != VDI_OK) return st;
     char* base = ws_base(ctx);
-    composite_queues(P, base, W.qbytes);
+    composite_queues(P, base, W.qbytes, W.chunk != 0);
     // the ordered merge's buffers after the queue and the block order
     char* obase = base + W.qbytes + W.obytes;
     if (W.chunk) composite_ordered(P, obase, W.chunk);
@@ -723,7 +735,7 @@ vdi_status vdi_composite_noalloc(vdi_ctx* ctx, const vdi_t* in, int k, const vdi
     if (need > kStaticScratchBytes)
         return fail(VDI_E_UNSUPPORTED, "%u pixels need %zu bytes of scratch, more than the fixed %zu", P.npix, need,
                     kStaticScratchBytes);
-    composite_queues(P, (char*)ctx->static_scratch, W.qbytes);
+    composite_queues(P, (char*)ctx->static_scratch, W.qbytes, false);
     launch_composite(P, (int)W.grid, (hipStream_t)stream);
     return launched();
 }

@@ -527,11 +527,15 @@ __device__ inline void finish_pixel(const CompParams& P, uint32_t p, int count, 
 // the midpoints of its first levels along the path toward `ghat` (a predicted
 // threshold; 0 or NaN: the all-feasible path), and its decisions are replayed
 // up to the first one the prediction got wrong; later scans carry two levels.
-// The result is the bisection's whatever ghat is.  With VALIDATE the first
-// pass checks the elements and returns false, with the pixel's output
-// incomplete, if one fails.
+// The result is the bisection's whatever ghat is.  With `defer`, a pixel
+// whose first scan left the predicted path before its last level goes on the
+// deferral list with its bracket instead (it would keep its wavefront busy
+// for more scans than its wave-mates need).  With VALIDATE the first pass
+// checks the elements and returns false, with the pixel's output incomplete,
+// if one fails.
 template <bool VALIDATE, typename R>
-__device__ bool resegment(const CompParams& P, const R& rd0, int total, uint32_t p, float ghat = 0.0f)
+__device__ bool resegment(const CompParams& P, const R& rd0, int total, uint32_t p, float ghat = 0.0f,
+                          bool defer = false)
 {
     COut o{P.out_color, P.out_depth, p, P.npix, P.out_n};
     int count;
@@ -592,6 +596,16 @@ __device__ bool resegment(const CompParams& P, const R& rd0, int total, uint32_t
             if (feasible) hi = m;
             else lo = m;
             if (feasible != pf[l]) break;
+        }
+        if (defer) {
+            const bool dfr = !bad && level < lim;
+            const int pos = wave_append(P.dq_count, dfr);
+            if (dfr) {
+                P.dq_pix[pos] = (int)p;
+                P.dq_br[pos] = make_float2(lo, hi);
+                P.dq_lv[pos] = level;
+                return true;
+            }
         }
         count = 0;
         if (!bad) count = bisect_finish(P, rd0, total, p, lo, hi, level, gm);
@@ -835,32 +849,18 @@ __device__ inline void merge_path(const uint16_t* src, uint16_t* dst, const floa
     }
 }
 
-// One tile of 8 chunk entries by a block of 256 threads.
-__device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile, unsigned char* lds_raw,
-                                 StageLds& S, uint32_t nq)
+// One tile of 8 chunk entries by a block of 256 threads: the counts
+// (validated), the inputs' bases and each entry's count prefix.  Entries past
+// the queue have no elements (length -1).
+__device__ void tile_setup(const CompParams& P, uint32_t e0, uint32_t le0, StageLds& S, uint32_t nq)
 {
-    int(&cntS)[kStageTile][kMaxInputs] = S.cntS;
-    uint32_t(&ebS)[kStageTile][kMaxInputs] = S.ebS;
-    int(&preS)[kStageTile][kMaxInputs + 1] = S.preS;
-    int* baseS = S.baseS;
-    uint8_t* rinS = S.rinS;
-    int* totS = S.totS;
-    int* badS = S.badS;
-    uint32_t* histS = S.histS;
     const int t = threadIdx.x;
-    const int cap = P.seq_cap;
-    float4* Ec = (float4*)lds_raw;                         // [cap][8]
-    float2* Ed = (float2*)(lds_raw + (size_t)cap * kStageTile * sizeof(float4));
-    uint16_t* mb0 = (uint16_t*)(lds_raw + (size_t)cap * kStageTile * (sizeof(float4) + sizeof(float2)));  // [8][cap]
-    uint16_t* mb1 = mb0 + (size_t)cap * kStageTile;
-    const uint32_t le0 = tile * kStageTile;
-    if (t < kStageTile) badS[t] = 0;
+    if (t < kStageTile) S.badS[t] = 0;
     if (t < P.k) {
         const int b = input_base(P, t);
-        baseS[t] = b;
-        for (int s_ = 0; s_ < P.in[t].max_n; ++s_) rinS[b + s_] = (uint8_t)t;
+        S.baseS[t] = b;
+        for (int s_ = 0; s_ < P.in[t].max_n; ++s_) S.rinS[b + s_] = (uint8_t)t;
     }
-    // counts, validated (an entry past the queue has none)
     if (t < kStageTile * P.k) {
         const int q = t / P.k, r = t - q * P.k;
         const uint32_t le = le0 + q;
@@ -874,28 +874,35 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
             const uint64_t last = in.compact ? (uint64_t)eb + (uint64_t)(c > 0 ? c : 0)
                                              : (uint64_t)(c > 0 ? c : 0) * P.npix;
             if (c < 0 || c > in.max_n || last > in.capacity) {
-                atomicOr(&badS[q], 1);
+                atomicOr(&S.badS[q], 1);
                 c = 0;
             }
         }
-        cntS[q][r] = c;
-        ebS[q][r] = eb;
+        S.cntS[q][r] = c;
+        S.ebS[q][r] = eb;
     }
     __syncthreads();
     if (t < kStageTile) {
         const uint32_t le = le0 + t;
         int acc = 0;
         for (int r = 0; r < P.k; ++r) {
-            preS[t][r] = acc;
-            acc += cntS[t][r];
+            S.preS[t][r] = acc;
+            acc += S.cntS[t][r];
         }
-        preS[t][P.k] = acc;
-        totS[t] = (le < P.chunk && e0 + le < nq) ? acc : -1;
+        S.preS[t][P.k] = acc;
+        S.totS[t] = (le < P.chunk && e0 + le < nq) ? acc : -1;
     }
-    // elements into LDS: (slot row, entry) with the entry fastest, so the 8
-    // entries of a row read one line of each slot-major plane; each thread
-    // keeps kStageBatch loads in flight
-    const int n_el = cap * kStageTile;
+    __syncthreads();
+}
+
+// The tile's elements into LDS, (slot row, entry) with the entry fastest, so
+// the 8 entries of a row read whole lines of each slot-major plane (the
+// colours only with COLOR); each thread keeps kStageBatch loads in flight.
+template <bool COLOR>
+__device__ void tile_load(const CompParams& P, const StageLds& S, float4* Ec, float2* Ed)
+{
+    const int t = threadIdx.x;
+    const int n_el = P.seq_cap * kStageTile;
     for (int b0 = 0; b0 < n_el; b0 += 256 * kStageBatch) {
         float4 c[kStageBatch];
         float2 d[kStageBatch];
@@ -906,12 +913,12 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
             v[u] = false;
             if (idx < n_el) {
                 const int q = idx & 7, rs = idx >> 3;
-                const int r = rinS[rs];
-                const int s_ = rs - baseS[r];
-                if (s_ < cntS[q][r]) {
+                const int r = S.rinS[rs];
+                const int s_ = rs - S.baseS[r];
+                if (s_ < S.cntS[q][r]) {
                     const CompInput& in = P.in[r];
-                    const uint32_t e = ebS[q][r] + (uint32_t)s_ * (in.compact ? 1u : P.npix);
-                    c[u] = gload(in.color, e);
+                    const uint32_t e = S.ebS[q][r] + (uint32_t)s_ * (in.compact ? 1u : P.npix);
+                    if (COLOR) c[u] = gload(in.color, e);
                     d[u] = gload(in.depth, e);
                     v[u] = true;
                 }
@@ -921,30 +928,45 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
         for (int u = 0; u < kStageBatch; ++u) {
             if (v[u]) {
                 const int idx = b0 + t + 256 * u;
-                Ec[idx] = c[u];
+                if (COLOR) Ec[idx] = c[u];
                 Ed[idx] = d[u];
             }
         }
     }
     __syncthreads();
-    // validation (finite depths, f < b, fronts non-decreasing along each
-    // list) and the merge's initial runs: each input's rows in order
+}
+
+// Merge order of one tile: validation (finite depths, f < b, fronts
+// non-decreasing along each list), then each entry's lists merged in LDS by
+// a tree of pairwise merges (at level l the runs are the merged lists of
+// 2^(l-1) consecutive inputs; each run pair, lower inputs first, is merged by
+// kStageLanes / (number of pairs) threads of its entry).  Writes the merged
+// element rows (input base + slot) and the entries' lengths (-1: rejected).
+__device__ void merge_order_tile(const CompParams& P, uint32_t e0, uint32_t tile, unsigned char* lds_raw,
+                                 StageLds& S, uint32_t nq)
+{
+    const int t = threadIdx.x;
+    const int cap = P.seq_cap;
+    float2* Ed = (float2*)lds_raw;                                           // [cap][8]
+    uint16_t* mb0 = (uint16_t*)(lds_raw + (size_t)cap * kStageTile * sizeof(float2));  // [8][cap]
+    uint16_t* mb1 = mb0 + (size_t)cap * kStageTile;
+    const uint32_t le0 = tile * kStageTile;
+    tile_setup(P, e0, le0, S, nq);
+    tile_load<false>(P, S, nullptr, Ed);
+    const int n_el = cap * kStageTile;
     for (int idx = t; idx < n_el; idx += 256) {
         const int q = idx & 7, rs = idx >> 3;
-        const int r = rinS[rs];
-        const int s_ = rs - baseS[r];
-        if (s_ < cntS[q][r]) {
+        const int r = S.rinS[rs];
+        const int s_ = rs - S.baseS[r];
+        if (s_ < S.cntS[q][r]) {
             const float2 d = Ed[idx];
             bool ok = isfinite(d.x) & isfinite(d.y) & (d.x < d.y);
             if (s_ > 0) ok &= d.x >= Ed[idx - kStageTile].x;
-            if (!ok) atomicOr(&badS[q], 1);
-            mb0[q * cap + preS[q][r] + s_] = (uint16_t)rs;
+            if (!ok) atomicOr(&S.badS[q], 1);
+            mb0[q * cap + S.preS[q][r] + s_] = (uint16_t)rs;
         }
     }
     __syncthreads();
-    // pairwise merge tree: at level l the runs are the merged lists of
-    // 2^(l-1) consecutive inputs; each run pair (lower inputs first) is
-    // merged by kStageLanes / (number of pairs) threads of its entry
     uint16_t* src = mb0;
     {
         const int q = t / kStageLanes, j = t - q * kStageLanes;
@@ -956,42 +978,85 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
             const int tpm = kStageLanes / pairs;
             const int m = j / tpm, jj = j - m * tpm;
             const int r0 = m * 2 * w;
-            const int a0 = preS[q][min(r0, P.k)], a1 = preS[q][min(r0 + w, P.k)], b1 = preS[q][min(r0 + 2 * w, P.k)];
-            if (totS[q] > 0) merge_path(src + q * cap, dst + q * cap, Ed, q, a0, a1, b1, jj, tpm);
+            const int a0 = S.preS[q][min(r0, P.k)], a1 = S.preS[q][min(r0 + w, P.k)];
+            const int b1 = S.preS[q][min(r0 + 2 * w, P.k)];
+            if (S.totS[q] > 0) merge_path(src + q * cap, dst + q * cap, Ed, q, a0, a1, b1, jj, tpm);
             __syncthreads();
             uint16_t* tmp = src;
             src = dst;
             dst = tmp;
         }
     }
-    // the merged rows are in src; the entries' lengths (-1: rejected)
     if (t < kStageTile) {
         const uint32_t le = le0 + t;
-        if (totS[t] >= 0) {
-            P.qtot[le] = badS[t] ? -1 : totS[t];
-            if (badS[t]) reject_pixel(P, (uint32_t)P.q_list[e0 + le]);
+        if (S.totS[t] >= 0) {
+            P.qtot[le] = S.badS[t] ? -1 : S.totS[t];
+            if (S.badS[t]) reject_pixel(P, (uint32_t)P.q_list[e0 + le]);
         }
-        if (badS[t]) totS[t] = -1;
+    }
+    // the merged rows out: row i of the 8 entries in one 16-byte run
+    uint16_t* seq = P.seq + (size_t)(le0 >> 3) * cap * 8;
+    for (int idx = t; idx < n_el; idx += 256) {
+        const int q = idx & 7, i = idx >> 3;
+        if (i < S.totS[q]) seq[idx] = src[q * cap + i];
+    }
+    __syncthreads();   // the next tile reuses the LDS
+}
+
+// Staging of one tile: the elements into LDS in whole lines, then out to the
+// staging rows in merge order (row i of the 8 entries are adjacent columns of
+// a slab row), with the distances between consecutive elements' per-step
+// premultiplied colours (the Eq. 1 operands) binned by log2 for the
+// threshold prediction.
+__device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile, unsigned char* lds_raw,
+                                 StageLds& S, uint32_t nq)
+{
+    const int t = threadIdx.x;
+    const int cap = P.seq_cap;
+    float4* Ec = (float4*)lds_raw;                         // [cap][8]
+    float2* Ed = (float2*)(lds_raw + (size_t)cap * kStageTile * sizeof(float4));
+    uint16_t* rowS = (uint16_t*)(lds_raw + (size_t)cap * kStageTile * (sizeof(float4) + sizeof(float2)));  // [cap][8]
+    uint32_t* histS = S.histS;
+    int* totS = S.totS;
+    const uint32_t le0 = tile * kStageTile;
+    tile_setup(P, e0, le0, S, nq);
+    // lengths as the order kernel found them (-1: rejected or past the queue)
+    if (t < kStageTile) {
+        const uint32_t le = le0 + t;
+        totS[t] = (le < P.chunk && e0 + le < nq) ? P.qtot[le] : -1;
     }
     for (int i = t; i < kStageTile * kPredBins; i += 256) histS[i] = 0u;
-    __syncthreads();
-    // merged order out: slab row i, columns of the 8 entries; and the
-    // distances between consecutive elements' per-step premultiplied colours
-    // (the Eq. 1 operands), binned by log2 for the threshold prediction
+    tile_load<true>(P, S, Ec, Ed);
     int tmax = 0;
 #pragma unroll
-    for (int e = 0; e < kStageTile; ++e) tmax = max(tmax, totS[e]);
+    for (int q = 0; q < kStageTile; ++q) tmax = max(tmax, totS[q]);
     const int n_out = tmax * kStageTile;
+    const uint16_t* seq = P.seq + (size_t)(le0 >> 3) * cap * 8;
+    for (int b0 = 0; b0 < n_out; b0 += 256 * kStageBatch) {
+        uint16_t row[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int idx = b0 + t + 256 * u;
+            const int q = idx & 7, i = idx >> 3;
+            row[u] = (idx < n_out && i < totS[q]) ? seq[idx] : (uint16_t)0xffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int idx = b0 + t + 256 * u;
+            if (idx < n_out) rowS[idx] = row[u];
+        }
+    }
+    __syncthreads();
     const size_t slab = (size_t)(le0 >> 6) * cap * 64 + (le0 & 63);
     for (int idx = t; idx < n_out; idx += 256) {
+        const int rs = rowS[idx];
+        if (rs == 0xffff) continue;
         const int q = idx & 7, i = idx >> 3;
-        if (i >= totS[q]) continue;
-        const int rs = src[q * cap + i];
         const float4 c = Ec[rs * kStageTile + q];
         P.stage_c[slab + (size_t)i * 64 + q] = c;
         P.stage_d[slab + (size_t)i * 64 + q] = Ed[rs * kStageTile + q];
         if (i > 0) {
-            const float4 c0 = Ec[src[q * cap + i - 1] * kStageTile + q];
+            const float4 c0 = Ec[rowS[idx - kStageTile] * kStageTile + q];
             const float d0 = c.x * c.w - c0.x * c0.w, d1 = c.y * c.w - c0.y * c0.w, d2 = c.z * c.w - c0.z * c0.w;
             const float l2 = 0.5f * hw_log2(d0 * d0 + d1 * d1 + d2 * d2);
             const float x = (l2 - kPredLo) * (kPredBins / (kPredHi - kPredLo));
@@ -1035,6 +1100,16 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
 
 // Persistent: blocks take tiles of 8 chunk entries until the chunk or the
 // queue ends.
+__global__ __launch_bounds__(256) void merge_order_kernel(CompParams P, uint32_t e0)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ StageLds S;
+    const uint32_t nq = (uint32_t)*P.q_count;
+    const uint32_t tiles = P.chunk / kStageTile;
+    for (uint32_t tl = blockIdx.x; tl < tiles && e0 + tl * kStageTile < nq; tl += gridDim.x)
+        merge_order_tile(P, e0, tl, lds_raw, S, nq);
+}
+
 __global__ __launch_bounds__(256) void merge_stage_kernel(CompParams P, uint32_t e0)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1060,8 +1135,16 @@ __global__ __launch_bounds__(64) void composite_staged_kernel(CompParams P, uint
         const uint32_t p = (uint32_t)P.q_list[e0 + le];
         const size_t slab = (size_t)g * P.seq_cap * 64;
         const StageReader rd{P.stage_c + slab, P.stage_d + slab, (uint32_t)t, (uint32_t)t};
+        if (P.rs_br) {
+            // the deferred round: the rest of the bisection from the bracket
+            const float2 br = P.rs_br[e0 + le];
+            float gm;
+            const int c = bisect_finish(P, rd, tot, p, br.x, br.y, P.rs_lv[e0 + le], gm);
+            finish_pixel(P, p, c, gm);
+            continue;
+        }
         const float gh = P.ghat ? (P.mlp_wb ? hw_exp2(P.ghat[le]) : P.ghat[le]) : 0.0f;
-        resegment<false>(P, rd, tot, p, gh);
+        resegment<false>(P, rd, tot, p, gh, P.dq_count != nullptr);
     }
 }
 
@@ -1088,6 +1171,7 @@ __global__ void queue_all_kernel(CompParams P)
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < P.npix) P.q_list[i] = (int)i;
     if (i == 0) *P.q_count = (int)P.npix;
+    if (i == 0 && P.dq_count) *P.dq_count = 0;
 }
 
 // Depth-disjoint path over all pixels; the others are queued.
@@ -1106,14 +1190,14 @@ __global__ __launch_bounds__(64) void composite_cat_kernel(CompParams P)
 }
 
 // General merge over the queued pixels (grid-stride).
-__global__ __launch_bounds__(64) void composite_queue_kernel(CompParams P)
+__global__ __launch_bounds__(64) void composite_queue_kernel(CompParams P, uint32_t first)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int t = threadIdx.x;
     setup_inputs(P, lds_raw, t);
     __syncthreads();
     const uint32_t n = (uint32_t)*P.q_count;
-    for (uint32_t idx = blockIdx.x * kWave + t; idx < n; idx += gridDim.x * kWave)
+    for (uint32_t idx = first + blockIdx.x * kWave + t; idx < n; idx += gridDim.x * kWave)
         composite_pixel(P, lds_raw, t, (uint32_t)P.q_list[idx]);
 }
 
@@ -1274,8 +1358,8 @@ __global__ __launch_bounds__(1024) void order_sort_kernel(CompParams P, uint32_t
 uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix)
 {
     if (seq_cap > kOrderedMaxCap) return 0;
-    const size_t per = (size_t)seq_cap * (sizeof(float4) + sizeof(float2)) + sizeof(int) + sizeof(float) +
-                       kPredBins * sizeof(uint16_t);
+    const size_t per = (size_t)seq_cap * (sizeof(float4) + sizeof(float2) + sizeof(uint16_t)) + sizeof(int) +
+                       sizeof(float) + kPredBins * sizeof(uint16_t);
     size_t c = bytes / per;
     const size_t all = ((size_t)npix + 63) & ~(size_t)63;
     c = std::min(c, all) & ~(size_t)63;
@@ -1286,17 +1370,23 @@ size_t ordered_ws_bytes(int seq_cap, uint32_t chunk)
 {
     const size_t c = chunk;
     const size_t stage = c * seq_cap * (sizeof(float4) + sizeof(float2));
+    const size_t seq = (c * seq_cap * sizeof(uint16_t) + 255) & ~(size_t)255;
     const size_t tot = (c * sizeof(int) + 255) & ~(size_t)255;
     const size_t gh = (c * sizeof(float) + 255) & ~(size_t)255;
     const size_t ft = c * kPredBins * sizeof(uint16_t);
-    return stage + tot + gh + ft;
+    return stage + seq + tot + gh + ft;
 }
 
-// Dynamic LDS of merge_stage_kernel: the tile's elements and the two merge
-// buffers of element rows.
+// Dynamic LDS of merge_order_kernel (the tile's depths and the two merge
+// buffers of element rows) and of merge_stage_kernel (the tile's elements
+// and the merged rows).
+static size_t order_lds_bytes(int seq_cap)
+{
+    return (size_t)seq_cap * kStageTile * (sizeof(float2) + 2 * sizeof(uint16_t));
+}
 static size_t stage_lds_bytes(int seq_cap)
 {
-    return (size_t)seq_cap * kStageTile * (sizeof(float4) + sizeof(float2) + 2 * sizeof(uint16_t));
+    return (size_t)seq_cap * kStageTile * (sizeof(float4) + sizeof(float2) + sizeof(uint16_t));
 }
 
 // Grids of the persistent ordered-merge kernels: enough blocks to fill the
@@ -1309,7 +1399,8 @@ static unsigned ord_grid(const CompParams& P, uint32_t units, int per_cu)
 static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s)
 {
     const uint32_t c = P.chunk;
-    const unsigned g2 = ord_grid(P, c / kStageTile, 4);
+    const unsigned g1 = ord_grid(P, c / kStageTile, 8), g2 = ord_grid(P, c / kStageTile, 4);
+    hipLaunchKernelGGL(merge_order_kernel, dim3(g1), dim3(256), order_lds_bytes(P.seq_cap), s, P, e0);
     hipLaunchKernelGGL(merge_stage_kernel, dim3(g2), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
     // the MLP's log2 threshold for every entry of the chunk (entries past
     // the queue get one too, unused)
@@ -1321,38 +1412,85 @@ static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s)
 static void launch_resegment(const CompParams& P, uint32_t e0, hipStream_t s)
 {
     const uint32_t c = P.chunk;
-    hipLaunchKernelGGL(composite_staged_kernel, dim3(ord_grid(P, c / 64, 20)), dim3(64), 0, s, P, e0);
+    // two waves per SIMD: the order and staging kernels of the next chunk run
+    // beside these on the second stream and need registers of their own
+    // (four waves here leave them none: 6% slower on the 16 x 20 frame)
+    hipLaunchKernelGGL(composite_staged_kernel, dim3(ord_grid(P, c / 64, 8)), dim3(64), 0, s, P, e0);
 }
 
 // The ordered general merge over the queue, chunk by chunk (every kernel
 // reads the queue length on the device; entries past it exit at once).  With
 // two buffers, chunk c + 1 is ordered and staged on the second stream while
 // chunk c is re-segmented.
+// Deferred pixels beyond the deferred round's one chunk: the general merge
+// with its merge sequence in LDS, from the start (no staging, no bracket).
+static void launch_overflow(const CompParams& D, hipStream_t s)
+{
+    CompParams O = D;
+    O.rs_br = nullptr;
+    O.rs_lv = nullptr;
+    const size_t lds = composite_lds_bytes(O.k, O.seq_cap, false);
+    hipLaunchKernelGGL(composite_queue_kernel, dim3((unsigned)(O.num_cus * 2)), dim3(kWave), lds, s, O, O.chunk);
+}
+
+// Parameters of the deferred round: the deferral list as the queue, the
+// brackets as the entries' starting points, no further deferral.
+static CompParams deferred_round(const CompParams& P)
+{
+    CompParams D = P;
+    D.q_list = P.dq_pix;
+    D.q_count = P.dq_count;
+    D.rs_br = P.dq_br;
+    D.rs_lv = P.dq_lv;
+    D.dq_count = nullptr;
+    D.dq_pix = nullptr;
+    D.dq_br = nullptr;
+    D.dq_lv = nullptr;
+    return D;
+}
+
 static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync* sync)
 {
     const uint32_t c = P.chunk;
+    const uint32_t n = (P.npix + c - 1) / c;
+    // the queue in up to n chunks, then (with deferral) one chunk of the
+    // deferral list (every kernel reads its round's length on the device;
+    // deferred pixels are a few per hundred, and any beyond that chunk are
+    // composited again from the start by the general merge without staging)
+    const uint32_t total = n + (P.dq_count ? 1u : 0u);
     if (!sync || !sync->P2) {
-        for (uint32_t e0 = 0; e0 < P.npix; e0 += c) {
-            launch_order_stage(P, e0, s);
-            launch_resegment(P, e0, s);
+        for (uint32_t i = 0; i < n; ++i) {
+            launch_order_stage(P, i * c, s);
+            launch_resegment(P, i * c, s);
+        }
+        if (P.dq_count) {
+            const CompParams D = deferred_round(P);
+            launch_order_stage(D, 0, s);
+            launch_resegment(D, 0, s);
+            launch_overflow(D, s);
         }
         return;
     }
-    const CompParams* buf[2] = {&P, sync->P2};
-    const uint32_t n = (P.npix + c - 1) / c;
+    const CompParams D1 = P.dq_count ? deferred_round(P) : P, D2 = P.dq_count ? deferred_round(*sync->P2) : P;
+    const CompParams* buf[2][2] = {{&P, sync->P2}, {&D1, &D2}};
     // fork: the second stream starts after the caller's work so far
     (void)hipEventRecord(sync->ev[0], s);
     (void)hipStreamWaitEvent(sync->aux, sync->ev[0], 0);
-    for (uint32_t i = 0; i < n; ++i) {
+    for (uint32_t i = 0; i < total; ++i) {
         const int b = (int)(i & 1u);
+        const int rd = i < n ? 0 : 1;
         // staging chunk i into buffer b waits until chunk i - 2 (same buffer)
-        // has been re-segmented
+        // has been re-segmented; the deferred round's first staging also
+        // until the last chunk of the queue has (it completes the list)
         if (i >= 2) (void)hipStreamWaitEvent(sync->aux, sync->ev[3 + b], 0);
-        launch_order_stage(*buf[b], i * c, sync->aux);
+        if (i == n && n >= 1) (void)hipStreamWaitEvent(sync->aux, sync->ev[3 + ((n - 1) & 1u)], 0);
+        const uint32_t e0 = (i - (uint32_t)rd * n) * c;
+        launch_order_stage(*buf[rd][b], e0, sync->aux);
         (void)hipEventRecord(sync->ev[1 + b], sync->aux);
         // re-segmenting chunk i waits for its staging
         (void)hipStreamWaitEvent(s, sync->ev[1 + b], 0);
-        launch_resegment(*buf[b], i * c, s);
+        launch_resegment(*buf[rd][b], e0, s);
+        if (rd) launch_overflow(*buf[rd][b], s);
         (void)hipEventRecord(sync->ev[3 + b], s);
     }
     // join: the second stream's work precedes everything after this call
@@ -1374,7 +1512,8 @@ void launch_composite(const CompParams& P, int grid_general, hipStream_t s, cons
         }
         return;
     }
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(1), 0, s, (uint32_t*)P.q_count, 0u);
+    // the queue's counter, and the deferral list's in the word after it
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(P.dq_count ? 2 : 1), 0, s, (uint32_t*)P.q_count, 0u);
     // Compact inputs: each lane walks its own contiguous list, reading 16 of
     // every 128 bytes per step, so a line is reused over eight steps only if
     // it stays cached; fewer resident waves (the general merge's LDS
@@ -1390,7 +1529,7 @@ void launch_composite(const CompParams& P, int grid_general, hipStream_t s, cons
     if (P.chunk)
         launch_ordered(P, s, sync);
     else
-        hipLaunchKernelGGL(composite_queue_kernel, dim3(g2), dim3(kWave), lds, s, P);
+        hipLaunchKernelGGL(composite_queue_kernel, dim3(g2), dim3(kWave), lds, s, P, 0u);
 }
 
 // ---------------------------------------------------------------- rendering

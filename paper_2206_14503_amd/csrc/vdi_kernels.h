@@ -137,6 +137,7 @@ struct CompParams {
     // re-segmentation scans; per group of 64 entries a slab of seq_cap * 64
     // elements, entry t's element i at [i * 64 + t]
     uint32_t chunk;           // 0: no staging (merge sequence in LDS)
+    uint16_t* seq;            // [chunk / 8][seq_cap][8]: merged element rows (input base + slot)
     int* qtot;                // [chunk]: merged-list length (-1: rejected)
     float* ghat;              // [chunk]: predicted threshold (speculation only; NULL: none),
                               // as log2 when predicted by the MLP (mlp_wb set)
@@ -147,6 +148,17 @@ struct CompParams {
     int num_cus;              // compute units of the device (grid sizes of the persistent kernels)
     float4* stage_c;
     float2* stage_d;
+    // deferral of the staged re-segmentation (NULL: none): a pixel whose
+    // first scan left the predicted path before its last level goes on this
+    // list with its bracket (lo, hi) and levels done, and a last round of
+    // chunks finishes those pixels together
+    int* dq_count;            // one word after q_count (cleared with it)
+    int* dq_pix;              // [npix]
+    float2* dq_br;            // [npix]
+    int* dq_lv;               // [npix]
+    // resume mode (that last round): entry e0 + le's bracket and levels
+    const float2* rs_br;
+    const int* rs_lv;
     // optional order of the 64-pixel blocks for the depth-disjoint pass
     // (longest merged list first), and its work space (a bucket per block)
     uint32_t* order;
