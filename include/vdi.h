@@ -186,7 +186,12 @@ const char *vdi_last_error(void);
  * bricks, layout of the outputs, tau_mode), VDI_OP_COMPOSITE (vdi_composite:
  * width, height, k inputs, in_max_n_sum = sum of the inputs' max_n),
  * VDI_OP_MLP_BACKWARD (vdi_mlp_backward: rows).  Other ops need none.  The
- * bytes depend on the device (its compute-unit count) but not on the data. */
+ * bytes depend on the device (its compute-unit count) but not on the data.
+ * For VDI_OP_COMPOSITE the size is the recommended one (the general merge
+ * stages up to 2 GiB of merged lists per chunk): a smaller caller workspace
+ * (vdi_ctx_set_workspace) makes vdi_composite stage in smaller chunks, down
+ * to 64 pixels, the queues still fitting beside them; below that it reports
+ * VDI_E_WORKSPACE.  Results do not depend on the chunk size. */
 typedef enum { VDI_OP_GENERATE = 0, VDI_OP_COMPOSITE = 1, VDI_OP_MLP_BACKWARD = 2 } vdi_op;
 typedef struct {
     int32_t op;              /* vdi_op */

@@ -248,7 +248,7 @@ struct CompWs {
     uint32_t chunk;
     int nbuf;          // ordered-merge buffers: 2 when the queue can span several chunks
 };
-static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, bool staged)
+static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, bool staged, size_t limit = 0)
 {
     CompWs W;
     const size_t nblk = (npix + 63) / 64;
@@ -263,6 +263,19 @@ static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, 
     W.nbuf = W.chunk == 0 ? 0 : (W.chunk < npix ? 2 : 1);
     W.buf = W.chunk ? ordered_ws_bytes(seq_cap, W.chunk) : 0;
     W.total = W.qbytes + W.obytes + W.nbuf * W.buf;
+    if (limit && W.chunk && W.total > limit && limit > W.qbytes + W.obytes + 2048) {
+        // a smaller caller workspace: the largest chunk two buffers of which
+        // fit beside the queues (down to 64 entries; below that the call
+        // reports VDI_E_WORKSPACE)
+        const size_t per_buf = (limit - W.qbytes - W.obytes) / 2 - 1024;
+        const uint32_t c = ordered_chunk(seq_cap, per_buf, (uint32_t)npix);
+        if (c >= 64) {
+            W.chunk = c;
+            W.nbuf = c < npix ? 2 : 1;
+            W.buf = ordered_ws_bytes(seq_cap, c);
+            W.total = W.qbytes + W.obytes + W.nbuf * W.buf;
+        }
+    }
     return W;
 }
 
@@ -700,7 +713,7 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     if (st != VDI_OK) return st;
     if (composite_lds_bytes(k, P.seq_cap, false) > 160 * 1024)
         return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", P.seq_cap);
-    const CompWs W = composite_ws(ctx, P.npix, k, P.seq_cap, true);
+    const CompWs W = composite_ws(ctx, P.npix, k, P.seq_cap, true, ctx->user_ws ? ctx->user_ws_bytes : 0);
     if ((st = ensure_scratch(ctx, W.total)) != VDI_OK) return st;
     char* base = ws_base(ctx);
     composite_queues(P, base, W.qbytes, W.chunk != 0);

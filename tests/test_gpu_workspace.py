@@ -48,15 +48,27 @@ def test_workspace_query_shapes(V):
 
 
 def test_too_small_workspace_is_reported(V):
+    """Below the queues and two minimal chunks the composite reports
+    VDI_E_WORKSPACE; just below the recommended size it stages in smaller
+    chunks and gives the same output."""
     dbr, cam, tf_d, step = _frame(V)
     need = V.workspace_size(V.OP_COMPOSITE, cam.width, cam.height, 2, in_max_n_sum=16)
     subs = V.generate(dbr, cam, tf_d, step, step, V.BISECT, 0.0, 8, 10)
-    small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
-    V.set_workspace(small)
+    ref = V.composite(subs, V.BISECT, 0.0, 8, 10)
+    tiny = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    V.set_workspace(tiny)
     try:
         with pytest.raises(V.VdiError) as e:
             V.composite(subs, V.BISECT, 0.0, 8, 10)
         assert e.value.status == -6
+    finally:
+        V.set_workspace(None)
+    near = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    V.set_workspace(near)
+    try:
+        out = V.composite(subs, V.BISECT, 0.0, 8, 10)
+        torch.cuda.synchronize()
+        assert _same(out, ref)
     finally:
         V.set_workspace(None)
 
@@ -147,5 +159,36 @@ def test_graph_capture_of_multi_chunk_general_merge(V):
             assert _same(out, ref), f"replay {rep} differs from the eager run"
         assert V.device_status() == 0
         del g
+    finally:
+        V.set_workspace(None)
+
+
+def test_small_workspace_stages_in_small_chunks(V):
+    """A caller workspace far below the recommended size: the general merge
+    stages in chunks of a few hundred pixels (hundreds of chunks, and more
+    deferred pixels than the deferred round's one chunk holds, so the rest go
+    to the unstaged general merge); the output equals the one with the
+    recommended workspace and the allocation-free path bit for bit."""
+    from paper_2206_14503_amd import synth
+    k, n, W, H = 16, 20, 256, 256
+    c, d, cnt = synth.dense_frame(k, n, W * H, seed=21)
+    ins = [V.VDI(W, H, n, 0.01, V.REGULAR, c[r], d[r], cnt[r]) for r in range(k)]
+    ref = V.composite(ins, V.BISECT, 0.0, n, 10)
+    alt = V.composite(ins, V.BISECT, 0.0, n, 10, noalloc=True)
+    torch.cuda.synchronize()
+    assert _same(alt, ref)
+    need = V.workspace_size(V.OP_COMPOSITE, W, H, k, in_max_n_sum=k * n)
+    # queues and block order (about 1.3 MB here) plus two chunks of 512
+    # entries (320 elements of 26 bytes and 76 bytes of per-entry data each)
+    small = 2 << 20
+    small += 2 * 512 * (320 * 26 + 76) + 8192
+    assert small < need // 4
+    ws = torch.empty(small, dtype=torch.uint8, device="cuda")
+    V.set_workspace(ws)
+    try:
+        out = V.composite(ins, V.BISECT, 0.0, n, 10)
+        torch.cuda.synchronize()
+        assert _same(out, ref)
+        assert V.device_status() == 0
     finally:
         V.set_workspace(None)
