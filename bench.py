@@ -534,6 +534,20 @@ def leg_learned_composite(args, result):
                                    **ev_}
     del ins, color, depth, count
     torch.cuda.empty_cache()
+    # the generated frames: the FHD frame's 8 slabs and the large volume's
+    # 16 bricks; only their pixels whose lists interleave in depth take the
+    # general merge, where the regressor steers
+    tf_d = torch.from_numpy(synth.transfer_function()).cuda()
+    for key, wl in (("fhd", synth.fhd(args.seed)), ("large_generated", synth.large(args.seed))):
+        vol = synth.workload_volume(wl, device="cuda")
+        dbr = vdi.device_bricks(vol, synth.brick_grid((wl.n, wl.n, wl.n), wl.grid))
+        cam_w = synth.camera_for(wl)
+        subs = vdi.generate(dbr, cam_w, tf_d, 1.0 / wl.n, 1.0 / wl.n, vdi.BISECT, 0.0, wl.max_n, wl.iters)
+        ev_w = learned.evaluate_composite(mlp, subs, wl.max_n, reps=5)
+        log(f"[bench] learned composite on {wl.name}: {ev_w}")
+        result["learned_composite"][key] = {"workload": wl.name, **ev_w}
+        del subs, dbr, vol
+        torch.cuda.empty_cache()
 
 
 # ---------------------------------------------------------------- batched composites

@@ -1402,10 +1402,10 @@ static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s)
     const unsigned g1 = ord_grid(P, c / kStageTile, 8), g2 = ord_grid(P, c / kStageTile, 4);
     hipLaunchKernelGGL(merge_order_kernel, dim3(g1), dim3(256), order_lds_bytes(P.seq_cap), s, P, e0);
     hipLaunchKernelGGL(merge_stage_kernel, dim3(g2), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
-    // the MLP's log2 threshold for every entry of the chunk (entries past
-    // the queue get one too, unused)
+    // the MLP's log2 threshold for the chunk's entries of the queue
     if (P.mlp_wb)
-        launch_mlp_fwd(P.mlp_wb, P.mlp_wf, P.feat, (int)c, nullptr, nullptr, P.num_cus * 3, P.ghat, nullptr, s);
+        launch_mlp_fwd(P.mlp_wb, P.mlp_wf, P.feat, (int)c, P.q_count, nullptr, P.num_cus * 3, P.ghat, nullptr, s,
+                       (int)e0);
 }
 
 // Re-segmentation of a staged chunk.

@@ -206,8 +206,9 @@ int mlp_act_floats();
 int mlp_rows_per_block();
 // rows: row count (an upper bound when rows_dev holds the count on the
 // device); out_idx: optional row -> output index map; max_blocks: grid cap
+// rows_dev (optional): a device count; the rows are then min(rows, *rows_dev - row_off).
 void launch_mlp_fwd(const uint16_t* wb, const float* wf, const uint16_t* x, int rows, const int* rows_dev,
-                    const int* out_idx, int max_blocks, float* y, float* acts, hipStream_t s);
+                    const int* out_idx, int max_blocks, float* y, float* acts, hipStream_t s, int row_off = 0);
 void launch_mlp_bwd(const uint16_t* wb, const uint16_t* x, const float* acts, const float* dy, int rows,
                     float* partial, float* grad, hipStream_t s);
 void launch_mlp_adam(float* wf, uint16_t* wb, const float* grad, float* m, float* v, float lr, float b1, float b2,

@@ -93,17 +93,20 @@ constexpr int kFwdRowsPerBlock = 4 * kFwdRowsPerWave;
 
 __global__ __launch_bounds__(256) void mlp_fwd_kernel(const uint16_t* __restrict__ wb, const float* __restrict__ wf,
                                                       const uint16_t* __restrict__ x, int rows_host,
-                                                      const int* __restrict__ rows_dev, const int* __restrict__ out_idx,
-                                                      float* __restrict__ y, float* __restrict__ acts)
+                                                      const int* __restrict__ rows_dev, int row_off,
+                                                      const int* __restrict__ out_idx, float* __restrict__ y,
+                                                      float* __restrict__ acts)
 {
     __shared__ __align__(16) uint16_t sW1[kHid * kIn];
     __shared__ __align__(16) uint16_t sW2[kHid * kHid];
+    // rows: rows_host, or those of the device count past row_off (at most rows_host)
+    const int rows = rows_dev ? max(0, min(rows_host, *rows_dev - row_off)) : rows_host;
+    if (blockIdx.x * kFwdRowsPerBlock >= rows) return;
     for (int e = threadIdx.x; e < kHid * kIn / 8; e += blockDim.x)
         ((uint4*)sW1)[e] = ((const uint4*)(wb + oW1))[e];
     for (int e = threadIdx.x; e < kHid * kHid / 8; e += blockDim.x)
         ((uint4*)sW2)[e] = ((const uint4*)(wb + oW2))[e];
     __syncthreads();
-    const int rows = rows_dev ? *rows_dev : rows_host;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
     const float b3 = wf[oB3];
     for (int base = blockIdx.x * kFwdRowsPerBlock; base < rows; base += gridDim.x * kFwdRowsPerBlock) {
@@ -442,11 +445,12 @@ int mlp_act_floats() { return kActFloats; }
 int mlp_rows_per_block() { return kRowsPerBlock; }
 
 void launch_mlp_fwd(const uint16_t* wb, const float* wf, const uint16_t* x, int rows, const int* rows_dev,
-                    const int* out_idx, int max_blocks, float* y, float* acts, hipStream_t s)
+                    const int* out_idx, int max_blocks, float* y, float* acts, hipStream_t s, int row_off)
 {
     int nb = (rows + kFwdRowsPerBlock - 1) / kFwdRowsPerBlock;
     nb = std::max(1, std::min(nb, max_blocks));
-    hipLaunchKernelGGL(mlp_fwd_kernel, dim3(nb), dim3(256), 0, s, wb, wf, x, rows, rows_dev, out_idx, y, acts);
+    hipLaunchKernelGGL(mlp_fwd_kernel, dim3(nb), dim3(256), 0, s, wb, wf, x, rows, rows_dev, row_off, out_idx, y,
+                       acts);
 }
 
 void launch_mlp_bwd(const uint16_t* wb, const uint16_t* x, const float* acts, const float* dy, int rows,
