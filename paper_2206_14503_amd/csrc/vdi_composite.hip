@@ -861,6 +861,7 @@ __device__ void tile_setup(const CompParams& P, uint32_t e0, uint32_t le0, Stage
         S.baseS[t] = b;
         for (int s_ = 0; s_ < P.in[t].max_n; ++s_) S.rinS[b + s_] = (uint8_t)t;
     }
+    __syncthreads();   // the flags are clear before any count sets one
     if (t < kStageTile * P.k) {
         const int q = t / P.k, r = t - q * P.k;
         const uint32_t le = le0 + q;
