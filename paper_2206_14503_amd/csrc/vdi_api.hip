@@ -252,7 +252,7 @@ static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, 
 {
     CompWs W;
     const size_t nblk = (npix + 63) / 64;
-    const size_t lds = composite_lds_bytes(k, seq_cap, false);
+    const size_t lds = composite_lds_bytes(k, seq_cap);
     const int per_cu = std::max(1, std::min<int>((int)((160 * 1024) / (lds + 64)), 28));
     W.grid = std::max<size_t>(1, std::min<size_t>((size_t)ctx->num_cus * per_cu, nblk));
     // counters and queue; staged: the deferral list (pixel, levels, bracket)
@@ -531,7 +531,7 @@ vdi_status vdi_workspace_size(vdi_ctx* ctx, const vdi_shape_t* shape, size_t* by
             return fail(VDI_E_INVALID, "bad width/height/k");
         if (shape->in_max_n_sum < shape->k || shape->in_max_n_sum > shape->k * VDI_MAX_N)
             return fail(VDI_E_INVALID, "in_max_n_sum %d outside [k, k*%d]", shape->in_max_n_sum, VDI_MAX_N);
-        if (composite_lds_bytes(shape->k, shape->in_max_n_sum, false) > 160 * 1024)
+        if (composite_lds_bytes(shape->k, shape->in_max_n_sum) > 160 * 1024)
             return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", shape->in_max_n_sum);
         *bytes = composite_ws(ctx, (size_t)shape->width * shape->height, shape->k, shape->in_max_n_sum, true).total;
         return VDI_OK;
@@ -711,7 +711,7 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     CompParams P;
     vdi_status st = composite_params(ctx, in, k, tau, out, P);
     if (st != VDI_OK) return st;
-    if (composite_lds_bytes(k, P.seq_cap, false) > 160 * 1024)
+    if (composite_lds_bytes(k, P.seq_cap) > 160 * 1024)
         return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large", P.seq_cap);
     const CompWs W = composite_ws(ctx, P.npix, k, P.seq_cap, true, ctx->user_ws ? ctx->user_ws_bytes : 0);
     if ((st = ensure_scratch(ctx, W.total)) != VDI_OK) return st;
@@ -741,7 +741,7 @@ vdi_status vdi_composite_noalloc(vdi_ctx* ctx, const vdi_t* in, int k, const vdi
     vdi_status st = composite_params(ctx, in, k, tau, out, P);
     if (st != VDI_OK) return st;
     // no staging slabs: the general merge keeps its merge sequence in LDS
-    if (composite_lds_bytes(k, P.seq_cap, false) > 160 * 1024)
+    if (composite_lds_bytes(k, P.seq_cap) > 160 * 1024)
         return fail(VDI_E_UNSUPPORTED, "merged list capacity %d too large for the merge sequence in LDS", P.seq_cap);
     const CompWs W = composite_ws(ctx, P.npix, k, P.seq_cap, false);
     const size_t need = W.qbytes + W.obytes;

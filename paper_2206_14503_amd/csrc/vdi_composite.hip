@@ -181,13 +181,12 @@ struct Lds {
 
 __device__ inline int seq_bytes(int k, int seq_cap) { return k <= 16 ? (seq_cap + 1) / 2 : seq_cap; }
 
-// staged: the merged list goes to global memory, no merge sequence in LDS
-__device__ inline Lds lds_layout(unsigned char* lds_raw, int k, int seq_cap, bool staged)
+__device__ inline Lds lds_layout(unsigned char* lds_raw, int k, int seq_cap)
 {
     Lds L;
     L.in = (const InLds*)lds_raw;
     unsigned char* q = lds_raw + sizeof(InLds) * kMaxInputs;
-    const int sb = staged ? 0 : (seq_bytes(k, seq_cap) + 3) & ~3;
+    const int sb = (seq_bytes(k, seq_cap) + 3) & ~3;
     L.seq = q;
     q += (size_t)sb * kWave;
     L.front = (float*)q;
@@ -691,7 +690,7 @@ __device__ bool composite_pixel_cat(const CompParams& P, unsigned char* lds_raw,
 // input) into an LDS merge sequence, then re-segmentation replaying it.
 __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int t, uint32_t p)
 {
-    const Lds L = lds_layout(lds_raw, P.k, P.seq_cap, false);
+    const Lds L = lds_layout(lds_raw, P.k, P.seq_cap);
     const SeqReader rd{&L, t, P.k, 0};
 
     // ---- load counts, validate, set up the merge cursors
@@ -1299,9 +1298,9 @@ void launch_batch(const CompParams* jobs, const uint2* tiles, uint32_t n_tiles, 
     hipLaunchKernelGGL(batch_queue_kernel, dim3(grid_gen), dim3(kWave), lds_gen, s, jobs, n_jobs, t_se);
 }
 
-size_t composite_lds_bytes(int k, int seq_cap, bool staged)
+size_t composite_lds_bytes(int k, int seq_cap)
 {
-    const size_t sb = staged ? 0 : ((size_t)(k <= 16 ? (seq_cap + 1) / 2 : seq_cap) + 3) & ~(size_t)3;
+    const size_t sb = ((size_t)(k <= 16 ? (seq_cap + 1) / 2 : seq_cap) + 3) & ~(size_t)3;
     return sizeof(InLds) * kMaxInputs + (size_t)kWave * (sb + 14 * (size_t)k);
 }
 
@@ -1430,7 +1429,7 @@ static void launch_overflow(const CompParams& D, hipStream_t s)
     CompParams O = D;
     O.rs_br = nullptr;
     O.rs_lv = nullptr;
-    const size_t lds = composite_lds_bytes(O.k, O.seq_cap, false);
+    const size_t lds = composite_lds_bytes(O.k, O.seq_cap);
     hipLaunchKernelGGL(composite_queue_kernel, dim3((unsigned)(O.num_cus * 2)), dim3(kWave), lds, s, O, O.chunk);
 }
 
@@ -1501,7 +1500,7 @@ static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync
 
 void launch_composite(const CompParams& P, int grid_general, hipStream_t s, const OrderedSync* sync)
 {
-    const size_t lds = composite_lds_bytes(P.k, P.seq_cap, false);
+    const size_t lds = composite_lds_bytes(P.k, P.seq_cap);
     const unsigned blocks = composite_blocks(P);
     const unsigned g2 = std::max(1u, std::min(blocks, (unsigned)grid_general));
     if (P.k > kCatMaxInputs) {

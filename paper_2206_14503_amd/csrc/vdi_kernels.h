@@ -169,7 +169,7 @@ constexpr int kOrderBuckets = 64;
 // Inputs up to which the depth-disjoint path runs (4-bit list ids).
 constexpr int kCatMaxInputs = 16;
 
-size_t composite_lds_bytes(int k, int seq_cap, bool staged = false);   // general merge
+size_t composite_lds_bytes(int k, int seq_cap);   // general merge
 // Merged-list capacity up to which the ordered general merge runs.
 constexpr int kOrderedMaxCap = 512;
 // Queue entries per chunk of the ordered merge for a staging budget of
