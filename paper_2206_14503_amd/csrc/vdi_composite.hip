@@ -1363,6 +1363,11 @@ uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix)
     size_t c = bytes / per;
     const size_t all = ((size_t)npix + 63) & ~(size_t)63;
     c = std::min(c, all) & ~(size_t)63;
+    if (c == 0) return 0;
+    // chunks of equal size (no short last chunk, whose re-segmentation takes
+    // as long as a full chunk's with little else on the device)
+    const size_t n = ((size_t)npix + c - 1) / c;
+    c = std::min(c, ((((size_t)npix + n - 1) / n) + 63) & ~(size_t)63);
     return (uint32_t)c;
 }
 
@@ -1418,10 +1423,6 @@ static void launch_resegment(const CompParams& P, uint32_t e0, hipStream_t s)
     hipLaunchKernelGGL(composite_staged_kernel, dim3(ord_grid(P, c / 64, 8)), dim3(64), 0, s, P, e0);
 }
 
-// The ordered general merge over the queue, chunk by chunk (every kernel
-// reads the queue length on the device; entries past it exit at once).  With
-// two buffers, chunk c + 1 is ordered and staged on the second stream while
-// chunk c is re-segmented.
 // Deferred pixels beyond the deferred round's one chunk: the general merge
 // with its merge sequence in LDS, from the start (no staging, no bracket).
 static void launch_overflow(const CompParams& D, hipStream_t s)
@@ -1449,6 +1450,10 @@ static CompParams deferred_round(const CompParams& P)
     return D;
 }
 
+// The ordered general merge over the queue, chunk by chunk (every kernel
+// reads the queue length on the device; entries past it exit at once).  With
+// two buffers, chunk c + 1 is ordered and staged on the second stream while
+// chunk c is re-segmented.
 static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync* sync)
 {
     const uint32_t c = P.chunk;
