@@ -1477,29 +1477,40 @@ static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync
         return;
     }
     const CompParams D1 = P.dq_count ? deferred_round(P) : P, D2 = P.dq_count ? deferred_round(*sync->P2) : P;
-    const CompParams* buf[2][2] = {{&P, sync->P2}, {&D1, &D2}};
+    // the last chunk of the queue defers nothing: its mispredicted lanes
+    // finish in their wavefronts, so the deferral list is complete when the
+    // chunk before it is, and the deferred round runs beside the last chunk
+    CompParams L1 = P, L2 = *sync->P2;
+    L1.dq_count = L2.dq_count = nullptr;
+    const CompParams* buf[3][2] = {{&P, sync->P2}, {&D1, &D2}, {&L1, &L2}};
+    hipStream_t aux = sync->aux;
     // fork: the second stream starts after the caller's work so far
     (void)hipEventRecord(sync->ev[0], s);
-    (void)hipStreamWaitEvent(sync->aux, sync->ev[0], 0);
+    (void)hipStreamWaitEvent(aux, sync->ev[0], 0);
     for (uint32_t i = 0; i < total; ++i) {
         const int b = (int)(i & 1u);
         const int rd = i < n ? 0 : 1;
+        const CompParams& B = *buf[i + 1 == n && P.dq_count ? 2 : rd][b];
         // staging chunk i into buffer b waits until chunk i - 2 (same buffer)
-        // has been re-segmented; the deferred round's first staging also
-        // until the last chunk of the queue has (it completes the list)
-        if (i >= 2) (void)hipStreamWaitEvent(sync->aux, sync->ev[3 + b], 0);
-        if (i == n && n >= 1) (void)hipStreamWaitEvent(sync->aux, sync->ev[3 + ((n - 1) & 1u)], 0);
+        // has been re-segmented (for the deferred round: the last chunk that
+        // defers, so the list is complete)
+        if (i >= 2) (void)hipStreamWaitEvent(aux, sync->ev[3 + b], 0);
         const uint32_t e0 = (i - (uint32_t)rd * n) * c;
-        launch_order_stage(*buf[rd][b], e0, sync->aux);
-        (void)hipEventRecord(sync->ev[1 + b], sync->aux);
+        launch_order_stage(B, e0, aux);
+        if (rd) {
+            // the deferred round: on the second stream, beside the last chunk
+            launch_resegment(B, e0, aux);
+            launch_overflow(B, aux);
+            continue;
+        }
+        (void)hipEventRecord(sync->ev[1 + b], aux);
         // re-segmenting chunk i waits for its staging
         (void)hipStreamWaitEvent(s, sync->ev[1 + b], 0);
-        launch_resegment(*buf[rd][b], e0, s);
-        if (rd) launch_overflow(*buf[rd][b], s);
+        launch_resegment(B, e0, s);
         (void)hipEventRecord(sync->ev[3 + b], s);
     }
     // join: the second stream's work precedes everything after this call
-    (void)hipEventRecord(sync->ev[0], sync->aux);
+    (void)hipEventRecord(sync->ev[0], aux);
     (void)hipStreamWaitEvent(s, sync->ev[0], 0);
 }
 
