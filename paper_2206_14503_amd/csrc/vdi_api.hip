@@ -246,7 +246,7 @@ static size_t mlp_bwd_ws_bytes(int rows)
 struct CompWs {
     size_t qbytes, obytes, grid, total, buf;
     uint32_t chunk;
-    int nbuf;          // ordered-merge buffers: 2 when the queue can span several chunks
+    int nbuf;          // ordered-merge buffers: 2 or 3 when the queue can span several chunks
 };
 static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, bool staged, size_t limit = 0)
 {
@@ -260,7 +260,7 @@ static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, 
                ~(size_t)255;
     W.obytes = (2 * nblk * sizeof(uint32_t) + 255) & ~(size_t)255;
     W.chunk = staged ? ordered_chunk(seq_cap, kStageBudget, (uint32_t)npix) : 0u;
-    W.nbuf = W.chunk == 0 ? 0 : (W.chunk < npix ? 2 : 1);
+    W.nbuf = W.chunk == 0 ? 0 : (W.chunk < npix ? std::min<int>(kStageBufs, (int)((npix + W.chunk - 1) / W.chunk)) : 1);
     W.buf = W.chunk ? ordered_ws_bytes(seq_cap, W.chunk) : 0;
     W.total = W.qbytes + W.obytes + W.nbuf * W.buf;
     if (limit && W.chunk && W.total > limit && limit > W.qbytes + W.obytes + 2048) {
@@ -470,11 +470,11 @@ vdi_status vdi_ctx_create(vdi_ctx** out, int device)
     c->device = device;
     c->static_scratch = sptr;
     c->aux = nullptr;
-    for (int i = 0; i < 5; ++i) c->ev[i] = nullptr;
+    for (int i = 0; i < 7; ++i) c->ev[i] = nullptr;
     hipError_t es = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
-    for (int i = 0; i < 5 && es == hipSuccess; ++i) es = hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming);
+    for (int i = 0; i < 7 && es == hipSuccess; ++i) es = hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming);
     if (es != hipSuccess) {
-        for (int i = 0; i < 5; ++i)
+        for (int i = 0; i < 7; ++i)
             if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
         if (c->aux) (void)hipStreamDestroy(c->aux);
         delete c;
@@ -489,7 +489,7 @@ vdi_status vdi_ctx_create(vdi_ctx** out, int device)
     hipError_t e = hipMalloc(&c->status, 64);
     if (e == hipSuccess) e = hipMemset(c->status, 0, 64);
     if (e != hipSuccess) {
-        for (int i = 0; i < 5; ++i) (void)hipEventDestroy(c->ev[i]);
+        for (int i = 0; i < 7; ++i) (void)hipEventDestroy(c->ev[i]);
         (void)hipStreamDestroy(c->aux);
         delete c;
         return fail(VDI_E_HIP, "status allocation failed: %s", hipGetErrorString(e));
@@ -506,7 +506,7 @@ vdi_status vdi_ctx_destroy(vdi_ctx* ctx)
     (void)hipDeviceSynchronize();
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->status) (void)hipFree(ctx->status);
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 7; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     delete ctx;
@@ -720,13 +720,18 @@ vdi_status vdi_composite(vdi_ctx* ctx, const vdi_t* in, int k, const vdi_tau_t* 
     // the ordered merge's buffers after the queue and the block order
     char* obase = base + W.qbytes + W.obytes;
     if (W.chunk) composite_ordered(P, obase, W.chunk);
-    if (W.nbuf == 2) {
-        CompParams P2 = P;
-        composite_ordered(P2, obase + W.buf, W.chunk);
+    if (W.nbuf >= 2) {
+        CompParams Pb[kStageBufs];
         OrderedSync sync;
         sync.aux = ctx->aux;
-        for (int i = 0; i < 5; ++i) sync.ev[i] = ctx->ev[i];
-        sync.P2 = &P2;
+        for (int i = 0; i < 7; ++i) sync.ev[i] = ctx->ev[i];
+        sync.nbuf = W.nbuf;
+        sync.B[0] = &P;
+        for (int b = 1; b < W.nbuf; ++b) {
+            Pb[b] = P;
+            composite_ordered(Pb[b], obase + b * W.buf, W.chunk);
+            sync.B[b] = &Pb[b];
+        }
         launch_composite(P, (int)W.grid, (hipStream_t)stream, &sync);
     } else {
         launch_composite(P, (int)W.grid, (hipStream_t)stream);

@@ -1452,8 +1452,8 @@ static CompParams deferred_round(const CompParams& P)
 
 // The ordered general merge over the queue, chunk by chunk (every kernel
 // reads the queue length on the device; entries past it exit at once).  With
-// two buffers, chunk c + 1 is ordered and staged on the second stream while
-// chunk c is re-segmented.
+// several buffers, chunks c + 1 (and c + 2) are ordered and staged on the
+// second stream while chunk c is re-segmented.
 static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync* sync)
 {
     const uint32_t c = P.chunk;
@@ -1463,7 +1463,7 @@ static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync
     // deferred pixels are a few per hundred, and any beyond that chunk are
     // composited again from the start by the general merge without staging)
     const uint32_t total = n + (P.dq_count ? 1u : 0u);
-    if (!sync || !sync->P2) {
+    if (!sync || sync->nbuf < 2) {
         for (uint32_t i = 0; i < n; ++i) {
             launch_order_stage(P, i * c, s);
             launch_resegment(P, i * c, s);
@@ -1476,26 +1476,34 @@ static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync
         }
         return;
     }
-    const CompParams D1 = P.dq_count ? deferred_round(P) : P, D2 = P.dq_count ? deferred_round(*sync->P2) : P;
-    // the last chunk of the queue defers nothing: its mispredicted lanes
-    // finish in their wavefronts, so the deferral list is complete when the
-    // chunk before it is, and the deferred round runs beside the last chunk
-    CompParams L1 = P, L2 = *sync->P2;
-    L1.dq_count = L2.dq_count = nullptr;
-    const CompParams* buf[3][2] = {{&P, sync->P2}, {&D1, &D2}, {&L1, &L2}};
+    // per buffer: the queue's chunks, the deferred round, and the last chunk
+    // of the queue, which defers nothing: its mispredicted lanes finish in
+    // their wavefronts, so the deferral list is complete when the chunk
+    // before it is, and the deferred round runs beside the last chunk
+    const int nb = sync->nbuf;
+    CompParams D[kStageBufs], L[kStageBufs];
+    for (int b = 0; b < nb; ++b) {
+        D[b] = P.dq_count ? deferred_round(*sync->B[b]) : *sync->B[b];
+        L[b] = *sync->B[b];
+        L[b].dq_count = nullptr;
+    }
     hipStream_t aux = sync->aux;
+    const hipEvent_t* staged = sync->ev + 1;
+    const hipEvent_t* done = sync->ev + 1 + kStageBufs;
     // fork: the second stream starts after the caller's work so far
     (void)hipEventRecord(sync->ev[0], s);
     (void)hipStreamWaitEvent(aux, sync->ev[0], 0);
     for (uint32_t i = 0; i < total; ++i) {
-        const int b = (int)(i & 1u);
-        const int rd = i < n ? 0 : 1;
-        const CompParams& B = *buf[i + 1 == n && P.dq_count ? 2 : rd][b];
-        // staging chunk i into buffer b waits until chunk i - 2 (same buffer)
-        // has been re-segmented (for the deferred round: the last chunk that
-        // defers, so the list is complete)
-        if (i >= 2) (void)hipStreamWaitEvent(aux, sync->ev[3 + b], 0);
-        const uint32_t e0 = (i - (uint32_t)rd * n) * c;
+        const int b = (int)(i % (uint32_t)nb);
+        const bool rd = i >= n;
+        const CompParams& B = rd ? D[b] : (i + 1 == n && P.dq_count ? L[b] : *sync->B[b]);
+        // staging chunk i into buffer b waits until chunk i - nb (same
+        // buffer) has been re-segmented; the deferred round also until the
+        // last chunk that defers (n - 2) has: the list is then complete
+        if (i >= (uint32_t)nb) (void)hipStreamWaitEvent(aux, done[b], 0);
+        if (rd && n >= 2 && i - (uint32_t)nb != n - 2)
+            (void)hipStreamWaitEvent(aux, done[(n - 2) % (uint32_t)nb], 0);
+        const uint32_t e0 = (rd ? 0u : i) * c;
         launch_order_stage(B, e0, aux);
         if (rd) {
             // the deferred round: on the second stream, beside the last chunk
@@ -1503,11 +1511,11 @@ static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync
             launch_overflow(B, aux);
             continue;
         }
-        (void)hipEventRecord(sync->ev[1 + b], aux);
+        (void)hipEventRecord(staged[b], aux);
         // re-segmenting chunk i waits for its staging
-        (void)hipStreamWaitEvent(s, sync->ev[1 + b], 0);
+        (void)hipStreamWaitEvent(s, staged[b], 0);
         launch_resegment(B, e0, s);
-        (void)hipEventRecord(sync->ev[3 + b], s);
+        (void)hipEventRecord(done[b], s);
     }
     // join: the second stream's work precedes everything after this call
     (void)hipEventRecord(sync->ev[0], aux);

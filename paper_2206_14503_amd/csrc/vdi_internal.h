@@ -26,7 +26,7 @@ struct vdi_ctx {
     size_t user_ws_bytes; // and never allocate
     void* static_scratch; // device address of the fixed scratch array on this device
     hipStream_t aux;      // second stream of the ordered general merge (fork/join with the caller's)
-    hipEvent_t ev[5];     // its fork/join events
+    hipEvent_t ev[7];     // its fork/join and chunk events
     int num_cus;
     char arch[64];
 };

@@ -182,15 +182,20 @@ constexpr size_t kStageBudget = (size_t)3 << 29;
 uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix);
 size_t ordered_ws_bytes(int seq_cap, uint32_t chunk);
 size_t cat_lds_bytes(int k);                      // depth-disjoint path
+// Staging buffers of the ordered general merge when the queue spans several
+// chunks: chunk c is staged into buffer c % kStageBufs.
+constexpr int kStageBufs = 3;
 // The ordered general merge runs the merge-order and staging kernels of
-// chunk c + 1 on a second stream while the re-segmentation of chunk c runs on
-// the caller's (two staging buffers, P and P2 differing only in them), joined
-// back by events: ev[0] fork, ev[1..2] staging done per buffer, ev[3..4]
-// re-segmentation done per buffer.
+// chunk c + 1 (and, with a third buffer, c + 2) on a second stream while
+// the re-segmentation of chunk c runs on the caller's (the buffers' params
+// differ only in their staging buffers), joined back by events: ev[0] fork
+// and join, ev[1 + b] staging into buffer b done, ev[1 + kStageBufs + b]
+// re-segmentation of buffer b done.
 struct OrderedSync {
     hipStream_t aux;
-    hipEvent_t ev[5];
-    const CompParams* P2;   // the second buffer (NULL: one buffer, one stream)
+    hipEvent_t ev[1 + 2 * kStageBufs];
+    const CompParams* B[kStageBufs];   // the buffers (B[0] the call's params)
+    int nbuf;                          // buffers in use (2 or 3)
 };
 // grid_general: blocks of the queue-driven general merge without staging
 void launch_composite(const CompParams& P, int grid_general, hipStream_t s, const OrderedSync* sync = nullptr);

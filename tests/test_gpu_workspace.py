@@ -122,13 +122,15 @@ def test_graph_capture_after_workspace_query(V, layout):
         V.set_workspace(None)
 
 
-def test_graph_capture_of_multi_chunk_general_merge(V):
+@pytest.mark.parametrize("W,H", [(640, 480), (1024, 600)], ids=["2chunks", "4chunks"])
+def test_graph_capture_of_multi_chunk_general_merge(V, W, H):
     """A general merge spanning several chunks (its staging runs on a second
-    stream forked from and joined back to the caller's): captured in a graph
-    and replayed, equal to the eager run and to the allocation-free path (no
-    staging) bit for bit."""
+    stream forked from and joined back to the caller's; two staging buffers
+    for two chunks, three for four): captured in a graph and replayed, equal
+    to the eager run and to the allocation-free path (no staging) bit for
+    bit."""
     from paper_2206_14503_amd import synth
-    k, n, W, H = 16, 20, 640, 480
+    k, n = 16, 20
     c, d, cnt = synth.dense_frame(k, n, W * H, seed=9)
     ins = [V.VDI(W, H, n, 0.01, V.REGULAR, c[r], d[r], cnt[r]) for r in range(k)]
     need = V.workspace_size(V.OP_COMPOSITE, W, H, k, in_max_n_sum=k * n)
