@@ -239,7 +239,7 @@ static size_t mlp_bwd_ws_bytes(int rows)
 // Workspace of vdi_composite: the queue of pixels left to the general merge
 // ([npix] + counter), the block order of the depth-disjoint pass (order and
 // bucket per block), then the ordered general merge's chunk: staging slabs,
-// merge orders and list lengths for up to 1.5 GiB of slabs (the queue is
+// merge orders and list lengths for up to 1 GiB of slabs (the queue is
 // processed in as many chunks as it takes).  Merged-list capacities above
 // kOrderedMaxCap (and the allocation-free entry point) take the general merge
 // with its merge sequence in LDS instead, without staging.

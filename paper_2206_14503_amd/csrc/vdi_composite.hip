@@ -1404,7 +1404,8 @@ static unsigned ord_grid(const CompParams& P, uint32_t units, int per_cu)
 static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s)
 {
     const uint32_t c = P.chunk;
-    const unsigned g1 = ord_grid(P, c / kStageTile, 8), g2 = ord_grid(P, c / kStageTile, 4);
+    // as many blocks as LDS lets stay resident (36 and 72 KB per block)
+    const unsigned g1 = ord_grid(P, c / kStageTile, 4), g2 = ord_grid(P, c / kStageTile, 2);
     hipLaunchKernelGGL(merge_order_kernel, dim3(g1), dim3(256), order_lds_bytes(P.seq_cap), s, P, e0);
     hipLaunchKernelGGL(merge_stage_kernel, dim3(g2), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
     // the MLP's log2 threshold for the chunk's entries of the queue

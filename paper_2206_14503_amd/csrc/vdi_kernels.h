@@ -174,9 +174,11 @@ size_t composite_lds_bytes(int k, int seq_cap);   // general merge
 constexpr int kOrderedMaxCap = 512;
 // Staging budget per buffer of the ordered merge.  The chunk it gives sets
 // how the two streams' work interleaves: on the 16 x 20 frame (1920 x 1080,
-// N = 20) 1.5 GiB (11 chunks) took 38.4 ms, 2 GiB (9) 39.6 ms, 1.25 GiB (14)
-// 43.2 ms and 1 GiB (17) 38.9 ms.
-constexpr size_t kStageBudget = (size_t)3 << 29;
+// N = 20; three buffers) 1 GiB (17 chunks of 122k pixels, just under one
+// persistent grid of the re-segmentation) took 34.8 ms, 0.75 GiB 38.4 ms,
+// 1.5 GiB 37.0 ms, 2 GiB 36.1 ms.  Each chunk's launches cost about 20 us
+// where the queue is empty (frames of depth-disjoint lists).
+constexpr size_t kStageBudget = (size_t)1 << 30;
 // Queue entries per chunk of the ordered merge for a staging budget of
 // `bytes` (0 if seq_cap exceeds kOrderedMaxCap); workspace of one chunk.
 uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix);

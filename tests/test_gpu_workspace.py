@@ -122,13 +122,14 @@ def test_graph_capture_after_workspace_query(V, layout):
         V.set_workspace(None)
 
 
-@pytest.mark.parametrize("W,H", [(640, 480), (1024, 600)], ids=["2chunks", "4chunks"])
+@pytest.mark.parametrize("W,H", [(480, 400), (1024, 600)], ids=["2chunks", "5chunks"])
 def test_graph_capture_of_multi_chunk_general_merge(V, W, H):
     """A general merge spanning several chunks (its staging runs on a second
-    stream forked from and joined back to the caller's; two staging buffers
-    for two chunks, three for four): captured in a graph and replayed, equal
-    to the eager run and to the allocation-free path (no staging) bit for
-    bit."""
+    stream forked from and joined back to the caller's; with 16 x 20 lists
+    per pixel, 192,000 pixels take two chunks and two staging buffers,
+    614,400 pixels five chunks and three buffers): captured in a graph and
+    replayed, equal to the eager run and to the allocation-free path (no
+    staging) bit for bit."""
     from paper_2206_14503_amd import synth
     k, n = 16, 20
     c, d, cnt = synth.dense_frame(k, n, W * H, seed=9)
