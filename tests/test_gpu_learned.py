@@ -333,3 +333,23 @@ def test_learned_composite_equals_bisection(V, orc, seed):
                          orc.BISECT, 0.0, N, 10)
     check_lists((b.color.cpu().numpy(), b.depth.cpu().numpy(), b.count.cpu().numpy(), b.gamma.cpu().numpy()),
                 oref, "learned composite")
+
+
+def test_learned_composite_equals_bisection_over_chunks(V):
+    """The same at a size whose general merge spans five chunks in three
+    staging buffers (16 x 20 lists per pixel, 1024 x 600 pixels): the MLP's
+    forward pass runs per chunk on the second stream over the chunk's queue
+    entries, and mispredicted lanes are deferred; the composite still equals
+    BISECT's bit for bit."""
+    import torch
+    from paper_2206_14503_amd import learned
+    k, n, W, H = 16, 20, 1024, 600
+    c, d, cnt = synth.dense_frame(k, n, W * H, seed=12)
+    ins = [V.VDI(W, H, n, 0.01, V.REGULAR, c[r], d[r], cnt[r]) for r in range(k)]
+    mlp = learned.init_mlp(3)
+    a = V.composite(ins, V.BISECT, 0.0, n, 10)
+    b = V.composite(ins, V.LEARNED, 0.0, n, 10, mlp=mlp)
+    torch.cuda.synchronize()
+    for name in ("color", "depth", "count", "gamma"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+    assert V.device_status() == 0
