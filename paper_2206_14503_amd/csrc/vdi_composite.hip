@@ -808,17 +808,21 @@ struct StageLds {
     uint32_t histS[kStageTile * kPredBins];
 };
 
-// Element row of an entry's element (the merge buffers hold rows: input
-// base + slot) and its front.
-__device__ inline float row_front(const float2* Ed, int row, int q) { return Ed[row * kStageTile + q].x; }
+// LDS row pitches of the order kernel.  The merge's threads read the fronts
+// of one entry at scattered element rows, so each entry's fronts (and backs)
+// are a row of their own, padded so that the 8 entries' rows start in
+// different banks (in rows of the 8 entries' fronts, an entry's fronts would
+// all fall in one or two banks).
+__host__ __device__ inline int front_pitch(int cap) { return cap + 8; }   // floats
+__host__ __device__ inline int merge_pitch(int cap) { return cap + 2; }   // uint16
 
-// Merge of the sorted runs A = src[a0, a1) and B = src[a1, b1) (rows of
-// entry q; an element of A precedes one of B on equal fronts: A holds the
-// lower inputs) into dst[a0, b1): thread j of `tpm` writes the outputs
-// [d0, d1) of the merged run, starting where a co-rank search over A places
-// output d0.
-__device__ inline void merge_path(const uint16_t* src, uint16_t* dst, const float2* Ed, int q, int a0, int a1, int b1,
-                                  int j, int tpm)
+// Merge of the sorted runs A = src[a0, a1) and B = src[a1, b1) (element rows
+// of one entry, whose fronts are F[row]; an element of A precedes one of B on
+// equal fronts: A holds the lower inputs) into dst[a0, b1): thread j of `tpm`
+// writes the outputs [d0, d1) of the merged run, starting where a co-rank
+// search over A places output d0.
+__device__ inline void merge_path(const uint16_t* src, uint16_t* dst, const float* F, int a0, int a1, int b1, int j,
+                                  int tpm)
 {
     const int a = a1 - a0, b = b1 - a1, n = a + b;
     const int d0 = (int)(((long long)j * n) / tpm), d1 = (int)(((long long)(j + 1) * n) / tpm);
@@ -828,22 +832,22 @@ __device__ inline void merge_path(const uint16_t* src, uint16_t* dst, const floa
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         // A[mid] before B[d0 - mid - 1]: more than mid outputs come from A
-        if (row_front(Ed, src[a0 + mid], q) <= row_front(Ed, src[a1 + d0 - mid - 1], q)) lo = mid + 1;
+        if (F[src[a0 + mid]] <= F[src[a1 + d0 - mid - 1]]) lo = mid + 1;
         else hi = mid;
     }
     int ia = lo, ib = d0 - lo;
-    float fa = ia < a ? row_front(Ed, src[a0 + ia], q) : 0.0f;
-    float fb = ib < b ? row_front(Ed, src[a1 + ib], q) : 0.0f;
+    float fa = ia < a ? F[src[a0 + ia]] : 0.0f;
+    float fb = ib < b ? F[src[a1 + ib]] : 0.0f;
     for (int d = d0; d < d1; ++d) {
         const bool take_a = ia < a && (ib >= b || fa <= fb);
         if (take_a) {
             dst[a0 + d] = src[a0 + ia];
             ++ia;
-            if (ia < a) fa = row_front(Ed, src[a0 + ia], q);
+            if (ia < a) fa = F[src[a0 + ia]];
         } else {
             dst[a0 + d] = src[a1 + ib];
             ++ib;
-            if (ib < b) fb = row_front(Ed, src[a1 + ib], q);
+            if (ib < b) fb = F[src[a1 + ib]];
         }
     }
 }
@@ -896,10 +900,12 @@ __device__ void tile_setup(const CompParams& P, uint32_t e0, uint32_t le0, Stage
 }
 
 // The tile's elements into LDS, (slot row, entry) with the entry fastest, so
-// the 8 entries of a row read whole lines of each slot-major plane (the
-// colours only with COLOR); each thread keeps kStageBatch loads in flight.
+// the 8 entries of a row read whole lines of each slot-major plane; each
+// thread keeps kStageBatch loads in flight.  COLOR (the staging kernel):
+// colours and depths at Ec/Ed[row * 8 + entry]; else (the order kernel) the
+// fronts and backs at Fx/Bk[entry * fp + row].
 template <bool COLOR>
-__device__ void tile_load(const CompParams& P, const StageLds& S, float4* Ec, float2* Ed)
+__device__ void tile_load(const CompParams& P, const StageLds& S, float4* Ec, float2* Ed, float* Fx, float* Bk, int fp)
 {
     const int t = threadIdx.x;
     const int n_el = P.seq_cap * kStageTile;
@@ -928,8 +934,14 @@ __device__ void tile_load(const CompParams& P, const StageLds& S, float4* Ec, fl
         for (int u = 0; u < kStageBatch; ++u) {
             if (v[u]) {
                 const int idx = b0 + t + 256 * u;
-                if (COLOR) Ec[idx] = c[u];
-                Ed[idx] = d[u];
+                if (COLOR) {
+                    Ec[idx] = c[u];
+                    Ed[idx] = d[u];
+                } else {
+                    const int at = (idx & 7) * fp + (idx >> 3);
+                    Fx[at] = d[u].x;
+                    Bk[at] = d[u].y;
+                }
             }
         }
     }
@@ -947,23 +959,25 @@ __device__ void merge_order_tile(const CompParams& P, uint32_t e0, uint32_t tile
 {
     const int t = threadIdx.x;
     const int cap = P.seq_cap;
-    float2* Ed = (float2*)lds_raw;                                           // [cap][8]
-    uint16_t* mb0 = (uint16_t*)(lds_raw + (size_t)cap * kStageTile * sizeof(float2));  // [8][cap]
-    uint16_t* mb1 = mb0 + (size_t)cap * kStageTile;
+    const int fp = front_pitch(cap), mp = merge_pitch(cap);
+    float* Fx = (float*)lds_raw;                                  // [8][fp] fronts
+    float* Bk = Fx + (size_t)kStageTile * fp;                     // [8][fp] backs
+    uint16_t* mb0 = (uint16_t*)(Bk + (size_t)kStageTile * fp);    // [8][mp]
+    uint16_t* mb1 = mb0 + (size_t)kStageTile * mp;
     const uint32_t le0 = tile * kStageTile;
     tile_setup(P, e0, le0, S, nq);
-    tile_load<false>(P, S, nullptr, Ed);
+    tile_load<false>(P, S, nullptr, nullptr, Fx, Bk, fp);
     const int n_el = cap * kStageTile;
     for (int idx = t; idx < n_el; idx += 256) {
         const int q = idx & 7, rs = idx >> 3;
         const int r = S.rinS[rs];
         const int s_ = rs - S.baseS[r];
         if (s_ < S.cntS[q][r]) {
-            const float2 d = Ed[idx];
-            bool ok = isfinite(d.x) & isfinite(d.y) & (d.x < d.y);
-            if (s_ > 0) ok &= d.x >= Ed[idx - kStageTile].x;
+            const float f = Fx[q * fp + rs], b = Bk[q * fp + rs];
+            bool ok = isfinite(f) & isfinite(b) & (f < b);
+            if (s_ > 0) ok &= f >= Fx[q * fp + rs - 1];
             if (!ok) atomicOr(&S.badS[q], 1);
-            mb0[q * cap + S.preS[q][r] + s_] = (uint16_t)rs;
+            mb0[q * mp + S.preS[q][r] + s_] = (uint16_t)rs;
         }
     }
     __syncthreads();
@@ -980,7 +994,7 @@ __device__ void merge_order_tile(const CompParams& P, uint32_t e0, uint32_t tile
             const int r0 = m * 2 * w;
             const int a0 = S.preS[q][min(r0, P.k)], a1 = S.preS[q][min(r0 + w, P.k)];
             const int b1 = S.preS[q][min(r0 + 2 * w, P.k)];
-            if (S.totS[q] > 0) merge_path(src + q * cap, dst + q * cap, Ed, q, a0, a1, b1, jj, tpm);
+            if (S.totS[q] > 0) merge_path(src + q * mp, dst + q * mp, Fx + q * fp, a0, a1, b1, jj, tpm);
             __syncthreads();
             uint16_t* tmp = src;
             src = dst;
@@ -998,7 +1012,7 @@ __device__ void merge_order_tile(const CompParams& P, uint32_t e0, uint32_t tile
     uint16_t* seq = P.seq + (size_t)(le0 >> 3) * cap * 8;
     for (int idx = t; idx < n_el; idx += 256) {
         const int q = idx & 7, i = idx >> 3;
-        if (i < S.totS[q]) seq[idx] = src[q * cap + i];
+        if (i < S.totS[q]) seq[idx] = src[q * mp + i];
     }
     __syncthreads();   // the next tile reuses the LDS
 }
@@ -1026,7 +1040,7 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
         totS[t] = (le < P.chunk && e0 + le < nq) ? P.qtot[le] : -1;
     }
     for (int i = t; i < kStageTile * kPredBins; i += 256) histS[i] = 0u;
-    tile_load<true>(P, S, Ec, Ed);
+    tile_load<true>(P, S, Ec, Ed, nullptr, nullptr, 0);
     int tmax = 0;
 #pragma unroll
     for (int q = 0; q < kStageTile; ++q) tmax = max(tmax, totS[q]);
@@ -1099,8 +1113,11 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
 }
 
 // Persistent: blocks take tiles of 8 chunk entries until the chunk or the
-// queue ends.
-__global__ __launch_bounds__(256) void merge_order_kernel(CompParams P, uint32_t e0)
+// queue ends.  At most 72 VGPRs (seven waves per SIMD): the order kernel runs
+// beside the re-segmentation and staging kernels of other chunks, and at 80
+// it found no room beside them (the dense 16 x 20 composite took 38.3 ms
+// instead of 34.0).
+__global__ __launch_bounds__(256, 7) void merge_order_kernel(CompParams P, uint32_t e0)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ StageLds S;
@@ -1382,12 +1399,12 @@ size_t ordered_ws_bytes(int seq_cap, uint32_t chunk)
     return stage + seq + tot + gh + ft;
 }
 
-// Dynamic LDS of merge_order_kernel (the tile's depths and the two merge
-// buffers of element rows) and of merge_stage_kernel (the tile's elements
-// and the merged rows).
+// Dynamic LDS of merge_order_kernel (the tile's fronts and backs and the two
+// merge buffers of element rows) and of merge_stage_kernel (the tile's
+// elements and the merged rows).
 static size_t order_lds_bytes(int seq_cap)
 {
-    return (size_t)seq_cap * kStageTile * (sizeof(float2) + 2 * sizeof(uint16_t));
+    return (size_t)kStageTile * (2 * sizeof(float) * front_pitch(seq_cap) + 2 * sizeof(uint16_t) * merge_pitch(seq_cap));
 }
 static size_t stage_lds_bytes(int seq_cap)
 {
