@@ -195,3 +195,22 @@ def test_small_workspace_stages_in_small_chunks(V):
         assert V.device_status() == 0
     finally:
         V.set_workspace(None)
+
+
+def test_many_inputs_over_chunks_equals_noalloc(V):
+    """24 interleaved inputs of 20 supersegments (above the depth-disjoint
+    path's input limit, so every pixel goes to the ordered general merge)
+    over 204,800 pixels: three chunks in three staging buffers, deferral and
+    the deferred round beside the last chunk; the output equals the
+    allocation-free path's (the merge sequence in LDS, no staging) bit for
+    bit."""
+    from paper_2206_14503_amd import synth
+    k, n, W, H = 24, 20, 512, 400
+    c, d, cnt = synth.dense_frame(k, n, W * H, seed=5)
+    ins = [V.VDI(W, H, n, 0.01, V.REGULAR, c[r], d[r], cnt[r]) for r in range(k)]
+    a = V.composite(ins, V.BISECT, 0.0, n, 10)
+    b = V.composite(ins, V.BISECT, 0.0, n, 10, noalloc=True)
+    torch.cuda.synchronize()
+    assert _same(a, b)
+    assert torch.equal(a.gamma, b.gamma)
+    assert V.device_status() == 0
