@@ -764,17 +764,19 @@ __device__ void composite_pixel(const CompParams& P, unsigned char* lds_raw, int
 // ---------------------------------------------------------------- ordered general merge
 //
 // The queue of pixels the depth-disjoint path left (or every pixel when k is
-// above its limit) is processed in chunks, each by two kernels:
-//   1. merge_stage_kernel: per tile of 8 entries (consecutive pixels when the
-//      queue holds whole blocks) the elements are read in whole lines into
-//      LDS and validated; each entry's lists are merged by (front, input) in
-//      LDS by a tree of pairwise merges (inputs 2i and 2i+1, then pairs of
+// above its limit) is processed in chunks, each by three kernels:
+//   1. merge_order_kernel: per tile of 8 entries (consecutive pixels when the
+//      queue holds whole blocks) the depths are read in whole lines into LDS
+//      and validated; each entry's lists are merged by (front, input) in LDS
+//      by a tree of pairwise merges (inputs 2i and 2i+1, then pairs of
 //      those, ...), each pairwise merge cut into equal output ranges for its
-//      threads by a co-rank search (merge path); the merged lists are written
-//      to the staging slab in order, in whole lines (the 8 entries are
-//      adjacent columns of a slab row), with the threshold-prediction
-//      features;
-//   2. composite_staged_kernel: one lane per entry, the re-segmentation scans
+//      threads by a co-rank search (merge path); the merge order and the
+//      depths in that order (the staged depth rows) are written out;
+//   2. merge_stage_kernel: per tile, the colours are read in whole lines into
+//      LDS and written to the staging slab in merge order, in whole lines
+//      (the 8 entries are adjacent columns of a slab row), with the
+//      threshold-prediction features;
+//   3. composite_staged_kernel: one lane per entry, the re-segmentation scans
 //      over the slab (each scan step of a wavefront reads whole rows).
 // Per-lane gathers from the inputs' slot-major planes, where a lane's 16
 // bytes come with a line its neighbours need at other times, are avoided.
@@ -902,10 +904,10 @@ __device__ void tile_setup(const CompParams& P, uint32_t e0, uint32_t le0, Stage
 // The tile's elements into LDS, (slot row, entry) with the entry fastest, so
 // the 8 entries of a row read whole lines of each slot-major plane; each
 // thread keeps kStageBatch loads in flight.  COLOR (the staging kernel):
-// colours and depths at Ec/Ed[row * 8 + entry]; else (the order kernel) the
-// fronts and backs at Fx/Bk[entry * fp + row].
+// the colours at Ec[row * 8 + entry]; else (the order kernel) the fronts and
+// backs at Fx/Bk[entry * fp + row].
 template <bool COLOR>
-__device__ void tile_load(const CompParams& P, const StageLds& S, float4* Ec, float2* Ed, float* Fx, float* Bk, int fp)
+__device__ void tile_load(const CompParams& P, const StageLds& S, float4* Ec, float* Fx, float* Bk, int fp)
 {
     const int t = threadIdx.x;
     const int n_el = P.seq_cap * kStageTile;
@@ -925,7 +927,7 @@ __device__ void tile_load(const CompParams& P, const StageLds& S, float4* Ec, fl
                     const CompInput& in = P.in[r];
                     const uint32_t e = S.ebS[q][r] + (uint32_t)s_ * (in.compact ? 1u : P.npix);
                     if (COLOR) c[u] = gload(in.color, e);
-                    d[u] = gload(in.depth, e);
+                    else d[u] = gload(in.depth, e);
                     v[u] = true;
                 }
             }
@@ -936,7 +938,6 @@ __device__ void tile_load(const CompParams& P, const StageLds& S, float4* Ec, fl
                 const int idx = b0 + t + 256 * u;
                 if (COLOR) {
                     Ec[idx] = c[u];
-                    Ed[idx] = d[u];
                 } else {
                     const int at = (idx & 7) * fp + (idx >> 3);
                     Fx[at] = d[u].x;
@@ -966,7 +967,7 @@ __device__ void merge_order_tile(const CompParams& P, uint32_t e0, uint32_t tile
     uint16_t* mb1 = mb0 + (size_t)kStageTile * mp;
     const uint32_t le0 = tile * kStageTile;
     tile_setup(P, e0, le0, S, nq);
-    tile_load<false>(P, S, nullptr, nullptr, Fx, Bk, fp);
+    tile_load<false>(P, S, nullptr, Fx, Bk, fp);
     const int n_el = cap * kStageTile;
     for (int idx = t; idx < n_el; idx += 256) {
         const int q = idx & 7, rs = idx >> 3;
@@ -1008,11 +1009,17 @@ __device__ void merge_order_tile(const CompParams& P, uint32_t e0, uint32_t tile
             if (S.badS[t]) reject_pixel(P, (uint32_t)P.q_list[e0 + le]);
         }
     }
-    // the merged rows out: row i of the 8 entries in one 16-byte run
+    // the merged rows out (row i of the 8 entries in one 16-byte run), and
+    // the staged depths in merge order
     uint16_t* seq = P.seq + (size_t)(le0 >> 3) * cap * 8;
+    const size_t slab = (size_t)(le0 >> 6) * cap * 64 + (le0 & 63);
     for (int idx = t; idx < n_el; idx += 256) {
         const int q = idx & 7, i = idx >> 3;
-        if (i < S.totS[q]) seq[idx] = src[q * mp + i];
+        if (i < S.totS[q]) {
+            const int row = src[q * mp + i];
+            seq[idx] = (uint16_t)row;
+            P.stage_d[slab + (size_t)i * 64 + q] = make_float2(Fx[q * fp + row], Bk[q * fp + row]);
+        }
     }
     __syncthreads();   // the next tile reuses the LDS
 }
@@ -1028,8 +1035,7 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
     const int t = threadIdx.x;
     const int cap = P.seq_cap;
     float4* Ec = (float4*)lds_raw;                         // [cap][8]
-    float2* Ed = (float2*)(lds_raw + (size_t)cap * kStageTile * sizeof(float4));
-    uint16_t* rowS = (uint16_t*)(lds_raw + (size_t)cap * kStageTile * (sizeof(float4) + sizeof(float2)));  // [cap][8]
+    uint16_t* rowS = (uint16_t*)(lds_raw + (size_t)cap * kStageTile * sizeof(float4));  // [cap][8]
     uint32_t* histS = S.histS;
     int* totS = S.totS;
     const uint32_t le0 = tile * kStageTile;
@@ -1040,7 +1046,7 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
         totS[t] = (le < P.chunk && e0 + le < nq) ? P.qtot[le] : -1;
     }
     for (int i = t; i < kStageTile * kPredBins; i += 256) histS[i] = 0u;
-    tile_load<true>(P, S, Ec, Ed, nullptr, nullptr, 0);
+    tile_load<true>(P, S, Ec, nullptr, nullptr, 0);
     int tmax = 0;
 #pragma unroll
     for (int q = 0; q < kStageTile; ++q) tmax = max(tmax, totS[q]);
@@ -1068,7 +1074,6 @@ __device__ void merge_stage_tile(const CompParams& P, uint32_t e0, uint32_t tile
         const int q = idx & 7, i = idx >> 3;
         const float4 c = Ec[rs * kStageTile + q];
         P.stage_c[slab + (size_t)i * 64 + q] = c;
-        P.stage_d[slab + (size_t)i * 64 + q] = Ed[rs * kStageTile + q];
         if (i > 0) {
             const float4 c0 = Ec[rowS[idx - kStageTile] * kStageTile + q];
             const float d0 = c.x * c.w - c0.x * c0.w, d1 = c.y * c.w - c0.y * c0.w, d2 = c.z * c.w - c0.z * c0.w;
@@ -1408,7 +1413,7 @@ static size_t order_lds_bytes(int seq_cap)
 }
 static size_t stage_lds_bytes(int seq_cap)
 {
-    return (size_t)seq_cap * kStageTile * (sizeof(float4) + sizeof(float2) + sizeof(uint16_t));
+    return (size_t)seq_cap * kStageTile * (sizeof(float4) + sizeof(uint16_t));
 }
 
 // Grids of the persistent ordered-merge kernels: enough blocks to fill the
@@ -1421,7 +1426,9 @@ static unsigned ord_grid(const CompParams& P, uint32_t units, int per_cu)
 static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s)
 {
     const uint32_t c = P.chunk;
-    // as many blocks as LDS lets stay resident (36 and 72 KB per block)
+    // four order blocks per CU (as many as LDS holds, 37 KB each) and two
+    // staging blocks (52 KB each; three were slower beside the
+    // re-segmentation: 34.6 ms against 32.9 ms on the 16 x 20 frame)
     const unsigned g1 = ord_grid(P, c / kStageTile, 4), g2 = ord_grid(P, c / kStageTile, 2);
     hipLaunchKernelGGL(merge_order_kernel, dim3(g1), dim3(256), order_lds_bytes(P.seq_cap), s, P, e0);
     hipLaunchKernelGGL(merge_stage_kernel, dim3(g2), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
