@@ -188,7 +188,7 @@ const char *vdi_last_error(void);
  * VDI_OP_MLP_BACKWARD (vdi_mlp_backward: rows).  Other ops need none.  The
  * bytes depend on the device (its compute-unit count) but not on the data.
  * For VDI_OP_COMPOSITE the size is the recommended one (the general merge
- * stages up to 1 GiB of merged lists per chunk, in up to three buffers, so
+ * stages up to 1.25 GiB of merged lists per chunk, in up to three buffers, so
  * that the next chunks are staged while one is re-segmented): a smaller
  * caller workspace
  * (vdi_ctx_set_workspace) makes vdi_composite stage in smaller chunks, down

@@ -239,7 +239,7 @@ static size_t mlp_bwd_ws_bytes(int rows)
 // Workspace of vdi_composite: the queue of pixels left to the general merge
 // ([npix] + counter), the block order of the depth-disjoint pass (order and
 // bucket per block), then the ordered general merge's chunk: staging slabs,
-// merge orders and list lengths for up to 1 GiB of slabs (the queue is
+// merge orders and list lengths for up to 1.25 GiB of slabs (the queue is
 // processed in as many chunks as it takes).  Merged-list capacities above
 // kOrderedMaxCap (and the allocation-free entry point) take the general merge
 // with its merge sequence in LDS instead, without staging.
@@ -259,7 +259,8 @@ static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, 
     W.qbytes = (((npix + 64) + (staged ? 2 * npix : 0)) * sizeof(int) + (staged ? npix * sizeof(float2) : 0) + 255) &
                ~(size_t)255;
     W.obytes = (2 * nblk * sizeof(uint32_t) + 255) & ~(size_t)255;
-    W.chunk = staged ? ordered_chunk(seq_cap, kStageBudget, (uint32_t)npix) : 0u;
+    const uint32_t grid = (uint32_t)ctx->num_cus * kResegBlocksPerCU * 64u;
+    W.chunk = staged ? ordered_chunk(seq_cap, kStageBudget, (uint32_t)npix, grid) : 0u;
     W.nbuf = W.chunk == 0 ? 0 : (W.chunk < npix ? std::min<int>(kStageBufs, (int)((npix + W.chunk - 1) / W.chunk)) : 1);
     W.buf = W.chunk ? ordered_ws_bytes(seq_cap, W.chunk) : 0;
     W.total = W.qbytes + W.obytes + W.nbuf * W.buf;
@@ -268,7 +269,7 @@ static CompWs composite_ws(const vdi_ctx* ctx, size_t npix, int k, int seq_cap, 
         // fit beside the queues (down to 64 entries; below that the call
         // reports VDI_E_WORKSPACE)
         const size_t per_buf = (limit - W.qbytes - W.obytes) / 2 - 1024;
-        const uint32_t c = ordered_chunk(seq_cap, per_buf, (uint32_t)npix);
+        const uint32_t c = ordered_chunk(seq_cap, per_buf, (uint32_t)npix, grid);
         if (c >= 64) {
             W.chunk = c;
             W.nbuf = c < npix ? 2 : 1;

@@ -1377,7 +1377,7 @@ __global__ __launch_bounds__(1024) void order_sort_kernel(CompParams P, uint32_t
     for (uint32_t i = t; i < blocks; i += blockDim.x) P.order[atomicAdd(&cnt[P.bucket[i]], 1u)] = i;
 }
 
-uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix)
+uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix, uint32_t grid)
 {
     if (seq_cap > kOrderedMaxCap) return 0;
     const size_t per = (size_t)seq_cap * (sizeof(float4) + sizeof(float2) + sizeof(uint16_t)) + sizeof(int) +
@@ -1385,6 +1385,7 @@ uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix)
     size_t c = bytes / per;
     const size_t all = ((size_t)npix + 63) & ~(size_t)63;
     c = std::min(c, all) & ~(size_t)63;
+    if (grid && c >= grid && c < all) c = c / grid * grid;
     if (c == 0) return 0;
     // chunks of equal size (no short last chunk, whose re-segmentation takes
     // as long as a full chunk's with little else on the device)
@@ -1445,7 +1446,7 @@ static void launch_resegment(const CompParams& P, uint32_t e0, hipStream_t s)
     // two waves per SIMD: the order and staging kernels of the next chunk run
     // beside these on the second stream and need registers of their own
     // (four waves here leave them none: 6% slower on the 16 x 20 frame)
-    hipLaunchKernelGGL(composite_staged_kernel, dim3(ord_grid(P, c / 64, 8)), dim3(64), 0, s, P, e0);
+    hipLaunchKernelGGL(composite_staged_kernel, dim3(ord_grid(P, c / 64, kResegBlocksPerCU)), dim3(64), 0, s, P, e0);
 }
 
 // Deferred pixels beyond the deferred round's one chunk: the general merge

@@ -172,16 +172,22 @@ constexpr int kCatMaxInputs = 16;
 size_t composite_lds_bytes(int k, int seq_cap);   // general merge
 // Merged-list capacity up to which the ordered general merge runs.
 constexpr int kOrderedMaxCap = 512;
-// Staging budget per buffer of the ordered merge.  The chunk it gives sets
-// how the two streams' work interleaves: on the 16 x 20 frame (1920 x 1080,
-// N = 20; three buffers) 1 GiB (17 chunks of 122k pixels, just under one
-// persistent grid of the re-segmentation) took 34.8 ms, 0.75 GiB 38.4 ms,
-// 1.5 GiB 37.0 ms, 2 GiB 36.1 ms.  Each chunk's launches cost about 20 us
-// where the queue is empty (frames of depth-disjoint lists).
-constexpr size_t kStageBudget = (size_t)1 << 30;
+// Blocks per CU of the re-segmentation's persistent grid (one wavefront of
+// 64 entries each: two waves per SIMD).
+constexpr int kResegBlocksPerCU = 8;
+// Staging budget per buffer of the ordered merge.  Within it a chunk is a
+// whole number of the re-segmentation's grids (num_cus * kResegBlocksPerCU
+// * 64 entries), so that its wavefronts start together and end together:
+// the chunk size sets how the two streams' work interleaves, and on the
+// 16 x 20 frame (1920 x 1080, N = 20) one grid per chunk (16 chunks of
+// 129,600 pixels) took 31.2 ms, 0.93 of one (17 chunks) 32.8 ms, 0.83 of one
+// 33.8 ms, 1.13 of one 43 ms.  Each chunk's launches cost about 20 us where
+// the queue is empty (frames of depth-disjoint lists).
+constexpr size_t kStageBudget = (size_t)5 << 28;
 // Queue entries per chunk of the ordered merge for a staging budget of
-// `bytes` (0 if seq_cap exceeds kOrderedMaxCap); workspace of one chunk.
-uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix);
+// `bytes`, in whole multiples of `grid` entries where the budget holds one
+// (0 if seq_cap exceeds kOrderedMaxCap); workspace of one chunk.
+uint32_t ordered_chunk(int seq_cap, size_t bytes, uint32_t npix, uint32_t grid);
 size_t ordered_ws_bytes(int seq_cap, uint32_t chunk);
 size_t cat_lds_bytes(int k);                      // depth-disjoint path
 // Staging buffers of the ordered general merge when the queue spans several
