@@ -1424,13 +1424,14 @@ static unsigned ord_grid(const CompParams& P, uint32_t units, int per_cu)
     return std::max(1u, std::min(units, (unsigned)(P.num_cus * per_cu)));
 }
 
-static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s)
+static void launch_order_stage(const CompParams& P, uint32_t e0, hipStream_t s, bool alone = false)
 {
     const uint32_t c = P.chunk;
     // four order blocks per CU (as many as LDS holds, 37 KB each) and two
     // staging blocks (52 KB each; three were slower beside the
-    // re-segmentation: 34.6 ms against 32.9 ms on the 16 x 20 frame)
-    const unsigned g1 = ord_grid(P, c / kStageTile, 4), g2 = ord_grid(P, c / kStageTile, 2);
+    // re-segmentation: 34.6 ms against 32.9 ms on the 16 x 20 frame), three
+    // for the first chunk, which nothing runs beside
+    const unsigned g1 = ord_grid(P, c / kStageTile, 4), g2 = ord_grid(P, c / kStageTile, alone ? 3 : 2);
     hipLaunchKernelGGL(merge_order_kernel, dim3(g1), dim3(256), order_lds_bytes(P.seq_cap), s, P, e0);
     hipLaunchKernelGGL(merge_stage_kernel, dim3(g2), dim3(256), stage_lds_bytes(P.seq_cap), s, P, e0);
     // the MLP's log2 threshold for the chunk's entries of the queue
@@ -1530,7 +1531,7 @@ static void launch_ordered(const CompParams& P, hipStream_t s, const OrderedSync
         if (rd && n >= 2 && i - (uint32_t)nb != n - 2)
             (void)hipStreamWaitEvent(aux, done[(n - 2) % (uint32_t)nb], 0);
         const uint32_t e0 = (rd ? 0u : i) * c;
-        launch_order_stage(B, e0, aux);
+        launch_order_stage(B, e0, aux, i == 0);
         if (rd) {
             // the deferred round: on the second stream, beside the last chunk
             launch_resegment(B, e0, aux);
